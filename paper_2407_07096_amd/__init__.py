@@ -1,0 +1,12 @@
+"""MI355X (gfx950) Gaussian kernel density estimation, after STAG 2.0.
+
+Exact KDE on the matrix cores, E2LSH hashing, the CKNS LSH estimator, kernel
+similarity-graph edge sampling and a continuous-batching serving loop, all in
+the HIP library ``libstagkde.so`` behind the C ABI of ``include/stag_kde.h``.
+This package is the thin Python binding of that ABI.
+"""
+from ._lib import (FORMS, StagError, collision_probability, declared_symbols, e2lsh_hash, kde_exact,  # noqa: F401
+                   last_error, library_path, load)
+
+__all__ = ["FORMS", "StagError", "collision_probability", "declared_symbols", "e2lsh_hash", "kde_exact",
+           "last_error", "library_path", "load"]

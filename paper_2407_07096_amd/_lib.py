@@ -1,0 +1,143 @@
+"""ctypes binding of libstagkde.so (argument marshalling only).
+
+Every function takes device tensors (torch, on the current HIP device), checks
+dtype/shape/contiguity, allocates outputs with torch and calls the C ABI on
+the tensor's current stream.  All arithmetic happens in the HIP library; if
+the library is missing the binding raises instead of falling back.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import re
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libstagkde.so")
+HEADER = os.path.join(HERE, "..", "include", "stag_kde.h")
+
+STAG_OK, STAG_E_INVAL, STAG_E_NOMEM, STAG_E_DEVICE, STAG_E_UNSUPPORTED, STAG_E_BUSY = range(6)
+FORMS = {"fp32": 0, "bf16_split": 1, "fp16_split": 2, "bf16_split3": 3}
+NORMALIZE = 1
+
+_lib = None
+
+
+class StagError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"stag status {status}: {msg}")
+        self.status = status
+
+
+def library_path() -> str:
+    return LIB_PATH
+
+
+def load():
+    """Load the HIP library (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2407_07096_amd/build.py "
+                           "(__graft_entry__.build()); there is no CPU fallback")
+    lib = C.CDLL(LIB_PATH)
+    vp, i64, i32, u32, f64 = C.c_void_p, C.c_int64, C.c_int32, C.c_uint32, C.c_double
+    lib.stag_last_error.restype = C.c_char_p
+    lib.stag_last_error.argtypes = []
+    lib.stag_version.restype = C.c_char_p
+    lib.stag_version.argtypes = []
+    lib.stag_e2lsh_collision_probability.restype = f64
+    lib.stag_e2lsh_collision_probability.argtypes = [f64, i32, i32]
+    lib.stag_kde_exact.restype = C.c_int
+    lib.stag_kde_exact.argtypes = [vp, i64, vp, i64, i32, f64, f64, i32, u32, vp, vp, vp]
+    lib.stag_e2lsh_hash.restype = C.c_int
+    lib.stag_e2lsh_hash.argtypes = [vp, i64, i32, vp, vp, i32, i32, vp, vp, vp]
+    _lib = lib
+    return lib
+
+
+def declared_symbols() -> list[str]:
+    """Function names declared in include/stag_kde.h."""
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(stag_[a-z0-9_]+)\s*\(", txt)))
+
+
+def check(status: int, what: str = ""):
+    if status != STAG_OK:
+        msg = load().stag_last_error().decode(errors="replace")
+        raise StagError(status, f"{what}: {msg}" if what else msg)
+
+
+def last_error() -> str:
+    return load().stag_last_error().decode(errors="replace")
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_handle(dev):
+    torch = _torch()
+    return C.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+
+
+def _need(t, dtype, ndim, name):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if t.dim() != ndim:
+        raise ValueError(f"{name} must have {ndim} dims, got {tuple(t.shape)}")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+def _ptr(t):
+    return C.c_void_p(0 if t is None else t.data_ptr())
+
+
+def collision_probability(c: float, K: int = 1, L: int = 1) -> float:
+    return float(load().stag_e2lsh_collision_probability(float(c), int(K), int(L)))
+
+
+def kde_exact(X, Q, a: float, form: str = "fp32", normalize: bool = False, return_bound: bool = False,
+              S_out=None, bound_out=None):
+    """S(q) = sum_i exp(-a ||q - x_i||^2) for every row q of Q (float64 [m]).
+    With return_bound also the per-result relative error bound."""
+    torch = _torch()
+    _need(X, torch.float32, 2, "X")
+    _need(Q, torch.float32, 2, "Q")
+    if X.shape[1] != Q.shape[1]:
+        raise ValueError("X and Q must have the same number of columns")
+    n, d = X.shape
+    m = Q.shape[0]
+    S = S_out if S_out is not None else torch.empty(m, dtype=torch.float64, device=X.device)
+    B = None
+    if return_bound:
+        B = bound_out if bound_out is not None else torch.empty(m, dtype=torch.float64, device=X.device)
+    st = load().stag_kde_exact(_ptr(X), n, _ptr(Q), m, d, float(a), 0.0, FORMS[form],
+                               NORMALIZE if normalize else 0, _ptr(S), _ptr(B), _stream_handle(X.device))
+    check(st, "stag_kde_exact")
+    return (S, B) if return_bound else S
+
+
+def e2lsh_hash(X, G, b, K: int, L: int, want_codes: bool = True, want_keys: bool = True):
+    """codes [n][L][K] int32 and keys [n][L] (int64 tensor holding the uint64 bits)."""
+    torch = _torch()
+    _need(X, torch.float32, 2, "X")
+    _need(G, torch.float32, 2, "G")
+    _need(b, torch.float64, 1, "b")
+    n, d = X.shape
+    if G.shape != (L * K, d) or b.shape[0] != L * K:
+        raise ValueError("G must be [L*K][d] and b [L*K]")
+    codes = torch.empty((n, L, K), dtype=torch.int32, device=X.device) if want_codes else None
+    keys = torch.empty((n, L), dtype=torch.int64, device=X.device) if want_keys else None
+    st = load().stag_e2lsh_hash(_ptr(X), n, d, _ptr(G), _ptr(b), K, L, _ptr(codes), _ptr(keys),
+                                _stream_handle(X.device))
+    check(st, "stag_e2lsh_hash")
+    return codes, keys

@@ -1,0 +1,556 @@
+// Exact Gaussian kernel density on the gfx950 matrix cores.
+//
+// S(q) = sum_i exp(-a ||q - x_i||^2)   (Sec. "Kernel Density Estimation": the
+// density K(q) = S(q)/n; ExactGaussianKDE evaluates it naively in O(dmn)).
+//
+// The squared distance is expanded, ||q-x||^2 = ||q||^2 + ||x||^2 - 2 q.x,
+// and the whole exponent in base 2,
+//     E = log2(e) * (-a ||q||^2 - a ||x||^2 + 2a q.x) = alpha_q + beta_x + (s q).x,
+// s = 2a log2(e), is produced by the matrix cores: the cross term from the
+// (split) operands, alpha and beta through one extra augmentation step whose
+// operands pair each of them with 1.0.  The epilogue is then just
+// k = exp2(E) and a row sum, per lane, with no cross-lane traffic per tile.
+//
+// Pipeline of one call:
+//   prep_rows  (data)    fp64 norms, beta, operand copy/split, padding rows
+//   prep_rows  (queries) fp64 norms, alpha, scaled operand copy/split
+//   tile_*               grid = (query tile of 128) x (data chunk of 4096 rows);
+//                        4 waves, each owns 32 queries held in registers as
+//                        the B operand; 32-row data tiles are streamed
+//                        through double-buffered LDS as the A operand; per
+//                        tile each lane adds its 16 kernel values in fp32 and
+//                        flushes them into an fp64 accumulator.
+//   reduce               S(q) = sum over chunks in chunk order (fp64), bound.
+// The value of a query depends only on its own row, X and a: chunking and
+// tiling are functions of n alone, so results are identical whatever m is and
+// whatever other queries share a launch.
+#include "runtime.h"
+#include "kde_exact.h"
+
+namespace stag {
+namespace {
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
+
+constexpr double kLog2e = 1.4426950408889634074;
+constexpr int kTileRows = 32;
+constexpr int kWaves = 4;
+constexpr int kBQ = 32 * kWaves;      // queries per workgroup
+constexpr int kChunkRows = 4096;      // data rows per partial sum
+constexpr float kPadOffset = -1.0e30f;  // exponent offset of padding rows: exp2 -> 0
+constexpr unsigned short kBf16One = 0x3F80;
+
+__device__ inline unsigned short bf16_rne(float f) {
+  unsigned int u = __float_as_uint(f);
+  if ((u & 0x7F800000u) == 0x7F800000u) return (unsigned short)((u >> 16) | ((u & 0xFFFFu) ? 0x40u : 0u));
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (unsigned short)(u >> 16);
+}
+__device__ inline float bf16_to_f32(unsigned short h) { return __uint_as_float((unsigned int)h << 16); }
+__device__ inline unsigned short f16_rne(float f) { return __builtin_bit_cast(unsigned short, (_Float16)f); }
+__device__ inline float f16_to_f32(unsigned short h) { return (float)__builtin_bit_cast(_Float16, h); }
+
+// Split v into parts of the form's element type: v ~= p0 + p1 (+ p2); each
+// remainder is exact in fp32 (Sterbenz), so only the last part is rounded.
+template <int FORM>
+__device__ inline void split_value(float v, unsigned short* p) {
+  if constexpr (FORM == STAG_FORM_FP16_SPLIT) {
+    if (!(fabsf(v) < 65504.0f)) {  // out of fp16 range: poison the result
+      p[0] = 0x7E00; p[1] = 0;
+      return;
+    }
+    p[0] = f16_rne(v);
+    p[1] = f16_rne(v - f16_to_f32(p[0]));
+  } else if constexpr (FORM == STAG_FORM_BF16_SPLIT) {
+    p[0] = bf16_rne(v);
+    p[1] = bf16_rne(v - bf16_to_f32(p[0]));
+  } else {  // three bf16 parts
+    p[0] = bf16_rne(v);
+    float r = v - bf16_to_f32(p[0]);
+    p[1] = bf16_rne(r);
+    p[2] = bf16_rne(r - bf16_to_f32(p[1]));
+  }
+}
+
+// One wave per row.  `scale` multiplies the operand (1 for data, 2a log2 e for
+// queries); off = -a log2(e) ||row||^2 in fp32; aug = bf16 three-way parts of
+// off laid out for the augmentation step (data: [o1,o2,o3,1,1,1,0,0],
+// queries: [1,1,1,o1,o2,o3,0,0]).  Rows >= n are padding.
+template <int FORM>
+__global__ __launch_bounds__(256) void prep_rows(const float* __restrict__ src, int64_t n, int d, int dp,
+                                                 int64_t rows_pad, double scale, double neg_a_log2e,
+                                                 int is_query, void* __restrict__ part0, void* __restrict__ part1,
+                                                 void* __restrict__ part2, float* __restrict__ off,
+                                                 u16x8* __restrict__ aug, double* __restrict__ nrm,
+                                                 unsigned long long* __restrict__ max_nrm_bits) {
+  const int lane = threadIdx.x & 63;
+  const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row >= rows_pad) return;
+  const bool real = row < n;
+  double sq = 0.0;
+  for (int j = lane; j < dp; j += 64) {
+    float v = 0.0f;
+    if (real && j < d) v = src[row * d + j];
+    sq += (double)v * (double)v;
+    const float w = (float)((double)v * scale);
+    const int64_t o = row * dp + j;
+    if constexpr (FORM == STAG_FORM_FP32) {
+      static_cast<float*>(part0)[o] = w;
+    } else {
+      unsigned short p[3] = {0, 0, 0};
+      split_value<FORM>(w, p);
+      static_cast<unsigned short*>(part0)[o] = p[0];
+      static_cast<unsigned short*>(part1)[o] = p[1];
+      if constexpr (FORM == STAG_FORM_BF16_SPLIT3) static_cast<unsigned short*>(part2)[o] = p[2];
+    }
+  }
+  for (int o = 32; o > 0; o >>= 1) sq += __shfl_xor(sq, o);
+  if (lane == 0) {
+    float ov = real ? (float)(neg_a_log2e * sq) : (is_query ? 0.0f : kPadOffset);
+    off[row] = ov;
+    if (aug) {
+      unsigned short p[3];
+      p[0] = bf16_rne(ov);
+      float r = ov - bf16_to_f32(p[0]);
+      p[1] = bf16_rne(r);
+      p[2] = bf16_rne(r - bf16_to_f32(p[1]));
+      u16x8 v;
+      if (is_query) v = u16x8{kBf16One, kBf16One, kBf16One, p[0], p[1], p[2], 0, 0};
+      else v = u16x8{p[0], p[1], p[2], kBf16One, kBf16One, kBf16One, 0, 0};
+      aug[row] = v;
+    }
+    if (real) {
+      if (nrm) nrm[row] = sq;
+      if (max_nrm_bits) atomicMax(max_nrm_bits, (unsigned long long)__double_as_longlong(sq));
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// FP32 form: v_mfma_f32_32x32x2_f32.  Lane l supplies A[l%32][k] and
+// B[k][l%32] for the k-slot k = l/32; with the k ordering chosen here, lane
+// half h covers dimensions [h*DP/2, (h+1)*DP/2) of every row.
+// ---------------------------------------------------------------------------
+template <int DP>
+__global__ __launch_bounds__(256, 2) void tile_f32(const float* __restrict__ Xp, const float* __restrict__ beta,
+                                                   const float* __restrict__ Qs, const float* __restrict__ alpha,
+                                                   int64_t n_pad, int n_qtiles, int64_t m_pad,
+                                                   double* __restrict__ partial) {
+  constexpr int H = DP / 2;
+  constexpr int LD = DP + 4;  // LDS row stride (floats): 16-byte aligned, rows 4 banks apart
+  constexpr int F4_ROW = DP / 4;
+  constexpr int NLD = (kTileRows * F4_ROW + 255) / 256;
+  __shared__ __attribute__((aligned(16))) float tile[2][kTileRows * LD];
+  __shared__ float tbeta[2][kTileRows];
+
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, r32 = lane & 31, h = lane >> 5;
+  const int qtile = blockIdx.x % n_qtiles;
+  const int chunk = blockIdx.x / n_qtiles;
+  const int64_t qi = (int64_t)qtile * kBQ + wave * 32 + r32;
+
+  float bq[H];
+  {
+    const f32x4* qrow = reinterpret_cast<const f32x4*>(Qs + qi * DP + h * H);
+#pragma unroll
+    for (int s = 0; s < H / 4; ++s) {
+      f32x4 v = qrow[s];
+      bq[4 * s] = v.x; bq[4 * s + 1] = v.y; bq[4 * s + 2] = v.z; bq[4 * s + 3] = v.w;
+    }
+  }
+  const float baug = h == 0 ? alpha[qi] : 1.0f;
+
+  const int64_t row0 = (int64_t)chunk * kChunkRows;
+  int64_t rem = (n_pad - row0) / kTileRows;
+  const int ntiles = (int)(rem < kChunkRows / kTileRows ? rem : kChunkRows / kTileRows);
+
+  f32x4 stage[NLD];
+  float sbeta = 0.0f;
+  auto gload = [&](int t) {
+    const f32x4* srcp = reinterpret_cast<const f32x4*>(Xp + (row0 + (int64_t)t * kTileRows) * DP);
+#pragma unroll
+    for (int k = 0; k < NLD; ++k) {
+      const int idx = tid + 256 * k;
+      if (idx < kTileRows * F4_ROW) stage[k] = srcp[idx];
+    }
+    if (tid < kTileRows) sbeta = beta[row0 + (int64_t)t * kTileRows + tid];
+  };
+  auto lstore = [&](int buf) {
+#pragma unroll
+    for (int k = 0; k < NLD; ++k) {
+      const int idx = tid + 256 * k;
+      if (idx < kTileRows * F4_ROW) {
+        const int r = idx / F4_ROW, c4 = idx % F4_ROW;
+        *reinterpret_cast<f32x4*>(&tile[buf][r * LD + c4 * 4]) = stage[k];
+      }
+    }
+    if (tid < kTileRows) tbeta[buf][tid] = sbeta;
+  };
+
+  gload(0);
+  lstore(0);
+  double acc = 0.0;
+  for (int t = 0; t < ntiles; ++t) {
+    const int buf = t & 1;
+    __syncthreads();
+    if (t + 1 < ntiles) gload(t + 1);
+    const float* arow = &tile[buf][r32 * LD + h * H];
+    f32x16 c = {0};
+#pragma unroll
+    for (int s = 0; s < H; s += 4) {
+      const f32x4 a4 = *reinterpret_cast<const f32x4*>(arow + s);
+      c = __builtin_amdgcn_mfma_f32_32x32x2f32(a4.x, bq[s], c, 0, 0, 0);
+      c = __builtin_amdgcn_mfma_f32_32x32x2f32(a4.y, bq[s + 1], c, 0, 0, 0);
+      c = __builtin_amdgcn_mfma_f32_32x32x2f32(a4.z, bq[s + 2], c, 0, 0, 0);
+      c = __builtin_amdgcn_mfma_f32_32x32x2f32(a4.w, bq[s + 3], c, 0, 0, 0);
+    }
+    const float aaug = h == 0 ? 1.0f : tbeta[buf][r32];
+    c = __builtin_amdgcn_mfma_f32_32x32x2f32(aaug, baug, c, 0, 0, 0);
+    float ssum = 0.0f;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) ssum += __builtin_amdgcn_exp2f(c[i]);
+    acc += (double)ssum;
+    if (t + 1 < ntiles) lstore(buf ^ 1);
+  }
+  const double other = __shfl_down(acc, 32);
+  if (h == 0) partial[(int64_t)chunk * m_pad + qi] = acc + other;
+}
+
+// ---------------------------------------------------------------------------
+// Split forms: v_mfma_f32_32x32x16_{f16,bf16}.  Lane l supplies 8 consecutive
+// k values of row/column l%32; lane half h covers dimensions
+// [16 s + 8 h, 16 s + 8 h + 8) of k-step s.
+// ---------------------------------------------------------------------------
+template <int FORM>
+__device__ inline f32x16 mma16(u16x8 a, u16x8 b, f32x16 c) {
+  if constexpr (FORM == STAG_FORM_FP16_SPLIT)
+    return __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(f16x8, a), __builtin_bit_cast(f16x8, b), c, 0,
+                                                  0, 0);
+  else
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c,
+                                                   0, 0, 0);
+}
+
+__device__ inline f32x16 mma16_bf16(u16x8 a, u16x8 b, f32x16 c) {
+  return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c, 0,
+                                                 0, 0);
+}
+
+template <int FORM, int DP>
+__global__ __launch_bounds__(256, 2) void tile_split(
+    const unsigned short* __restrict__ X0, const unsigned short* __restrict__ X1,
+    const unsigned short* __restrict__ X2, const u16x8* __restrict__ Xaug, const unsigned short* __restrict__ Q0,
+    const unsigned short* __restrict__ Q1, const unsigned short* __restrict__ Q2, const u16x8* __restrict__ Qaug,
+    int64_t n_pad, int n_qtiles, int64_t m_pad, double* __restrict__ partial) {
+  constexpr int NP = FORM == STAG_FORM_BF16_SPLIT3 ? 3 : 2;
+  constexpr int KS = DP / 16;
+  constexpr int LD = DP + 8;  // LDS row stride (halves): 16-byte aligned
+  constexpr int V_ROW = DP / 8;  // 16-byte vectors per row
+  constexpr int NLD = (kTileRows * V_ROW + 255) / 256;
+  __shared__ __attribute__((aligned(16))) unsigned short tile[2][NP][kTileRows * LD];
+  __shared__ u16x8 taug[2][kTileRows];
+
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, r32 = lane & 31, h = lane >> 5;
+  const int qtile = blockIdx.x % n_qtiles;
+  const int chunk = blockIdx.x / n_qtiles;
+  const int64_t qi = (int64_t)qtile * kBQ + wave * 32 + r32;
+
+  const unsigned short* Qp[3] = {Q0, Q1, Q2};
+  const unsigned short* Xpp[3] = {X0, X1, X2};
+  u16x8 bq[NP][KS];
+#pragma unroll
+  for (int p = 0; p < NP; ++p)
+#pragma unroll
+    for (int s = 0; s < KS; ++s)
+      bq[p][s] = *reinterpret_cast<const u16x8*>(Qp[p] + qi * DP + s * 16 + h * 8);
+  const u16x8 zero8 = {0, 0, 0, 0, 0, 0, 0, 0};
+  const u16x8 baug = h == 0 ? Qaug[qi] : zero8;
+
+  const int64_t row0 = (int64_t)chunk * kChunkRows;
+  int64_t rem = (n_pad - row0) / kTileRows;
+  const int ntiles = (int)(rem < kChunkRows / kTileRows ? rem : kChunkRows / kTileRows);
+
+  u16x8 stage[NP][NLD];
+  u16x8 saug = zero8;
+  auto gload = [&](int t) {
+    const int64_t base = (row0 + (int64_t)t * kTileRows) * DP;
+#pragma unroll
+    for (int p = 0; p < NP; ++p)
+#pragma unroll
+      for (int k = 0; k < NLD; ++k) {
+        const int idx = tid + 256 * k;
+        if (idx < kTileRows * V_ROW) stage[p][k] = reinterpret_cast<const u16x8*>(Xpp[p] + base)[idx];
+      }
+    if (tid < kTileRows) saug = Xaug[row0 + (int64_t)t * kTileRows + tid];
+  };
+  auto lstore = [&](int buf) {
+#pragma unroll
+    for (int p = 0; p < NP; ++p)
+#pragma unroll
+      for (int k = 0; k < NLD; ++k) {
+        const int idx = tid + 256 * k;
+        if (idx < kTileRows * V_ROW) {
+          const int r = idx / V_ROW, c8 = idx % V_ROW;
+          *reinterpret_cast<u16x8*>(&tile[buf][p][r * LD + c8 * 8]) = stage[p][k];
+        }
+      }
+    if (tid < kTileRows) taug[buf][tid] = saug;
+  };
+
+  gload(0);
+  lstore(0);
+  double acc = 0.0;
+  for (int t = 0; t < ntiles; ++t) {
+    const int buf = t & 1;
+    __syncthreads();
+    if (t + 1 < ntiles) gload(t + 1);
+    f32x16 c = {0};
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+      u16x8 a[NP];
+#pragma unroll
+      for (int p = 0; p < NP; ++p)
+        a[p] = *reinterpret_cast<const u16x8*>(&tile[buf][p][r32 * LD + s * 16 + h * 8]);
+      // small corrections first, then the leading product
+      if constexpr (NP == 3) {
+        c = mma16<FORM>(a[2], bq[0][s], c);
+        c = mma16<FORM>(a[1], bq[1][s], c);
+        c = mma16<FORM>(a[0], bq[2][s], c);
+      }
+      c = mma16<FORM>(a[1], bq[0][s], c);
+      c = mma16<FORM>(a[0], bq[1][s], c);
+      c = mma16<FORM>(a[0], bq[0][s], c);
+    }
+    const u16x8 aaug = h == 0 ? taug[buf][r32] : zero8;
+    c = mma16_bf16(aaug, baug, c);
+    float ssum = 0.0f;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) ssum += __builtin_amdgcn_exp2f(c[i]);
+    acc += (double)ssum;
+    if (t + 1 < ntiles) lstore(buf ^ 1);
+  }
+  const double other = __shfl_down(acc, 32);
+  if (h == 0) partial[(int64_t)chunk * m_pad + qi] = acc + other;
+}
+
+// S(q) = sum of chunk partials in chunk order; optional 1/n; a-priori bound.
+__global__ void reduce_partials(const double* __restrict__ partial, int P, int64_t m_pad, int64_t m, double scale,
+                                const double* __restrict__ qnrm, const unsigned long long* __restrict__ max_xnrm_bits,
+                                BoundModel bm, double* __restrict__ S_out, double* __restrict__ bound_out) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= m) return;
+  double s = 0.0;
+  for (int p = 0; p < P; ++p) s += partial[(int64_t)p * m_pad + q];
+  S_out[q] = s * scale;
+  if (bound_out) {
+    const double xm = __longlong_as_double((long long)*max_xnrm_bits);
+    bound_out[q] = relative_bound(bm, qnrm[q], xm);
+  }
+}
+
+template <int DP>
+stag_status launch_tile_f32(const float* Xp, const float* beta, const float* Qs, const float* alpha, int64_t n_pad,
+                            int n_qtiles, int64_t m_pad, int P, double* partial, hipStream_t st) {
+  ScopedTimer tm("kde_tile_f32", st);
+  hipLaunchKernelGGL(tile_f32<DP>, dim3((unsigned)((int64_t)n_qtiles * P)), dim3(256), 0, st, Xp, beta, Qs, alpha,
+                     n_pad, n_qtiles, m_pad, partial);
+  return check_launch("tile_f32");
+}
+
+template <int FORM, int DP>
+stag_status launch_tile_split(void* const* xp, const u16x8* xaug, void* const* qp, const u16x8* qaug, int64_t n_pad,
+                              int n_qtiles, int64_t m_pad, int P, double* partial, hipStream_t st) {
+  using U = const unsigned short*;
+  ScopedTimer tm(FORM == STAG_FORM_FP16_SPLIT ? "kde_tile_fp16x3" : (FORM == STAG_FORM_BF16_SPLIT ? "kde_tile_bf16x3" : "kde_tile_bf16x6"), st);
+  hipLaunchKernelGGL((tile_split<FORM, DP>), dim3((unsigned)((int64_t)n_qtiles * P)), dim3(256), 0, st, (U)xp[0],
+                     (U)xp[1], (U)xp[2], xaug, (U)qp[0], (U)qp[1], (U)qp[2], qaug, n_pad, n_qtiles, m_pad, partial);
+  return check_launch("tile_split");
+}
+
+template <int FORM>
+stag_status dispatch_split(int dp, void* const* xp, const u16x8* xaug, void* const* qp, const u16x8* qaug,
+                           int64_t n_pad, int n_qtiles, int64_t m_pad, int P, double* partial, hipStream_t st) {
+  switch (dp) {
+    case 16: return launch_tile_split<FORM, 16>(xp, xaug, qp, qaug, n_pad, n_qtiles, m_pad, P, partial, st);
+    case 32: return launch_tile_split<FORM, 32>(xp, xaug, qp, qaug, n_pad, n_qtiles, m_pad, P, partial, st);
+    case 64: return launch_tile_split<FORM, 64>(xp, xaug, qp, qaug, n_pad, n_qtiles, m_pad, P, partial, st);
+    case 96: return launch_tile_split<FORM, 96>(xp, xaug, qp, qaug, n_pad, n_qtiles, m_pad, P, partial, st);
+    case 128: return launch_tile_split<FORM, 128>(xp, xaug, qp, qaug, n_pad, n_qtiles, m_pad, P, partial, st);
+    case 160: return launch_tile_split<FORM, 160>(xp, xaug, qp, qaug, n_pad, n_qtiles, m_pad, P, partial, st);
+    case 192: return launch_tile_split<FORM, 192>(xp, xaug, qp, qaug, n_pad, n_qtiles, m_pad, P, partial, st);
+    case 224: return launch_tile_split<FORM, 224>(xp, xaug, qp, qaug, n_pad, n_qtiles, m_pad, P, partial, st);
+    case 256: return launch_tile_split<FORM, 256>(xp, xaug, qp, qaug, n_pad, n_qtiles, m_pad, P, partial, st);
+  }
+  return fail(STAG_E_UNSUPPORTED, "padded dimension %d not instantiated", dp);
+}
+
+stag_status dispatch_f32(int dp, const float* Xp, const float* beta, const float* Qs, const float* alpha,
+                         int64_t n_pad, int n_qtiles, int64_t m_pad, int P, double* partial, hipStream_t st) {
+  switch (dp) {
+    case 16: return launch_tile_f32<16>(Xp, beta, Qs, alpha, n_pad, n_qtiles, m_pad, P, partial, st);
+    case 32: return launch_tile_f32<32>(Xp, beta, Qs, alpha, n_pad, n_qtiles, m_pad, P, partial, st);
+    case 64: return launch_tile_f32<64>(Xp, beta, Qs, alpha, n_pad, n_qtiles, m_pad, P, partial, st);
+    case 96: return launch_tile_f32<96>(Xp, beta, Qs, alpha, n_pad, n_qtiles, m_pad, P, partial, st);
+    case 128: return launch_tile_f32<128>(Xp, beta, Qs, alpha, n_pad, n_qtiles, m_pad, P, partial, st);
+    case 160: return launch_tile_f32<160>(Xp, beta, Qs, alpha, n_pad, n_qtiles, m_pad, P, partial, st);
+    case 192: return launch_tile_f32<192>(Xp, beta, Qs, alpha, n_pad, n_qtiles, m_pad, P, partial, st);
+    case 224: return launch_tile_f32<224>(Xp, beta, Qs, alpha, n_pad, n_qtiles, m_pad, P, partial, st);
+    case 256: return launch_tile_f32<256>(Xp, beta, Qs, alpha, n_pad, n_qtiles, m_pad, P, partial, st);
+  }
+  return fail(STAG_E_UNSUPPORTED, "padded dimension %d not instantiated", dp);
+}
+
+template <int FORM>
+stag_status launch_prep(const float* src, int64_t n, int d, int dp, int64_t rows_pad, double scale, double neg_a_l2e,
+                        int is_query, void* const* parts, float* off, u16x8* aug, double* nrm,
+                        unsigned long long* maxbits, hipStream_t st) {
+  ScopedTimer tm("kde_prep", st);
+  hipLaunchKernelGGL(prep_rows<FORM>, dim3((unsigned)ceil_div(rows_pad, 4)), dim3(256), 0, st, src, n, d, dp,
+                     rows_pad, scale, neg_a_l2e, is_query, parts[0], parts[1], parts[2], off, aug, nrm, maxbits);
+  return check_launch("prep_rows");
+}
+
+stag_status prep_any(int form, const float* src, int64_t n, int d, int dp, int64_t rows_pad, double scale,
+                     double neg_a_l2e, int is_query, void* const* parts, float* off, u16x8* aug, double* nrm,
+                     unsigned long long* maxbits, hipStream_t st) {
+  switch (form) {
+    case STAG_FORM_FP32:
+      return launch_prep<STAG_FORM_FP32>(src, n, d, dp, rows_pad, scale, neg_a_l2e, is_query, parts, off, aug, nrm,
+                                         maxbits, st);
+    case STAG_FORM_BF16_SPLIT:
+      return launch_prep<STAG_FORM_BF16_SPLIT>(src, n, d, dp, rows_pad, scale, neg_a_l2e, is_query, parts, off, aug,
+                                               nrm, maxbits, st);
+    case STAG_FORM_FP16_SPLIT:
+      return launch_prep<STAG_FORM_FP16_SPLIT>(src, n, d, dp, rows_pad, scale, neg_a_l2e, is_query, parts, off, aug,
+                                               nrm, maxbits, st);
+    default:
+      return launch_prep<STAG_FORM_BF16_SPLIT3>(src, n, d, dp, rows_pad, scale, neg_a_l2e, is_query, parts, off, aug,
+                                                nrm, maxbits, st);
+  }
+}
+
+}  // namespace
+
+int exact_padded_dim(int d) {
+  static const int dims[] = {16, 32, 64, 96, 128, 160, 192, 224, 256};
+  for (int v : dims)
+    if (d <= v) return v;
+  return 0;
+}
+
+size_t form_element_bytes(int form) { return form == STAG_FORM_FP32 ? 4 : 2; }
+int form_parts(int form) {
+  return form == STAG_FORM_FP32 ? 1 : (form == STAG_FORM_BF16_SPLIT3 ? 3 : 2);
+}
+
+stag_status prepare_operands(int form, const float* src, int64_t rows, int d, double a, bool is_query,
+                             Workspace& ws, Operands* out, hipStream_t st) {
+  const int dp = exact_padded_dim(d);
+  const int64_t rows_pad = round_up(rows, is_query ? kBQ : kTileRows);
+  out->form = form;
+  out->rows = rows;
+  out->rows_pad = rows_pad;
+  out->d = d;
+  out->dp = dp;
+  for (int p = 0; p < 3; ++p) out->part[p] = nullptr;
+  for (int p = 0; p < form_parts(form); ++p)
+    STAG_TRY(ws.alloc_bytes(&out->part[p], (size_t)rows_pad * dp * form_element_bytes(form)));
+  STAG_TRY(ws.alloc(&out->off, (size_t)rows_pad));
+  out->aug = nullptr;
+  if (form != STAG_FORM_FP32) {
+    void* v;
+    STAG_TRY(ws.alloc_bytes(&v, (size_t)rows_pad * 16));
+    out->aug = v;
+  }
+  STAG_TRY(ws.alloc(&out->nrm, (size_t)rows));
+  STAG_TRY(ws.alloc(&out->max_nrm_bits, 1));
+  STAG_HIP(hipMemsetAsync(out->max_nrm_bits, 0, sizeof(unsigned long long), st));
+  const double scale = is_query ? 2.0 * a * kLog2e : 1.0;
+  return prep_any(form, src, rows, d, dp, rows_pad, scale, -a * kLog2e, is_query ? 1 : 0, out->part, out->off,
+                  static_cast<u16x8*>(out->aug), out->nrm, out->max_nrm_bits, st);
+}
+
+int64_t exact_chunks(int64_t n_pad) { return ceil_div(n_pad, kChunkRows); }
+
+stag_status launch_exact_tiles(const Operands& xo, const Operands& qo, double* partial, hipStream_t st) {
+  const int P = (int)exact_chunks(xo.rows_pad);
+  const int n_qtiles = (int)(qo.rows_pad / kBQ);
+  if (xo.form == STAG_FORM_FP32)
+    return dispatch_f32(xo.dp, (const float*)xo.part[0], xo.off, (const float*)qo.part[0], qo.off, xo.rows_pad,
+                        n_qtiles, qo.rows_pad, P, partial, st);
+  const u16x8* xaug = static_cast<const u16x8*>(xo.aug);
+  const u16x8* qaug = static_cast<const u16x8*>(qo.aug);
+  switch (xo.form) {
+    case STAG_FORM_BF16_SPLIT:
+      return dispatch_split<STAG_FORM_BF16_SPLIT>(xo.dp, xo.part, xaug, qo.part, qaug, xo.rows_pad, n_qtiles,
+                                                  qo.rows_pad, P, partial, st);
+    case STAG_FORM_FP16_SPLIT:
+      return dispatch_split<STAG_FORM_FP16_SPLIT>(xo.dp, xo.part, xaug, qo.part, qaug, xo.rows_pad, n_qtiles,
+                                                  qo.rows_pad, P, partial, st);
+    default:
+      return dispatch_split<STAG_FORM_BF16_SPLIT3>(xo.dp, xo.part, xaug, qo.part, qaug, xo.rows_pad, n_qtiles,
+                                                   qo.rows_pad, P, partial, st);
+  }
+}
+
+stag_status launch_reduce(const double* partial, int P, const Operands& qo, const Operands& xo, double scale,
+                          const BoundModel& bm, double* S_out, double* bound_out, hipStream_t st) {
+  const int64_t m = qo.rows;
+  ScopedTimer tm("kde_reduce", st);
+  hipLaunchKernelGGL(reduce_partials, dim3((unsigned)ceil_div(m, 256)), dim3(256), 0, st, partial, P, qo.rows_pad, m,
+                     scale, qo.nrm, xo.max_nrm_bits, bm, S_out, bound_out);
+  return check_launch("reduce_partials");
+}
+
+BoundModel make_bound_model(int form, int d, double a) {
+  BoundModel bm;
+  const double u = 0x1.0p-24;
+  bm.la = a * kLog2e;
+  // fp32 accumulation of the d cross products and the six offset parts,
+  // probabilistic model with lambda = 6 (Higham & Mary 2019)
+  bm.c_acc = 6.0 * std::sqrt((double)d + 6.0) * u;
+  double c_split;
+  switch (form) {
+    case STAG_FORM_FP32: c_split = u; break;                          // rounding of s*q to fp32
+    case STAG_FORM_FP16_SPLIT: c_split = 3.0 * 0x1.0p-22 + u; break;  // dropped lo*lo, part rounding
+    case STAG_FORM_BF16_SPLIT: c_split = 3.0 * 0x1.0p-16 + u; break;
+    default: c_split = 4.0 * 0x1.0p-24 + u; break;
+  }
+  bm.c_split = c_split;
+  bm.c_off = 3.0 * u;                   // alpha, beta rounded to fp32
+  bm.c_tail = 0x1.0p-22 + 16.0 * u;     // exp2 and the 16-term fp32 tile sums
+  return bm;
+}
+
+}  // namespace stag
+
+extern "C" stag_status stag_kde_exact(const float* X, int64_t n, const float* Q, int64_t m, int32_t d, double a,
+                                      double eps, int32_t form, uint32_t flags, double* S_out, double* bound_out,
+                                      hipStream_t stream) {
+  using namespace stag;
+  (void)eps;
+  if (!X || !Q || !S_out) return fail(STAG_E_INVAL, "stag_kde_exact: NULL pointer argument");
+  if (n < 1 || m < 1 || d < 1) return fail(STAG_E_INVAL, "stag_kde_exact: n, m, d must be >= 1");
+  if (!(a > 0.0) || !std::isfinite(a)) return fail(STAG_E_INVAL, "stag_kde_exact: a must be positive and finite");
+  if (form < STAG_FORM_FP32 || form > STAG_FORM_BF16_SPLIT3)
+    return fail(STAG_E_INVAL, "stag_kde_exact: unknown form %d", form);
+  if (flags & ~STAG_NORMALIZE) return fail(STAG_E_INVAL, "stag_kde_exact: unknown flags 0x%x", flags);
+  if (d > 256) return fail(STAG_E_UNSUPPORTED, "stag_kde_exact: d = %d > 256 is not supported", d);
+  if ((double)n * d >= 2147483648.0 || (double)m * d >= 2147483648.0)
+    return fail(STAG_E_INVAL, "stag_kde_exact: n*d and m*d must be < 2^31");
+  clear_error();
+  Workspace ws(stream);
+  Operands xo, qo;
+  STAG_TRY(prepare_operands(form, X, n, d, a, false, ws, &xo, stream));
+  STAG_TRY(prepare_operands(form, Q, m, d, a, true, ws, &qo, stream));
+  const int P = (int)exact_chunks(xo.rows_pad);
+  double* partial = nullptr;
+  STAG_TRY(ws.alloc(&partial, (size_t)P * qo.rows_pad));
+  STAG_TRY(launch_exact_tiles(xo, qo, partial, stream));
+  const double scale = (flags & STAG_NORMALIZE) ? 1.0 / (double)n : 1.0;
+  STAG_TRY(launch_reduce(partial, P, qo, xo, scale, make_bound_model(form, d, a), S_out, bound_out, stream));
+  return STAG_OK;
+}

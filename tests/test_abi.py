@@ -1,0 +1,51 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every function the header declares, validates arguments before touching the
+device, and its host-only collision probability agrees with the oracle."""
+import ctypes as C
+
+import pytest
+
+import paper_2407_07096_amd as stag
+from paper_2407_07096_amd import _lib
+
+
+def test_library_exports_every_declared_symbol():
+    lib = stag.load()
+    names = stag.declared_symbols()
+    assert "stag_kde_exact" in names and "stag_e2lsh_hash" in names
+    missing = [s for s in names if not hasattr(lib, s)]
+    assert not missing, missing
+    assert b"gfx950" in lib.stag_version()
+
+
+@pytest.mark.parametrize("c", [0.0, 0.1, 0.5, 1.0, 2.0, 4.0, 8.0])
+@pytest.mark.parametrize("K,L", [(1, 1), (8, 16), (9, 17)])
+def test_collision_probability_host(orc, c, K, L):
+    assert stag.collision_probability(c, K, L) == pytest.approx(orc.boosted_probability(c, K, L), rel=1e-12,
+                                                                abs=1e-300)
+
+
+def test_collision_probability_rejects():
+    import math
+    assert math.isnan(stag.collision_probability(-1.0))
+    assert math.isnan(stag.collision_probability(1.0, 0, 1))
+
+
+def test_invalid_arguments_rejected_before_launch():
+    lib = stag.load()
+    null = C.c_void_p(0)
+    fake = C.c_void_p(0x1000)  # never dereferenced: validation fails first
+    st = lib.stag_kde_exact(null, 10, fake, 10, 4, 1.0, 0.0, 0, 0, fake, null, null)
+    assert st == _lib.STAG_E_INVAL and "NULL" in stag.last_error()
+    st = lib.stag_kde_exact(fake, 10, fake, 10, 4, -1.0, 0.0, 0, 0, fake, null, null)
+    assert st == _lib.STAG_E_INVAL and "a must be" in stag.last_error()
+    st = lib.stag_kde_exact(fake, 0, fake, 10, 4, 1.0, 0.0, 0, 0, fake, null, null)
+    assert st == _lib.STAG_E_INVAL
+    st = lib.stag_kde_exact(fake, 10, fake, 10, 4, 1.0, 0.0, 9, 0, fake, null, null)
+    assert st == _lib.STAG_E_INVAL
+    st = lib.stag_kde_exact(fake, 10, fake, 10, 4, 1.0, 0.0, 0, 0x80, fake, null, null)
+    assert st == _lib.STAG_E_INVAL
+    st = lib.stag_e2lsh_hash(fake, 10, 4, fake, fake, 0, 3, fake, null, null)
+    assert st == _lib.STAG_E_INVAL
+    st = lib.stag_e2lsh_hash(fake, 10, 4, fake, fake, 2, 3, null, null, null)
+    assert st == _lib.STAG_E_INVAL

@@ -1,0 +1,65 @@
+"""GPU E2LSH codes and keys are bit-exact against the oracle given the same
+stored projections and offsets (Sec. "Random Projection", Sec. "Boosting
+the Probability")."""
+import numpy as np
+import pytest
+
+import synth
+from tests.gpu_util import announce, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def stag():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_2407_07096_amd as s
+    s.load()
+    return s
+
+
+def _gpu_hash(stag, X, G, b, K, L):
+    import torch
+    codes, keys = stag.e2lsh_hash(to_dev(X), to_dev(G), to_dev(b), K, L)
+    torch.cuda.synchronize()
+    return codes.cpu().numpy(), keys.cpu().numpy().view(np.uint64)
+
+
+def test_config1_bit_exact(stag, orc):
+    X, _, _ = synth.config_points(1)
+    K, L = 8, 16
+    G, b = synth.e2lsh_randomness(K * L, 10, seed=3001)
+    announce("e2lsh config1 n=1000 d=10 K=8 L=16")
+    c_ref, k_ref = orc.e2lsh_hash(X, G, b, K, L)
+    c, k = _gpu_hash(stag, X, G, b, K, L)
+    assert np.array_equal(c, c_ref)
+    assert np.array_equal(k, k_ref)
+
+
+@pytest.mark.parametrize("n,d,K,L", [(1, 1, 1, 1), (65, 3, 9, 17), (300, 64, 9, 17), (129, 100, 5, 7),
+                                     (70, 784, 3, 4), (200, 33, 17, 3)])
+def test_shapes_bit_exact(stag, orc, n, d, K, L):
+    rng = np.random.default_rng(n + d)
+    X = (rng.normal(size=(n, d)) * rng.uniform(0.1, 20)).astype(np.float32)
+    G, b = synth.e2lsh_randomness(K * L, d, seed=n * 31 + d)
+    G = (G / rng.uniform(0.5, 30)).astype(np.float32)  # level-scaled projections
+    announce(f"e2lsh n={n} d={d} K={K} L={L}")
+    c_ref, k_ref = orc.e2lsh_hash(X, G, b, K, L)
+    c, k = _gpu_hash(stag, X, G, b, K, L)
+    assert np.array_equal(c, c_ref)
+    assert np.array_equal(k, k_ref)
+    if n * L * K >= 100:
+        assert (c < 0).any()  # negative codes exercised (floor, not truncation)
+
+
+def test_collision_rate_on_gpu(stag, orc):
+    """Collision frequency of GPU-hashed pairs at distance c matches p(c)."""
+    d, nproj = 8, 100_000
+    X = np.zeros((2, d), np.float32)
+    X[1, 0] = 2.0
+    G, b = synth.e2lsh_randomness(nproj, d, seed=11)
+    c, _ = _gpu_hash(stag, X, G, b, 1, nproj)
+    rate = np.mean(c[0, :, 0] == c[1, :, 0])
+    p = orc.collision_probability(2.0)
+    assert abs(rate - p) < 4 * np.sqrt(p * (1 - p) / nproj)
