@@ -122,6 +122,88 @@ stag_status stag_kde_exact(const float* X, int64_t n, const float* Q, int64_t m,
 stag_status stag_e2lsh_hash(const float* X, int64_t n, int32_t d, const float* G, const double* b, int32_t K,
                             int32_t L, int32_t* codes_out, uint64_t* keys_out, hipStream_t stream);
 
+/* ------------------------------------------------------------------------
+ * CKNS approximate kernel density (Sec. "The CKNS Algorithm"; the three
+ * CKNSGaussianKDE constructors map onto stag_lsh_params).
+ *
+ * Reading of the parameters (the paper states them only up to constants):
+ *   mu_min  = min_mu > 0 ? min_mu : 1/n
+ *   J       = max(1, ceil(log2(1/mu_min))) levels ("log n" subsamples)
+ *   p_i     = min(1, 2^-i / (n mu_min)) * 2^-p_offset   (= 2^-i by default)
+ *   T_i     = i ln2 / a: level i holds points with T_{i-1} <= D < T_i, i.e.
+ *             kernel value in (2^-i, 2^-i+1]; points beyond T_J are not counted
+ *   L       = ceil(K2_constant) tables per level (default ceil(log2 n), <= 64)
+ *   K       = largest k with 1 - (1 - p(1)^k)^L >= 1 - eps/4
+ *   K1      = k1 > 0 ? k1 : ceil(log2(n) / eps^2) independent copies
+ *   level i hashes the space scaled by r_i = sqrt(T_i):
+ *             g = fp32(g0 / r_i) for the stored N(0,1) vector g0
+ * Estimate of copy t: sum over levels i and tables l of every member j of q's
+ * bucket not already found in an earlier table of that level, with
+ * T_{i-1} <= D < T_i, of exp(-a D) / (p_i R_i), R_i = 1 - (1 - p(sqrt(D)/r_i)^K)^L
+ * (R_i = 1 with STAG_LSH_LITERAL, the paper's 2^i weighting).  The result is
+ * the mean over copies.  D is the fused-order squared distance: D = fma(e, e,
+ * D) over coordinates in order, e = (double)q_h - (double)x_h.
+ * Subsample membership: j is in copy t, level i iff
+ *   (mix(s + (j+1) 0x9E3779B97F4A7C15) >> 11) < floor(p_i 2^53),
+ *   s = mix(mix(mix(seed ^ 0x4D41534B) ^ t) ^ i), mix the SplitMix64 finaliser.
+ * ------------------------------------------------------------------------ */
+#define STAG_LSH_LITERAL 1u      /* weight 1/p_i only (no recovery reweighting) */
+#define STAG_LSH_ALL_SAMPLED 2u  /* test hook: p_i = 1 on every level */
+
+typedef struct {
+  double min_mu;       /* <= 0: 1/n */
+  int32_t k1;          /* <= 0: ceil(log2(n) / eps^2) */
+  double k2_constant;  /* <= 0: ceil(log2 n) */
+  int32_t p_offset;    /* >= 0 */
+  uint64_t seed;       /* subsampling stream (and default projections) */
+  uint32_t flags;      /* STAG_LSH_* */
+  const float* G0;     /* device [K1][J][L][K][d] N(0,1) values, or NULL: drawn from seed */
+  const double* b;     /* device [K1][J][L][K] offsets in [0,4), or NULL (NULL iff G0 is NULL) */
+} stag_lsh_params;
+
+typedef struct {
+  int32_t J, L, K, K1;
+  double mu_min;
+} stag_lsh_shape;
+
+typedef struct stag_lsh_index stag_lsh_index; /* opaque; owns its device arrays */
+
+/* Host-only: the derived shape for (n, a, eps, params); p may be NULL. */
+stag_status stag_lsh_derive(int64_t n, double a, double eps, const stag_lsh_params* p, stag_lsh_shape* out);
+
+/* Builds the index over X [n][d] (device fp32, copied; the caller may free X
+ * afterwards).  Synchronises `stream` once (segment sizes are read back).
+ * Limits: 1 <= n < 2^31, 1 <= d <= 4096, K1*J <= 65535, L <= 64. */
+stag_status stag_lsh_index_create(const float* X, int64_t n, int32_t d, double a, double eps,
+                                  const stag_lsh_params* p, stag_lsh_index** out, hipStream_t stream);
+
+/* Estimates S(q) for Q [m][d] (device fp32) into S_out [m] (device f64).
+ * The index is read-only: concurrent queries on different streams are safe. */
+stag_status stag_lsh_index_query(const stag_lsh_index* idx, const float* Q, int64_t m, double* S_out,
+                                 hipStream_t stream);
+
+/* As stag_lsh_index_query, plus optional per-copy estimates S_copies [m][K1]
+ * (f64), and per query the number of bucket members examined n_cand [m] and
+ * of accepted terms n_acc [m] (int64); each may be NULL. */
+stag_status stag_lsh_index_query_ex(const stag_lsh_index* idx, const float* Q, int64_t m, double* S_out,
+                                    double* S_copies, int64_t* n_cand, int64_t* n_acc, hipStream_t stream);
+
+stag_status stag_lsh_index_shape(const stag_lsh_index* idx, stag_lsh_shape* out);
+
+/* Copies the subsample of copy t (0-based), level i (1-based) to HOST
+ * memory: *count points, members_host [count] ascending point indices and
+ * keys_host [count][L] their bucket keys (either may be NULL).  Synchronises
+ * `stream`. */
+stag_status stag_lsh_index_segment(const stag_lsh_index* idx, int32_t t, int32_t i, int64_t* count,
+                                   int32_t* members_host, uint64_t* keys_host, hipStream_t stream);
+
+/* Waits for the device and frees the index (NULL is ignored). */
+void stag_lsh_index_destroy(stag_lsh_index* idx);
+
+/* create + query + destroy. */
+stag_status stag_kde_lsh(const float* X, int64_t n, const float* Q, int64_t m, int32_t d, double a, double eps,
+                         const stag_lsh_params* p, double* S_out, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -5,8 +5,9 @@ similarity-graph edge sampling and a continuous-batching serving loop, all in
 the HIP library ``libstagkde.so`` behind the C ABI of ``include/stag_kde.h``.
 This package is the thin Python binding of that ABI.
 """
-from ._lib import (FORMS, StagError, collision_probability, declared_symbols, e2lsh_hash, kde_exact,  # noqa: F401
-                   last_error, library_path, load)
+from ._lib import (FORMS, LSH_ALL_SAMPLED, LSH_LITERAL, LshIndex, StagError, collision_probability,  # noqa: F401
+                   declared_symbols, e2lsh_hash, kde_exact, kde_lsh, last_error, library_path, load, lsh_derive)
 
-__all__ = ["FORMS", "StagError", "collision_probability", "declared_symbols", "e2lsh_hash", "kde_exact",
-           "last_error", "library_path", "load"]
+__all__ = ["FORMS", "LSH_ALL_SAMPLED", "LSH_LITERAL", "LshIndex", "StagError", "collision_probability",
+           "declared_symbols", "e2lsh_hash", "kde_exact", "kde_lsh", "last_error", "library_path", "load",
+           "lsh_derive"]

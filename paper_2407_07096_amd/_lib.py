@@ -19,7 +19,19 @@ STAG_OK, STAG_E_INVAL, STAG_E_NOMEM, STAG_E_DEVICE, STAG_E_UNSUPPORTED, STAG_E_B
 FORMS = {"fp32": 0, "bf16_split": 1, "fp16_split": 2, "bf16_split3": 3}
 NORMALIZE = 1
 
+LSH_LITERAL = 1
+LSH_ALL_SAMPLED = 2
+
 _lib = None
+
+
+class LshParams(C.Structure):
+    _fields_ = [("min_mu", C.c_double), ("k1", C.c_int32), ("k2_constant", C.c_double), ("p_offset", C.c_int32),
+                ("seed", C.c_uint64), ("flags", C.c_uint32), ("G0", C.c_void_p), ("b", C.c_void_p)]
+
+
+class LshShape(C.Structure):
+    _fields_ = [("J", C.c_int32), ("L", C.c_int32), ("K", C.c_int32), ("K1", C.c_int32), ("mu_min", C.c_double)]
 
 
 class StagError(RuntimeError):
@@ -52,6 +64,23 @@ def load():
     lib.stag_kde_exact.argtypes = [vp, i64, vp, i64, i32, f64, f64, i32, u32, vp, vp, vp]
     lib.stag_e2lsh_hash.restype = C.c_int
     lib.stag_e2lsh_hash.argtypes = [vp, i64, i32, vp, vp, i32, i32, vp, vp, vp]
+    pp = C.POINTER(LshParams)
+    lib.stag_lsh_derive.restype = C.c_int
+    lib.stag_lsh_derive.argtypes = [i64, f64, f64, pp, C.POINTER(LshShape)]
+    lib.stag_lsh_index_create.restype = C.c_int
+    lib.stag_lsh_index_create.argtypes = [vp, i64, i32, f64, f64, pp, C.POINTER(vp), vp]
+    lib.stag_lsh_index_query.restype = C.c_int
+    lib.stag_lsh_index_query.argtypes = [vp, vp, i64, vp, vp]
+    lib.stag_lsh_index_query_ex.restype = C.c_int
+    lib.stag_lsh_index_query_ex.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp]
+    lib.stag_lsh_index_shape.restype = C.c_int
+    lib.stag_lsh_index_shape.argtypes = [vp, C.POINTER(LshShape)]
+    lib.stag_lsh_index_segment.restype = C.c_int
+    lib.stag_lsh_index_segment.argtypes = [vp, i32, i32, C.POINTER(C.c_int64), vp, vp, vp]
+    lib.stag_lsh_index_destroy.restype = None
+    lib.stag_lsh_index_destroy.argtypes = [vp]
+    lib.stag_kde_lsh.restype = C.c_int
+    lib.stag_kde_lsh.argtypes = [vp, i64, vp, i64, i32, f64, f64, pp, vp, vp]
     _lib = lib
     return lib
 
@@ -141,3 +170,92 @@ def e2lsh_hash(X, G, b, K: int, L: int, want_codes: bool = True, want_keys: bool
                                 _stream_handle(X.device))
     check(st, "stag_e2lsh_hash")
     return codes, keys
+
+
+def _lsh_params(min_mu=0.0, k1=0, k2_constant=0.0, p_offset=0, seed=0, flags=0, G0=None, b=None):
+    return LshParams(float(min_mu), int(k1), float(k2_constant), int(p_offset), int(seed) & 0xFFFFFFFFFFFFFFFF,
+                     int(flags), None if G0 is None else G0.data_ptr(), None if b is None else b.data_ptr())
+
+
+def lsh_derive(n: int, a: float, eps: float = 0.5, **kw) -> dict:
+    """Derived CKNS shape (host only): dict(J, L, K, K1, mu_min)."""
+    prm = _lsh_params(**kw)
+    sh = LshShape()
+    check(load().stag_lsh_derive(int(n), float(a), float(eps), C.byref(prm), C.byref(sh)), "stag_lsh_derive")
+    return dict(J=sh.J, L=sh.L, K=sh.K, K1=sh.K1, mu_min=sh.mu_min)
+
+
+class LshIndex:
+    """CKNS index over device data X (fp32 [n][d]); see include/stag_kde.h."""
+
+    def __init__(self, X, a: float, eps: float = 0.5, G0=None, b=None, **kw):
+        torch = _torch()
+        _need(X, torch.float32, 2, "X")
+        if G0 is not None:
+            _need(G0, torch.float32, G0.dim(), "G0")
+            _need(b, torch.float64, b.dim(), "b")
+        self._keep = (G0, b)
+        prm = _lsh_params(G0=G0, b=b, **kw)
+        h = C.c_void_p()
+        self.device = X.device
+        st = load().stag_lsh_index_create(_ptr(X), X.shape[0], X.shape[1], float(a), float(eps), C.byref(prm),
+                                          C.byref(h), _stream_handle(X.device))
+        check(st, "stag_lsh_index_create")
+        self._h = h
+        self.d = X.shape[1]
+        sh = LshShape()
+        check(load().stag_lsh_index_shape(self._h, C.byref(sh)))
+        self.shape = dict(J=sh.J, L=sh.L, K=sh.K, K1=sh.K1, mu_min=sh.mu_min)
+
+    def query(self, Q, stats: bool = False):
+        torch = _torch()
+        _need(Q, torch.float32, 2, "Q")
+        if Q.shape[1] != self.d:
+            raise ValueError("Q has the wrong number of columns")
+        m = Q.shape[0]
+        S = torch.empty(m, dtype=torch.float64, device=Q.device)
+        if not stats:
+            check(load().stag_lsh_index_query(self._h, _ptr(Q), m, _ptr(S), _stream_handle(Q.device)),
+                  "stag_lsh_index_query")
+            return S
+        K1 = self.shape["K1"]
+        cp = torch.empty((m, K1), dtype=torch.float64, device=Q.device)
+        nc = torch.empty(m, dtype=torch.int64, device=Q.device)
+        na = torch.empty(m, dtype=torch.int64, device=Q.device)
+        check(load().stag_lsh_index_query_ex(self._h, _ptr(Q), m, _ptr(S), _ptr(cp), _ptr(nc), _ptr(na),
+                                             _stream_handle(Q.device)), "stag_lsh_index_query_ex")
+        return S, dict(S_copies=cp, n_cand=nc, n_acc=na)
+
+    def segment(self, t: int, i: int):
+        """(members, keys) of copy t, level i as numpy arrays (host)."""
+        import numpy as np
+        cnt = C.c_int64()
+        check(load().stag_lsh_index_segment(self._h, t, i, C.byref(cnt), None, None, _stream_handle(self.device)))
+        mem = np.empty(cnt.value, dtype=np.int32)
+        keys = np.empty((cnt.value, self.shape["L"]), dtype=np.uint64)
+        check(load().stag_lsh_index_segment(self._h, t, i, C.byref(cnt), mem.ctypes.data_as(C.c_void_p),
+                                            keys.ctypes.data_as(C.c_void_p), _stream_handle(self.device)))
+        return mem, keys
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().stag_lsh_index_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def kde_lsh(X, Q, a: float, eps: float = 0.5, G0=None, b=None, **kw):
+    """One-shot CKNS estimate (index create + query + destroy)."""
+    torch = _torch()
+    _need(X, torch.float32, 2, "X")
+    _need(Q, torch.float32, 2, "Q")
+    prm = _lsh_params(G0=G0, b=b, **kw)
+    S = torch.empty(Q.shape[0], dtype=torch.float64, device=Q.device)
+    check(load().stag_kde_lsh(_ptr(X), X.shape[0], _ptr(Q), Q.shape[0], X.shape[1], float(a), float(eps),
+                              C.byref(prm), _ptr(S), _stream_handle(X.device)), "stag_kde_lsh")
+    return S

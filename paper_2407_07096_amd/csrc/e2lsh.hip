@@ -21,8 +21,6 @@ namespace stag {
 
 namespace {
 
-constexpr uint64_t kKeySalt = 0x243F6A8885A308D3ULL;
-
 // Regroup fp32 projections [L*K][d] (table-major) into binary64
 // G8[l][c][j][e] = g[l*K + 8c + e][j] (zero for 8c+e >= K or j >= d).
 __global__ void regroup_projections(const float* __restrict__ G, int K, int L, int d, int dg, int nch,
@@ -43,42 +41,6 @@ __global__ void regroup_projections(const float* __restrict__ G, int K, int L, i
   }
 }
 
-template <int KC, int DREG>
-__device__ inline void chunk_sums(const double* xr, const float* __restrict__ xrow, int d, int dg,
-                                  const double* __restrict__ g8, double* s) {
-#pragma unroll
-  for (int e = 0; e < KC; ++e) s[e] = 0.0;
-  if constexpr (DREG > 0) {
-#pragma unroll
-    for (int j = 0; j < DREG; ++j) {
-      const double xj = xr[j];
-#pragma unroll
-      for (int e = 0; e < KC; ++e) s[e] = __builtin_fma(xj, g8[j * 8 + e], s[e]);
-    }
-  } else {
-    for (int j = 0; j < dg; ++j) {
-      const double xj = j < d ? (double)xrow[j] : 0.0;
-#pragma unroll
-      for (int e = 0; e < KC; ++e) s[e] = __builtin_fma(xj, g8[j * 8 + e], s[e]);
-    }
-  }
-}
-
-template <int KC, int DREG>
-__device__ inline uint64_t chunk_fold(uint64_t hkey, const double* xr, const float* __restrict__ xrow, int d,
-                                      int dg, const double* __restrict__ g8, const double* __restrict__ bl, int kbase,
-                                      int32_t* __restrict__ codes_row) {
-  double s[KC];
-  chunk_sums<KC, DREG>(xr, xrow, d, dg, g8, s);
-#pragma unroll
-  for (int e = 0; e < KC; ++e) {
-    const int32_t code = code_of(s[e], bl[kbase + e]);
-    if (codes_row) codes_row[kbase + e] = code;
-    hkey = mix64(hkey ^ (uint64_t)(uint32_t)code);
-  }
-  return hkey;
-}
-
 // One lane per point; wave w of block (bx, by) hashes tables
 // [(by*4 + w)*tpw, +tpw) of points [bx*64, +64).
 template <int DREG>
@@ -93,29 +55,12 @@ __global__ __launch_bounds__(256) void e2lsh_kernel(const float* __restrict__ X,
   const int64_t irow = live ? i : 0;
   const float* xrow = X + irow * d;
   double xr[DREG > 0 ? DREG : 1];
-  if constexpr (DREG > 0) {
-#pragma unroll
-    for (int j = 0; j < DREG; ++j) xr[j] = j < d ? (double)xrow[j] : 0.0;
-  }
+  load_point<DREG>(xr, xrow, d);
   const int l0 = (blockIdx.y * 4 + wave) * tpw;
   for (int l = l0; l < l0 + tpw && l < L; ++l) {
-    uint64_t hkey = mix64(kKeySalt ^ (uint64_t)(uint32_t)l);
-    const double* bl = b + (int64_t)l * K;
     int32_t* crow = (codes && live) ? codes + (irow * L + l) * K : nullptr;
-    for (int c = 0; c < nch; ++c) {
-      const double* g8 = G8 + ((int64_t)l * nch + c) * dg * 8;
-      const int kc = K - 8 * c < 8 ? K - 8 * c : 8;
-      switch (kc) {
-        case 1: hkey = chunk_fold<1, DREG>(hkey, xr, xrow, d, dg, g8, bl, 8 * c, crow); break;
-        case 2: hkey = chunk_fold<2, DREG>(hkey, xr, xrow, d, dg, g8, bl, 8 * c, crow); break;
-        case 3: hkey = chunk_fold<3, DREG>(hkey, xr, xrow, d, dg, g8, bl, 8 * c, crow); break;
-        case 4: hkey = chunk_fold<4, DREG>(hkey, xr, xrow, d, dg, g8, bl, 8 * c, crow); break;
-        case 5: hkey = chunk_fold<5, DREG>(hkey, xr, xrow, d, dg, g8, bl, 8 * c, crow); break;
-        case 6: hkey = chunk_fold<6, DREG>(hkey, xr, xrow, d, dg, g8, bl, 8 * c, crow); break;
-        case 7: hkey = chunk_fold<7, DREG>(hkey, xr, xrow, d, dg, g8, bl, 8 * c, crow); break;
-        default: hkey = chunk_fold<8, DREG>(hkey, xr, xrow, d, dg, g8, bl, 8 * c, crow); break;
-      }
-    }
+    const uint64_t hkey = table_key<DREG>(l, xr, xrow, d, dg, G8 + (int64_t)l * nch * dg * 8, b + (int64_t)l * K, K,
+                                          nch, crow);
     if (keys && live) keys[irow * L + l] = hkey;
   }
 }

@@ -54,6 +54,19 @@ __device__ inline float bf16_to_f32(unsigned short h) { return __uint_as_float((
 __device__ inline unsigned short f16_rne(float f) { return __builtin_bit_cast(unsigned short, (_Float16)f); }
 __device__ inline float f16_to_f32(unsigned short h) { return (float)__builtin_bit_cast(_Float16, h); }
 
+// Kernel values of one 32x32 accumulator tile held by a lane (16 exponents),
+// summed as a balanced tree in fp32.
+__device__ inline float exp2_tile_sum(const float* c) {
+  float k[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) k[i] = __builtin_amdgcn_exp2f(c[i]);
+#pragma unroll
+  for (int w = 8; w > 0; w >>= 1)
+#pragma unroll
+    for (int i = 0; i < w; ++i) k[i] = k[i] + k[i + w];
+  return k[0];
+}
+
 // Split v into parts of the form's element type: v ~= p0 + p1 (+ p2); each
 // remainder is exact in fp32 (Sterbenz), so only the last part is rounded.
 template <int FORM>
@@ -76,10 +89,14 @@ __device__ inline void split_value(float v, unsigned short* p) {
   }
 }
 
-// One wave per row.  `scale` multiplies the operand (1 for data, 2a log2 e for
-// queries); off = -a log2(e) ||row||^2 in fp32; aug = bf16 three-way parts of
-// off laid out for the augmentation step (data: [o1,o2,o3,1,1,1,0,0],
-// queries: [1,1,1,o1,o2,o3,0,0]).  Rows >= n are padding.
+// One wave per row, 16 rows per wave, 64 rows per block.  `scale` multiplies
+// the operand (1 for data, 2a log2 e for queries); off = -a log2(e) ||row||^2
+// in fp32; aug = bf16 three-way parts of off laid out for the augmentation
+// step (data: [o1,o2,o3,1,1,1,0,0], queries: [1,1,1,o1,o2,o3,0,0]).  Rows >= n
+// are padding.  The block's largest norm goes to max_nrm_bits with one atomic.
+constexpr int kPrepRowsPerWave = 16;
+constexpr int kPrepRowsPerBlock = 4 * kPrepRowsPerWave;
+
 template <int FORM>
 __global__ __launch_bounds__(256) void prep_rows(const float* __restrict__ src, int64_t n, int d, int dp,
                                                  int64_t rows_pad, double scale, double neg_a_log2e,
@@ -87,54 +104,75 @@ __global__ __launch_bounds__(256) void prep_rows(const float* __restrict__ src, 
                                                  void* __restrict__ part2, float* __restrict__ off,
                                                  u16x8* __restrict__ aug, double* __restrict__ nrm,
                                                  unsigned long long* __restrict__ max_nrm_bits) {
-  const int lane = threadIdx.x & 63;
-  const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (row >= rows_pad) return;
-  const bool real = row < n;
-  double sq = 0.0;
-  for (int j = lane; j < dp; j += 64) {
-    float v = 0.0f;
-    if (real && j < d) v = src[row * d + j];
-    sq += (double)v * (double)v;
-    const float w = (float)((double)v * scale);
-    const int64_t o = row * dp + j;
-    if constexpr (FORM == STAG_FORM_FP32) {
-      static_cast<float*>(part0)[o] = w;
-    } else {
-      unsigned short p[3] = {0, 0, 0};
-      split_value<FORM>(w, p);
-      static_cast<unsigned short*>(part0)[o] = p[0];
-      static_cast<unsigned short*>(part1)[o] = p[1];
-      if constexpr (FORM == STAG_FORM_BF16_SPLIT3) static_cast<unsigned short*>(part2)[o] = p[2];
+  __shared__ double wmax[4];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  double mx = 0.0;
+  for (int rr = 0; rr < kPrepRowsPerWave; ++rr) {
+    const int64_t row = (int64_t)blockIdx.x * kPrepRowsPerBlock + wave * kPrepRowsPerWave + rr;
+    if (row >= rows_pad) break;
+    const bool real = row < n;
+    double sq = 0.0;
+    for (int j = lane; j < dp; j += 64) {
+      float v = 0.0f;
+      if (real && j < d) v = src[row * d + j];
+      sq += (double)v * (double)v;
+      const float w = (float)((double)v * scale);
+      const int64_t o = row * dp + j;
+      if constexpr (FORM == STAG_FORM_FP32) {
+        static_cast<float*>(part0)[o] = w;
+      } else {
+        unsigned short p[3] = {0, 0, 0};
+        split_value<FORM>(w, p);
+        static_cast<unsigned short*>(part0)[o] = p[0];
+        static_cast<unsigned short*>(part1)[o] = p[1];
+        if constexpr (FORM == STAG_FORM_BF16_SPLIT3) static_cast<unsigned short*>(part2)[o] = p[2];
+      }
+    }
+    for (int o = 32; o > 0; o >>= 1) sq += __shfl_xor(sq, o);
+    if (real) mx = fmax(mx, sq);
+    if (lane == 0) {
+      const float ov = real ? (float)(neg_a_log2e * sq) : (is_query ? 0.0f : kPadOffset);
+      off[row] = ov;
+      if (aug) {
+        unsigned short p[3];
+        p[0] = bf16_rne(ov);
+        const float r = ov - bf16_to_f32(p[0]);
+        p[1] = bf16_rne(r);
+        p[2] = bf16_rne(r - bf16_to_f32(p[1]));
+        u16x8 v;
+        if (is_query) v = u16x8{kBf16One, kBf16One, kBf16One, p[0], p[1], p[2], 0, 0};
+        else v = u16x8{p[0], p[1], p[2], kBf16One, kBf16One, kBf16One, 0, 0};
+        aug[row] = v;
+      }
+      if (real && nrm) nrm[row] = sq;
     }
   }
-  for (int o = 32; o > 0; o >>= 1) sq += __shfl_xor(sq, o);
-  if (lane == 0) {
-    float ov = real ? (float)(neg_a_log2e * sq) : (is_query ? 0.0f : kPadOffset);
-    off[row] = ov;
-    if (aug) {
-      unsigned short p[3];
-      p[0] = bf16_rne(ov);
-      float r = ov - bf16_to_f32(p[0]);
-      p[1] = bf16_rne(r);
-      p[2] = bf16_rne(r - bf16_to_f32(p[1]));
-      u16x8 v;
-      if (is_query) v = u16x8{kBf16One, kBf16One, kBf16One, p[0], p[1], p[2], 0, 0};
-      else v = u16x8{p[0], p[1], p[2], kBf16One, kBf16One, kBf16One, 0, 0};
-      aug[row] = v;
-    }
-    if (real) {
-      if (nrm) nrm[row] = sq;
-      if (max_nrm_bits) atomicMax(max_nrm_bits, (unsigned long long)__double_as_longlong(sq));
+  if (max_nrm_bits) {
+    if (lane == 0) wmax[wave] = mx;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const double b = fmax(fmax(wmax[0], wmax[1]), fmax(wmax[2], wmax[3]));
+      atomicMax(max_nrm_bits, (unsigned long long)__double_as_longlong(b));
     }
   }
 }
 
 // ---------------------------------------------------------------------------
+// Tile loop shared by both forms.  Each step t (one 32-row data tile):
+//   barrier (tile t is in LDS buffer t&1, buffer (t+1)&1 is free)
+//   epilogue of tile t-1: exp2 of its 16 accumulators, fp32 tree sum, fp64 add
+//   matrix-core chain of tile t (independent of the epilogue, so the two are
+//   interleaved in one basic block)
+//   store tile t+1 (loaded into registers one step earlier) to LDS and load
+//   tile t+2 into registers.
+// Staging is branch-free: indices past the end are clamped, so the redundant
+// copies write identical values.  Two steps per loop iteration swap the roles
+// of the two accumulator sets without register copies.
+// ---------------------------------------------------------------------------
+
 // FP32 form: v_mfma_f32_32x32x2_f32.  Lane l supplies A[l%32][k] and
 // B[k][l%32] for the k-slot k = l/32; with the k ordering chosen here, lane
 // half h covers dimensions [h*DP/2, (h+1)*DP/2) of every row.
-// ---------------------------------------------------------------------------
 template <int DP>
 __global__ __launch_bounds__(256, 2) void tile_f32(const float* __restrict__ Xp, const float* __restrict__ beta,
                                                    const float* __restrict__ Qs, const float* __restrict__ alpha,
@@ -143,7 +181,9 @@ __global__ __launch_bounds__(256, 2) void tile_f32(const float* __restrict__ Xp,
   constexpr int H = DP / 2;
   constexpr int LD = DP + 4;  // LDS row stride (floats): 16-byte aligned, rows 4 banks apart
   constexpr int F4_ROW = DP / 4;
-  constexpr int NLD = (kTileRows * F4_ROW + 255) / 256;
+  constexpr int NV = kTileRows * F4_ROW;
+  constexpr int NLD = (NV + 255) / 256;
+  constexpr int NMMA = H + 1;
   __shared__ __attribute__((aligned(16))) float tile[2][kTileRows * LD];
   __shared__ float tbeta[2][kTileRows];
 
@@ -164,39 +204,37 @@ __global__ __launch_bounds__(256, 2) void tile_f32(const float* __restrict__ Xp,
   const float baug = h == 0 ? alpha[qi] : 1.0f;
 
   const int64_t row0 = (int64_t)chunk * kChunkRows;
-  int64_t rem = (n_pad - row0) / kTileRows;
+  const int64_t rem = (n_pad - row0) / kTileRows;
   const int ntiles = (int)(rem < kChunkRows / kTileRows ? rem : kChunkRows / kTileRows);
 
   f32x4 stage[NLD];
-  float sbeta = 0.0f;
+  float sbeta;
   auto gload = [&](int t) {
     const f32x4* srcp = reinterpret_cast<const f32x4*>(Xp + (row0 + (int64_t)t * kTileRows) * DP);
 #pragma unroll
-    for (int k = 0; k < NLD; ++k) {
-      const int idx = tid + 256 * k;
-      if (idx < kTileRows * F4_ROW) stage[k] = srcp[idx];
-    }
-    if (tid < kTileRows) sbeta = beta[row0 + (int64_t)t * kTileRows + tid];
+    for (int k = 0; k < NLD; ++k) stage[k] = srcp[min(tid + 256 * k, NV - 1)];
+    sbeta = beta[row0 + (int64_t)t * kTileRows + (tid & 31)];
   };
   auto lstore = [&](int buf) {
 #pragma unroll
     for (int k = 0; k < NLD; ++k) {
-      const int idx = tid + 256 * k;
-      if (idx < kTileRows * F4_ROW) {
-        const int r = idx / F4_ROW, c4 = idx % F4_ROW;
-        *reinterpret_cast<f32x4*>(&tile[buf][r * LD + c4 * 4]) = stage[k];
-      }
+      const int idx = min(tid + 256 * k, NV - 1);
+      const int r = idx / F4_ROW, c4 = idx % F4_ROW;
+      *reinterpret_cast<f32x4*>(&tile[buf][r * LD + c4 * 4]) = stage[k];
     }
-    if (tid < kTileRows) tbeta[buf][tid] = sbeta;
+    tbeta[buf][tid & 31] = sbeta;
   };
 
-  gload(0);
-  lstore(0);
   double acc = 0.0;
-  for (int t = 0; t < ntiles; ++t) {
+  auto step = [&](int t, const f32x16& cdone, f32x16& cnew) {
     const int buf = t & 1;
     __syncthreads();
-    if (t + 1 < ntiles) gload(t + 1);
+    {
+      float cp[16];
+#pragma unroll
+      for (int i = 0; i < 16; ++i) cp[i] = cdone[i];
+      acc += (double)exp2_tile_sum(cp);
+    }
     const float* arow = &tile[buf][r32 * LD + h * H];
     f32x16 c = {0};
 #pragma unroll
@@ -207,23 +245,46 @@ __global__ __launch_bounds__(256, 2) void tile_f32(const float* __restrict__ Xp,
       c = __builtin_amdgcn_mfma_f32_32x32x2f32(a4.z, bq[s + 2], c, 0, 0, 0);
       c = __builtin_amdgcn_mfma_f32_32x32x2f32(a4.w, bq[s + 3], c, 0, 0, 0);
     }
-    const float aaug = h == 0 ? 1.0f : tbeta[buf][r32];
-    c = __builtin_amdgcn_mfma_f32_32x32x2f32(aaug, baug, c, 0, 0, 0);
-    float ssum = 0.0f;
+    const float tb = tbeta[buf][r32];
+    c = __builtin_amdgcn_mfma_f32_32x32x2f32(h == 0 ? 1.0f : tb, baug, c, 0, 0, 0);
+    cnew = c;
+    lstore(buf ^ 1);
+    gload(min(t + 2, ntiles - 1));
 #pragma unroll
-    for (int i = 0; i < 16; ++i) ssum += __builtin_amdgcn_exp2f(c[i]);
-    acc += (double)ssum;
-    if (t + 1 < ntiles) lstore(buf ^ 1);
+    for (int i = 0; i < NMMA; ++i) {
+      __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+      __builtin_amdgcn_sched_group_barrier(0x002, (40 + NMMA - 1) / NMMA, 0);
+    }
+  };
+
+  gload(0);
+  lstore(0);
+  gload(min(1, ntiles - 1));
+  f32x16 ca, cb;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) ca[i] = kPadOffset;  // exp2 -> 0: neutral first epilogue
+  int t = 0;
+  for (; t + 1 < ntiles; t += 2) {
+    step(t, ca, cb);
+    step(t + 1, cb, ca);
+  }
+  if (t < ntiles) {
+    step(t, ca, cb);
+    ca = cb;
+  }
+  {
+    float cp[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) cp[i] = ca[i];
+    acc += (double)exp2_tile_sum(cp);
   }
   const double other = __shfl_down(acc, 32);
   if (h == 0) partial[(int64_t)chunk * m_pad + qi] = acc + other;
 }
 
-// ---------------------------------------------------------------------------
 // Split forms: v_mfma_f32_32x32x16_{f16,bf16}.  Lane l supplies 8 consecutive
 // k values of row/column l%32; lane half h covers dimensions
 // [16 s + 8 h, 16 s + 8 h + 8) of k-step s.
-// ---------------------------------------------------------------------------
 template <int FORM>
 __device__ inline f32x16 mma16(u16x8 a, u16x8 b, f32x16 c) {
   if constexpr (FORM == STAG_FORM_FP16_SPLIT)
@@ -247,9 +308,11 @@ __global__ __launch_bounds__(256, 2) void tile_split(
     int64_t n_pad, int n_qtiles, int64_t m_pad, double* __restrict__ partial) {
   constexpr int NP = FORM == STAG_FORM_BF16_SPLIT3 ? 3 : 2;
   constexpr int KS = DP / 16;
-  constexpr int LD = DP + 8;  // LDS row stride (halves): 16-byte aligned
+  constexpr int LD = DP + 8;     // LDS row stride (halves): 16-byte aligned
   constexpr int V_ROW = DP / 8;  // 16-byte vectors per row
-  constexpr int NLD = (kTileRows * V_ROW + 255) / 256;
+  constexpr int NV = kTileRows * V_ROW;
+  constexpr int NLD = (NV + 255) / 256;
+  constexpr int NMMA = KS * (NP == 3 ? 6 : 3) + 1;
   __shared__ __attribute__((aligned(16))) unsigned short tile[2][NP][kTileRows * LD];
   __shared__ u16x8 taug[2][kTileRows];
 
@@ -266,47 +329,47 @@ __global__ __launch_bounds__(256, 2) void tile_split(
 #pragma unroll
     for (int s = 0; s < KS; ++s)
       bq[p][s] = *reinterpret_cast<const u16x8*>(Qp[p] + qi * DP + s * 16 + h * 8);
-  const u16x8 zero8 = {0, 0, 0, 0, 0, 0, 0, 0};
-  const u16x8 baug = h == 0 ? Qaug[qi] : zero8;
+  const unsigned short hm = h == 0 ? 0xFFFF : 0;
+  const u16x8 hmask = {hm, hm, hm, hm, hm, hm, hm, hm};
+  const u16x8 baug = Qaug[qi] & hmask;
 
   const int64_t row0 = (int64_t)chunk * kChunkRows;
-  int64_t rem = (n_pad - row0) / kTileRows;
+  const int64_t rem = (n_pad - row0) / kTileRows;
   const int ntiles = (int)(rem < kChunkRows / kTileRows ? rem : kChunkRows / kTileRows);
 
   u16x8 stage[NP][NLD];
-  u16x8 saug = zero8;
+  u16x8 saug;
   auto gload = [&](int t) {
     const int64_t base = (row0 + (int64_t)t * kTileRows) * DP;
 #pragma unroll
     for (int p = 0; p < NP; ++p)
 #pragma unroll
-      for (int k = 0; k < NLD; ++k) {
-        const int idx = tid + 256 * k;
-        if (idx < kTileRows * V_ROW) stage[p][k] = reinterpret_cast<const u16x8*>(Xpp[p] + base)[idx];
-      }
-    if (tid < kTileRows) saug = Xaug[row0 + (int64_t)t * kTileRows + tid];
+      for (int k = 0; k < NLD; ++k)
+        stage[p][k] = reinterpret_cast<const u16x8*>(Xpp[p] + base)[min(tid + 256 * k, NV - 1)];
+    saug = Xaug[row0 + (int64_t)t * kTileRows + (tid & 31)];
   };
   auto lstore = [&](int buf) {
 #pragma unroll
     for (int p = 0; p < NP; ++p)
 #pragma unroll
       for (int k = 0; k < NLD; ++k) {
-        const int idx = tid + 256 * k;
-        if (idx < kTileRows * V_ROW) {
-          const int r = idx / V_ROW, c8 = idx % V_ROW;
-          *reinterpret_cast<u16x8*>(&tile[buf][p][r * LD + c8 * 8]) = stage[p][k];
-        }
+        const int idx = min(tid + 256 * k, NV - 1);
+        const int r = idx / V_ROW, c8 = idx % V_ROW;
+        *reinterpret_cast<u16x8*>(&tile[buf][p][r * LD + c8 * 8]) = stage[p][k];
       }
-    if (tid < kTileRows) taug[buf][tid] = saug;
+    taug[buf][tid & 31] = saug;
   };
 
-  gload(0);
-  lstore(0);
   double acc = 0.0;
-  for (int t = 0; t < ntiles; ++t) {
+  auto step = [&](int t, const f32x16& cdone, f32x16& cnew) {
     const int buf = t & 1;
     __syncthreads();
-    if (t + 1 < ntiles) gload(t + 1);
+    {
+      float cp[16];
+#pragma unroll
+      for (int i = 0; i < 16; ++i) cp[i] = cdone[i];
+      acc += (double)exp2_tile_sum(cp);
+    }
     f32x16 c = {0};
 #pragma unroll
     for (int s = 0; s < KS; ++s) {
@@ -324,13 +387,37 @@ __global__ __launch_bounds__(256, 2) void tile_split(
       c = mma16<FORM>(a[0], bq[1][s], c);
       c = mma16<FORM>(a[0], bq[0][s], c);
     }
-    const u16x8 aaug = h == 0 ? taug[buf][r32] : zero8;
-    c = mma16_bf16(aaug, baug, c);
-    float ssum = 0.0f;
+    c = mma16_bf16(taug[buf][r32] & hmask, baug, c);
+    cnew = c;
+    lstore(buf ^ 1);
+    gload(min(t + 2, ntiles - 1));
 #pragma unroll
-    for (int i = 0; i < 16; ++i) ssum += __builtin_amdgcn_exp2f(c[i]);
-    acc += (double)ssum;
-    if (t + 1 < ntiles) lstore(buf ^ 1);
+    for (int i = 0; i < NMMA; ++i) {
+      __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+      __builtin_amdgcn_sched_group_barrier(0x002, (40 + NMMA - 1) / NMMA, 0);
+    }
+  };
+
+  gload(0);
+  lstore(0);
+  gload(min(1, ntiles - 1));
+  f32x16 ca, cb;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) ca[i] = kPadOffset;  // exp2 -> 0: neutral first epilogue
+  int t = 0;
+  for (; t + 1 < ntiles; t += 2) {
+    step(t, ca, cb);
+    step(t + 1, cb, ca);
+  }
+  if (t < ntiles) {
+    step(t, ca, cb);
+    ca = cb;
+  }
+  {
+    float cp[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) cp[i] = ca[i];
+    acc += (double)exp2_tile_sum(cp);
   }
   const double other = __shfl_down(acc, 32);
   if (h == 0) partial[(int64_t)chunk * m_pad + qi] = acc + other;
@@ -408,7 +495,8 @@ stag_status launch_prep(const float* src, int64_t n, int d, int dp, int64_t rows
                         int is_query, void* const* parts, float* off, u16x8* aug, double* nrm,
                         unsigned long long* maxbits, hipStream_t st) {
   ScopedTimer tm("kde_prep", st);
-  hipLaunchKernelGGL(prep_rows<FORM>, dim3((unsigned)ceil_div(rows_pad, 4)), dim3(256), 0, st, src, n, d, dp,
+  hipLaunchKernelGGL(prep_rows<FORM>, dim3((unsigned)ceil_div(rows_pad, kPrepRowsPerBlock)), dim3(256), 0, st, src,
+                     n, d, dp,
                      rows_pad, scale, neg_a_l2e, is_query, parts[0], parts[1], parts[2], off, aug, nrm, maxbits);
   return check_launch("prep_rows");
 }
@@ -466,8 +554,11 @@ stag_status prepare_operands(int form, const float* src, int64_t rows, int d, do
     out->aug = v;
   }
   STAG_TRY(ws.alloc(&out->nrm, (size_t)rows));
-  STAG_TRY(ws.alloc(&out->max_nrm_bits, 1));
-  STAG_HIP(hipMemsetAsync(out->max_nrm_bits, 0, sizeof(unsigned long long), st));
+  out->max_nrm_bits = nullptr;
+  if (!is_query) {
+    STAG_TRY(ws.alloc(&out->max_nrm_bits, 1));
+    STAG_HIP(hipMemsetAsync(out->max_nrm_bits, 0, sizeof(unsigned long long), st));
+  }
   const double scale = is_query ? 2.0 * a * kLog2e : 1.0;
   return prep_any(form, src, rows, d, dp, rows_pad, scale, -a * kLog2e, is_query ? 1 : 0, out->part, out->off,
                   static_cast<u16x8*>(out->aug), out->nrm, out->max_nrm_bits, st);

@@ -1,0 +1,869 @@
+// CKNS kernel density estimator on E2LSH tables (Sec. "The CKNS Algorithm":
+// levels L_i of points whose kernel value lies in (2^-i, 2^-i+1], log n
+// subsamples drawn with probability 2^-i, one E2LSH table set per subsample
+// to recover L_i, the importance-weighted sum, independent repetitions;
+// constructor parameters eps, min_mu, K1, K2_constant, p_offset of
+// CKNSGaussianKDE).
+//
+// Readings taken where the paper is silent (same as the library docs):
+//   J = ceil(log2(1/mu_min)) levels, T_i = i ln2 / a, level i holds
+//   T_{i-1} <= D < T_i; p_i = min(1, 2^-i/(n mu_min)) 2^-p_offset; L =
+//   ceil(K2_constant) tables per level (default ceil(log2 n)); K the largest
+//   with 1-(1-p(1)^K)^L >= 1 - eps/4; K1 = ceil(log2(n)/eps^2) copies; level i
+//   hashes the space scaled by r_i = sqrt(T_i); a point found in several tables
+//   of one level counts once (first table); each accepted term is reweighted
+//   by 1/(p_i R_i) with R_i the recovery probability at its scaled distance
+//   (1/p_i alone with STAG_LSH_LITERAL); copies are averaged.
+//
+// Device layout of an index (M = total sampled points over all copies/levels,
+// segment s = t*J + (i-1), table group g = s*L + l):
+//   X          [n][dx]       fp32 copy of the data (dx = d rounded up to 4)
+//   G8         [K1 J L][nch][dg][8] binary64 level-scaled projections
+//   B          [K1 J L][K]   offsets
+//   seg_off    [K1 J + 1]    start of each segment in members/mkeys
+//   members    [M]           point index, ascending within a segment
+//   mkeys      [M][L]        bucket key of each member in each table
+//   tab_*      per group an open-addressing table (capacity cap_s, a power of
+//              two >= 2 |segment|): key, start and count of its bucket
+//   csr        [M][L]        per group, member positions grouped by bucket,
+//              ascending within a bucket (deterministic construction)
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "e2lsh.h"
+#include "lsh.h"
+#include "runtime.h"
+#include "scan.h"
+
+namespace stag {
+namespace {
+
+constexpr uint64_t kGamma = 0x9E3779B97F4A7C15ULL;
+constexpr uint64_t kTagMask = 0x4D41534BULL;
+constexpr uint64_t kTagProj = 0x50524F4AULL;
+constexpr uint64_t kTagOffs = 0x4F464653ULL;
+constexpr uint64_t kEmpty = 0xFFFFFFFFFFFFFFFFULL;
+constexpr int kMaskBlock = 1024;  // points per counting block (4 per thread)
+
+// State of the SplitMix64 stream (seed, tag, a, b); output c of it is
+// mix64(state + (c + 1) gamma).
+__host__ __device__ inline uint64_t mix64_hd(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+  return z ^ (z >> 31);
+}
+__host__ __device__ inline uint64_t stream_state(uint64_t seed, uint64_t tag, uint64_t a, uint64_t b) {
+  return mix64_hd(mix64_hd(mix64_hd(seed ^ tag) ^ a) ^ b);
+}
+
+// ---------------------------------------------------------------------------
+// randomness and projections
+// ---------------------------------------------------------------------------
+
+// Default randomness when the caller passes none: g ~ N(0,1) by Box-Muller on
+// two counter uniforms, b = 4 U.
+__global__ void gen_randomness(uint64_t seed, int64_t nproj, int d, float* __restrict__ G0,
+                               double* __restrict__ B) {
+  const int64_t total = nproj * d;
+  const uint64_t sp = stream_state(seed, kTagProj, 0, 0);
+  const uint64_t so = stream_state(seed, kTagOffs, 0, 0);
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const double u1 = (double)((mix64_hd(sp + (uint64_t)(2 * e + 1) * kGamma) >> 11) + 1) * 0x1.0p-53;  // (0,1]
+    const double u2 = (double)(mix64_hd(sp + (uint64_t)(2 * e + 2) * kGamma) >> 11) * 0x1.0p-53;
+    G0[e] = (float)(sqrt(-2.0 * log(u1)) * cos(6.283185307179586477 * u2));
+    if (e < nproj) B[e] = 4.0 * (double)(mix64_hd(so + (uint64_t)(e + 1) * kGamma) >> 11) * 0x1.0p-53;
+  }
+}
+
+// G8[tab][c][j][e] = fp32(G0[tab][8c+e][j] / r_i) as binary64 (0 beyond K, d).
+__global__ void scale_projections(const float* __restrict__ G0, int64_t ntab, int J, int L, int K, int d, int dg,
+                                  int nch, const double* __restrict__ rlev, double* __restrict__ G8) {
+  const int64_t total = ntab * nch * dg * 8;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int e = (int)(idx & 7);
+    const int64_t r = idx >> 3;
+    const int j = (int)(r % dg);
+    const int64_t tc = r / dg;
+    const int c = (int)(tc % nch);
+    const int64_t tab = tc / nch;
+    const int k = 8 * c + e;
+    const int i = (int)((tab / L) % J) + 1;
+    double v = 0.0;
+    if (k < K && j < d) v = (double)(float)((double)G0[(tab * K + k) * d + j] / rlev[i]);
+    G8[idx] = v;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// subsampling: count per (segment, block of points), then scatter in order
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void mask_count(uint64_t seed, int J, int64_t n, int nblk,
+                                                  const uint64_t* __restrict__ thr, uint32_t* __restrict__ cnt) {
+  const int seg = blockIdx.y;
+  const int t = seg / J, i = seg % J + 1;
+  const uint64_t st = stream_state(seed, kTagMask, (uint64_t)t, (uint64_t)i);
+  const uint64_t th = thr[i];
+  const int64_t j0 = (int64_t)blockIdx.x * kMaskBlock + threadIdx.x * 4;
+  uint32_t c = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int64_t j = j0 + k;
+    if (j < n && (mix64_hd(st + (uint64_t)(j + 1) * kGamma) >> 11) < th) ++c;
+  }
+  for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o);
+  __shared__ uint32_t ws[4];
+  if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) cnt[(int64_t)seg * nblk + blockIdx.x] = ws[0] + ws[1] + ws[2] + ws[3];
+}
+
+__global__ __launch_bounds__(256) void mask_scatter(uint64_t seed, int J, int64_t n, int nblk,
+                                                    const uint64_t* __restrict__ thr,
+                                                    const uint64_t* __restrict__ off, int32_t* __restrict__ members) {
+  const int seg = blockIdx.y;
+  const int t = seg / J, i = seg % J + 1;
+  const uint64_t st = stream_state(seed, kTagMask, (uint64_t)t, (uint64_t)i);
+  const uint64_t th = thr[i];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __shared__ uint32_t ws[4];
+  // four passes of 256 consecutive points keep the output in ascending order
+  uint64_t base = off[(int64_t)seg * nblk + blockIdx.x];
+  for (int k = 0; k < 4; ++k) {
+    const int64_t j = (int64_t)blockIdx.x * kMaskBlock + k * 256 + threadIdx.x;
+    const bool keep = j < n && (mix64_hd(st + (uint64_t)(j + 1) * kGamma) >> 11) < th;
+    const uint64_t bal = __ballot(keep);
+    const uint32_t before = __popcll(bal & ((1ULL << lane) - 1ULL));
+    if (lane == 0) ws[wave] = __popcll(bal);
+    __syncthreads();
+    uint32_t wbase = 0;
+    for (int w = 0; w < wave; ++w) wbase += ws[w];
+    if (keep) members[base + wbase + before] = (int32_t)j;
+    base += ws[0] + ws[1] + ws[2] + ws[3];
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// hashing of the sampled points: one lane per member, waves over tables
+// ---------------------------------------------------------------------------
+struct MemberBlock {
+  int32_t seg;
+  int32_t u0;
+};
+
+template <int DREG>
+__global__ __launch_bounds__(256) void hash_members(const float* __restrict__ X, int dx, int d, int dg,
+                                                    const MemberBlock* __restrict__ blocks,
+                                                    const uint64_t* __restrict__ seg_off,
+                                                    const int32_t* __restrict__ members, const double* __restrict__ G8,
+                                                    const double* __restrict__ B, int K, int L, int nch,
+                                                    uint64_t* __restrict__ mkeys) {
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const MemberBlock blk = blocks[blockIdx.x];
+  const int64_t s0 = (int64_t)seg_off[blk.seg];
+  const int64_t cnt = (int64_t)seg_off[blk.seg + 1] - s0;
+  const int64_t u = blk.u0 + lane;
+  const bool live = u < cnt;
+  const int32_t j = members[s0 + (live ? u : 0)];
+  const float* xrow = X + (int64_t)j * dx;
+  double xr[DREG > 0 ? DREG : 1];
+  load_point<DREG>(xr, xrow, d);
+  for (int l = wave; l < L; l += 4) {
+    const int64_t tab = (int64_t)blk.seg * L + l;
+    const uint64_t key =
+        table_key<DREG>(l, xr, xrow, d, dg, G8 + tab * nch * dg * 8, B + tab * K, K, nch, nullptr);
+    if (live) mkeys[(s0 + u) * L + l] = key;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// bucket tables: one workgroup per table group
+// ---------------------------------------------------------------------------
+__device__ inline uint32_t probe_insert(uint64_t* __restrict__ keys, uint32_t mask, uint64_t key) {
+  uint32_t s = (uint32_t)key & mask;
+  while (true) {
+    const unsigned long long prev =
+        atomicCAS(reinterpret_cast<unsigned long long*>(keys + s), (unsigned long long)kEmpty,
+                  (unsigned long long)key);
+    if (prev == kEmpty || prev == key) return s;
+    s = (s + 1) & mask;
+  }
+}
+
+__device__ inline uint32_t lookup_present(const uint64_t* __restrict__ keys, uint32_t mask, uint64_t key) {
+  uint32_t s = (uint32_t)key & mask;
+  while (keys[s] != key) s = (s + 1) & mask;
+  return s;
+}
+
+__global__ __launch_bounds__(256) void build_tables(int L, const uint64_t* __restrict__ seg_off,
+                                                    const uint64_t* __restrict__ tab_seg_off,
+                                                    const uint32_t* __restrict__ seg_cap,
+                                                    const uint64_t* __restrict__ mkeys, uint64_t* __restrict__ tab_key,
+                                                    uint32_t* __restrict__ tab_start, uint32_t* __restrict__ tab_cnt,
+                                                    uint32_t* __restrict__ cursor, int32_t* __restrict__ csr) {
+  const int64_t g = blockIdx.x;
+  const int seg = (int)(g / L), l = (int)(g % L);
+  const int64_t s0 = (int64_t)seg_off[seg];
+  const int64_t cnt = (int64_t)seg_off[seg + 1] - s0;
+  if (cnt == 0) return;
+  const uint32_t cap = seg_cap[seg], mask = cap - 1;
+  const int64_t tb = (int64_t)tab_seg_off[seg] + (int64_t)l * cap;
+  uint64_t* tk = tab_key + tb;
+  uint32_t* tc = tab_cnt + tb;
+  uint32_t* ts = tab_start + tb;
+  uint32_t* cur = cursor + tb;
+  const uint64_t* mk = mkeys + s0 * L + l;
+  int32_t* out = csr + s0 * L + (int64_t)l * cnt;
+  const int tid = threadIdx.x;
+  for (uint32_t s = tid; s < cap; s += 256) {
+    tk[s] = kEmpty;
+    tc[s] = 0;
+    cur[s] = 0;
+  }
+  __syncthreads();
+  for (int64_t u = tid; u < cnt; u += 256) {
+    const uint32_t s = probe_insert(tk, mask, mk[u * L]);
+    atomicAdd(tc + s, 1u);
+  }
+  __syncthreads();
+  // exclusive scan of the counts over the slots
+  __shared__ uint32_t wsum[4];
+  __shared__ uint32_t carry;
+  if (tid == 0) carry = 0;
+  __syncthreads();
+  for (uint32_t s0c = 0; s0c < cap; s0c += 256) {
+    const uint32_t s = s0c + tid;
+    const uint32_t v = s < cap ? tc[s] : 0;
+    uint32_t inc = v;
+    const int lane = tid & 63, wave = tid >> 6;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t y = __shfl_up(inc, o);
+      if (lane >= o) inc += y;
+    }
+    if (lane == 63) wsum[wave] = inc;
+    __syncthreads();
+    uint32_t wb = 0;
+    for (int w = 0; w < wave; ++w) wb += wsum[w];
+    if (s < cap) ts[s] = carry + wb + inc - v;
+    __syncthreads();
+    if (tid == 0) carry += wsum[0] + wsum[1] + wsum[2] + wsum[3];
+    __syncthreads();
+  }
+  // place members in ascending order within each bucket
+  __shared__ uint32_t sl[256];
+  for (int64_t c0 = 0; c0 < cnt; c0 += 256) {
+    const int64_t u = c0 + tid;
+    const bool valid = u < cnt;
+    const uint32_t s = valid ? lookup_present(tk, mask, mk[u * L]) : 0xFFFFFFFFu;
+    sl[tid] = s;
+    __syncthreads();
+    if (valid) {
+      uint32_t rank = 0;
+      for (int k = 0; k < tid; ++k) rank += (sl[k] == s) ? 1u : 0u;
+      out[ts[s] + cur[s] + rank] = (int32_t)u;
+    }
+    __syncthreads();
+    if (valid) atomicAdd(cur + s, 1u);
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// queries
+// ---------------------------------------------------------------------------
+template <int DREG>
+__global__ __launch_bounds__(256) void hash_queries(const float* __restrict__ Q, int64_t q0, int64_t mb, int d,
+                                                    int dg, const double* __restrict__ G8,
+                                                    const double* __restrict__ B, int K, int L, int nch,
+                                                    int64_t ntab, int tpw, uint64_t* __restrict__ qkeys) {
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t ql = (int64_t)blockIdx.x * 64 + lane;
+  const bool live = ql < mb;
+  const float* xrow = Q + (q0 + (live ? ql : 0)) * d;
+  double xr[DREG > 0 ? DREG : 1];
+  load_point<DREG>(xr, xrow, d);
+  const int64_t t0 = ((int64_t)blockIdx.y * 4 + wave) * tpw;
+  for (int64_t tab = t0; tab < t0 + tpw && tab < ntab; ++tab) {
+    const int l = (int)(tab % L);
+    const uint64_t key =
+        table_key<DREG>(l, xr, xrow, d, dg, G8 + tab * nch * dg * 8, B + tab * K, K, nch, nullptr);
+    if (live) qkeys[ql * ntab + tab] = key;
+  }
+}
+
+__device__ inline double collision_p_dev(double c) {
+  if (c <= 0.0) return 1.0;
+  const double inv_sqrt_2pi = 0.39894228040143267794;
+  return erf(2.0 * sqrt(2.0) / c) - 0.5 * inv_sqrt_2pi * c * (-expm1(-8.0 / (c * c)));
+}
+
+__device__ inline double recovery_dev(double c, int K, int L) {
+  const double x = pow(collision_p_dev(c), (double)K);
+  if (x >= 1.0) return 1.0;
+  return -expm1((double)L * log1p(-x));
+}
+
+struct LevelConst {
+  double p[65], T[65], r[65];
+};
+
+// One wave per (query, copy): levels and tables in order, lanes over the
+// members of each bucket.
+template <int DREG>
+__global__ __launch_bounds__(256) void probe_queries(
+    const float* __restrict__ Q, int64_t q0, int64_t mb, int d, int dx, const float* __restrict__ X, int K1, int J,
+    int L, int K, double a, int literal, LevelConst lc, const uint64_t* __restrict__ qkeys, int64_t ntab,
+    const uint64_t* __restrict__ seg_off, const int32_t* __restrict__ members, const uint64_t* __restrict__ mkeys,
+    const uint64_t* __restrict__ tab_seg_off, const uint32_t* __restrict__ seg_cap,
+    const uint64_t* __restrict__ tab_key, const uint32_t* __restrict__ tab_start,
+    const uint32_t* __restrict__ tab_cnt, const int32_t* __restrict__ csr, double* __restrict__ Scopy,
+    int64_t* __restrict__ ncand, int64_t* __restrict__ nacc) {
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int64_t pair = (int64_t)blockIdx.x * 4 + wave;
+  if (pair >= mb * K1) return;
+  const int64_t ql = pair / K1;
+  const int t = (int)(pair % K1);
+  const float* qrow = Q + (q0 + ql) * d;
+  double qr[DREG > 0 ? DREG : 1];
+  load_point<DREG>(qr, qrow, d);
+  __shared__ uint64_t qk_s[4][64];
+  double acc = 0.0;
+  int64_t nc = 0, na = 0;
+  for (int i = 1; i <= J; ++i) {
+    const int seg = t * J + (i - 1);
+    const int64_t s0 = (int64_t)seg_off[seg];
+    const int64_t cnt = (int64_t)seg_off[seg + 1] - s0;
+    if (cnt == 0) continue;
+    const uint32_t cap = seg_cap[seg], mask = cap - 1;
+    const double Tlo = lc.T[i - 1], Thi = lc.T[i], pi = lc.p[i], ri = lc.r[i];
+    const uint64_t* qk = qkeys + ql * ntab + (int64_t)seg * L;
+    for (int l0 = 0; l0 < L; l0 += 64) {
+      if (l0 + lane < L) qk_s[wave][l0 + lane] = qk[l0 + lane];
+    }
+    __builtin_amdgcn_wave_barrier();
+    for (int l = 0; l < L; ++l) {
+      const uint64_t key = qk_s[wave][l];
+      const int64_t tb = (int64_t)tab_seg_off[seg] + (int64_t)l * cap;
+      // lane-parallel linear probe: first slot holding the key or empty
+      uint32_t slot = 0;
+      bool found = false;
+      for (uint32_t p0 = 0; p0 < cap; p0 += 64) {
+        const uint32_t s = ((uint32_t)key + p0 + lane) & mask;
+        const uint64_t v = (p0 + lane < cap) ? tab_key[tb + s] : kEmpty;
+        const uint64_t hit = __ballot(v == key);
+        const uint64_t emp = __ballot(v == kEmpty);
+        if (hit != 0 || emp != 0) {
+          const int fh = hit ? __ffsll((long long)hit) - 1 : 64;
+          const int fe = emp ? __ffsll((long long)emp) - 1 : 64;
+          if (fh < fe) {
+            found = true;
+            slot = ((uint32_t)key + p0 + fh) & mask;
+          }
+          break;
+        }
+      }
+      if (!found) continue;
+      const uint32_t start = tab_start[tb + slot], c = tab_cnt[tb + slot];
+      const int32_t* bucket = csr + s0 * L + (int64_t)l * cnt + start;
+      for (uint32_t k = lane; k < c; k += 64) {
+        const int32_t u = bucket[k];
+        ++nc;
+        const uint64_t* mk = mkeys + (s0 + u) * L;
+        bool seen = false;
+        for (int l2 = 0; l2 < l; ++l2)
+          if (mk[l2] == qk_s[wave][l2]) {
+            seen = true;
+            break;
+          }
+        if (seen) continue;
+        const float* xrow = X + (int64_t)members[s0 + u] * dx;
+        double D = 0.0;
+        if constexpr (DREG > 0) {
+#pragma unroll
+          for (int h = 0; h < DREG; ++h) {
+            if (h < d) {
+              const double dl = qr[h] - (double)xrow[h];
+              D = __builtin_fma(dl, dl, D);
+            }
+          }
+        } else {
+          for (int h = 0; h < d; ++h) {
+            const double dl = (double)qrow[h] - (double)xrow[h];
+            D = __builtin_fma(dl, dl, D);
+          }
+        }
+        if (!(D >= Tlo && D < Thi)) continue;
+        const double R = literal ? 1.0 : recovery_dev(sqrt(D) / ri, K, L);
+        acc += exp(-a * D) / (pi * R);
+        ++na;
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    acc += __shfl_xor(acc, o);
+    nc += __shfl_xor(nc, o);
+    na += __shfl_xor(na, o);
+  }
+  if (lane == 0) {
+    Scopy[ql * K1 + t] = acc;
+    if (ncand) atomicAdd(reinterpret_cast<unsigned long long*>(ncand + q0 + ql), (unsigned long long)nc);
+    if (nacc) atomicAdd(reinterpret_cast<unsigned long long*>(nacc + q0 + ql), (unsigned long long)na);
+  }
+}
+
+__global__ void mean_copies(const double* __restrict__ Scopy, int64_t q0, int64_t mb, int K1,
+                            double* __restrict__ S_out, double* __restrict__ copies_out) {
+  const int64_t ql = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (ql >= mb) return;
+  double s = 0.0;
+  for (int t = 0; t < K1; ++t) {
+    const double v = Scopy[ql * K1 + t];
+    s += v;
+    if (copies_out) copies_out[(q0 + ql) * K1 + t] = v;
+  }
+  S_out[q0 + ql] = s / (double)K1;
+}
+
+__global__ void zero_i64(int64_t* p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+
+int ceil_log2_i64(int64_t n) {
+  int J = 0;
+  while (((int64_t)1 << J) < n) ++J;
+  return J;
+}
+
+double collision_p_host(double c) {
+  if (c <= 0.0) return 1.0;
+  const double inv_sqrt_2pi = 0.39894228040143267794;
+  return std::erf(2.0 * std::sqrt(2.0) / c) - 0.5 * inv_sqrt_2pi * c * (-std::expm1(-8.0 / (c * c)));
+}
+
+double recovery_host(double c, int K, int L) {
+  const double x = std::pow(collision_p_host(c), (double)K);
+  if (x >= 1.0) return 1.0;
+  return -std::expm1((double)L * std::log1p(-x));
+}
+
+}  // namespace
+
+// Parameter reading for CKNSGaussianKDE(data, a, eps, min_mu, K1, K2_constant,
+// p_offset); see the file header.
+stag_status lsh_derive_params(int64_t n, double a, double eps, const stag_lsh_params* p, LshParams* out) {
+  stag_lsh_params dflt = {};
+  if (!p) p = &dflt;
+  if (n < 1) return fail(STAG_E_INVAL, "lsh: n must be >= 1");
+  if (!(a > 0.0) || !std::isfinite(a)) return fail(STAG_E_INVAL, "lsh: a must be positive and finite");
+  if (!(eps > 0.0 && eps < 1.0)) return fail(STAG_E_INVAL, "lsh: eps must be in (0, 1)");
+  if (p->p_offset < 0 || p->p_offset > 60) return fail(STAG_E_INVAL, "lsh: p_offset must be in [0, 60]");
+  if (p->flags & ~(uint32_t)(STAG_LSH_LITERAL | STAG_LSH_ALL_SAMPLED))
+    return fail(STAG_E_INVAL, "lsh: unknown flags 0x%x", p->flags);
+  LshParams& s = *out;
+  s.flags = p->flags;
+  s.seed = p->seed;
+  const bool default_mu = !(p->min_mu > 0.0);
+  s.shape.mu_min = default_mu ? 1.0 / (double)n : p->min_mu;
+  int J = default_mu ? ceil_log2_i64(n) : (int)std::ceil(std::log2(1.0 / s.shape.mu_min));
+  if (J < 1) J = 1;
+  if (J > 64) return fail(STAG_E_INVAL, "lsh: min_mu too small (more than 64 levels)");
+  s.shape.J = J;
+  const int L = (p->k2_constant > 0.0) ? (int)std::ceil(std::min(p->k2_constant, 1e6)) : std::max(1, ceil_log2_i64(n));
+  if (L > 64) return fail(STAG_E_UNSUPPORTED, "lsh: at most 64 tables per level (K2_constant <= 64)");
+  s.shape.L = L;
+  int K = 1;
+  for (int k = 2; k <= 64; ++k) {
+    if (recovery_host(1.0, k, L) >= 1.0 - eps / 4.0) K = k;
+    else break;
+  }
+  s.shape.K = K;
+  s.shape.K1 = (p->k1 > 0) ? p->k1 : std::max(1, (int)std::ceil(std::log2((double)n) / (eps * eps)));
+  const double ln2 = std::log(2.0);
+  s.lc_p[0] = 1.0;
+  s.lc_T[0] = 0.0;
+  s.lc_r[0] = 0.0;
+  s.thr[0] = 0;
+  for (int i = 1; i <= J; ++i) {
+    double pi;
+    if (p->flags & STAG_LSH_ALL_SAMPLED) pi = 1.0;
+    else if (default_mu) pi = std::ldexp(1.0, -i - p->p_offset);
+    else pi = std::min(1.0, std::ldexp(1.0, -i) / ((double)n * s.shape.mu_min)) * std::ldexp(1.0, -p->p_offset);
+    s.lc_p[i] = pi;
+    s.thr[i] = (uint64_t)std::ldexp(pi, 53);
+    s.lc_T[i] = (double)i * ln2 / a;
+    s.lc_r[i] = std::sqrt(s.lc_T[i]);
+  }
+  s.a = a;
+  s.eps = eps;
+  s.n = n;
+  return STAG_OK;
+}
+
+}  // namespace stag
+
+// ---------------------------------------------------------------------------
+// index object
+// ---------------------------------------------------------------------------
+struct stag_lsh_index {
+  stag::LshParams prm;
+  int d = 0, dx = 0, dg = 0, nch = 0, dreg = 0;
+  int64_t nseg = 0, ntab = 0, M = 0, total_slots = 0;
+  int device = 0;
+  std::vector<uint64_t> h_seg_off;
+  std::vector<void*> owned;
+  float* X = nullptr;
+  double* G8 = nullptr;
+  double* B = nullptr;
+  uint64_t* seg_off = nullptr;
+  int32_t* members = nullptr;
+  uint64_t* mkeys = nullptr;
+  uint64_t* tab_seg_off = nullptr;
+  uint32_t* seg_cap = nullptr;
+  uint64_t* tab_key = nullptr;
+  uint32_t* tab_start = nullptr;
+  uint32_t* tab_cnt = nullptr;
+  int32_t* csr = nullptr;
+  double* rlev = nullptr;
+  uint64_t* thr = nullptr;
+};
+
+namespace stag {
+namespace {
+
+template <typename T>
+stag_status own_alloc(stag_lsh_index* idx, T** p, size_t count) {
+  void* v = nullptr;
+  hipError_t e = hipMalloc(&v, std::max<size_t>(count * sizeof(T), 256));
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(e == hipErrorOutOfMemory ? STAG_E_NOMEM : STAG_E_DEVICE, "lsh index allocation of %zu bytes: %s",
+                count * sizeof(T), hipGetErrorString(e));
+  }
+  idx->owned.push_back(v);
+  *p = static_cast<T*>(v);
+  return STAG_OK;
+}
+
+void free_index(stag_lsh_index* idx) {
+  if (!idx) return;
+  for (void* p : idx->owned) (void)hipFree(p);
+  delete idx;
+}
+
+template <typename F>
+stag_status dispatch_dreg(int dreg, F&& f) {
+  switch (dreg) {
+    case 16: return f(std::integral_constant<int, 16>());
+    case 32: return f(std::integral_constant<int, 32>());
+    case 64: return f(std::integral_constant<int, 64>());
+    default: return f(std::integral_constant<int, 0>());
+  }
+}
+
+__global__ void copy_rows(const float* __restrict__ src, int64_t n, int d, int dx, float* __restrict__ dst) {
+  const int64_t total = n * dx;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = e / dx;
+    const int c = (int)(e % dx);
+    dst[e] = c < d ? src[r * d + c] : 0.0f;
+  }
+}
+
+stag_status create_index(const float* X, int64_t n, int d, double a, double eps, const stag_lsh_params* p,
+                         stag_lsh_index* idx, hipStream_t st) {
+  STAG_TRY(lsh_derive_params(n, a, eps, p, &idx->prm));
+  LshParams& prm = idx->prm;
+  const int J = prm.shape.J, L = prm.shape.L, K = prm.shape.K, K1 = prm.shape.K1;
+  idx->d = d;
+  idx->dx = (int)round_up(d, 4);
+  idx->dreg = e2lsh_reg_dim(d);
+  idx->dg = idx->dreg > 0 ? idx->dreg : d;
+  idx->nch = (int)ceil_div(K, 8);
+  idx->nseg = (int64_t)K1 * J;
+  idx->ntab = idx->nseg * L;
+  const int64_t nproj = idx->ntab * K;
+  Workspace ws(st);
+
+  STAG_TRY(own_alloc(idx, &idx->X, (size_t)n * idx->dx));
+  hipLaunchKernelGGL(copy_rows, dim3((unsigned)std::min<int64_t>(ceil_div(n * idx->dx, 256), 65536)), dim3(256), 0,
+                     st, X, n, d, idx->dx, idx->X);
+  STAG_TRY(check_launch("copy_rows"));
+
+  // level constants
+  STAG_TRY(own_alloc(idx, &idx->rlev, 65));
+  STAG_TRY(own_alloc(idx, &idx->thr, 65));
+  STAG_HIP(hipMemcpyAsync(idx->rlev, prm.lc_r, sizeof(double) * (J + 1), hipMemcpyHostToDevice, st));
+  STAG_HIP(hipMemcpyAsync(idx->thr, prm.thr, sizeof(uint64_t) * (J + 1), hipMemcpyHostToDevice, st));
+
+  // projections and offsets
+  const float* G0 = p ? p->G0 : nullptr;
+  STAG_TRY(own_alloc(idx, &idx->B, (size_t)nproj));
+  if (p && p->b) {
+    STAG_HIP(hipMemcpyAsync(idx->B, p->b, sizeof(double) * nproj, hipMemcpyDeviceToDevice, st));
+  }
+  if (!G0 || !(p && p->b)) {
+    float* g = nullptr;
+    STAG_TRY(ws.alloc(&g, (size_t)nproj * d));
+    double* bb = nullptr;
+    STAG_TRY(ws.alloc(&bb, (size_t)nproj));
+    {
+      ScopedTimer tm("lsh_gen_randomness", st);
+      hipLaunchKernelGGL(gen_randomness, dim3((unsigned)std::min<int64_t>(ceil_div(nproj * d, 256), 65536)),
+                         dim3(256), 0, st, prm.seed, nproj, d, g, bb);
+    }
+    STAG_TRY(check_launch("gen_randomness"));
+    if (!G0) G0 = g;
+    if (!(p && p->b)) STAG_HIP(hipMemcpyAsync(idx->B, bb, sizeof(double) * nproj, hipMemcpyDeviceToDevice, st));
+  }
+  STAG_TRY(own_alloc(idx, &idx->G8, (size_t)idx->ntab * idx->nch * idx->dg * 8));
+  {
+    ScopedTimer tm("lsh_scale_projections", st);
+    const int64_t tot = idx->ntab * idx->nch * idx->dg * 8;
+    hipLaunchKernelGGL(scale_projections, dim3((unsigned)std::min<int64_t>(ceil_div(tot, 256), 65536)), dim3(256), 0,
+                       st, G0, idx->ntab, J, L, K, d, idx->dg, idx->nch, idx->rlev, idx->G8);
+  }
+  STAG_TRY(check_launch("scale_projections"));
+
+  // subsamples
+  const int nblk = (int)ceil_div(n, kMaskBlock);
+  if (idx->nseg > 65535) return fail(STAG_E_UNSUPPORTED, "lsh: K1*J = %lld segments exceeds 65535", (long long)idx->nseg);
+  uint32_t* cnt = nullptr;
+  uint64_t* off = nullptr;
+  const int64_t ncnt = idx->nseg * nblk;
+  STAG_TRY(ws.alloc(&cnt, (size_t)ncnt));
+  STAG_TRY(ws.alloc(&off, (size_t)ncnt + 1));
+  {
+    ScopedTimer tm("lsh_mask", st);
+    hipLaunchKernelGGL(mask_count, dim3(nblk, (unsigned)idx->nseg), dim3(256), 0, st, prm.seed, J, n, nblk, idx->thr,
+                       cnt);
+    STAG_TRY(check_launch("mask_count"));
+    STAG_TRY(exclusive_scan_u32(cnt, off, ncnt, ws, st));
+  }
+  // segment offsets: off[seg * nblk]; bring them to the host (one synchronisation)
+  std::vector<uint64_t> all_off((size_t)ncnt + 1);
+  STAG_HIP(hipMemcpyAsync(all_off.data(), off, sizeof(uint64_t) * (ncnt + 1), hipMemcpyDeviceToHost, st));
+  STAG_HIP(hipStreamSynchronize(st));
+  idx->h_seg_off.resize((size_t)idx->nseg + 1);
+  for (int64_t s = 0; s < idx->nseg; ++s) idx->h_seg_off[s] = all_off[(size_t)s * nblk];
+  idx->h_seg_off[idx->nseg] = all_off[ncnt];
+  idx->M = (int64_t)idx->h_seg_off[idx->nseg];
+  STAG_TRY(own_alloc(idx, &idx->seg_off, (size_t)idx->nseg + 1));
+  STAG_HIP(hipMemcpyAsync(idx->seg_off, idx->h_seg_off.data(), sizeof(uint64_t) * (idx->nseg + 1),
+                          hipMemcpyHostToDevice, st));
+  STAG_TRY(own_alloc(idx, &idx->members, (size_t)idx->M));
+  {
+    ScopedTimer tm("lsh_mask", st);
+    hipLaunchKernelGGL(mask_scatter, dim3(nblk, (unsigned)idx->nseg), dim3(256), 0, st, prm.seed, J, n, nblk,
+                       idx->thr, off, idx->members);
+  }
+  STAG_TRY(check_launch("mask_scatter"));
+
+  // member keys
+  STAG_TRY(own_alloc(idx, &idx->mkeys, (size_t)idx->M * L));
+  std::vector<MemberBlock> blocks;
+  std::vector<uint32_t> cap((size_t)idx->nseg);
+  std::vector<uint64_t> tso((size_t)idx->nseg + 1, 0);
+  for (int64_t s = 0; s < idx->nseg; ++s) {
+    const int64_t c = (int64_t)(idx->h_seg_off[s + 1] - idx->h_seg_off[s]);
+    for (int64_t u0 = 0; u0 < c; u0 += 64) blocks.push_back({(int32_t)s, (int32_t)u0});
+    uint32_t cp = 2;
+    while ((int64_t)cp < 2 * c) cp <<= 1;
+    cap[s] = c > 0 ? cp : 0;
+    tso[s + 1] = tso[s] + (uint64_t)cap[s] * L;
+  }
+  idx->total_slots = (int64_t)tso[idx->nseg];
+  if (!blocks.empty()) {
+    MemberBlock* dblk = nullptr;
+    STAG_TRY(ws.alloc(&dblk, blocks.size()));
+    STAG_HIP(hipMemcpyAsync(dblk, blocks.data(), sizeof(MemberBlock) * blocks.size(), hipMemcpyHostToDevice, st));
+    ScopedTimer tm("lsh_hash_members", st);
+    STAG_TRY(dispatch_dreg(idx->dreg, [&](auto D) {
+      hipLaunchKernelGGL(hash_members<decltype(D)::value>, dim3((unsigned)blocks.size()), dim3(256), 0, st, idx->X,
+                         idx->dx, d, idx->dg, dblk, idx->seg_off, idx->members, idx->G8, idx->B, K, L, idx->nch,
+                         idx->mkeys);
+      return check_launch("hash_members");
+    }));
+  }
+
+  // bucket tables
+  STAG_TRY(own_alloc(idx, &idx->seg_cap, (size_t)idx->nseg));
+  STAG_TRY(own_alloc(idx, &idx->tab_seg_off, (size_t)idx->nseg + 1));
+  STAG_HIP(hipMemcpyAsync(idx->seg_cap, cap.data(), sizeof(uint32_t) * idx->nseg, hipMemcpyHostToDevice, st));
+  STAG_HIP(hipMemcpyAsync(idx->tab_seg_off, tso.data(), sizeof(uint64_t) * (idx->nseg + 1), hipMemcpyHostToDevice, st));
+  STAG_TRY(own_alloc(idx, &idx->tab_key, (size_t)idx->total_slots));
+  STAG_TRY(own_alloc(idx, &idx->tab_start, (size_t)idx->total_slots));
+  STAG_TRY(own_alloc(idx, &idx->tab_cnt, (size_t)idx->total_slots));
+  STAG_TRY(own_alloc(idx, &idx->csr, (size_t)idx->M * L));
+  uint32_t* cursor = nullptr;
+  STAG_TRY(ws.alloc(&cursor, (size_t)idx->total_slots));
+  if (idx->ntab > 0) {
+    ScopedTimer tm("lsh_build_tables", st);
+    hipLaunchKernelGGL(build_tables, dim3((unsigned)idx->ntab), dim3(256), 0, st, L, idx->seg_off, idx->tab_seg_off,
+                       idx->seg_cap, idx->mkeys, idx->tab_key, idx->tab_start, idx->tab_cnt, cursor, idx->csr);
+    STAG_TRY(check_launch("build_tables"));
+  }
+  STAG_HIP(hipGetDevice(&idx->device));
+  // the workspace (cursor, counts) is released in stream order
+  return STAG_OK;
+}
+
+stag_status query_index(const stag_lsh_index* idx, const float* Q, int64_t m, double* S_out, double* copies_out,
+                        int64_t* ncand, int64_t* nacc, hipStream_t st) {
+  const LshParams& prm = idx->prm;
+  const int J = prm.shape.J, L = prm.shape.L, K = prm.shape.K, K1 = prm.shape.K1;
+  const int d = idx->d;
+  Workspace ws(st);
+  // query batches: keys of one batch take at most ~1 GiB
+  int64_t mb = ((int64_t)1 << 30) / (8 * std::max<int64_t>(idx->ntab, 1)) / 64 * 64;
+  mb = std::max<int64_t>(64, std::min(mb, round_up(m, 64)));
+  uint64_t* qkeys = nullptr;
+  double* scopy = nullptr;
+  STAG_TRY(ws.alloc(&qkeys, (size_t)mb * idx->ntab));
+  STAG_TRY(ws.alloc(&scopy, (size_t)mb * K1));
+  if (ncand) hipLaunchKernelGGL(zero_i64, dim3((unsigned)ceil_div(m, 256)), dim3(256), 0, st, ncand, m);
+  if (nacc) hipLaunchKernelGGL(zero_i64, dim3((unsigned)ceil_div(m, 256)), dim3(256), 0, st, nacc, m);
+  LevelConst lc;
+  for (int i = 0; i <= 64; ++i) {
+    lc.p[i] = i <= J ? prm.lc_p[i] : 0.0;
+    lc.T[i] = i <= J ? prm.lc_T[i] : 0.0;
+    lc.r[i] = i <= J ? prm.lc_r[i] : 0.0;
+  }
+  const int literal = (prm.flags & STAG_LSH_LITERAL) ? 1 : 0;
+  for (int64_t q0 = 0; q0 < m; q0 += mb) {
+    const int64_t cur = std::min(mb, m - q0);
+    int tpw = 1;
+    const int64_t qblocks = ceil_div(cur, 64);
+    while (tpw < idx->ntab && (qblocks * ceil_div(idx->ntab, 4 * tpw) > 262144 || ceil_div(idx->ntab, 4 * tpw) > 65535))
+      tpw *= 2;
+    {
+      ScopedTimer tm("lsh_hash_queries", st);
+      STAG_TRY(dispatch_dreg(idx->dreg, [&](auto D) {
+        hipLaunchKernelGGL(hash_queries<decltype(D)::value>,
+                           dim3((unsigned)qblocks, (unsigned)ceil_div(idx->ntab, 4 * tpw)), dim3(256), 0, st, Q, q0,
+                           cur, d, idx->dg, idx->G8, idx->B, K, L, idx->nch, idx->ntab, tpw, qkeys);
+        return check_launch("hash_queries");
+      }));
+    }
+    {
+      ScopedTimer tm("lsh_probe", st);
+      STAG_TRY(dispatch_dreg(idx->dreg, [&](auto D) {
+        hipLaunchKernelGGL(probe_queries<decltype(D)::value>, dim3((unsigned)ceil_div(cur * K1, 4)), dim3(256), 0,
+                           st, Q, q0, cur, d, idx->dx, idx->X, K1, J, L, K, prm.a, literal, lc, qkeys, idx->ntab,
+                           idx->seg_off, idx->members, idx->mkeys, idx->tab_seg_off, idx->seg_cap, idx->tab_key,
+                           idx->tab_start, idx->tab_cnt, idx->csr, scopy, ncand, nacc);
+        return check_launch("probe_queries");
+      }));
+    }
+    hipLaunchKernelGGL(mean_copies, dim3((unsigned)ceil_div(cur, 256)), dim3(256), 0, st, scopy, q0, cur, K1, S_out,
+                       copies_out);
+    STAG_TRY(check_launch("mean_copies"));
+  }
+  return STAG_OK;
+}
+
+}  // namespace
+}  // namespace stag
+
+using namespace stag;
+
+extern "C" {
+
+stag_status stag_lsh_derive(int64_t n, double a, double eps, const stag_lsh_params* p, stag_lsh_shape* out) {
+  if (!out) return fail(STAG_E_INVAL, "stag_lsh_derive: out is NULL");
+  LshParams prm;
+  STAG_TRY(lsh_derive_params(n, a, eps, p, &prm));
+  *out = prm.shape;
+  return STAG_OK;
+}
+
+stag_status stag_lsh_index_create(const float* X, int64_t n, int32_t d, double a, double eps,
+                                  const stag_lsh_params* p, stag_lsh_index** out, hipStream_t stream) {
+  if (!out) return fail(STAG_E_INVAL, "stag_lsh_index_create: out is NULL");
+  *out = nullptr;
+  if (!X) return fail(STAG_E_INVAL, "stag_lsh_index_create: X is NULL");
+  if (n < 1 || n > 2147483647LL || d < 1 || d > 4096)
+    return fail(STAG_E_INVAL, "stag_lsh_index_create: need 1 <= n < 2^31 and 1 <= d <= 4096");
+  if ((p && p->G0) != (p && p->b))
+    return fail(STAG_E_INVAL, "stag_lsh_index_create: pass both G0 and b, or neither");
+  LshParams prm;
+  STAG_TRY(lsh_derive_params(n, a, eps, p, &prm));
+  clear_error();
+  stag_lsh_index* idx = new (std::nothrow) stag_lsh_index();
+  if (!idx) return fail(STAG_E_NOMEM, "stag_lsh_index_create: host allocation failed");
+  stag_status stt = create_index(X, n, d, a, eps, p, idx, stream);
+  if (stt != STAG_OK) {
+    (void)hipStreamSynchronize(stream);
+    free_index(idx);
+    return stt;
+  }
+  *out = idx;
+  return STAG_OK;
+}
+
+stag_status stag_lsh_index_shape(const stag_lsh_index* idx, stag_lsh_shape* out) {
+  if (!idx || !out) return fail(STAG_E_INVAL, "stag_lsh_index_shape: NULL argument");
+  *out = idx->prm.shape;
+  return STAG_OK;
+}
+
+stag_status stag_lsh_index_query_ex(const stag_lsh_index* idx, const float* Q, int64_t m, double* S_out,
+                                    double* S_copies, int64_t* n_cand, int64_t* n_acc, hipStream_t stream) {
+  if (!idx || !Q || !S_out) return fail(STAG_E_INVAL, "stag_lsh_index_query: NULL argument");
+  if (m < 1) return fail(STAG_E_INVAL, "stag_lsh_index_query: m must be >= 1");
+  clear_error();
+  return query_index(idx, Q, m, S_out, S_copies, n_cand, n_acc, stream);
+}
+
+stag_status stag_lsh_index_query(const stag_lsh_index* idx, const float* Q, int64_t m, double* S_out,
+                                 hipStream_t stream) {
+  return stag_lsh_index_query_ex(idx, Q, m, S_out, nullptr, nullptr, nullptr, stream);
+}
+
+stag_status stag_lsh_index_segment(const stag_lsh_index* idx, int32_t t, int32_t i, int64_t* count,
+                                   int32_t* members_host, uint64_t* keys_host, hipStream_t stream) {
+  if (!idx || !count) return fail(STAG_E_INVAL, "stag_lsh_index_segment: NULL argument");
+  const int J = idx->prm.shape.J, L = idx->prm.shape.L;
+  if (t < 0 || t >= idx->prm.shape.K1 || i < 1 || i > J)
+    return fail(STAG_E_INVAL, "stag_lsh_index_segment: (t, i) out of range");
+  const int64_t s = (int64_t)t * J + (i - 1);
+  const int64_t s0 = (int64_t)idx->h_seg_off[s], c = (int64_t)idx->h_seg_off[s + 1] - s0;
+  *count = c;
+  if (c > 0 && members_host)
+    STAG_HIP(hipMemcpyAsync(members_host, idx->members + s0, sizeof(int32_t) * c, hipMemcpyDeviceToHost, stream));
+  if (c > 0 && keys_host)
+    STAG_HIP(hipMemcpyAsync(keys_host, idx->mkeys + s0 * L, sizeof(uint64_t) * c * L, hipMemcpyDeviceToHost, stream));
+  STAG_HIP(hipStreamSynchronize(stream));
+  return STAG_OK;
+}
+
+void stag_lsh_index_destroy(stag_lsh_index* idx) {
+  if (!idx) return;
+  const int dev = idx->device;
+  int cur = dev;
+  if (hipGetDevice(&cur) == hipSuccess && cur != dev) (void)hipSetDevice(dev);
+  (void)hipDeviceSynchronize();
+  free_index(idx);
+  if (cur != dev) (void)hipSetDevice(cur);
+}
+
+stag_status stag_kde_lsh(const float* X, int64_t n, const float* Q, int64_t m, int32_t d, double a, double eps,
+                         const stag_lsh_params* p, double* S_out, hipStream_t stream) {
+  if (!Q || !S_out || m < 1) return fail(STAG_E_INVAL, "stag_kde_lsh: invalid query arguments");
+  stag_lsh_index* idx = nullptr;
+  STAG_TRY(stag_lsh_index_create(X, n, d, a, eps, p, &idx, stream));
+  stag_status st = stag_lsh_index_query(idx, Q, m, S_out, stream);
+  (void)hipStreamSynchronize(stream);
+  stag_lsh_index_destroy(idx);
+  return st;
+}
+
+}  // extern "C"

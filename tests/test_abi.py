@@ -49,3 +49,25 @@ def test_invalid_arguments_rejected_before_launch():
     assert st == _lib.STAG_E_INVAL
     st = lib.stag_e2lsh_hash(fake, 10, 4, fake, fake, 2, 3, null, null, null)
     assert st == _lib.STAG_E_INVAL
+
+
+@pytest.mark.parametrize("n", [1, 7, 1000, 100_000, 2_000_000])
+@pytest.mark.parametrize("kw", [dict(), dict(k1=10, k2_constant=5, p_offset=1, min_mu=1e-4),
+                                dict(k1=1, k2_constant=8, p_offset=1), dict(eps=0.2), dict(eps=0.9, k2_constant=3)])
+def test_lsh_parameter_reading_matches_oracle(orc, n, kw):
+    kw = dict(kw)
+    eps = kw.pop("eps", 0.5)
+    got = stag.lsh_derive(n, 0.01, eps, **kw)
+    ref = orc.lsh_derive(n, 0.01, eps, **kw)
+    for k in ("J", "L", "K", "K1"):
+        assert got[k] == ref[k], (k, got, ref)
+    assert got["mu_min"] == ref["mu_min"]
+
+
+def test_lsh_parameter_validation():
+    with pytest.raises(stag.StagError):
+        stag.lsh_derive(100, 0.01, 1.5)
+    with pytest.raises(stag.StagError):
+        stag.lsh_derive(100, -1.0, 0.5)
+    with pytest.raises(stag.StagError):
+        stag.lsh_derive(100, 0.01, 0.5, k2_constant=65)

@@ -1,0 +1,155 @@
+"""GPU parity of the CKNS estimator (Sec. "The CKNS Algorithm") against the
+oracle given the same stored projections, offsets and subsampling seed:
+subsamples, bucket keys and per-query candidate/accept counts are bit-exact,
+estimates agree within 1e-9 relative (only the order of fp64 sums and the
+last bits of exp/erf differ)."""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from tests.gpu_util import announce, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def stag():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_2407_07096_amd as s
+    s.load()
+    return s
+
+
+def _randomness(orc, n, d, a, seed, **kw):
+    sh = orc.lsh_derive(n, a, **kw)
+    npj = sh["K1"] * sh["J"] * sh["L"] * sh["K"]
+    G0, B = synth.e2lsh_randomness(npj, d, seed)
+    return sh, G0, B
+
+
+def _compare(stag, orc, X, Q, a, seed, check_segments=True, **kw):
+    import torch
+    n, d = X.shape
+    sh, G0, B = _randomness(orc, n, d, a, seed, **{k: v for k, v in kw.items() if k != "flags" or True})
+    idx = stag.LshIndex(to_dev(X), a, G0=to_dev(G0), b=to_dev(B), seed=seed, **kw)
+    assert {k: idx.shape[k] for k in ("J", "L", "K", "K1")} == {k: sh[k] for k in ("J", "L", "K", "K1")}
+    S, st = idx.query(to_dev(Q), stats=True)
+    torch.cuda.synchronize()
+    S_ref, st_ref = orc.lsh_kde(X, Q, a, G0, B, seed=seed, return_stats=True, **kw)
+    assert np.array_equal(st["n_cand"].cpu().numpy(), st_ref["n_cand"])
+    assert np.array_equal(st["n_acc"].cpu().numpy(), st_ref["n_acc"])
+    S = S.cpu().numpy()
+    ok = S_ref > 0
+    assert np.all(S[~ok] == 0)
+    assert np.allclose(S[ok], S_ref[ok], rtol=1e-9, atol=0)
+    assert np.allclose(st["S_copies"].cpu().numpy(), st_ref["S_copies"], rtol=1e-9, atol=1e-300)
+    if check_segments:
+        J, L, K, K1 = sh["J"], sh["L"], sh["K"], sh["K1"]
+        for t in range(min(K1, 2)):
+            for i in range(1, J + 1):
+                mem, keys = idx.segment(t, i)
+                keep = orc.lsh_mask(seed, t, i, n, int(sh["thr"][i]))
+                assert np.array_equal(mem, np.nonzero(keep)[0])
+                if len(mem) == 0:
+                    continue
+                base = ((t * J) + (i - 1)) * L * K
+                G = (G0[base:base + L * K].astype(np.float64) / sh["r"][i]).astype(np.float32)
+                _, kref = orc.e2lsh_hash(X[mem], G, B[base:base + L * K], K, L)
+                assert np.array_equal(keys, kref)
+    idx.close()
+    return S, S_ref, st_ref
+
+
+def test_config1_structure_and_values(stag, orc):
+    X, Q, _ = synth.config_points(1)
+    announce("lsh config1 n=1000 d=10 a=0.5 k1=4")
+    _compare(stag, orc, X, Q[:200], 0.5, seed=3001, k1=4)
+
+
+def test_config1_literal_and_offset(stag, orc):
+    X, Q, _ = synth.config_points(1)
+    announce("lsh config1 literal p_offset=1 min_mu=1e-3 k2=5")
+    _compare(stag, orc, X, Q[:100], 0.5, seed=7, k1=3, flags=stag.LSH_LITERAL, p_offset=1, min_mu=1e-3,
+             k2_constant=5)
+
+
+def test_config2_bench_parameters(stag, orc):
+    """n = 100,000, d = 64 with the parameters the benchmark uses."""
+    X, Q, _ = synth.config_points(2)
+    rng = np.random.default_rng(5)
+    idx = rng.choice(Q.shape[0], size=64, replace=False)
+    announce("lsh config2 n=1e5 d=64 k1=1 k2=8 p_offset=1")
+    S, S_ref, st = _compare(stag, orc, X, Q[idx], 0.01, seed=3002, check_segments=False, k1=1, k2_constant=8,
+                            p_offset=1)
+    ex = orc.kde_exact(X, Q[idx], 0.01)
+    assert np.mean(np.abs(S - ex) / ex) < 0.2
+
+
+def test_config2_default_parameters_reduced(stag, orc):
+    """Default (eps=0.5) reading: K1 = ceil(4 log2 n) copies, L = ceil(log2 n)."""
+    X, Q, _ = synth.config_points(2, n=8000, m=24)
+    announce("lsh config2-reduced n=8000 default parameters")
+    S, S_ref, _ = _compare(stag, orc, X, Q, 0.01, seed=11, check_segments=True)
+    ex = orc.kde_exact(X, Q, 0.01)
+    ok = ex >= 1.0
+    assert np.mean(np.abs(S[ok] - ex[ok]) / ex[ok] <= 0.5) >= 0.9
+
+
+def test_degenerate_case_is_truncated_exact(stag, orc):
+    X, Q, _ = synth.config_points(1, n=300, m=40)
+    a = 0.05
+    sh, G0, B = _randomness(orc, 300, 10, a, 5, k1=2, flags=3)
+    import torch
+    idx = stag.LshIndex(to_dev(X), a, G0=to_dev(np.zeros_like(G0)), b=to_dev(B), seed=5, k1=2,
+                        flags=stag.LSH_LITERAL | stag.LSH_ALL_SAMPLED)
+    S = idx.query(to_dev(Q)).cpu().numpy()
+    D = ((Q.astype(np.float64)[:, None, :] - X.astype(np.float64)[None]) ** 2).sum(-1)
+    ref = np.where(D < sh["T"][-1], np.exp(-a * D), 0.0).sum(1)
+    assert np.allclose(S, ref, rtol=1e-12)
+    idx.close()
+
+
+def test_unbiased_on_gpu(stag, orc):
+    """Mean of 2000 independent GPU copies = truncated exact sum (4 SE)."""
+    import torch
+    rng = np.random.default_rng(5)
+    n, d, a = 40, 3, 0.4
+    X = (rng.normal(size=(n, d)) * 1.5).astype(np.float32)
+    Q = rng.normal(size=(4, d)).astype(np.float32)
+    kw = dict(k1=2000, k2_constant=3)
+    sh, G0, B = _randomness(orc, n, d, a, 21, **kw)
+    idx = stag.LshIndex(to_dev(X), a, G0=to_dev(G0), b=to_dev(B), seed=77, **kw)
+    S, st = idx.query(to_dev(Q), stats=True)
+    Sc = st["S_copies"].cpu().numpy()
+    D = ((Q.astype(np.float64)[:, None, :] - X.astype(np.float64)[None]) ** 2).sum(-1)
+    ref = np.where(D < sh["T"][-1], np.exp(-a * D), 0.0).sum(1)
+    se = Sc.std(axis=1, ddof=1) / math.sqrt(Sc.shape[1])
+    assert np.all(np.abs(Sc.mean(axis=1) - ref) < 4 * se)
+    idx.close()
+
+
+def test_default_randomness_path(stag, orc):
+    """Without caller projections the index draws its own (counter RNG +
+    Box-Muller); the estimate must still be accurate on average."""
+    import torch
+    X, Q, _ = synth.config_points(2, n=20000, m=64)
+    S = stag.kde_lsh(to_dev(X), to_dev(Q), 0.01, seed=99, k1=4, k2_constant=8).cpu().numpy()
+    ex = orc.kde_exact(X, Q, 0.01)
+    assert np.mean(np.abs(S - ex) / ex) < 0.1
+
+
+def test_query_batch_independence(stag):
+    import torch
+    X, Q, _ = synth.config_points(2, n=20000, m=300)
+    idx = stag.LshIndex(to_dev(X), 0.01, seed=4, k1=2, k2_constant=6)
+    Qd = to_dev(Q)
+    S1 = idx.query(Qd)
+    S2 = idx.query(Qd[100:200].contiguous())
+    S3 = idx.query(Qd)
+    torch.cuda.synchronize()
+    assert torch.equal(S1, S3)
+    assert torch.equal(S1[100:200], S2)
+    idx.close()
