@@ -96,8 +96,8 @@ double stag_e2lsh_collision_probability(double c, int32_t K, int32_t L);
  *                       result (the value is |S_gpu - S| / S <= bound except
  *                       with probability < 1e-9 per result; see the library
  *                       documentation for the model).
- * Limits: 1 <= d <= 256 (STAG_E_UNSUPPORTED above), n, m >= 1,
- * n*d and m*d < 2^31.  FP16_SPLIT additionally needs |x_j| and
+ * Limits: 1 <= d <= 1024 (d > 256: fp32 form only; STAG_E_UNSUPPORTED
+ * otherwise), n, m >= 1, n*d and m*d < 2^31.  FP16_SPLIT additionally needs |x_j| and
  * |2a log2(e) q_j| below 65504; out-of-range inputs give a NaN result.
  * Results are deterministic and do not depend on m or on the other rows of Q
  * (each row's reduction order depends only on n). */
@@ -203,6 +203,36 @@ void stag_lsh_index_destroy(stag_lsh_index* idx);
 /* create + query + destroy. */
 stag_status stag_kde_lsh(const float* X, int64_t n, const float* Q, int64_t m, int32_t d, double a, double eps,
                          const stag_lsh_params* p, double* S_out, hipStream_t stream);
+
+/* ------------------------------------------------------------------------
+ * Similarity-graph edge sampling (Sec. "The MS Algorithm", eq. sampling_prob:
+ * edge (i,j) sampled with probability proportional to w/deg(i) + w/deg(j),
+ * deg(i) = sum_j k(||x_i - x_j||); approximate_similarity_graph).
+ *
+ * Every node i draws s neighbours j != i with probability k_ij / rest_i,
+ * rest_i = sum_{j != i} k_ij; draw r of node i is output at index i*s + r with
+ * weight 1 / (s (1/rest_i + 1/rest_j)), so that the expected sampled weight of
+ * each pair equals k_ij (the fully connected graph without self-loops).
+ * Duplicates are kept (the caller may merge them); deg(i) = 1 + rest_i.
+ * The draw uses U = (mix(s_i + (r+1) 0x9E3779B97F4A7C15) >> 11) 2^-53,
+ * s_i = mix(mix(mix(seed ^ 0x44524157) ^ i) ^ 0), inverting the cumulative
+ * sum of the row in ascending j.
+ *   STAG_SIMGRAPH_EXACT: kernel row sums from one exact tile pass in `form`
+ *     (chunk and tile sums), the final 32 values recomputed in fp64.
+ *   STAG_SIMGRAPH_LSH: rest_i is the CKNS estimate (eps, lsh params) of
+ *     sum_{j != i} k_ij and the draw inverts the estimator's own terms (copy,
+ *     level, table, bucket order): E[term of j] = k_ij.
+ * Outputs (device): src/dst int64 [n*s], w f64 [n*s], deg f64 [n] or NULL.
+ * dst = -1 (w = 0) for a node whose row is empty (all kernel values 0).
+ * samples_per_node 0 means ceil(log2 n); at most 64.
+ * ------------------------------------------------------------------------ */
+#define STAG_SIMGRAPH_EXACT 0
+#define STAG_SIMGRAPH_LSH 1
+
+stag_status stag_simgraph_sample(const float* X, int64_t n, int32_t d, double a, int32_t samples_per_node,
+                                 int32_t kde_mode, int32_t form, double eps, const stag_lsh_params* lsh,
+                                 uint64_t seed, int64_t* src_out, int64_t* dst_out, double* w_out, double* deg_out,
+                                 hipStream_t stream);
 
 #ifdef __cplusplus
 }

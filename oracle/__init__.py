@@ -68,7 +68,11 @@ def _load():
     lib.orc_draw_uniform.argtypes = [C.c_uint64, C.c_int64, C.c_int32]
     lib.orc_simgraph_exact.restype = None
     lib.orc_simgraph_exact.argtypes = [f32p, C.c_int64, C.c_int32, C.c_double, C.c_int32, C.c_uint64, i64p, i64p, f64p,
-                                       f64p, C.c_int32]
+                                       f64p, f64p, C.c_int32]
+    lib.orc_simgraph_lsh.restype = C.c_int32
+    lib.orc_simgraph_lsh.argtypes = [f32p, C.c_int64, C.c_int32, C.c_double, C.c_double, C.c_double, C.c_int32,
+                                     C.c_double, C.c_int32, C.c_uint64, C.c_uint32, f32p, f64p, C.c_int32, C.c_uint64,
+                                     i64p, i64p, f64p, f64p, f64p, C.c_int32]
     _lib = lib
     return lib
 
@@ -198,8 +202,8 @@ def draw_uniform(seed, i, r) -> float:
     return float(_load().orc_draw_uniform(seed & 0xFFFFFFFFFFFFFFFF, int(i), int(r)))
 
 
-def simgraph_exact(X, a, s, seed, nthreads: int = 0):
-    """(src, dst, w, deg) of the exact-kernel edge sampler."""
+def simgraph_exact(X, a, s, seed, nthreads: int = 0, return_margin: bool = False):
+    """(src, dst, w, deg) of the exact-kernel edge sampler (+ margin)."""
     X = _f32(X)
     n, d = X.shape
     e = n * s
@@ -207,7 +211,31 @@ def simgraph_exact(X, a, s, seed, nthreads: int = 0):
     dst = np.empty(e, dtype=np.int64)
     w = np.empty(e, dtype=np.float64)
     deg = np.empty(n, dtype=np.float64)
+    mg = np.empty(e, dtype=np.float64)
     _load().orc_simgraph_exact(_p(X, C.c_float), n, d, float(a), int(s), seed & 0xFFFFFFFFFFFFFFFF,
                                _p(src, C.c_int64), _p(dst, C.c_int64), _p(w, C.c_double), _p(deg, C.c_double),
-                               int(nthreads))
-    return src, dst, w, deg
+                               _p(mg, C.c_double), int(nthreads))
+    return (src, dst, w, deg, mg) if return_margin else (src, dst, w, deg)
+
+
+def simgraph_lsh(X, a, s, draw_seed, G0, B, lsh_seed, eps=0.5, min_mu=0.0, k1=0, k2_constant=0.0, p_offset=0,
+                 flags=0, nthreads: int = 0):
+    """(src, dst, w, deg, margin) of the CKNS-based edge sampler."""
+    X = _f32(X)
+    n, d = X.shape
+    e = n * s
+    src = np.empty(e, dtype=np.int64)
+    dst = np.empty(e, dtype=np.int64)
+    w = np.empty(e, dtype=np.float64)
+    deg = np.empty(n, dtype=np.float64)
+    mg = np.empty(e, dtype=np.float64)
+    G0 = _f32(G0).reshape(-1)
+    B = np.ascontiguousarray(B, dtype=np.float64).reshape(-1)
+    rc = _load().orc_simgraph_lsh(_p(X, C.c_float), n, d, float(a), float(eps), float(min_mu), int(k1),
+                                  float(k2_constant), int(p_offset), lsh_seed & 0xFFFFFFFFFFFFFFFF, int(flags),
+                                  _p(G0, C.c_float), _p(B, C.c_double), int(s), draw_seed & 0xFFFFFFFFFFFFFFFF,
+                                  _p(src, C.c_int64), _p(dst, C.c_int64), _p(w, C.c_double), _p(deg, C.c_double),
+                                  _p(mg, C.c_double), int(nthreads))
+    if rc:
+        raise ValueError(f"orc_simgraph_lsh failed ({rc})")
+    return src, dst, w, deg, mg

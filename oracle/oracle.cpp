@@ -26,9 +26,10 @@
 //                             set per subsample, the importance-weighted sum,
 //                             repetition; constructor parameters eps, min_mu,
 //                             K1, K2_constant, p_offset of CKNSGaussianKDE.
-//   orc_kernel_row, orc_simgraph_exact
+//   orc_kernel_row, orc_simgraph_exact, orc_simgraph_lsh
 //                           - Sec. "The MS Algorithm", eq. (sampling_prob) and
-//                             the degree deg_F(i) = sum_j K(||x_i - x_j||).
+//                             the degree deg_F(i) = sum_j K(||x_i - x_j||),
+//                             with exact or CKNS kernel sums.
 //
 // Where the paper leaves a detail open, the reading taken is stated at the
 // function (level boundaries half-open, log base 2, reweighting by the
@@ -418,7 +419,8 @@ double orc_draw_uniform(uint64_t seed, int64_t i, int32_t r) {
 // weight of every pair equal to k_ij (eq. sampling_prob).  Output is
 // node-major, draw-minor: entry i*s + r.  deg_out [n] may be NULL.
 void orc_simgraph_exact(const float* X, int64_t n, int32_t d, double a, int32_t s, uint64_t seed,
-                        int64_t* src, int64_t* dst, double* w, double* deg_out, int32_t nthreads) {
+                        int64_t* src, int64_t* dst, double* w, double* deg_out, double* margin_out,
+                        int32_t nthreads) {
   if (nthreads <= 0) nthreads = omp_get_max_threads();
   std::vector<double> rest((size_t)n);  // deg(i) - 1 = sum over j != i
 #pragma omp parallel num_threads(nthreads)
@@ -439,14 +441,18 @@ void orc_simgraph_exact(const float* X, int64_t n, int32_t d, double a, int32_t 
         const double target = orc_draw_uniform(seed, i, r) * rest[i];
         double c = 0.0;
         int64_t pick = -1, last = -1;
+        double before = 0.0;
         for (int64_t j = 0; j < n; ++j) {
           if (j == i) continue;
           if (row[j] > 0.0) last = j;
+          before = c;
           c = c + row[j];
           if (c > target) { pick = j; break; }
         }
-        if (pick < 0) pick = last;  // rounding left the target above the total
         const size_t e = (size_t)i * s + r;
+        // relative distance of the target to the nearest cumulative boundary
+        if (margin_out) margin_out[e] = pick >= 0 ? std::min(target - before, c - target) / rest[i] : 0.0;
+        if (pick < 0) pick = last;  // rounding left the target above the total
         src[e] = i;
         dst[e] = pick;
         if (pick < 0) { w[e] = 0.0; continue; }
@@ -456,6 +462,142 @@ void orc_simgraph_exact(const float* X, int64_t n, int32_t d, double a, int32_t 
   }
   if (deg_out)
     for (int64_t i = 0; i < n; ++i) deg_out[i] = rest[i] + 1.0;
+}
+
+
+// Edge sampling with the CKNS estimator in place of exact degrees (the
+// similarity-graph construction on top of the LSH kernel density estimate).
+// Every node i is queried against the data with its own point excluded:
+// S'_t(i) is copy t's estimate of sum_{j != i} k_ij, accumulated in the
+// canonical order (level, table, bucket member ascending);
+// rest_i = mean_t S'_t(i), deg(i) = 1 + rest_i.  A draw takes the target
+// U(i, r) * sum_t S'_t(i), picks the copy whose cumulative estimate passes
+// it, then the term of that copy whose cumulative sum passes the remainder;
+// its point j is the neighbour, with weight 1/(s (1/rest_i + 1/rest_j)).
+// margin_out: relative distance of the target to the nearest boundary.
+int32_t orc_simgraph_lsh(const float* X, int64_t n, int32_t d, double a, double eps, double min_mu, int32_t k1,
+                         double k2c, int32_t p_offset, uint64_t lsh_seed, uint32_t flags, const float* G0,
+                         const double* B, int32_t s, uint64_t draw_seed, int64_t* src, int64_t* dst, double* w,
+                         double* deg_out, double* margin_out, int32_t nthreads) {
+  LshShape sh;
+  int rc = derive(n, a, eps, min_mu, k1, k2c, p_offset, flags, &sh);
+  if (rc) return rc;
+  if (nthreads <= 0) nthreads = omp_get_max_threads();
+  const int J = sh.J, L = sh.L, K = sh.K, K1 = sh.K1;
+  // terms[(node * K1 + t)] = ordered (j, value)
+  std::vector<std::vector<std::pair<int32_t, double>>> terms((size_t)n * K1);
+  std::vector<float> g((size_t)L * K * d);
+  std::vector<int32_t> members;
+  std::vector<uint64_t> mkeys;
+  for (int t = 0; t < K1; ++t) {
+    for (int i = 1; i <= J; ++i) {
+      const size_t base = ((size_t)t * J + (i - 1)) * (size_t)L * K;
+      for (size_t e = 0; e < (size_t)L * K * d; ++e) g[e] = (float)((double)G0[base * d + e] / sh.r[i]);
+      const double* bb = B + base;
+      members.clear();
+      for (int64_t j = 0; j < n; ++j)
+        if ((counter_bits(lsh_seed, kTagMask, (uint64_t)t, (uint64_t)i, (uint64_t)j) >> 11) < sh.thr[i])
+          members.push_back((int32_t)j);
+      const int64_t ns = (int64_t)members.size();
+      mkeys.assign((size_t)ns * L, 0);
+#pragma omp parallel for schedule(static) num_threads(nthreads)
+      for (int64_t u = 0; u < ns; ++u) {
+        std::vector<int32_t> codes((size_t)K);
+        const float* x = X + (size_t)members[u] * d;
+        for (int l = 0; l < L; ++l) {
+          for (int k = 0; k < K; ++k) codes[k] = e2lsh_code(x, &g[((size_t)l * K + k) * d], bb[l * K + k], d);
+          mkeys[(size_t)u * L + l] = bucket_key(l, codes.data(), K);
+        }
+      }
+      std::vector<std::unordered_map<uint64_t, std::vector<int64_t>>> tab((size_t)L);
+      for (int64_t u = 0; u < ns; ++u)
+        for (int l = 0; l < L; ++l) tab[l][mkeys[(size_t)u * L + l]].push_back(u);
+      const double Tlo = sh.T[i - 1], Thi = sh.T[i], pi = sh.p[i], ri = sh.r[i];
+#pragma omp parallel for schedule(dynamic, 16) num_threads(nthreads)
+      for (int64_t qi = 0; qi < n; ++qi) {
+        const float* q = X + (size_t)qi * d;
+        std::vector<uint64_t> qk((size_t)L);
+        std::vector<int32_t> codes((size_t)K);
+        for (int l = 0; l < L; ++l) {
+          for (int k = 0; k < K; ++k) codes[k] = e2lsh_code(q, &g[((size_t)l * K + k) * d], bb[l * K + k], d);
+          qk[l] = bucket_key(l, codes.data(), K);
+        }
+        auto& out = terms[(size_t)qi * K1 + t];
+        for (int l = 0; l < L; ++l) {
+          auto it = tab[l].find(qk[l]);
+          if (it == tab[l].end()) continue;
+          for (int64_t u : it->second) {
+            bool seen = false;
+            for (int l2 = 0; l2 < l; ++l2)
+              if (mkeys[(size_t)u * L + l2] == qk[l2]) { seen = true; break; }
+            if (seen) continue;
+            const int32_t j = members[u];
+            if (j == qi) continue;
+            const double D = sqdist_fused(q, X + (size_t)j * d, d);
+            if (!(D >= Tlo && D < Thi)) continue;
+            double R = 1.0;
+            if (!(flags & kFlagLiteral)) R = boosted_p(std::sqrt(D) / ri, K, L);
+            out.push_back({j, std::exp(-a * D) / (pi * R)});
+          }
+        }
+      }
+    }
+  }
+  std::vector<double> St((size_t)n * K1), rest((size_t)n);
+  for (int64_t qi = 0; qi < n; ++qi) {
+    double tot = 0.0;
+    for (int t = 0; t < K1; ++t) {
+      double sum = 0.0;
+      for (auto& pr : terms[(size_t)qi * K1 + t]) sum += pr.second;
+      St[(size_t)qi * K1 + t] = sum;
+      tot += sum;
+    }
+    rest[qi] = tot / (double)K1;
+  }
+  for (int64_t qi = 0; qi < n; ++qi) {
+    double tot = 0.0;
+    for (int t = 0; t < K1; ++t) tot += St[(size_t)qi * K1 + t];
+    for (int32_t r = 0; r < s; ++r) {
+      const size_t e = (size_t)qi * s + r;
+      src[e] = qi;
+      dst[e] = -1;
+      w[e] = 0.0;
+      if (margin_out) margin_out[e] = 0.0;
+      if (!(tot > 0.0)) continue;
+      const double target = orc_draw_uniform(draw_seed, qi, r) * tot;
+      double c = 0.0;
+      int tsel = -1;
+      for (int t = 0; t < K1; ++t) {
+        if (c + St[(size_t)qi * K1 + t] > target) { tsel = t; break; }
+        c += St[(size_t)qi * K1 + t];
+      }
+      if (tsel < 0) {  // rounding: last copy with mass
+        for (int t = K1 - 1; t >= 0; --t)
+          if (St[(size_t)qi * K1 + t] > 0.0) { tsel = t; break; }
+        c = 0.0;
+        for (int t = 0; t < tsel; ++t) c += St[(size_t)qi * K1 + t];
+      }
+      const double resid = target - c;
+      const auto& tl = terms[(size_t)qi * K1 + tsel];
+      double cc = 0.0, before = 0.0;
+      int64_t pick = -1;
+      for (auto& pr : tl) {
+        before = cc;
+        cc = cc + pr.second;
+        if (cc > resid) { pick = pr.first; break; }
+      }
+      if (pick < 0) {
+        pick = tl.back().first;
+      } else if (margin_out) {
+        margin_out[e] = std::min(resid - before, cc - resid) / tot;
+      }
+      dst[e] = pick;
+      w[e] = 1.0 / ((double)s * (1.0 / rest[qi] + 1.0 / rest[pick]));
+    }
+  }
+  if (deg_out)
+    for (int64_t i = 0; i < n; ++i) deg_out[i] = 1.0 + rest[i];
+  return 0;
 }
 
 }  // extern "C"

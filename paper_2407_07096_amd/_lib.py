@@ -79,6 +79,8 @@ def load():
     lib.stag_lsh_index_segment.argtypes = [vp, i32, i32, C.POINTER(C.c_int64), vp, vp, vp]
     lib.stag_lsh_index_destroy.restype = None
     lib.stag_lsh_index_destroy.argtypes = [vp]
+    lib.stag_simgraph_sample.restype = C.c_int
+    lib.stag_simgraph_sample.argtypes = [vp, i64, i32, f64, i32, i32, i32, f64, pp, C.c_uint64, vp, vp, vp, vp, vp]
     lib.stag_kde_lsh.restype = C.c_int
     lib.stag_kde_lsh.argtypes = [vp, i64, vp, i64, i32, f64, f64, pp, vp, vp]
     _lib = lib
@@ -259,3 +261,27 @@ def kde_lsh(X, Q, a: float, eps: float = 0.5, G0=None, b=None, **kw):
     check(load().stag_kde_lsh(_ptr(X), X.shape[0], _ptr(Q), Q.shape[0], X.shape[1], float(a), float(eps),
                               C.byref(prm), _ptr(S), _stream_handle(X.device)), "stag_kde_lsh")
     return S
+
+
+def simgraph_sample(X, a: float, samples_per_node: int = 0, mode: str = "exact", form: str = "fp32",
+                    eps: float = 0.5, seed: int = 0, G0=None, b=None, lsh_seed: int = 0, **lsh_kw):
+    """Edge sample of the kernel similarity graph: (src, dst, w, deg) tensors.
+    seed drives the draws; lsh_seed and lsh_kw (k1, k2_constant, p_offset,
+    min_mu, flags) the CKNS index of the "lsh" mode."""
+    torch = _torch()
+    _need(X, torch.float32, 2, "X")
+    n, d = X.shape
+    if samples_per_node <= 0:
+        s = max(1, int(n - 1).bit_length())
+    else:
+        s = int(samples_per_node)
+    src = torch.empty(n * s, dtype=torch.int64, device=X.device)
+    dst = torch.empty(n * s, dtype=torch.int64, device=X.device)
+    w = torch.empty(n * s, dtype=torch.float64, device=X.device)
+    deg = torch.empty(n, dtype=torch.float64, device=X.device)
+    prm = _lsh_params(G0=G0, b=b, seed=lsh_seed, **lsh_kw)
+    st = load().stag_simgraph_sample(_ptr(X), n, d, float(a), s, {"exact": 0, "lsh": 1}[mode], FORMS[form],
+                                     float(eps), C.byref(prm), int(seed) & 0xFFFFFFFFFFFFFFFF, _ptr(src), _ptr(dst),
+                                     _ptr(w), _ptr(deg), _stream_handle(X.device))
+    check(st, "stag_simgraph_sample")
+    return src, dst, w, deg

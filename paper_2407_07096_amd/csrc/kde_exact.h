@@ -37,6 +37,15 @@ __host__ __device__ inline double relative_bound(const BoundModel& bm, double qn
   return expm1(0.69314718055994530942 * dE) + bm.c_tail;
 }
 
+// Optional epilogue outputs of the tiles (edge sampling): drop the diagonal
+// when a data set is queried against itself, and write per-32-row-tile
+// partial sums tp[tile][m_pad] (fp32).
+struct TileExtra {
+  int self = 0;
+  float* tp = nullptr;
+  int64_t m_pad = 0;
+};
+
 int exact_padded_dim(int d);  // 0 if unsupported
 int form_parts(int form);
 size_t form_element_bytes(int form);
@@ -45,7 +54,8 @@ BoundModel make_bound_model(int form, int d, double a);
 
 stag_status prepare_operands(int form, const float* src, int64_t rows, int d, double a, bool is_query,
                              Workspace& ws, Operands* out, hipStream_t st);
-stag_status launch_exact_tiles(const Operands& xo, const Operands& qo, double* partial, hipStream_t st);
+stag_status launch_exact_tiles(const Operands& xo, const Operands& qo, double* partial, const TileExtra& ex,
+                               hipStream_t st);
 stag_status launch_reduce(const double* partial, int P, const Operands& qo, const Operands& xo, double scale,
                           const BoundModel& bm, double* S_out, double* bound_out, hipStream_t st);
 

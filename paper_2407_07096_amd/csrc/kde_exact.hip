@@ -43,6 +43,7 @@ constexpr int kBQ = 32 * kWaves;      // queries per workgroup
 constexpr int kChunkRows = 4096;      // data rows per partial sum
 constexpr float kPadOffset = -1.0e30f;  // exponent offset of padding rows: exp2 -> 0
 constexpr unsigned short kBf16One = 0x3F80;
+constexpr int kWideMaxDim = 1024;     // largest d of the wide fp32 tile
 
 __device__ inline unsigned short bf16_rne(float f) {
   unsigned int u = __float_as_uint(f);
@@ -65,6 +66,36 @@ __device__ inline float exp2_tile_sum(const float* c) {
 #pragma unroll
     for (int i = 0; i < w; ++i) k[i] = k[i] + k[i + w];
   return k[0];
+}
+
+// Epilogue of one finished 32x32 tile held by a lane (column qi, half h):
+// exp2 and fp32 tree sum; with EXTRA, optionally drops the diagonal element
+// (data row == query index, for a data set queried against itself) and
+// writes the tile's 32-row partial sum (both halves, fixed order).
+template <bool EXTRA>
+__device__ inline float tile_epilogue(const f32x16& c, int64_t row_base, int64_t col_base, int r32, int h,
+                                      int64_t qi, const TileExtra& ex) {
+  float cp[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) cp[i] = c[i];
+  if constexpr (EXTRA) {
+    if (ex.self && row_base == col_base) {
+      // lane (column r32, half h) holds rows 8(i/4) + 4h + i%4
+      const int idg = 4 * (r32 >> 3) + (r32 & 3);
+      const bool mine = h == ((r32 & 7) >> 2);
+#pragma unroll
+      for (int i = 0; i < 16; ++i) cp[i] = (mine && i == idg) ? kPadOffset : cp[i];
+    }
+  }
+  const float s = exp2_tile_sum(cp);
+  if constexpr (EXTRA) {
+    if (ex.tp) {
+      const float o = __shfl_xor(s, 32);
+      const float tot = h == 0 ? s + o : o + s;
+      if (h == 0) ex.tp[(row_base / kTileRows) * ex.m_pad + qi] = tot;
+    }
+  }
+  return s;
 }
 
 // Split v into parts of the form's element type: v ~= p0 + p1 (+ p2); each
@@ -173,11 +204,11 @@ __global__ __launch_bounds__(256) void prep_rows(const float* __restrict__ src, 
 // FP32 form: v_mfma_f32_32x32x2_f32.  Lane l supplies A[l%32][k] and
 // B[k][l%32] for the k-slot k = l/32; with the k ordering chosen here, lane
 // half h covers dimensions [h*DP/2, (h+1)*DP/2) of every row.
-template <int DP>
+template <int DP, bool EXTRA>
 __global__ __launch_bounds__(256, 2) void tile_f32(const float* __restrict__ Xp, const float* __restrict__ beta,
                                                    const float* __restrict__ Qs, const float* __restrict__ alpha,
                                                    int64_t n_pad, int n_qtiles, int64_t m_pad,
-                                                   double* __restrict__ partial) {
+                                                   double* __restrict__ partial, TileExtra ex) {
   constexpr int H = DP / 2;
   constexpr int LD = DP + 4;  // LDS row stride (floats): 16-byte aligned, rows 4 banks apart
   constexpr int F4_ROW = DP / 4;
@@ -190,7 +221,8 @@ __global__ __launch_bounds__(256, 2) void tile_f32(const float* __restrict__ Xp,
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, r32 = lane & 31, h = lane >> 5;
   const int qtile = blockIdx.x % n_qtiles;
   const int chunk = blockIdx.x / n_qtiles;
-  const int64_t qi = (int64_t)qtile * kBQ + wave * 32 + r32;
+  const int64_t col_base = (int64_t)qtile * kBQ + wave * 32;
+  const int64_t qi = col_base + r32;
 
   float bq[H];
   {
@@ -229,11 +261,10 @@ __global__ __launch_bounds__(256, 2) void tile_f32(const float* __restrict__ Xp,
   auto step = [&](int t, const f32x16& cdone, f32x16& cnew) {
     const int buf = t & 1;
     __syncthreads();
-    {
-      float cp[16];
-#pragma unroll
-      for (int i = 0; i < 16; ++i) cp[i] = cdone[i];
-      acc += (double)exp2_tile_sum(cp);
+    if constexpr (EXTRA) {
+      if (t > 0) acc += (double)tile_epilogue<true>(cdone, row0 + (int64_t)(t - 1) * kTileRows, col_base, r32, h, qi, ex);
+    } else {
+      acc += (double)tile_epilogue<false>(cdone, 0, 0, r32, h, qi, ex);
     }
     const float* arow = &tile[buf][r32 * LD + h * H];
     f32x16 c = {0};
@@ -272,12 +303,7 @@ __global__ __launch_bounds__(256, 2) void tile_f32(const float* __restrict__ Xp,
     step(t, ca, cb);
     ca = cb;
   }
-  {
-    float cp[16];
-#pragma unroll
-    for (int i = 0; i < 16; ++i) cp[i] = ca[i];
-    acc += (double)exp2_tile_sum(cp);
-  }
+  acc += (double)tile_epilogue<EXTRA>(ca, row0 + (int64_t)(ntiles - 1) * kTileRows, col_base, r32, h, qi, ex);
   const double other = __shfl_down(acc, 32);
   if (h == 0) partial[(int64_t)chunk * m_pad + qi] = acc + other;
 }
@@ -300,12 +326,12 @@ __device__ inline f32x16 mma16_bf16(u16x8 a, u16x8 b, f32x16 c) {
                                                  0, 0);
 }
 
-template <int FORM, int DP>
+template <int FORM, int DP, bool EXTRA>
 __global__ __launch_bounds__(256, 2) void tile_split(
     const unsigned short* __restrict__ X0, const unsigned short* __restrict__ X1,
     const unsigned short* __restrict__ X2, const u16x8* __restrict__ Xaug, const unsigned short* __restrict__ Q0,
     const unsigned short* __restrict__ Q1, const unsigned short* __restrict__ Q2, const u16x8* __restrict__ Qaug,
-    int64_t n_pad, int n_qtiles, int64_t m_pad, double* __restrict__ partial) {
+    int64_t n_pad, int n_qtiles, int64_t m_pad, double* __restrict__ partial, TileExtra ex) {
   constexpr int NP = FORM == STAG_FORM_BF16_SPLIT3 ? 3 : 2;
   constexpr int KS = DP / 16;
   constexpr int LD = DP + 8;     // LDS row stride (halves): 16-byte aligned
@@ -319,7 +345,8 @@ __global__ __launch_bounds__(256, 2) void tile_split(
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, r32 = lane & 31, h = lane >> 5;
   const int qtile = blockIdx.x % n_qtiles;
   const int chunk = blockIdx.x / n_qtiles;
-  const int64_t qi = (int64_t)qtile * kBQ + wave * 32 + r32;
+  const int64_t col_base = (int64_t)qtile * kBQ + wave * 32;
+  const int64_t qi = col_base + r32;
 
   const unsigned short* Qp[3] = {Q0, Q1, Q2};
   const unsigned short* Xpp[3] = {X0, X1, X2};
@@ -364,11 +391,10 @@ __global__ __launch_bounds__(256, 2) void tile_split(
   auto step = [&](int t, const f32x16& cdone, f32x16& cnew) {
     const int buf = t & 1;
     __syncthreads();
-    {
-      float cp[16];
-#pragma unroll
-      for (int i = 0; i < 16; ++i) cp[i] = cdone[i];
-      acc += (double)exp2_tile_sum(cp);
+    if constexpr (EXTRA) {
+      if (t > 0) acc += (double)tile_epilogue<true>(cdone, row0 + (int64_t)(t - 1) * kTileRows, col_base, r32, h, qi, ex);
+    } else {
+      acc += (double)tile_epilogue<false>(cdone, 0, 0, r32, h, qi, ex);
     }
     f32x16 c = {0};
 #pragma unroll
@@ -413,14 +439,80 @@ __global__ __launch_bounds__(256, 2) void tile_split(
     step(t, ca, cb);
     ca = cb;
   }
-  {
-    float cp[16];
-#pragma unroll
-    for (int i = 0; i < 16; ++i) cp[i] = ca[i];
-    acc += (double)exp2_tile_sum(cp);
-  }
+  acc += (double)tile_epilogue<EXTRA>(ca, row0 + (int64_t)(ntiles - 1) * kTileRows, col_base, r32, h, qi, ex);
   const double other = __shfl_down(acc, 32);
   if (h == 0) partial[(int64_t)chunk * m_pad + qi] = acc + other;
+}
+
+// ---------------------------------------------------------------------------
+// Wide rows (256 < d <= 1024), fp32 form.  The 32 queries of a workgroup sit
+// in LDS as the B operand ([32][DP+4] floats, loaded once); each of the 4
+// waves takes every 4th 32-row data tile of the chunk and streams its A
+// operand straight from global memory in blocks of 32 coordinates (register
+// double-buffered).  Per-wave fp64 sums are combined in wave order.
+// ---------------------------------------------------------------------------
+template <bool EXTRA>
+__global__ __launch_bounds__(256) void tile_f32_wide(const float* __restrict__ Xp, const float* __restrict__ beta,
+                                                     const float* __restrict__ Qs, const float* __restrict__ alpha,
+                                                     int DP, int64_t n_pad, int n_qt32, int64_t m_pad,
+                                                     double* __restrict__ partial, TileExtra ex) {
+  extern __shared__ __attribute__((aligned(16))) float qlds[];
+  __shared__ double wsum[4][32];
+  const int H = DP / 2, LD = DP + 4;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, r32 = lane & 31, h = lane >> 5;
+  const int qtile = blockIdx.x % n_qt32;
+  const int chunk = blockIdx.x / n_qt32;
+  const int64_t col_base = (int64_t)qtile * 32;
+  const int64_t qi = col_base + r32;
+  // B operand into LDS
+  {
+    const f32x4* src = reinterpret_cast<const f32x4*>(Qs + col_base * DP);
+    const int nv = 32 * DP / 4;
+    for (int v = tid; v < nv; v += 256) {
+      const int r = (v * 4) / DP, c = (v * 4) % DP;
+      *reinterpret_cast<f32x4*>(&qlds[r * LD + c]) = src[v];
+    }
+  }
+  __syncthreads();
+  const float baug = h == 0 ? alpha[qi] : 1.0f;
+  const int64_t row0 = (int64_t)chunk * kChunkRows;
+  const int64_t rem = (n_pad - row0) / kTileRows;
+  const int ntiles = (int)(rem < kChunkRows / kTileRows ? rem : kChunkRows / kTileRows);
+  const float* brow = &qlds[r32 * LD + h * H];
+  double acc = 0.0;
+  for (int t = wave; t < ntiles; t += 4) {
+    const int64_t rb = row0 + (int64_t)t * kTileRows;
+    const f32x4* arow = reinterpret_cast<const f32x4*>(Xp + (rb + r32) * DP + h * H);
+    f32x16 c = {0};
+    f32x4 a_cur[8], a_nxt[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) a_cur[k] = arow[k];
+    for (int kb = 0; kb < H; kb += 32) {
+      const bool more = kb + 32 < H;
+#pragma unroll
+      for (int k = 0; k < 8; ++k) a_nxt[k] = more ? arow[(kb + 32) / 4 + k] : a_cur[k];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const f32x4 b4 = *reinterpret_cast<const f32x4*>(brow + kb + 4 * k);
+        c = __builtin_amdgcn_mfma_f32_32x32x2f32(a_cur[k].x, b4.x, c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_32x32x2f32(a_cur[k].y, b4.y, c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_32x32x2f32(a_cur[k].z, b4.z, c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_32x32x2f32(a_cur[k].w, b4.w, c, 0, 0, 0);
+      }
+#pragma unroll
+      for (int k = 0; k < 8; ++k) a_cur[k] = a_nxt[k];
+    }
+    const float tb = beta[rb + r32];
+    c = __builtin_amdgcn_mfma_f32_32x32x2f32(h == 0 ? 1.0f : tb, baug, c, 0, 0, 0);
+    acc += (double)tile_epilogue<EXTRA>(c, rb, col_base, r32, h, qi, ex);
+  }
+  const double other = __shfl_down(acc, 32);
+  if (h == 0) wsum[wave][r32] = acc + other;
+  __syncthreads();
+  if (tid < 32) {
+    const double tot = ((wsum[0][tid] + wsum[1][tid]) + wsum[2][tid]) + wsum[3][tid];
+    partial[(int64_t)chunk * m_pad + col_base + tid] = tot;
+  }
 }
 
 // S(q) = sum of chunk partials in chunk order; optional 1/n; a-priori bound.
@@ -440,52 +532,66 @@ __global__ void reduce_partials(const double* __restrict__ partial, int P, int64
 
 template <int DP>
 stag_status launch_tile_f32(const float* Xp, const float* beta, const float* Qs, const float* alpha, int64_t n_pad,
-                            int n_qtiles, int64_t m_pad, int P, double* partial, hipStream_t st) {
+                            int n_qtiles, int64_t m_pad, int P, double* partial, const TileExtra& ex,
+                            hipStream_t st) {
   ScopedTimer tm("kde_tile_f32", st);
-  hipLaunchKernelGGL(tile_f32<DP>, dim3((unsigned)((int64_t)n_qtiles * P)), dim3(256), 0, st, Xp, beta, Qs, alpha,
-                     n_pad, n_qtiles, m_pad, partial);
+  if (ex.self || ex.tp)
+    hipLaunchKernelGGL((tile_f32<DP, true>), dim3((unsigned)((int64_t)n_qtiles * P)), dim3(256), 0, st, Xp, beta, Qs,
+                       alpha, n_pad, n_qtiles, m_pad, partial, ex);
+  else
+    hipLaunchKernelGGL((tile_f32<DP, false>), dim3((unsigned)((int64_t)n_qtiles * P)), dim3(256), 0, st, Xp, beta,
+                       Qs, alpha, n_pad, n_qtiles, m_pad, partial, ex);
   return check_launch("tile_f32");
 }
 
 template <int FORM, int DP>
 stag_status launch_tile_split(void* const* xp, const u16x8* xaug, void* const* qp, const u16x8* qaug, int64_t n_pad,
-                              int n_qtiles, int64_t m_pad, int P, double* partial, hipStream_t st) {
+                              int n_qtiles, int64_t m_pad, int P, double* partial, const TileExtra& ex,
+                              hipStream_t st) {
   using U = const unsigned short*;
   ScopedTimer tm(FORM == STAG_FORM_FP16_SPLIT ? "kde_tile_fp16x3" : (FORM == STAG_FORM_BF16_SPLIT ? "kde_tile_bf16x3" : "kde_tile_bf16x6"), st);
-  hipLaunchKernelGGL((tile_split<FORM, DP>), dim3((unsigned)((int64_t)n_qtiles * P)), dim3(256), 0, st, (U)xp[0],
-                     (U)xp[1], (U)xp[2], xaug, (U)qp[0], (U)qp[1], (U)qp[2], qaug, n_pad, n_qtiles, m_pad, partial);
+  if (ex.self || ex.tp)
+    hipLaunchKernelGGL((tile_split<FORM, DP, true>), dim3((unsigned)((int64_t)n_qtiles * P)), dim3(256), 0, st,
+                       (U)xp[0], (U)xp[1], (U)xp[2], xaug, (U)qp[0], (U)qp[1], (U)qp[2], qaug, n_pad, n_qtiles, m_pad,
+                       partial, ex);
+  else
+    hipLaunchKernelGGL((tile_split<FORM, DP, false>), dim3((unsigned)((int64_t)n_qtiles * P)), dim3(256), 0, st,
+                       (U)xp[0], (U)xp[1], (U)xp[2], xaug, (U)qp[0], (U)qp[1], (U)qp[2], qaug, n_pad, n_qtiles, m_pad,
+                       partial, ex);
   return check_launch("tile_split");
 }
 
 template <int FORM>
 stag_status dispatch_split(int dp, void* const* xp, const u16x8* xaug, void* const* qp, const u16x8* qaug,
-                           int64_t n_pad, int n_qtiles, int64_t m_pad, int P, double* partial, hipStream_t st) {
+                           int64_t n_pad, int n_qtiles, int64_t m_pad, int P, double* partial, const TileExtra& ex,
+                           hipStream_t st) {
   switch (dp) {
-    case 16: return launch_tile_split<FORM, 16>(xp, xaug, qp, qaug, n_pad, n_qtiles, m_pad, P, partial, st);
-    case 32: return launch_tile_split<FORM, 32>(xp, xaug, qp, qaug, n_pad, n_qtiles, m_pad, P, partial, st);
-    case 64: return launch_tile_split<FORM, 64>(xp, xaug, qp, qaug, n_pad, n_qtiles, m_pad, P, partial, st);
-    case 96: return launch_tile_split<FORM, 96>(xp, xaug, qp, qaug, n_pad, n_qtiles, m_pad, P, partial, st);
-    case 128: return launch_tile_split<FORM, 128>(xp, xaug, qp, qaug, n_pad, n_qtiles, m_pad, P, partial, st);
-    case 160: return launch_tile_split<FORM, 160>(xp, xaug, qp, qaug, n_pad, n_qtiles, m_pad, P, partial, st);
-    case 192: return launch_tile_split<FORM, 192>(xp, xaug, qp, qaug, n_pad, n_qtiles, m_pad, P, partial, st);
-    case 224: return launch_tile_split<FORM, 224>(xp, xaug, qp, qaug, n_pad, n_qtiles, m_pad, P, partial, st);
-    case 256: return launch_tile_split<FORM, 256>(xp, xaug, qp, qaug, n_pad, n_qtiles, m_pad, P, partial, st);
+    case 16: return launch_tile_split<FORM, 16>(xp, xaug, qp, qaug, n_pad, n_qtiles, m_pad, P, partial, ex, st);
+    case 32: return launch_tile_split<FORM, 32>(xp, xaug, qp, qaug, n_pad, n_qtiles, m_pad, P, partial, ex, st);
+    case 64: return launch_tile_split<FORM, 64>(xp, xaug, qp, qaug, n_pad, n_qtiles, m_pad, P, partial, ex, st);
+    case 96: return launch_tile_split<FORM, 96>(xp, xaug, qp, qaug, n_pad, n_qtiles, m_pad, P, partial, ex, st);
+    case 128: return launch_tile_split<FORM, 128>(xp, xaug, qp, qaug, n_pad, n_qtiles, m_pad, P, partial, ex, st);
+    case 160: return launch_tile_split<FORM, 160>(xp, xaug, qp, qaug, n_pad, n_qtiles, m_pad, P, partial, ex, st);
+    case 192: return launch_tile_split<FORM, 192>(xp, xaug, qp, qaug, n_pad, n_qtiles, m_pad, P, partial, ex, st);
+    case 224: return launch_tile_split<FORM, 224>(xp, xaug, qp, qaug, n_pad, n_qtiles, m_pad, P, partial, ex, st);
+    case 256: return launch_tile_split<FORM, 256>(xp, xaug, qp, qaug, n_pad, n_qtiles, m_pad, P, partial, ex, st);
   }
   return fail(STAG_E_UNSUPPORTED, "padded dimension %d not instantiated", dp);
 }
 
 stag_status dispatch_f32(int dp, const float* Xp, const float* beta, const float* Qs, const float* alpha,
-                         int64_t n_pad, int n_qtiles, int64_t m_pad, int P, double* partial, hipStream_t st) {
+                         int64_t n_pad, int n_qtiles, int64_t m_pad, int P, double* partial, const TileExtra& ex,
+                         hipStream_t st) {
   switch (dp) {
-    case 16: return launch_tile_f32<16>(Xp, beta, Qs, alpha, n_pad, n_qtiles, m_pad, P, partial, st);
-    case 32: return launch_tile_f32<32>(Xp, beta, Qs, alpha, n_pad, n_qtiles, m_pad, P, partial, st);
-    case 64: return launch_tile_f32<64>(Xp, beta, Qs, alpha, n_pad, n_qtiles, m_pad, P, partial, st);
-    case 96: return launch_tile_f32<96>(Xp, beta, Qs, alpha, n_pad, n_qtiles, m_pad, P, partial, st);
-    case 128: return launch_tile_f32<128>(Xp, beta, Qs, alpha, n_pad, n_qtiles, m_pad, P, partial, st);
-    case 160: return launch_tile_f32<160>(Xp, beta, Qs, alpha, n_pad, n_qtiles, m_pad, P, partial, st);
-    case 192: return launch_tile_f32<192>(Xp, beta, Qs, alpha, n_pad, n_qtiles, m_pad, P, partial, st);
-    case 224: return launch_tile_f32<224>(Xp, beta, Qs, alpha, n_pad, n_qtiles, m_pad, P, partial, st);
-    case 256: return launch_tile_f32<256>(Xp, beta, Qs, alpha, n_pad, n_qtiles, m_pad, P, partial, st);
+    case 16: return launch_tile_f32<16>(Xp, beta, Qs, alpha, n_pad, n_qtiles, m_pad, P, partial, ex, st);
+    case 32: return launch_tile_f32<32>(Xp, beta, Qs, alpha, n_pad, n_qtiles, m_pad, P, partial, ex, st);
+    case 64: return launch_tile_f32<64>(Xp, beta, Qs, alpha, n_pad, n_qtiles, m_pad, P, partial, ex, st);
+    case 96: return launch_tile_f32<96>(Xp, beta, Qs, alpha, n_pad, n_qtiles, m_pad, P, partial, ex, st);
+    case 128: return launch_tile_f32<128>(Xp, beta, Qs, alpha, n_pad, n_qtiles, m_pad, P, partial, ex, st);
+    case 160: return launch_tile_f32<160>(Xp, beta, Qs, alpha, n_pad, n_qtiles, m_pad, P, partial, ex, st);
+    case 192: return launch_tile_f32<192>(Xp, beta, Qs, alpha, n_pad, n_qtiles, m_pad, P, partial, ex, st);
+    case 224: return launch_tile_f32<224>(Xp, beta, Qs, alpha, n_pad, n_qtiles, m_pad, P, partial, ex, st);
+    case 256: return launch_tile_f32<256>(Xp, beta, Qs, alpha, n_pad, n_qtiles, m_pad, P, partial, ex, st);
   }
   return fail(STAG_E_UNSUPPORTED, "padded dimension %d not instantiated", dp);
 }
@@ -526,6 +632,7 @@ int exact_padded_dim(int d) {
   static const int dims[] = {16, 32, 64, 96, 128, 160, 192, 224, 256};
   for (int v : dims)
     if (d <= v) return v;
+  if (d <= kWideMaxDim) return (int)round_up(d, 64);
   return 0;
 }
 
@@ -566,24 +673,44 @@ stag_status prepare_operands(int form, const float* src, int64_t rows, int d, do
 
 int64_t exact_chunks(int64_t n_pad) { return ceil_div(n_pad, kChunkRows); }
 
-stag_status launch_exact_tiles(const Operands& xo, const Operands& qo, double* partial, hipStream_t st) {
+stag_status launch_exact_tiles(const Operands& xo, const Operands& qo, double* partial, const TileExtra& ex,
+                               hipStream_t st) {
   const int P = (int)exact_chunks(xo.rows_pad);
   const int n_qtiles = (int)(qo.rows_pad / kBQ);
+  if (xo.dp > 256) {
+    if (xo.form != STAG_FORM_FP32) return fail(STAG_E_UNSUPPORTED, "d > 256 needs the fp32 form");
+    const int n_qt32 = (int)(qo.rows_pad / 32);
+    const size_t lds = (size_t)32 * (xo.dp + 4) * sizeof(float);
+    STAG_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&tile_f32_wide<true>),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    STAG_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&tile_f32_wide<false>),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    ScopedTimer tm("kde_tile_f32_wide", st);
+    if (ex.self || ex.tp)
+      hipLaunchKernelGGL(tile_f32_wide<true>, dim3((unsigned)((int64_t)n_qt32 * P)), dim3(256), lds, st,
+                         (const float*)xo.part[0], xo.off, (const float*)qo.part[0], qo.off, xo.dp, xo.rows_pad,
+                         n_qt32, qo.rows_pad, partial, ex);
+    else
+      hipLaunchKernelGGL(tile_f32_wide<false>, dim3((unsigned)((int64_t)n_qt32 * P)), dim3(256), lds, st,
+                         (const float*)xo.part[0], xo.off, (const float*)qo.part[0], qo.off, xo.dp, xo.rows_pad,
+                         n_qt32, qo.rows_pad, partial, ex);
+    return check_launch("tile_f32_wide");
+  }
   if (xo.form == STAG_FORM_FP32)
     return dispatch_f32(xo.dp, (const float*)xo.part[0], xo.off, (const float*)qo.part[0], qo.off, xo.rows_pad,
-                        n_qtiles, qo.rows_pad, P, partial, st);
+                        n_qtiles, qo.rows_pad, P, partial, ex, st);
   const u16x8* xaug = static_cast<const u16x8*>(xo.aug);
   const u16x8* qaug = static_cast<const u16x8*>(qo.aug);
   switch (xo.form) {
     case STAG_FORM_BF16_SPLIT:
       return dispatch_split<STAG_FORM_BF16_SPLIT>(xo.dp, xo.part, xaug, qo.part, qaug, xo.rows_pad, n_qtiles,
-                                                  qo.rows_pad, P, partial, st);
+                                                  qo.rows_pad, P, partial, ex, st);
     case STAG_FORM_FP16_SPLIT:
       return dispatch_split<STAG_FORM_FP16_SPLIT>(xo.dp, xo.part, xaug, qo.part, qaug, xo.rows_pad, n_qtiles,
-                                                  qo.rows_pad, P, partial, st);
+                                                  qo.rows_pad, P, partial, ex, st);
     default:
       return dispatch_split<STAG_FORM_BF16_SPLIT3>(xo.dp, xo.part, xaug, qo.part, qaug, xo.rows_pad, n_qtiles,
-                                                   qo.rows_pad, P, partial, st);
+                                                   qo.rows_pad, P, partial, ex, st);
   }
 }
 
@@ -629,7 +756,9 @@ extern "C" stag_status stag_kde_exact(const float* X, int64_t n, const float* Q,
   if (form < STAG_FORM_FP32 || form > STAG_FORM_BF16_SPLIT3)
     return fail(STAG_E_INVAL, "stag_kde_exact: unknown form %d", form);
   if (flags & ~STAG_NORMALIZE) return fail(STAG_E_INVAL, "stag_kde_exact: unknown flags 0x%x", flags);
-  if (d > 256) return fail(STAG_E_UNSUPPORTED, "stag_kde_exact: d = %d > 256 is not supported", d);
+  if (d > 1024) return fail(STAG_E_UNSUPPORTED, "stag_kde_exact: d = %d > 1024 is not supported", d);
+  if (d > 256 && form != STAG_FORM_FP32)
+    return fail(STAG_E_UNSUPPORTED, "stag_kde_exact: d = %d > 256 is supported by the fp32 form only", d);
   if ((double)n * d >= 2147483648.0 || (double)m * d >= 2147483648.0)
     return fail(STAG_E_INVAL, "stag_kde_exact: n*d and m*d must be < 2^31");
   clear_error();
@@ -640,7 +769,7 @@ extern "C" stag_status stag_kde_exact(const float* X, int64_t n, const float* Q,
   const int P = (int)exact_chunks(xo.rows_pad);
   double* partial = nullptr;
   STAG_TRY(ws.alloc(&partial, (size_t)P * qo.rows_pad));
-  STAG_TRY(launch_exact_tiles(xo, qo, partial, stream));
+  STAG_TRY(launch_exact_tiles(xo, qo, partial, TileExtra{}, stream));
   const double scale = (flags & STAG_NORMALIZE) ? 1.0 / (double)n : 1.0;
   STAG_TRY(launch_reduce(partial, P, qo, xo, scale, make_bound_model(form, d, a), S_out, bound_out, stream));
   return STAG_OK;

@@ -18,4 +18,10 @@ struct LshParams {
 
 stag_status lsh_derive_params(int64_t n, double a, double eps, const stag_lsh_params* p, LshParams* out);
 
+// Similarity-graph edges from the CKNS estimator of an index built over the
+// data itself: s draws per node into src/dst/w [n*s], degrees into deg_out [n]
+// (may be NULL).
+stag_status lsh_sample_edges(const stag_lsh_index* idx, int s, uint64_t seed, int64_t* src, int64_t* dst, double* w,
+                             double* deg_out, hipStream_t st);
+
 }  // namespace stag

@@ -41,6 +41,7 @@ namespace {
 
 constexpr uint64_t kGamma = 0x9E3779B97F4A7C15ULL;
 constexpr uint64_t kTagMask = 0x4D41534BULL;
+constexpr uint64_t kTagDraw = 0x44524157ULL;
 constexpr uint64_t kTagProj = 0x50524F4AULL;
 constexpr uint64_t kTagOffs = 0x4F464653ULL;
 constexpr uint64_t kEmpty = 0xFFFFFFFFFFFFFFFFULL;
@@ -277,15 +278,15 @@ __global__ __launch_bounds__(256) void build_tables(int L, const uint64_t* __res
 // queries
 // ---------------------------------------------------------------------------
 template <int DREG>
-__global__ __launch_bounds__(256) void hash_queries(const float* __restrict__ Q, int64_t q0, int64_t mb, int d,
-                                                    int dg, const double* __restrict__ G8,
+__global__ __launch_bounds__(256) void hash_queries(const float* __restrict__ Q, int ldq, int64_t q0, int64_t mb,
+                                                    int d, int dg, const double* __restrict__ G8,
                                                     const double* __restrict__ B, int K, int L, int nch,
                                                     int64_t ntab, int tpw, uint64_t* __restrict__ qkeys) {
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int64_t ql = (int64_t)blockIdx.x * 64 + lane;
   const bool live = ql < mb;
-  const float* xrow = Q + (q0 + (live ? ql : 0)) * d;
+  const float* xrow = Q + (q0 + (live ? ql : 0)) * ldq;
   double xr[DREG > 0 ? DREG : 1];
   load_point<DREG>(xr, xrow, d);
   const int64_t t0 = ((int64_t)blockIdx.y * 4 + wave) * tpw;
@@ -313,50 +314,53 @@ struct LevelConst {
   double p[65], T[65], r[65];
 };
 
-// One wave per (query, copy): levels and tables in order, lanes over the
-// members of each bucket.
-template <int DREG>
-__global__ __launch_bounds__(256) void probe_queries(
-    const float* __restrict__ Q, int64_t q0, int64_t mb, int d, int dx, const float* __restrict__ X, int K1, int J,
-    int L, int K, double a, int literal, LevelConst lc, const uint64_t* __restrict__ qkeys, int64_t ntab,
-    const uint64_t* __restrict__ seg_off, const int32_t* __restrict__ members, const uint64_t* __restrict__ mkeys,
-    const uint64_t* __restrict__ tab_seg_off, const uint32_t* __restrict__ seg_cap,
-    const uint64_t* __restrict__ tab_key, const uint32_t* __restrict__ tab_start,
-    const uint32_t* __restrict__ tab_cnt, const int32_t* __restrict__ csr, double* __restrict__ Scopy,
-    int64_t* __restrict__ ncand, int64_t* __restrict__ nacc) {
+// Read-only view of an index for device code.
+struct IndexView {
+  const float* X;
+  int dx, d, K1, J, L, K;
+  double a;
+  int literal;
+  const uint64_t* seg_off;
+  const int32_t* members;
+  const uint64_t* mkeys;
+  const uint64_t* tab_seg_off;
+  const uint32_t* seg_cap;
+  const uint64_t* tab_key;
+  const uint32_t* tab_start;
+  const uint32_t* tab_cnt;
+  const int32_t* csr;
+};
+
+// Walks copy t of the estimator for one query (one wave): levels and tables
+// in order, bucket members in ascending order in batches of 64 (one per lane).
+// For every batch, on_batch(v, j, valid) receives each lane's term v (0 if
+// the member was seen in an earlier table, lies outside the level, or is the
+// query's own point when self_idx >= 0) and its point j.
+template <int DREG, class F>
+__device__ inline void walk_copy(const IndexView& ix, const LevelConst& lc, int t, const uint64_t* __restrict__ qk,
+                                 uint64_t* qk_s, const double* qr, const float* __restrict__ qrow, int64_t self_idx,
+                                 F&& on_batch) {
   const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
-  const int64_t pair = (int64_t)blockIdx.x * 4 + wave;
-  if (pair >= mb * K1) return;
-  const int64_t ql = pair / K1;
-  const int t = (int)(pair % K1);
-  const float* qrow = Q + (q0 + ql) * d;
-  double qr[DREG > 0 ? DREG : 1];
-  load_point<DREG>(qr, qrow, d);
-  __shared__ uint64_t qk_s[4][64];
-  double acc = 0.0;
-  int64_t nc = 0, na = 0;
-  for (int i = 1; i <= J; ++i) {
-    const int seg = t * J + (i - 1);
-    const int64_t s0 = (int64_t)seg_off[seg];
-    const int64_t cnt = (int64_t)seg_off[seg + 1] - s0;
+  const int L = ix.L, d = ix.d;
+  for (int i = 1; i <= ix.J; ++i) {
+    const int seg = t * ix.J + (i - 1);
+    const int64_t s0 = (int64_t)ix.seg_off[seg];
+    const int64_t cnt = (int64_t)ix.seg_off[seg + 1] - s0;
     if (cnt == 0) continue;
-    const uint32_t cap = seg_cap[seg], mask = cap - 1;
+    const uint32_t cap = ix.seg_cap[seg], mask = cap - 1;
     const double Tlo = lc.T[i - 1], Thi = lc.T[i], pi = lc.p[i], ri = lc.r[i];
-    const uint64_t* qk = qkeys + ql * ntab + (int64_t)seg * L;
-    for (int l0 = 0; l0 < L; l0 += 64) {
-      if (l0 + lane < L) qk_s[wave][l0 + lane] = qk[l0 + lane];
-    }
+    const uint64_t* qks = qk + (int64_t)seg * L;
+    if (lane < L) qk_s[lane] = qks[lane];
     __builtin_amdgcn_wave_barrier();
     for (int l = 0; l < L; ++l) {
-      const uint64_t key = qk_s[wave][l];
-      const int64_t tb = (int64_t)tab_seg_off[seg] + (int64_t)l * cap;
+      const uint64_t key = qk_s[l];
+      const int64_t tb = (int64_t)ix.tab_seg_off[seg] + (int64_t)l * cap;
       // lane-parallel linear probe: first slot holding the key or empty
       uint32_t slot = 0;
       bool found = false;
       for (uint32_t p0 = 0; p0 < cap; p0 += 64) {
-        const uint32_t s = ((uint32_t)key + p0 + lane) & mask;
-        const uint64_t v = (p0 + lane < cap) ? tab_key[tb + s] : kEmpty;
+        const uint32_t sl = ((uint32_t)key + p0 + lane) & mask;
+        const uint64_t v = (p0 + lane < cap) ? ix.tab_key[tb + sl] : kEmpty;
         const uint64_t hit = __ballot(v == key);
         const uint64_t emp = __ballot(v == kEmpty);
         if (hit != 0 || emp != 0) {
@@ -370,52 +374,178 @@ __global__ __launch_bounds__(256) void probe_queries(
         }
       }
       if (!found) continue;
-      const uint32_t start = tab_start[tb + slot], c = tab_cnt[tb + slot];
-      const int32_t* bucket = csr + s0 * L + (int64_t)l * cnt + start;
-      for (uint32_t k = lane; k < c; k += 64) {
-        const int32_t u = bucket[k];
-        ++nc;
-        const uint64_t* mk = mkeys + (s0 + u) * L;
-        bool seen = false;
-        for (int l2 = 0; l2 < l; ++l2)
-          if (mk[l2] == qk_s[wave][l2]) {
-            seen = true;
-            break;
-          }
-        if (seen) continue;
-        const float* xrow = X + (int64_t)members[s0 + u] * dx;
-        double D = 0.0;
-        if constexpr (DREG > 0) {
+      const uint32_t start = ix.tab_start[tb + slot], c = ix.tab_cnt[tb + slot];
+      const int32_t* bucket = ix.csr + s0 * L + (int64_t)l * cnt + start;
+      for (uint32_t k0 = 0; k0 < c; k0 += 64) {
+        const uint32_t k = k0 + lane;
+        const bool valid = k < c;
+        double v = 0.0;
+        int32_t j = -1;
+        if (valid) {
+          const int32_t u = bucket[k];
+          const uint64_t* mk = ix.mkeys + (s0 + u) * L;
+          bool seen = false;
+          for (int l2 = 0; l2 < l; ++l2)
+            if (mk[l2] == qk_s[l2]) {
+              seen = true;
+              break;
+            }
+          j = ix.members[s0 + u];
+          if (!seen && j != self_idx) {
+            const float* xrow = ix.X + (int64_t)j * ix.dx;
+            double D = 0.0;
+            if constexpr (DREG > 0) {
 #pragma unroll
-          for (int h = 0; h < DREG; ++h) {
-            if (h < d) {
-              const double dl = qr[h] - (double)xrow[h];
-              D = __builtin_fma(dl, dl, D);
+              for (int h = 0; h < DREG; ++h) {
+                if (h < d) {
+                  const double dl = qr[h] - (double)xrow[h];
+                  D = __builtin_fma(dl, dl, D);
+                }
+              }
+            } else {
+              for (int h = 0; h < d; ++h) {
+                const double dl = (double)qrow[h] - (double)xrow[h];
+                D = __builtin_fma(dl, dl, D);
+              }
+            }
+            if (D >= Tlo && D < Thi) {
+              const double R = ix.literal ? 1.0 : recovery_dev(sqrt(D) / ri, ix.K, L);
+              v = exp(-ix.a * D) / (pi * R);
             }
           }
-        } else {
-          for (int h = 0; h < d; ++h) {
-            const double dl = (double)qrow[h] - (double)xrow[h];
-            D = __builtin_fma(dl, dl, D);
-          }
         }
-        if (!(D >= Tlo && D < Thi)) continue;
-        const double R = literal ? 1.0 : recovery_dev(sqrt(D) / ri, K, L);
-        acc += exp(-a * D) / (pi * R);
-        ++na;
+        on_batch(v, j, valid);
       }
     }
     __builtin_amdgcn_wave_barrier();
   }
+}
+
+// One wave per (query, copy): the copy's estimate and candidate counts.
+template <int DREG>
+__global__ __launch_bounds__(256) void probe_queries(const float* __restrict__ Q, int ldq, int64_t q0, int64_t mb,
+                                                     IndexView ix, LevelConst lc, const uint64_t* __restrict__ qkeys,
+                                                     int64_t ntab, int self_excl, double* __restrict__ Scopy,
+                                                     int64_t* __restrict__ ncand, int64_t* __restrict__ nacc) {
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int64_t pair = (int64_t)blockIdx.x * 4 + wave;
+  if (pair >= mb * ix.K1) return;
+  const int64_t ql = pair / ix.K1;
+  const int t = (int)(pair % ix.K1);
+  const float* qrow = Q + (q0 + ql) * ldq;
+  double qr[DREG > 0 ? DREG : 1];
+  load_point<DREG>(qr, qrow, ix.d);
+  __shared__ uint64_t qk_s[4][64];
+  double acc = 0.0;
+  int64_t nc = 0, na = 0;
+  walk_copy<DREG>(ix, lc, t, qkeys + ql * ntab, qk_s[wave], qr, qrow, self_excl ? q0 + ql : -1,
+                  [&](double v, int32_t j, bool valid) {
+                    acc += v;
+                    nc += valid ? 1 : 0;
+                    na += v > 0.0 ? 1 : 0;
+                  });
   for (int o = 32; o > 0; o >>= 1) {
     acc += __shfl_xor(acc, o);
     nc += __shfl_xor(nc, o);
     na += __shfl_xor(na, o);
   }
   if (lane == 0) {
-    Scopy[ql * K1 + t] = acc;
+    Scopy[ql * ix.K1 + t] = acc;
     if (ncand) atomicAdd(reinterpret_cast<unsigned long long*>(ncand + q0 + ql), (unsigned long long)nc);
     if (nacc) atomicAdd(reinterpret_cast<unsigned long long*>(nacc + q0 + ql), (unsigned long long)na);
+  }
+}
+
+__device__ inline double wave_incl_scan_f64(double v) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const double u = __shfl_up(v, o);
+    if (lane >= o) v += u;
+  }
+  return v;
+}
+
+// Edge draws from the estimator's terms: one wave per node i (queried against
+// the data without its own point).  Lane r < s holds draw r: target
+// U(i, r) * sum_t S'_t(i), its copy (cumulative over copies) and remainder;
+// each needed copy is walked once, in batches whose inclusive prefix sums
+// locate every pending remainder.
+template <int DREG>
+__global__ __launch_bounds__(256) void draw_lsh(IndexView ix, LevelConst lc, const uint64_t* __restrict__ qkeys,
+                                                int64_t ntab, int64_t q0, int64_t mb, const double* __restrict__ Scopy,
+                                                const double* __restrict__ rest, int s, uint64_t seed,
+                                                int64_t* __restrict__ src, int64_t* __restrict__ dst,
+                                                double* __restrict__ w) {
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int64_t ql = (int64_t)blockIdx.x * 4 + wave;
+  if (ql >= mb) return;
+  const int64_t qi = q0 + ql;
+  const float* qrow = ix.X + qi * ix.dx;
+  double qr[DREG > 0 ? DREG : 1];
+  load_point<DREG>(qr, qrow, ix.d);
+  __shared__ uint64_t qk_s[4][64];
+  const double* sc = Scopy + ql * ix.K1;
+  double tot = 0.0;
+  for (int t = 0; t < ix.K1; ++t) tot += sc[t];
+  // this lane's draw
+  const bool mine = lane < s;
+  int tsel = -1;
+  double resid = 0.0;
+  int64_t pick = -1;
+  if (mine && tot > 0.0) {
+    const uint64_t ds = stream_state(seed, kTagDraw, (uint64_t)qi, 0);
+    const double u = (double)(mix64_hd(ds + (uint64_t)(lane + 1) * kGamma) >> 11) * 0x1.0p-53;
+    const double target = u * tot;
+    double c = 0.0;
+    for (int t = 0; t < ix.K1; ++t) {
+      if (c + sc[t] > target) {
+        tsel = t;
+        break;
+      }
+      c += sc[t];
+    }
+    if (tsel < 0) {
+      for (int t = ix.K1 - 1; t >= 0; --t)
+        if (sc[t] > 0.0) {
+          tsel = t;
+          break;
+        }
+      c = 0.0;
+      for (int t = 0; t < tsel; ++t) c += sc[t];
+    }
+    resid = target - c;
+  }
+  for (int t = 0; t < ix.K1; ++t) {
+    if (__ballot(mine && tsel == t) == 0) continue;
+    double running = 0.0;
+    int32_t lastj = -1;
+    walk_copy<DREG>(ix, lc, t, qkeys + ql * ntab, qk_s[wave], qr, qrow, qi, [&](double v, int32_t j, bool valid) {
+      const double incl = wave_incl_scan_f64(v);
+      const double btot = __shfl(incl, 63);
+      const uint64_t pos = __ballot(v > 0.0);
+      if (pos) lastj = __shfl(j, 63 - __clzll((long long)pos));
+      uint64_t pend = __ballot(mine && tsel == t && pick < 0 && resid < running + btot);
+      while (pend) {
+        const int r = __ffsll((long long)pend) - 1;
+        pend &= pend - 1;
+        const double x = __shfl(resid, r);
+        const uint64_t over = __ballot(running + incl > x);
+        const int kl = __ffsll((long long)over) - 1;
+        const int32_t jj = __shfl(j, kl);
+        if (lane == r) pick = jj;
+      }
+      running += btot;
+    });
+    if (mine && tsel == t && pick < 0) pick = lastj;  // rounding left the remainder above the total
+  }
+  if (mine) {
+    const int64_t e = qi * s + lane;
+    src[e] = qi;
+    dst[e] = pick;
+    w[e] = pick >= 0 ? 1.0 / ((double)s * (1.0 / rest[qi] + 1.0 / rest[pick])) : 0.0;
   }
 }
 
@@ -430,6 +560,11 @@ __global__ void mean_copies(const double* __restrict__ Scopy, int64_t q0, int64_
     if (copies_out) copies_out[(q0 + ql) * K1 + t] = v;
   }
   S_out[q0 + ql] = s / (double)K1;
+}
+
+__global__ void one_plus(const double* __restrict__ v, int64_t n, double* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = 1.0 + v[i];
 }
 
 __global__ void zero_i64(int64_t* p, int64_t n) {
@@ -716,50 +851,85 @@ stag_status create_index(const float* X, int64_t n, int d, double a, double eps,
   return STAG_OK;
 }
 
-stag_status query_index(const stag_lsh_index* idx, const float* Q, int64_t m, double* S_out, double* copies_out,
-                        int64_t* ncand, int64_t* nacc, hipStream_t st) {
+IndexView make_view(const stag_lsh_index* idx) {
   const LshParams& prm = idx->prm;
-  const int J = prm.shape.J, L = prm.shape.L, K = prm.shape.K, K1 = prm.shape.K1;
-  const int d = idx->d;
-  Workspace ws(st);
-  // query batches: keys of one batch take at most ~1 GiB
+  IndexView v;
+  v.X = idx->X;
+  v.dx = idx->dx;
+  v.d = idx->d;
+  v.K1 = prm.shape.K1;
+  v.J = prm.shape.J;
+  v.L = prm.shape.L;
+  v.K = prm.shape.K;
+  v.a = prm.a;
+  v.literal = (prm.flags & STAG_LSH_LITERAL) ? 1 : 0;
+  v.seg_off = idx->seg_off;
+  v.members = idx->members;
+  v.mkeys = idx->mkeys;
+  v.tab_seg_off = idx->tab_seg_off;
+  v.seg_cap = idx->seg_cap;
+  v.tab_key = idx->tab_key;
+  v.tab_start = idx->tab_start;
+  v.tab_cnt = idx->tab_cnt;
+  v.csr = idx->csr;
+  return v;
+}
+
+LevelConst make_levels(const LshParams& prm) {
+  LevelConst lc;
+  for (int i = 0; i <= 64; ++i) {
+    lc.p[i] = i <= prm.shape.J ? prm.lc_p[i] : 0.0;
+    lc.T[i] = i <= prm.shape.J ? prm.lc_T[i] : 0.0;
+    lc.r[i] = i <= prm.shape.J ? prm.lc_r[i] : 0.0;
+  }
+  return lc;
+}
+
+int64_t query_batch(const stag_lsh_index* idx, int64_t m) {
   int64_t mb = ((int64_t)1 << 30) / (8 * std::max<int64_t>(idx->ntab, 1)) / 64 * 64;
-  mb = std::max<int64_t>(64, std::min(mb, round_up(m, 64)));
+  return std::max<int64_t>(64, std::min(mb, round_up(m, 64)));
+}
+
+stag_status hash_query_batch(const stag_lsh_index* idx, const float* Q, int ldq, int64_t q0, int64_t cur,
+                             uint64_t* qkeys, hipStream_t st) {
+  const LshParams& prm = idx->prm;
+  int tpw = 1;
+  const int64_t qblocks = ceil_div(cur, 64);
+  while (tpw < idx->ntab && (qblocks * ceil_div(idx->ntab, 4 * tpw) > 262144 || ceil_div(idx->ntab, 4 * tpw) > 65535))
+    tpw *= 2;
+  ScopedTimer tm("lsh_hash_queries", st);
+  return dispatch_dreg(idx->dreg, [&](auto D) {
+    hipLaunchKernelGGL(hash_queries<decltype(D)::value>, dim3((unsigned)qblocks, (unsigned)ceil_div(idx->ntab, 4 * tpw)),
+                       dim3(256), 0, st, Q, ldq, q0, cur, idx->d, idx->dg, idx->G8, idx->B, prm.shape.K, prm.shape.L,
+                       idx->nch, idx->ntab, tpw, qkeys);
+    return check_launch("hash_queries");
+  });
+}
+
+// Estimates for rows of Q (self_excl: Q is the index's own data and each
+// row's own point is left out).  Optional per-copy values and counts.
+stag_status query_index(const stag_lsh_index* idx, const float* Q, int ldq, int64_t m, int self_excl,
+                        double* S_out, double* copies_out, int64_t* ncand, int64_t* nacc, hipStream_t st) {
+  const LshParams& prm = idx->prm;
+  const int K1 = prm.shape.K1;
+  Workspace ws(st);
+  const int64_t mb = query_batch(idx, m);
   uint64_t* qkeys = nullptr;
   double* scopy = nullptr;
   STAG_TRY(ws.alloc(&qkeys, (size_t)mb * idx->ntab));
   STAG_TRY(ws.alloc(&scopy, (size_t)mb * K1));
   if (ncand) hipLaunchKernelGGL(zero_i64, dim3((unsigned)ceil_div(m, 256)), dim3(256), 0, st, ncand, m);
   if (nacc) hipLaunchKernelGGL(zero_i64, dim3((unsigned)ceil_div(m, 256)), dim3(256), 0, st, nacc, m);
-  LevelConst lc;
-  for (int i = 0; i <= 64; ++i) {
-    lc.p[i] = i <= J ? prm.lc_p[i] : 0.0;
-    lc.T[i] = i <= J ? prm.lc_T[i] : 0.0;
-    lc.r[i] = i <= J ? prm.lc_r[i] : 0.0;
-  }
-  const int literal = (prm.flags & STAG_LSH_LITERAL) ? 1 : 0;
+  const IndexView ix = make_view(idx);
+  const LevelConst lc = make_levels(prm);
   for (int64_t q0 = 0; q0 < m; q0 += mb) {
     const int64_t cur = std::min(mb, m - q0);
-    int tpw = 1;
-    const int64_t qblocks = ceil_div(cur, 64);
-    while (tpw < idx->ntab && (qblocks * ceil_div(idx->ntab, 4 * tpw) > 262144 || ceil_div(idx->ntab, 4 * tpw) > 65535))
-      tpw *= 2;
-    {
-      ScopedTimer tm("lsh_hash_queries", st);
-      STAG_TRY(dispatch_dreg(idx->dreg, [&](auto D) {
-        hipLaunchKernelGGL(hash_queries<decltype(D)::value>,
-                           dim3((unsigned)qblocks, (unsigned)ceil_div(idx->ntab, 4 * tpw)), dim3(256), 0, st, Q, q0,
-                           cur, d, idx->dg, idx->G8, idx->B, K, L, idx->nch, idx->ntab, tpw, qkeys);
-        return check_launch("hash_queries");
-      }));
-    }
+    STAG_TRY(hash_query_batch(idx, Q, ldq, q0, cur, qkeys, st));
     {
       ScopedTimer tm("lsh_probe", st);
       STAG_TRY(dispatch_dreg(idx->dreg, [&](auto D) {
         hipLaunchKernelGGL(probe_queries<decltype(D)::value>, dim3((unsigned)ceil_div(cur * K1, 4)), dim3(256), 0,
-                           st, Q, q0, cur, d, idx->dx, idx->X, K1, J, L, K, prm.a, literal, lc, qkeys, idx->ntab,
-                           idx->seg_off, idx->members, idx->mkeys, idx->tab_seg_off, idx->seg_cap, idx->tab_key,
-                           idx->tab_start, idx->tab_cnt, idx->csr, scopy, ncand, nacc);
+                           st, Q, ldq, q0, cur, ix, lc, qkeys, idx->ntab, self_excl, scopy, ncand, nacc);
         return check_launch("probe_queries");
       }));
     }
@@ -771,6 +941,42 @@ stag_status query_index(const stag_lsh_index* idx, const float* Q, int64_t m, do
 }
 
 }  // namespace
+
+// Edge sampling with the CKNS estimator (see draw_lsh): rest_i = mean over
+// copies of the estimate of sum_{j != i} k_ij; deg = 1 + rest.
+stag_status lsh_sample_edges(const stag_lsh_index* idx, int s, uint64_t seed, int64_t* src, int64_t* dst, double* w,
+                             double* deg_out, hipStream_t st) {
+  const LshParams& prm = idx->prm;
+  const int K1 = prm.shape.K1;
+  const int64_t n = prm.n;
+  Workspace ws(st);
+  double* rest = nullptr;
+  double* copies = nullptr;
+  STAG_TRY(ws.alloc(&rest, (size_t)n));
+  STAG_TRY(ws.alloc(&copies, (size_t)n * K1));
+  STAG_TRY(query_index(idx, idx->X, idx->dx, n, 1, rest, copies, nullptr, nullptr, st));
+  const int64_t mb = query_batch(idx, n);
+  uint64_t* qkeys = nullptr;
+  STAG_TRY(ws.alloc(&qkeys, (size_t)mb * idx->ntab));
+  const IndexView ix = make_view(idx);
+  const LevelConst lc = make_levels(prm);
+  for (int64_t q0 = 0; q0 < n; q0 += mb) {
+    const int64_t cur = std::min(mb, n - q0);
+    STAG_TRY(hash_query_batch(idx, idx->X, idx->dx, q0, cur, qkeys, st));
+    ScopedTimer tm("simgraph_draw_lsh", st);
+    STAG_TRY(dispatch_dreg(idx->dreg, [&](auto D) {
+      hipLaunchKernelGGL(draw_lsh<decltype(D)::value>, dim3((unsigned)ceil_div(cur, 4)), dim3(256), 0, st, ix, lc,
+                         qkeys, idx->ntab, q0, cur, copies + q0 * K1, rest, s, seed, src, dst, w);
+      return check_launch("draw_lsh");
+    }));
+  }
+  if (deg_out) {
+    hipLaunchKernelGGL(one_plus, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, st, rest, n, deg_out);
+    STAG_TRY(check_launch("one_plus"));
+  }
+  return STAG_OK;
+}
+
 }  // namespace stag
 
 using namespace stag;
@@ -820,7 +1026,7 @@ stag_status stag_lsh_index_query_ex(const stag_lsh_index* idx, const float* Q, i
   if (!idx || !Q || !S_out) return fail(STAG_E_INVAL, "stag_lsh_index_query: NULL argument");
   if (m < 1) return fail(STAG_E_INVAL, "stag_lsh_index_query: m must be >= 1");
   clear_error();
-  return query_index(idx, Q, m, S_out, S_copies, n_cand, n_acc, stream);
+  return query_index(idx, Q, idx->d, m, 0, S_out, S_copies, n_cand, n_acc, stream);
 }
 
 stag_status stag_lsh_index_query(const stag_lsh_index* idx, const float* Q, int64_t m, double* S_out,

@@ -58,3 +58,47 @@ def test_uniform_draws(orc):
     u = np.array([orc.draw_uniform(5, i, r) for i in range(200) for r in range(50)])
     assert np.all((u >= 0) & (u < 1))
     assert stats.kstest(u, "uniform").pvalue > 1e-4
+
+
+def test_lsh_mode_degenerate_equals_exact_rows(orc):
+    """With every point sampled, zero projections and 2^i weights the CKNS
+    terms of node i are exactly k_ij for D < T_J, so the LSH-mode degrees equal
+    the exact ones (all pairs within T_J here) and the draws follow k_ij."""
+    import synth
+    rng = np.random.default_rng(8)
+    n, d, a, s = 14, 2, 0.2, 64
+    X = (0.6 * rng.normal(size=(n, d))).astype(np.float32)
+    kw = dict(eps=0.5, k1=1, k2_constant=2, flags=orc.FLAG_LITERAL | orc.FLAG_ALL_SAMPLED)
+    sh = orc.lsh_derive(n, a, **kw)
+    Kf = _kmat(X, a)
+    D = -np.log(Kf) / a
+    assert D.max() < sh["T"][-1]
+    npj = sh["K1"] * sh["J"] * sh["L"] * sh["K"]
+    G0, B = synth.e2lsh_randomness(npj, d, 3)
+    src, dst, w, deg, mg = orc.simgraph_lsh(X, a, s, 21, np.zeros_like(G0), B, lsh_seed=4, **kw)
+    assert np.allclose(deg, Kf.sum(1), rtol=1e-12)
+    _, _, w_ex, deg_ex = orc.simgraph_exact(X, a, s, seed=21)
+    assert np.allclose(deg, deg_ex, rtol=1e-12)
+    assert np.all(src != dst) and np.all(w > 0)
+    # chi-square of all draws pooled over nodes against k_ij / rest_i
+    obs = np.zeros((n, n))
+    np.add.at(obs, (src, dst), 1)
+    exp_ = (Kf - np.eye(n)) / (Kf.sum(1, keepdims=True) - 1) * s
+    keep = exp_ > 0
+    chi = stats.chisquare(obs[keep], exp_[keep] * obs[keep].sum() / exp_[keep].sum())
+    assert chi.pvalue > 1e-4
+
+
+def test_lsh_mode_weights_and_margins(orc):
+    import synth
+    X, _, _ = synth.config_points(1, n=300, m=1)
+    kw = dict(eps=0.5, k1=2, k2_constant=4)
+    sh = orc.lsh_derive(300, 0.05, **kw)
+    npj = sh["K1"] * sh["J"] * sh["L"] * sh["K"]
+    G0, B = synth.e2lsh_randomness(npj, 10, 9)
+    src, dst, w, deg, mg = orc.simgraph_lsh(X, 0.05, 6, 5, G0, B, lsh_seed=6, **kw)
+    ok = dst >= 0
+    assert ok.mean() > 0.9
+    rest = deg - 1
+    assert np.allclose(w[ok], 1 / (6 * (1 / rest[src[ok]] + 1 / rest[dst[ok]])), rtol=1e-14)
+    assert np.all(mg[ok] >= 0) and np.all(src[ok] != dst[ok])
