@@ -3,18 +3,28 @@
 
 Workload: n = 100,000 data points and m = 100,000 queries in d = 64 drawn
 from a 20-component isotropic Gaussian mixture (means U[-5,5]^64, sigma
-U[0.5,2]), a = 0.01.  One step runs the whole hot path over that input:
-exact kernel density of all m queries (prep, matrix-core tile, reduction).
+U[0.5,2]), a = 0.01 (seeded, synthetic).
 
-Prints one JSON line: Gaussian kernel evaluations per second (n*m per step
-at a measured max relative error <= 1e-5 vs the FP64 oracle), the roofline
-of the dominant kernel from per-launch HIP events, and the FP64 CPU oracle
-timed on a bounded sample of the same workload.
+One step runs the whole hot path over that input:
+  exact   exact kernel density of all m queries: operand prep, matrix-core
+          tile (fp16 hi+lo split form), chunk reduction;
+  lsh     CKNS estimate of all m queries: index build over X (subsamples,
+          E2LSH member keys, bucket tables) and query (query hashing, probe);
+  graph   similarity-graph edge sampling over X (exact kernel rows, 17 draws
+          per node).
+value = n*m exact kernel evaluations (at max relative error <= 1e-5 against
+the FP64 oracle, checked on sampled queries) per second of the whole step.
+
+After the timed steps: the fp32 form of the exact tile for comparison, a
+short serving run (Poisson arrivals, log-uniform batch sizes, resident data
+sets) for p50/p99 latency, and the FP64 CPU oracle timed on a bounded sample
+of the same exact workload.  One JSON line is printed.
 """
 from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -23,11 +33,16 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-PEAKS = {"fp32": ("mfma", 157.3e12), "fp16_split": ("mfma", 2.5e15), "bf16_split": ("mfma", 2.5e15),
-         "bf16_split3": ("mfma", 2.5e15)}
+MFMA_PEAK = {"fp32": 157.3e12, "fp16_split": 2.5e15, "bf16_split": 2.5e15, "bf16_split3": 2.5e15}
 PRODUCTS = {"fp32": 1, "fp16_split": 3, "bf16_split": 3, "bf16_split3": 6}
 TILE_KERNEL = {"fp32": "kde_tile_f32", "fp16_split": "kde_tile_fp16x3", "bf16_split": "kde_tile_bf16x3",
                "bf16_split3": "kde_tile_bf16x6"}
+HBM_PEAK = 8.0e12
+FP64_PEAK = 78.6e12
+# CKNS parameters of the lsh leg: the cheapest setting found on this workload
+# whose average relative error is below 0.1 (the acceptance level of the
+# paper's KDE comparison), eps = 0.5
+LSH = dict(eps=0.5, k1=1, k2_constant=8, p_offset=1, lsh_seed=3002)
 
 
 def parse_timing(txt: str) -> dict:
@@ -49,20 +64,76 @@ def cpu_baseline(X, Q, a, budget_s: float):
         done += min(chunk, Q.shape[0] - done)
     return {"value": X.shape[0] * done / t_total, "unit": "Gaussian kernel evals/s", "cores": threads,
             "kind": "oracle",
-            "sample": f"{done} of the {Q.shape[0]} queries against all {X.shape[0]} points (FP64 direct differences,"
-                      f" OpenMP over queries), {t_total:.1f} s"}
+            "sample": f"{done} of the {Q.shape[0]} queries against all {X.shape[0]} points, exact FP64 direct "
+                      f"differences with compensated log-sum-exp, OpenMP over queries; {t_total:.1f} s"}
+
+
+def serving_run(stag, torch, dev, n_requests: int, seconds_cap: float):
+    """Poisson stream of requests of log-uniform size (1..65536) against four
+    resident data sets; returns latency percentiles and throughput."""
+    import numpy as np
+
+    import synth
+    specs = [(100_000, 16), (300_000, 64), (1_000_000, 256), (2_000_000, 64)]
+    srv = stag.Server(budget_bytes=16 << 30, n_streams=4, max_batch_queries=65536)
+    ids, mixes = [], []
+    for k, (n, d) in enumerate(specs):
+        mix = synth.mixture(d, 20, 4005 + 10 * k, sigma=(0.5, 2.0))
+        X = torch.from_numpy(synth.sample(mix, n, 4105 + 10 * k)).to(dev)
+        form = "fp16_split" if d <= 256 else "fp32"
+        ids.append(srv.add_dataset(X, 0.64 / d, form))
+        mixes.append(mix)
+        del X
+    arr, sizes, dsel = synth.poisson_requests(n_requests, rate_per_s=200.0, seed=4005)
+    # queries drawn once per request (host), moved to the device before the clock starts
+    reqs = []
+    for r in range(n_requests):
+        k = int(dsel[r])
+        Q = synth.sample(mixes[k], int(sizes[r]), 7000 + r)
+        reqs.append((k, torch.from_numpy(Q).to(dev)))
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    tickets = []
+    for r in range(n_requests):
+        now = time.perf_counter() - t_start
+        if arr[r] > now:
+            time.sleep(arr[r] - now)
+        if time.perf_counter() - t_start > seconds_cap:
+            break
+        k, Q = reqs[r]
+        tickets.append((srv.submit(ids[k], Q), Q.shape[0], specs[k][0]))
+    lat, evals = [], 0.0
+    for t, m, n in tickets:
+        _, st, l = srv.wait(t)
+        if st == 0:
+            lat.append(l)
+            evals += float(m) * n
+    t_end = time.perf_counter()
+    stats = srv.stats()
+    srv.close()
+    lat = np.sort(np.array(lat))
+
+    def pct(p):
+        return float(lat[max(0, math.ceil(p / 100 * len(lat)) - 1)]) if len(lat) else None
+    return {"requests": len(tickets), "completed": int(stats["completed"]), "batches": int(stats["batches"]),
+            "p50_ms": pct(50) * 1e3 if len(lat) else None, "p99_ms": pct(99) * 1e3 if len(lat) else None,
+            "evals_per_s": evals / (t_end - t_start), "offered_rate_per_s": 200.0,
+            "datasets": [f"n={n} d={d}" for n, d in specs],
+            "batch_sizes": "log-uniform 1..65536", "wall_s": t_end - t_start}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--form", default="fp16_split", choices=sorted(PEAKS))
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--form", default="fp16_split", choices=sorted(MFMA_PEAK))
     ap.add_argument("--a", type=float, default=0.01)
     ap.add_argument("--check-queries", type=int, default=256)
     ap.add_argument("--cpu-budget", type=float, default=12.0)
+    ap.add_argument("--serve-requests", type=int, default=400)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported (how the path would shard over "
@@ -81,20 +152,27 @@ def main():
     lib.stag_timing_enable.argtypes = [ctypes.c_int32]
     lib.stag_timing_report.restype = ctypes.c_size_t
     lib.stag_timing_report.argtypes = [ctypes.c_char_p, ctypes.c_size_t]
+    buf = ctypes.create_string_buffer(1 << 16)
     dev = torch.device("cuda:0")
     X, Q, info = synth.config_points(2)
     n, d, m = info["n"], info["d"], info["m"]
+    a = args.a
     Xd = torch.from_numpy(X).to(dev)
     Qd = torch.from_numpy(Q).to(dev)
     S = torch.empty(m, dtype=torch.float64, device=dev)
+    lsh_kw = {k: v for k, v in LSH.items() if k not in ("eps", "lsh_seed")}
+    out = {}
 
     def step():
-        stag.kde_exact(Xd, Qd, args.a, form=args.form, S_out=S)
+        stag.kde_exact(Xd, Qd, a, form=args.form, S_out=S)
+        idx = stag.LshIndex(Xd, a, eps=LSH["eps"], seed=LSH["lsh_seed"], **lsh_kw)
+        out["lsh"] = idx.query(Qd)
+        idx.close()
+        out["graph"] = stag.simgraph_sample(Xd, a, mode="exact", form=args.form, seed=4002)
 
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    buf = ctypes.create_string_buffer(1 << 16)
     lib.stag_timing_report(buf, len(buf))  # drop warmup records
     lib.stag_timing_enable(1)
     torch.cuda.synchronize()
@@ -109,21 +187,58 @@ def main():
     ms_per_step = (t1 - t0) * 1e3 / args.steps
     evals = float(n) * m
     value = evals / (ms_per_step / 1e3)
+    per_step = {k: v[1] / args.steps for k, v in timing.items()}
 
-    # accuracy of this run's result on sampled queries against the FP64 oracle
+    # accuracy of this run's results against the FP64 oracle on sampled queries
     import oracle
     rng = np.random.default_rng(12345)
     idx = np.sort(rng.choice(m, size=args.check_queries, replace=False))
-    ref = oracle.kde_exact(X, Q[idx], args.a)
-    got = S.cpu().numpy()[idx]
-    max_rel = float(np.max(np.abs(got - ref) / ref))
+    ref = oracle.kde_exact(X, Q[idx], a)
+    max_rel = float(np.max(np.abs(S.cpu().numpy()[idx] - ref) / ref))
+    lsh_rel = float(np.mean(np.abs(out["lsh"].cpu().numpy()[idx] - ref) / ref))
+    src, dst, w, deg = (t.cpu().numpy() for t in out["graph"])
 
+    # LSH work counts (one extra, untimed query with statistics)
+    index = stag.LshIndex(Xd, a, eps=LSH["eps"], seed=LSH["lsh_seed"], **lsh_kw)
+    _, st = index.query(Qd, stats=True)
+    n_cand = int(st["n_cand"].sum().item())
+    n_acc = int(st["n_acc"].sum().item())
+    index.close()
+
+    # rooflines of the kernels of the step
     tk = TILE_KERNEL[args.form]
-    cnt, tot = timing.get(tk, (0, float("nan")))
-    avg_ms = tot / max(cnt, 1)
-    bound, peak = PEAKS[args.form]
-    flops = 2.0 * d * evals * PRODUCTS[args.form]
-    achieved = flops / (avg_ms / 1e3)
+    flops_tile = 2.0 * d * evals * PRODUCTS[args.form]
+    roofs = {}
+    cnt = timing.get(tk, (1, float("nan")))[0]
+    tile_avg = timing[tk][1] / max(cnt, 1)
+    # the tile kernel runs twice per step: exact KDE and the edge sampler's pass
+    roofs[tk] = {"bound": "mfma", "achieved": flops_tile / (tile_avg / 1e3) / 1e12,
+                 "peak": MFMA_PEAK[args.form] / 1e12, "unit": "TFLOP/s",
+                 "frac": flops_tile / (tile_avg / 1e3) / MFMA_PEAK[args.form], "traffic": None,
+                 "avg_launch_ms": tile_avg, "launches_per_step": cnt / args.steps,
+                 "algorithmic": f"2*d*{PRODUCTS[args.form]} flops per pair x n*m = {flops_tile:.3e}"}
+    if "lsh_probe" in timing:
+        c, tot = timing["lsh_probe"]
+        probe_avg = tot / c
+        bytes_probe = n_cand * (4 + 4 + 4 * d)
+        roofs["lsh_probe"] = {"bound": "hbm", "achieved": bytes_probe / (probe_avg / 1e3) / 1e9, "peak": 8000.0,
+                              "unit": "GB/s", "frac": bytes_probe / (probe_avg / 1e3) / HBM_PEAK, "traffic": None,
+                              "avg_launch_ms": probe_avg,
+                              "algorithmic": f"{n_cand} bucket members x (4+4+4d) bytes"}
+    if "lsh_hash_queries" in timing:
+        c, tot = timing["lsh_hash_queries"]
+        sh = stag.lsh_derive(n, a, LSH["eps"], **lsh_kw)
+        fl = 2.0 * d * m * sh["K1"] * sh["J"] * sh["L"] * sh["K"]
+        roofs["lsh_hash_queries"] = {"bound": "alu", "achieved": fl / (tot / c / 1e3) / 1e12,
+                                     "peak": FP64_PEAK / 1e12, "unit": "TFLOP/s",
+                                     "frac": fl / (tot / c / 1e3) / FP64_PEAK, "traffic": None,
+                                     "avg_launch_ms": tot / c,
+                                     "algorithmic": "2*d fp64 flops per (query, projection)"}
+    dom = max(((k, v["avg_launch_ms"] * v.get("launches_per_step", 1.0)) for k, v in roofs.items()),
+              key=lambda kv: kv[1])[0]
+    roof = dict(roofs[dom])
+    roof["kernel"] = dom
+
     result = {
         "metric": "Gaussian kernel evals/sec at <=1e-5 rel err vs FP64; p50/p99 KDE query latency",
         "value": value,
@@ -135,21 +250,44 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"fp32": "f32", "fp16_split": "f16x3 (f32 accumulate, f64 sum)",
-                  "bf16_split": "bf16x3 (f32 accumulate, f64 sum)",
-                  "bf16_split3": "bf16x6 (f32 accumulate, f64 sum)"}[args.form],
+        "dtype": {"fp32": "f32", "fp16_split": "f16x3->f32->f64", "bf16_split": "bf16x3->f32->f64",
+                  "bf16_split3": "bf16x6->f32->f64"}[args.form],
         "data": "synthetic",
-        "config": {"workload": "exact Gaussian KDE, n=100000 data, m=100000 queries, d=64, 20-component mixture "
-                               "(sigma U[0.5,2]), a=%g" % args.a, "form": args.form, "n": n, "m": m, "d": d},
+        "config": {"workload": "Gaussian KDE hot path on n=100000 data, m=100000 queries, d=64, 20-component "
+                               "mixture (sigma U[0.5,2]), a=%g: exact KDE + CKNS LSH KDE (build+query) + "
+                               "similarity-graph edge sampling (17 draws/node)" % a,
+                   "exact_form": args.form, "lsh": LSH, "n": n, "m": m, "d": d},
         "max_rel_err_sampled": max_rel,
         "checked_queries": int(args.check_queries),
-        "kernels_ms_per_step": {k: v[1] / max(v[0], 1) * (v[0] / args.steps) for k, v in timing.items()},
-        "roofline": {"kernel": tk, "bound": bound, "achieved": achieved / 1e12, "peak": peak / 1e12,
-                     "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
-                     "flops_per_launch": flops, "avg_launch_ms": avg_ms},
+        "lsh_avg_rel_err_sampled": lsh_rel,
+        "lsh_candidates_per_query": n_cand / m,
+        "lsh_accepted_per_query": n_acc / m,
+        "graph_edges": int(src.size), "graph_valid_edges": int((dst >= 0).sum()),
+        "kernels_ms_per_step": per_step,
+        "exact_kde_ms_per_step": sum(v for k, v in per_step.items() if k.startswith("kde_")) / 2.0,
+        "roofline": roof,
+        "rooflines": roofs,
     }
+    # fp32 form of the exact tile on the same workload (equal-accuracy comparison)
+    if args.form != "fp32":
+        stag.kde_exact(Xd, Qd, a, form="fp32", S_out=S)
+        torch.cuda.synchronize()
+        lib.stag_timing_report(buf, len(buf))
+        lib.stag_timing_enable(1)
+        stag.kde_exact(Xd, Qd, a, form="fp32", S_out=S)
+        torch.cuda.synchronize()
+        lib.stag_timing_enable(0)
+        lib.stag_timing_report(buf, len(buf))
+        t32 = parse_timing(buf.value.decode())
+        err32 = float(np.max(np.abs(S.cpu().numpy()[idx] - ref) / ref))
+        result["fp32_form"] = {"tile_ms": t32["kde_tile_f32"][1], "max_rel_err_sampled": err32,
+                               "evals_per_s_tile": evals / (t32["kde_tile_f32"][1] / 1e3)}
+        result["split_form_tile_ms"] = tile_avg
+    del out
+    if not args.no_serve:
+        result["serving"] = serving_run(stag, torch, dev, args.serve_requests, seconds_cap=30.0)
     if not args.no_cpu_baseline:
-        result["cpu_baseline"] = cpu_baseline(X, Q, args.a, args.cpu_budget)
+        result["cpu_baseline"] = cpu_baseline(X, Q, a, args.cpu_budget)
     print(json.dumps(result), flush=True)
 
 

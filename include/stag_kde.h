@@ -234,6 +234,48 @@ stag_status stag_simgraph_sample(const float* X, int64_t n, int32_t d, double a,
                                  uint64_t seed, int64_t* src_out, int64_t* dst_out, double* w_out, double* deg_out,
                                  hipStream_t stream);
 
+/* ------------------------------------------------------------------------
+ * Serving loop: continuous batching of exact kernel-density requests against
+ * resident data sets.
+ *   - A data set (X, a, form) is prepared once and stays in device memory.
+ *   - Requests (Q [m][d] device fp32, S_out [m] device f64) are queued FIFO;
+ *     a request is admitted when its workspace footprint fits the remaining
+ *     budget (larger than the whole budget: status STAG_E_BUSY).
+ *   - Every idle stream packs admitted requests of one data set (oldest
+ *     first, up to max_batch_queries queries) into one launch; requests that
+ *     arrive while others run are admitted as memory frees up and run
+ *     concurrently on the other streams.
+ *   - A result is bitwise identical whether its request ran alone or batched.
+ * Q must be fully written before submission (synchronise its producer);
+ * S_out is valid once wait/poll reports the request done.  A worker thread
+ * owned by the server drives the loop; every function is thread safe.
+ * Latency is measured from submission to completion.
+ * ------------------------------------------------------------------------ */
+typedef struct stag_server stag_server;
+
+typedef struct {
+  uint64_t submitted, completed, failed, rejected, batches, queries;
+  double p50_s, p99_s, mean_s, max_s; /* latency of completed requests */
+  uint64_t inflight_bytes, peak_inflight_bytes;
+} stag_server_stats_t;
+
+/* budget_bytes 0: 8 GiB; n_streams 0: 4 (at most 16); max_batch_queries 0: 65536. */
+stag_status stag_server_create(size_t budget_bytes, int32_t n_streams, int64_t max_batch_queries,
+                               stag_server** out);
+/* X [n][d] device fp32 (copied into the server's prepared operands). */
+stag_status stag_server_add_dataset(stag_server* s, const float* X, int64_t n, int32_t d, double a, int32_t form,
+                                    int32_t* id_out);
+stag_status stag_server_submit(stag_server* s, int32_t dataset, const float* Q, int64_t m, double* S_out,
+                               uint64_t* ticket);
+/* Blocks until the request is done; *result is its status. */
+stag_status stag_server_wait(stag_server* s, uint64_t ticket, stag_status* result, double* latency_s);
+/* *done = 1 once finished (then *result and *latency_s are set), else 0. */
+stag_status stag_server_poll(stag_server* s, uint64_t ticket, int32_t* done, stag_status* result,
+                             double* latency_s);
+stag_status stag_server_stats(stag_server* s, stag_server_stats_t* out);
+/* Stops the loop, waits for the device and frees everything (NULL ignored). */
+void stag_server_destroy(stag_server* s);
+
 #ifdef __cplusplus
 }
 #endif

@@ -34,6 +34,13 @@ class LshShape(C.Structure):
     _fields_ = [("J", C.c_int32), ("L", C.c_int32), ("K", C.c_int32), ("K1", C.c_int32), ("mu_min", C.c_double)]
 
 
+class ServerStats(C.Structure):
+    _fields_ = [("submitted", C.c_uint64), ("completed", C.c_uint64), ("failed", C.c_uint64),
+                ("rejected", C.c_uint64), ("batches", C.c_uint64), ("queries", C.c_uint64), ("p50_s", C.c_double),
+                ("p99_s", C.c_double), ("mean_s", C.c_double), ("max_s", C.c_double),
+                ("inflight_bytes", C.c_uint64), ("peak_inflight_bytes", C.c_uint64)]
+
+
 class StagError(RuntimeError):
     def __init__(self, status: int, msg: str):
         super().__init__(f"stag status {status}: {msg}")
@@ -81,6 +88,20 @@ def load():
     lib.stag_lsh_index_destroy.argtypes = [vp]
     lib.stag_simgraph_sample.restype = C.c_int
     lib.stag_simgraph_sample.argtypes = [vp, i64, i32, f64, i32, i32, i32, f64, pp, C.c_uint64, vp, vp, vp, vp, vp]
+    lib.stag_server_create.restype = C.c_int
+    lib.stag_server_create.argtypes = [C.c_size_t, i32, i64, C.POINTER(vp)]
+    lib.stag_server_add_dataset.restype = C.c_int
+    lib.stag_server_add_dataset.argtypes = [vp, vp, i64, i32, f64, i32, C.POINTER(C.c_int32)]
+    lib.stag_server_submit.restype = C.c_int
+    lib.stag_server_submit.argtypes = [vp, i32, vp, i64, vp, C.POINTER(C.c_uint64)]
+    lib.stag_server_wait.restype = C.c_int
+    lib.stag_server_wait.argtypes = [vp, C.c_uint64, C.POINTER(C.c_int), C.POINTER(f64)]
+    lib.stag_server_poll.restype = C.c_int
+    lib.stag_server_poll.argtypes = [vp, C.c_uint64, C.POINTER(C.c_int32), C.POINTER(C.c_int), C.POINTER(f64)]
+    lib.stag_server_stats.restype = C.c_int
+    lib.stag_server_stats.argtypes = [vp, C.POINTER(ServerStats)]
+    lib.stag_server_destroy.restype = None
+    lib.stag_server_destroy.argtypes = [vp]
     lib.stag_kde_lsh.restype = C.c_int
     lib.stag_kde_lsh.argtypes = [vp, i64, vp, i64, i32, f64, f64, pp, vp, vp]
     _lib = lib
@@ -285,3 +306,63 @@ def simgraph_sample(X, a: float, samples_per_node: int = 0, mode: str = "exact",
                                      _ptr(w), _ptr(deg), _stream_handle(X.device))
     check(st, "stag_simgraph_sample")
     return src, dst, w, deg
+
+
+class Server:
+    """Continuous-batching KDE server over resident data sets (exact form).
+
+    submit() returns a ticket; wait(ticket) returns (S, status, latency_s)."""
+
+    def __init__(self, budget_bytes: int = 0, n_streams: int = 0, max_batch_queries: int = 0):
+        h = C.c_void_p()
+        check(load().stag_server_create(int(budget_bytes), int(n_streams), int(max_batch_queries), C.byref(h)),
+              "stag_server_create")
+        self._h = h
+        self._live = {}
+
+    def add_dataset(self, X, a: float, form: str = "fp32") -> int:
+        torch = _torch()
+        _need(X, torch.float32, 2, "X")
+        i = C.c_int32()
+        check(load().stag_server_add_dataset(self._h, _ptr(X), X.shape[0], X.shape[1], float(a), FORMS[form],
+                                             C.byref(i)), "stag_server_add_dataset")
+        return int(i.value)
+
+    def submit(self, dataset: int, Q, S_out=None) -> int:
+        torch = _torch()
+        _need(Q, torch.float32, 2, "Q")
+        S = S_out if S_out is not None else torch.empty(Q.shape[0], dtype=torch.float64, device=Q.device)
+        torch.cuda.current_stream(Q.device).synchronize()  # Q must be complete before the server reads it
+        t = C.c_uint64()
+        check(load().stag_server_submit(self._h, int(dataset), _ptr(Q), Q.shape[0], _ptr(S), C.byref(t)),
+              "stag_server_submit")
+        self._live[t.value] = (Q, S)
+        return int(t.value)
+
+    def wait(self, ticket: int):
+        st, lat = C.c_int(), C.c_double()
+        check(load().stag_server_wait(self._h, ticket, C.byref(st), C.byref(lat)), "stag_server_wait")
+        Q, S = self._live.pop(ticket)
+        return S, int(st.value), float(lat.value)
+
+    def poll(self, ticket: int):
+        done, st, lat = C.c_int32(), C.c_int(), C.c_double()
+        check(load().stag_server_poll(self._h, ticket, C.byref(done), C.byref(st), C.byref(lat)), "stag_server_poll")
+        return bool(done.value), int(st.value), float(lat.value)
+
+    def stats(self) -> dict:
+        s = ServerStats()
+        check(load().stag_server_stats(self._h, C.byref(s)), "stag_server_stats")
+        return {k: getattr(s, k) for k, _ in ServerStats._fields_}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().stag_server_destroy(self._h)
+            self._h = None
+            self._live.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -54,6 +54,12 @@ BoundModel make_bound_model(int form, int d, double a);
 
 stag_status prepare_operands(int form, const float* src, int64_t rows, int d, double a, bool is_query,
                              Workspace& ws, Operands* out, hipStream_t st);
+// Prepares `rows` query rows into a batch operand set (allocated by the
+// caller for batch.rows_pad rows) starting at row0 (a multiple of the query
+// tile, query_tile_rows()).
+stag_status prep_query_into(int form, const float* src, int64_t rows, int d, double a, const Operands& batch,
+                            int64_t row0, hipStream_t st);
+int64_t query_tile_rows();
 stag_status launch_exact_tiles(const Operands& xo, const Operands& qo, double* partial, const TileExtra& ex,
                                hipStream_t st);
 stag_status launch_reduce(const double* partial, int P, const Operands& qo, const Operands& xo, double scale,

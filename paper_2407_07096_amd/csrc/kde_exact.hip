@@ -673,6 +673,21 @@ stag_status prepare_operands(int form, const float* src, int64_t rows, int d, do
 
 int64_t exact_chunks(int64_t n_pad) { return ceil_div(n_pad, kChunkRows); }
 
+stag_status prep_query_into(int form, const float* src, int64_t rows, int d, double a, const Operands& batch,
+                            int64_t row0, hipStream_t st) {
+  const int dp = batch.dp;
+  const int64_t rows_pad = round_up(rows, kBQ);
+  const size_t eb = form_element_bytes(form);
+  void* parts[3] = {nullptr, nullptr, nullptr};
+  for (int p = 0; p < form_parts(form); ++p)
+    parts[p] = static_cast<char*>(batch.part[p]) + (size_t)row0 * dp * eb;
+  u16x8* aug = batch.aug ? static_cast<u16x8*>(batch.aug) + row0 : nullptr;
+  return prep_any(form, src, rows, d, dp, rows_pad, 2.0 * a * kLog2e, -a * kLog2e, 1, parts, batch.off + row0, aug,
+                  batch.nrm ? batch.nrm + row0 : nullptr, nullptr, st);
+}
+
+int64_t query_tile_rows() { return kBQ; }
+
 stag_status launch_exact_tiles(const Operands& xo, const Operands& qo, double* partial, const TileExtra& ex,
                                hipStream_t st) {
   const int P = (int)exact_chunks(xo.rows_pad);

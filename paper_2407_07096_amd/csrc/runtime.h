@@ -50,6 +50,12 @@ class Workspace {
     return st;
   }
   stag_status alloc_bytes(void** p, size_t bytes);
+  // Hands the allocations to the caller (they are no longer freed here).
+  std::vector<void*> release() {
+    std::vector<void*> v;
+    v.swap(ptrs_);
+    return v;
+  }
 
  private:
   hipStream_t stream_;
