@@ -134,6 +134,9 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=400)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--calib-copy-mb", type=int, default=0,
+                    help="after the timed steps, one plain device copy of this many MiB (a reference for "
+                         "hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported (how the path would shard over "
@@ -284,6 +287,14 @@ def main():
                                "evals_per_s_tile": evals / (t32["kde_tile_f32"][1] / 1e3)}
         result["split_form_tile_ms"] = tile_avg
     del out
+    if args.calib_copy_mb > 0:
+        src_c = torch.ones(args.calib_copy_mb << 18, dtype=torch.float32, device=dev)
+        dst_c = torch.empty_like(src_c)
+        torch.cuda.synchronize()
+        dst_c.copy_(src_c)
+        torch.cuda.synchronize()
+        result["calib_copy_bytes"] = args.calib_copy_mb << 20
+        del src_c, dst_c
     if not args.no_serve:
         result["serving"] = serving_run(stag, torch, dev, args.serve_requests, seconds_cap=30.0)
     if not args.no_cpu_baseline:

@@ -39,11 +39,11 @@ __host__ __device__ inline double relative_bound(const BoundModel& bm, double qn
 
 // Optional epilogue outputs of the tiles (edge sampling): drop the diagonal
 // when a data set is queried against itself, and write per-32-row-tile
-// partial sums tp[tile][m_pad] (fp32).
+// partial sums tp[query][tile] (fp32, ntile = padded data rows / 32).
 struct TileExtra {
   int self = 0;
   float* tp = nullptr;
-  int64_t m_pad = 0;
+  int64_t ntile = 0;
 };
 
 int exact_padded_dim(int d);  // 0 if unsupported

@@ -92,7 +92,7 @@ __device__ inline float tile_epilogue(const f32x16& c, int64_t row_base, int64_t
     if (ex.tp) {
       const float o = __shfl_xor(s, 32);
       const float tot = h == 0 ? s + o : o + s;
-      if (h == 0) ex.tp[(row_base / kTileRows) * ex.m_pad + qi] = tot;
+      if (h == 0) ex.tp[qi * ex.ntile + row_base / kTileRows] = tot;
     }
   }
   return s;

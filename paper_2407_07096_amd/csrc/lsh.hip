@@ -331,15 +331,30 @@ struct IndexView {
   const int32_t* csr;
 };
 
-// Walks copy t of the estimator for one query (one wave): levels and tables
-// in order, bucket members in ascending order in batches of 64 (one per lane).
-// For every batch, on_batch(v, j, valid) receives each lane's term v (0 if
-// the member was seen in an earlier table, lies outside the level, or is the
-// query's own point when self_idx >= 0) and its point j.
-template <int DREG, class F>
+template <int DREG>
+__device__ inline void load_point_f32(float* xr, const float* __restrict__ xrow, int d) {
+  if constexpr (DREG > 0) {
+#pragma unroll
+    for (int j = 0; j < DREG; ++j) xr[j] = j < d ? xrow[j] : 0.0f;
+  }
+}
+
+// Per-wave scratch of a copy walk (LDS).
+struct WalkScratch {
+  uint64_t qk[64];     // the query's keys of the current level, per table
+  int64_t base[64];    // csr index of the query's bucket in each table
+  uint32_t pre[64];    // exclusive prefix of the bucket sizes over tables
+};
+
+// Walks copy t of the estimator for one query (one wave).  Per level, lane l
+// resolves the query's bucket in table l; the buckets' members are then
+// taken as one flattened list (table, member ascending) in batches of 64, one
+// candidate per lane.  For every batch, on_batch(v, j, valid) receives each
+// lane's term v (0 if the member was seen in an earlier table, lies outside
+// the level, or is the query's own point when self_idx >= 0) and its point j.
+template <class F>
 __device__ inline void walk_copy(const IndexView& ix, const LevelConst& lc, int t, const uint64_t* __restrict__ qk,
-                                 uint64_t* qk_s, const double* qr, const float* __restrict__ qrow, int64_t self_idx,
-                                 F&& on_batch) {
+                                 WalkScratch& ws, const float* __restrict__ qrow, int64_t self_idx, F&& on_batch) {
   const int lane = threadIdx.x & 63;
   const int L = ix.L, d = ix.d;
   for (int i = 1; i <= ix.J; ++i) {
@@ -349,102 +364,113 @@ __device__ inline void walk_copy(const IndexView& ix, const LevelConst& lc, int 
     if (cnt == 0) continue;
     const uint32_t cap = ix.seg_cap[seg], mask = cap - 1;
     const double Tlo = lc.T[i - 1], Thi = lc.T[i], pi = lc.p[i], ri = lc.r[i];
-    const uint64_t* qks = qk + (int64_t)seg * L;
-    if (lane < L) qk_s[lane] = qks[lane];
-    __builtin_amdgcn_wave_barrier();
-    for (int l = 0; l < L; ++l) {
-      const uint64_t key = qk_s[l];
-      const int64_t tb = (int64_t)ix.tab_seg_off[seg] + (int64_t)l * cap;
-      // lane-parallel linear probe: first slot holding the key or empty
-      uint32_t slot = 0;
-      bool found = false;
-      for (uint32_t p0 = 0; p0 < cap; p0 += 64) {
-        const uint32_t sl = ((uint32_t)key + p0 + lane) & mask;
-        const uint64_t v = (p0 + lane < cap) ? ix.tab_key[tb + sl] : kEmpty;
-        const uint64_t hit = __ballot(v == key);
-        const uint64_t emp = __ballot(v == kEmpty);
-        if (hit != 0 || emp != 0) {
-          const int fh = hit ? __ffsll((long long)hit) - 1 : 64;
-          const int fe = emp ? __ffsll((long long)emp) - 1 : 64;
-          if (fh < fe) {
-            found = true;
-            slot = ((uint32_t)key + p0 + fh) & mask;
-          }
+    uint32_t c = 0;
+    int64_t base = 0;
+    if (lane < L) {
+      const uint64_t key = qk[(int64_t)seg * L + lane];
+      ws.qk[lane] = key;
+      const int64_t tb = (int64_t)ix.tab_seg_off[seg] + (int64_t)lane * cap;
+      uint32_t sl = (uint32_t)key & mask;
+      while (true) {
+        const uint64_t v = ix.tab_key[tb + sl];
+        if (v == key) {
+          c = ix.tab_cnt[tb + sl];
+          base = s0 * L + (int64_t)lane * cnt + ix.tab_start[tb + sl];
           break;
         }
+        if (v == kEmpty) break;
+        sl = (sl + 1) & mask;
       }
-      if (!found) continue;
-      const uint32_t start = ix.tab_start[tb + slot], c = ix.tab_cnt[tb + slot];
-      const int32_t* bucket = ix.csr + s0 * L + (int64_t)l * cnt + start;
-      for (uint32_t k0 = 0; k0 < c; k0 += 64) {
-        const uint32_t k = k0 + lane;
-        const bool valid = k < c;
-        double v = 0.0;
-        int32_t j = -1;
-        if (valid) {
-          const int32_t u = bucket[k];
-          const uint64_t* mk = ix.mkeys + (s0 + u) * L;
-          bool seen = false;
-          for (int l2 = 0; l2 < l; ++l2)
-            if (mk[l2] == qk_s[l2]) {
-              seen = true;
-              break;
-            }
-          j = ix.members[s0 + u];
-          if (!seen && j != self_idx) {
-            const float* xrow = ix.X + (int64_t)j * ix.dx;
-            double D = 0.0;
-            if constexpr (DREG > 0) {
+    }
+    uint32_t incl = c;
 #pragma unroll
-              for (int h = 0; h < DREG; ++h) {
-                if (h < d) {
-                  const double dl = qr[h] - (double)xrow[h];
-                  D = __builtin_fma(dl, dl, D);
-                }
-              }
-            } else {
-              for (int h = 0; h < d; ++h) {
-                const double dl = (double)qrow[h] - (double)xrow[h];
-                D = __builtin_fma(dl, dl, D);
-              }
-            }
-            if (D >= Tlo && D < Thi) {
-              const double R = ix.literal ? 1.0 : recovery_dev(sqrt(D) / ri, ix.K, L);
-              v = exp(-ix.a * D) / (pi * R);
-            }
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t y = __shfl_up(incl, o);
+      if (lane >= o) incl += y;
+    }
+    const uint32_t total = __shfl(incl, 63);
+    if (lane < L) {
+      ws.pre[lane] = incl - c;
+      ws.base[lane] = base;
+    }
+    __builtin_amdgcn_wave_barrier();
+    for (uint32_t k0 = 0; k0 < total; k0 += 64) {
+      const uint32_t k = k0 + lane;
+      const bool valid = k < total;
+      double v = 0.0;
+      int32_t j = -1;
+      if (valid) {
+        int lo = 0, hi = L - 1;  // last table whose prefix is <= k
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (ws.pre[mid] <= k) lo = mid;
+          else hi = mid - 1;
+        }
+        const int l = lo;
+        const int32_t u = ix.csr[ws.base[l] + (k - ws.pre[l])];
+        j = ix.members[s0 + u];
+        const uint64_t* mk = ix.mkeys + (s0 + u) * L;
+        bool seen = false;
+        for (int l2 = 0; l2 < l; ++l2)
+          if (mk[l2] == ws.qk[l2]) {
+            seen = true;
+            break;
+          }
+        if (!seen && j != self_idx) {
+          // fused-order squared distance; the query row is wave-uniform
+          // (scalar loads), the data row is read as float4
+          const float4* x4 = reinterpret_cast<const float4*>(ix.X + (int64_t)j * ix.dx);
+          double D = 0.0;
+          const int d4 = d >> 2;
+          for (int h4 = 0; h4 < d4; ++h4) {
+            const float4 xv = x4[h4];
+            double dl = (double)qrow[4 * h4] - (double)xv.x;
+            D = __builtin_fma(dl, dl, D);
+            dl = (double)qrow[4 * h4 + 1] - (double)xv.y;
+            D = __builtin_fma(dl, dl, D);
+            dl = (double)qrow[4 * h4 + 2] - (double)xv.z;
+            D = __builtin_fma(dl, dl, D);
+            dl = (double)qrow[4 * h4 + 3] - (double)xv.w;
+            D = __builtin_fma(dl, dl, D);
+          }
+          const float* xrow = ix.X + (int64_t)j * ix.dx;
+          for (int h = 4 * d4; h < d; ++h) {
+            const double dl = (double)qrow[h] - (double)xrow[h];
+            D = __builtin_fma(dl, dl, D);
+          }
+          if (D >= Tlo && D < Thi) {
+            const double R = ix.literal ? 1.0 : recovery_dev(sqrt(D) / ri, ix.K, L);
+            v = exp(-ix.a * D) / (pi * R);
           }
         }
-        on_batch(v, j, valid);
       }
+      on_batch(v, j, valid);
     }
     __builtin_amdgcn_wave_barrier();
   }
 }
 
 // One wave per (query, copy): the copy's estimate and candidate counts.
-template <int DREG>
 __global__ __launch_bounds__(256) void probe_queries(const float* __restrict__ Q, int ldq, int64_t q0, int64_t mb,
                                                      IndexView ix, LevelConst lc, const uint64_t* __restrict__ qkeys,
                                                      int64_t ntab, int self_excl, double* __restrict__ Scopy,
                                                      int64_t* __restrict__ ncand, int64_t* __restrict__ nacc) {
   const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int64_t pair = (int64_t)blockIdx.x * 4 + wave;
   if (pair >= mb * ix.K1) return;
   const int64_t ql = pair / ix.K1;
   const int t = (int)(pair % ix.K1);
   const float* qrow = Q + (q0 + ql) * ldq;
-  double qr[DREG > 0 ? DREG : 1];
-  load_point<DREG>(qr, qrow, ix.d);
-  __shared__ uint64_t qk_s[4][64];
+  __shared__ WalkScratch wsc[4];
   double acc = 0.0;
   int64_t nc = 0, na = 0;
-  walk_copy<DREG>(ix, lc, t, qkeys + ql * ntab, qk_s[wave], qr, qrow, self_excl ? q0 + ql : -1,
-                  [&](double v, int32_t j, bool valid) {
-                    acc += v;
-                    nc += valid ? 1 : 0;
-                    na += v > 0.0 ? 1 : 0;
-                  });
+  walk_copy(ix, lc, t, qkeys + ql * ntab, wsc[wave], qrow, self_excl ? q0 + ql : -1,
+            [&](double v, int32_t j, bool valid) {
+              acc += v;
+              nc += valid ? 1 : 0;
+              na += v > 0.0 ? 1 : 0;
+            });
   for (int o = 32; o > 0; o >>= 1) {
     acc += __shfl_xor(acc, o);
     nc += __shfl_xor(nc, o);
@@ -472,21 +498,18 @@ __device__ inline double wave_incl_scan_f64(double v) {
 // U(i, r) * sum_t S'_t(i), its copy (cumulative over copies) and remainder;
 // each needed copy is walked once, in batches whose inclusive prefix sums
 // locate every pending remainder.
-template <int DREG>
 __global__ __launch_bounds__(256) void draw_lsh(IndexView ix, LevelConst lc, const uint64_t* __restrict__ qkeys,
                                                 int64_t ntab, int64_t q0, int64_t mb, const double* __restrict__ Scopy,
                                                 const double* __restrict__ rest, int s, uint64_t seed,
                                                 int64_t* __restrict__ src, int64_t* __restrict__ dst,
                                                 double* __restrict__ w) {
   const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int64_t ql = (int64_t)blockIdx.x * 4 + wave;
   if (ql >= mb) return;
   const int64_t qi = q0 + ql;
   const float* qrow = ix.X + qi * ix.dx;
-  double qr[DREG > 0 ? DREG : 1];
-  load_point<DREG>(qr, qrow, ix.d);
-  __shared__ uint64_t qk_s[4][64];
+  __shared__ WalkScratch wsc[4];
   const double* sc = Scopy + ql * ix.K1;
   double tot = 0.0;
   for (int t = 0; t < ix.K1; ++t) tot += sc[t];
@@ -522,7 +545,7 @@ __global__ __launch_bounds__(256) void draw_lsh(IndexView ix, LevelConst lc, con
     if (__ballot(mine && tsel == t) == 0) continue;
     double running = 0.0;
     int32_t lastj = -1;
-    walk_copy<DREG>(ix, lc, t, qkeys + ql * ntab, qk_s[wave], qr, qrow, qi, [&](double v, int32_t j, bool valid) {
+    walk_copy(ix, lc, t, qkeys + ql * ntab, wsc[wave], qrow, qi, [&](double v, int32_t j, bool valid) {
       const double incl = wave_incl_scan_f64(v);
       const double btot = __shfl(incl, 63);
       const uint64_t pos = __ballot(v > 0.0);
@@ -927,11 +950,9 @@ stag_status query_index(const stag_lsh_index* idx, const float* Q, int ldq, int6
     STAG_TRY(hash_query_batch(idx, Q, ldq, q0, cur, qkeys, st));
     {
       ScopedTimer tm("lsh_probe", st);
-      STAG_TRY(dispatch_dreg(idx->dreg, [&](auto D) {
-        hipLaunchKernelGGL(probe_queries<decltype(D)::value>, dim3((unsigned)ceil_div(cur * K1, 4)), dim3(256), 0,
-                           st, Q, ldq, q0, cur, ix, lc, qkeys, idx->ntab, self_excl, scopy, ncand, nacc);
-        return check_launch("probe_queries");
-      }));
+      hipLaunchKernelGGL(probe_queries, dim3((unsigned)ceil_div(cur * K1, 4)), dim3(256), 0, st, Q, ldq, q0, cur, ix,
+                         lc, qkeys, idx->ntab, self_excl, scopy, ncand, nacc);
+      STAG_TRY(check_launch("probe_queries"));
     }
     hipLaunchKernelGGL(mean_copies, dim3((unsigned)ceil_div(cur, 256)), dim3(256), 0, st, scopy, q0, cur, K1, S_out,
                        copies_out);
@@ -964,11 +985,9 @@ stag_status lsh_sample_edges(const stag_lsh_index* idx, int s, uint64_t seed, in
     const int64_t cur = std::min(mb, n - q0);
     STAG_TRY(hash_query_batch(idx, idx->X, idx->dx, q0, cur, qkeys, st));
     ScopedTimer tm("simgraph_draw_lsh", st);
-    STAG_TRY(dispatch_dreg(idx->dreg, [&](auto D) {
-      hipLaunchKernelGGL(draw_lsh<decltype(D)::value>, dim3((unsigned)ceil_div(cur, 4)), dim3(256), 0, st, ix, lc,
-                         qkeys, idx->ntab, q0, cur, copies + q0 * K1, rest, s, seed, src, dst, w);
-      return check_launch("draw_lsh");
-    }));
+    hipLaunchKernelGGL(draw_lsh, dim3((unsigned)ceil_div(cur, 4)), dim3(256), 0, st, ix, lc, qkeys, idx->ntab, q0,
+                       cur, copies + q0 * K1, rest, s, seed, src, dst, w);
+    STAG_TRY(check_launch("draw_lsh"));
   }
   if (deg_out) {
     hipLaunchKernelGGL(one_plus, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, st, rest, n, deg_out);

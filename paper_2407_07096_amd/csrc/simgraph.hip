@@ -10,7 +10,8 @@
 //
 // Exact mode: one self-excluding pass of the exact tile kernel gives the
 // per-chunk (4096 rows) fp64 sums and per-tile (32 rows) fp32 sums of every
-// row of the kernel matrix; a draw walks chunk sums, then tile sums, then
+// row of the kernel matrix (tile sums stored node-major, so one draw reads
+// its chunk's 128 tile sums contiguously); a draw walks chunk sums, then tile sums, then
 // recomputes the 32 kernel values of its tile in fp64 (direct differences)
 // and inverts the cumulative sum at each level, j ascending.
 // LSH mode: the CKNS estimator's terms replace the kernel row (lsh.hip).
@@ -103,7 +104,7 @@ __global__ __launch_bounds__(256) void draw_exact(const float* __restrict__ X, i
       const int64_t t0 = (int64_t)c * kChunkTiles;
       const int nt = (int)((ntile - t0) < kChunkTiles ? (ntile - t0) : kChunkTiles);
       double resid2 = 0.0;
-      const int tl = invert_level(nt, resid, [&](int k) { return (double)tp[(t0 + k) * m_pad + i]; }, &resid2);
+      const int tl = invert_level(nt, resid, [&](int k) { return (double)tp[i * ntile + t0 + k]; }, &resid2);
       if (tl >= 0) {
         const int64_t rb = (t0 + tl) * 32;
         const int64_t j = rb + lane;
@@ -148,7 +149,7 @@ stag_status sample_exact(const float* X, int64_t n, int d, double a, int form, i
   TileExtra ex;
   ex.self = 1;
   ex.tp = tp;
-  ex.m_pad = qo.rows_pad;
+  ex.ntile = ntile;
   STAG_TRY(launch_exact_tiles(xo, qo, partial, ex, st));
   hipLaunchKernelGGL(row_rest, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, st, partial, P, qo.rows_pad, n, rest,
                      deg_out);
