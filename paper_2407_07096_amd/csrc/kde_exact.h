@@ -39,7 +39,8 @@ __host__ __device__ inline double relative_bound(const BoundModel& bm, double qn
 
 // Optional epilogue outputs of the tiles (edge sampling): drop the diagonal
 // when a data set is queried against itself, and write per-32-row-tile
-// partial sums tp[query][tile] (fp32, ntile = padded data rows / 32).
+// partial sums tp[query * ntile + tile] (fp32; ntile, the row stride, is at
+// least padded data rows / 32 and a multiple of 8).
 struct TileExtra {
   int self = 0;
   float* tp = nullptr;

@@ -68,13 +68,23 @@ __device__ inline float exp2_tile_sum(const float* c) {
   return k[0];
 }
 
+// A lane's tile sums of 8 consecutive data tiles (global tile indices
+// 8g .. 8g+7), written to tp as two 16-byte stores once the group is complete
+// (or the chunk ends): the row stride of tp is a multiple of 8 tiles.
+struct TileSums8 {
+  float v[8];
+};
+
 // Epilogue of one finished 32x32 tile held by a lane (column qi, half h):
 // exp2 and fp32 tree sum; with EXTRA, optionally drops the diagonal element
 // (data row == query index, for a data set queried against itself) and
-// writes the tile's 32-row partial sum (both halves, fixed order).
+// records the tile's 32-row partial sum (both halves, fixed order), through
+// the group buffer `grp` when the caller walks tiles in order (`last` marks
+// the chunk's final tile), else with a direct store.
 template <bool EXTRA>
 __device__ inline float tile_epilogue(const f32x16& c, int64_t row_base, int64_t col_base, int r32, int h,
-                                      int64_t qi, const TileExtra& ex) {
+                                      int64_t qi, const TileExtra& ex, TileSums8* grp = nullptr,
+                                      bool last = false) {
   float cp[16];
 #pragma unroll
   for (int i = 0; i < 16; ++i) cp[i] = c[i];
@@ -92,7 +102,19 @@ __device__ inline float tile_epilogue(const f32x16& c, int64_t row_base, int64_t
     if (ex.tp) {
       const float o = __shfl_xor(s, 32);
       const float tot = h == 0 ? s + o : o + s;
-      if (h == 0) ex.tp[qi * ex.ntile + row_base / kTileRows] = tot;
+      const int64_t tile = row_base / kTileRows;
+      if (grp == nullptr) {
+        if (h == 0) ex.tp[qi * ex.ntile + tile] = tot;
+      } else {
+        const int k = (int)(tile & 7);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) grp->v[e] = e == k ? tot : grp->v[e];
+        if ((k == 7 || last) && h == 0) {
+          f32x4* dst = reinterpret_cast<f32x4*>(ex.tp + qi * ex.ntile + (tile & ~(int64_t)7));
+          dst[0] = f32x4{grp->v[0], grp->v[1], grp->v[2], grp->v[3]};
+          dst[1] = f32x4{grp->v[4], grp->v[5], grp->v[6], grp->v[7]};
+        }
+      }
     }
   }
   return s;
@@ -258,11 +280,13 @@ __global__ __launch_bounds__(256, 2) void tile_f32(const float* __restrict__ Xp,
   };
 
   double acc = 0.0;
+  TileSums8 grp = {};
   auto step = [&](int t, const f32x16& cdone, f32x16& cnew) {
     const int buf = t & 1;
     __syncthreads();
     if constexpr (EXTRA) {
-      if (t > 0) acc += (double)tile_epilogue<true>(cdone, row0 + (int64_t)(t - 1) * kTileRows, col_base, r32, h, qi, ex);
+      if (t > 0)
+        acc += (double)tile_epilogue<true>(cdone, row0 + (int64_t)(t - 1) * kTileRows, col_base, r32, h, qi, ex, &grp);
     } else {
       acc += (double)tile_epilogue<false>(cdone, 0, 0, r32, h, qi, ex);
     }
@@ -303,7 +327,8 @@ __global__ __launch_bounds__(256, 2) void tile_f32(const float* __restrict__ Xp,
     step(t, ca, cb);
     ca = cb;
   }
-  acc += (double)tile_epilogue<EXTRA>(ca, row0 + (int64_t)(ntiles - 1) * kTileRows, col_base, r32, h, qi, ex);
+  acc += (double)tile_epilogue<EXTRA>(ca, row0 + (int64_t)(ntiles - 1) * kTileRows, col_base, r32, h, qi, ex, &grp,
+                                     true);
   const double other = __shfl_down(acc, 32);
   if (h == 0) partial[(int64_t)chunk * m_pad + qi] = acc + other;
 }
@@ -388,11 +413,13 @@ __global__ __launch_bounds__(256, 2) void tile_split(
   };
 
   double acc = 0.0;
+  TileSums8 grp = {};
   auto step = [&](int t, const f32x16& cdone, f32x16& cnew) {
     const int buf = t & 1;
     __syncthreads();
     if constexpr (EXTRA) {
-      if (t > 0) acc += (double)tile_epilogue<true>(cdone, row0 + (int64_t)(t - 1) * kTileRows, col_base, r32, h, qi, ex);
+      if (t > 0)
+        acc += (double)tile_epilogue<true>(cdone, row0 + (int64_t)(t - 1) * kTileRows, col_base, r32, h, qi, ex, &grp);
     } else {
       acc += (double)tile_epilogue<false>(cdone, 0, 0, r32, h, qi, ex);
     }
@@ -439,7 +466,8 @@ __global__ __launch_bounds__(256, 2) void tile_split(
     step(t, ca, cb);
     ca = cb;
   }
-  acc += (double)tile_epilogue<EXTRA>(ca, row0 + (int64_t)(ntiles - 1) * kTileRows, col_base, r32, h, qi, ex);
+  acc += (double)tile_epilogue<EXTRA>(ca, row0 + (int64_t)(ntiles - 1) * kTileRows, col_base, r32, h, qi, ex, &grp,
+                                     true);
   const double other = __shfl_down(acc, 32);
   if (h == 0) partial[(int64_t)chunk * m_pad + qi] = acc + other;
 }

@@ -304,10 +304,23 @@ __device__ inline double collision_p_dev(double c) {
   return erf(2.0 * sqrt(2.0) / c) - 0.5 * inv_sqrt_2pi * c * (-expm1(-8.0 / (c * c)));
 }
 
+// x^k for an integer k >= 0 by binary powering.
+__device__ inline double ipow_dev(double x, int k) {
+  double r = 1.0;
+  while (k > 0) {
+    if (k & 1) r *= x;
+    x *= x;
+    k >>= 1;
+  }
+  return r;
+}
+
+// Recovery probability 1 - (1 - p(c)^K)^L (integer powers; equal to the
+// expm1/log1p form up to rounding).
 __device__ inline double recovery_dev(double c, int K, int L) {
-  const double x = pow(collision_p_dev(c), (double)K);
+  const double x = ipow_dev(collision_p_dev(c), K);
   if (x >= 1.0) return 1.0;
-  return -expm1((double)L * log1p(-x));
+  return 1.0 - ipow_dev(1.0 - x, L);
 }
 
 struct LevelConst {
@@ -344,19 +357,78 @@ struct WalkScratch {
   uint64_t qk[64];     // the query's keys of the current level, per table
   int64_t base[64];    // csr index of the query's bucket in each table
   uint32_t pre[64];    // exclusive prefix of the bucket sizes over tables
+  int32_t ring[128];   // survivors of the fp32 screen, in candidate order
 };
+
+// Relative error bound of the fp32 squared distance of d coordinates (one
+// rounding per difference, square and accumulation: gamma_{d+2} of unit
+// roundoff 2^-24, doubled for margin).
+__device__ inline double screen_delta(int d) { return 2.0 * (double)(d + 3) * 0x1.0p-24; }
+
+// fp64 squared distance in the order the level test uses (fused, ascending
+// coordinates); the query row is wave-uniform (scalar loads).
+__device__ inline double dist2_f64(const float* __restrict__ qrow, const float* __restrict__ xrow, int d) {
+  const float4* x4 = reinterpret_cast<const float4*>(xrow);
+  double D = 0.0;
+  const int d4 = d >> 2;
+  for (int h4 = 0; h4 < d4; ++h4) {
+    const float4 xv = x4[h4];
+    double dl = (double)qrow[4 * h4] - (double)xv.x;
+    D = __builtin_fma(dl, dl, D);
+    dl = (double)qrow[4 * h4 + 1] - (double)xv.y;
+    D = __builtin_fma(dl, dl, D);
+    dl = (double)qrow[4 * h4 + 2] - (double)xv.z;
+    D = __builtin_fma(dl, dl, D);
+    dl = (double)qrow[4 * h4 + 3] - (double)xv.w;
+    D = __builtin_fma(dl, dl, D);
+  }
+  for (int h = 4 * d4; h < d; ++h) {
+    const double dl = (double)qrow[h] - (double)xrow[h];
+    D = __builtin_fma(dl, dl, D);
+  }
+  return D;
+}
+
+__device__ inline float dist2_f32(const float* __restrict__ qrow, const float* __restrict__ xrow, int d) {
+  const float4* x4 = reinterpret_cast<const float4*>(xrow);
+  float D0 = 0.0f, D1 = 0.0f;
+  const int d4 = d >> 2;
+  for (int h4 = 0; h4 < d4; ++h4) {
+    const float4 xv = x4[h4];
+    float dl = qrow[4 * h4] - xv.x;
+    D0 = __builtin_fmaf(dl, dl, D0);
+    dl = qrow[4 * h4 + 1] - xv.y;
+    D1 = __builtin_fmaf(dl, dl, D1);
+    dl = qrow[4 * h4 + 2] - xv.z;
+    D0 = __builtin_fmaf(dl, dl, D0);
+    dl = qrow[4 * h4 + 3] - xv.w;
+    D1 = __builtin_fmaf(dl, dl, D1);
+  }
+  for (int h = 4 * d4; h < d; ++h) {
+    const float dl = qrow[h] - xrow[h];
+    D0 = __builtin_fmaf(dl, dl, D0);
+  }
+  return D0 + D1;
+}
 
 // Walks copy t of the estimator for one query (one wave).  Per level, lane l
 // resolves the query's bucket in table l; the buckets' members are then
 // taken as one flattened list (table, member ascending) in batches of 64, one
-// candidate per lane.  For every batch, on_batch(v, j, valid) receives each
-// lane's term v (0 if the member was seen in an earlier table, lies outside
-// the level, or is the query's own point when self_idx >= 0) and its point j.
+// candidate per lane.  A candidate is dropped if it was seen in an earlier
+// table of the level or is the query's own point (self_idx >= 0); the rest
+// pass an fp32 distance screen that removes only points certainly outside
+// the level (bound screen_delta), and the survivors queue up in candidate
+// order.  Every 64 queued points (and at the end of a level) form a batch in
+// which each lane decides the level in fp64 and computes its term:
+// on_batch(v, j, valid) receives it (0 outside the level) and the point j.
+// Returns the number of candidates walked.
 template <class F>
-__device__ inline void walk_copy(const IndexView& ix, const LevelConst& lc, int t, const uint64_t* __restrict__ qk,
-                                 WalkScratch& ws, const float* __restrict__ qrow, int64_t self_idx, F&& on_batch) {
+__device__ inline int64_t walk_copy(const IndexView& ix, const LevelConst& lc, int t, const uint64_t* __restrict__ qk,
+                                    WalkScratch& ws, const float* __restrict__ qrow, int64_t self_idx, F&& on_batch) {
   const int lane = threadIdx.x & 63;
   const int L = ix.L, d = ix.d;
+  const double delta = screen_delta(d);
+  int64_t walked = 0;
   for (int i = 1; i <= ix.J; ++i) {
     const int seg = t * ix.J + (i - 1);
     const int64_t s0 = (int64_t)ix.seg_off[seg];
@@ -364,6 +436,7 @@ __device__ inline void walk_copy(const IndexView& ix, const LevelConst& lc, int 
     if (cnt == 0) continue;
     const uint32_t cap = ix.seg_cap[seg], mask = cap - 1;
     const double Tlo = lc.T[i - 1], Thi = lc.T[i], pi = lc.p[i], ri = lc.r[i];
+    const double lo_s = Tlo * (1.0 - delta), hi_s = Thi * (1.0 + delta);
     uint32_t c = 0;
     int64_t base = 0;
     if (lane < L) {
@@ -389,17 +462,33 @@ __device__ inline void walk_copy(const IndexView& ix, const LevelConst& lc, int 
       if (lane >= o) incl += y;
     }
     const uint32_t total = __shfl(incl, 63);
+    walked += total;
     if (lane < L) {
       ws.pre[lane] = incl - c;
       ws.base[lane] = base;
     }
     __builtin_amdgcn_wave_barrier();
-    for (uint32_t k0 = 0; k0 < total; k0 += 64) {
-      const uint32_t k = k0 + lane;
-      const bool valid = k < total;
+    // exact decision and term of the queued points [head, head + count)
+    auto drain = [&](uint32_t head, uint32_t count) {
+      const bool valid = (uint32_t)lane < count;
       double v = 0.0;
       int32_t j = -1;
       if (valid) {
+        j = ws.ring[(head + lane) & 127];
+        const double D = dist2_f64(qrow, ix.X + (int64_t)j * ix.dx, d);
+        if (D >= Tlo && D < Thi) {
+          const double R = ix.literal ? 1.0 : recovery_dev(sqrt(D) / ri, ix.K, L);
+          v = exp(-ix.a * D) / (pi * R);
+        }
+      }
+      on_batch(v, j, valid);
+    };
+    uint32_t head = 0, tail = 0;
+    for (uint32_t k0 = 0; k0 < total; k0 += 64) {
+      const uint32_t k = k0 + lane;
+      bool keep = false;
+      int32_t j = -1;
+      if (k < total) {
         int lo = 0, hi = L - 1;  // last table whose prefix is <= k
         while (lo < hi) {
           const int mid = (lo + hi + 1) >> 1;
@@ -411,43 +500,28 @@ __device__ inline void walk_copy(const IndexView& ix, const LevelConst& lc, int 
         j = ix.members[s0 + u];
         const uint64_t* mk = ix.mkeys + (s0 + u) * L;
         bool seen = false;
-        for (int l2 = 0; l2 < l; ++l2)
-          if (mk[l2] == ws.qk[l2]) {
-            seen = true;
-            break;
-          }
+#pragma unroll 4
+        for (int l2 = 0; l2 < l; ++l2) seen |= mk[l2] == ws.qk[l2];
         if (!seen && j != self_idx) {
-          // fused-order squared distance; the query row is wave-uniform
-          // (scalar loads), the data row is read as float4
-          const float4* x4 = reinterpret_cast<const float4*>(ix.X + (int64_t)j * ix.dx);
-          double D = 0.0;
-          const int d4 = d >> 2;
-          for (int h4 = 0; h4 < d4; ++h4) {
-            const float4 xv = x4[h4];
-            double dl = (double)qrow[4 * h4] - (double)xv.x;
-            D = __builtin_fma(dl, dl, D);
-            dl = (double)qrow[4 * h4 + 1] - (double)xv.y;
-            D = __builtin_fma(dl, dl, D);
-            dl = (double)qrow[4 * h4 + 2] - (double)xv.z;
-            D = __builtin_fma(dl, dl, D);
-            dl = (double)qrow[4 * h4 + 3] - (double)xv.w;
-            D = __builtin_fma(dl, dl, D);
-          }
-          const float* xrow = ix.X + (int64_t)j * ix.dx;
-          for (int h = 4 * d4; h < d; ++h) {
-            const double dl = (double)qrow[h] - (double)xrow[h];
-            D = __builtin_fma(dl, dl, D);
-          }
-          if (D >= Tlo && D < Thi) {
-            const double R = ix.literal ? 1.0 : recovery_dev(sqrt(D) / ri, ix.K, L);
-            v = exp(-ix.a * D) / (pi * R);
-          }
+          const double D32 = (double)dist2_f32(qrow, ix.X + (int64_t)j * ix.dx, d);
+          keep = D32 >= lo_s && D32 < hi_s;
         }
       }
-      on_batch(v, j, valid);
+      const uint64_t km = __ballot(keep);
+      const uint32_t pos = __builtin_amdgcn_mbcnt_hi((uint32_t)(km >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)km, 0u));
+      if (keep) ws.ring[(tail + pos) & 127] = j;
+      tail += (uint32_t)__popcll(km);
+      __builtin_amdgcn_wave_barrier();
+      if (tail - head >= 64) {
+        drain(head, 64);
+        head += 64;
+        __builtin_amdgcn_wave_barrier();
+      }
     }
+    if (tail > head) drain(head, tail - head);
     __builtin_amdgcn_wave_barrier();
   }
+  return walked;
 }
 
 // One wave per (query, copy): the copy's estimate and candidate counts.
@@ -465,15 +539,13 @@ __global__ __launch_bounds__(256) void probe_queries(const float* __restrict__ Q
   __shared__ WalkScratch wsc[4];
   double acc = 0.0;
   int64_t nc = 0, na = 0;
-  walk_copy(ix, lc, t, qkeys + ql * ntab, wsc[wave], qrow, self_excl ? q0 + ql : -1,
-            [&](double v, int32_t j, bool valid) {
-              acc += v;
-              nc += valid ? 1 : 0;
-              na += v > 0.0 ? 1 : 0;
-            });
+  nc = walk_copy(ix, lc, t, qkeys + ql * ntab, wsc[wave], qrow, self_excl ? q0 + ql : -1,
+                 [&](double v, int32_t j, bool valid) {
+                   acc += v;
+                   na += v > 0.0 ? 1 : 0;
+                 });
   for (int o = 32; o > 0; o >>= 1) {
     acc += __shfl_xor(acc, o);
-    nc += __shfl_xor(nc, o);
     na += __shfl_xor(na, o);
   }
   if (lane == 0) {
@@ -593,6 +665,247 @@ __global__ void one_plus(const double* __restrict__ v, int64_t n, double* __rest
 __global__ void zero_i64(int64_t* p, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = 0;
+}
+
+// ---------------------------------------------------------------------------
+// Bucket join (query batches with d <= 128 and L <= 32).  The batch's queries
+// are grouped by the bucket they fall in, per table; a wave then takes up to
+// 64 queries of one bucket (one per lane, row in registers) against up to
+// kJoinMembers members of that bucket, which it stages through LDS
+// kJoinChunk rows at a time, so that every member row is read once per 64
+// queries instead of once per query.  Per pair: first-table dedupe, self
+// exclusion and the fp32 distance screen; the survivors of a staged chunk are
+// then settled per lane in member order (fp64 distance, level test, term).
+// A lane's partial over its member range goes to tpart; combine_groups adds
+// the ranges of a bucket in order and the tables of a copy in order, so a
+// query's estimate does not depend on the other queries of its batch.
+// ---------------------------------------------------------------------------
+constexpr int kJoinMembers = 512;
+constexpr int kJoinChunk = 32;
+
+// Bytes of dynamic LDS of one join wave (layout: rows, point ids, member
+// keys, query keys).
+__host__ __device__ inline int join_lds_rows(int dq) { return kJoinChunk * (dq + 4) * 4; }
+__host__ __device__ inline int join_lds_bytes(int dq, int L) {
+  const int lm1 = L > 1 ? L - 1 : 1;
+  return join_lds_rows(dq) + kJoinChunk * 4 + kJoinChunk * lm1 * 8 + lm1 * 64 * 8;
+}
+
+// The bucket (global slot) of every (query, table) pair of the batch, or -1,
+// and the pair's rank among the bucket's queries (arrival order).
+__global__ __launch_bounds__(256) void locate_queries(const uint64_t* __restrict__ qkeys, int64_t total, int64_t ntab,
+                                                      int L, const uint64_t* __restrict__ tab_seg_off,
+                                                      const uint32_t* __restrict__ seg_cap,
+                                                      const uint64_t* __restrict__ tab_key, int32_t* __restrict__ qslot,
+                                                      uint32_t* __restrict__ qrank, uint32_t* __restrict__ qcount) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t g = e % ntab;
+    const int64_t seg = g / L;
+    const int l = (int)(g % L);
+    const uint32_t cap = seg_cap[seg];
+    int32_t slot = -1;
+    if (cap > 0) {
+      const uint64_t key = qkeys[e];
+      const int64_t tb = (int64_t)tab_seg_off[seg] + (int64_t)l * cap;
+      uint32_t sl = (uint32_t)key & (cap - 1);
+      while (true) {
+        const uint64_t v = tab_key[tb + sl];
+        if (v == key) {
+          slot = (int32_t)(tb + sl);
+          break;
+        }
+        if (v == kEmpty) break;
+        sl = (sl + 1) & (cap - 1);
+      }
+    }
+    qslot[e] = slot;
+    if (slot >= 0) qrank[e] = atomicAdd(qcount + slot, 1u);
+  }
+}
+
+__global__ __launch_bounds__(256) void scatter_queries(const int32_t* __restrict__ qslot,
+                                                       const uint32_t* __restrict__ qrank, int64_t total, int64_t ntab,
+                                                       const uint64_t* __restrict__ qstart, int32_t* __restrict__ qlist) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t slot = qslot[e];
+    if (slot >= 0) qlist[qstart[slot] + qrank[e]] = (int32_t)(e / ntab);
+  }
+}
+
+// Tasks of a bucket: ceil(queries / 64) x ceil(members / kJoinMembers).
+__global__ __launch_bounds__(256) void count_tasks(const uint32_t* __restrict__ qcount,
+                                                   const uint32_t* __restrict__ tab_cnt, int64_t nslots,
+                                                   uint32_t* __restrict__ ntask) {
+  const int64_t sl = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (sl >= nslots) return;
+  const uint32_t nq = qcount[sl], nm = tab_cnt[sl];
+  ntask[sl] = (nq > 0 && nm > 0) ? ((nq + 63) / 64) * ((nm + kJoinMembers - 1) / kJoinMembers) : 0u;
+}
+
+// Largest index s in [0, n) with v[s] <= x (v ascending, v[0] <= x).
+__device__ inline int64_t last_le(const uint64_t* __restrict__ v, int64_t n, uint64_t x) {
+  int64_t lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi + 1) >> 1;
+    if (v[mid] <= x) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+template <int DQ>
+__global__ __launch_bounds__(64) void join_buckets(IndexView ix, LevelConst lc, const float* __restrict__ Q, int ldq,
+                                                   int64_t q0, const uint64_t* __restrict__ qkeys, int64_t ntab,
+                                                   const uint32_t* __restrict__ qcount,
+                                                   const uint64_t* __restrict__ qstart,
+                                                   const int32_t* __restrict__ qlist,
+                                                   const uint64_t* __restrict__ task_base, int64_t nslots, int nseg,
+                                                   int self_excl, double* __restrict__ tpart,
+                                                   int64_t* __restrict__ nacc) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char jlds[];
+  constexpr int RS = DQ + 4;  // LDS row stride (floats)
+  const int lane = threadIdx.x;
+  const int L = ix.L, d = ix.d, dx = ix.dx;
+  const int lm1 = L > 1 ? L - 1 : 1;
+  float* rows = reinterpret_cast<float*>(jlds);
+  int32_t* jl = reinterpret_cast<int32_t*>(jlds + join_lds_rows(DQ));
+  uint64_t* mk = reinterpret_cast<uint64_t*>(jlds + join_lds_rows(DQ) + kJoinChunk * 4);
+  uint64_t* qk = mk + kJoinChunk * lm1;
+
+  const int64_t task = blockIdx.x;
+  const int64_t slot = last_le(task_base, nslots + 1, (uint64_t)task);
+  const int seg = (int)last_le(ix.tab_seg_off, (int64_t)nseg + 1, (uint64_t)slot);
+  const uint32_t cap = ix.seg_cap[seg];
+  const int l = (int)((slot - (int64_t)ix.tab_seg_off[seg]) / cap);
+  const int i = seg % ix.J + 1;
+  const int64_t s0 = (int64_t)ix.seg_off[seg];
+  const int64_t cnt = (int64_t)ix.seg_off[seg + 1] - s0;
+  const uint32_t nq = qcount[slot], nm = ix.tab_cnt[slot];
+  const int nmc = (int)((nm + kJoinMembers - 1) / kJoinMembers);
+  const int64_t r = task - (int64_t)task_base[slot];
+  const int qc = (int)(r / nmc), mc = (int)(r % nmc);
+  const int64_t mbase = s0 * L + (int64_t)l * cnt + ix.tab_start[slot];
+  const double Tlo = lc.T[i - 1], Thi = lc.T[i], pi = lc.p[i], ri = lc.r[i];
+  const double delta = screen_delta(d);
+  const double lo_s = Tlo * (1.0 - delta), hi_s = Thi * (1.0 + delta);
+
+  const uint32_t qp = (uint32_t)qc * 64u + (uint32_t)lane;
+  const bool qvalid = qp < nq;
+  const int32_t ql = qlist[qstart[slot] + (qvalid ? qp : 0u)];
+  const int64_t self_idx = self_excl ? q0 + ql : -1;
+  float q[DQ];
+  {
+    const float* qrow = Q + (q0 + ql) * (int64_t)ldq;
+#pragma unroll
+    for (int h = 0; h < DQ; ++h) q[h] = h < d ? qrow[h] : 0.0f;
+  }
+  for (int l2 = 0; l2 < l; ++l2) qk[l2 * 64 + lane] = qkeys[(int64_t)ql * ntab + (int64_t)seg * L + l2];
+  if (dx < DQ)
+    for (int e = lane; e < kJoinChunk * RS; e += 64) rows[e] = 0.0f;
+
+  double acc = 0.0;
+  int64_t na = 0;
+  const int dx4 = dx >> 2;
+  const int kbeg = mc * kJoinMembers;
+  const int kend = (int)min((uint32_t)(kbeg + kJoinMembers), nm);
+  for (int k0 = kbeg; k0 < kend; k0 += kJoinChunk) {
+    const int nk = min(kJoinChunk, kend - k0);
+    __builtin_amdgcn_wave_barrier();
+    if (lane < nk) {
+      const int32_t u = ix.csr[mbase + k0 + lane];
+      jl[lane] = ix.members[s0 + u];
+      const uint64_t* mrow = ix.mkeys + (s0 + u) * L;
+      for (int l2 = 0; l2 < l; ++l2) mk[lane * lm1 + l2] = mrow[l2];
+    }
+    __builtin_amdgcn_wave_barrier();
+    for (int e = lane; e < nk * dx4; e += 64) {
+      const int rr = e / dx4, c4 = e - rr * dx4;
+      const float4 v = reinterpret_cast<const float4*>(ix.X + (int64_t)jl[rr] * dx)[c4];
+      *reinterpret_cast<float4*>(&rows[rr * RS + 4 * c4]) = v;
+    }
+    __builtin_amdgcn_wave_barrier();
+    uint32_t mask = 0;
+    for (int m = 0; m < nk; ++m) {
+      const float* xr = &rows[m * RS];
+      float D0 = 0.0f, D1 = 0.0f;
+#pragma unroll
+      for (int h4 = 0; h4 < DQ / 4; ++h4) {
+        const float4 xv = *reinterpret_cast<const float4*>(xr + 4 * h4);
+        float t0 = q[4 * h4] - xv.x;
+        D0 = __builtin_fmaf(t0, t0, D0);
+        t0 = q[4 * h4 + 1] - xv.y;
+        D1 = __builtin_fmaf(t0, t0, D1);
+        t0 = q[4 * h4 + 2] - xv.z;
+        D0 = __builtin_fmaf(t0, t0, D0);
+        t0 = q[4 * h4 + 3] - xv.w;
+        D1 = __builtin_fmaf(t0, t0, D1);
+      }
+      const double D32 = (double)(D0 + D1);
+      bool seen = false;
+      for (int l2 = 0; l2 < l; ++l2) seen |= mk[m * lm1 + l2] == qk[l2 * 64 + lane];
+      const bool keep = qvalid && !seen && (int64_t)jl[m] != self_idx && D32 >= lo_s && D32 < hi_s;
+      mask |= keep ? (1u << m) : 0u;
+    }
+    // survivors, per lane in member order
+    while (__ballot(mask != 0u)) {
+      if (mask) {
+        const int m = __builtin_ctz(mask);
+        mask &= mask - 1u;
+        const float* xr = &rows[m * RS];
+        double D = 0.0;
+#pragma unroll
+        for (int h = 0; h < DQ; ++h) {
+          float qh = q[h];
+          asm volatile("" : "+v"(qh));  // keeps the widening here (no hoisted fp64 copy of the row)
+          const double t0 = (double)qh - (double)xr[h];
+          D = __builtin_fma(t0, t0, D);
+        }
+        if (D >= Tlo && D < Thi) {
+          const double R = ix.literal ? 1.0 : recovery_dev(sqrt(D) / ri, ix.K, L);
+          acc += exp(-ix.a * D) / (pi * R);
+          ++na;
+        }
+      }
+    }
+  }
+  tpart[task * 64 + lane] = acc;
+  if (qvalid && na > 0 && nacc) atomicAdd(reinterpret_cast<unsigned long long*>(nacc + q0 + ql), (unsigned long long)na);
+}
+
+// Per query: the copy sums from the lane partials (bucket ranges in order,
+// then the tables and levels of a copy in order) and the candidate count.
+__global__ __launch_bounds__(256) void combine_groups(const int32_t* __restrict__ qslot,
+                                                      const uint32_t* __restrict__ qrank, int64_t mb, int64_t ntab,
+                                                      int K1, const uint32_t* __restrict__ tab_cnt,
+                                                      const uint64_t* __restrict__ task_base,
+                                                      const double* __restrict__ tpart, int64_t q0,
+                                                      double* __restrict__ Scopy, int64_t* __restrict__ ncand) {
+  const int64_t ql = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (ql >= mb) return;
+  const int64_t per_copy = ntab / K1;
+  int64_t nc = 0;
+  for (int t = 0; t < K1; ++t) {
+    double acc = 0.0;
+    for (int64_t g = (int64_t)t * per_copy; g < (int64_t)(t + 1) * per_copy; ++g) {
+      const int64_t e = ql * ntab + g;
+      const int32_t slot = qslot[e];
+      if (slot < 0) continue;
+      const uint32_t rank = qrank[e], nm = tab_cnt[slot];
+      const int64_t nmc = (nm + kJoinMembers - 1) / kJoinMembers;
+      const int64_t base = (int64_t)task_base[slot] + (int64_t)(rank / 64) * nmc;
+      const int lane = (int)(rank % 64);
+      double gs = 0.0;
+      for (int64_t c = 0; c < nmc; ++c) gs += tpart[(base + c) * 64 + lane];
+      acc += gs;
+      nc += nm;
+    }
+    Scopy[ql * K1 + t] = acc;
+  }
+  if (ncand) ncand[q0 + ql] += nc;
+}
+
+__global__ void zero_u32(uint32_t* p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = 0;
 }
 
 int ceil_log2_i64(int64_t n) {
@@ -929,6 +1242,81 @@ stag_status hash_query_batch(const stag_lsh_index* idx, const float* Q, int ldq,
   });
 }
 
+bool join_applies(const stag_lsh_index* idx) {
+  return idx->d <= 128 && idx->prm.shape.L <= 32 && idx->total_slots > 0 && idx->total_slots < INT32_MAX;
+}
+
+// Copy sums of one hashed query batch through the bucket join.
+stag_status join_batch(const stag_lsh_index* idx, const float* Q, int ldq, int64_t q0, int64_t cur, int self_excl,
+                       const uint64_t* qkeys, double* scopy, int64_t* ncand, int64_t* nacc, hipStream_t st) {
+  const LshParams& prm = idx->prm;
+  const int L = prm.shape.L, K1 = prm.shape.K1;
+  const int64_t ntab = idx->ntab, nslots = idx->total_slots, pairs = cur * ntab;
+  Workspace ws(st);
+  int32_t* qslot = nullptr;
+  uint32_t* qrank = nullptr;
+  uint32_t* qcount = nullptr;
+  uint64_t* qstart = nullptr;
+  int32_t* qlist = nullptr;
+  uint32_t* ntask = nullptr;
+  uint64_t* task_base = nullptr;
+  STAG_TRY(ws.alloc(&qslot, (size_t)pairs));
+  STAG_TRY(ws.alloc(&qrank, (size_t)pairs));
+  STAG_TRY(ws.alloc(&qcount, (size_t)nslots));
+  STAG_TRY(ws.alloc(&qstart, (size_t)nslots + 1));
+  STAG_TRY(ws.alloc(&qlist, (size_t)pairs));
+  STAG_TRY(ws.alloc(&ntask, (size_t)nslots));
+  STAG_TRY(ws.alloc(&task_base, (size_t)nslots + 1));
+  const unsigned gpairs = (unsigned)std::min<int64_t>(ceil_div(pairs, 256), 65536);
+  uint64_t ntasks = 0;
+  {
+    ScopedTimer tm("lsh_join_setup", st);
+    hipLaunchKernelGGL(zero_u32, dim3((unsigned)std::min<int64_t>(ceil_div(nslots, 256), 65536)), dim3(256), 0, st,
+                       qcount, nslots);
+    hipLaunchKernelGGL(locate_queries, dim3(gpairs), dim3(256), 0, st, qkeys, pairs, ntab, L, idx->tab_seg_off,
+                       idx->seg_cap, idx->tab_key, qslot, qrank, qcount);
+    STAG_TRY(check_launch("locate_queries"));
+    STAG_TRY(exclusive_scan_u32(qcount, qstart, nslots, ws, st));
+    hipLaunchKernelGGL(scatter_queries, dim3(gpairs), dim3(256), 0, st, qslot, qrank, pairs, ntab, qstart, qlist);
+    STAG_TRY(check_launch("scatter_queries"));
+    hipLaunchKernelGGL(count_tasks, dim3((unsigned)ceil_div(nslots, 256)), dim3(256), 0, st, qcount, idx->tab_cnt,
+                       nslots, ntask);
+    STAG_TRY(check_launch("count_tasks"));
+    STAG_TRY(exclusive_scan_u32(ntask, task_base, nslots, ws, st));
+    STAG_HIP(hipMemcpyAsync(&ntasks, task_base + nslots, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
+    STAG_HIP(hipStreamSynchronize(st));
+  }
+  if (ntasks > (uint64_t)INT32_MAX) return fail(STAG_E_UNSUPPORTED, "lsh: %llu join tasks in one batch",
+                                                (unsigned long long)ntasks);
+  double* tpart = nullptr;
+  STAG_TRY(ws.alloc(&tpart, (size_t)std::max<uint64_t>(ntasks, 1) * 64));
+  const IndexView ix = make_view(idx);
+  const LevelConst lc = make_levels(prm);
+  if (ntasks > 0) {
+    ScopedTimer tm("lsh_join", st);
+    const int dq = idx->d <= 16 ? 16 : idx->d <= 32 ? 32 : idx->d <= 64 ? 64 : 128;
+    const size_t lds = (size_t)join_lds_bytes(dq, L);
+    auto launch = [&](auto kern) {
+      hipLaunchKernelGGL(kern, dim3((unsigned)ntasks), dim3(64), lds, st, ix, lc, Q, ldq, q0, qkeys, ntab, qcount,
+                         qstart, qlist, task_base, nslots, (int)idx->nseg, self_excl, tpart, nacc);
+    };
+    switch (dq) {
+      case 16: launch(join_buckets<16>); break;
+      case 32: launch(join_buckets<32>); break;
+      case 64: launch(join_buckets<64>); break;
+      default: launch(join_buckets<128>); break;
+    }
+    STAG_TRY(check_launch("join_buckets"));
+  }
+  {
+    ScopedTimer tm("lsh_combine", st);
+    hipLaunchKernelGGL(combine_groups, dim3((unsigned)ceil_div(cur, 256)), dim3(256), 0, st, qslot, qrank, cur, ntab,
+                       K1, idx->tab_cnt, task_base, tpart, q0, scopy, ncand);
+    STAG_TRY(check_launch("combine_groups"));
+  }
+  return STAG_OK;
+}
+
 // Estimates for rows of Q (self_excl: Q is the index's own data and each
 // row's own point is left out).  Optional per-copy values and counts.
 stag_status query_index(const stag_lsh_index* idx, const float* Q, int ldq, int64_t m, int self_excl,
@@ -948,7 +1336,9 @@ stag_status query_index(const stag_lsh_index* idx, const float* Q, int ldq, int6
   for (int64_t q0 = 0; q0 < m; q0 += mb) {
     const int64_t cur = std::min(mb, m - q0);
     STAG_TRY(hash_query_batch(idx, Q, ldq, q0, cur, qkeys, st));
-    {
+    if (join_applies(idx)) {
+      STAG_TRY(join_batch(idx, Q, ldq, q0, cur, self_excl, qkeys, scopy, ncand, nacc, st));
+    } else {
       ScopedTimer tm("lsh_probe", st);
       hipLaunchKernelGGL(probe_queries, dim3((unsigned)ceil_div(cur * K1, 4)), dim3(256), 0, st, Q, ldq, q0, cur, ix,
                          lc, qkeys, idx->ntab, self_excl, scopy, ncand, nacc);

@@ -12,8 +12,9 @@
 // per-chunk (4096 rows) fp64 sums and per-tile (32 rows) fp32 sums of every
 // row of the kernel matrix (tile sums stored node-major, so one draw reads
 // its chunk's 128 tile sums contiguously); a draw walks chunk sums, then tile sums, then
-// recomputes the 32 kernel values of its tile in fp64 (direct differences)
-// and inverts the cumulative sum at each level, j ascending.
+// recomputes the 32 kernel values of its tile in fp64 (direct differences,
+// two lanes per row) and inverts the cumulative sum at each level, j
+// ascending.
 // LSH mode: the CKNS estimator's terms replace the kernel row (lsh.hip).
 #include <cmath>
 
@@ -84,9 +85,9 @@ __device__ inline int invert_level(int count, double target, Fetch&& fetch, doub
 
 // One wave per draw (node i, draw r).
 __global__ __launch_bounds__(256) void draw_exact(const float* __restrict__ X, int64_t n, int d, double a, int s,
-                                                  uint64_t seed, int P, int64_t m_pad, int64_t ntile,
+                                                  uint64_t seed, int P, int64_t m_pad, int64_t ntile, int64_t tstride,
                                                   const double* __restrict__ partial, const float* __restrict__ tp,
-                                                  const double* __restrict__ rest, int64_t* __restrict__ src,
+                                                  const double* __restrict__ rest, int vec4, int64_t* __restrict__ src,
                                                   int64_t* __restrict__ dst, double* __restrict__ w) {
   const int lane = threadIdx.x & 63;
   const int64_t e = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -104,21 +105,41 @@ __global__ __launch_bounds__(256) void draw_exact(const float* __restrict__ X, i
       const int64_t t0 = (int64_t)c * kChunkTiles;
       const int nt = (int)((ntile - t0) < kChunkTiles ? (ntile - t0) : kChunkTiles);
       double resid2 = 0.0;
-      const int tl = invert_level(nt, resid, [&](int k) { return (double)tp[i * ntile + t0 + k]; }, &resid2);
+      const int tl = invert_level(nt, resid, [&](int k) { return (double)tp[i * tstride + t0 + k]; }, &resid2);
       if (tl >= 0) {
+        // rows of the tile: lanes l and l + 32 share row l % 32 and take
+        // alternate 16-byte pieces (or alternate elements) of it
         const int64_t rb = (t0 + tl) * 32;
-        const int64_t j = rb + lane;
-        double kv = 0.0;
-        if (lane < 32 && j < n && j != i) {
+        const int half = lane >> 5;
+        const int64_t j = rb + (lane & 31);
+        const bool live = j < n && j != i;
+        double D = 0.0;
+        if (live) {
           const float* xi = X + i * d;
           const float* xj = X + j * d;
-          double D = 0.0;
-          for (int h = 0; h < d; ++h) {
-            const double t = (double)xi[h] - (double)xj[h];
-            D = __dadd_rn(D, __dmul_rn(t, t));
+          if (vec4) {
+            const float4* a4 = reinterpret_cast<const float4*>(xi);
+            const float4* b4 = reinterpret_cast<const float4*>(xj);
+            for (int k4 = half; k4 < (d >> 2); k4 += 2) {
+              const float4 p = a4[k4], q = b4[k4];
+              double t = (double)p.x - (double)q.x;
+              D = __builtin_fma(t, t, D);
+              t = (double)p.y - (double)q.y;
+              D = __builtin_fma(t, t, D);
+              t = (double)p.z - (double)q.z;
+              D = __builtin_fma(t, t, D);
+              t = (double)p.w - (double)q.w;
+              D = __builtin_fma(t, t, D);
+            }
+          } else {
+            for (int h = half; h < d; h += 2) {
+              const double t = (double)xi[h] - (double)xj[h];
+              D = __builtin_fma(t, t, D);
+            }
           }
-          kv = exp(-a * D);
         }
+        D += __shfl_xor(D, 32);
+        const double kv = (lane < 32 && live) ? exp(-a * D) : 0.0;
         double resid3 = 0.0;
         const int jl = invert_level(32, resid2, [&](int) { return kv; }, &resid3);  // lane k owns row k
         if (jl >= 0) pick = rb + jl;
@@ -140,23 +161,25 @@ stag_status sample_exact(const float* X, int64_t n, int d, double a, int form, i
   STAG_TRY(prepare_operands(form, X, n, d, a, true, ws, &qo, st));
   const int P = (int)exact_chunks(xo.rows_pad);
   const int64_t ntile = xo.rows_pad / 32;
+  const int64_t tstride = round_up(ntile, 8);
   double* partial = nullptr;
   float* tp = nullptr;
   double* rest = nullptr;
   STAG_TRY(ws.alloc(&partial, (size_t)P * qo.rows_pad));
-  STAG_TRY(ws.alloc(&tp, (size_t)ntile * qo.rows_pad));
+  STAG_TRY(ws.alloc(&tp, (size_t)tstride * qo.rows_pad));
   STAG_TRY(ws.alloc(&rest, (size_t)n));
   TileExtra ex;
   ex.self = 1;
   ex.tp = tp;
-  ex.ntile = ntile;
+  ex.ntile = tstride;
   STAG_TRY(launch_exact_tiles(xo, qo, partial, ex, st));
   hipLaunchKernelGGL(row_rest, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, st, partial, P, qo.rows_pad, n, rest,
                      deg_out);
   STAG_TRY(check_launch("row_rest"));
+  const int vec4 = (d % 4 == 0) && (reinterpret_cast<uintptr_t>(X) % 16 == 0);
   ScopedTimer tm("simgraph_draw_exact", st);
   hipLaunchKernelGGL(draw_exact, dim3((unsigned)ceil_div(n * s, 4)), dim3(256), 0, st, X, n, d, a, s, seed, P,
-                     qo.rows_pad, ntile, partial, tp, rest, src, dst, w);
+                     qo.rows_pad, ntile, tstride, partial, tp, rest, vec4, src, dst, w);
   return check_launch("draw_exact");
 }
 
