@@ -294,7 +294,7 @@ __global__ __launch_bounds__(256) void hash_queries(const float* __restrict__ Q,
     const int l = (int)(tab % L);
     const uint64_t key =
         table_key<DREG>(l, xr, xrow, d, dg, G8 + tab * nch * dg * 8, B + tab * K, K, nch, nullptr);
-    if (live) qkeys[ql * ntab + tab] = key;
+    if (live) qkeys[tab * mb + ql] = key;
   }
 }
 
@@ -424,7 +424,8 @@ __device__ inline float dist2_f32(const float* __restrict__ qrow, const float* _
 // Returns the number of candidates walked.
 template <class F>
 __device__ inline int64_t walk_copy(const IndexView& ix, const LevelConst& lc, int t, const uint64_t* __restrict__ qk,
-                                    WalkScratch& ws, const float* __restrict__ qrow, int64_t self_idx, F&& on_batch) {
+                                    int64_t qs, WalkScratch& ws, const float* __restrict__ qrow, int64_t self_idx,
+                                    F&& on_batch) {
   const int lane = threadIdx.x & 63;
   const int L = ix.L, d = ix.d;
   const double delta = screen_delta(d);
@@ -440,7 +441,7 @@ __device__ inline int64_t walk_copy(const IndexView& ix, const LevelConst& lc, i
     uint32_t c = 0;
     int64_t base = 0;
     if (lane < L) {
-      const uint64_t key = qk[(int64_t)seg * L + lane];
+      const uint64_t key = qk[((int64_t)seg * L + lane) * qs];
       ws.qk[lane] = key;
       const int64_t tb = (int64_t)ix.tab_seg_off[seg] + (int64_t)lane * cap;
       uint32_t sl = (uint32_t)key & mask;
@@ -539,7 +540,7 @@ __global__ __launch_bounds__(256) void probe_queries(const float* __restrict__ Q
   __shared__ WalkScratch wsc[4];
   double acc = 0.0;
   int64_t nc = 0, na = 0;
-  nc = walk_copy(ix, lc, t, qkeys + ql * ntab, wsc[wave], qrow, self_excl ? q0 + ql : -1,
+  nc = walk_copy(ix, lc, t, qkeys + ql, mb, wsc[wave], qrow, self_excl ? q0 + ql : -1,
                  [&](double v, int32_t j, bool valid) {
                    acc += v;
                    na += v > 0.0 ? 1 : 0;
@@ -617,7 +618,7 @@ __global__ __launch_bounds__(256) void draw_lsh(IndexView ix, LevelConst lc, con
     if (__ballot(mine && tsel == t) == 0) continue;
     double running = 0.0;
     int32_t lastj = -1;
-    walk_copy(ix, lc, t, qkeys + ql * ntab, wsc[wave], qrow, qi, [&](double v, int32_t j, bool valid) {
+    walk_copy(ix, lc, t, qkeys + ql, mb, wsc[wave], qrow, qi, [&](double v, int32_t j, bool valid) {
       const double incl = wave_incl_scan_f64(v);
       const double btot = __shfl(incl, 63);
       const uint64_t pos = __ballot(v > 0.0);
@@ -691,44 +692,62 @@ __host__ __device__ inline int join_lds_bytes(int dq, int L) {
   return join_lds_rows(dq) + kJoinChunk * 4 + kJoinChunk * lm1 * 8 + lm1 * 64 * 8;
 }
 
-// The bucket (global slot) of every (query, table) pair of the batch, or -1,
-// and the pair's rank among the bucket's queries (arrival order).
-__global__ __launch_bounds__(256) void locate_queries(const uint64_t* __restrict__ qkeys, int64_t total, int64_t ntab,
+// The bucket (global slot) of every (table, query) pair of the batch (pair
+// e = table * mb + query), or -1, and the pair's rank among the bucket's
+// queries (arrival order; lanes of a wave that share a bucket take one atomic).
+__global__ __launch_bounds__(256) void locate_queries(const uint64_t* __restrict__ qkeys, int64_t total, int64_t mb,
                                                       int L, const uint64_t* __restrict__ tab_seg_off,
                                                       const uint32_t* __restrict__ seg_cap,
                                                       const uint64_t* __restrict__ tab_key, int32_t* __restrict__ qslot,
                                                       uint32_t* __restrict__ qrank, uint32_t* __restrict__ qcount) {
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t g = e % ntab;
-    const int64_t seg = g / L;
-    const int l = (int)(g % L);
-    const uint32_t cap = seg_cap[seg];
+  const int lane = threadIdx.x & 63;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t e0 = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63); e0 < total; e0 += stride) {
+    const int64_t e = e0 + lane;
     int32_t slot = -1;
-    if (cap > 0) {
-      const uint64_t key = qkeys[e];
-      const int64_t tb = (int64_t)tab_seg_off[seg] + (int64_t)l * cap;
-      uint32_t sl = (uint32_t)key & (cap - 1);
-      while (true) {
-        const uint64_t v = tab_key[tb + sl];
-        if (v == key) {
-          slot = (int32_t)(tb + sl);
-          break;
+    if (e < total) {
+      const int64_t g = e / mb;
+      const int64_t seg = g / L;
+      const int l = (int)(g % L);
+      const uint32_t cap = seg_cap[seg];
+      if (cap > 0) {
+        const uint64_t key = qkeys[e];
+        const int64_t tb = (int64_t)tab_seg_off[seg] + (int64_t)l * cap;
+        uint32_t sl = (uint32_t)key & (cap - 1);
+        while (true) {
+          const uint64_t v = tab_key[tb + sl];
+          if (v == key) {
+            slot = (int32_t)(tb + sl);
+            break;
+          }
+          if (v == kEmpty) break;
+          sl = (sl + 1) & (cap - 1);
         }
-        if (v == kEmpty) break;
-        sl = (sl + 1) & (cap - 1);
       }
+      qslot[e] = slot;
     }
-    qslot[e] = slot;
-    if (slot >= 0) qrank[e] = atomicAdd(qcount + slot, 1u);
+    uint32_t rank = 0;
+    uint64_t pending = __ballot(slot >= 0);
+    while (pending) {
+      const int leader = __ffsll((long long)pending) - 1;
+      const int32_t ls = __shfl(slot, leader);
+      const uint64_t same = __ballot(slot == ls) & pending;
+      uint32_t base = 0;
+      if (lane == leader) base = atomicAdd(qcount + ls, (uint32_t)__popcll(same));
+      base = __shfl(base, leader);
+      if ((same >> lane) & 1ull) rank = base + (uint32_t)__popcll(same & ((1ull << lane) - 1ull));
+      pending &= ~same;
+    }
+    if (slot >= 0) qrank[e] = rank;
   }
 }
 
 __global__ __launch_bounds__(256) void scatter_queries(const int32_t* __restrict__ qslot,
-                                                       const uint32_t* __restrict__ qrank, int64_t total, int64_t ntab,
+                                                       const uint32_t* __restrict__ qrank, int64_t total, int64_t mb,
                                                        const uint64_t* __restrict__ qstart, int32_t* __restrict__ qlist) {
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
     const int32_t slot = qslot[e];
-    if (slot >= 0) qlist[qstart[slot] + qrank[e]] = (int32_t)(e / ntab);
+    if (slot >= 0) qlist[qstart[slot] + qrank[e]] = (int32_t)(e % mb);
   }
 }
 
@@ -755,7 +774,7 @@ __device__ inline int64_t last_le(const uint64_t* __restrict__ v, int64_t n, uin
 
 template <int DQ>
 __global__ __launch_bounds__(64) void join_buckets(IndexView ix, LevelConst lc, const float* __restrict__ Q, int ldq,
-                                                   int64_t q0, const uint64_t* __restrict__ qkeys, int64_t ntab,
+                                                   int64_t q0, const uint64_t* __restrict__ qkeys, int64_t mb,
                                                    const uint32_t* __restrict__ qcount,
                                                    const uint64_t* __restrict__ qstart,
                                                    const int32_t* __restrict__ qlist,
@@ -799,7 +818,7 @@ __global__ __launch_bounds__(64) void join_buckets(IndexView ix, LevelConst lc, 
 #pragma unroll
     for (int h = 0; h < DQ; ++h) q[h] = h < d ? qrow[h] : 0.0f;
   }
-  for (int l2 = 0; l2 < l; ++l2) qk[l2 * 64 + lane] = qkeys[(int64_t)ql * ntab + (int64_t)seg * L + l2];
+  for (int l2 = 0; l2 < l; ++l2) qk[l2 * 64 + lane] = qkeys[((int64_t)seg * L + l2) * mb + ql];
   if (dx < DQ)
     for (int e = lane; e < kJoinChunk * RS; e += 64) rows[e] = 0.0f;
 
@@ -887,7 +906,7 @@ __global__ __launch_bounds__(256) void combine_groups(const int32_t* __restrict_
   for (int t = 0; t < K1; ++t) {
     double acc = 0.0;
     for (int64_t g = (int64_t)t * per_copy; g < (int64_t)(t + 1) * per_copy; ++g) {
-      const int64_t e = ql * ntab + g;
+      const int64_t e = g * mb + ql;
       const int32_t slot = qslot[e];
       if (slot < 0) continue;
       const uint32_t rank = qrank[e], nm = tab_cnt[slot];
@@ -1229,15 +1248,16 @@ int64_t query_batch(const stag_lsh_index* idx, int64_t m) {
 stag_status hash_query_batch(const stag_lsh_index* idx, const float* Q, int ldq, int64_t q0, int64_t cur,
                              uint64_t* qkeys, hipStream_t st) {
   const LshParams& prm = idx->prm;
-  int tpw = 1;
-  const int64_t qblocks = ceil_div(cur, 64);
-  while (tpw < idx->ntab && (qblocks * ceil_div(idx->ntab, 4 * tpw) > 262144 || ceil_div(idx->ntab, 4 * tpw) > 65535))
-    tpw *= 2;
   ScopedTimer tm("lsh_hash_queries", st);
+  // tables per wave: enough waves to fill the chip (about 8 per SIMD), as few
+  // reloads of a query row as that allows
+  const int64_t qblocks = ceil_div(cur, 64);
+  int64_t tpw = std::max<int64_t>(1, std::min<int64_t>(idx->ntab, idx->ntab * qblocks * 4 / 32768));
+  while (tpw < idx->ntab && ceil_div(idx->ntab, 4 * tpw) > 65535) tpw *= 2;
   return dispatch_dreg(idx->dreg, [&](auto D) {
     hipLaunchKernelGGL(hash_queries<decltype(D)::value>, dim3((unsigned)qblocks, (unsigned)ceil_div(idx->ntab, 4 * tpw)),
                        dim3(256), 0, st, Q, ldq, q0, cur, idx->d, idx->dg, idx->G8, idx->B, prm.shape.K, prm.shape.L,
-                       idx->nch, idx->ntab, tpw, qkeys);
+                       idx->nch, idx->ntab, (int)tpw, qkeys);
     return check_launch("hash_queries");
   });
 }
@@ -1273,11 +1293,11 @@ stag_status join_batch(const stag_lsh_index* idx, const float* Q, int ldq, int64
     ScopedTimer tm("lsh_join_setup", st);
     hipLaunchKernelGGL(zero_u32, dim3((unsigned)std::min<int64_t>(ceil_div(nslots, 256), 65536)), dim3(256), 0, st,
                        qcount, nslots);
-    hipLaunchKernelGGL(locate_queries, dim3(gpairs), dim3(256), 0, st, qkeys, pairs, ntab, L, idx->tab_seg_off,
+    hipLaunchKernelGGL(locate_queries, dim3(gpairs), dim3(256), 0, st, qkeys, pairs, cur, L, idx->tab_seg_off,
                        idx->seg_cap, idx->tab_key, qslot, qrank, qcount);
     STAG_TRY(check_launch("locate_queries"));
     STAG_TRY(exclusive_scan_u32(qcount, qstart, nslots, ws, st));
-    hipLaunchKernelGGL(scatter_queries, dim3(gpairs), dim3(256), 0, st, qslot, qrank, pairs, ntab, qstart, qlist);
+    hipLaunchKernelGGL(scatter_queries, dim3(gpairs), dim3(256), 0, st, qslot, qrank, pairs, cur, qstart, qlist);
     STAG_TRY(check_launch("scatter_queries"));
     hipLaunchKernelGGL(count_tasks, dim3((unsigned)ceil_div(nslots, 256)), dim3(256), 0, st, qcount, idx->tab_cnt,
                        nslots, ntask);
@@ -1297,7 +1317,7 @@ stag_status join_batch(const stag_lsh_index* idx, const float* Q, int ldq, int64
     const int dq = idx->d <= 16 ? 16 : idx->d <= 32 ? 32 : idx->d <= 64 ? 64 : 128;
     const size_t lds = (size_t)join_lds_bytes(dq, L);
     auto launch = [&](auto kern) {
-      hipLaunchKernelGGL(kern, dim3((unsigned)ntasks), dim3(64), lds, st, ix, lc, Q, ldq, q0, qkeys, ntab, qcount,
+      hipLaunchKernelGGL(kern, dim3((unsigned)ntasks), dim3(64), lds, st, ix, lc, Q, ldq, q0, qkeys, cur, qcount,
                          qstart, qlist, task_base, nslots, (int)idx->nseg, self_excl, tpart, nacc);
     };
     switch (dq) {
