@@ -298,10 +298,23 @@ __global__ __launch_bounds__(256) void hash_queries(const float* __restrict__ Q,
   }
 }
 
-__device__ inline double collision_p_dev(double c) {
-  if (c <= 0.0) return 1.0;
-  const double inv_sqrt_2pi = 0.39894228040143267794;
-  return erf(2.0 * sqrt(2.0) / c) - 0.5 * inv_sqrt_2pi * c * (-expm1(-8.0 / (c * c)));
+// Collision probability p(c) of a level from its Chebyshev interpolant on the
+// level's range of c = sqrt(D) / r_i (see cheb_levels); row layout
+// {lo, 2 / (1 - lo), a_0 .. a_32}.
+constexpr int kChebTerms = 33;
+constexpr int kChebRow = kChebTerms + 2;
+
+__device__ inline double collision_p_cheb(const double* __restrict__ row, double c) {
+  const double t = (c - row[0]) * row[1] - 1.0;
+  const double t2 = 2.0 * t;
+  double b1 = 0.0, b2 = 0.0;
+#pragma unroll
+  for (int k = kChebTerms - 1; k >= 1; --k) {
+    const double b0 = __builtin_fma(t2, b1, row[2 + k] - b2);
+    b2 = b1;
+    b1 = b0;
+  }
+  return __builtin_fma(t, b1, 0.5 * row[2] - b2);
 }
 
 // x^k for an integer k >= 0 by binary powering.
@@ -317,8 +330,8 @@ __device__ inline double ipow_dev(double x, int k) {
 
 // Recovery probability 1 - (1 - p(c)^K)^L (integer powers; equal to the
 // expm1/log1p form up to rounding).
-__device__ inline double recovery_dev(double c, int K, int L) {
-  const double x = ipow_dev(collision_p_dev(c), K);
+__device__ inline double recovery_dev(const double* __restrict__ cheb_row, double c, int K, int L) {
+  const double x = ipow_dev(collision_p_cheb(cheb_row, c), K);
   if (x >= 1.0) return 1.0;
   return 1.0 - ipow_dev(1.0 - x, L);
 }
@@ -333,6 +346,7 @@ struct IndexView {
   int dx, d, K1, J, L, K;
   double a;
   int literal;
+  const double* cheb;  // [J + 1][kChebRow] collision-probability interpolants
   const uint64_t* seg_off;
   const int32_t* members;
   const uint64_t* mkeys;
@@ -478,7 +492,7 @@ __device__ inline int64_t walk_copy(const IndexView& ix, const LevelConst& lc, i
         j = ws.ring[(head + lane) & 127];
         const double D = dist2_f64(qrow, ix.X + (int64_t)j * ix.dx, d);
         if (D >= Tlo && D < Thi) {
-          const double R = ix.literal ? 1.0 : recovery_dev(sqrt(D) / ri, ix.K, L);
+          const double R = ix.literal ? 1.0 : recovery_dev(ix.cheb + i * kChebRow, sqrt(D) / ri, ix.K, L);
           v = exp(-ix.a * D) / (pi * R);
         }
       }
@@ -685,11 +699,11 @@ constexpr int kJoinMembers = 512;
 constexpr int kJoinChunk = 32;
 
 // Bytes of dynamic LDS of one join wave (layout: rows, point ids, member
-// keys, query keys).
+// norms, member keys, query keys).
 __host__ __device__ inline int join_lds_rows(int dq) { return kJoinChunk * (dq + 4) * 4; }
 __host__ __device__ inline int join_lds_bytes(int dq, int L) {
   const int lm1 = L > 1 ? L - 1 : 1;
-  return join_lds_rows(dq) + kJoinChunk * 4 + kJoinChunk * lm1 * 8 + lm1 * 64 * 8;
+  return join_lds_rows(dq) + kJoinChunk * 8 + kJoinChunk * lm1 * 8 + lm1 * 64 * 8;
 }
 
 // The bucket (global slot) of every (table, query) pair of the batch (pair
@@ -788,7 +802,8 @@ __global__ __launch_bounds__(64) void join_buckets(IndexView ix, LevelConst lc, 
   const int lm1 = L > 1 ? L - 1 : 1;
   float* rows = reinterpret_cast<float*>(jlds);
   int32_t* jl = reinterpret_cast<int32_t*>(jlds + join_lds_rows(DQ));
-  uint64_t* mk = reinterpret_cast<uint64_t*>(jlds + join_lds_rows(DQ) + kJoinChunk * 4);
+  float* nxl = reinterpret_cast<float*>(jl + kJoinChunk);
+  uint64_t* mk = reinterpret_cast<uint64_t*>(jlds + join_lds_rows(DQ) + kJoinChunk * 8);
   uint64_t* qk = mk + kJoinChunk * lm1;
 
   const int64_t task = blockIdx.x;
@@ -805,8 +820,10 @@ __global__ __launch_bounds__(64) void join_buckets(IndexView ix, LevelConst lc, 
   const int qc = (int)(r / nmc), mc = (int)(r % nmc);
   const int64_t mbase = s0 * L + (int64_t)l * cnt + ix.tab_start[slot];
   const double Tlo = lc.T[i - 1], Thi = lc.T[i], pi = lc.p[i], ri = lc.r[i];
-  const double delta = screen_delta(d);
-  const double lo_s = Tlo * (1.0 - delta), hi_s = Thi * (1.0 + delta);
+  const float Tlo_f = (float)Tlo, Thi_f = (float)Thi;
+  // |fl(D) - D| <= ce (|q|^2 + |x|^2) for D = |q|^2 + |x|^2 - 2 q.x with fp32
+  // fused dot products and norms (gamma bounds, with margin)
+  const float ce = (float)(2 * DQ + 24) * 0x1.0p-24f;
 
   const uint32_t qp = (uint32_t)qc * 64u + (uint32_t)lane;
   const bool qvalid = qp < nq;
@@ -818,6 +835,9 @@ __global__ __launch_bounds__(64) void join_buckets(IndexView ix, LevelConst lc, 
 #pragma unroll
     for (int h = 0; h < DQ; ++h) q[h] = h < d ? qrow[h] : 0.0f;
   }
+  float qnorm = 0.0f;
+#pragma unroll
+  for (int h = 0; h < DQ; ++h) qnorm = __builtin_fmaf(q[h], q[h], qnorm);
   for (int l2 = 0; l2 < l; ++l2) qk[l2 * 64 + lane] = qkeys[((int64_t)seg * L + l2) * mb + ql];
   if (dx < DQ)
     for (int e = lane; e < kJoinChunk * RS; e += 64) rows[e] = 0.0f;
@@ -843,26 +863,40 @@ __global__ __launch_bounds__(64) void join_buckets(IndexView ix, LevelConst lc, 
       *reinterpret_cast<float4*>(&rows[rr * RS + 4 * c4]) = v;
     }
     __builtin_amdgcn_wave_barrier();
+    if (lane < nk) {
+      float nr = 0.0f;
+#pragma unroll
+      for (int h4 = 0; h4 < DQ / 4; ++h4) {
+        const float4 xv = *reinterpret_cast<const float4*>(&rows[lane * RS + 4 * h4]);
+        nr = __builtin_fmaf(xv.x, xv.x, nr);
+        nr = __builtin_fmaf(xv.y, xv.y, nr);
+        nr = __builtin_fmaf(xv.z, xv.z, nr);
+        nr = __builtin_fmaf(xv.w, xv.w, nr);
+      }
+      nxl[lane] = nr;
+    }
+    __builtin_amdgcn_wave_barrier();
     uint32_t mask = 0;
     for (int m = 0; m < nk; ++m) {
       const float* xr = &rows[m * RS];
-      float D0 = 0.0f, D1 = 0.0f;
+      float p0 = 0.0f, p1 = 0.0f;
 #pragma unroll
       for (int h4 = 0; h4 < DQ / 4; ++h4) {
         const float4 xv = *reinterpret_cast<const float4*>(xr + 4 * h4);
-        float t0 = q[4 * h4] - xv.x;
-        D0 = __builtin_fmaf(t0, t0, D0);
-        t0 = q[4 * h4 + 1] - xv.y;
-        D1 = __builtin_fmaf(t0, t0, D1);
-        t0 = q[4 * h4 + 2] - xv.z;
-        D0 = __builtin_fmaf(t0, t0, D0);
-        t0 = q[4 * h4 + 3] - xv.w;
-        D1 = __builtin_fmaf(t0, t0, D1);
+        p0 = __builtin_fmaf(q[4 * h4], xv.x, p0);
+        p1 = __builtin_fmaf(q[4 * h4 + 1], xv.y, p1);
+        p0 = __builtin_fmaf(q[4 * h4 + 2], xv.z, p0);
+        p1 = __builtin_fmaf(q[4 * h4 + 3], xv.w, p1);
       }
-      const double D32 = (double)(D0 + D1);
-      bool seen = false;
-      for (int l2 = 0; l2 < l; ++l2) seen |= mk[m * lm1 + l2] == qk[l2 * 64 + lane];
-      const bool keep = qvalid && !seen && (int64_t)jl[m] != self_idx && D32 >= lo_s && D32 < hi_s;
+      const float sn = qnorm + nxl[m];
+      const float D32 = __builtin_fmaf(-2.0f, p0 + p1, sn);
+      const float E = ce * sn;
+      bool keep = qvalid && D32 >= Tlo_f - E && D32 < Thi_f + E;
+      if (__ballot(keep)) {
+        bool seen = (int64_t)jl[m] == self_idx;
+        for (int l2 = 0; l2 < l; ++l2) seen |= mk[m * lm1 + l2] == qk[l2 * 64 + lane];
+        keep = keep && !seen;
+      }
       mask |= keep ? (1u << m) : 0u;
     }
     // survivors, per lane in member order
@@ -873,14 +907,20 @@ __global__ __launch_bounds__(64) void join_buckets(IndexView ix, LevelConst lc, 
         const float* xr = &rows[m * RS];
         double D = 0.0;
 #pragma unroll
-        for (int h = 0; h < DQ; ++h) {
-          float qh = q[h];
-          asm volatile("" : "+v"(qh));  // keeps the widening here (no hoisted fp64 copy of the row)
-          const double t0 = (double)qh - (double)xr[h];
-          D = __builtin_fma(t0, t0, D);
+        for (int h4 = 0; h4 < DQ / 4; ++h4) {
+          const float4 xv = *reinterpret_cast<const float4*>(xr + 4 * h4);
+          const float xs[4] = {xv.x, xv.y, xv.z, xv.w};
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            float qh = q[4 * h4 + e];
+            asm volatile("" : "+v"(qh));  // keeps the widening here (no hoisted fp64 copy of the row)
+            const double t0 = (double)qh - (double)xs[e];
+            D = __builtin_fma(t0, t0, D);
+          }
+          if (h4 % 2 == 1) __builtin_amdgcn_sched_barrier(0);
         }
         if (D >= Tlo && D < Thi) {
-          const double R = ix.literal ? 1.0 : recovery_dev(sqrt(D) / ri, ix.K, L);
+          const double R = ix.literal ? 1.0 : recovery_dev(ix.cheb + i * kChebRow, sqrt(D) / ri, ix.K, L);
           acc += exp(-ix.a * D) / (pi * R);
           ++na;
         }
@@ -943,6 +983,33 @@ double recovery_host(double c, int K, int L) {
   const double x = std::pow(collision_p_host(c), (double)K);
   if (x >= 1.0) return 1.0;
   return -std::expm1((double)L * std::log1p(-x));
+}
+
+// Chebyshev interpolants (33 terms) of the collision probability p(c) over
+// each level's range of c = sqrt(D) / r_i, D in [T_{i-1}, T_i): c in
+// [sqrt(T_{i-1} / T_i), 1].  On these ranges the interpolant agrees with the
+// closed form to about 1e-15 relative (smooth function, degree 32).
+std::vector<double> cheb_levels(const LshParams& prm) {
+  const int J = prm.shape.J, n = kChebTerms;
+  std::vector<double> out((size_t)(J + 1) * kChebRow, 0.0);
+  const double pi = 3.14159265358979323846;
+  for (int i = 1; i <= J; ++i) {
+    const double lo = std::sqrt(prm.lc_T[i - 1]) / prm.lc_r[i];
+    double* row = out.data() + (size_t)i * kChebRow;
+    row[0] = lo;
+    row[1] = 2.0 / (1.0 - lo);
+    std::vector<double> f((size_t)n);
+    for (int j = 0; j < n; ++j) {
+      const double x = std::cos(pi * (j + 0.5) / n);
+      f[(size_t)j] = collision_p_host(lo + (1.0 - lo) * (x + 1.0) / 2.0);
+    }
+    for (int k = 0; k < n; ++k) {
+      double sum = 0.0;
+      for (int j = 0; j < n; ++j) sum += f[(size_t)j] * std::cos(pi * k * (j + 0.5) / n);
+      row[2 + k] = 2.0 * sum / n;
+    }
+  }
+  return out;
 }
 
 }  // namespace
@@ -1023,6 +1090,8 @@ struct stag_lsh_index {
   uint32_t* tab_cnt = nullptr;
   int32_t* csr = nullptr;
   double* rlev = nullptr;
+  double* cheb = nullptr;
+  std::vector<double> h_cheb;
   uint64_t* thr = nullptr;
 };
 
@@ -1092,6 +1161,10 @@ stag_status create_index(const float* X, int64_t n, int d, double a, double eps,
   STAG_TRY(own_alloc(idx, &idx->rlev, 65));
   STAG_TRY(own_alloc(idx, &idx->thr, 65));
   STAG_HIP(hipMemcpyAsync(idx->rlev, prm.lc_r, sizeof(double) * (J + 1), hipMemcpyHostToDevice, st));
+  idx->h_cheb = cheb_levels(prm);
+  STAG_TRY(own_alloc(idx, &idx->cheb, idx->h_cheb.size()));
+  STAG_HIP(hipMemcpyAsync(idx->cheb, idx->h_cheb.data(), sizeof(double) * idx->h_cheb.size(), hipMemcpyHostToDevice,
+                          st));
   STAG_HIP(hipMemcpyAsync(idx->thr, prm.thr, sizeof(uint64_t) * (J + 1), hipMemcpyHostToDevice, st));
 
   // projections and offsets
@@ -1218,6 +1291,7 @@ IndexView make_view(const stag_lsh_index* idx) {
   v.K = prm.shape.K;
   v.a = prm.a;
   v.literal = (prm.flags & STAG_LSH_LITERAL) ? 1 : 0;
+  v.cheb = idx->cheb;
   v.seg_off = idx->seg_off;
   v.members = idx->members;
   v.mkeys = idx->mkeys;
