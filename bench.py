@@ -168,10 +168,13 @@ def main():
     out = {}
 
     def step():
-        stag.kde_exact(Xd, Qd, a, form=args.form, S_out=S)
+        # the LSH leg synchronises with the host (index sizes, task counts);
+        # the exact KDE and the edge sampler are queued behind it and keep the
+        # GPU busy while the host starts the next step
         idx = stag.LshIndex(Xd, a, eps=LSH["eps"], seed=LSH["lsh_seed"], **lsh_kw)
         out["lsh"] = idx.query(Qd)
         idx.close()
+        stag.kde_exact(Xd, Qd, a, form=args.form, S_out=S)
         out["graph"] = stag.simgraph_sample(Xd, a, mode="exact", form=args.form, seed=4002)
 
     for _ in range(args.warmup):

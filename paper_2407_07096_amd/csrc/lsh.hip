@@ -277,19 +277,20 @@ __global__ __launch_bounds__(256) void build_tables(int L, const uint64_t* __res
 // ---------------------------------------------------------------------------
 // queries
 // ---------------------------------------------------------------------------
+// One lane per query; the 4 waves of a block take 256 consecutive queries
+// through the same tpw tables, so that the projections a block reads (scalar
+// loads) are shared by all its waves.
 template <int DREG>
 __global__ __launch_bounds__(256) void hash_queries(const float* __restrict__ Q, int ldq, int64_t q0, int64_t mb,
                                                     int d, int dg, const double* __restrict__ G8,
                                                     const double* __restrict__ B, int K, int L, int nch,
                                                     int64_t ntab, int tpw, uint64_t* __restrict__ qkeys) {
-  const int lane = threadIdx.x & 63;
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int64_t ql = (int64_t)blockIdx.x * 64 + lane;
+  const int64_t ql = (int64_t)blockIdx.x * 256 + threadIdx.x;
   const bool live = ql < mb;
   const float* xrow = Q + (q0 + (live ? ql : 0)) * ldq;
   double xr[DREG > 0 ? DREG : 1];
   load_point<DREG>(xr, xrow, d);
-  const int64_t t0 = ((int64_t)blockIdx.y * 4 + wave) * tpw;
+  const int64_t t0 = (int64_t)blockIdx.y * tpw;
   for (int64_t tab = t0; tab < t0 + tpw && tab < ntab; ++tab) {
     const int l = (int)(tab % L);
     const uint64_t key =
@@ -1076,7 +1077,9 @@ struct stag_lsh_index {
   int64_t nseg = 0, ntab = 0, M = 0, total_slots = 0;
   int device = 0;
   std::vector<uint64_t> h_seg_off;
-  std::vector<void*> owned;
+  std::vector<std::pair<void*, size_t>> owned;  // blocks and their sizes
+  char* arena = nullptr;  // current block of small index allocations
+  size_t arena_used = 0;
   float* X = nullptr;
   double* G8 = nullptr;
   double* B = nullptr;
@@ -1098,23 +1101,39 @@ struct stag_lsh_index {
 namespace stag {
 namespace {
 
+// Index memory (cached device blocks, reused by later indexes): requests
+// below 1 MiB are 256-byte slices of 4 MiB blocks, larger ones blocks of
+// their own; all go back to the cache with the index.
 template <typename T>
 stag_status own_alloc(stag_lsh_index* idx, T** p, size_t count) {
+  const size_t bytes = std::max<size_t>((count * sizeof(T) + 255) / 256 * 256, 256);
+  const size_t kSmall = (size_t)1 << 20, kBlock = (size_t)4 << 20;
+  auto raw = [&](void** v, size_t b) -> stag_status {
+    STAG_TRY(cached_alloc(v, b));
+    idx->owned.push_back({*v, b});
+    return STAG_OK;
+  };
   void* v = nullptr;
-  hipError_t e = hipMalloc(&v, std::max<size_t>(count * sizeof(T), 256));
-  if (e != hipSuccess) {
-    (void)hipGetLastError();
-    return fail(e == hipErrorOutOfMemory ? STAG_E_NOMEM : STAG_E_DEVICE, "lsh index allocation of %zu bytes: %s",
-                count * sizeof(T), hipGetErrorString(e));
+  if (bytes >= kSmall) {
+    STAG_TRY(raw(&v, bytes));
+  } else {
+    if (idx->arena == nullptr || idx->arena_used + bytes > kBlock) {
+      void* blk = nullptr;
+      STAG_TRY(raw(&blk, kBlock));
+      idx->arena = static_cast<char*>(blk);
+      idx->arena_used = 0;
+    }
+    v = idx->arena + idx->arena_used;
+    idx->arena_used += bytes;
   }
-  idx->owned.push_back(v);
   *p = static_cast<T*>(v);
   return STAG_OK;
 }
 
 void free_index(stag_lsh_index* idx) {
   if (!idx) return;
-  for (void* p : idx->owned) (void)hipFree(p);
+  // callers have synchronised the device: nothing uses the memory any more
+  for (const auto& b : idx->owned) cached_free(b.first, b.second);
   delete idx;
 }
 
@@ -1323,13 +1342,12 @@ stag_status hash_query_batch(const stag_lsh_index* idx, const float* Q, int ldq,
                              uint64_t* qkeys, hipStream_t st) {
   const LshParams& prm = idx->prm;
   ScopedTimer tm("lsh_hash_queries", st);
-  // tables per wave: enough waves to fill the chip (about 8 per SIMD), as few
-  // reloads of a query row as that allows
-  const int64_t qblocks = ceil_div(cur, 64);
-  int64_t tpw = std::max<int64_t>(1, std::min<int64_t>(idx->ntab, idx->ntab * qblocks * 4 / 32768));
-  while (tpw < idx->ntab && ceil_div(idx->ntab, 4 * tpw) > 65535) tpw *= 2;
+  // tables per block: about 2048 blocks (8 waves per SIMD), as few reloads
+  // of a query row as that allows
+  const int64_t qb = ceil_div(cur, 256);
+  const int64_t tpw = std::max<int64_t>(1, std::min<int64_t>(idx->ntab, idx->ntab * qb / 2048));
   return dispatch_dreg(idx->dreg, [&](auto D) {
-    hipLaunchKernelGGL(hash_queries<decltype(D)::value>, dim3((unsigned)qblocks, (unsigned)ceil_div(idx->ntab, 4 * tpw)),
+    hipLaunchKernelGGL(hash_queries<decltype(D)::value>, dim3((unsigned)qb, (unsigned)ceil_div(idx->ntab, tpw)),
                        dim3(256), 0, st, Q, ldq, q0, cur, idx->d, idx->dg, idx->G8, idx->B, prm.shape.K, prm.shape.L,
                        idx->nch, idx->ntab, (int)tpw, qkeys);
     return check_launch("hash_queries");

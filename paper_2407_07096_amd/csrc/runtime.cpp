@@ -37,9 +37,65 @@ Workspace::~Workspace() {
   for (void* p : ptrs_) (void)hipFreeAsync(p, stream_);
 }
 
-stag_status Workspace::alloc_bytes(void** p, size_t bytes) {
+namespace {
+std::mutex g_pool_mu;
+bool g_pool_done[64] = {};
+}  // namespace
+
+void keep_pool_memory() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return;
+  std::lock_guard<std::mutex> lk(g_pool_mu);
+  if (g_pool_done[dev]) return;
+  g_pool_done[dev] = true;
+  hipMemPool_t pool = nullptr;
+  if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess && pool) {
+    uint64_t thr = UINT64_MAX;
+    (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+  }
+  (void)hipGetLastError();
+}
+
+namespace {
+std::mutex g_cache_mu;
+std::map<int, std::multimap<size_t, void*>> g_cache;
+}  // namespace
+
+stag_status cached_alloc(void** p, size_t bytes) {
   *p = nullptr;
-  if (bytes == 0) bytes = 256;
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  {
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    auto& c = g_cache[dev];
+    auto it = c.lower_bound(bytes);
+    if (it != c.end() && it->first <= 2 * bytes) {
+      *p = it->second;
+      c.erase(it);
+      return STAG_OK;
+    }
+  }
+  hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) {
+    *p = nullptr;
+    (void)hipGetLastError();
+    return fail(e == hipErrorOutOfMemory ? STAG_E_NOMEM : STAG_E_DEVICE, "device allocation of %zu bytes: %s", bytes,
+                hipGetErrorString(e));
+  }
+  return STAG_OK;
+}
+
+void cached_free(void* p, size_t bytes) {
+  if (!p) return;
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  std::lock_guard<std::mutex> lk(g_cache_mu);
+  g_cache[dev].emplace(bytes, p);
+}
+
+stag_status Workspace::raw_alloc(void** p, size_t bytes) {
+  *p = nullptr;
+  keep_pool_memory();
   hipError_t e = hipMallocAsync(p, bytes, stream_);
   if (e != hipSuccess) {
     *p = nullptr;
@@ -48,6 +104,23 @@ stag_status Workspace::alloc_bytes(void** p, size_t bytes) {
                 bytes, hipGetErrorString(e));
   }
   ptrs_.push_back(*p);
+  return STAG_OK;
+}
+
+stag_status Workspace::alloc_bytes(void** p, size_t bytes) {
+  *p = nullptr;
+  bytes = (bytes + 255) / 256 * 256;
+  if (bytes == 0) bytes = 256;
+  if (bytes >= kSmallBytes) return raw_alloc(p, bytes);
+  if (cur_ == nullptr || used_ + bytes > cap_) {
+    void* blk = nullptr;
+    STAG_TRY(raw_alloc(&blk, kBlockBytes));
+    cur_ = static_cast<char*>(blk);
+    used_ = 0;
+    cap_ = kBlockBytes;
+  }
+  *p = cur_ + used_;
+  used_ += bytes;
   return STAG_OK;
 }
 

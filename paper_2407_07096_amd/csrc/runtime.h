@@ -36,6 +36,18 @@ void clear_error();
 stag_status check_launch(const char* what);
 
 // Temporary device memory, allocated and released in stream order.
+// The current device's default stream-ordered pool keeps freed memory for
+// reuse (release threshold at the maximum) instead of returning it to the
+// system at every synchronisation; set once per device on first use.
+void keep_pool_memory();
+
+// Long-lived device blocks (index memory) with a per-device cache: a freed
+// block is kept and handed to a later request of at most its size (and at
+// least half of it) on the same device; blocks are returned to the system
+// only at process exit.  cached_free requires the block to be idle.
+stag_status cached_alloc(void** p, size_t bytes);
+void cached_free(void* p, size_t bytes);
+
 class Workspace {
  public:
   explicit Workspace(hipStream_t s) : stream_(s) {}
@@ -49,17 +61,26 @@ class Workspace {
     *p = static_cast<T*>(v);
     return st;
   }
+  // Requests below kSmallBytes share kBlockBytes blocks (256-byte aligned
+  // slices); larger ones get an allocation of their own.
   stag_status alloc_bytes(void** p, size_t bytes);
   // Hands the allocations to the caller (they are no longer freed here).
   std::vector<void*> release() {
     std::vector<void*> v;
     v.swap(ptrs_);
+    cur_ = nullptr;
+    used_ = cap_ = 0;
     return v;
   }
+  static constexpr size_t kSmallBytes = (size_t)1 << 20;
+  static constexpr size_t kBlockBytes = (size_t)4 << 20;
 
  private:
+  stag_status raw_alloc(void** p, size_t bytes);
   hipStream_t stream_;
   std::vector<void*> ptrs_;
+  char* cur_ = nullptr;
+  size_t used_ = 0, cap_ = 0;
 };
 
 // Optional per-kernel timing: when enabled, ScopedTimer records a HIP event
