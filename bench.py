@@ -123,6 +123,34 @@ def serving_run(stag, torch, dev, n_requests: int, seconds_cap: float):
             "batch_sizes": "log-uniform 1..65536", "wall_s": t_end - t_start}
 
 
+HERE = os.path.dirname(os.path.abspath(__file__))
+TRAFFIC_FILE = os.path.join(HERE, "profiles", "hot_path_step_n100k_d64_hbm_traffic.txt")
+CSRC = os.path.join(HERE, "paper_2407_07096_amd", "csrc")
+TRAFFIC_SOURCES = {"kde_tile": ["kde_exact.hip", "kde_exact.h"], "simgraph_tile": ["kde_exact.hip", "kde_exact.h"],
+                   "lsh_": ["lsh.hip", "e2lsh.h"], "simgraph_draw": ["simgraph.hip"]}
+
+
+def committed_traffic(key):
+    """HBM bytes per launch of a kernel from the committed counter summary
+    (FETCH_SIZE/WRITE_SIZE scaled by the copy calibration), or None when the
+    summary has no entry or the kernel's sources changed since it was taken."""
+    import hashlib
+    srcs = next((v for k, v in TRAFFIC_SOURCES.items() if key.startswith(k)), None)
+    if srcs is None or not os.path.exists(TRAFFIC_FILE):
+        return None
+    h = hashlib.sha256()
+    for f in srcs:
+        with open(os.path.join(CSRC, f), "rb") as fh:
+            h.update(fh.read())
+    cur = h.hexdigest()[:16]
+    with open(TRAFFIC_FILE) as fh:
+        for line in fh:
+            parts = line.split()
+            if len(parts) == 6 and parts[0] == key and not line.startswith("#"):
+                return float(parts[5]) if parts[2] == cur else None
+    return None
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -250,6 +278,8 @@ def main():
                                      "frac": fl / (tot / c / 1e3) / FP64_PEAK, "traffic": None,
                                      "avg_launch_ms": tot / c,
                                      "algorithmic": "2*d fp64 flops per (query, projection)"}
+    for k, v in roofs.items():
+        v["traffic"] = committed_traffic(k)
     dom = max(((k, v["avg_launch_ms"] * v.get("launches_per_step", 1.0)) for k, v in roofs.items()),
               key=lambda kv: kv[1])[0]
     roof = dict(roofs[dom])
