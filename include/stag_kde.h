@@ -197,7 +197,9 @@ stag_status stag_lsh_index_shape(const stag_lsh_index* idx, stag_lsh_shape* out)
 stag_status stag_lsh_index_segment(const stag_lsh_index* idx, int32_t t, int32_t i, int64_t* count,
                                    int32_t* members_host, uint64_t* keys_host, hipStream_t stream);
 
-/* Waits for the device and frees the index (NULL is ignored). */
+/* Waits for the device and releases the index (NULL is ignored).  Its device
+ * memory goes back to a per-device cache of the library, reused by later
+ * indexes and returned to the system at process exit. */
 void stag_lsh_index_destroy(stag_lsh_index* idx);
 
 /* create + query + destroy. */
