@@ -63,10 +63,64 @@ def cpu_baseline(X, Q, a, budget_s: float):
         oracle.kde_exact(X, Q[done:done + chunk], a, nthreads=threads)
         t_total += time.perf_counter() - t0
         done += min(chunk, Q.shape[0] - done)
+    # single-thread figure on a short sample
+    done1, t1 = 0, 0.0
+    while t1 < min(3.0, budget_s / 4) and done1 < Q.shape[0]:
+        t0 = time.perf_counter()
+        oracle.kde_exact(X, Q[done1:done1 + 8], a, nthreads=1)
+        t1 += time.perf_counter() - t0
+        done1 += min(8, Q.shape[0] - done1)
     return {"value": X.shape[0] * done / t_total, "unit": "Gaussian kernel evals/s", "cores": threads,
-            "kind": "oracle",
+            "kind": "oracle", "value_1thread": X.shape[0] * done1 / t1,
             "sample": f"{done} of the {Q.shape[0]} queries against all {X.shape[0]} points, exact FP64 direct "
                       f"differences with compensated log-sum-exp, OpenMP over queries; {t_total:.1f} s"}
+
+
+def precision_config_run(stag, torch, dev, lib, buf, n_check: int = 64):
+    """Exact KDE at the precision-form configuration (n = 2e6, m = 2e5,
+    d = 128, 50-component mixture, a = 0.01): tile time, pairs/s and
+    matrix-core fraction per form, and the error against the FP64 oracle on
+    sampled queries next to the largest stated per-result bound."""
+    import numpy as np
+
+    import oracle
+    import synth
+    X, Q, info = synth.config_points(3)
+    n, m, d = X.shape[0], Q.shape[0], X.shape[1]
+    a = 0.01
+    rng = np.random.default_rng(2003)
+    idx = np.sort(rng.choice(m, size=n_check, replace=False))
+    ref = oracle.kde_exact(X, Q[idx], a)
+    Xd, Qd = torch.from_numpy(X).to(dev), torch.from_numpy(Q).to(dev)
+    del X, Q
+    S = torch.empty(m, dtype=torch.float64, device=dev)
+    B = torch.empty(m, dtype=torch.float64, device=dev)
+    out = {"workload": "exact KDE n=2000000 data, m=200000 queries, d=128, 50-component mixture "
+                       "(sigma U[0.5,2]), a=0.01", "checked_queries": n_check, "forms": {}}
+    for form in ["fp16_split", "bf16_split", "fp32"]:
+        stag.kde_exact(Xd, Qd, a, form=form, S_out=S)  # warm-up
+        torch.cuda.synchronize()
+        lib.stag_timing_report(buf, len(buf))
+        lib.stag_timing_enable(1)
+        reps = 3
+        for _ in range(reps):
+            stag.kde_exact(Xd, Qd, a, form=form, S_out=S, bound_out=B, return_bound=True)
+        torch.cuda.synchronize()
+        lib.stag_timing_enable(0)
+        lib.stag_timing_report(buf, len(buf))
+        t = parse_timing(buf.value.decode())
+        tk = TILE_KERNEL[form]
+        tile_ms = t[tk][1] / t[tk][0]
+        flops = 2.0 * d * n * m * PRODUCTS[form]
+        err = np.abs(S.cpu().numpy()[idx] - ref) / ref
+        out["forms"][form] = {"tile_ms": tile_ms, "pairs_per_s": n * m / (tile_ms / 1e3),
+                              "achieved_tflops": flops / (tile_ms / 1e3) / 1e12,
+                              "frac_of_peak": flops / (tile_ms / 1e3) / MFMA_PEAK[form],
+                              "max_rel_err_sampled": float(err.max()),
+                              "max_bound_sampled": float(B.cpu().numpy()[idx].max())}
+    del Xd, Qd, S, B
+    torch.cuda.empty_cache()
+    return out
 
 
 def serving_run(stag, torch, dev, n_requests: int, seconds_cap: float):
@@ -163,6 +217,8 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=400)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-precision-config", action="store_true",
+                    help="skip the n=2e6, m=2e5, d=128 exact-tile measurement")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="after the timed steps, one plain device copy of this many MiB (a reference for "
                          "hardware byte counters)")
@@ -240,6 +296,12 @@ def main():
     n_acc = int(st["n_acc"].sum().item())
     index.close()
 
+    # the LSH leg: effective rate (n*m per second of its kernels) beside the
+    # distance and kernel evaluations it actually performs
+    t_lsh = sum(v for k, v in per_step.items() if k.startswith("lsh_")) / 1e3
+    lsh_leg = {"kernel_ms_per_step": t_lsh * 1e3, "effective_evals_per_s": n * m / t_lsh,
+               "distance_evals_per_s": n_cand / t_lsh, "kernel_evals_per_s": n_acc / t_lsh}
+
     # rooflines of the kernels of the step
     tk = TILE_KERNEL[args.form]
     flops_tile = 2.0 * d * evals * PRODUCTS[args.form]
@@ -308,6 +370,7 @@ def main():
         "lsh_avg_rel_err_sampled": lsh_rel,
         "lsh_candidates_per_query": n_cand / m,
         "lsh_accepted_per_query": n_acc / m,
+        "lsh_leg": lsh_leg,
         "graph_edges": int(src.size), "graph_valid_edges": int((dst >= 0).sum()),
         "kernels_ms_per_step": per_step,
         "exact_kde_ms_per_step": sum(v for k, v in per_step.items() if k.startswith("kde_")) / 2.0,
@@ -338,6 +401,8 @@ def main():
         torch.cuda.synchronize()
         result["calib_copy_bytes"] = args.calib_copy_mb << 20
         del src_c, dst_c
+    if not args.no_precision_config:
+        result["precision_config"] = precision_config_run(stag, torch, dev, lib, buf)
     if not args.no_serve:
         result["serving"] = serving_run(stag, torch, dev, args.serve_requests, seconds_cap=30.0)
     if not args.no_cpu_baseline:
