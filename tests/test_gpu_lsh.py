@@ -153,3 +153,25 @@ def test_query_batch_independence(stag):
     assert torch.equal(S1, S3)
     assert torch.equal(S1[100:200], S2)
     idx.close()
+
+
+@pytest.mark.parametrize("d,k2", [(24, 6), (100, 6), (200, 4), (16, 40)])
+def test_query_paths_by_dimension_and_tables(stag, orc, d, k2):
+    """Bucket join at the register widths 32 (d = 24) and 128 (d = 100), and
+    the per-query walk for d > 128 and for more than 32 tables per level:
+    bit-exact counts and 1e-9 values against the oracle, ragged sizes."""
+    mix = synth.mixture(d, 6, 7100 + d, sigma=(0.5, 1.5), box=3.0)
+    X = synth.sample(mix, 1537, 7200 + d)
+    Q = np.concatenate([synth.sample(mix, 131, 7300 + d), X[:5]])
+    a = 0.08 / math.sqrt(d / 16)
+    announce(f"lsh query paths d={d} k2={k2} n=1537 m=136")
+    _compare(stag, orc, X, Q, a, seed=7400 + d, check_segments=False, k1=2, k2_constant=k2)
+
+
+def test_single_query_and_self_batch(stag, orc):
+    """m = 1 (one partially filled wave per bucket) and a batch of the data
+    points themselves."""
+    X, Q, _ = synth.config_points(1)
+    announce("lsh m=1 and Q = X")
+    _compare(stag, orc, X, Q[:1], 0.5, seed=3001, check_segments=False, k1=2)
+    _compare(stag, orc, X, X[:300], 0.5, seed=3001, check_segments=False, k1=2)
