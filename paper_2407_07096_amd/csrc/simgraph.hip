@@ -45,12 +45,18 @@ __device__ inline double scan64(double v) {
   return v;
 }
 
+// rest_i (chunk order) and a node-major copy of the chunk sums, so that a
+// draw reads its node's P sums from consecutive addresses.
 __global__ void row_rest(const double* __restrict__ partial, int P, int64_t m_pad, int64_t n,
-                         double* __restrict__ rest, double* __restrict__ deg) {
+                         double* __restrict__ rest, double* __restrict__ deg, double* __restrict__ chunk_t) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   double s = 0.0;
-  for (int p = 0; p < P; ++p) s += partial[(int64_t)p * m_pad + i];
+  for (int p = 0; p < P; ++p) {
+    const double v = partial[(int64_t)p * m_pad + i];
+    chunk_t[i * P + p] = v;
+    s += v;
+  }
   rest[i] = s;
   if (deg) deg[i] = 1.0 + s;
 }
@@ -86,7 +92,7 @@ __device__ inline int invert_level(int count, double target, Fetch&& fetch, doub
 // One wave per draw (node i, draw r).
 __global__ __launch_bounds__(256) void draw_exact(const float* __restrict__ X, int64_t n, int d, double a, int s,
                                                   uint64_t seed, int P, int64_t m_pad, int64_t ntile, int64_t tstride,
-                                                  const double* __restrict__ partial, const float* __restrict__ tp,
+                                                  const double* __restrict__ chunk_t, const float* __restrict__ tp,
                                                   const double* __restrict__ rest, int vec4, int64_t* __restrict__ src,
                                                   int64_t* __restrict__ dst, double* __restrict__ w) {
   const int lane = threadIdx.x & 63;
@@ -100,7 +106,7 @@ __global__ __launch_bounds__(256) void draw_exact(const float* __restrict__ X, i
   int64_t pick = -1;
   if (tot > 0.0) {
     double resid = 0.0;
-    const int c = invert_level(P, u * tot, [&](int k) { return partial[(int64_t)k * m_pad + i]; }, &resid);
+    const int c = invert_level(P, u * tot, [&](int k) { return chunk_t[i * P + k]; }, &resid);
     if (c >= 0) {
       const int64_t t0 = (int64_t)c * kChunkTiles;
       const int nt = (int)((ntile - t0) < kChunkTiles ? (ntile - t0) : kChunkTiles);
@@ -165,7 +171,9 @@ stag_status sample_exact(const float* X, int64_t n, int d, double a, int form, i
   double* partial = nullptr;
   float* tp = nullptr;
   double* rest = nullptr;
+  double* chunk_t = nullptr;
   STAG_TRY(ws.alloc(&partial, (size_t)P * qo.rows_pad));
+  STAG_TRY(ws.alloc(&chunk_t, (size_t)P * n));
   STAG_TRY(ws.alloc(&tp, (size_t)tstride * qo.rows_pad));
   STAG_TRY(ws.alloc(&rest, (size_t)n));
   TileExtra ex;
@@ -174,12 +182,12 @@ stag_status sample_exact(const float* X, int64_t n, int d, double a, int form, i
   ex.ntile = tstride;
   STAG_TRY(launch_exact_tiles(xo, qo, partial, ex, st));
   hipLaunchKernelGGL(row_rest, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, st, partial, P, qo.rows_pad, n, rest,
-                     deg_out);
+                     deg_out, chunk_t);
   STAG_TRY(check_launch("row_rest"));
   const int vec4 = (d % 4 == 0) && (reinterpret_cast<uintptr_t>(X) % 16 == 0);
   ScopedTimer tm("simgraph_draw_exact", st);
   hipLaunchKernelGGL(draw_exact, dim3((unsigned)ceil_div(n * s, 4)), dim3(256), 0, st, X, n, d, a, s, seed, P,
-                     qo.rows_pad, ntile, tstride, partial, tp, rest, vec4, src, dst, w);
+                     qo.rows_pad, ntile, tstride, chunk_t, tp, rest, vec4, src, dst, w);
   return check_launch("draw_exact");
 }
 
