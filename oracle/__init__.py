@@ -55,6 +55,9 @@ def _load():
     lib.orc_kernel_row.argtypes = [f32p, C.c_int64, C.c_int32, C.c_double, C.c_int64, f64p]
     lib.orc_e2lsh_hash.restype = None
     lib.orc_e2lsh_hash.argtypes = [f32p, C.c_int64, C.c_int32, f32p, f64p, C.c_int32, C.c_int32, i32p, u64p, C.c_int32]
+    lib.orc_e2lsh_near_neighbours.restype = None
+    lib.orc_e2lsh_near_neighbours.argtypes = [f32p, C.c_int64, f32p, C.c_int64, C.c_int32, f32p, f64p, C.c_int32,
+                                              C.c_int32, C.POINTER(C.c_int64), i32p, C.c_int32]
     lib.orc_lsh_derive.restype = C.c_int32
     lib.orc_lsh_derive.argtypes = [C.c_int64, C.c_double, C.c_double, C.c_double, C.c_int32, C.c_double, C.c_int32,
                                    C.c_uint32, i32p, f64p, f64p, u64p, f64p, f64p]
@@ -145,6 +148,27 @@ def e2lsh_hash(X, G, b, K: int, L: int, nthreads: int = 0):
     _load().orc_e2lsh_hash(_p(X, C.c_float), n, d, _p(G, C.c_float), _p(b, C.c_double), K, L,
                            _p(codes, C.c_int32), _p(keys, C.c_uint64), int(nthreads))
     return codes, keys
+
+
+def e2lsh_near_neighbours(X, Q, G, b, K: int, L: int, nthreads: int = 0):
+    """(offsets [m+1] int64, idx int32): the points colliding with each query
+    in some table, table by table, ascending within a table, each once."""
+    X, Q, G = _f32(X), _f32(Q), _f32(G)
+    b = np.ascontiguousarray(b, dtype=np.float64)
+    n, d = X.shape
+    m = Q.shape[0]
+    assert Q.shape[1] == d and G.shape == (L * K, d) and b.shape == (L * K,)
+    counts = np.empty(m, dtype=np.int64)
+    lib = _load()
+    lib.orc_e2lsh_near_neighbours(_p(X, C.c_float), n, _p(Q, C.c_float), m, d, _p(G, C.c_float),
+                                  _p(b, C.c_double), K, L, _p(counts, C.c_int64), None, int(nthreads))
+    off = np.zeros(m + 1, dtype=np.int64)
+    np.cumsum(counts, out=off[1:])
+    idx = np.empty(int(off[-1]), dtype=np.int32)
+    lib.orc_e2lsh_near_neighbours(_p(X, C.c_float), n, _p(Q, C.c_float), m, d, _p(G, C.c_float),
+                                  _p(b, C.c_double), K, L, _p(counts, C.c_int64), _p(idx, C.c_int32),
+                                  int(nthreads))
+    return off, idx
 
 
 def lsh_derive(n, a, eps=0.5, min_mu=0.0, k1=0, k2_constant=0.0, p_offset=0, flags=0):

@@ -20,6 +20,9 @@
 //                             Sec. "Boosting the Probability".
 //   orc_e2lsh_hash          - Sec. "Random Projection": h(x) = floor((<x,g>+b)/4),
 //                             K concatenated hashes per table, L tables.
+//   orc_e2lsh_near_neighbours
+//                           - the E2LSH class's get_near_neighbours: points that
+//                             share a bucket with the query in some table.
 //   orc_lsh_derive, orc_lsh_kde
 //                           - Sec. "The CKNS Algorithm": levels L_i, log n
 //                             subsamples with probability 2^-i, one LSH table
@@ -274,6 +277,43 @@ void orc_e2lsh_hash(const float* X, int64_t n, int32_t d, const float* G, const 
       }
       if (keys_out) keys_out[(size_t)i * L + l] = bucket_key(l, codes.data(), K);
     }
+  }
+}
+
+// Near neighbours under an E2LSH table of L tables with K codes each (Sec.
+// "Random Projection", "Boosting the Probability"; the get_near_neighbours
+// method of the E2LSH class): the points whose key equals the query's in at
+// least one table.  The paper returns them as a set; the listing order taken
+// here is table by table (0 first), ascending point index within a table,
+// each point only in the first table where it collides.  counts_out [m];
+// idx_out, if not NULL, receives the lists back to back (sum of counts).
+void orc_e2lsh_near_neighbours(const float* X, int64_t n, const float* Q, int64_t m, int32_t d, const float* G,
+                               const double* b, int32_t K, int32_t L, int64_t* counts_out, int32_t* idx_out,
+                               int32_t nthreads) {
+  if (nthreads <= 0) nthreads = omp_get_max_threads();
+  std::vector<uint64_t> kx((size_t)n * L), kq((size_t)m * L);
+  orc_e2lsh_hash(X, n, d, G, b, K, L, nullptr, kx.data(), nthreads);
+  orc_e2lsh_hash(Q, m, d, G, b, K, L, nullptr, kq.data(), nthreads);
+  auto first_table = [&](int64_t q, int64_t j) {  // first colliding table, or L
+    for (int32_t l = 0; l < L; ++l)
+      if (kx[(size_t)j * L + l] == kq[(size_t)q * L + l]) return l;
+    return L;
+  };
+#pragma omp parallel for schedule(static) num_threads(nthreads)
+  for (int64_t q = 0; q < m; ++q) {
+    int64_t c = 0;
+    for (int64_t j = 0; j < n; ++j) c += first_table(q, j) < L ? 1 : 0;
+    counts_out[q] = c;
+  }
+  if (!idx_out) return;
+  std::vector<int64_t> off((size_t)m + 1, 0);
+  for (int64_t q = 0; q < m; ++q) off[(size_t)q + 1] = off[(size_t)q] + counts_out[q];
+#pragma omp parallel for schedule(static) num_threads(nthreads)
+  for (int64_t q = 0; q < m; ++q) {
+    int64_t w = off[(size_t)q];
+    for (int32_t l = 0; l < L; ++l)
+      for (int64_t j = 0; j < n; ++j)
+        if (first_table(q, j) == l) idx_out[w++] = (int32_t)j;
   }
 }
 
