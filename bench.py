@@ -123,6 +123,38 @@ def precision_config_run(stag, torch, dev, lib, buf, n_check: int = 64):
     return out
 
 
+def e2lsh_table_run(stag, torch, dev, lib, buf, Xd, Qd, K: int = 6, L: int = 50):
+    """E2LSH table (K = 6, L = 50, the paper's example) over the step's data:
+    build and near-neighbour listing of all queries, with kernel times."""
+    import synth
+    n, d = Xd.shape
+    m = Qd.shape[0]
+    G, b = synth.e2lsh_randomness(K * L, d, 3002)
+    Gd, bd = torch.from_numpy(G).to(dev), torch.from_numpy(b).to(dev)
+    t = stag.E2LSHTable(Xd, Gd, bd, K, L)  # warm-up
+    t.near_neighbours(Qd)
+    t.close()
+    torch.cuda.synchronize()
+    lib.stag_timing_report(buf, len(buf))
+    lib.stag_timing_enable(1)
+    t0 = time.perf_counter()
+    t = stag.E2LSHTable(Xd, Gd, bd, K, L)
+    t1 = time.perf_counter()
+    off, idx = t.near_neighbours(Qd)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    lib.stag_timing_enable(0)
+    lib.stag_timing_report(buf, len(buf))
+    t.close()
+    tm = parse_timing(buf.value.decode())
+    total = int(off[-1].item())
+    ms = {k: v[1] for k, v in tm.items()}
+    return {"workload": f"E2LSH table K={K}, L={L} over n={n} points, d={d}; near neighbours of m={m} queries",
+            "build_wall_ms": (t1 - t0) * 1e3, "query_wall_ms": (t2 - t1) * 1e3,
+            "kernels_ms": ms, "neighbours_per_query": total / m,
+            "queries_per_s": m / (t2 - t1), "listed_per_s": total / (t2 - t1)}
+
+
 def serving_run(stag, torch, dev, n_requests: int, seconds_cap: float):
     """Poisson stream of requests of log-uniform size (1..65536) against four
     resident data sets; returns latency percentiles and throughput."""
@@ -401,6 +433,7 @@ def main():
         torch.cuda.synchronize()
         result["calib_copy_bytes"] = args.calib_copy_mb << 20
         del src_c, dst_c
+    result["e2lsh_table"] = e2lsh_table_run(stag, torch, dev, lib, buf, Xd, Qd)
     if not args.no_precision_config:
         result["precision_config"] = precision_config_run(stag, torch, dev, lib, buf)
     if not args.no_serve:

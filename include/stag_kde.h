@@ -122,6 +122,38 @@ stag_status stag_kde_exact(const float* X, int64_t n, const float* Q, int64_t m,
 stag_status stag_e2lsh_hash(const float* X, int64_t n, int32_t d, const float* G, const double* b, int32_t K,
                             int32_t L, int32_t* codes_out, uint64_t* keys_out, hipStream_t stream);
 
+/* E2LSH hash table (the E2LSH class: Sec. "Random Projection", "Boosting the
+ * Probability"): the keys of the n points of X under L tables of K
+ * concatenated hashes, bucketed per table.  Approximate near neighbours of a
+ * query (get_near_neighbours) are the points that share its bucket in at
+ * least one table.
+ *   X [n][d] fp32 device; G [L*K][d] fp32 and b [L*K] f64 device as for
+ *   stag_e2lsh_hash (codes and keys are identical to it).  The table copies
+ *   what it needs (not X); the caller may free X, G, b after the call.
+ * Limits: 1 <= n <= 2^30, 1 <= d <= 4096, 1 <= K, L <= 64, n*d < 2^33.
+ * Synchronises `stream` once (the build reads host-side layout data).
+ * Errors: STAG_E_INVAL for bad arguments (before any launch), STAG_E_NOMEM. */
+typedef struct stag_e2lsh_table stag_e2lsh_table;
+stag_status stag_e2lsh_table_create(const float* X, int64_t n, int32_t d, const float* G, const double* b, int32_t K,
+                                    int32_t L, stag_e2lsh_table** out, hipStream_t stream);
+
+/* Near-neighbour counts of the m rows of Q [m][d] (fp32 device):
+ * offsets_out [m+1] int64 device receives the exclusive prefix sum of the
+ * counts (offsets_out[m] = total).  A point is counted once per query. */
+stag_status stag_e2lsh_table_count(const stag_e2lsh_table* t, const float* Q, int64_t m, int64_t* offsets_out,
+                                   hipStream_t stream);
+
+/* The lists themselves: idx_out [offsets[m]] int32 device (offsets from
+ * stag_e2lsh_table_count for the same Q).  Query q's list is at
+ * idx_out[offsets[q] .. offsets[q+1]): table by table (table 0 first),
+ * ascending point index within a bucket, each point in the first table where
+ * it collides with q.  Deterministic. */
+stag_status stag_e2lsh_table_neighbours(const stag_e2lsh_table* t, const float* Q, int64_t m, const int64_t* offsets,
+                                        int32_t* idx_out, hipStream_t stream);
+
+/* Waits for the device and frees the table (NULL is ignored). */
+void stag_e2lsh_table_destroy(stag_e2lsh_table* t);
+
 /* ------------------------------------------------------------------------
  * CKNS approximate kernel density (Sec. "The CKNS Algorithm"; the three
  * CKNSGaussianKDE constructors map onto stag_lsh_params).

@@ -104,6 +104,14 @@ def load():
     lib.stag_server_destroy.argtypes = [vp]
     lib.stag_kde_lsh.restype = C.c_int
     lib.stag_kde_lsh.argtypes = [vp, i64, vp, i64, i32, f64, f64, pp, vp, vp]
+    lib.stag_e2lsh_table_create.restype = C.c_int
+    lib.stag_e2lsh_table_create.argtypes = [vp, i64, i32, vp, vp, i32, i32, C.POINTER(vp), vp]
+    lib.stag_e2lsh_table_count.restype = C.c_int
+    lib.stag_e2lsh_table_count.argtypes = [vp, vp, i64, vp, vp]
+    lib.stag_e2lsh_table_neighbours.restype = C.c_int
+    lib.stag_e2lsh_table_neighbours.argtypes = [vp, vp, i64, vp, vp, vp]
+    lib.stag_e2lsh_table_destroy.restype = None
+    lib.stag_e2lsh_table_destroy.argtypes = [vp]
     _lib = lib
     return lib
 
@@ -263,6 +271,54 @@ class LshIndex:
     def close(self):
         if getattr(self, "_h", None):
             load().stag_lsh_index_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class E2LSHTable:
+    """E2LSH hash table over device points X (fp32 [n][d]) with projections
+    G (fp32 [L*K][d]) and offsets b (f64 [L*K]); see include/stag_kde.h."""
+
+    def __init__(self, X, G, b, K: int, L: int):
+        torch = _torch()
+        _need(X, torch.float32, 2, "X")
+        _need(G, torch.float32, 2, "G")
+        _need(b, torch.float64, 1, "b")
+        if G.shape != (L * K, X.shape[1]) or b.shape[0] != L * K:
+            raise ValueError("G must be [L*K][d] and b [L*K]")
+        h = C.c_void_p()
+        self.device = X.device
+        check(load().stag_e2lsh_table_create(_ptr(X), X.shape[0], X.shape[1], _ptr(G), _ptr(b), int(K), int(L),
+                                             C.byref(h), _stream_handle(X.device)), "stag_e2lsh_table_create")
+        self._h = h
+        self.d = X.shape[1]
+
+    def near_neighbours(self, Q):
+        """(offsets int64 [m+1], idx int32 [offsets[m]]): query q's neighbours
+        are idx[offsets[q]:offsets[q+1]]."""
+        torch = _torch()
+        _need(Q, torch.float32, 2, "Q")
+        if Q.shape[1] != self.d:
+            raise ValueError("Q has the wrong number of columns")
+        m = Q.shape[0]
+        off = torch.empty(m + 1, dtype=torch.int64, device=Q.device)
+        check(load().stag_e2lsh_table_count(self._h, _ptr(Q), m, _ptr(off), _stream_handle(Q.device)),
+              "stag_e2lsh_table_count")
+        total = int(off[m].item())
+        idx = torch.empty(max(total, 1), dtype=torch.int32, device=Q.device)
+        if total > 0:
+            check(load().stag_e2lsh_table_neighbours(self._h, _ptr(Q), m, _ptr(off), _ptr(idx),
+                                                     _stream_handle(Q.device)), "stag_e2lsh_table_neighbours")
+        return off, idx[:total]
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().stag_e2lsh_table_destroy(self._h)
             self._h = None
 
     def __del__(self):

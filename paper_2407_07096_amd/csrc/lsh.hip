@@ -968,6 +968,89 @@ __global__ void zero_u32(uint32_t* p, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = 0;
 }
 
+// ---------------------------------------------------------------------------
+// E2LSH table with near-neighbour listing (the E2LSH class of Sec. "Random
+// Projection" / "Boosting the Probability" and its get_near_neighbours): one
+// segment holding all n points, L open-addressing tables, CSR members
+// ascending within a bucket (built by build_tables).  A query lists the points
+// that collide with it in some table: table by table, ascending within a
+// bucket, each point in the first table where it collides.
+// ---------------------------------------------------------------------------
+// One wave per query.  LIST = false: counts[q]; LIST = true: the list at
+// idx_out + offsets[q].
+template <bool LIST>
+__global__ __launch_bounds__(256) void nn_walk(const uint64_t* __restrict__ qkeys, int64_t m, int L, int64_t n,
+                                               uint32_t cap, const uint64_t* __restrict__ tab_key,
+                                               const uint32_t* __restrict__ tab_start,
+                                               const uint32_t* __restrict__ tab_cnt, const int32_t* __restrict__ csr,
+                                               const uint64_t* __restrict__ mkeys, uint32_t* __restrict__ counts,
+                                               const uint64_t* __restrict__ offsets, int32_t* __restrict__ idx_out) {
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t q = (int64_t)blockIdx.x * 4 + wave;
+  if (q >= m) return;
+  __shared__ uint64_t sqk[4][64];
+  __shared__ int64_t sbase[4][64];
+  __shared__ uint32_t spre[4][64];
+  uint32_t c = 0;
+  int64_t base = 0;
+  if (lane < L) {
+    const uint64_t key = qkeys[q * L + lane];
+    sqk[wave][lane] = key;
+    const int64_t tb = (int64_t)lane * cap;
+    uint32_t sl = (uint32_t)key & (cap - 1);
+    while (true) {
+      const uint64_t v = tab_key[tb + sl];
+      if (v == key) {
+        c = tab_cnt[tb + sl];
+        base = (int64_t)lane * n + tab_start[tb + sl];
+        break;
+      }
+      if (v == kEmpty) break;
+      sl = (sl + 1) & (cap - 1);
+    }
+  }
+  uint32_t incl = c;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t y = __shfl_up(incl, o);
+    if (lane >= o) incl += y;
+  }
+  const uint32_t total = __shfl(incl, 63);
+  if (lane < L) {
+    spre[wave][lane] = incl - c;
+    sbase[wave][lane] = base;
+  }
+  __builtin_amdgcn_wave_barrier();
+  int64_t kept = 0;
+  const int64_t out0 = LIST ? (int64_t)offsets[q] : 0;
+  for (uint32_t k0 = 0; k0 < total; k0 += 64) {
+    const uint32_t k = k0 + lane;
+    bool keep = false;
+    int32_t j = 0;
+    if (k < total) {
+      int lo = 0, hi = L - 1;  // last table whose prefix is <= k
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (spre[wave][mid] <= k) lo = mid;
+        else hi = mid - 1;
+      }
+      j = csr[sbase[wave][lo] + (k - spre[wave][lo])];
+      const uint64_t* mk = mkeys + (int64_t)j * L;
+      bool seen = false;
+      for (int l2 = 0; l2 < lo; ++l2) seen |= mk[l2] == sqk[wave][l2];
+      keep = !seen;
+    }
+    const uint64_t km = __ballot(keep);
+    if constexpr (LIST) {
+      const uint32_t pos = __builtin_amdgcn_mbcnt_hi((uint32_t)(km >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)km, 0u));
+      if (keep) idx_out[out0 + kept + pos] = j;
+    }
+    kept += __popcll(km);
+  }
+  if (!LIST && lane == 0) counts[q] = (uint32_t)kept;
+}
+
 int ceil_log2_i64(int64_t n) {
   int J = 0;
   while (((int64_t)1 << J) < n) ++J;
@@ -1096,6 +1179,23 @@ struct stag_lsh_index {
   double* cheb = nullptr;
   std::vector<double> h_cheb;
   uint64_t* thr = nullptr;
+};
+
+struct stag_e2lsh_table {
+  int64_t n = 0;
+  int d = 0, K = 0, L = 0, dg = 0;
+  uint32_t cap = 0;
+  int device = 0;
+  std::vector<void*> owned;  // stream-ordered pool blocks
+  double* G8 = nullptr;
+  double* b = nullptr;
+  uint64_t* mkeys = nullptr;
+  uint64_t* tab_key = nullptr;
+  uint32_t* tab_start = nullptr;
+  uint32_t* tab_cnt = nullptr;
+  int32_t* csr = nullptr;
+  std::vector<uint64_t> h_off;  // host copies of the one-segment layout
+  std::vector<uint32_t> h_cap;
 };
 
 namespace stag {
@@ -1591,6 +1691,128 @@ stag_status stag_kde_lsh(const float* X, int64_t n, const float* Q, int64_t m, i
   (void)hipStreamSynchronize(stream);
   stag_lsh_index_destroy(idx);
   return st;
+}
+
+namespace {
+void e2lsh_table_free(stag_e2lsh_table* t) {
+  for (void* p : t->owned) (void)hipFreeAsync(p, nullptr);
+  (void)hipStreamSynchronize(nullptr);
+  delete t;
+}
+
+stag_status e2lsh_query_keys(const stag_e2lsh_table* t, const float* Q, int64_t m, Workspace& ws, uint64_t** qk,
+                             hipStream_t st) {
+  STAG_TRY(ws.alloc(qk, (size_t)m * t->L));
+  return e2lsh_launch(Q, m, t->d, t->G8, t->dg, t->b, t->K, t->L, nullptr, *qk, st);
+}
+}  // namespace
+
+stag_status stag_e2lsh_table_create(const float* X, int64_t n, int32_t d, const float* G, const double* b, int32_t K,
+                                    int32_t L, stag_e2lsh_table** out, hipStream_t stream) {
+  if (!out) return fail(STAG_E_INVAL, "stag_e2lsh_table_create: out is NULL");
+  *out = nullptr;
+  if (!X || !G || !b) return fail(STAG_E_INVAL, "stag_e2lsh_table_create: NULL input pointer");
+  if (n < 1 || n > 1073741824LL || d < 1 || d > 4096)
+    return fail(STAG_E_INVAL, "stag_e2lsh_table_create: need 1 <= n <= 2^30 and 1 <= d <= 4096");
+  if (K < 1 || K > 64 || L < 1 || L > 64) return fail(STAG_E_INVAL, "stag_e2lsh_table_create: need 1 <= K, L <= 64");
+  if ((double)n * d >= 2147483648.0 * 4.0) return fail(STAG_E_INVAL, "stag_e2lsh_table_create: n*d too large");
+  clear_error();
+  stag_e2lsh_table* t = new (std::nothrow) stag_e2lsh_table();
+  if (!t) return fail(STAG_E_NOMEM, "stag_e2lsh_table_create: host allocation failed");
+  t->n = n;
+  t->d = d;
+  t->K = K;
+  t->L = L;
+  (void)hipGetDevice(&t->device);
+  uint32_t cap = 2;
+  while ((int64_t)cap < 2 * n) cap <<= 1;
+  t->cap = cap;
+  t->h_off = {0, (uint64_t)n, 0, (uint64_t)cap * L};
+  t->h_cap = {cap};
+  stag_status st = STAG_OK;
+  {
+    Workspace ws(stream);
+    Workspace tmp(stream);
+    auto body = [&]() -> stag_status {
+      uint64_t* seg_off = nullptr;
+      uint64_t* tso = nullptr;
+      uint32_t* segcap = nullptr;
+      uint32_t* cursor = nullptr;
+      STAG_TRY(e2lsh_regroup(G, K, L, d, ws, &t->G8, &t->dg, stream));
+      STAG_TRY(ws.alloc(&t->b, (size_t)K * L));
+      STAG_HIP(hipMemcpyAsync(t->b, b, sizeof(double) * K * L, hipMemcpyDeviceToDevice, stream));
+      STAG_TRY(ws.alloc(&t->mkeys, (size_t)n * L));
+      STAG_TRY(e2lsh_launch(X, n, d, t->G8, t->dg, t->b, K, L, nullptr, t->mkeys, stream));
+      STAG_TRY(ws.alloc(&t->tab_key, (size_t)cap * L));
+      STAG_TRY(ws.alloc(&t->tab_start, (size_t)cap * L));
+      STAG_TRY(ws.alloc(&t->tab_cnt, (size_t)cap * L));
+      STAG_TRY(ws.alloc(&t->csr, (size_t)n * L));
+      STAG_TRY(tmp.alloc(&seg_off, 2));
+      STAG_TRY(tmp.alloc(&tso, 2));
+      STAG_TRY(tmp.alloc(&segcap, 1));
+      STAG_TRY(tmp.alloc(&cursor, (size_t)cap * L));
+      STAG_HIP(hipMemcpyAsync(seg_off, t->h_off.data(), sizeof(uint64_t) * 2, hipMemcpyHostToDevice, stream));
+      STAG_HIP(hipMemcpyAsync(tso, t->h_off.data() + 2, sizeof(uint64_t) * 2, hipMemcpyHostToDevice, stream));
+      STAG_HIP(hipMemcpyAsync(segcap, t->h_cap.data(), sizeof(uint32_t), hipMemcpyHostToDevice, stream));
+      ScopedTimer tm("e2lsh_table_build", stream);
+      hipLaunchKernelGGL(build_tables, dim3((unsigned)L), dim3(256), 0, stream, L, seg_off, tso, segcap, t->mkeys,
+                         t->tab_key, t->tab_start, t->tab_cnt, cursor, t->csr);
+      return check_launch("build_tables");
+    };
+    st = body();
+    t->owned = ws.release();
+    (void)hipStreamSynchronize(stream);  // the host copies feed the build
+  }
+  if (st != STAG_OK) {
+    e2lsh_table_free(t);
+    return st;
+  }
+  *out = t;
+  return STAG_OK;
+}
+
+stag_status stag_e2lsh_table_count(const stag_e2lsh_table* t, const float* Q, int64_t m, int64_t* offsets_out,
+                                   hipStream_t stream) {
+  if (!t || !Q || !offsets_out) return fail(STAG_E_INVAL, "stag_e2lsh_table_count: NULL argument");
+  if (m < 1 || m > 2147483647LL) return fail(STAG_E_INVAL, "stag_e2lsh_table_count: need 1 <= m < 2^31");
+  clear_error();
+  Workspace ws(stream);
+  uint64_t* qk = nullptr;
+  uint32_t* cnt = nullptr;
+  STAG_TRY(e2lsh_query_keys(t, Q, m, ws, &qk, stream));
+  STAG_TRY(ws.alloc(&cnt, (size_t)m));
+  {
+    ScopedTimer tm("e2lsh_table_query", stream);
+    hipLaunchKernelGGL(nn_walk<false>, dim3((unsigned)ceil_div(m, 4)), dim3(256), 0, stream, qk, m, t->L, t->n, t->cap,
+                       t->tab_key, t->tab_start, t->tab_cnt, t->csr, t->mkeys, cnt, nullptr, nullptr);
+    STAG_TRY(check_launch("nn_walk"));
+  }
+  return exclusive_scan_u32(cnt, reinterpret_cast<uint64_t*>(offsets_out), m, ws, stream);
+}
+
+stag_status stag_e2lsh_table_neighbours(const stag_e2lsh_table* t, const float* Q, int64_t m, const int64_t* offsets,
+                                        int32_t* idx_out, hipStream_t stream) {
+  if (!t || !Q || !offsets || !idx_out) return fail(STAG_E_INVAL, "stag_e2lsh_table_neighbours: NULL argument");
+  if (m < 1 || m > 2147483647LL) return fail(STAG_E_INVAL, "stag_e2lsh_table_neighbours: need 1 <= m < 2^31");
+  clear_error();
+  Workspace ws(stream);
+  uint64_t* qk = nullptr;
+  STAG_TRY(e2lsh_query_keys(t, Q, m, ws, &qk, stream));
+  ScopedTimer tm("e2lsh_table_query", stream);
+  hipLaunchKernelGGL(nn_walk<true>, dim3((unsigned)ceil_div(m, 4)), dim3(256), 0, stream, qk, m, t->L, t->n, t->cap,
+                     t->tab_key, t->tab_start, t->tab_cnt, t->csr, t->mkeys, nullptr,
+                     reinterpret_cast<const uint64_t*>(offsets), idx_out);
+  return check_launch("nn_walk");
+}
+
+void stag_e2lsh_table_destroy(stag_e2lsh_table* t) {
+  if (!t) return;
+  const int dev = t->device;
+  int cur = dev;
+  if (hipGetDevice(&cur) == hipSuccess && cur != dev) (void)hipSetDevice(dev);
+  (void)hipDeviceSynchronize();
+  e2lsh_table_free(t);
+  if (cur != dev) (void)hipSetDevice(cur);
 }
 
 }  // extern "C"

@@ -49,6 +49,18 @@ def test_invalid_arguments_rejected_before_launch():
     assert st == _lib.STAG_E_INVAL
     st = lib.stag_e2lsh_hash(fake, 10, 4, fake, fake, 2, 3, null, null, null)
     assert st == _lib.STAG_E_INVAL
+    h = C.c_void_p(0)
+    st = lib.stag_e2lsh_table_create(fake, 10, 4, fake, fake, 2, 65, C.byref(h), null)
+    assert st == _lib.STAG_E_INVAL and h.value is None
+    st = lib.stag_e2lsh_table_create(fake, 0, 4, fake, fake, 2, 3, C.byref(h), null)
+    assert st == _lib.STAG_E_INVAL and h.value is None
+    st = lib.stag_e2lsh_table_create(null, 10, 4, fake, fake, 2, 3, C.byref(h), null)
+    assert st == _lib.STAG_E_INVAL and "NULL" in stag.last_error()
+    st = lib.stag_e2lsh_table_count(null, fake, 3, fake, null)
+    assert st == _lib.STAG_E_INVAL
+    st = lib.stag_e2lsh_table_neighbours(fake, fake, 0, fake, fake, null)
+    assert st == _lib.STAG_E_INVAL
+    lib.stag_e2lsh_table_destroy(null)
 
 
 @pytest.mark.parametrize("n", [1, 7, 1000, 100_000, 2_000_000])
