@@ -57,8 +57,8 @@ def load():
     if _lib is not None:
         return _lib
     if not os.path.exists(LIB_PATH):
-        raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2407_07096_amd/build.py "
-                           "(__graft_entry__.build()); there is no CPU fallback")
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2407_07096_amd/build.py; "
+                           "there is no CPU fallback")
     lib = C.CDLL(LIB_PATH)
     vp, i64, i32, u32, f64 = C.c_void_p, C.c_int64, C.c_int32, C.c_uint32, C.c_double
     lib.stag_last_error.restype = C.c_char_p

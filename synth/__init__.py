@@ -96,8 +96,17 @@ def e2lsh_randomness(n_proj: int, d: int, seed: int):
 # --------------------------------------------------------------------------
 
 def config_points(cfg: int, n: int | None = None, m: int | None = None, queries_from_data: bool = False):
-    """Data X and queries Q for workload ``cfg`` (1..4) at optional reduced
-    sizes.  Returns (X, Q, info dict)."""
+    """Data X and queries Q of one of four synthetic workloads, at optional
+    reduced sizes.  Returns (X, Q, info dict).
+
+      1: n = m = 1,000, d = 10, 5-component isotropic Gaussian mixture,
+         means U[-5,5]^d, sigma = 1 (correctness size);
+      2: n = m = 100,000, d = 64, 20 components, sigma U[0.5,2];
+      3: n = 2,000,000, m = 200,000, d = 128, 50 components, sigma U[0.5,2]
+         (the precision-form workload);
+      4: n = 70,000, d = 784, entries 0 with probability 0.8 else U[0,1]
+         (queries are the data; edge sampling).
+    Queries are fresh draws from the same mixture (or rows of X)."""
     if cfg == 1:
         d, k, sig, n0, m0 = 10, 5, 1.0, 1000, 1000
     elif cfg == 2:
