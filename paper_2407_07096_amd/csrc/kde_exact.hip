@@ -236,9 +236,9 @@ __global__ __launch_bounds__(256, 2) void tile_f32(const float* __restrict__ Xp,
   constexpr int F4_ROW = DP / 4;
   constexpr int NV = kTileRows * F4_ROW;
   constexpr int NLD = (NV + 255) / 256;
-  constexpr int NMMA = H + 1;
+  constexpr int NMMA = H;
   __shared__ __attribute__((aligned(16))) float tile[2][kTileRows * LD];
-  __shared__ float tbeta[2][kTileRows];
+  __shared__ __attribute__((aligned(16))) float tbeta[2][kTileRows];
 
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, r32 = lane & 31, h = lane >> 5;
   const int qtile = blockIdx.x % n_qtiles;
@@ -255,7 +255,7 @@ __global__ __launch_bounds__(256, 2) void tile_f32(const float* __restrict__ Xp,
       bq[4 * s] = v.x; bq[4 * s + 1] = v.y; bq[4 * s + 2] = v.z; bq[4 * s + 3] = v.w;
     }
   }
-  const float baug = h == 0 ? alpha[qi] : 1.0f;
+  const float aq = alpha[qi];
 
   const int64_t row0 = (int64_t)chunk * kChunkRows;
   const int64_t rem = (n_pad - row0) / kTileRows;
@@ -291,7 +291,16 @@ __global__ __launch_bounds__(256, 2) void tile_f32(const float* __restrict__ Xp,
       acc += (double)tile_epilogue<false>(cdone, 0, 0, r32, h, qi, ex);
     }
     const float* arow = &tile[buf][r32 * LD + h * H];
-    f32x16 c = {0};
+    // the accumulators start from the offsets alpha_q + beta_x of their pairs
+    f32x16 c;
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+      const f32x4 bv = *reinterpret_cast<const f32x4*>(&tbeta[buf][8 * g + 4 * h]);
+      c[4 * g] = aq + bv.x;
+      c[4 * g + 1] = aq + bv.y;
+      c[4 * g + 2] = aq + bv.z;
+      c[4 * g + 3] = aq + bv.w;
+    }
 #pragma unroll
     for (int s = 0; s < H; s += 4) {
       const f32x4 a4 = *reinterpret_cast<const f32x4*>(arow + s);
@@ -300,8 +309,6 @@ __global__ __launch_bounds__(256, 2) void tile_f32(const float* __restrict__ Xp,
       c = __builtin_amdgcn_mfma_f32_32x32x2f32(a4.z, bq[s + 2], c, 0, 0, 0);
       c = __builtin_amdgcn_mfma_f32_32x32x2f32(a4.w, bq[s + 3], c, 0, 0, 0);
     }
-    const float tb = tbeta[buf][r32];
-    c = __builtin_amdgcn_mfma_f32_32x32x2f32(h == 0 ? 1.0f : tb, baug, c, 0, 0, 0);
     cnew = c;
     lstore(buf ^ 1);
     gload(min(t + 2, ntiles - 1));
@@ -354,8 +361,8 @@ __device__ inline f32x16 mma16_bf16(u16x8 a, u16x8 b, f32x16 c) {
 template <int FORM, int DP, bool EXTRA>
 __global__ __launch_bounds__(256, 2) void tile_split(
     const unsigned short* __restrict__ X0, const unsigned short* __restrict__ X1,
-    const unsigned short* __restrict__ X2, const u16x8* __restrict__ Xaug, const unsigned short* __restrict__ Q0,
-    const unsigned short* __restrict__ Q1, const unsigned short* __restrict__ Q2, const u16x8* __restrict__ Qaug,
+    const unsigned short* __restrict__ X2, const float* __restrict__ Xoff, const unsigned short* __restrict__ Q0,
+    const unsigned short* __restrict__ Q1, const unsigned short* __restrict__ Q2, const float* __restrict__ Qoff,
     int64_t n_pad, int n_qtiles, int64_t m_pad, double* __restrict__ partial, TileExtra ex) {
   constexpr int NP = FORM == STAG_FORM_BF16_SPLIT3 ? 3 : 2;
   constexpr int KS = DP / 16;
@@ -363,9 +370,9 @@ __global__ __launch_bounds__(256, 2) void tile_split(
   constexpr int V_ROW = DP / 8;  // 16-byte vectors per row
   constexpr int NV = kTileRows * V_ROW;
   constexpr int NLD = (NV + 255) / 256;
-  constexpr int NMMA = KS * (NP == 3 ? 6 : 3) + 1;
+  constexpr int NMMA = KS * (NP == 3 ? 6 : 3);
   __shared__ __attribute__((aligned(16))) unsigned short tile[2][NP][kTileRows * LD];
-  __shared__ u16x8 taug[2][kTileRows];
+  __shared__ __attribute__((aligned(16))) float tbeta[2][kTileRows];
 
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, r32 = lane & 31, h = lane >> 5;
   const int qtile = blockIdx.x % n_qtiles;
@@ -381,16 +388,14 @@ __global__ __launch_bounds__(256, 2) void tile_split(
 #pragma unroll
     for (int s = 0; s < KS; ++s)
       bq[p][s] = *reinterpret_cast<const u16x8*>(Qp[p] + qi * DP + s * 16 + h * 8);
-  const unsigned short hm = h == 0 ? 0xFFFF : 0;
-  const u16x8 hmask = {hm, hm, hm, hm, hm, hm, hm, hm};
-  const u16x8 baug = Qaug[qi] & hmask;
+  const float alpha = Qoff[qi];
 
   const int64_t row0 = (int64_t)chunk * kChunkRows;
   const int64_t rem = (n_pad - row0) / kTileRows;
   const int ntiles = (int)(rem < kChunkRows / kTileRows ? rem : kChunkRows / kTileRows);
 
   u16x8 stage[NP][NLD];
-  u16x8 saug;
+  float sbeta;
   auto gload = [&](int t) {
     const int64_t base = (row0 + (int64_t)t * kTileRows) * DP;
 #pragma unroll
@@ -398,7 +403,7 @@ __global__ __launch_bounds__(256, 2) void tile_split(
 #pragma unroll
       for (int k = 0; k < NLD; ++k)
         stage[p][k] = reinterpret_cast<const u16x8*>(Xpp[p] + base)[min(tid + 256 * k, NV - 1)];
-    saug = Xaug[row0 + (int64_t)t * kTileRows + (tid & 31)];
+    sbeta = Xoff[row0 + (int64_t)t * kTileRows + (tid & 31)];
   };
   auto lstore = [&](int buf) {
 #pragma unroll
@@ -409,7 +414,7 @@ __global__ __launch_bounds__(256, 2) void tile_split(
         const int r = idx / V_ROW, c8 = idx % V_ROW;
         *reinterpret_cast<u16x8*>(&tile[buf][p][r * LD + c8 * 8]) = stage[p][k];
       }
-    taug[buf][tid & 31] = saug;
+    tbeta[buf][tid & 31] = sbeta;
   };
 
   double acc = 0.0;
@@ -423,7 +428,16 @@ __global__ __launch_bounds__(256, 2) void tile_split(
     } else {
       acc += (double)tile_epilogue<false>(cdone, 0, 0, r32, h, qi, ex);
     }
-    f32x16 c = {0};
+    // the accumulators start from the offsets alpha_q + beta_x of their pairs
+    f32x16 c;
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+      const f32x4 bv = *reinterpret_cast<const f32x4*>(&tbeta[buf][8 * g + 4 * h]);
+      c[4 * g] = alpha + bv.x;
+      c[4 * g + 1] = alpha + bv.y;
+      c[4 * g + 2] = alpha + bv.z;
+      c[4 * g + 3] = alpha + bv.w;
+    }
 #pragma unroll
     for (int s = 0; s < KS; ++s) {
       u16x8 a[NP];
@@ -440,7 +454,6 @@ __global__ __launch_bounds__(256, 2) void tile_split(
       c = mma16<FORM>(a[0], bq[1][s], c);
       c = mma16<FORM>(a[0], bq[0][s], c);
     }
-    c = mma16_bf16(taug[buf][r32] & hmask, baug, c);
     cnew = c;
     lstore(buf ^ 1);
     gload(min(t + 2, ntiles - 1));
@@ -573,7 +586,7 @@ stag_status launch_tile_f32(const float* Xp, const float* beta, const float* Qs,
 }
 
 template <int FORM, int DP>
-stag_status launch_tile_split(void* const* xp, const u16x8* xaug, void* const* qp, const u16x8* qaug, int64_t n_pad,
+stag_status launch_tile_split(void* const* xp, const float* xaug, void* const* qp, const float* qaug, int64_t n_pad,
                               int n_qtiles, int64_t m_pad, int P, double* partial, const TileExtra& ex,
                               hipStream_t st) {
   using U = const unsigned short*;
@@ -590,7 +603,7 @@ stag_status launch_tile_split(void* const* xp, const u16x8* xaug, void* const* q
 }
 
 template <int FORM>
-stag_status dispatch_split(int dp, void* const* xp, const u16x8* xaug, void* const* qp, const u16x8* qaug,
+stag_status dispatch_split(int dp, void* const* xp, const float* xaug, void* const* qp, const float* qaug,
                            int64_t n_pad, int n_qtiles, int64_t m_pad, int P, double* partial, const TileExtra& ex,
                            hipStream_t st) {
   switch (dp) {
@@ -682,12 +695,7 @@ stag_status prepare_operands(int form, const float* src, int64_t rows, int d, do
   for (int p = 0; p < form_parts(form); ++p)
     STAG_TRY(ws.alloc_bytes(&out->part[p], (size_t)rows_pad * dp * form_element_bytes(form)));
   STAG_TRY(ws.alloc(&out->off, (size_t)rows_pad));
-  out->aug = nullptr;
-  if (form != STAG_FORM_FP32) {
-    void* v;
-    STAG_TRY(ws.alloc_bytes(&v, (size_t)rows_pad * 16));
-    out->aug = v;
-  }
+  out->aug = nullptr;  // the tiles take the offsets directly
   STAG_TRY(ws.alloc(&out->nrm, (size_t)rows));
   out->max_nrm_bits = nullptr;
   if (!is_query) {
@@ -742,8 +750,8 @@ stag_status launch_exact_tiles(const Operands& xo, const Operands& qo, double* p
   if (xo.form == STAG_FORM_FP32)
     return dispatch_f32(xo.dp, (const float*)xo.part[0], xo.off, (const float*)qo.part[0], qo.off, xo.rows_pad,
                         n_qtiles, qo.rows_pad, P, partial, ex, st);
-  const u16x8* xaug = static_cast<const u16x8*>(xo.aug);
-  const u16x8* qaug = static_cast<const u16x8*>(qo.aug);
+  const float* xaug = xo.off;
+  const float* qaug = qo.off;
   switch (xo.form) {
     case STAG_FORM_BF16_SPLIT:
       return dispatch_split<STAG_FORM_BF16_SPLIT>(xo.dp, xo.part, xaug, qo.part, qaug, xo.rows_pad, n_qtiles,

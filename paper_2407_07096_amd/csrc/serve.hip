@@ -106,7 +106,7 @@ class GpuExecutor : public serve::Executor {
     if (dsi < 0 || dsi >= (int)datasets_.size()) return 0;
     const Dataset& ds = *datasets_[dsi];
     const int64_t mp = round_up(m, query_tile_rows());
-    const size_t per_row = (size_t)ds.xo.dp * form_element_bytes(ds.form) * form_parts(ds.form) + 4 + 16 + 8 +
+    const size_t per_row = (size_t)ds.xo.dp * form_element_bytes(ds.form) * form_parts(ds.form) + 4 + 8 +
                            (size_t)ds.P * 8;
     return (size_t)mp * per_row;
   }
@@ -147,7 +147,6 @@ class GpuExecutor : public serve::Executor {
     void* v = nullptr;
     if (rc == STAG_OK) rc = alloc(&v, (size_t)total * sizeof(float));
     qo.off = static_cast<float*>(v);
-    if (rc == STAG_OK && ds.form != STAG_FORM_FP32) rc = alloc(&qo.aug, (size_t)total * 16);
     if (rc == STAG_OK) rc = alloc(&v, (size_t)total * sizeof(double));
     qo.nrm = static_cast<double*>(v);
     double* partial = nullptr;
