@@ -51,6 +51,10 @@ def _load():
     lib.orc_gaussian_kernel.argtypes = [C.c_double, f32p, f32p, C.c_int32]
     lib.orc_kde_exact.restype = None
     lib.orc_kde_exact.argtypes = [f32p, C.c_int64, f32p, C.c_int64, C.c_int32, C.c_double, f64p, f64p, C.c_int32]
+    lib.orc_kde_kernel.restype = C.c_int32
+    lib.orc_kde_kernel.argtypes = [f32p, C.c_int64, f32p, C.c_int64, C.c_int32, C.c_int32, C.c_double, f64p, C.c_int32]
+    lib.orc_kernel_value.restype = C.c_double
+    lib.orc_kernel_value.argtypes = [C.c_int32, C.c_double, C.c_double]
     lib.orc_kernel_row.restype = None
     lib.orc_kernel_row.argtypes = [f32p, C.c_int64, C.c_int32, C.c_double, C.c_int64, f64p]
     lib.orc_e2lsh_hash.restype = None
@@ -127,6 +131,27 @@ def kde_exact(X, Q, a: float, nthreads: int = 0, return_log: bool = False):
     _load().orc_kde_exact(_p(X, C.c_float), n, _p(Q, C.c_float), m, d, float(a), _p(S, C.c_double),
                           _p(lg, C.c_double), int(nthreads))
     return (S, lg) if return_log else S
+
+
+KERNELS = {"gaussian": 0, "exponential": 1, "logistic": 2}
+
+
+def kde_kernel(X, Q, a: float, kernel: str = "gaussian", nthreads: int = 0):
+    """S(q) = sum_i k(||q - x_i||) for each row of Q (float64); kernel is
+    "gaussian" exp(-a r^2), "exponential" exp(-a r) or "logistic"
+    4/(2 + e^{ar} + e^{-ar})."""
+    X, Q = _f32(X), _f32(Q)
+    n, d = X.shape
+    m = Q.shape[0]
+    S = np.empty(m, dtype=np.float64)
+    rc = _load().orc_kde_kernel(_p(X, C.c_float), n, _p(Q, C.c_float), m, d, KERNELS[kernel], float(a),
+                                _p(S, C.c_double), int(nthreads))
+    assert rc == 0
+    return S
+
+
+def kernel_value(kernel: str, a: float, r: float) -> float:
+    return float(_load().orc_kernel_value(KERNELS[kernel], float(a), float(r)))
 
 
 def kernel_row(X, a: float, i: int):

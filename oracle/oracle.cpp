@@ -15,6 +15,8 @@
 //   orc_kde_exact           - Sec. "Kernel Density Estimation", definition of
 //                             K(q) with the Gaussian kernel exp(-a x^2); the
 //                             "naive" O(dmn) computation of ExactGaussianKDE.
+//   orc_kde_kernel          - the same definition with the exponential and
+//                             logistic kernels of that section.
 //   orc_collision_probability, orc_boosted_probability
 //                           - Sec. "Random Projection" closed form of p(c);
 //                             Sec. "Boosting the Probability".
@@ -252,6 +254,45 @@ void orc_kde_exact(const float* X, int64_t n, const float* Q, int64_t m, int32_t
     }
   }
 }
+
+// Kernel functions of Sec. "Kernel Density Estimation" as functions of the
+// distance r = ||q - x|| (kernel ids: 0 Gaussian, 1 exponential, 2 logistic):
+//   Gaussian     exp(-a r^2)
+//   exponential  exp(-a r)
+//   logistic     4 / (2 + e^{a r} + e^{-a r}); the paper writes it without a
+//                bandwidth, which is the case a = 1 here.
+double kernel_of_distance(int32_t kernel, double a, double r) {
+  switch (kernel) {
+    case 0: return std::exp(-a * r * r);
+    case 1: return std::exp(-a * r);
+    default: {
+      const double u = a * r;
+      return 4.0 / (2.0 + std::exp(u) + std::exp(-u));
+    }
+  }
+}
+
+// S(q) = sum_i k(||q - x_i||) for every row q of Q, with the kernel chosen by
+// id as above: the definition of K(q) = S(q)/n written out, r_i = sqrt(D_i)
+// from the direct-difference squared distance, the terms summed over i
+// ascending with compensation.  Returns -1 for an unknown kernel id.
+int32_t orc_kde_kernel(const float* X, int64_t n, const float* Q, int64_t m, int32_t d, int32_t kernel, double a,
+                       double* S_out, int32_t nthreads) {
+  if (kernel < 0 || kernel > 2) return -1;
+  if (nthreads <= 0) nthreads = omp_get_max_threads();
+#pragma omp parallel for schedule(static) num_threads(nthreads)
+  for (int64_t qi = 0; qi < m; ++qi) {
+    const float* q = Q + (size_t)qi * d;
+    KahanSum acc;
+    for (int64_t i = 0; i < n; ++i)
+      acc.add(kernel_of_distance(kernel, a, std::sqrt(sqdist_direct(q, X + (size_t)i * d, d))));
+    S_out[qi] = acc.value();
+  }
+  return 0;
+}
+
+// One kernel value k(r) (the same functions, for pins of their shape).
+double orc_kernel_value(int32_t kernel, double a, double r) { return kernel_of_distance(kernel, a, r); }
 
 // Kernel values of one data point against all others: out[j] = exp(-a D_ij).
 void orc_kernel_row(const float* X, int64_t n, int32_t d, double a, int64_t i, double* out) {
