@@ -123,6 +123,45 @@ def precision_config_run(stag, torch, dev, lib, buf, n_check: int = 64):
     return out
 
 
+def kernels_run(stag, torch, dev, lib, buf, X, Q, Xd, Qd, form: str, n_check: int = 32):
+    """Exact KDE with each kernel function of the paper (Gaussian a = 0.01,
+    exponential and logistic a = 0.2) over the step's data and queries in one
+    form: tile time, pairs/s, matrix-core fraction (the same products as the
+    Gaussian tile) and the error against the FP64 oracle on sampled queries."""
+    import numpy as np
+
+    import oracle
+    n, d = X.shape
+    m = Q.shape[0]
+    rng = np.random.default_rng(2005)
+    idx = np.sort(rng.choice(m, size=n_check, replace=False))
+    S = torch.empty(m, dtype=torch.float64, device=dev)
+    B = torch.empty(m, dtype=torch.float64, device=dev)
+    out = {"workload": f"exact KDE n={n}, m={m}, d={d}, form {form}", "checked_queries": n_check, "kernels": {}}
+    for kernel, a in [("gaussian", 0.01), ("exponential", 0.2), ("logistic", 0.2)]:
+        stag.kde_exact(Xd, Qd, a, form=form, S_out=S, kernel=kernel)  # warm-up
+        torch.cuda.synchronize()
+        lib.stag_timing_report(buf, len(buf))
+        lib.stag_timing_enable(1)
+        reps = 3
+        for _ in range(reps):
+            stag.kde_exact(Xd, Qd, a, form=form, S_out=S, bound_out=B, return_bound=True, kernel=kernel)
+        torch.cuda.synchronize()
+        lib.stag_timing_enable(0)
+        lib.stag_timing_report(buf, len(buf))
+        t = parse_timing(buf.value.decode())
+        tk = TILE_KERNEL[form]
+        tile_ms = t[tk][1] / t[tk][0]
+        flops = 2.0 * d * n * m * PRODUCTS[form]
+        ref = oracle.kde_kernel(X, Q[idx], a, kernel)
+        err = np.abs(S.cpu().numpy()[idx] - ref) / ref
+        out["kernels"][kernel] = {"a": a, "tile_ms": tile_ms, "pairs_per_s": n * m / (tile_ms / 1e3),
+                                  "frac_of_peak": flops / (tile_ms / 1e3) / MFMA_PEAK[form],
+                                  "max_rel_err_sampled": float(err.max()),
+                                  "max_bound_sampled": float(B.cpu().numpy()[idx].max())}
+    return out
+
+
 def e2lsh_table_run(stag, torch, dev, lib, buf, Xd, Qd, K: int = 6, L: int = 50):
     """E2LSH table (K = 6, L = 50, the paper's example) over the step's data:
     build and near-neighbour listing of all queries, with kernel times."""
@@ -212,7 +251,7 @@ def serving_run(stag, torch, dev, n_requests: int, seconds_cap: float):
 HERE = os.path.dirname(os.path.abspath(__file__))
 TRAFFIC_FILE = os.path.join(HERE, "profiles", "hot_path_step_n100k_d64_hbm_traffic.txt")
 CSRC = os.path.join(HERE, "paper_2407_07096_amd", "csrc")
-TRAFFIC_SOURCES = {"kde_tile": ["kde_exact.hip", "kde_exact.h"], "simgraph_tile": ["kde_exact.hip", "kde_exact.h"],
+TRAFFIC_SOURCES = {"kde_tile": ["kde_tiles.h", "kde_tiles_gauss.hip", "kde_tiles_gauss_extra.hip", "kde_exact.h"],
                    "lsh_": ["lsh.hip", "e2lsh.h"], "simgraph_draw": ["simgraph.hip"]}
 
 
@@ -434,6 +473,7 @@ def main():
         result["calib_copy_bytes"] = args.calib_copy_mb << 20
         del src_c, dst_c
     result["e2lsh_table"] = e2lsh_table_run(stag, torch, dev, lib, buf, Xd, Qd)
+    result["kernels"] = kernels_run(stag, torch, dev, lib, buf, X, Q, Xd, Qd, args.form)
     if not args.no_precision_config:
         result["precision_config"] = precision_config_run(stag, torch, dev, lib, buf)
     if not args.no_serve:

@@ -57,6 +57,13 @@ typedef enum {
   STAG_FORM_BF16_SPLIT3 = 3  /* x = hi + mid + lo in bf16, six bf16 products */
 } stag_form;
 
+/* Kernel functions of Sec. "Kernel Density Estimation" (r = ||q - x||). */
+typedef enum {
+  STAG_KERNEL_GAUSSIAN = 0,     /* exp(-a r^2) */
+  STAG_KERNEL_EXPONENTIAL = 1,  /* exp(-a r) */
+  STAG_KERNEL_LOGISTIC = 2      /* 4 / (2 + e^{a r} + e^{-a r}); a = 1 is the paper's */
+} stag_kernel;
+
 /* flags of stag_kde_exact */
 #define STAG_NORMALIZE 1u  /* return S/n (the paper's K(q)) instead of S */
 
@@ -104,6 +111,23 @@ double stag_e2lsh_collision_probability(double c, int32_t K, int32_t L);
 stag_status stag_kde_exact(const float* X, int64_t n, const float* Q, int64_t m, int32_t d, double a,
                            double eps, int32_t form, uint32_t flags, double* S_out, double* bound_out,
                            hipStream_t stream);
+
+/* Exact kernel density S(q) = sum_i k(||q - x_i||) with any of the three
+ * kernel functions of Sec. "Kernel Density Estimation" (stag_kernel); the
+ * arguments, limits and determinism are those of stag_kde_exact, which is
+ * this call with STAG_KERNEL_GAUSSIAN.
+ * The tile computes E = -lambda D, D = ||q||^2 + ||x||^2 - 2 q.x, with
+ * lambda = (a log2 e)^2 for the exponential and logistic kernels, and takes
+ * y = sqrt(max(-E, 0)) = a r log2(e); FP16_SPLIT then needs
+ * |2 (a log2 e)^2 q_j| below 65504.
+ * bound_out: the a-priori relative error bound per result.  Through the
+ * expanded distance, the exponential kernel's bound is dominated by pairs at
+ * distance near zero (an error dE in the exponent moves sqrt(-E) by up to
+ * sqrt(dE)); the logistic kernel is flat at r = 0 and keeps a bound of the
+ * Gaussian's order.  Unknown kernel: STAG_E_INVAL. */
+stag_status stag_kde_exact_kernel(const float* X, int64_t n, const float* Q, int64_t m, int32_t d, int32_t kernel,
+                                  double a, int32_t form, uint32_t flags, double* S_out, double* bound_out,
+                                  hipStream_t stream);
 
 /* E2LSH codes and bucket keys (Sec. "Random Projection": h(x) =
  * floor((<x, g> + b) / 4); Sec. "Boosting the Probability": K concatenated

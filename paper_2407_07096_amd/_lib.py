@@ -17,6 +17,7 @@ HEADER = os.path.join(HERE, "..", "include", "stag_kde.h")
 
 STAG_OK, STAG_E_INVAL, STAG_E_NOMEM, STAG_E_DEVICE, STAG_E_UNSUPPORTED, STAG_E_BUSY = range(6)
 FORMS = {"fp32": 0, "bf16_split": 1, "fp16_split": 2, "bf16_split3": 3}
+KERNELS = {"gaussian": 0, "exponential": 1, "logistic": 2}
 NORMALIZE = 1
 
 LSH_LITERAL = 1
@@ -69,6 +70,8 @@ def load():
     lib.stag_e2lsh_collision_probability.argtypes = [f64, i32, i32]
     lib.stag_kde_exact.restype = C.c_int
     lib.stag_kde_exact.argtypes = [vp, i64, vp, i64, i32, f64, f64, i32, u32, vp, vp, vp]
+    lib.stag_kde_exact_kernel.restype = C.c_int
+    lib.stag_kde_exact_kernel.argtypes = [vp, i64, vp, i64, i32, i32, f64, i32, u32, vp, vp, vp]
     lib.stag_e2lsh_hash.restype = C.c_int
     lib.stag_e2lsh_hash.argtypes = [vp, i64, i32, vp, vp, i32, i32, vp, vp, vp]
     pp = C.POINTER(LshParams)
@@ -166,23 +169,33 @@ def collision_probability(c: float, K: int = 1, L: int = 1) -> float:
 
 
 def kde_exact(X, Q, a: float, form: str = "fp32", normalize: bool = False, return_bound: bool = False,
-              S_out=None, bound_out=None):
-    """S(q) = sum_i exp(-a ||q - x_i||^2) for every row q of Q (float64 [m]).
-    With return_bound also the per-result relative error bound."""
+              S_out=None, bound_out=None, kernel: str = "gaussian"):
+    """S(q) = sum_i k(||q - x_i||) for every row q of Q (float64 [m]); kernel
+    "gaussian" exp(-a r^2) (default), "exponential" exp(-a r) or "logistic"
+    4/(2 + e^{ar} + e^{-ar}).  With return_bound also the per-result relative
+    error bound."""
     torch = _torch()
     _need(X, torch.float32, 2, "X")
     _need(Q, torch.float32, 2, "Q")
     if X.shape[1] != Q.shape[1]:
         raise ValueError("X and Q must have the same number of columns")
+    if kernel not in KERNELS:
+        raise ValueError(f"unknown kernel {kernel!r}")
     n, d = X.shape
     m = Q.shape[0]
     S = S_out if S_out is not None else torch.empty(m, dtype=torch.float64, device=X.device)
     B = None
     if return_bound:
         B = bound_out if bound_out is not None else torch.empty(m, dtype=torch.float64, device=X.device)
-    st = load().stag_kde_exact(_ptr(X), n, _ptr(Q), m, d, float(a), 0.0, FORMS[form],
-                               NORMALIZE if normalize else 0, _ptr(S), _ptr(B), _stream_handle(X.device))
-    check(st, "stag_kde_exact")
+    flags = NORMALIZE if normalize else 0
+    if kernel == "gaussian":
+        st = load().stag_kde_exact(_ptr(X), n, _ptr(Q), m, d, float(a), 0.0, FORMS[form], flags, _ptr(S), _ptr(B),
+                                   _stream_handle(X.device))
+        check(st, "stag_kde_exact")
+    else:
+        st = load().stag_kde_exact_kernel(_ptr(X), n, _ptr(Q), m, d, KERNELS[kernel], float(a), FORMS[form], flags,
+                                          _ptr(S), _ptr(B), _stream_handle(X.device))
+        check(st, "stag_kde_exact_kernel")
     return (S, B) if return_bound else S
 
 

@@ -22,26 +22,42 @@ struct Operands {
   unsigned long long* max_nrm_bits = nullptr;   // max ||row||^2 (fp64 bits)
 };
 
-// Rounding-error model of one result, in base-2 exponent units:
-//   dE <= c_acc (cross + offs) + c_split cross + c_off offs
-// with cross = 2 a log2(e) ||q|| max||x|| and offs = a log2(e)(||q||^2 + max||x||^2);
-// relative bound = 2^dE - 1 + c_tail.
+// Rounding-error model of one result.  The tiles produce the exponent
+// E = -lambda D (base 2; lambda = la) with an absolute error of at most
+//   dE = c_acc (cross + offs) + c_split cross + c_off offs,
+// cross = 2 la ||q|| max||x||, offs = la (||q||^2 + max||x||^2).  The
+// relative error of every kernel value, and so of the sum, is then at most
+//   Gaussian     2^dE - 1
+//   exponential  2^(sqrt(dE) + dy) - 1     (|sqrt(u) - sqrt(v)| <= sqrt|u - v|)
+//   logistic     e^(dE / (4 log2(e)^2) + ln2 dy) - 1 + 5 ulp
+// plus c_tail (exp2, the 16-term fp32 tile sums).  For the logistic kernel
+// |d ln k / d(r^2)| <= 1/4 bounds the effect of the exponent error, and
+// dy = 2^-23 min(150, sqrt(la) (||q|| + max||x||)) is the rounding of
+// y = sqrt(-E) (terms with y > 150 are below 2^-150 and flush to zero).
 struct BoundModel {
   double la, c_acc, c_split, c_off, c_tail;
+  int kern = 0;  // a stag_kernel
 };
 
 __host__ __device__ inline double relative_bound(const BoundModel& bm, double qn, double xm) {
+  const double ln2 = 0.69314718055994530942;
   const double cross = 2.0 * bm.la * sqrt(qn) * sqrt(xm);
   const double offs = bm.la * (qn + xm);
   const double dE = bm.c_acc * (cross + offs) + bm.c_split * cross + bm.c_off * offs;
-  return expm1(0.69314718055994530942 * dE) + bm.c_tail;
+  if (bm.kern == 0) return expm1(ln2 * dE) + bm.c_tail;
+  const double dy = 0x1.0p-23 * fmin(150.0, sqrt(bm.la) * (sqrt(qn) + sqrt(xm)));
+  if (bm.kern == 1) return expm1(ln2 * (sqrt(dE) + dy)) + bm.c_tail;
+  const double log2e = 1.4426950408889634074;
+  return expm1(dE / (4.0 * log2e * log2e) + ln2 * dy) + bm.c_tail + 5.0 * 0x1.0p-23;
 }
 
-// Optional epilogue outputs of the tiles (edge sampling): drop the diagonal
+// Epilogue options of the tiles: the kernel function, and for edge sampling
+// (Gaussian only) two optional outputs: drop the diagonal
 // when a data set is queried against itself, and write per-32-row-tile
 // partial sums tp[query * ntile + tile] (fp32; ntile, the row stride, is at
 // least padded data rows / 32 and a multiple of 8).
 struct TileExtra {
+  int kernel = 0;  // a stag_kernel; the two outputs below need the Gaussian
   int self = 0;
   float* tp = nullptr;
   int64_t ntile = 0;
@@ -51,7 +67,10 @@ int exact_padded_dim(int d);  // 0 if unsupported
 int form_parts(int form);
 size_t form_element_bytes(int form);
 int64_t exact_chunks(int64_t n_pad);
-BoundModel make_bound_model(int form, int d, double a);
+// lambda of the tiles for a kernel: a log2(e) (Gaussian), (a log2(e))^2
+// (exponential, logistic); operands are prepared with a / log2(e) * lambda.
+double kernel_tile_a(int kernel, double a);
+BoundModel make_bound_model(int form, int d, double a_tile, int kernel = 0);
 
 stag_status prepare_operands(int form, const float* src, int64_t rows, int d, double a, bool is_query,
                              Workspace& ws, Operands* out, hipStream_t st);

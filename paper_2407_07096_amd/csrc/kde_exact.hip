@@ -1,15 +1,19 @@
-// Exact Gaussian kernel density on the gfx950 matrix cores.
+// Exact kernel density on the gfx950 matrix cores: operand preparation, the
+// cross-chunk reduction and the C ABI entry points.  The tiles themselves are
+// in kde_tiles.h.
 //
-// S(q) = sum_i exp(-a ||q - x_i||^2)   (Sec. "Kernel Density Estimation": the
-// density K(q) = S(q)/n; ExactGaussianKDE evaluates it naively in O(dmn)).
+// S(q) = sum_i k(||q - x_i||)   (Sec. "Kernel Density Estimation": the density
+// K(q) = S(q)/n; ExactGaussianKDE evaluates it naively in O(dmn)); k is the
+// Gaussian exp(-a r^2), the exponential exp(-a r) or the logistic
+// 4/(2 + e^{ar} + e^{-ar}) kernel.
 //
 // The squared distance is expanded, ||q-x||^2 = ||q||^2 + ||x||^2 - 2 q.x,
-// and the whole exponent in base 2,
-//     E = log2(e) * (-a ||q||^2 - a ||x||^2 + 2a q.x) = alpha_q + beta_x + (s q).x,
-// s = 2a log2(e), is produced by the matrix cores: the cross term from the
-// (split) operands, alpha and beta through one extra augmentation step whose
-// operands pair each of them with 1.0.  The epilogue is then just
-// k = exp2(E) and a row sum, per lane, with no cross-lane traffic per tile.
+// and scaled into a base-2 exponent
+//     E = -lambda ||q-x||^2 = alpha_q + beta_x + (s q).x,
+// alpha = -lambda ||q||^2, beta = -lambda ||x||^2, s = 2 lambda, with
+// lambda = a log2(e) for the Gaussian kernel and (a log2(e))^2 for the other
+// two.  The matrix cores produce the cross term from the (split) operands on
+// top of alpha + beta; the epilogue maps E to the kernel value and sums.
 //
 // Pipeline of one call:
 //   prep_rows  (data)    fp64 norms, beta, operand copy/split, padding rows
@@ -26,102 +30,13 @@
 // whatever other queries share a launch.
 #include "runtime.h"
 #include "kde_exact.h"
+#include "kde_tiles.h"
 
 namespace stag {
 namespace {
 
-typedef float f32x16 __attribute__((ext_vector_type(16)));
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
+using namespace tiles;
 
-constexpr double kLog2e = 1.4426950408889634074;
-constexpr int kTileRows = 32;
-constexpr int kWaves = 4;
-constexpr int kBQ = 32 * kWaves;      // queries per workgroup
-constexpr int kChunkRows = 4096;      // data rows per partial sum
-constexpr float kPadOffset = -1.0e30f;  // exponent offset of padding rows: exp2 -> 0
-constexpr unsigned short kBf16One = 0x3F80;
-constexpr int kWideMaxDim = 1024;     // largest d of the wide fp32 tile
-
-__device__ inline unsigned short bf16_rne(float f) {
-  unsigned int u = __float_as_uint(f);
-  if ((u & 0x7F800000u) == 0x7F800000u) return (unsigned short)((u >> 16) | ((u & 0xFFFFu) ? 0x40u : 0u));
-  u += 0x7FFFu + ((u >> 16) & 1u);
-  return (unsigned short)(u >> 16);
-}
-__device__ inline float bf16_to_f32(unsigned short h) { return __uint_as_float((unsigned int)h << 16); }
-__device__ inline unsigned short f16_rne(float f) { return __builtin_bit_cast(unsigned short, (_Float16)f); }
-__device__ inline float f16_to_f32(unsigned short h) { return (float)__builtin_bit_cast(_Float16, h); }
-
-// Kernel values of one 32x32 accumulator tile held by a lane (16 exponents),
-// summed as a balanced tree in fp32.
-__device__ inline float exp2_tile_sum(const float* c) {
-  float k[16];
-#pragma unroll
-  for (int i = 0; i < 16; ++i) k[i] = __builtin_amdgcn_exp2f(c[i]);
-#pragma unroll
-  for (int w = 8; w > 0; w >>= 1)
-#pragma unroll
-    for (int i = 0; i < w; ++i) k[i] = k[i] + k[i + w];
-  return k[0];
-}
-
-// A lane's tile sums of 8 consecutive data tiles (global tile indices
-// 8g .. 8g+7), written to tp as two 16-byte stores once the group is complete
-// (or the chunk ends): the row stride of tp is a multiple of 8 tiles.
-struct TileSums8 {
-  float v[8];
-};
-
-// Epilogue of one finished 32x32 tile held by a lane (column qi, half h):
-// exp2 and fp32 tree sum; with EXTRA, optionally drops the diagonal element
-// (data row == query index, for a data set queried against itself) and
-// records the tile's 32-row partial sum (both halves, fixed order), through
-// the group buffer `grp` when the caller walks tiles in order (`last` marks
-// the chunk's final tile), else with a direct store.
-template <bool EXTRA>
-__device__ inline float tile_epilogue(const f32x16& c, int64_t row_base, int64_t col_base, int r32, int h,
-                                      int64_t qi, const TileExtra& ex, TileSums8* grp = nullptr,
-                                      bool last = false) {
-  float cp[16];
-#pragma unroll
-  for (int i = 0; i < 16; ++i) cp[i] = c[i];
-  if constexpr (EXTRA) {
-    if (ex.self && row_base == col_base) {
-      // lane (column r32, half h) holds rows 8(i/4) + 4h + i%4
-      const int idg = 4 * (r32 >> 3) + (r32 & 3);
-      const bool mine = h == ((r32 & 7) >> 2);
-#pragma unroll
-      for (int i = 0; i < 16; ++i) cp[i] = (mine && i == idg) ? kPadOffset : cp[i];
-    }
-  }
-  const float s = exp2_tile_sum(cp);
-  if constexpr (EXTRA) {
-    if (ex.tp) {
-      const float o = __shfl_xor(s, 32);
-      const float tot = h == 0 ? s + o : o + s;
-      const int64_t tile = row_base / kTileRows;
-      if (grp == nullptr) {
-        if (h == 0) ex.tp[qi * ex.ntile + tile] = tot;
-      } else {
-        const int k = (int)(tile & 7);
-#pragma unroll
-        for (int e = 0; e < 8; ++e) grp->v[e] = e == k ? tot : grp->v[e];
-        if ((k == 7 || last) && h == 0) {
-          f32x4* dst = reinterpret_cast<f32x4*>(ex.tp + qi * ex.ntile + (tile & ~(int64_t)7));
-          dst[0] = f32x4{grp->v[0], grp->v[1], grp->v[2], grp->v[3]};
-          dst[1] = f32x4{grp->v[4], grp->v[5], grp->v[6], grp->v[7]};
-        }
-      }
-    }
-  }
-  return s;
-}
-
-// Split v into parts of the form's element type: v ~= p0 + p1 (+ p2); each
-// remainder is exact in fp32 (Sterbenz), so only the last part is rounded.
 template <int FORM>
 __device__ inline void split_value(float v, unsigned short* p) {
   if constexpr (FORM == STAG_FORM_FP16_SPLIT) {
@@ -210,352 +125,6 @@ __global__ __launch_bounds__(256) void prep_rows(const float* __restrict__ src, 
   }
 }
 
-// ---------------------------------------------------------------------------
-// Tile loop shared by both forms.  Each step t (one 32-row data tile):
-//   barrier (tile t is in LDS buffer t&1, buffer (t+1)&1 is free)
-//   epilogue of tile t-1: exp2 of its 16 accumulators, fp32 tree sum, fp64 add
-//   matrix-core chain of tile t (independent of the epilogue, so the two are
-//   interleaved in one basic block)
-//   store tile t+1 (loaded into registers one step earlier) to LDS and load
-//   tile t+2 into registers.
-// Staging is branch-free: indices past the end are clamped, so the redundant
-// copies write identical values.  Two steps per loop iteration swap the roles
-// of the two accumulator sets without register copies.
-// ---------------------------------------------------------------------------
-
-// FP32 form: v_mfma_f32_32x32x2_f32.  Lane l supplies A[l%32][k] and
-// B[k][l%32] for the k-slot k = l/32; with the k ordering chosen here, lane
-// half h covers dimensions [h*DP/2, (h+1)*DP/2) of every row.
-template <int DP, bool EXTRA>
-__global__ __launch_bounds__(256, 2) void tile_f32(const float* __restrict__ Xp, const float* __restrict__ beta,
-                                                   const float* __restrict__ Qs, const float* __restrict__ alpha,
-                                                   int64_t n_pad, int n_qtiles, int64_t m_pad,
-                                                   double* __restrict__ partial, TileExtra ex) {
-  constexpr int H = DP / 2;
-  constexpr int LD = DP + 4;  // LDS row stride (floats): 16-byte aligned, rows 4 banks apart
-  constexpr int F4_ROW = DP / 4;
-  constexpr int NV = kTileRows * F4_ROW;
-  constexpr int NLD = (NV + 255) / 256;
-  constexpr int NMMA = H;
-  __shared__ __attribute__((aligned(16))) float tile[2][kTileRows * LD];
-  __shared__ __attribute__((aligned(16))) float tbeta[2][kTileRows];
-
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, r32 = lane & 31, h = lane >> 5;
-  const int qtile = blockIdx.x % n_qtiles;
-  const int chunk = blockIdx.x / n_qtiles;
-  const int64_t col_base = (int64_t)qtile * kBQ + wave * 32;
-  const int64_t qi = col_base + r32;
-
-  float bq[H];
-  {
-    const f32x4* qrow = reinterpret_cast<const f32x4*>(Qs + qi * DP + h * H);
-#pragma unroll
-    for (int s = 0; s < H / 4; ++s) {
-      f32x4 v = qrow[s];
-      bq[4 * s] = v.x; bq[4 * s + 1] = v.y; bq[4 * s + 2] = v.z; bq[4 * s + 3] = v.w;
-    }
-  }
-  const float aq = alpha[qi];
-
-  const int64_t row0 = (int64_t)chunk * kChunkRows;
-  const int64_t rem = (n_pad - row0) / kTileRows;
-  const int ntiles = (int)(rem < kChunkRows / kTileRows ? rem : kChunkRows / kTileRows);
-
-  f32x4 stage[NLD];
-  float sbeta;
-  auto gload = [&](int t) {
-    const f32x4* srcp = reinterpret_cast<const f32x4*>(Xp + (row0 + (int64_t)t * kTileRows) * DP);
-#pragma unroll
-    for (int k = 0; k < NLD; ++k) stage[k] = srcp[min(tid + 256 * k, NV - 1)];
-    sbeta = beta[row0 + (int64_t)t * kTileRows + (tid & 31)];
-  };
-  auto lstore = [&](int buf) {
-#pragma unroll
-    for (int k = 0; k < NLD; ++k) {
-      const int idx = min(tid + 256 * k, NV - 1);
-      const int r = idx / F4_ROW, c4 = idx % F4_ROW;
-      *reinterpret_cast<f32x4*>(&tile[buf][r * LD + c4 * 4]) = stage[k];
-    }
-    tbeta[buf][tid & 31] = sbeta;
-  };
-
-  double acc = 0.0;
-  TileSums8 grp = {};
-  auto step = [&](int t, const f32x16& cdone, f32x16& cnew) {
-    const int buf = t & 1;
-    __syncthreads();
-    if constexpr (EXTRA) {
-      if (t > 0)
-        acc += (double)tile_epilogue<true>(cdone, row0 + (int64_t)(t - 1) * kTileRows, col_base, r32, h, qi, ex, &grp);
-    } else {
-      acc += (double)tile_epilogue<false>(cdone, 0, 0, r32, h, qi, ex);
-    }
-    const float* arow = &tile[buf][r32 * LD + h * H];
-    // the accumulators start from the offsets alpha_q + beta_x of their pairs
-    f32x16 c;
-#pragma unroll
-    for (int g = 0; g < 4; ++g) {
-      const f32x4 bv = *reinterpret_cast<const f32x4*>(&tbeta[buf][8 * g + 4 * h]);
-      c[4 * g] = aq + bv.x;
-      c[4 * g + 1] = aq + bv.y;
-      c[4 * g + 2] = aq + bv.z;
-      c[4 * g + 3] = aq + bv.w;
-    }
-#pragma unroll
-    for (int s = 0; s < H; s += 4) {
-      const f32x4 a4 = *reinterpret_cast<const f32x4*>(arow + s);
-      c = __builtin_amdgcn_mfma_f32_32x32x2f32(a4.x, bq[s], c, 0, 0, 0);
-      c = __builtin_amdgcn_mfma_f32_32x32x2f32(a4.y, bq[s + 1], c, 0, 0, 0);
-      c = __builtin_amdgcn_mfma_f32_32x32x2f32(a4.z, bq[s + 2], c, 0, 0, 0);
-      c = __builtin_amdgcn_mfma_f32_32x32x2f32(a4.w, bq[s + 3], c, 0, 0, 0);
-    }
-    cnew = c;
-    lstore(buf ^ 1);
-    gload(min(t + 2, ntiles - 1));
-#pragma unroll
-    for (int i = 0; i < NMMA; ++i) {
-      __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
-      __builtin_amdgcn_sched_group_barrier(0x002, (40 + NMMA - 1) / NMMA, 0);
-    }
-  };
-
-  gload(0);
-  lstore(0);
-  gload(min(1, ntiles - 1));
-  f32x16 ca, cb;
-#pragma unroll
-  for (int i = 0; i < 16; ++i) ca[i] = kPadOffset;  // exp2 -> 0: neutral first epilogue
-  int t = 0;
-  for (; t + 1 < ntiles; t += 2) {
-    step(t, ca, cb);
-    step(t + 1, cb, ca);
-  }
-  if (t < ntiles) {
-    step(t, ca, cb);
-    ca = cb;
-  }
-  acc += (double)tile_epilogue<EXTRA>(ca, row0 + (int64_t)(ntiles - 1) * kTileRows, col_base, r32, h, qi, ex, &grp,
-                                     true);
-  const double other = __shfl_down(acc, 32);
-  if (h == 0) partial[(int64_t)chunk * m_pad + qi] = acc + other;
-}
-
-// Split forms: v_mfma_f32_32x32x16_{f16,bf16}.  Lane l supplies 8 consecutive
-// k values of row/column l%32; lane half h covers dimensions
-// [16 s + 8 h, 16 s + 8 h + 8) of k-step s.
-template <int FORM>
-__device__ inline f32x16 mma16(u16x8 a, u16x8 b, f32x16 c) {
-  if constexpr (FORM == STAG_FORM_FP16_SPLIT)
-    return __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(f16x8, a), __builtin_bit_cast(f16x8, b), c, 0,
-                                                  0, 0);
-  else
-    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c,
-                                                   0, 0, 0);
-}
-
-__device__ inline f32x16 mma16_bf16(u16x8 a, u16x8 b, f32x16 c) {
-  return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c, 0,
-                                                 0, 0);
-}
-
-template <int FORM, int DP, bool EXTRA>
-__global__ __launch_bounds__(256, 2) void tile_split(
-    const unsigned short* __restrict__ X0, const unsigned short* __restrict__ X1,
-    const unsigned short* __restrict__ X2, const float* __restrict__ Xoff, const unsigned short* __restrict__ Q0,
-    const unsigned short* __restrict__ Q1, const unsigned short* __restrict__ Q2, const float* __restrict__ Qoff,
-    int64_t n_pad, int n_qtiles, int64_t m_pad, double* __restrict__ partial, TileExtra ex) {
-  constexpr int NP = FORM == STAG_FORM_BF16_SPLIT3 ? 3 : 2;
-  constexpr int KS = DP / 16;
-  constexpr int LD = DP + 8;     // LDS row stride (halves): 16-byte aligned
-  constexpr int V_ROW = DP / 8;  // 16-byte vectors per row
-  constexpr int NV = kTileRows * V_ROW;
-  constexpr int NLD = (NV + 255) / 256;
-  constexpr int NMMA = KS * (NP == 3 ? 6 : 3);
-  __shared__ __attribute__((aligned(16))) unsigned short tile[2][NP][kTileRows * LD];
-  __shared__ __attribute__((aligned(16))) float tbeta[2][kTileRows];
-
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, r32 = lane & 31, h = lane >> 5;
-  const int qtile = blockIdx.x % n_qtiles;
-  const int chunk = blockIdx.x / n_qtiles;
-  const int64_t col_base = (int64_t)qtile * kBQ + wave * 32;
-  const int64_t qi = col_base + r32;
-
-  const unsigned short* Qp[3] = {Q0, Q1, Q2};
-  const unsigned short* Xpp[3] = {X0, X1, X2};
-  u16x8 bq[NP][KS];
-#pragma unroll
-  for (int p = 0; p < NP; ++p)
-#pragma unroll
-    for (int s = 0; s < KS; ++s)
-      bq[p][s] = *reinterpret_cast<const u16x8*>(Qp[p] + qi * DP + s * 16 + h * 8);
-  const float alpha = Qoff[qi];
-
-  const int64_t row0 = (int64_t)chunk * kChunkRows;
-  const int64_t rem = (n_pad - row0) / kTileRows;
-  const int ntiles = (int)(rem < kChunkRows / kTileRows ? rem : kChunkRows / kTileRows);
-
-  u16x8 stage[NP][NLD];
-  float sbeta;
-  auto gload = [&](int t) {
-    const int64_t base = (row0 + (int64_t)t * kTileRows) * DP;
-#pragma unroll
-    for (int p = 0; p < NP; ++p)
-#pragma unroll
-      for (int k = 0; k < NLD; ++k)
-        stage[p][k] = reinterpret_cast<const u16x8*>(Xpp[p] + base)[min(tid + 256 * k, NV - 1)];
-    sbeta = Xoff[row0 + (int64_t)t * kTileRows + (tid & 31)];
-  };
-  auto lstore = [&](int buf) {
-#pragma unroll
-    for (int p = 0; p < NP; ++p)
-#pragma unroll
-      for (int k = 0; k < NLD; ++k) {
-        const int idx = min(tid + 256 * k, NV - 1);
-        const int r = idx / V_ROW, c8 = idx % V_ROW;
-        *reinterpret_cast<u16x8*>(&tile[buf][p][r * LD + c8 * 8]) = stage[p][k];
-      }
-    tbeta[buf][tid & 31] = sbeta;
-  };
-
-  double acc = 0.0;
-  TileSums8 grp = {};
-  auto step = [&](int t, const f32x16& cdone, f32x16& cnew) {
-    const int buf = t & 1;
-    __syncthreads();
-    if constexpr (EXTRA) {
-      if (t > 0)
-        acc += (double)tile_epilogue<true>(cdone, row0 + (int64_t)(t - 1) * kTileRows, col_base, r32, h, qi, ex, &grp);
-    } else {
-      acc += (double)tile_epilogue<false>(cdone, 0, 0, r32, h, qi, ex);
-    }
-    // the accumulators start from the offsets alpha_q + beta_x of their pairs
-    f32x16 c;
-#pragma unroll
-    for (int g = 0; g < 4; ++g) {
-      const f32x4 bv = *reinterpret_cast<const f32x4*>(&tbeta[buf][8 * g + 4 * h]);
-      c[4 * g] = alpha + bv.x;
-      c[4 * g + 1] = alpha + bv.y;
-      c[4 * g + 2] = alpha + bv.z;
-      c[4 * g + 3] = alpha + bv.w;
-    }
-#pragma unroll
-    for (int s = 0; s < KS; ++s) {
-      u16x8 a[NP];
-#pragma unroll
-      for (int p = 0; p < NP; ++p)
-        a[p] = *reinterpret_cast<const u16x8*>(&tile[buf][p][r32 * LD + s * 16 + h * 8]);
-      // small corrections first, then the leading product
-      if constexpr (NP == 3) {
-        c = mma16<FORM>(a[2], bq[0][s], c);
-        c = mma16<FORM>(a[1], bq[1][s], c);
-        c = mma16<FORM>(a[0], bq[2][s], c);
-      }
-      c = mma16<FORM>(a[1], bq[0][s], c);
-      c = mma16<FORM>(a[0], bq[1][s], c);
-      c = mma16<FORM>(a[0], bq[0][s], c);
-    }
-    cnew = c;
-    lstore(buf ^ 1);
-    gload(min(t + 2, ntiles - 1));
-#pragma unroll
-    for (int i = 0; i < NMMA; ++i) {
-      __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
-      __builtin_amdgcn_sched_group_barrier(0x002, (40 + NMMA - 1) / NMMA, 0);
-    }
-  };
-
-  gload(0);
-  lstore(0);
-  gload(min(1, ntiles - 1));
-  f32x16 ca, cb;
-#pragma unroll
-  for (int i = 0; i < 16; ++i) ca[i] = kPadOffset;  // exp2 -> 0: neutral first epilogue
-  int t = 0;
-  for (; t + 1 < ntiles; t += 2) {
-    step(t, ca, cb);
-    step(t + 1, cb, ca);
-  }
-  if (t < ntiles) {
-    step(t, ca, cb);
-    ca = cb;
-  }
-  acc += (double)tile_epilogue<EXTRA>(ca, row0 + (int64_t)(ntiles - 1) * kTileRows, col_base, r32, h, qi, ex, &grp,
-                                     true);
-  const double other = __shfl_down(acc, 32);
-  if (h == 0) partial[(int64_t)chunk * m_pad + qi] = acc + other;
-}
-
-// ---------------------------------------------------------------------------
-// Wide rows (256 < d <= 1024), fp32 form.  The 32 queries of a workgroup sit
-// in LDS as the B operand ([32][DP+4] floats, loaded once); each of the 4
-// waves takes every 4th 32-row data tile of the chunk and streams its A
-// operand straight from global memory in blocks of 32 coordinates (register
-// double-buffered).  Per-wave fp64 sums are combined in wave order.
-// ---------------------------------------------------------------------------
-template <bool EXTRA>
-__global__ __launch_bounds__(256) void tile_f32_wide(const float* __restrict__ Xp, const float* __restrict__ beta,
-                                                     const float* __restrict__ Qs, const float* __restrict__ alpha,
-                                                     int DP, int64_t n_pad, int n_qt32, int64_t m_pad,
-                                                     double* __restrict__ partial, TileExtra ex) {
-  extern __shared__ __attribute__((aligned(16))) float qlds[];
-  __shared__ double wsum[4][32];
-  const int H = DP / 2, LD = DP + 4;
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, r32 = lane & 31, h = lane >> 5;
-  const int qtile = blockIdx.x % n_qt32;
-  const int chunk = blockIdx.x / n_qt32;
-  const int64_t col_base = (int64_t)qtile * 32;
-  const int64_t qi = col_base + r32;
-  // B operand into LDS
-  {
-    const f32x4* src = reinterpret_cast<const f32x4*>(Qs + col_base * DP);
-    const int nv = 32 * DP / 4;
-    for (int v = tid; v < nv; v += 256) {
-      const int r = (v * 4) / DP, c = (v * 4) % DP;
-      *reinterpret_cast<f32x4*>(&qlds[r * LD + c]) = src[v];
-    }
-  }
-  __syncthreads();
-  const float baug = h == 0 ? alpha[qi] : 1.0f;
-  const int64_t row0 = (int64_t)chunk * kChunkRows;
-  const int64_t rem = (n_pad - row0) / kTileRows;
-  const int ntiles = (int)(rem < kChunkRows / kTileRows ? rem : kChunkRows / kTileRows);
-  const float* brow = &qlds[r32 * LD + h * H];
-  double acc = 0.0;
-  for (int t = wave; t < ntiles; t += 4) {
-    const int64_t rb = row0 + (int64_t)t * kTileRows;
-    const f32x4* arow = reinterpret_cast<const f32x4*>(Xp + (rb + r32) * DP + h * H);
-    f32x16 c = {0};
-    f32x4 a_cur[8], a_nxt[8];
-#pragma unroll
-    for (int k = 0; k < 8; ++k) a_cur[k] = arow[k];
-    for (int kb = 0; kb < H; kb += 32) {
-      const bool more = kb + 32 < H;
-#pragma unroll
-      for (int k = 0; k < 8; ++k) a_nxt[k] = more ? arow[(kb + 32) / 4 + k] : a_cur[k];
-#pragma unroll
-      for (int k = 0; k < 8; ++k) {
-        const f32x4 b4 = *reinterpret_cast<const f32x4*>(brow + kb + 4 * k);
-        c = __builtin_amdgcn_mfma_f32_32x32x2f32(a_cur[k].x, b4.x, c, 0, 0, 0);
-        c = __builtin_amdgcn_mfma_f32_32x32x2f32(a_cur[k].y, b4.y, c, 0, 0, 0);
-        c = __builtin_amdgcn_mfma_f32_32x32x2f32(a_cur[k].z, b4.z, c, 0, 0, 0);
-        c = __builtin_amdgcn_mfma_f32_32x32x2f32(a_cur[k].w, b4.w, c, 0, 0, 0);
-      }
-#pragma unroll
-      for (int k = 0; k < 8; ++k) a_cur[k] = a_nxt[k];
-    }
-    const float tb = beta[rb + r32];
-    c = __builtin_amdgcn_mfma_f32_32x32x2f32(h == 0 ? 1.0f : tb, baug, c, 0, 0, 0);
-    acc += (double)tile_epilogue<EXTRA>(c, rb, col_base, r32, h, qi, ex);
-  }
-  const double other = __shfl_down(acc, 32);
-  if (h == 0) wsum[wave][r32] = acc + other;
-  __syncthreads();
-  if (tid < 32) {
-    const double tot = ((wsum[0][tid] + wsum[1][tid]) + wsum[2][tid]) + wsum[3][tid];
-    partial[(int64_t)chunk * m_pad + col_base + tid] = tot;
-  }
-}
-
 // S(q) = sum of chunk partials in chunk order; optional 1/n; a-priori bound.
 __global__ void reduce_partials(const double* __restrict__ partial, int P, int64_t m_pad, int64_t m, double scale,
                                 const double* __restrict__ qnrm, const unsigned long long* __restrict__ max_xnrm_bits,
@@ -569,72 +138,6 @@ __global__ void reduce_partials(const double* __restrict__ partial, int P, int64
     const double xm = __longlong_as_double((long long)*max_xnrm_bits);
     bound_out[q] = relative_bound(bm, qnrm[q], xm);
   }
-}
-
-template <int DP>
-stag_status launch_tile_f32(const float* Xp, const float* beta, const float* Qs, const float* alpha, int64_t n_pad,
-                            int n_qtiles, int64_t m_pad, int P, double* partial, const TileExtra& ex,
-                            hipStream_t st) {
-  ScopedTimer tm("kde_tile_f32", st);
-  if (ex.self || ex.tp)
-    hipLaunchKernelGGL((tile_f32<DP, true>), dim3((unsigned)((int64_t)n_qtiles * P)), dim3(256), 0, st, Xp, beta, Qs,
-                       alpha, n_pad, n_qtiles, m_pad, partial, ex);
-  else
-    hipLaunchKernelGGL((tile_f32<DP, false>), dim3((unsigned)((int64_t)n_qtiles * P)), dim3(256), 0, st, Xp, beta,
-                       Qs, alpha, n_pad, n_qtiles, m_pad, partial, ex);
-  return check_launch("tile_f32");
-}
-
-template <int FORM, int DP>
-stag_status launch_tile_split(void* const* xp, const float* xaug, void* const* qp, const float* qaug, int64_t n_pad,
-                              int n_qtiles, int64_t m_pad, int P, double* partial, const TileExtra& ex,
-                              hipStream_t st) {
-  using U = const unsigned short*;
-  ScopedTimer tm(FORM == STAG_FORM_FP16_SPLIT ? "kde_tile_fp16x3" : (FORM == STAG_FORM_BF16_SPLIT ? "kde_tile_bf16x3" : "kde_tile_bf16x6"), st);
-  if (ex.self || ex.tp)
-    hipLaunchKernelGGL((tile_split<FORM, DP, true>), dim3((unsigned)((int64_t)n_qtiles * P)), dim3(256), 0, st,
-                       (U)xp[0], (U)xp[1], (U)xp[2], xaug, (U)qp[0], (U)qp[1], (U)qp[2], qaug, n_pad, n_qtiles, m_pad,
-                       partial, ex);
-  else
-    hipLaunchKernelGGL((tile_split<FORM, DP, false>), dim3((unsigned)((int64_t)n_qtiles * P)), dim3(256), 0, st,
-                       (U)xp[0], (U)xp[1], (U)xp[2], xaug, (U)qp[0], (U)qp[1], (U)qp[2], qaug, n_pad, n_qtiles, m_pad,
-                       partial, ex);
-  return check_launch("tile_split");
-}
-
-template <int FORM>
-stag_status dispatch_split(int dp, void* const* xp, const float* xaug, void* const* qp, const float* qaug,
-                           int64_t n_pad, int n_qtiles, int64_t m_pad, int P, double* partial, const TileExtra& ex,
-                           hipStream_t st) {
-  switch (dp) {
-    case 16: return launch_tile_split<FORM, 16>(xp, xaug, qp, qaug, n_pad, n_qtiles, m_pad, P, partial, ex, st);
-    case 32: return launch_tile_split<FORM, 32>(xp, xaug, qp, qaug, n_pad, n_qtiles, m_pad, P, partial, ex, st);
-    case 64: return launch_tile_split<FORM, 64>(xp, xaug, qp, qaug, n_pad, n_qtiles, m_pad, P, partial, ex, st);
-    case 96: return launch_tile_split<FORM, 96>(xp, xaug, qp, qaug, n_pad, n_qtiles, m_pad, P, partial, ex, st);
-    case 128: return launch_tile_split<FORM, 128>(xp, xaug, qp, qaug, n_pad, n_qtiles, m_pad, P, partial, ex, st);
-    case 160: return launch_tile_split<FORM, 160>(xp, xaug, qp, qaug, n_pad, n_qtiles, m_pad, P, partial, ex, st);
-    case 192: return launch_tile_split<FORM, 192>(xp, xaug, qp, qaug, n_pad, n_qtiles, m_pad, P, partial, ex, st);
-    case 224: return launch_tile_split<FORM, 224>(xp, xaug, qp, qaug, n_pad, n_qtiles, m_pad, P, partial, ex, st);
-    case 256: return launch_tile_split<FORM, 256>(xp, xaug, qp, qaug, n_pad, n_qtiles, m_pad, P, partial, ex, st);
-  }
-  return fail(STAG_E_UNSUPPORTED, "padded dimension %d not instantiated", dp);
-}
-
-stag_status dispatch_f32(int dp, const float* Xp, const float* beta, const float* Qs, const float* alpha,
-                         int64_t n_pad, int n_qtiles, int64_t m_pad, int P, double* partial, const TileExtra& ex,
-                         hipStream_t st) {
-  switch (dp) {
-    case 16: return launch_tile_f32<16>(Xp, beta, Qs, alpha, n_pad, n_qtiles, m_pad, P, partial, ex, st);
-    case 32: return launch_tile_f32<32>(Xp, beta, Qs, alpha, n_pad, n_qtiles, m_pad, P, partial, ex, st);
-    case 64: return launch_tile_f32<64>(Xp, beta, Qs, alpha, n_pad, n_qtiles, m_pad, P, partial, ex, st);
-    case 96: return launch_tile_f32<96>(Xp, beta, Qs, alpha, n_pad, n_qtiles, m_pad, P, partial, ex, st);
-    case 128: return launch_tile_f32<128>(Xp, beta, Qs, alpha, n_pad, n_qtiles, m_pad, P, partial, ex, st);
-    case 160: return launch_tile_f32<160>(Xp, beta, Qs, alpha, n_pad, n_qtiles, m_pad, P, partial, ex, st);
-    case 192: return launch_tile_f32<192>(Xp, beta, Qs, alpha, n_pad, n_qtiles, m_pad, P, partial, ex, st);
-    case 224: return launch_tile_f32<224>(Xp, beta, Qs, alpha, n_pad, n_qtiles, m_pad, P, partial, ex, st);
-    case 256: return launch_tile_f32<256>(Xp, beta, Qs, alpha, n_pad, n_qtiles, m_pad, P, partial, ex, st);
-  }
-  return fail(STAG_E_UNSUPPORTED, "padded dimension %d not instantiated", dp);
 }
 
 template <int FORM>
@@ -726,42 +229,13 @@ int64_t query_tile_rows() { return kBQ; }
 
 stag_status launch_exact_tiles(const Operands& xo, const Operands& qo, double* partial, const TileExtra& ex,
                                hipStream_t st) {
-  const int P = (int)exact_chunks(xo.rows_pad);
-  const int n_qtiles = (int)(qo.rows_pad / kBQ);
-  if (xo.dp > 256) {
-    if (xo.form != STAG_FORM_FP32) return fail(STAG_E_UNSUPPORTED, "d > 256 needs the fp32 form");
-    const int n_qt32 = (int)(qo.rows_pad / 32);
-    const size_t lds = (size_t)32 * (xo.dp + 4) * sizeof(float);
-    STAG_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&tile_f32_wide<true>),
-                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    STAG_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&tile_f32_wide<false>),
-                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    ScopedTimer tm("kde_tile_f32_wide", st);
-    if (ex.self || ex.tp)
-      hipLaunchKernelGGL(tile_f32_wide<true>, dim3((unsigned)((int64_t)n_qt32 * P)), dim3(256), lds, st,
-                         (const float*)xo.part[0], xo.off, (const float*)qo.part[0], qo.off, xo.dp, xo.rows_pad,
-                         n_qt32, qo.rows_pad, partial, ex);
-    else
-      hipLaunchKernelGGL(tile_f32_wide<false>, dim3((unsigned)((int64_t)n_qt32 * P)), dim3(256), lds, st,
-                         (const float*)xo.part[0], xo.off, (const float*)qo.part[0], qo.off, xo.dp, xo.rows_pad,
-                         n_qt32, qo.rows_pad, partial, ex);
-    return check_launch("tile_f32_wide");
-  }
-  if (xo.form == STAG_FORM_FP32)
-    return dispatch_f32(xo.dp, (const float*)xo.part[0], xo.off, (const float*)qo.part[0], qo.off, xo.rows_pad,
-                        n_qtiles, qo.rows_pad, P, partial, ex, st);
-  const float* xaug = xo.off;
-  const float* qaug = qo.off;
-  switch (xo.form) {
-    case STAG_FORM_BF16_SPLIT:
-      return dispatch_split<STAG_FORM_BF16_SPLIT>(xo.dp, xo.part, xaug, qo.part, qaug, xo.rows_pad, n_qtiles,
-                                                  qo.rows_pad, P, partial, ex, st);
-    case STAG_FORM_FP16_SPLIT:
-      return dispatch_split<STAG_FORM_FP16_SPLIT>(xo.dp, xo.part, xaug, qo.part, qaug, xo.rows_pad, n_qtiles,
-                                                  qo.rows_pad, P, partial, ex, st);
-    default:
-      return dispatch_split<STAG_FORM_BF16_SPLIT3>(xo.dp, xo.part, xaug, qo.part, qaug, xo.rows_pad, n_qtiles,
-                                                   qo.rows_pad, P, partial, ex, st);
+  if (ex.kernel != STAG_KERNEL_GAUSSIAN && (ex.self || ex.tp))
+    return fail(STAG_E_UNSUPPORTED, "tile extras need the Gaussian kernel");
+  switch (tiles::tile_mode(ex)) {
+    case tiles::kModeGauss: return launch_tiles_gauss(xo, qo, partial, ex, st);
+    case tiles::kModeGaussExtra: return launch_tiles_gauss_extra(xo, qo, partial, ex, st);
+    case tiles::kModeExponential: return launch_tiles_exponential(xo, qo, partial, ex, st);
+    default: return launch_tiles_logistic(xo, qo, partial, ex, st);
   }
 }
 
@@ -774,10 +248,13 @@ stag_status launch_reduce(const double* partial, int P, const Operands& qo, cons
   return check_launch("reduce_partials");
 }
 
-BoundModel make_bound_model(int form, int d, double a) {
+double kernel_tile_a(int kernel, double a) { return kernel == STAG_KERNEL_GAUSSIAN ? a : a * a * kLog2e; }
+
+BoundModel make_bound_model(int form, int d, double a_tile, int kernel) {
   BoundModel bm;
   const double u = 0x1.0p-24;
-  bm.la = a * kLog2e;
+  bm.la = a_tile * kLog2e;
+  bm.kern = kernel;
   // fp32 accumulation of the d cross products and the six offset parts,
   // probabilistic model with lambda = 6 (Higham & Mary 2019)
   bm.c_acc = 6.0 * std::sqrt((double)d + 6.0) * u;
@@ -796,32 +273,56 @@ BoundModel make_bound_model(int form, int d, double a) {
 
 }  // namespace stag
 
-extern "C" stag_status stag_kde_exact(const float* X, int64_t n, const float* Q, int64_t m, int32_t d, double a,
-                                      double eps, int32_t form, uint32_t flags, double* S_out, double* bound_out,
-                                      hipStream_t stream) {
-  using namespace stag;
-  (void)eps;
-  if (!X || !Q || !S_out) return fail(STAG_E_INVAL, "stag_kde_exact: NULL pointer argument");
-  if (n < 1 || m < 1 || d < 1) return fail(STAG_E_INVAL, "stag_kde_exact: n, m, d must be >= 1");
-  if (!(a > 0.0) || !std::isfinite(a)) return fail(STAG_E_INVAL, "stag_kde_exact: a must be positive and finite");
-  if (form < STAG_FORM_FP32 || form > STAG_FORM_BF16_SPLIT3)
-    return fail(STAG_E_INVAL, "stag_kde_exact: unknown form %d", form);
-  if (flags & ~STAG_NORMALIZE) return fail(STAG_E_INVAL, "stag_kde_exact: unknown flags 0x%x", flags);
-  if (d > 1024) return fail(STAG_E_UNSUPPORTED, "stag_kde_exact: d = %d > 1024 is not supported", d);
+namespace stag {
+namespace {
+
+stag_status exact_kernel_impl(const char* fn, const float* X, int64_t n, const float* Q, int64_t m, int32_t d,
+                              int32_t kernel, double a, int32_t form, uint32_t flags, double* S_out,
+                              double* bound_out, hipStream_t stream) {
+  if (!X || !Q || !S_out) return fail(STAG_E_INVAL, "%s: NULL pointer argument", fn);
+  if (n < 1 || m < 1 || d < 1) return fail(STAG_E_INVAL, "%s: n, m, d must be >= 1", fn);
+  if (!(a > 0.0) || !std::isfinite(a)) return fail(STAG_E_INVAL, "%s: a must be positive and finite", fn);
+  if (kernel < STAG_KERNEL_GAUSSIAN || kernel > STAG_KERNEL_LOGISTIC)
+    return fail(STAG_E_INVAL, "%s: unknown kernel %d", fn, kernel);
+  if (form < STAG_FORM_FP32 || form > STAG_FORM_BF16_SPLIT3) return fail(STAG_E_INVAL, "%s: unknown form %d", fn, form);
+  if (flags & ~STAG_NORMALIZE) return fail(STAG_E_INVAL, "%s: unknown flags 0x%x", fn, flags);
+  if (d > 1024) return fail(STAG_E_UNSUPPORTED, "%s: d = %d > 1024 is not supported", fn, d);
   if (d > 256 && form != STAG_FORM_FP32)
-    return fail(STAG_E_UNSUPPORTED, "stag_kde_exact: d = %d > 256 is supported by the fp32 form only", d);
+    return fail(STAG_E_UNSUPPORTED, "%s: d = %d > 256 is supported by the fp32 form only", fn, d);
   if ((double)n * d >= 2147483648.0 || (double)m * d >= 2147483648.0)
-    return fail(STAG_E_INVAL, "stag_kde_exact: n*d and m*d must be < 2^31");
+    return fail(STAG_E_INVAL, "%s: n*d and m*d must be < 2^31", fn);
+  const double at = kernel_tile_a(kernel, a);
+  if (!std::isfinite(at) || !(at > 0.0)) return fail(STAG_E_INVAL, "%s: a out of range for this kernel", fn);
   clear_error();
   Workspace ws(stream);
   Operands xo, qo;
-  STAG_TRY(prepare_operands(form, X, n, d, a, false, ws, &xo, stream));
-  STAG_TRY(prepare_operands(form, Q, m, d, a, true, ws, &qo, stream));
+  STAG_TRY(prepare_operands(form, X, n, d, at, false, ws, &xo, stream));
+  STAG_TRY(prepare_operands(form, Q, m, d, at, true, ws, &qo, stream));
   const int P = (int)exact_chunks(xo.rows_pad);
   double* partial = nullptr;
   STAG_TRY(ws.alloc(&partial, (size_t)P * qo.rows_pad));
-  STAG_TRY(launch_exact_tiles(xo, qo, partial, TileExtra{}, stream));
+  TileExtra ex;
+  ex.kernel = kernel;
+  STAG_TRY(launch_exact_tiles(xo, qo, partial, ex, stream));
   const double scale = (flags & STAG_NORMALIZE) ? 1.0 / (double)n : 1.0;
-  STAG_TRY(launch_reduce(partial, P, qo, xo, scale, make_bound_model(form, d, a), S_out, bound_out, stream));
+  STAG_TRY(launch_reduce(partial, P, qo, xo, scale, make_bound_model(form, d, at, kernel), S_out, bound_out, stream));
   return STAG_OK;
+}
+
+}  // namespace
+}  // namespace stag
+
+extern "C" stag_status stag_kde_exact(const float* X, int64_t n, const float* Q, int64_t m, int32_t d, double a,
+                                      double eps, int32_t form, uint32_t flags, double* S_out, double* bound_out,
+                                      hipStream_t stream) {
+  (void)eps;
+  return stag::exact_kernel_impl("stag_kde_exact", X, n, Q, m, d, STAG_KERNEL_GAUSSIAN, a, form, flags, S_out,
+                                 bound_out, stream);
+}
+
+extern "C" stag_status stag_kde_exact_kernel(const float* X, int64_t n, const float* Q, int64_t m, int32_t d,
+                                             int32_t kernel, double a, int32_t form, uint32_t flags, double* S_out,
+                                             double* bound_out, hipStream_t stream) {
+  return stag::exact_kernel_impl("stag_kde_exact_kernel", X, n, Q, m, d, kernel, a, form, flags, S_out, bound_out,
+                                 stream);
 }

@@ -1,0 +1,599 @@
+// Matrix-core tiles of the exact kernel density (internal; included by the
+// per-mode translation units kde_tiles_*.hip and, for the shared constants
+// and conversions, by kde_exact.hip).  Each epilogue mode is instantiated in
+// a translation unit of its own so that the four compile in parallel.
+//
+// A tile accumulates E = alpha_q + beta_x + (s q).x (base-2 exponent of the
+// Gaussian, or -lambda D for the other kernels) for 32 data rows x 32 queries
+// per wave; the epilogue turns the 16 values a lane holds into kernel values
+// and an fp32 tree sum, flushed into a per-lane fp64 accumulator.
+#pragma once
+
+#include "runtime.h"
+#include "kde_exact.h"
+
+namespace stag {
+namespace tiles {
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
+
+constexpr double kLog2e = 1.4426950408889634074;
+constexpr int kTileRows = 32;
+constexpr int kWaves = 4;
+constexpr int kBQ = 32 * kWaves;      // queries per workgroup
+constexpr int kChunkRows = 4096;      // data rows per partial sum
+constexpr float kPadOffset = -1.0e30f;  // exponent offset of padding rows: exp2 -> 0
+constexpr unsigned short kBf16One = 0x3F80;
+constexpr int kWideMaxDim = 1024;     // largest d of the wide fp32 tile
+
+__device__ inline unsigned short bf16_rne(float f) {
+  unsigned int u = __float_as_uint(f);
+  if ((u & 0x7F800000u) == 0x7F800000u) return (unsigned short)((u >> 16) | ((u & 0xFFFFu) ? 0x40u : 0u));
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (unsigned short)(u >> 16);
+}
+__device__ inline float bf16_to_f32(unsigned short h) { return __uint_as_float((unsigned int)h << 16); }
+__device__ inline unsigned short f16_rne(float f) { return __builtin_bit_cast(unsigned short, (_Float16)f); }
+__device__ inline float f16_to_f32(unsigned short h) { return (float)__builtin_bit_cast(_Float16, h); }
+
+// Epilogue modes of the tiles.  The accumulators hold E = -lambda D (base 2)
+// with lambda = a log2(e) for the Gaussian kernel and (a log2(e))^2 for the
+// other two, so that for those sqrt(-E) = a log2(e) r:
+//   Gaussian       k = 2^E
+//   exponential    k = 2^-y,             y = sqrt(max(-E, 0)) = a r log2(e)
+//   logistic       k = 4t / (1 + t)^2,   t = 2^-y = e^{-a r}
+// (4t/(1+t)^2 = 4/(2 + e^{ar} + e^{-ar})).  The clamp keeps a NaN exponent NaN.
+// kModeGaussExtra is the Gaussian with the TileExtra outputs.
+constexpr int kModeGauss = 0;
+constexpr int kModeGaussExtra = 1;
+constexpr int kModeExponential = 2;
+constexpr int kModeLogistic = 3;
+
+template <int MODE>
+__device__ inline float kernel_value(float e) {
+  if constexpr (MODE == kModeGauss || MODE == kModeGaussExtra) {
+    return __builtin_amdgcn_exp2f(e);
+  } else {
+    const float ne = -e;
+    const float t = __builtin_amdgcn_exp2f(-__builtin_amdgcn_sqrtf(ne < 0.0f ? 0.0f : ne));
+    if constexpr (MODE == kModeExponential) {
+      return t;
+    } else {
+      const float u = 1.0f + t;
+      return 4.0f * t * __builtin_amdgcn_rcpf(u * u);
+    }
+  }
+}
+
+// Kernel values of one 32x32 accumulator tile held by a lane (16 exponents),
+// summed as a balanced tree in fp32.
+template <int MODE>
+__device__ inline float kernel_tile_sum(const float* c) {
+  float k[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) k[i] = kernel_value<MODE>(c[i]);
+#pragma unroll
+  for (int w = 8; w > 0; w >>= 1)
+#pragma unroll
+    for (int i = 0; i < w; ++i) k[i] = k[i] + k[i + w];
+  return k[0];
+}
+
+// A lane's tile sums of 8 consecutive data tiles (global tile indices
+// 8g .. 8g+7), written to tp as two 16-byte stores once the group is complete
+// (or the chunk ends): the row stride of tp is a multiple of 8 tiles.
+struct TileSums8 {
+  float v[8];
+};
+
+// Epilogue of one finished 32x32 tile held by a lane (column qi, half h):
+// kernel values and fp32 tree sum; in kModeGaussExtra, optionally drops the diagonal element
+// (data row == query index, for a data set queried against itself) and
+// records the tile's 32-row partial sum (both halves, fixed order), through
+// the group buffer `grp` when the caller walks tiles in order (`last` marks
+// the chunk's final tile), else with a direct store.
+template <int MODE>
+__device__ inline float tile_epilogue(const f32x16& c, int64_t row_base, int64_t col_base, int r32, int h,
+                                      int64_t qi, const TileExtra& ex, TileSums8* grp = nullptr,
+                                      bool last = false) {
+  constexpr bool EXTRA = MODE == kModeGaussExtra;
+  float cp[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) cp[i] = c[i];
+  if constexpr (EXTRA) {
+    if (ex.self && row_base == col_base) {
+      // lane (column r32, half h) holds rows 8(i/4) + 4h + i%4
+      const int idg = 4 * (r32 >> 3) + (r32 & 3);
+      const bool mine = h == ((r32 & 7) >> 2);
+#pragma unroll
+      for (int i = 0; i < 16; ++i) cp[i] = (mine && i == idg) ? kPadOffset : cp[i];
+    }
+  }
+  const float s = kernel_tile_sum<MODE>(cp);
+  if constexpr (EXTRA) {
+    if (ex.tp) {
+      const float o = __shfl_xor(s, 32);
+      const float tot = h == 0 ? s + o : o + s;
+      const int64_t tile = row_base / kTileRows;
+      if (grp == nullptr) {
+        if (h == 0) ex.tp[qi * ex.ntile + tile] = tot;
+      } else {
+        const int k = (int)(tile & 7);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) grp->v[e] = e == k ? tot : grp->v[e];
+        if ((k == 7 || last) && h == 0) {
+          f32x4* dst = reinterpret_cast<f32x4*>(ex.tp + qi * ex.ntile + (tile & ~(int64_t)7));
+          dst[0] = f32x4{grp->v[0], grp->v[1], grp->v[2], grp->v[3]};
+          dst[1] = f32x4{grp->v[4], grp->v[5], grp->v[6], grp->v[7]};
+        }
+      }
+    }
+  }
+  return s;
+}
+
+// Split v into parts of the form's element type: v ~= p0 + p1 (+ p2); each
+// remainder is exact in fp32 (Sterbenz), so only the last part is rounded.
+
+// ---------------------------------------------------------------------------
+// Tile loop shared by both forms.  Each step t (one 32-row data tile):
+//   barrier (tile t is in LDS buffer t&1, buffer (t+1)&1 is free)
+//   epilogue of tile t-1: exp2 of its 16 accumulators, fp32 tree sum, fp64 add
+//   matrix-core chain of tile t (independent of the epilogue, so the two are
+//   interleaved in one basic block)
+//   store tile t+1 (loaded into registers one step earlier) to LDS and load
+//   tile t+2 into registers.
+// Staging is branch-free: indices past the end are clamped, so the redundant
+// copies write identical values.  Two steps per loop iteration swap the roles
+// of the two accumulator sets without register copies.
+// ---------------------------------------------------------------------------
+
+// FP32 form: v_mfma_f32_32x32x2_f32.  Lane l supplies A[l%32][k] and
+// B[k][l%32] for the k-slot k = l/32; with the k ordering chosen here, lane
+// half h covers dimensions [h*DP/2, (h+1)*DP/2) of every row.
+template <int DP, int MODE>
+__global__ __launch_bounds__(256, 2) void tile_f32(const float* __restrict__ Xp, const float* __restrict__ beta,
+                                                   const float* __restrict__ Qs, const float* __restrict__ alpha,
+                                                   int64_t n_pad, int n_qtiles, int64_t m_pad,
+                                                   double* __restrict__ partial, TileExtra ex) {
+  constexpr int H = DP / 2;
+  constexpr int LD = DP + 4;  // LDS row stride (floats): 16-byte aligned, rows 4 banks apart
+  constexpr int F4_ROW = DP / 4;
+  constexpr int NV = kTileRows * F4_ROW;
+  constexpr int NLD = (NV + 255) / 256;
+  constexpr int NMMA = H;
+  __shared__ __attribute__((aligned(16))) float tile[2][kTileRows * LD];
+  __shared__ __attribute__((aligned(16))) float tbeta[2][kTileRows];
+
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, r32 = lane & 31, h = lane >> 5;
+  const int qtile = blockIdx.x % n_qtiles;
+  const int chunk = blockIdx.x / n_qtiles;
+  const int64_t col_base = (int64_t)qtile * kBQ + wave * 32;
+  const int64_t qi = col_base + r32;
+
+  float bq[H];
+  {
+    const f32x4* qrow = reinterpret_cast<const f32x4*>(Qs + qi * DP + h * H);
+#pragma unroll
+    for (int s = 0; s < H / 4; ++s) {
+      f32x4 v = qrow[s];
+      bq[4 * s] = v.x; bq[4 * s + 1] = v.y; bq[4 * s + 2] = v.z; bq[4 * s + 3] = v.w;
+    }
+  }
+  const float aq = alpha[qi];
+
+  const int64_t row0 = (int64_t)chunk * kChunkRows;
+  const int64_t rem = (n_pad - row0) / kTileRows;
+  const int ntiles = (int)(rem < kChunkRows / kTileRows ? rem : kChunkRows / kTileRows);
+
+  f32x4 stage[NLD];
+  float sbeta;
+  auto gload = [&](int t) {
+    const f32x4* srcp = reinterpret_cast<const f32x4*>(Xp + (row0 + (int64_t)t * kTileRows) * DP);
+#pragma unroll
+    for (int k = 0; k < NLD; ++k) stage[k] = srcp[min(tid + 256 * k, NV - 1)];
+    sbeta = beta[row0 + (int64_t)t * kTileRows + (tid & 31)];
+  };
+  auto lstore = [&](int buf) {
+#pragma unroll
+    for (int k = 0; k < NLD; ++k) {
+      const int idx = min(tid + 256 * k, NV - 1);
+      const int r = idx / F4_ROW, c4 = idx % F4_ROW;
+      *reinterpret_cast<f32x4*>(&tile[buf][r * LD + c4 * 4]) = stage[k];
+    }
+    tbeta[buf][tid & 31] = sbeta;
+  };
+
+  double acc = 0.0;
+  TileSums8 grp = {};
+  auto step = [&](int t, const f32x16& cdone, f32x16& cnew) {
+    const int buf = t & 1;
+    __syncthreads();
+    if constexpr (MODE == kModeGaussExtra) {
+      if (t > 0)
+        acc += (double)tile_epilogue<MODE>(cdone, row0 + (int64_t)(t - 1) * kTileRows, col_base, r32, h, qi, ex, &grp);
+    } else {
+      acc += (double)tile_epilogue<MODE>(cdone, 0, 0, r32, h, qi, ex);
+    }
+    const float* arow = &tile[buf][r32 * LD + h * H];
+    // the accumulators start from the offsets alpha_q + beta_x of their pairs
+    f32x16 c;
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+      const f32x4 bv = *reinterpret_cast<const f32x4*>(&tbeta[buf][8 * g + 4 * h]);
+      c[4 * g] = aq + bv.x;
+      c[4 * g + 1] = aq + bv.y;
+      c[4 * g + 2] = aq + bv.z;
+      c[4 * g + 3] = aq + bv.w;
+    }
+#pragma unroll
+    for (int s = 0; s < H; s += 4) {
+      const f32x4 a4 = *reinterpret_cast<const f32x4*>(arow + s);
+      c = __builtin_amdgcn_mfma_f32_32x32x2f32(a4.x, bq[s], c, 0, 0, 0);
+      c = __builtin_amdgcn_mfma_f32_32x32x2f32(a4.y, bq[s + 1], c, 0, 0, 0);
+      c = __builtin_amdgcn_mfma_f32_32x32x2f32(a4.z, bq[s + 2], c, 0, 0, 0);
+      c = __builtin_amdgcn_mfma_f32_32x32x2f32(a4.w, bq[s + 3], c, 0, 0, 0);
+    }
+    cnew = c;
+    lstore(buf ^ 1);
+    gload(min(t + 2, ntiles - 1));
+#pragma unroll
+    for (int i = 0; i < NMMA; ++i) {
+      __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+      __builtin_amdgcn_sched_group_barrier(0x002, (40 + NMMA - 1) / NMMA, 0);
+    }
+  };
+
+  gload(0);
+  lstore(0);
+  gload(min(1, ntiles - 1));
+  f32x16 ca, cb;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) ca[i] = kPadOffset;  // kernel value 0: neutral first epilogue
+  int t = 0;
+  for (; t + 1 < ntiles; t += 2) {
+    step(t, ca, cb);
+    step(t + 1, cb, ca);
+  }
+  if (t < ntiles) {
+    step(t, ca, cb);
+    ca = cb;
+  }
+  acc += (double)tile_epilogue<MODE>(ca, row0 + (int64_t)(ntiles - 1) * kTileRows, col_base, r32, h, qi, ex, &grp,
+                                    true);
+  const double other = __shfl_down(acc, 32);
+  if (h == 0) partial[(int64_t)chunk * m_pad + qi] = acc + other;
+}
+
+// Split forms: v_mfma_f32_32x32x16_{f16,bf16}.  Lane l supplies 8 consecutive
+// k values of row/column l%32; lane half h covers dimensions
+// [16 s + 8 h, 16 s + 8 h + 8) of k-step s.
+template <int FORM>
+__device__ inline f32x16 mma16(u16x8 a, u16x8 b, f32x16 c) {
+  if constexpr (FORM == STAG_FORM_FP16_SPLIT)
+    return __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(f16x8, a), __builtin_bit_cast(f16x8, b), c, 0,
+                                                  0, 0);
+  else
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c,
+                                                   0, 0, 0);
+}
+
+__device__ inline f32x16 mma16_bf16(u16x8 a, u16x8 b, f32x16 c) {
+  return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c, 0,
+                                                 0, 0);
+}
+
+template <int FORM, int DP, int MODE>
+__global__ __launch_bounds__(256, 2) void tile_split(
+    const unsigned short* __restrict__ X0, const unsigned short* __restrict__ X1,
+    const unsigned short* __restrict__ X2, const float* __restrict__ Xoff, const unsigned short* __restrict__ Q0,
+    const unsigned short* __restrict__ Q1, const unsigned short* __restrict__ Q2, const float* __restrict__ Qoff,
+    int64_t n_pad, int n_qtiles, int64_t m_pad, double* __restrict__ partial, TileExtra ex) {
+  constexpr int NP = FORM == STAG_FORM_BF16_SPLIT3 ? 3 : 2;
+  constexpr int KS = DP / 16;
+  constexpr int LD = DP + 8;     // LDS row stride (halves): 16-byte aligned
+  constexpr int V_ROW = DP / 8;  // 16-byte vectors per row
+  constexpr int NV = kTileRows * V_ROW;
+  constexpr int NLD = (NV + 255) / 256;
+  constexpr int NMMA = KS * (NP == 3 ? 6 : 3);
+  __shared__ __attribute__((aligned(16))) unsigned short tile[2][NP][kTileRows * LD];
+  __shared__ __attribute__((aligned(16))) float tbeta[2][kTileRows];
+
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, r32 = lane & 31, h = lane >> 5;
+  const int qtile = blockIdx.x % n_qtiles;
+  const int chunk = blockIdx.x / n_qtiles;
+  const int64_t col_base = (int64_t)qtile * kBQ + wave * 32;
+  const int64_t qi = col_base + r32;
+
+  const unsigned short* Qp[3] = {Q0, Q1, Q2};
+  const unsigned short* Xpp[3] = {X0, X1, X2};
+  u16x8 bq[NP][KS];
+#pragma unroll
+  for (int p = 0; p < NP; ++p)
+#pragma unroll
+    for (int s = 0; s < KS; ++s)
+      bq[p][s] = *reinterpret_cast<const u16x8*>(Qp[p] + qi * DP + s * 16 + h * 8);
+  const float alpha = Qoff[qi];
+
+  const int64_t row0 = (int64_t)chunk * kChunkRows;
+  const int64_t rem = (n_pad - row0) / kTileRows;
+  const int ntiles = (int)(rem < kChunkRows / kTileRows ? rem : kChunkRows / kTileRows);
+
+  u16x8 stage[NP][NLD];
+  float sbeta;
+  auto gload = [&](int t) {
+    const int64_t base = (row0 + (int64_t)t * kTileRows) * DP;
+#pragma unroll
+    for (int p = 0; p < NP; ++p)
+#pragma unroll
+      for (int k = 0; k < NLD; ++k)
+        stage[p][k] = reinterpret_cast<const u16x8*>(Xpp[p] + base)[min(tid + 256 * k, NV - 1)];
+    sbeta = Xoff[row0 + (int64_t)t * kTileRows + (tid & 31)];
+  };
+  auto lstore = [&](int buf) {
+#pragma unroll
+    for (int p = 0; p < NP; ++p)
+#pragma unroll
+      for (int k = 0; k < NLD; ++k) {
+        const int idx = min(tid + 256 * k, NV - 1);
+        const int r = idx / V_ROW, c8 = idx % V_ROW;
+        *reinterpret_cast<u16x8*>(&tile[buf][p][r * LD + c8 * 8]) = stage[p][k];
+      }
+    tbeta[buf][tid & 31] = sbeta;
+  };
+
+  double acc = 0.0;
+  TileSums8 grp = {};
+  auto step = [&](int t, const f32x16& cdone, f32x16& cnew) {
+    const int buf = t & 1;
+    __syncthreads();
+    if constexpr (MODE == kModeGaussExtra) {
+      if (t > 0)
+        acc += (double)tile_epilogue<MODE>(cdone, row0 + (int64_t)(t - 1) * kTileRows, col_base, r32, h, qi, ex, &grp);
+    } else {
+      acc += (double)tile_epilogue<MODE>(cdone, 0, 0, r32, h, qi, ex);
+    }
+    // the accumulators start from the offsets alpha_q + beta_x of their pairs
+    f32x16 c;
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+      const f32x4 bv = *reinterpret_cast<const f32x4*>(&tbeta[buf][8 * g + 4 * h]);
+      c[4 * g] = alpha + bv.x;
+      c[4 * g + 1] = alpha + bv.y;
+      c[4 * g + 2] = alpha + bv.z;
+      c[4 * g + 3] = alpha + bv.w;
+    }
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+      u16x8 a[NP];
+#pragma unroll
+      for (int p = 0; p < NP; ++p)
+        a[p] = *reinterpret_cast<const u16x8*>(&tile[buf][p][r32 * LD + s * 16 + h * 8]);
+      // small corrections first, then the leading product
+      if constexpr (NP == 3) {
+        c = mma16<FORM>(a[2], bq[0][s], c);
+        c = mma16<FORM>(a[1], bq[1][s], c);
+        c = mma16<FORM>(a[0], bq[2][s], c);
+      }
+      c = mma16<FORM>(a[1], bq[0][s], c);
+      c = mma16<FORM>(a[0], bq[1][s], c);
+      c = mma16<FORM>(a[0], bq[0][s], c);
+    }
+    cnew = c;
+    lstore(buf ^ 1);
+    gload(min(t + 2, ntiles - 1));
+#pragma unroll
+    for (int i = 0; i < NMMA; ++i) {
+      __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+      __builtin_amdgcn_sched_group_barrier(0x002, (40 + NMMA - 1) / NMMA, 0);
+    }
+  };
+
+  gload(0);
+  lstore(0);
+  gload(min(1, ntiles - 1));
+  f32x16 ca, cb;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) ca[i] = kPadOffset;  // kernel value 0: neutral first epilogue
+  int t = 0;
+  for (; t + 1 < ntiles; t += 2) {
+    step(t, ca, cb);
+    step(t + 1, cb, ca);
+  }
+  if (t < ntiles) {
+    step(t, ca, cb);
+    ca = cb;
+  }
+  acc += (double)tile_epilogue<MODE>(ca, row0 + (int64_t)(ntiles - 1) * kTileRows, col_base, r32, h, qi, ex, &grp,
+                                    true);
+  const double other = __shfl_down(acc, 32);
+  if (h == 0) partial[(int64_t)chunk * m_pad + qi] = acc + other;
+}
+
+// ---------------------------------------------------------------------------
+// Wide rows (256 < d <= 1024), fp32 form.  The 32 queries of a workgroup sit
+// in LDS as the B operand ([32][DP+4] floats, loaded once); each of the 4
+// waves takes every 4th 32-row data tile of the chunk and streams its A
+// operand straight from global memory in blocks of 32 coordinates (register
+// double-buffered).  Per-wave fp64 sums are combined in wave order.
+// ---------------------------------------------------------------------------
+template <int MODE>
+__global__ __launch_bounds__(256) void tile_f32_wide(const float* __restrict__ Xp, const float* __restrict__ beta,
+                                                     const float* __restrict__ Qs, const float* __restrict__ alpha,
+                                                     int DP, int64_t n_pad, int n_qt32, int64_t m_pad,
+                                                     double* __restrict__ partial, TileExtra ex) {
+  extern __shared__ __attribute__((aligned(16))) float qlds[];
+  __shared__ double wsum[4][32];
+  const int H = DP / 2, LD = DP + 4;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, r32 = lane & 31, h = lane >> 5;
+  const int qtile = blockIdx.x % n_qt32;
+  const int chunk = blockIdx.x / n_qt32;
+  const int64_t col_base = (int64_t)qtile * 32;
+  const int64_t qi = col_base + r32;
+  // B operand into LDS
+  {
+    const f32x4* src = reinterpret_cast<const f32x4*>(Qs + col_base * DP);
+    const int nv = 32 * DP / 4;
+    for (int v = tid; v < nv; v += 256) {
+      const int r = (v * 4) / DP, c = (v * 4) % DP;
+      *reinterpret_cast<f32x4*>(&qlds[r * LD + c]) = src[v];
+    }
+  }
+  __syncthreads();
+  const float baug = h == 0 ? alpha[qi] : 1.0f;
+  const int64_t row0 = (int64_t)chunk * kChunkRows;
+  const int64_t rem = (n_pad - row0) / kTileRows;
+  const int ntiles = (int)(rem < kChunkRows / kTileRows ? rem : kChunkRows / kTileRows);
+  const float* brow = &qlds[r32 * LD + h * H];
+  double acc = 0.0;
+  for (int t = wave; t < ntiles; t += 4) {
+    const int64_t rb = row0 + (int64_t)t * kTileRows;
+    const f32x4* arow = reinterpret_cast<const f32x4*>(Xp + (rb + r32) * DP + h * H);
+    f32x16 c = {0};
+    f32x4 a_cur[8], a_nxt[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) a_cur[k] = arow[k];
+    for (int kb = 0; kb < H; kb += 32) {
+      const bool more = kb + 32 < H;
+#pragma unroll
+      for (int k = 0; k < 8; ++k) a_nxt[k] = more ? arow[(kb + 32) / 4 + k] : a_cur[k];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const f32x4 b4 = *reinterpret_cast<const f32x4*>(brow + kb + 4 * k);
+        c = __builtin_amdgcn_mfma_f32_32x32x2f32(a_cur[k].x, b4.x, c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_32x32x2f32(a_cur[k].y, b4.y, c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_32x32x2f32(a_cur[k].z, b4.z, c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_32x32x2f32(a_cur[k].w, b4.w, c, 0, 0, 0);
+      }
+#pragma unroll
+      for (int k = 0; k < 8; ++k) a_cur[k] = a_nxt[k];
+    }
+    const float tb = beta[rb + r32];
+    c = __builtin_amdgcn_mfma_f32_32x32x2f32(h == 0 ? 1.0f : tb, baug, c, 0, 0, 0);
+    acc += (double)tile_epilogue<MODE>(c, rb, col_base, r32, h, qi, ex);
+  }
+  const double other = __shfl_down(acc, 32);
+  if (h == 0) wsum[wave][r32] = acc + other;
+  __syncthreads();
+  if (tid < 32) {
+    const double tot = ((wsum[0][tid] + wsum[1][tid]) + wsum[2][tid]) + wsum[3][tid];
+    partial[(int64_t)chunk * m_pad + col_base + tid] = tot;
+  }
+}
+
+// Epilogue mode of a launch (kernel function, TileExtra outputs).
+inline int tile_mode(const TileExtra& ex) {
+  if (ex.kernel == STAG_KERNEL_EXPONENTIAL) return kModeExponential;
+  if (ex.kernel == STAG_KERNEL_LOGISTIC) return kModeLogistic;
+  return (ex.self || ex.tp) ? kModeGaussExtra : kModeGauss;
+}
+
+template <int DP, int MODE>
+stag_status launch_tile_f32(const float* Xp, const float* beta, const float* Qs, const float* alpha, int64_t n_pad,
+                            int n_qtiles, int64_t m_pad, int P, double* partial, const TileExtra& ex,
+                            hipStream_t st) {
+  ScopedTimer tm("kde_tile_f32", st);
+  hipLaunchKernelGGL((tile_f32<DP, MODE>), dim3((unsigned)((int64_t)n_qtiles * P)), dim3(256), 0, st, Xp, beta, Qs,
+                     alpha, n_pad, n_qtiles, m_pad, partial, ex);
+  return check_launch("tile_f32");
+}
+
+template <int FORM, int DP, int MODE>
+stag_status launch_tile_split(void* const* xp, const float* xaug, void* const* qp, const float* qaug, int64_t n_pad,
+                              int n_qtiles, int64_t m_pad, int P, double* partial, const TileExtra& ex,
+                              hipStream_t st) {
+  using U = const unsigned short*;
+  ScopedTimer tm(FORM == STAG_FORM_FP16_SPLIT ? "kde_tile_fp16x3" : (FORM == STAG_FORM_BF16_SPLIT ? "kde_tile_bf16x3" : "kde_tile_bf16x6"), st);
+  hipLaunchKernelGGL((tile_split<FORM, DP, MODE>), dim3((unsigned)((int64_t)n_qtiles * P)), dim3(256), 0, st,
+                     (U)xp[0], (U)xp[1], (U)xp[2], xaug, (U)qp[0], (U)qp[1], (U)qp[2], qaug, n_pad, n_qtiles, m_pad,
+                     partial, ex);
+  return check_launch("tile_split");
+}
+
+template <int FORM, int MODE>
+stag_status dispatch_split(int dp, void* const* xp, const float* xaug, void* const* qp, const float* qaug,
+                           int64_t n_pad, int n_qtiles, int64_t m_pad, int P, double* partial, const TileExtra& ex,
+                           hipStream_t st) {
+  switch (dp) {
+    case 16: return launch_tile_split<FORM, 16, MODE>(xp, xaug, qp, qaug, n_pad, n_qtiles, m_pad, P, partial, ex, st);
+    case 32: return launch_tile_split<FORM, 32, MODE>(xp, xaug, qp, qaug, n_pad, n_qtiles, m_pad, P, partial, ex, st);
+    case 64: return launch_tile_split<FORM, 64, MODE>(xp, xaug, qp, qaug, n_pad, n_qtiles, m_pad, P, partial, ex, st);
+    case 96: return launch_tile_split<FORM, 96, MODE>(xp, xaug, qp, qaug, n_pad, n_qtiles, m_pad, P, partial, ex, st);
+    case 128: return launch_tile_split<FORM, 128, MODE>(xp, xaug, qp, qaug, n_pad, n_qtiles, m_pad, P, partial, ex, st);
+    case 160: return launch_tile_split<FORM, 160, MODE>(xp, xaug, qp, qaug, n_pad, n_qtiles, m_pad, P, partial, ex, st);
+    case 192: return launch_tile_split<FORM, 192, MODE>(xp, xaug, qp, qaug, n_pad, n_qtiles, m_pad, P, partial, ex, st);
+    case 224: return launch_tile_split<FORM, 224, MODE>(xp, xaug, qp, qaug, n_pad, n_qtiles, m_pad, P, partial, ex, st);
+    case 256: return launch_tile_split<FORM, 256, MODE>(xp, xaug, qp, qaug, n_pad, n_qtiles, m_pad, P, partial, ex, st);
+  }
+  return fail(STAG_E_UNSUPPORTED, "padded dimension %d not instantiated", dp);
+}
+
+template <int MODE>
+stag_status dispatch_f32(int dp, const float* Xp, const float* beta, const float* Qs, const float* alpha,
+                         int64_t n_pad, int n_qtiles, int64_t m_pad, int P, double* partial, const TileExtra& ex,
+                         hipStream_t st) {
+  switch (dp) {
+    case 16: return launch_tile_f32<16, MODE>(Xp, beta, Qs, alpha, n_pad, n_qtiles, m_pad, P, partial, ex, st);
+    case 32: return launch_tile_f32<32, MODE>(Xp, beta, Qs, alpha, n_pad, n_qtiles, m_pad, P, partial, ex, st);
+    case 64: return launch_tile_f32<64, MODE>(Xp, beta, Qs, alpha, n_pad, n_qtiles, m_pad, P, partial, ex, st);
+    case 96: return launch_tile_f32<96, MODE>(Xp, beta, Qs, alpha, n_pad, n_qtiles, m_pad, P, partial, ex, st);
+    case 128: return launch_tile_f32<128, MODE>(Xp, beta, Qs, alpha, n_pad, n_qtiles, m_pad, P, partial, ex, st);
+    case 160: return launch_tile_f32<160, MODE>(Xp, beta, Qs, alpha, n_pad, n_qtiles, m_pad, P, partial, ex, st);
+    case 192: return launch_tile_f32<192, MODE>(Xp, beta, Qs, alpha, n_pad, n_qtiles, m_pad, P, partial, ex, st);
+    case 224: return launch_tile_f32<224, MODE>(Xp, beta, Qs, alpha, n_pad, n_qtiles, m_pad, P, partial, ex, st);
+    case 256: return launch_tile_f32<256, MODE>(Xp, beta, Qs, alpha, n_pad, n_qtiles, m_pad, P, partial, ex, st);
+  }
+  return fail(STAG_E_UNSUPPORTED, "padded dimension %d not instantiated", dp);
+}
+// All tiles of one launch in epilogue mode MODE: wide fp32 rows, the fp32
+// tile or a split form, by padded dimension.
+template <int MODE>
+stag_status launch_tiles(const Operands& xo, const Operands& qo, double* partial, const TileExtra& ex,
+                         hipStream_t st) {
+  const int P = (int)exact_chunks(xo.rows_pad);
+  const int n_qtiles = (int)(qo.rows_pad / kBQ);
+  if (xo.dp > 256) {
+    if (xo.form != STAG_FORM_FP32) return fail(STAG_E_UNSUPPORTED, "d > 256 needs the fp32 form");
+    const int n_qt32 = (int)(qo.rows_pad / 32);
+    const size_t lds = (size_t)32 * (xo.dp + 4) * sizeof(float);
+    STAG_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&tile_f32_wide<MODE>),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    ScopedTimer tm("kde_tile_f32_wide", st);
+    hipLaunchKernelGGL(tile_f32_wide<MODE>, dim3((unsigned)((int64_t)n_qt32 * P)), dim3(256), lds, st,
+                       (const float*)xo.part[0], xo.off, (const float*)qo.part[0], qo.off, xo.dp, xo.rows_pad,
+                       n_qt32, qo.rows_pad, partial, ex);
+    return check_launch("tile_f32_wide");
+  }
+  if (xo.form == STAG_FORM_FP32)
+    return dispatch_f32<MODE>(xo.dp, (const float*)xo.part[0], xo.off, (const float*)qo.part[0], qo.off,
+                              xo.rows_pad, n_qtiles, qo.rows_pad, P, partial, ex, st);
+  switch (xo.form) {
+    case STAG_FORM_BF16_SPLIT:
+      return dispatch_split<STAG_FORM_BF16_SPLIT, MODE>(xo.dp, xo.part, xo.off, qo.part, qo.off, xo.rows_pad,
+                                                        n_qtiles, qo.rows_pad, P, partial, ex, st);
+    case STAG_FORM_FP16_SPLIT:
+      return dispatch_split<STAG_FORM_FP16_SPLIT, MODE>(xo.dp, xo.part, xo.off, qo.part, qo.off, xo.rows_pad,
+                                                        n_qtiles, qo.rows_pad, P, partial, ex, st);
+    default:
+      return dispatch_split<STAG_FORM_BF16_SPLIT3, MODE>(xo.dp, xo.part, xo.off, qo.part, qo.off, xo.rows_pad,
+                                                         n_qtiles, qo.rows_pad, P, partial, ex, st);
+  }
+}
+
+}  // namespace tiles
+
+// Per-mode entry points (one translation unit each).
+stag_status launch_tiles_gauss(const Operands& xo, const Operands& qo, double* partial, const TileExtra& ex,
+                               hipStream_t st);
+stag_status launch_tiles_gauss_extra(const Operands& xo, const Operands& qo, double* partial, const TileExtra& ex,
+                                     hipStream_t st);
+stag_status launch_tiles_exponential(const Operands& xo, const Operands& qo, double* partial, const TileExtra& ex,
+                                     hipStream_t st);
+stag_status launch_tiles_logistic(const Operands& xo, const Operands& qo, double* partial, const TileExtra& ex,
+                                  hipStream_t st);
+
+}  // namespace stag

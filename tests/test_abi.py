@@ -45,6 +45,16 @@ def test_invalid_arguments_rejected_before_launch():
     assert st == _lib.STAG_E_INVAL
     st = lib.stag_kde_exact(fake, 10, fake, 10, 4, 1.0, 0.0, 0, 0x80, fake, null, null)
     assert st == _lib.STAG_E_INVAL
+    st = lib.stag_kde_exact_kernel(fake, 10, fake, 10, 4, 3, 1.0, 0, 0, fake, null, null)
+    assert st == _lib.STAG_E_INVAL and "unknown kernel" in stag.last_error()
+    st = lib.stag_kde_exact_kernel(fake, 10, fake, 10, 4, -1, 1.0, 0, 0, fake, null, null)
+    assert st == _lib.STAG_E_INVAL
+    st = lib.stag_kde_exact_kernel(fake, 10, fake, 10, 4, 1, 0.0, 0, 0, fake, null, null)
+    assert st == _lib.STAG_E_INVAL and "a must be" in stag.last_error()
+    st = lib.stag_kde_exact_kernel(fake, 10, fake, 10, 4, 2, 1e200, 0, 0, fake, null, null)
+    assert st == _lib.STAG_E_INVAL and "out of range" in stag.last_error()
+    st = lib.stag_kde_exact_kernel(fake, 10, fake, 10, 300, 1, 1.0, 2, 0, fake, null, null)
+    assert st == _lib.STAG_E_UNSUPPORTED
     st = lib.stag_e2lsh_hash(fake, 10, 4, fake, fake, 0, 3, fake, null, null)
     assert st == _lib.STAG_E_INVAL
     st = lib.stag_e2lsh_hash(fake, 10, 4, fake, fake, 2, 3, null, null, null)
