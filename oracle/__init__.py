@@ -3,8 +3,9 @@
 Only the test suite, the smoke check and the benchmark's CPU-baseline leg may
 import this package.  The product library does not depend on it and shares no
 code with it.  Every function here is a thin numpy/ctypes shim over
-``oracle.cpp``; the arithmetic lives there, each function citing the passage
-of the paper it follows.
+``oracle.cpp``, where the arithmetic lives, each function citing the passage
+of the paper it follows; the spectral embedding is plain numpy
+(``oracle/spectral.py``).
 """
 from __future__ import annotations
 
@@ -55,6 +56,9 @@ def _load():
     lib.orc_kde_kernel.argtypes = [f32p, C.c_int64, f32p, C.c_int64, C.c_int32, C.c_int32, C.c_double, f64p, C.c_int32]
     lib.orc_kernel_value.restype = C.c_double
     lib.orc_kernel_value.argtypes = [C.c_int32, C.c_double, C.c_double]
+    lib.orc_kmeans.restype = C.c_int32
+    lib.orc_kmeans.argtypes = [f64p, C.c_int64, C.c_int32, C.c_int32, C.c_uint64, C.c_int32, f64p, i32p, f64p,
+                               C.POINTER(C.c_int32), i64p]
     lib.orc_kernel_row.restype = None
     lib.orc_kernel_row.argtypes = [f32p, C.c_int64, C.c_int32, C.c_double, C.c_int64, f64p]
     lib.orc_e2lsh_hash.restype = None
@@ -152,6 +156,26 @@ def kde_kernel(X, Q, a: float, kernel: str = "gaussian", nthreads: int = 0):
 
 def kernel_value(kernel: str, a: float, r: float) -> float:
     return float(_load().orc_kernel_value(KERNELS[kernel], float(a), float(r)))
+
+
+def kmeans(P, k: int, seed: int, max_iter: int = 300, init=None):
+    """k-means (Lloyd, k-means++ seeding) as stated in oracle.cpp; returns
+    (labels int32 [n], centres float64 [k][dim], iterations, seed indices)."""
+    P = np.ascontiguousarray(P, dtype=np.float64)
+    n, dim = P.shape
+    labels = np.empty(n, dtype=np.int32)
+    Cm = np.empty((k, dim), dtype=np.float64)
+    seeds = np.empty(k, dtype=np.int64)
+    it = C.c_int32(0)
+    ini = None
+    if init is not None:
+        ini = np.ascontiguousarray(init, dtype=np.float64)
+        assert ini.shape == (k, dim)
+    rc = _load().orc_kmeans(_p(P, C.c_double), n, dim, int(k), C.c_uint64(int(seed) & (2**64 - 1)), int(max_iter),
+                            None if ini is None else _p(ini, C.c_double), _p(labels, C.c_int32), _p(Cm, C.c_double),
+                            C.byref(it), _p(seeds, C.c_int64))
+    assert rc == 0
+    return labels, Cm, int(it.value), seeds
 
 
 def kernel_row(X, a: float, i: int):

@@ -681,4 +681,143 @@ int32_t orc_simgraph_lsh(const float* X, int64_t n, int32_t d, double a, double 
   return 0;
 }
 
+
+// ---------------------------------------------------------------------------
+// k-means for the third step of spectral clustering (Sec. "Fast Spectral
+// Clustering": k-means on the embedded points).  Lloyd's iteration with
+// k-means++ seeding (Arthur & Vassilvitskii 2007: first centre uniform, each
+// further centre drawn with probability proportional to the squared distance
+// to the nearest chosen centre).  The paper names k-means only; the seeding,
+// the tie rules and the summation orders below are this library's reading,
+// written out so that every decision is reproducible:
+//   dist2(p, c)  = sum over j ascending of (p_j - c_j)^2, each subtraction,
+//                  product and addition rounded (no fused operations);
+//   U_r          = (counter_bits(seed, "KMNS", 0, 0, r) >> 11) 2^-53;
+//   first centre = floor(U_0 n), taken exactly with integer arithmetic;
+//   centre c > 0 = the first point i with Cum(i) > U_c T, where D2(i) is the
+//                  squared distance to the nearest chosen centre, points are
+//                  grouped in blocks of 1024, S_b is the sequential sum of D2
+//                  over block b, B_b the sequential sum of S_0..S_{b-1},
+//                  Cum(i) = B_b + (sequential sum of D2 over block b up to and
+//                  including i) and T = B_{nb}; if no point qualifies (U_c T
+//                  rounded up to T) the last point with D2 > 0; if T = 0 the
+//                  lowest index not chosen yet;
+//   assignment   = argmin over centres of dist2, ties to the lowest centre;
+//   update       = per cluster, coordinate sums in the same blocked order
+//                  (sequential over the points of a block, then over blocks),
+//                  divided by the count; an empty cluster keeps its centre;
+//   stop         = after an assignment that changes no label (the centres are
+//                  then those the labels were assigned with) or after max_iter
+//                  assignment + update rounds.
+// ---------------------------------------------------------------------------
+const uint64_t kTagKmeans = 0x4B4D4E53ULL;  // "KMNS"
+const int64_t kKmBlock = 1024;
+
+double dist2_seq(const double* p, const double* c, int32_t dim) {
+  double s = 0.0;
+  for (int32_t j = 0; j < dim; ++j) {
+    const double t = p[j] - c[j];
+    s = s + t * t;
+  }
+  return s;
+}
+
+double kmeans_uniform(uint64_t seed, int64_t r) {
+  return (double)(counter_bits(seed, kTagKmeans, 0, 0, (uint64_t)r) >> 11) * 0x1.0p-53;
+}
+
+// Returns 0, or -1 for invalid sizes.  init (k x dim) replaces the seeding
+// when not NULL; seeds_out (k) receives the seeded point indices (-1 with init).
+int32_t orc_kmeans(const double* P, int64_t n, int32_t dim, int32_t k, uint64_t seed, int32_t max_iter,
+                   const double* init, int32_t* labels, double* C, int32_t* iters_out, int64_t* seeds_out) {
+  if (n < 1 || dim < 1 || k < 1 || k > n || max_iter < 1) return -1;
+  const int64_t nb = (n + kKmBlock - 1) / kKmBlock;
+  if (init) {
+    std::memcpy(C, init, sizeof(double) * (size_t)k * dim);
+    if (seeds_out)
+      for (int32_t c = 0; c < k; ++c) seeds_out[c] = -1;
+  } else {
+    std::vector<double> D2((size_t)n, INFINITY);
+    std::vector<char> chosen((size_t)n, 0);
+    const uint64_t u0 = counter_bits(seed, kTagKmeans, 0, 0, 0) >> 11;
+    int64_t pick = (int64_t)(((unsigned __int128)u0 * (uint64_t)n) >> 53);
+    for (int32_t c = 0; c < k; ++c) {
+      if (c > 0) {
+        const double* last = C + (size_t)(c - 1) * dim;
+        for (int64_t i = 0; i < n; ++i) D2[i] = std::min(D2[i], dist2_seq(P + (size_t)i * dim, last, dim));
+        std::vector<double> B((size_t)nb + 1, 0.0);
+        for (int64_t b = 0; b < nb; ++b) {
+          double sb = 0.0;
+          for (int64_t i = b * kKmBlock; i < std::min(n, (b + 1) * kKmBlock); ++i) sb = sb + D2[i];
+          B[b + 1] = B[b] + sb;
+        }
+        const double T = B[nb];
+        pick = -1;
+        if (T > 0.0) {
+          const double t = kmeans_uniform(seed, c) * T;
+          for (int64_t b = 0; b < nb && pick < 0; ++b) {
+            if (!(B[b + 1] > t)) continue;
+            double cum = 0.0;
+            for (int64_t i = b * kKmBlock; i < std::min(n, (b + 1) * kKmBlock); ++i) {
+              cum = cum + D2[i];
+              if (B[b] + cum > t) {
+                pick = i;
+                break;
+              }
+            }
+          }
+          if (pick < 0)
+            for (int64_t i = n - 1; i >= 0 && pick < 0; --i)
+              if (D2[i] > 0.0) pick = i;
+        } else {
+          for (int64_t i = 0; i < n && pick < 0; ++i)
+            if (!chosen[i]) pick = i;
+        }
+      }
+      chosen[pick] = 1;
+      if (seeds_out) seeds_out[c] = pick;
+      std::memcpy(C + (size_t)c * dim, P + (size_t)pick * dim, sizeof(double) * dim);
+    }
+  }
+  for (int64_t i = 0; i < n; ++i) labels[i] = -1;
+  std::vector<double> tot((size_t)k * dim), acc((size_t)k * dim);
+  std::vector<int64_t> cnt((size_t)k);
+  int32_t it = 0;
+  while (it < max_iter) {
+    ++it;
+    bool changed = false;
+    for (int64_t i = 0; i < n; ++i) {
+      const double* p = P + (size_t)i * dim;
+      int32_t best = 0;
+      double bd = dist2_seq(p, C, dim);
+      for (int32_t c = 1; c < k; ++c) {
+        const double dc = dist2_seq(p, C + (size_t)c * dim, dim);
+        if (dc < bd) {
+          bd = dc;
+          best = c;
+        }
+      }
+      if (labels[i] != best) changed = true;
+      labels[i] = best;
+    }
+    if (!changed) break;
+    std::fill(tot.begin(), tot.end(), 0.0);
+    std::fill(cnt.begin(), cnt.end(), 0);
+    for (int64_t b = 0; b < nb; ++b) {
+      std::fill(acc.begin(), acc.end(), 0.0);
+      for (int64_t i = b * kKmBlock; i < std::min(n, (b + 1) * kKmBlock); ++i) {
+        const int32_t l = labels[i];
+        cnt[l] += 1;
+        for (int32_t j = 0; j < dim; ++j) acc[(size_t)l * dim + j] = acc[(size_t)l * dim + j] + P[(size_t)i * dim + j];
+      }
+      for (size_t e = 0; e < tot.size(); ++e) tot[e] = tot[e] + acc[e];
+    }
+    for (int32_t c = 0; c < k; ++c)
+      if (cnt[c] > 0)
+        for (int32_t j = 0; j < dim; ++j) C[(size_t)c * dim + j] = tot[(size_t)c * dim + j] / (double)cnt[c];
+  }
+  *iters_out = it;
+  return 0;
+}
+
 }  // extern "C"
