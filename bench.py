@@ -162,6 +162,47 @@ def kernels_run(stag, torch, dev, lib, buf, X, Q, Xd, Qd, form: str, n_check: in
     return out
 
 
+def spectral_run(stag, torch, lib, buf, graph, n: int, k: int, labels_true, seed: int = 4003):
+    """Spectral clustering of the step's sampled graph (k = the mixture's
+    component count): embedding (bottom-k eigenvectors of the normalised
+    Laplacian) and k-means times with their kernels, the largest eigen-residual
+    ||N u - lambda u|| recomputed on the host from the downloaded graph, and
+    the purity of the clusters against the mixture components."""
+    import numpy as np
+    from scipy.sparse import coo_matrix
+    src, dst, w, _ = graph
+    stag.spectral_embedding(n, src, dst, w, k, seed=seed)  # warm-up
+    torch.cuda.synchronize()
+    lib.stag_timing_report(buf, len(buf))
+    lib.stag_timing_enable(1)
+    t0 = time.perf_counter()
+    lam, U, iters = stag.spectral_embedding(n, src, dst, w, k, seed=seed)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    lab, _, rounds, _ = stag.kmeans(U, k, seed=seed)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    lib.stag_timing_enable(0)
+    lib.stag_timing_report(buf, len(buf))
+    tm = parse_timing(buf.value.decode())
+    s_, d_, w_ = (t.cpu().numpy() for t in (src, dst, w))
+    ok = d_ >= 0
+    A = coo_matrix((np.concatenate([w_[ok], w_[ok]]), (np.concatenate([s_[ok], d_[ok]]),
+                                                       np.concatenate([d_[ok], s_[ok]]))), shape=(n, n)).tocsr()
+    deg = np.asarray(A.sum(axis=1)).ravel()
+    dinv = np.where(deg > 0, 1.0 / np.sqrt(np.where(deg > 0, deg, 1.0)), 0.0)
+    Uh, lh = U.cpu().numpy(), lam.cpu().numpy()
+    NU = Uh - dinv[:, None] * (A @ (dinv[:, None] * Uh))
+    res = float(np.linalg.norm(NU - Uh * lh[None, :], axis=0).max())
+    labh = lab.cpu().numpy()
+    purity = sum(np.bincount(labh[labels_true == c]).max() for c in range(k) if np.any(labels_true == c)) / n
+    return {"workload": f"spectral clustering of the step's sampled graph: n={n}, {int(ok.sum())} edges, k={k}",
+            "embedding_ms": (t1 - t0) * 1e3, "kmeans_ms": (t2 - t1) * 1e3, "filter_steps": iters,
+            "kmeans_rounds": rounds, "eigenvalues_head": [float(v) for v in lh[:4]],
+            "eigenvalue_k": float(lh[-1]), "max_residual_host": res, "purity_vs_components": float(purity),
+            "kernels_ms": {kk: v[1] for kk, v in tm.items()}}
+
+
 def e2lsh_table_run(stag, torch, dev, lib, buf, Xd, Qd, K: int = 6, L: int = 50):
     """E2LSH table (K = 6, L = 50, the paper's example) over the step's data:
     build and near-neighbour listing of all queries, with kernel times."""
@@ -463,6 +504,7 @@ def main():
         result["fp32_form"] = {"tile_ms": t32["kde_tile_f32"][1], "max_rel_err_sampled": err32,
                                "evals_per_s_tile": evals / (t32["kde_tile_f32"][1] / 1e3)}
         result["split_form_tile_ms"] = tile_avg
+    graph = out["graph"]
     del out
     if args.calib_copy_mb > 0:
         src_c = torch.ones(args.calib_copy_mb << 18, dtype=torch.float32, device=dev)
@@ -474,6 +516,8 @@ def main():
         del src_c, dst_c
     result["e2lsh_table"] = e2lsh_table_run(stag, torch, dev, lib, buf, Xd, Qd)
     result["kernels"] = kernels_run(stag, torch, dev, lib, buf, X, Q, Xd, Qd, args.form)
+    result["spectral"] = spectral_run(stag, torch, lib, buf, graph, n, info["k"], info["labels"])
+    del graph
     if not args.no_precision_config:
         result["precision_config"] = precision_config_run(stag, torch, dev, lib, buf)
     if not args.no_serve:

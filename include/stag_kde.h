@@ -293,6 +293,66 @@ stag_status stag_simgraph_sample(const float* X, int64_t n, int32_t d, double a,
                                  hipStream_t stream);
 
 /* ------------------------------------------------------------------------
+ * Spectral clustering (Sec. "Fast Spectral Clustering": a similarity graph,
+ * the bottom k eigenvectors of its Laplacian as an embedding in R^k, then
+ * k-means on the embedded vertices; spectral_cluster).
+ *
+ * Graph: an edge list src/dst int64 [n_edges], w f64 [n_edges] (device), as
+ * written by stag_simgraph_sample: every edge adds w to A[src][dst] and to
+ * A[dst][src] (duplicates add up, a self loop adds 2w to A[i][i]); dst = -1
+ * marks an empty draw and is skipped.  Any other index outside [0, n), or a
+ * negative or non-finite weight, is STAG_E_INVAL (checked on the device
+ * before any further work).  Limits: 1 <= n < 2^31, 0 <= n_edges < 2^30.
+ * Laplacian: the normalised N = I - D^{-1/2} A D^{-1/2}, D the row sums of A,
+ * with D^{-1/2} = 0 for an isolated vertex.
+ * ------------------------------------------------------------------------ */
+
+/* Bottom k eigenpairs of N (1 <= k <= min(56, n)) by Chebyshev-filtered
+ * subspace iteration on M = I - N with a block of 8..64 columns, until every
+ * residual ||M u_j - theta_j u_j|| <= tol (tol > 0) or after max_iter filter
+ * steps (>= 0).  seed selects the random starting block.
+ *   eigvals_out [k] f64 device or NULL: eigenvalues of N, ascending.
+ *   U_out [n][k] f64 device: row i is vertex i's embedding; column j is the
+ *     unit eigenvector of eigvals_out[j], its entry of largest magnitude (the
+ *     lowest row among equals) positive.
+ *   iters_out (host, may be NULL): filter steps taken.
+ * Synchronises `stream` several times per step; deterministic. */
+stag_status stag_spectral_embedding(int64_t n, const int64_t* src, const int64_t* dst, const double* w,
+                                    int64_t n_edges, int32_t k, double tol, int32_t max_iter, uint64_t seed,
+                                    double* eigvals_out, double* U_out, int32_t* iters_out, hipStream_t stream);
+
+/* k-means of the n points P [n][dim] (f64 device) into k clusters (1 <= k <=
+ * n, k*dim <= 4096): Lloyd's iteration from init [k][dim] (device) or, with
+ * init NULL, from k-means++ seeding.  Every decision is specified:
+ *   dist2(p, c) = sum over j ascending of (p_j - c_j)^2, each operation
+ *     rounded separately (no fused multiply-add);
+ *   U_r = (s >> 11) 2^-53 with s = mix(t + (r+1) 0x9E3779B97F4A7C15),
+ *     t = mix(mix(mix(seed ^ 0x4B4D4E53))), mix the SplitMix64 finaliser;
+ *   seed 0 = floor(U_0 n) (exact integer product); seed c > 0 = the first
+ *     point i with B_b + (sum of D2 over block b up to i) > U_c T, where D2
+ *     is the squared distance to the nearest chosen seed, blocks hold 1024
+ *     points, B_b is the sum of the block sums before b, T the total (all
+ *     sums sequential); if none, the last point with D2 > 0; if T = 0, the
+ *     lowest index not chosen yet;
+ *   assignment: the nearest centre, ties to the lowest index;
+ *   update: per cluster, coordinate sums in the same blocked order divided by
+ *     the count; an empty cluster keeps its centre;
+ *   stop: after an assignment that changes no label (centres are those the
+ *     labels were assigned with), or after max_iter (>= 1) rounds.
+ * labels_out [n] int32 device; centroids_out [k][dim] f64 device or NULL;
+ * seeds_out [k] int64 device or NULL (-1 with init); iters_out host or NULL
+ * (assignment rounds).  Deterministic; synchronises `stream` once per round. */
+stag_status stag_kmeans(const double* P, int64_t n, int32_t dim, int32_t k, uint64_t seed, int32_t max_iter,
+                        const double* init, int32_t* labels_out, double* centroids_out, int64_t* seeds_out,
+                        int32_t* iters_out, hipStream_t stream);
+
+/* stag_spectral_embedding (tol 1e-8, at most 300 steps) followed by
+ * stag_kmeans of the embedding (dim = k, k-means++ with the same seed, at
+ * most 300 rounds): labels_out [n] int32 device. */
+stag_status stag_spectral_cluster(int64_t n, const int64_t* src, const int64_t* dst, const double* w, int64_t n_edges,
+                                  int32_t k, uint64_t seed, int32_t* labels_out, hipStream_t stream);
+
+/* ------------------------------------------------------------------------
  * Serving loop: continuous batching of exact kernel-density requests against
  * resident data sets.
  *   - A data set (X, a, form) is prepared once and stays in device memory.

@@ -62,6 +62,7 @@ def load():
                            "there is no CPU fallback")
     lib = C.CDLL(LIB_PATH)
     vp, i64, i32, u32, f64 = C.c_void_p, C.c_int64, C.c_int32, C.c_uint32, C.c_double
+    u64 = C.c_uint64
     lib.stag_last_error.restype = C.c_char_p
     lib.stag_last_error.argtypes = []
     lib.stag_version.restype = C.c_char_p
@@ -72,6 +73,12 @@ def load():
     lib.stag_kde_exact.argtypes = [vp, i64, vp, i64, i32, f64, f64, i32, u32, vp, vp, vp]
     lib.stag_kde_exact_kernel.restype = C.c_int
     lib.stag_kde_exact_kernel.argtypes = [vp, i64, vp, i64, i32, i32, f64, i32, u32, vp, vp, vp]
+    lib.stag_spectral_embedding.restype = C.c_int
+    lib.stag_spectral_embedding.argtypes = [i64, vp, vp, vp, i64, i32, f64, i32, u64, vp, vp, C.POINTER(C.c_int32), vp]
+    lib.stag_kmeans.restype = C.c_int
+    lib.stag_kmeans.argtypes = [vp, i64, i32, i32, u64, i32, vp, vp, vp, vp, C.POINTER(C.c_int32), vp]
+    lib.stag_spectral_cluster.restype = C.c_int
+    lib.stag_spectral_cluster.argtypes = [i64, vp, vp, vp, i64, i32, u64, vp, vp]
     lib.stag_e2lsh_hash.restype = C.c_int
     lib.stag_e2lsh_hash.argtypes = [vp, i64, i32, vp, vp, i32, i32, vp, vp, vp]
     pp = C.POINTER(LshParams)
@@ -375,6 +382,62 @@ def simgraph_sample(X, a: float, samples_per_node: int = 0, mode: str = "exact",
                                      _ptr(w), _ptr(deg), _stream_handle(X.device))
     check(st, "stag_simgraph_sample")
     return src, dst, w, deg
+
+
+def _edges(src, dst, w):
+    torch = _torch()
+    _need(src, torch.int64, 1, "src")
+    _need(dst, torch.int64, 1, "dst")
+    _need(w, torch.float64, 1, "w")
+    if not (src.shape == dst.shape == w.shape):
+        raise ValueError("src, dst and w must have the same length")
+    return src.shape[0]
+
+
+def spectral_embedding(n: int, src, dst, w, k: int, tol: float = 1e-8, max_iter: int = 300, seed: int = 0):
+    """Bottom-k eigenpairs of the normalised Laplacian of the edge-list graph:
+    (eigenvalues float64 [k] ascending, U float64 [n][k], filter steps)."""
+    torch = _torch()
+    E = _edges(src, dst, w)
+    lam = torch.empty(k, dtype=torch.float64, device=src.device)
+    U = torch.empty((n, k), dtype=torch.float64, device=src.device)
+    it = C.c_int32(0)
+    st = load().stag_spectral_embedding(int(n), _ptr(src), _ptr(dst), _ptr(w), E, int(k), float(tol), int(max_iter),
+                                        int(seed) & 0xFFFFFFFFFFFFFFFF, _ptr(lam), _ptr(U), C.byref(it),
+                                        _stream_handle(src.device))
+    check(st, "stag_spectral_embedding")
+    return lam, U, int(it.value)
+
+
+def kmeans(P, k: int, seed: int = 0, max_iter: int = 300, init=None):
+    """k-means of the rows of P (float64 [n][dim]): (labels int32 [n],
+    centroids float64 [k][dim], rounds, seed indices int64 [k])."""
+    torch = _torch()
+    _need(P, torch.float64, 2, "P")
+    n, dim = P.shape
+    if init is not None:
+        _need(init, torch.float64, 2, "init")
+        if tuple(init.shape) != (k, dim):
+            raise ValueError("init must be [k][dim]")
+    labels = torch.empty(n, dtype=torch.int32, device=P.device)
+    Cm = torch.empty((k, dim), dtype=torch.float64, device=P.device)
+    seeds = torch.empty(k, dtype=torch.int64, device=P.device)
+    it = C.c_int32(0)
+    st = load().stag_kmeans(_ptr(P), n, dim, int(k), int(seed) & 0xFFFFFFFFFFFFFFFF, int(max_iter), _ptr(init),
+                            _ptr(labels), _ptr(Cm), _ptr(seeds), C.byref(it), _stream_handle(P.device))
+    check(st, "stag_kmeans")
+    return labels, Cm, int(it.value), seeds
+
+
+def spectral_cluster(n: int, src, dst, w, k: int, seed: int = 0):
+    """Cluster labels (int32 [n]) of the edge-list graph: embedding + k-means."""
+    torch = _torch()
+    E = _edges(src, dst, w)
+    labels = torch.empty(n, dtype=torch.int32, device=src.device)
+    st = load().stag_spectral_cluster(int(n), _ptr(src), _ptr(dst), _ptr(w), E, int(k),
+                                      int(seed) & 0xFFFFFFFFFFFFFFFF, _ptr(labels), _stream_handle(src.device))
+    check(st, "stag_spectral_cluster")
+    return labels
 
 
 class Server:

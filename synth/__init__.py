@@ -106,7 +106,8 @@ def config_points(cfg: int, n: int | None = None, m: int | None = None, queries_
          (the precision-form workload);
       4: n = 70,000, d = 784, entries 0 with probability 0.8 else U[0,1]
          (queries are the data; edge sampling).
-    Queries are fresh draws from the same mixture (or rows of X)."""
+    Queries are fresh draws from the same mixture (or rows of X); for the
+    mixtures info["labels"] holds each data point's component."""
     if cfg == 1:
         d, k, sig, n0, m0 = 10, 5, 1.0, 1000, 1000
     elif cfg == 2:
@@ -122,13 +123,13 @@ def config_points(cfg: int, n: int | None = None, m: int | None = None, queries_
     n = n0 if n is None else n
     m = m0 if m is None else m
     mix = mixture(d, k, 1000 + cfg, sigma=sig)
-    X = sample(mix, n, 1000 + cfg + 10_000)
+    X, lab = sample(mix, n, 1000 + cfg + 10_000, return_labels=True)
     if queries_from_data:
         rng = np.random.default_rng(2000 + cfg)
         Q = np.ascontiguousarray(X[rng.choice(n, size=m, replace=m > n)])
     else:
         Q = sample(mix, m, 2000 + cfg)
-    return X, Q, {"d": d, "n": n, "m": m, "k": k}
+    return X, Q, {"d": d, "n": n, "m": m, "k": k, "labels": lab}
 
 
 def poisson_requests(count: int, rate_per_s: float, seed: int, max_batch: int = 65536,

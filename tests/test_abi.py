@@ -55,6 +55,25 @@ def test_invalid_arguments_rejected_before_launch():
     assert st == _lib.STAG_E_INVAL and "out of range" in stag.last_error()
     st = lib.stag_kde_exact_kernel(fake, 10, fake, 10, 300, 1, 1.0, 2, 0, fake, null, null)
     assert st == _lib.STAG_E_UNSUPPORTED
+    it = C.c_int32(0)
+    st = lib.stag_spectral_embedding(10, fake, fake, fake, 5, 0, 1e-8, 10, 0, null, fake, C.byref(it), null)
+    assert st == _lib.STAG_E_INVAL and "k must be" in stag.last_error()
+    st = lib.stag_spectral_embedding(10, fake, fake, fake, 5, 57, 1e-8, 10, 0, null, fake, C.byref(it), null)
+    assert st == _lib.STAG_E_INVAL
+    st = lib.stag_spectral_embedding(3, fake, fake, fake, 5, 4, 1e-8, 10, 0, null, fake, C.byref(it), null)
+    assert st == _lib.STAG_E_INVAL
+    st = lib.stag_spectral_embedding(10, null, fake, fake, 5, 2, 1e-8, 10, 0, null, fake, C.byref(it), null)
+    assert st == _lib.STAG_E_INVAL and "NULL" in stag.last_error()
+    st = lib.stag_spectral_embedding(10, fake, fake, fake, 5, 2, 0.0, 10, 0, null, fake, C.byref(it), null)
+    assert st == _lib.STAG_E_INVAL
+    st = lib.stag_spectral_cluster(0, fake, fake, fake, 5, 2, 0, fake, null)
+    assert st == _lib.STAG_E_INVAL
+    st = lib.stag_kmeans(fake, 10, 2, 11, 0, 10, null, fake, null, null, C.byref(it), null)
+    assert st == _lib.STAG_E_INVAL
+    st = lib.stag_kmeans(fake, 10000, 100, 50, 0, 10, null, fake, null, null, C.byref(it), null)
+    assert st == _lib.STAG_E_UNSUPPORTED
+    st = lib.stag_kmeans(fake, 10, 2, 3, 0, 0, null, fake, null, null, C.byref(it), null)
+    assert st == _lib.STAG_E_INVAL
     st = lib.stag_e2lsh_hash(fake, 10, 4, fake, fake, 0, 3, fake, null, null)
     assert st == _lib.STAG_E_INVAL
     st = lib.stag_e2lsh_hash(fake, 10, 4, fake, fake, 2, 3, null, null, null)
