@@ -59,6 +59,11 @@ def _load():
     lib.orc_kmeans.restype = C.c_int32
     lib.orc_kmeans.argtypes = [f64p, C.c_int64, C.c_int32, C.c_int32, C.c_uint64, C.c_int32, f64p, i32p, f64p,
                                C.POINTER(C.c_int32), i64p]
+    lib.orc_kde_random_sample.restype = None
+    lib.orc_kde_random_sample.argtypes = [f32p, C.c_int64, f32p, C.c_int64, C.c_int32, C.c_double, C.c_int64,
+                                          C.c_uint64, f64p, i64p, C.c_int32]
+    lib.orc_rs_sample_size.restype = C.c_int64
+    lib.orc_rs_sample_size.argtypes = [C.c_double, C.c_double, C.c_int64, C.c_double]
     lib.orc_kernel_row.restype = None
     lib.orc_kernel_row.argtypes = [f32p, C.c_int64, C.c_int32, C.c_double, C.c_int64, f64p]
     lib.orc_e2lsh_hash.restype = None
@@ -176,6 +181,24 @@ def kmeans(P, k: int, seed: int, max_iter: int = 300, init=None):
                             C.byref(it), _p(seeds, C.c_int64))
     assert rc == 0
     return labels, Cm, int(it.value), seeds
+
+
+def kde_random_sample(X, Q, a: float, s: int, seed: int, nthreads: int = 0):
+    """(estimates float64 [m], sample indices int64 [s]) of the random-sampling
+    estimator (n/s) sum_r exp(-a ||q - x_{j_r}||^2)."""
+    X, Q = _f32(X), _f32(Q)
+    n, d = X.shape
+    m = Q.shape[0]
+    S = np.empty(m, dtype=np.float64)
+    idx = np.empty(int(s), dtype=np.int64)
+    _load().orc_kde_random_sample(_p(X, C.c_float), n, _p(Q, C.c_float), m, d, float(a), int(s),
+                                  C.c_uint64(int(seed) & (2**64 - 1)), _p(S, C.c_double), _p(idx, C.c_int64),
+                                  int(nthreads))
+    return S, idx
+
+
+def rs_sample_size(eps: float, mu: float, m: int, delta: float) -> int:
+    return int(_load().orc_rs_sample_size(float(eps), float(mu), int(m), float(delta)))
 
 
 def kernel_row(X, a: float, i: int):

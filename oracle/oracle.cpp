@@ -820,4 +820,46 @@ int32_t orc_kmeans(const double* P, int64_t n, int32_t dim, int32_t k, uint64_t 
   return 0;
 }
 
+
+// ---------------------------------------------------------------------------
+// Random-sampling KDE (the baseline of Sec. "Kernel Density Estimation" and of
+// the experiments: estimate K(q) from a uniformly random sample of the data).
+// Reading: s indices drawn independently and uniformly with replacement,
+//   j_r = floor(U_r n), U_r = (counter_bits(seed, "RSKD", 0, 0, r) >> 11) 2^-53,
+// taken exactly with integer arithmetic; one sample serves all queries; the
+// estimate of S(q) = n K(q) is (n/s) sum_r exp(-a ||q - x_{j_r}||^2), the sum
+// compensated over r ascending and scaled by the once-rounded n/s.
+// Sample size for a (1 +- eps) estimate of every one of m queries whose
+// density is at least mu, with failure probability at most delta: the
+// multiplicative Chernoff bound for s independent values in [0, 1] with mean
+// K >= mu, P(|mean - K| > eps K) <= 2 exp(-eps^2 K s / 3), and a union bound
+// over the m queries give s = ceil(3 ln(2m/delta) / (eps^2 mu)).
+// ---------------------------------------------------------------------------
+const uint64_t kTagSample = 0x52534B44ULL;  // "RSKD"
+
+int64_t sample_index(uint64_t seed, int64_t r, int64_t n) {
+  const uint64_t u = counter_bits(seed, kTagSample, 0, 0, (uint64_t)r) >> 11;
+  return (int64_t)(((unsigned __int128)u * (uint64_t)n) >> 53);
+}
+
+void orc_kde_random_sample(const float* X, int64_t n, const float* Q, int64_t m, int32_t d, double a, int64_t s,
+                           uint64_t seed, double* S_out, int64_t* idx_out, int32_t nthreads) {
+  if (nthreads <= 0) nthreads = omp_get_max_threads();
+  std::vector<int64_t> idx((size_t)s);
+  for (int64_t r = 0; r < s; ++r) idx[r] = sample_index(seed, r, n);
+  if (idx_out) std::memcpy(idx_out, idx.data(), sizeof(int64_t) * (size_t)s);
+  const double scale = (double)n / (double)s;
+#pragma omp parallel for schedule(static) num_threads(nthreads)
+  for (int64_t qi = 0; qi < m; ++qi) {
+    const float* q = Q + (size_t)qi * d;
+    KahanSum acc;
+    for (int64_t r = 0; r < s; ++r) acc.add(std::exp(-a * sqdist_direct(q, X + (size_t)idx[r] * d, d)));
+    S_out[qi] = acc.value() * scale;
+  }
+}
+
+int64_t orc_rs_sample_size(double eps, double mu, int64_t m, double delta) {
+  return (int64_t)std::ceil(3.0 * std::log(2.0 * (double)m / delta) / (eps * eps * mu));
+}
+
 }  // extern "C"
