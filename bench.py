@@ -203,6 +203,43 @@ def spectral_run(stag, torch, lib, buf, graph, n: int, k: int, labels_true, seed
             "kernels_ms": {kk: v[1] for kk, v in tm.items()}}
 
 
+def rs_run(stag, torch, lib, buf, X, Q, Xd, Qd, a: float, form: str, n_check: int = 32):
+    """Random-sampling KDE (the paper's sampling baseline) over the step's
+    data and queries at s = n/100 and n/10 samples: time, throughput of
+    estimated queries, error against the exact density of every query (GPU,
+    fp32 form), and parity with the oracle's estimator on sampled queries."""
+    import numpy as np
+
+    import oracle
+    n = X.shape[0]
+    m = Q.shape[0]
+    exact = stag.kde_exact(Xd, Qd, a, form="fp32").cpu().numpy()
+    rng = np.random.default_rng(2006)
+    idx = np.sort(rng.choice(m, size=n_check, replace=False))
+    out = {"workload": f"random-sampling KDE over n={n}, m={m}, d={X.shape[1]}, a={a}, form {form}", "samples": {}}
+    for s in (n // 100, n // 10):
+        stag.kde_random_sample(Xd, Qd, a, s, seed=7, form=form)  # warm-up
+        torch.cuda.synchronize()
+        lib.stag_timing_report(buf, len(buf))
+        lib.stag_timing_enable(1)
+        t0 = time.perf_counter()
+        S = stag.kde_random_sample(Xd, Qd, a, s, seed=7, form=form)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        lib.stag_timing_enable(0)
+        lib.stag_timing_report(buf, len(buf))
+        tm = parse_timing(buf.value.decode())
+        Sh = S.cpu().numpy()
+        rel = np.abs(Sh - exact) / exact
+        ref, _ = oracle.kde_random_sample(X, Q[idx], a, s, 7)
+        out["samples"][str(s)] = {"wall_ms": (t1 - t0) * 1e3, "queries_per_s": m / (t1 - t0),
+                                  "kernels_ms": {k: v[1] for k, v in tm.items()},
+                                  "mean_rel_err_vs_exact": float(rel.mean()), "max_rel_err_vs_exact": float(rel.max()),
+                                  "frac_within_10pct": float(np.mean(rel <= 0.1)),
+                                  "max_rel_diff_vs_oracle_estimator": float(np.max(np.abs(Sh[idx] - ref) / ref))}
+    return out
+
+
 def e2lsh_table_run(stag, torch, dev, lib, buf, Xd, Qd, K: int = 6, L: int = 50):
     """E2LSH table (K = 6, L = 50, the paper's example) over the step's data:
     build and near-neighbour listing of all queries, with kernel times."""
@@ -516,6 +553,7 @@ def main():
         del src_c, dst_c
     result["e2lsh_table"] = e2lsh_table_run(stag, torch, dev, lib, buf, Xd, Qd)
     result["kernels"] = kernels_run(stag, torch, dev, lib, buf, X, Q, Xd, Qd, args.form)
+    result["random_sampling"] = rs_run(stag, torch, lib, buf, X, Q, Xd, Qd, a, args.form)
     result["spectral"] = spectral_run(stag, torch, lib, buf, graph, n, info["k"], info["labels"])
     del graph
     if not args.no_precision_config:

@@ -129,6 +129,30 @@ stag_status stag_kde_exact_kernel(const float* X, int64_t n, const float* Q, int
                                   double a, int32_t form, uint32_t flags, double* S_out, double* bound_out,
                                   hipStream_t stream);
 
+/* Random-sampling kernel density (the sampling baseline of Sec. "Kernel
+ * Density Estimation" and of the paper's KDE experiments: K(q) estimated from
+ * a uniformly random sample of the data).
+ *   samples (s >= 1) indices drawn with replacement, j_r = floor(U_r n) taken
+ *   exactly, U_r = (mix(t + (r+1) 0x9E3779B97F4A7C15) >> 11) 2^-53,
+ *   t = mix(mix(mix(seed ^ 0x52534B44))), mix the SplitMix64 finaliser; one
+ *   sample serves every query.
+ *   S_out [m] f64 device: (n/s) sum_r exp(-a ||q - x_{j_r}||^2), n/s rounded
+ *   once; an unbiased estimate of S(q).
+ *   bound_out [m] f64 device or NULL: relative error bound of S_out against
+ *   the exact fp64 value of that same estimator (as stag_kde_exact's).
+ *   idx_out [s] int64 device or NULL: the sampled indices.
+ * form, d and size limits as stag_kde_exact (samples * d < 2^31). */
+stag_status stag_kde_random_sample(const float* X, int64_t n, const float* Q, int64_t m, int32_t d, double a,
+                                   int64_t samples, uint64_t seed, int32_t form, double* S_out, double* bound_out,
+                                   int64_t* idx_out, hipStream_t stream);
+
+/* Host-only: the sample size ceil(3 ln(2m/delta) / (eps^2 mu)) after which,
+ * by the multiplicative Chernoff bound for values in [0, 1] and a union bound
+ * over m queries, every query whose density K(q) is at least mu is estimated
+ * within a factor 1 +- eps (0 < eps < 1) with probability at least 1 - delta.
+ * Returns 0 for invalid arguments. */
+int64_t stag_rs_sample_size(double eps, double mu, int64_t m, double delta);
+
 /* E2LSH codes and bucket keys (Sec. "Random Projection": h(x) =
  * floor((<x, g> + b) / 4); Sec. "Boosting the Probability": K concatenated
  * functions per table, L tables).

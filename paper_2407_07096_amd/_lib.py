@@ -73,6 +73,10 @@ def load():
     lib.stag_kde_exact.argtypes = [vp, i64, vp, i64, i32, f64, f64, i32, u32, vp, vp, vp]
     lib.stag_kde_exact_kernel.restype = C.c_int
     lib.stag_kde_exact_kernel.argtypes = [vp, i64, vp, i64, i32, i32, f64, i32, u32, vp, vp, vp]
+    lib.stag_kde_random_sample.restype = C.c_int
+    lib.stag_kde_random_sample.argtypes = [vp, i64, vp, i64, i32, f64, i64, u64, i32, vp, vp, vp, vp]
+    lib.stag_rs_sample_size.restype = i64
+    lib.stag_rs_sample_size.argtypes = [f64, f64, i64, f64]
     lib.stag_spectral_embedding.restype = C.c_int
     lib.stag_spectral_embedding.argtypes = [i64, vp, vp, vp, i64, i32, f64, i32, u64, vp, vp, C.POINTER(C.c_int32), vp]
     lib.stag_kmeans.restype = C.c_int
@@ -204,6 +208,37 @@ def kde_exact(X, Q, a: float, form: str = "fp32", normalize: bool = False, retur
                                           _ptr(S), _ptr(B), _stream_handle(X.device))
         check(st, "stag_kde_exact_kernel")
     return (S, B) if return_bound else S
+
+
+def kde_random_sample(X, Q, a: float, samples: int, seed: int = 0, form: str = "fp32", return_bound: bool = False,
+                      return_indices: bool = False):
+    """Random-sampling estimate (n/s) sum_r exp(-a ||q - x_{j_r}||^2) of S(q)
+    for every row of Q (float64 [m]); optionally the per-result bound and the
+    sampled indices (int64 [samples])."""
+    torch = _torch()
+    _need(X, torch.float32, 2, "X")
+    _need(Q, torch.float32, 2, "Q")
+    if X.shape[1] != Q.shape[1]:
+        raise ValueError("X and Q must have the same number of columns")
+    n, d = X.shape
+    m = Q.shape[0]
+    S = torch.empty(m, dtype=torch.float64, device=X.device)
+    B = torch.empty(m, dtype=torch.float64, device=X.device) if return_bound else None
+    I = torch.empty(int(samples), dtype=torch.int64, device=X.device) if return_indices else None
+    st = load().stag_kde_random_sample(_ptr(X), n, _ptr(Q), m, d, float(a), int(samples),
+                                       int(seed) & 0xFFFFFFFFFFFFFFFF, FORMS[form], _ptr(S), _ptr(B), _ptr(I),
+                                       _stream_handle(X.device))
+    check(st, "stag_kde_random_sample")
+    out = (S,)
+    if return_bound:
+        out += (B,)
+    if return_indices:
+        out += (I,)
+    return out if len(out) > 1 else S
+
+
+def rs_sample_size(eps: float, mu: float, m: int, delta: float) -> int:
+    return int(load().stag_rs_sample_size(float(eps), float(mu), int(m), float(delta)))
 
 
 def e2lsh_hash(X, G, b, K: int, L: int, want_codes: bool = True, want_keys: bool = True):

@@ -74,6 +74,10 @@ def test_invalid_arguments_rejected_before_launch():
     assert st == _lib.STAG_E_UNSUPPORTED
     st = lib.stag_kmeans(fake, 10, 2, 3, 0, 0, null, fake, null, null, C.byref(it), null)
     assert st == _lib.STAG_E_INVAL
+    st = lib.stag_kde_random_sample(fake, 10, fake, 10, 4, 1.0, 0, 1, 0, fake, null, null, null)
+    assert st == _lib.STAG_E_INVAL
+    st = lib.stag_kde_random_sample(fake, 10, null, 10, 4, 1.0, 5, 1, 0, fake, null, null, null)
+    assert st == _lib.STAG_E_INVAL and "NULL" in stag.last_error()
     st = lib.stag_e2lsh_hash(fake, 10, 4, fake, fake, 0, 3, fake, null, null)
     assert st == _lib.STAG_E_INVAL
     st = lib.stag_e2lsh_hash(fake, 10, 4, fake, fake, 2, 3, null, null, null)
@@ -112,3 +116,14 @@ def test_lsh_parameter_validation():
         stag.lsh_derive(100, -1.0, 0.5)
     with pytest.raises(stag.StagError):
         stag.lsh_derive(100, 0.01, 0.5, k2_constant=65)
+
+
+@pytest.mark.parametrize("eps,mu,m,delta", [(0.1, 1e-3, 1000, 0.01), (0.5, 0.2, 1, 0.5), (0.05, 1e-5, 10**6, 1e-3)])
+def test_rs_sample_size_matches_oracle(orc, eps, mu, m, delta):
+    assert stag.rs_sample_size(eps, mu, m, delta) == orc.rs_sample_size(eps, mu, m, delta)
+
+
+def test_rs_sample_size_rejects():
+    for args in [(0.0, 0.1, 10, 0.1), (1.0, 0.1, 10, 0.1), (0.1, 0.0, 10, 0.1), (0.1, 0.1, 0, 0.1),
+                 (0.1, 0.1, 10, 1.0)]:
+        assert stag.rs_sample_size(*args) == 0
