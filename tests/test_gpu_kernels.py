@@ -120,3 +120,18 @@ def test_batch_independence(stag, kernel):
     S_all, _ = _run(stag, X, Q, 0.2, "fp16_split", kernel)
     S_one, _ = _run(stag, X, Q[137:138], 0.2, "fp16_split", kernel)
     assert S_all[137] == S_one[0]
+
+
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_full_size_sampled(stag, orc, kernel):
+    """n = m = 100,000, d = 64, fp16 split: full launch, oracle on 48 sampled queries."""
+    X, Q, _ = synth.config_points(2)
+    a = 0.2
+    rng = np.random.default_rng(77)
+    idx = np.sort(rng.choice(len(Q), size=48, replace=False))
+    announce(f"kernel={kernel} full n=m=1e5 d=64 form=fp16_split")
+    S, B = _run(stag, X, Q, a, "fp16_split", kernel)
+    ref = orc.kde_kernel(X, Q[idx], a, kernel)
+    err = rel_err(S[idx], ref)
+    assert np.all(err <= B[idx]), (err.max(), B[idx].min())
+    assert err.max() <= MEASURED[kernel], err.max()

@@ -69,3 +69,20 @@ def test_batch_independence_and_unbiasedness(stag):
     exact = oracle.kde_exact(X, Q[:5], 0.5)
     est = np.array([_run(stag, X, Q[:5], 0.5, 200, seed, "fp32")[0] for seed in range(400)])
     assert np.all(np.abs(est.mean(0) - exact) < 5 * est.std(0) / np.sqrt(len(est)))
+
+
+def test_full_size_sampled(stag):
+    """n = m = 100,000, d = 64, s = 10,000 samples, fp16 split: full launch,
+    oracle on 48 sampled queries (same sample)."""
+    X, Q, _ = synth.config_points(2)
+    rng = np.random.default_rng(78)
+    idx = np.sort(rng.choice(len(Q), size=48, replace=False))
+    announce("random sampling full n=m=1e5 s=1e4 fp16_split")
+    import torch
+    S, B, I = stag.kde_random_sample(to_dev(X), to_dev(Q), 0.01, 10_000, seed=9, form="fp16_split",
+                                     return_bound=True, return_indices=True)
+    torch.cuda.synchronize()
+    ref, ridx = oracle.kde_random_sample(X, Q[idx], 0.01, 10_000, 9)
+    assert np.array_equal(I.cpu().numpy(), ridx)
+    err = rel_err(S.cpu().numpy()[idx], ref)
+    assert np.all(err <= B.cpu().numpy()[idx]) and err.max() <= 1e-5

@@ -211,3 +211,50 @@ def test_spectral_cluster_end_to_end(stag, cfg, n, k, a):
     t = info["labels"]
     purity = sum(np.bincount(lab[t == c]).max() for c in range(k)) / n
     assert purity >= 0.97, purity
+
+
+def _planted_graph(n, k, deg, seed):
+    # seeded synthetic graph: k planted clusters, each node draws `deg`
+    # neighbours inside its cluster and one anywhere with probability 0.05;
+    # weights U[0.5, 1]
+    rng = np.random.default_rng(seed)
+    lab = rng.integers(0, k, n)
+    members = [np.flatnonzero(lab == c) for c in range(k)]
+    src = np.repeat(np.arange(n), deg)
+    dst = np.empty(n * deg, dtype=np.int64)
+    for c in range(k):
+        rows = np.flatnonzero(lab[src] == c)
+        dst[rows] = members[c][rng.integers(0, len(members[c]), len(rows))]
+    cross = rng.random(n * deg) < 0.05 / deg
+    dst[cross] = rng.integers(0, n, int(cross.sum()))
+    keep = dst != src
+    return src[keep], dst[keep], rng.uniform(0.5, 1.0, int(keep.sum())), lab
+
+
+def test_full_size_planted_graph(stag):
+    """n = 100,000 vertices, ~1.6e6 edges, k = 20: properties that hold at any
+    size, checked on the host: residuals ||N u - lambda u|| <= 1e-8,
+    orthonormal columns, eigenvalues equal to ARPACK's smallest of N, and the
+    planted clusters recovered."""
+    import torch
+    from scipy.sparse import coo_matrix, identity
+    from scipy.sparse.linalg import eigsh
+    n, k = 100_000, 20
+    src, dst, w, lab = _planted_graph(n, k, 16, 31)
+    announce("spectral full size planted n=1e5 k=20")
+    lam, U, it = _embed(stag, n, src, dst, w, k)
+    A = coo_matrix((np.concatenate([w, w]), (np.concatenate([src, dst]), np.concatenate([dst, src]))),
+                   shape=(n, n)).tocsr()
+    deg = np.asarray(A.sum(axis=1)).ravel()
+    dinv = 1.0 / np.sqrt(deg)
+    Mop = A.multiply(dinv[:, None]).multiply(dinv[None, :]).tocsr()
+    NU = U - Mop @ U
+    assert np.linalg.norm(NU - U * lam[None, :], axis=0).max() <= 1e-8
+    np.testing.assert_allclose(U.T @ U, np.eye(k), atol=1e-10)
+    theta = np.sort(eigsh(Mop, k=k + 1, which="LA", tol=1e-12)[0])[::-1]
+    np.testing.assert_allclose(lam, 1.0 - theta[:k], atol=1e-8)
+    labels = stag.spectral_cluster(n, *_dev_edges(src, dst, w), k, seed=3)
+    torch.cuda.synchronize()
+    labels = labels.cpu().numpy()
+    purity = sum(np.bincount(labels[lab == c]).max() for c in range(k)) / n
+    assert purity >= 0.97, purity
