@@ -35,6 +35,7 @@
 #include "lsh.h"
 #include "runtime.h"
 #include "scan.h"
+#include "sort.h"
 
 namespace stag {
 namespace {
@@ -181,7 +182,10 @@ __global__ __launch_bounds__(256) void hash_members(const float* __restrict__ X,
 }
 
 // ---------------------------------------------------------------------------
-// bucket tables: one workgroup per table group
+// bucket tables: open addressing over each (segment, table), capacity a
+// power of two >= 2 x members; every (table, member) pair is inserted at
+// once, then the pairs are sorted stably by their bucket's global slot, which
+// lays out the CSR with each bucket's members in ascending order
 // ---------------------------------------------------------------------------
 __device__ inline uint32_t probe_insert(uint64_t* __restrict__ keys, uint32_t mask, uint64_t key) {
   uint32_t s = (uint32_t)key & mask;
@@ -200,78 +204,117 @@ __device__ inline uint32_t lookup_present(const uint64_t* __restrict__ keys, uin
   return s;
 }
 
-__global__ __launch_bounds__(256) void build_tables(int L, const uint64_t* __restrict__ seg_off,
-                                                    const uint64_t* __restrict__ tab_seg_off,
-                                                    const uint32_t* __restrict__ seg_cap,
-                                                    const uint64_t* __restrict__ mkeys, uint64_t* __restrict__ tab_key,
-                                                    uint32_t* __restrict__ tab_start, uint32_t* __restrict__ tab_cnt,
-                                                    uint32_t* __restrict__ cursor, int32_t* __restrict__ csr) {
-  const int64_t g = blockIdx.x;
-  const int seg = (int)(g / L), l = (int)(g % L);
-  const int64_t s0 = (int64_t)seg_off[seg];
-  const int64_t cnt = (int64_t)seg_off[seg + 1] - s0;
-  if (cnt == 0) return;
-  const uint32_t cap = seg_cap[seg], mask = cap - 1;
-  const int64_t tb = (int64_t)tab_seg_off[seg] + (int64_t)l * cap;
-  uint64_t* tk = tab_key + tb;
-  uint32_t* tc = tab_cnt + tb;
-  uint32_t* ts = tab_start + tb;
-  uint32_t* cur = cursor + tb;
-  const uint64_t* mk = mkeys + s0 * L + l;
-  int32_t* out = csr + s0 * L + (int64_t)l * cnt;
-  const int tid = threadIdx.x;
-  for (uint32_t s = tid; s < cap; s += 256) {
-    tk[s] = kEmpty;
-    tc[s] = 0;
-    cur[s] = 0;
+// Bucket tables of every (segment, table) pair at once.  The pairs
+// (segment, table l, member u) are numbered table-major, [seg][l][u], which
+// is also the CSR layout; pair p of segment seg starts at seg_off[seg] * L.
+__device__ inline int upper_seg(const uint64_t* __restrict__ off, int count, uint64_t scale, uint64_t v) {
+  // largest k in [0, count) with off[k] * scale <= v
+  int lo = 0, hi = count - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (off[mid] * scale <= v) lo = mid;
+    else hi = mid - 1;
   }
-  __syncthreads();
-  for (int64_t u = tid; u < cnt; u += 256) {
-    const uint32_t s = probe_insert(tk, mask, mk[u * L]);
-    atomicAdd(tc + s, 1u);
-  }
-  __syncthreads();
-  // exclusive scan of the counts over the slots
-  __shared__ uint32_t wsum[4];
-  __shared__ uint32_t carry;
-  if (tid == 0) carry = 0;
-  __syncthreads();
-  for (uint32_t s0c = 0; s0c < cap; s0c += 256) {
-    const uint32_t s = s0c + tid;
-    const uint32_t v = s < cap ? tc[s] : 0;
-    uint32_t inc = v;
-    const int lane = tid & 63, wave = tid >> 6;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-      const uint32_t y = __shfl_up(inc, o);
-      if (lane >= o) inc += y;
-    }
-    if (lane == 63) wsum[wave] = inc;
-    __syncthreads();
-    uint32_t wb = 0;
-    for (int w = 0; w < wave; ++w) wb += wsum[w];
-    if (s < cap) ts[s] = carry + wb + inc - v;
-    __syncthreads();
-    if (tid == 0) carry += wsum[0] + wsum[1] + wsum[2] + wsum[3];
-    __syncthreads();
-  }
-  // place members in ascending order within each bucket
-  __shared__ uint32_t sl[256];
-  for (int64_t c0 = 0; c0 < cnt; c0 += 256) {
-    const int64_t u = c0 + tid;
-    const bool valid = u < cnt;
-    const uint32_t s = valid ? lookup_present(tk, mask, mk[u * L]) : 0xFFFFFFFFu;
-    sl[tid] = s;
-    __syncthreads();
-    if (valid) {
-      uint32_t rank = 0;
-      for (int k = 0; k < tid; ++k) rank += (sl[k] == s) ? 1u : 0u;
-      out[ts[s] + cur[s] + rank] = (int32_t)u;
-    }
-    __syncthreads();
-    if (valid) atomicAdd(cur + s, 1u);
-    __syncthreads();
-  }
+  return lo;
+}
+
+struct PairPos {
+  int seg, l;
+  int64_t u, s0, cnt, tb;
+  uint32_t mask;
+};
+
+__device__ inline PairPos pair_pos(int64_t p, int L, int nseg, const uint64_t* __restrict__ seg_off,
+                                   const uint64_t* __restrict__ tab_seg_off, const uint32_t* __restrict__ seg_cap) {
+  PairPos q;
+  q.seg = upper_seg(seg_off, nseg, (uint64_t)L, (uint64_t)p);
+  q.s0 = (int64_t)seg_off[q.seg];
+  q.cnt = (int64_t)seg_off[q.seg + 1] - q.s0;
+  const int64_t r = p - q.s0 * L;
+  q.l = (int)(r / q.cnt);
+  q.u = r - (int64_t)q.l * q.cnt;
+  const uint32_t cap = seg_cap[q.seg];
+  q.mask = cap - 1;
+  q.tb = (int64_t)tab_seg_off[q.seg] + (int64_t)q.l * cap;
+  return q;
+}
+
+__global__ void table_clear(uint64_t* __restrict__ tab_key, uint32_t* __restrict__ tab_cnt, int64_t total) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= total) return;
+  tab_key[g] = kEmpty;
+  tab_cnt[g] = 0;
+}
+
+__global__ void table_insert(int L, int nseg, int64_t npairs, const uint64_t* __restrict__ seg_off,
+                             const uint64_t* __restrict__ tab_seg_off, const uint32_t* __restrict__ seg_cap,
+                             const uint64_t* __restrict__ mkeys, uint64_t* __restrict__ tab_key,
+                             uint32_t* __restrict__ tab_cnt) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= npairs) return;
+  const PairPos q = pair_pos(p, L, nseg, seg_off, tab_seg_off, seg_cap);
+  const uint32_t s = probe_insert(tab_key + q.tb, q.mask, mkeys[(q.s0 + q.u) * L + q.l]);
+  atomicAdd(tab_cnt + q.tb + s, 1u);
+}
+
+// Sort key of a pair: its bucket's global slot; value: the member index.
+__global__ void table_pairs(int L, int nseg, int64_t npairs, const uint64_t* __restrict__ seg_off,
+                            const uint64_t* __restrict__ tab_seg_off, const uint32_t* __restrict__ seg_cap,
+                            const uint64_t* __restrict__ mkeys, const uint64_t* __restrict__ tab_key,
+                            uint32_t* __restrict__ skey, uint32_t* __restrict__ sval) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= npairs) return;
+  const PairPos q = pair_pos(p, L, nseg, seg_off, tab_seg_off, seg_cap);
+  const uint32_t s = lookup_present(tab_key + q.tb, q.mask, mkeys[(q.s0 + q.u) * L + q.l]);
+  skey[p] = (uint32_t)(q.tb + s);
+  sval[p] = (uint32_t)q.u;
+}
+
+// Start of a slot's bucket relative to its table: the global scan of the
+// slot counts at the slot minus at the table's first slot.
+__global__ void table_starts(int L, int nseg, int64_t total, const uint64_t* __restrict__ tab_seg_off,
+                             const uint32_t* __restrict__ seg_cap, const uint64_t* __restrict__ scan,
+                             uint32_t* __restrict__ tab_start) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= total) return;
+  const int seg = upper_seg(tab_seg_off, nseg, 1, (uint64_t)g);
+  const uint32_t cap = seg_cap[seg];
+  const int64_t first = (int64_t)tab_seg_off[seg] + ((g - (int64_t)tab_seg_off[seg]) / cap) * cap;
+  tab_start[g] = (uint32_t)(scan[g] - scan[first]);
+}
+
+// Builds tab_key / tab_cnt / tab_start and the CSR of every (segment, table)
+// pair: npairs = members x L pairs, total_slots slots (both known on the host).
+stag_status build_tables_sorted(int L, int nseg, int64_t npairs, int64_t total_slots, const uint64_t* seg_off,
+                                const uint64_t* tab_seg_off, const uint32_t* seg_cap, const uint64_t* mkeys,
+                                uint64_t* tab_key, uint32_t* tab_start, uint32_t* tab_cnt, int32_t* csr, Workspace& ws,
+                                hipStream_t st) {
+  if (total_slots <= 0 || npairs <= 0) return STAG_OK;
+  if (npairs >= ((int64_t)1 << 31) || total_slots >= ((int64_t)1 << 32))
+    return fail(STAG_E_UNSUPPORTED, "bucket tables: %lld pairs / %lld slots exceed the 32-bit build",
+                (long long)npairs, (long long)total_slots);
+  uint32_t *skey = nullptr, *sval = nullptr, *skey2 = nullptr;
+  uint64_t* scan = nullptr;
+  STAG_TRY(ws.alloc(&skey, (size_t)npairs));
+  STAG_TRY(ws.alloc(&sval, (size_t)npairs));
+  STAG_TRY(ws.alloc(&skey2, (size_t)npairs));
+  STAG_TRY(ws.alloc(&scan, (size_t)total_slots + 1));
+  hipLaunchKernelGGL(table_clear, dim3((unsigned)ceil_div(total_slots, 256)), dim3(256), 0, st, tab_key, tab_cnt,
+                     total_slots);
+  STAG_TRY(check_launch("table_clear"));
+  hipLaunchKernelGGL(table_insert, dim3((unsigned)ceil_div(npairs, 256)), dim3(256), 0, st, L, nseg, npairs, seg_off,
+                     tab_seg_off, seg_cap, mkeys, tab_key, tab_cnt);
+  STAG_TRY(check_launch("table_insert"));
+  hipLaunchKernelGGL(table_pairs, dim3((unsigned)ceil_div(npairs, 256)), dim3(256), 0, st, L, nseg, npairs, seg_off,
+                     tab_seg_off, seg_cap, mkeys, tab_key, skey, sval);
+  STAG_TRY(check_launch("table_pairs"));
+  int bits = 1;
+  while (bits < 32 && ((uint64_t)(total_slots - 1) >> bits) != 0) ++bits;
+  STAG_TRY(radix_sort_pairs_u32(skey, sval, skey2, reinterpret_cast<uint32_t*>(csr), npairs, bits, ws, st));
+  STAG_TRY(exclusive_scan_u32(tab_cnt, scan, total_slots, ws, st));
+  hipLaunchKernelGGL(table_starts, dim3((unsigned)ceil_div(total_slots, 256)), dim3(256), 0, st, L, nseg,
+                     total_slots, tab_seg_off, seg_cap, scan, tab_start);
+  return check_launch("table_starts");
 }
 
 // ---------------------------------------------------------------------------
@@ -972,7 +1015,7 @@ __global__ void zero_u32(uint32_t* p, int64_t n) {
 // E2LSH table with near-neighbour listing (the E2LSH class of Sec. "Random
 // Projection" / "Boosting the Probability" and its get_near_neighbours): one
 // segment holding all n points, L open-addressing tables, CSR members
-// ascending within a bucket (built by build_tables).  A query lists the points
+// ascending within a bucket (built by build_tables_sorted).  A query lists the points
 // that collide with it in some table: table by table, ascending within a
 // bucket, each point in the first table where it collides.
 // ---------------------------------------------------------------------------
@@ -1385,16 +1428,14 @@ stag_status create_index(const float* X, int64_t n, int d, double a, double eps,
   STAG_TRY(own_alloc(idx, &idx->tab_start, (size_t)idx->total_slots));
   STAG_TRY(own_alloc(idx, &idx->tab_cnt, (size_t)idx->total_slots));
   STAG_TRY(own_alloc(idx, &idx->csr, (size_t)idx->M * L));
-  uint32_t* cursor = nullptr;
-  STAG_TRY(ws.alloc(&cursor, (size_t)idx->total_slots));
   if (idx->ntab > 0) {
     ScopedTimer tm("lsh_build_tables", st);
-    hipLaunchKernelGGL(build_tables, dim3((unsigned)idx->ntab), dim3(256), 0, st, L, idx->seg_off, idx->tab_seg_off,
-                       idx->seg_cap, idx->mkeys, idx->tab_key, idx->tab_start, idx->tab_cnt, cursor, idx->csr);
-    STAG_TRY(check_launch("build_tables"));
+    STAG_TRY(build_tables_sorted(L, (int)idx->nseg, idx->M * L, idx->total_slots, idx->seg_off, idx->tab_seg_off,
+                                 idx->seg_cap, idx->mkeys, idx->tab_key, idx->tab_start, idx->tab_cnt, idx->csr, ws,
+                                 st));
   }
   STAG_HIP(hipGetDevice(&idx->device));
-  // the workspace (cursor, counts) is released in stream order
+  // the workspace (sort buffers, counts) is released in stream order
   return STAG_OK;
 }
 
@@ -1737,7 +1778,6 @@ stag_status stag_e2lsh_table_create(const float* X, int64_t n, int32_t d, const 
       uint64_t* seg_off = nullptr;
       uint64_t* tso = nullptr;
       uint32_t* segcap = nullptr;
-      uint32_t* cursor = nullptr;
       STAG_TRY(e2lsh_regroup(G, K, L, d, ws, &t->G8, &t->dg, stream));
       STAG_TRY(ws.alloc(&t->b, (size_t)K * L));
       STAG_HIP(hipMemcpyAsync(t->b, b, sizeof(double) * K * L, hipMemcpyDeviceToDevice, stream));
@@ -1750,14 +1790,12 @@ stag_status stag_e2lsh_table_create(const float* X, int64_t n, int32_t d, const 
       STAG_TRY(tmp.alloc(&seg_off, 2));
       STAG_TRY(tmp.alloc(&tso, 2));
       STAG_TRY(tmp.alloc(&segcap, 1));
-      STAG_TRY(tmp.alloc(&cursor, (size_t)cap * L));
       STAG_HIP(hipMemcpyAsync(seg_off, t->h_off.data(), sizeof(uint64_t) * 2, hipMemcpyHostToDevice, stream));
       STAG_HIP(hipMemcpyAsync(tso, t->h_off.data() + 2, sizeof(uint64_t) * 2, hipMemcpyHostToDevice, stream));
       STAG_HIP(hipMemcpyAsync(segcap, t->h_cap.data(), sizeof(uint32_t), hipMemcpyHostToDevice, stream));
       ScopedTimer tm("e2lsh_table_build", stream);
-      hipLaunchKernelGGL(build_tables, dim3((unsigned)L), dim3(256), 0, stream, L, seg_off, tso, segcap, t->mkeys,
-                         t->tab_key, t->tab_start, t->tab_cnt, cursor, t->csr);
-      return check_launch("build_tables");
+      return build_tables_sorted(L, 1, n * L, (int64_t)cap * L, seg_off, tso, segcap, t->mkeys, t->tab_key,
+                                 t->tab_start, t->tab_cnt, t->csr, tmp, stream);
     };
     st = body();
     t->owned = ws.release();

@@ -62,7 +62,11 @@ class Workspace {
     return st;
   }
   // Requests below kSmallBytes share kBlockBytes blocks (256-byte aligned
-  // slices); larger ones get an allocation of their own.
+  // slices); larger ones get an allocation of their own.  Every pool
+  // allocation and stream-ordered free costs host time on the caller's
+  // critical path, so the blocks are large: a call's temporaries (sort
+  // buffers, scans, partial sums of up to 32 MiB each) then come from one or
+  // two pool allocations.
   stag_status alloc_bytes(void** p, size_t bytes);
   // Hands the allocations to the caller (they are no longer freed here).
   std::vector<void*> release() {
@@ -72,8 +76,8 @@ class Workspace {
     used_ = cap_ = 0;
     return v;
   }
-  static constexpr size_t kSmallBytes = (size_t)1 << 20;
-  static constexpr size_t kBlockBytes = (size_t)4 << 20;
+  static constexpr size_t kSmallBytes = (size_t)32 << 20;
+  static constexpr size_t kBlockBytes = (size_t)64 << 20;
 
  private:
   stag_status raw_alloc(void** p, size_t bytes);
