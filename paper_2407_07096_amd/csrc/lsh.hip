@@ -727,11 +727,14 @@ constexpr int kJoinMembers = 512;
 constexpr int kJoinChunk = 32;
 
 // Bytes of dynamic LDS of one join wave (layout: rows, point ids, member
-// norms, member keys, query keys).
+// norms, member keys, query keys).  With L <= kJoinRegKeys + 1 the query
+// keys of the earlier tables are held in registers instead (fewer LDS bytes
+// per wave, more waves per CU).
+constexpr int kJoinRegKeys = 7;
 __host__ __device__ inline int join_lds_rows(int dq) { return kJoinChunk * (dq + 4) * 4; }
-__host__ __device__ inline int join_lds_bytes(int dq, int L) {
+__host__ __device__ inline int join_lds_bytes(int dq, int L, bool reg_keys) {
   const int lm1 = L > 1 ? L - 1 : 1;
-  return join_lds_rows(dq) + kJoinChunk * 8 + kJoinChunk * lm1 * 8 + lm1 * 64 * 8;
+  return join_lds_rows(dq) + kJoinChunk * 8 + kJoinChunk * lm1 * 8 + (reg_keys ? 0 : lm1 * 64 * 8);
 }
 
 // The bucket (global slot) of every (table, query) pair of the batch (pair
@@ -814,7 +817,7 @@ __device__ inline int64_t last_le(const uint64_t* __restrict__ v, int64_t n, uin
   return lo;
 }
 
-template <int DQ>
+template <int DQ, int QKR>
 __global__ __launch_bounds__(64) void join_buckets(IndexView ix, LevelConst lc, const float* __restrict__ Q, int ldq,
                                                    int64_t q0, const uint64_t* __restrict__ qkeys, int64_t mb,
                                                    const uint32_t* __restrict__ qcount,
@@ -832,7 +835,8 @@ __global__ __launch_bounds__(64) void join_buckets(IndexView ix, LevelConst lc, 
   int32_t* jl = reinterpret_cast<int32_t*>(jlds + join_lds_rows(DQ));
   float* nxl = reinterpret_cast<float*>(jl + kJoinChunk);
   uint64_t* mk = reinterpret_cast<uint64_t*>(jlds + join_lds_rows(DQ) + kJoinChunk * 8);
-  uint64_t* qk = mk + kJoinChunk * lm1;
+  uint64_t* qk = mk + kJoinChunk * lm1;  // query keys in LDS (QKR == 0)
+  uint64_t qkr[QKR > 0 ? QKR : 1];       // or in registers (l <= QKR)
 
   const int64_t task = blockIdx.x;
   const int64_t slot = last_le(task_base, nslots + 1, (uint64_t)task);
@@ -866,7 +870,12 @@ __global__ __launch_bounds__(64) void join_buckets(IndexView ix, LevelConst lc, 
   float qnorm = 0.0f;
 #pragma unroll
   for (int h = 0; h < DQ; ++h) qnorm = __builtin_fmaf(q[h], q[h], qnorm);
-  for (int l2 = 0; l2 < l; ++l2) qk[l2 * 64 + lane] = qkeys[((int64_t)seg * L + l2) * mb + ql];
+  if constexpr (QKR > 0) {
+#pragma unroll
+    for (int l2 = 0; l2 < QKR; ++l2) qkr[l2] = l2 < l ? qkeys[((int64_t)seg * L + l2) * mb + ql] : 0ull;
+  } else {
+    for (int l2 = 0; l2 < l; ++l2) qk[l2 * 64 + lane] = qkeys[((int64_t)seg * L + l2) * mb + ql];
+  }
   if (dx < DQ)
     for (int e = lane; e < kJoinChunk * RS; e += 64) rows[e] = 0.0f;
 
@@ -922,7 +931,13 @@ __global__ __launch_bounds__(64) void join_buckets(IndexView ix, LevelConst lc, 
       bool keep = qvalid && D32 >= Tlo_f - E && D32 < Thi_f + E;
       if (__ballot(keep)) {
         bool seen = (int64_t)jl[m] == self_idx;
-        for (int l2 = 0; l2 < l; ++l2) seen |= mk[m * lm1 + l2] == qk[l2 * 64 + lane];
+        if constexpr (QKR > 0) {
+#pragma unroll
+          for (int l2 = 0; l2 < QKR; ++l2)
+            if (l2 < l) seen |= mk[m * lm1 + l2] == qkr[l2];
+        } else {
+          for (int l2 = 0; l2 < l; ++l2) seen |= mk[m * lm1 + l2] == qk[l2 * 64 + lane];
+        }
         keep = keep && !seen;
       }
       mask |= keep ? (1u << m) : 0u;
@@ -1539,16 +1554,26 @@ stag_status join_batch(const stag_lsh_index* idx, const float* Q, int ldq, int64
   if (ntasks > 0) {
     ScopedTimer tm("lsh_join", st);
     const int dq = idx->d <= 16 ? 16 : idx->d <= 32 ? 32 : idx->d <= 64 ? 64 : 128;
-    const size_t lds = (size_t)join_lds_bytes(dq, L);
+    const bool reg_keys = L <= kJoinRegKeys + 1;
+    const size_t lds = (size_t)join_lds_bytes(dq, L, reg_keys);
     auto launch = [&](auto kern) {
       hipLaunchKernelGGL(kern, dim3((unsigned)ntasks), dim3(64), lds, st, ix, lc, Q, ldq, q0, qkeys, cur, qcount,
                          qstart, qlist, task_base, nslots, (int)idx->nseg, self_excl, tpart, nacc);
     };
-    switch (dq) {
-      case 16: launch(join_buckets<16>); break;
-      case 32: launch(join_buckets<32>); break;
-      case 64: launch(join_buckets<64>); break;
-      default: launch(join_buckets<128>); break;
+    if (reg_keys) {
+      switch (dq) {
+        case 16: launch(join_buckets<16, kJoinRegKeys>); break;
+        case 32: launch(join_buckets<32, kJoinRegKeys>); break;
+        case 64: launch(join_buckets<64, kJoinRegKeys>); break;
+        default: launch(join_buckets<128, kJoinRegKeys>); break;
+      }
+    } else {
+      switch (dq) {
+        case 16: launch(join_buckets<16, 0>); break;
+        case 32: launch(join_buckets<32, 0>); break;
+        case 64: launch(join_buckets<64, 0>); break;
+        default: launch(join_buckets<128, 0>); break;
+      }
     }
     STAG_TRY(check_launch("join_buckets"));
   }
