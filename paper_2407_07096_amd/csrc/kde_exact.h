@@ -55,7 +55,7 @@ __host__ __device__ inline double relative_bound(const BoundModel& bm, double qn
 // (Gaussian only) two optional outputs: drop the diagonal
 // when a data set is queried against itself, and write per-32-row-tile
 // partial sums tp[query * ntile + tile] (fp32; ntile, the row stride, is at
-// least padded data rows / 32 and a multiple of 8).
+// least padded data rows / 32 and a multiple of 16).
 struct TileExtra {
   int kernel = 0;  // a stag_kernel; the two outputs below need the Gaussian
   int self = 0;

@@ -83,9 +83,12 @@ __device__ inline float kernel_tile_sum(const float* c) {
   return k[0];
 }
 
-// A lane's tile sums of 8 consecutive data tiles (global tile indices
-// 8g .. 8g+7), written to tp as two 16-byte stores once the group is complete
-// (or the chunk ends): the row stride of tp is a multiple of 8 tiles.
+// Tile sums of a group of 16 consecutive data tiles (global tile indices
+// 16g .. 16g+15) for one query: lane half h buffers tiles 16g + 8h .. +7, and
+// once the group is complete (or the chunk ends) both halves store their 32
+// bytes in the same instructions, so each query's 64-byte segment of tp is
+// written whole.  The row stride of tp is a multiple of 16 tiles; slots past
+// the last data tile receive stale values and are never read.
 struct TileSums8 {
   float v[8];
 };
@@ -122,11 +125,12 @@ __device__ inline float tile_epilogue(const f32x16& c, int64_t row_base, int64_t
       if (grp == nullptr) {
         if (h == 0) ex.tp[qi * ex.ntile + tile] = tot;
       } else {
-        const int k = (int)(tile & 7);
+        const int k16 = (int)(tile & 15);
+        const int k = k16 - 8 * h;  // this half's slot, if in [0, 8)
 #pragma unroll
         for (int e = 0; e < 8; ++e) grp->v[e] = e == k ? tot : grp->v[e];
-        if ((k == 7 || last) && h == 0) {
-          f32x4* dst = reinterpret_cast<f32x4*>(ex.tp + qi * ex.ntile + (tile & ~(int64_t)7));
+        if (k16 == 15 || last) {
+          f32x4* dst = reinterpret_cast<f32x4*>(ex.tp + qi * ex.ntile + (tile & ~(int64_t)15) + 8 * h);
           dst[0] = f32x4{grp->v[0], grp->v[1], grp->v[2], grp->v[3]};
           dst[1] = f32x4{grp->v[4], grp->v[5], grp->v[6], grp->v[7]};
         }

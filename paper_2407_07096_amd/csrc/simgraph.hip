@@ -167,7 +167,7 @@ stag_status sample_exact(const float* X, int64_t n, int d, double a, int form, i
   STAG_TRY(prepare_operands(form, X, n, d, a, true, ws, &qo, st));
   const int P = (int)exact_chunks(xo.rows_pad);
   const int64_t ntile = xo.rows_pad / 32;
-  const int64_t tstride = round_up(ntile, 8);
+  const int64_t tstride = round_up(ntile, 16);
   double* partial = nullptr;
   float* tp = nullptr;
   double* rest = nullptr;
