@@ -373,8 +373,9 @@ def main():
                          "hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported (how the path would shard over "
-              "several GPUs is described in DESIGN.md)", file=sys.stderr)
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported.  Over several GPUs the exact "
+              "KDE would split X by rows (one fp64 sum all-reduce of the m results), the CKNS estimator its "
+              "independent copies, and the edge sampler its nodes with X replicated", file=sys.stderr)
         sys.exit(2)
 
     import ctypes
