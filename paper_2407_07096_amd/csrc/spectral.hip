@@ -18,8 +18,9 @@
 //              degree p that is bounded by 1 on the unwanted interval
 //              [-1, c] (c = the block's smallest Ritz value) and grows fast
 //              above it; three-term recurrence, one fused SpMM per degree
-//   orthonormalise twice by SVQB (Gram matrix V^T V, its eigenvectors Q and
-//              eigenvalues L on the host, V <- V Q L^{-1/2})
+//   orthonormalise twice by Cholesky QR (Gram matrix V^T V = R^T R on the
+//              host, V <- V R^{-1}; by its eigen-decomposition, V <- V Q L^{-1/2},
+//              if a pivot fails)
 //   Rayleigh-Ritz  W = M V, H = V^T W, H = Z diag(theta) Z^T on the host,
 //              V <- V Z, W <- W Z (theta descending)
 //   stop       when the k leading residuals ||W_j - theta_j V_j|| <= tol.
@@ -196,12 +197,26 @@ __global__ __launch_bounds__(256) void gram_partial(const double* __restrict__ A
   }
 }
 
+// Sum of v[k * stride] over k < count in order; the loads are issued eight at
+// a time so that they overlap, the additions stay sequential.
+__device__ inline double ordered_sum(const double* __restrict__ v, int64_t count, int64_t stride) {
+  double s = 0.0;
+  int64_t k = 0;
+  for (; k + 8 <= count; k += 8) {
+    double t[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) t[u] = v[(k + u) * stride];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s += t[u];
+  }
+  for (; k < count; ++k) s += v[k * stride];
+  return s;
+}
+
 __global__ void gram_final(const double* __restrict__ part, int64_t nblk, int bb, double* __restrict__ G) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= bb) return;
-  double s = 0.0;
-  for (int64_t k = 0; k < nblk; ++k) s += part[k * bb + e];
-  G[e] = s;
+  G[e] = ordered_sum(part + e, nblk, bb);
 }
 
 // Y[:, :b] = X[:, :b] R (R b x b row-major), Y[:, b:bp] = 0.
@@ -351,6 +366,34 @@ void jacobi_eigen(std::vector<double> A, int b, std::vector<double>& w, std::vec
   Z.swap(Zs);
 }
 
+// Upper-triangular R with G = R^T R (b x b, row-major), returned as R^{-1};
+// false if a pivot is not positive (then the caller orthonormalises by the
+// eigen-decomposition instead).
+bool cholesky_inverse(const std::vector<double>& G, int b, std::vector<double>& Rinv) {
+  std::vector<double> R((size_t)b * b, 0.0);
+  for (int j = 0; j < b; ++j) {
+    double dj = G[(size_t)j * b + j];
+    for (int k = 0; k < j; ++k) dj -= R[(size_t)k * b + j] * R[(size_t)k * b + j];
+    if (!(dj > 0.0) || !std::isfinite(dj)) return false;
+    const double rjj = std::sqrt(dj);
+    R[(size_t)j * b + j] = rjj;
+    for (int i = j + 1; i < b; ++i) {
+      double v = G[(size_t)j * b + i];
+      for (int k = 0; k < j; ++k) v -= R[(size_t)k * b + j] * R[(size_t)k * b + i];
+      R[(size_t)j * b + i] = v / rjj;
+    }
+  }
+  // back substitution, column by column: R X = I
+  Rinv.assign((size_t)b * b, 0.0);
+  for (int c = 0; c < b; ++c)
+    for (int i = c; i >= 0; --i) {
+      double v = (i == c) ? 1.0 : 0.0;
+      for (int k = i + 1; k <= c; ++k) v -= R[(size_t)i * b + k] * Rinv[(size_t)k * b + c];
+      Rinv[(size_t)i * b + c] = v / R[(size_t)i * b + i];
+    }
+  return true;
+}
+
 // ---------------------------------------------------------------------------
 // Subspace iteration driver
 // ---------------------------------------------------------------------------
@@ -494,17 +537,21 @@ class Subspace {
     return check_launch("apply_small");
   }
 
-  // V <- V Q L^{-1/2} from the eigen-decomposition of V^T V, twice.
+  // Twice: V <- V R^{-1} from the Cholesky factor of V^T V (Cholesky QR), or,
+  // if that breaks down, V <- V Q L^{-1/2} from its eigen-decomposition.
   stag_status orthonormalise() {
     for (int pass = 0; pass < 2; ++pass) {
-      std::vector<double> G, lam, Q;
+      std::vector<double> G, R;
       STAG_TRY(gram(V_, V_, G));
-      jacobi_eigen(G, b_, lam, Q);
-      const double floor_ = std::max(lam[0], 1e-300) * 1e-30;
-      std::vector<double> R((size_t)b_ * b_);
-      for (int c = 0; c < b_; ++c) {
-        const double s = 1.0 / std::sqrt(std::max(lam[c], floor_));
-        for (int r = 0; r < b_; ++r) R[(size_t)r * b_ + c] = Q[(size_t)r * b_ + c] * s;
+      if (!cholesky_inverse(G, b_, R)) {
+        std::vector<double> lam, Q;
+        jacobi_eigen(G, b_, lam, Q);
+        const double floor_ = std::max(lam[0], 1e-300) * 1e-30;
+        R.assign((size_t)b_ * b_, 0.0);
+        for (int c = 0; c < b_; ++c) {
+          const double sc = 1.0 / std::sqrt(std::max(lam[c], floor_));
+          for (int r = 0; r < b_; ++r) R[(size_t)r * b_ + c] = Q[(size_t)r * b_ + c] * sc;
+        }
       }
       STAG_TRY(upload(R));
       STAG_TRY(apply(V_, T_));
@@ -747,7 +794,18 @@ __global__ void km_update(const double* __restrict__ part, const int64_t* __rest
   const int c = v / dim;
   double s = 0.0;
   int64_t m = 0;
-  for (int64_t b = 0; b < nb; ++b) {
+  int64_t b = 0;
+  for (; b + 8 <= nb; b += 8) {
+    double t[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      t[u] = part[(b + u) * k * dim + v];
+      m += cnt[(b + u) * k + c];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s = __dadd_rn(s, t[u]);
+  }
+  for (; b < nb; ++b) {
     s = __dadd_rn(s, part[b * k * dim + v]);
     m += cnt[b * k + c];
   }
