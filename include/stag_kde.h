@@ -54,7 +54,8 @@ typedef enum {
   STAG_FORM_FP32 = 0,        /* fp32 matrix-core products */
   STAG_FORM_BF16_SPLIT = 1,  /* x = hi + lo in bf16, three bf16 products */
   STAG_FORM_FP16_SPLIT = 2,  /* x = hi + lo in fp16, three fp16 products */
-  STAG_FORM_BF16_SPLIT3 = 3  /* x = hi + mid + lo in bf16, six bf16 products */
+  STAG_FORM_BF16_SPLIT3 = 3, /* x = hi + mid + lo in bf16, six bf16 products */
+  STAG_FORM_AUTO = 4         /* exact KDE only: the cheapest form whose a-priori bound is <= eps */
 } stag_form;
 
 /* Kernel functions of Sec. "Kernel Density Estimation" (r = ||q - x||). */
@@ -65,7 +66,8 @@ typedef enum {
 } stag_kernel;
 
 /* flags of stag_kde_exact */
-#define STAG_NORMALIZE 1u  /* return S/n (the paper's K(q)) instead of S */
+#define STAG_NORMALIZE 1u     /* return S/n (the paper's K(q)) instead of S */
+#define STAG_CHECK_FINITE 2u  /* scan X and Q on the device first; a NaN or Inf is STAG_E_INVAL */
 
 /* Message describing the last non-OK status returned on this thread (never
  * NULL; empty string if none). */
@@ -95,9 +97,19 @@ double stag_e2lsh_collision_probability(double c, int32_t K, int32_t L);
  * query over a matrix of queries).
  *   X [n][d], Q [m][d]  fp32 device, row-major.
  *   a > 0, finite       Gaussian bandwidth parameter of k(x) = exp(-a x^2).
- *   eps                 reserved, pass 0.
- *   form                a stag_form.
- *   flags               STAG_NORMALIZE or 0.
+ *   eps                 target relative accuracy, used by STAG_FORM_AUTO
+ *                       (0 < eps; ignored by the other forms).
+ *   form                a stag_form.  STAG_FORM_AUTO scans X and Q once on the
+ *                       device (largest norms and elements; one
+ *                       synchronisation of `stream`) and takes, in order of
+ *                       cost, FP16_SPLIT (if the operands fit fp16's range),
+ *                       BF16_SPLIT, BF16_SPLIT3, FP32: the first whose
+ *                       a-priori bound at the largest query norm is <= eps;
+ *                       FP32 if none is (bound_out then shows it).  The
+ *                       result equals that of the chosen form bit for bit.
+ *   flags               STAG_NORMALIZE, STAG_CHECK_FINITE (one device scan
+ *                       and synchronisation; a NaN or Inf in X or Q is
+ *                       STAG_E_INVAL with nothing launched after the scan).
  *   S_out [m]  f64 device: S(q) (or S(q)/n).
  *   bound_out [m] f64 device or NULL: a-priori relative error bound of each
  *                       result (the value is |S_gpu - S| / S <= bound except
@@ -126,8 +138,8 @@ stag_status stag_kde_exact(const float* X, int64_t n, const float* Q, int64_t m,
  * sqrt(dE)); the logistic kernel is flat at r = 0 and keeps a bound of the
  * Gaussian's order.  Unknown kernel: STAG_E_INVAL. */
 stag_status stag_kde_exact_kernel(const float* X, int64_t n, const float* Q, int64_t m, int32_t d, int32_t kernel,
-                                  double a, int32_t form, uint32_t flags, double* S_out, double* bound_out,
-                                  hipStream_t stream);
+                                  double a, double eps, int32_t form, uint32_t flags, double* S_out,
+                                  double* bound_out, hipStream_t stream);
 
 /* Random-sampling kernel density (the sampling baseline of Sec. "Kernel
  * Density Estimation" and of the paper's KDE experiments: K(q) estimated from

@@ -16,9 +16,10 @@ LIB_PATH = os.path.join(HERE, "libstagkde.so")
 HEADER = os.path.join(HERE, "..", "include", "stag_kde.h")
 
 STAG_OK, STAG_E_INVAL, STAG_E_NOMEM, STAG_E_DEVICE, STAG_E_UNSUPPORTED, STAG_E_BUSY = range(6)
-FORMS = {"fp32": 0, "bf16_split": 1, "fp16_split": 2, "bf16_split3": 3}
+FORMS = {"fp32": 0, "bf16_split": 1, "fp16_split": 2, "bf16_split3": 3, "auto": 4}
 KERNELS = {"gaussian": 0, "exponential": 1, "logistic": 2}
 NORMALIZE = 1
+CHECK_FINITE = 2
 
 LSH_LITERAL = 1
 LSH_ALL_SAMPLED = 2
@@ -72,7 +73,7 @@ def load():
     lib.stag_kde_exact.restype = C.c_int
     lib.stag_kde_exact.argtypes = [vp, i64, vp, i64, i32, f64, f64, i32, u32, vp, vp, vp]
     lib.stag_kde_exact_kernel.restype = C.c_int
-    lib.stag_kde_exact_kernel.argtypes = [vp, i64, vp, i64, i32, i32, f64, i32, u32, vp, vp, vp]
+    lib.stag_kde_exact_kernel.argtypes = [vp, i64, vp, i64, i32, i32, f64, f64, i32, u32, vp, vp, vp]
     lib.stag_kde_random_sample.restype = C.c_int
     lib.stag_kde_random_sample.argtypes = [vp, i64, vp, i64, i32, f64, i64, u64, i32, vp, vp, vp, vp]
     lib.stag_rs_sample_size.restype = i64
@@ -180,11 +181,12 @@ def collision_probability(c: float, K: int = 1, L: int = 1) -> float:
 
 
 def kde_exact(X, Q, a: float, form: str = "fp32", normalize: bool = False, return_bound: bool = False,
-              S_out=None, bound_out=None, kernel: str = "gaussian"):
+              S_out=None, bound_out=None, kernel: str = "gaussian", eps: float = 0.0, check_finite: bool = False):
     """S(q) = sum_i k(||q - x_i||) for every row q of Q (float64 [m]); kernel
     "gaussian" exp(-a r^2) (default), "exponential" exp(-a r) or "logistic"
-    4/(2 + e^{ar} + e^{-ar}).  With return_bound also the per-result relative
-    error bound."""
+    4/(2 + e^{ar} + e^{-ar}).  form "auto" takes the cheapest arithmetic form
+    whose a-priori bound is <= eps.  check_finite rejects NaN/Inf inputs.
+    With return_bound also the per-result relative error bound."""
     torch = _torch()
     _need(X, torch.float32, 2, "X")
     _need(Q, torch.float32, 2, "Q")
@@ -198,14 +200,14 @@ def kde_exact(X, Q, a: float, form: str = "fp32", normalize: bool = False, retur
     B = None
     if return_bound:
         B = bound_out if bound_out is not None else torch.empty(m, dtype=torch.float64, device=X.device)
-    flags = NORMALIZE if normalize else 0
+    flags = (NORMALIZE if normalize else 0) | (CHECK_FINITE if check_finite else 0)
     if kernel == "gaussian":
-        st = load().stag_kde_exact(_ptr(X), n, _ptr(Q), m, d, float(a), 0.0, FORMS[form], flags, _ptr(S), _ptr(B),
-                                   _stream_handle(X.device))
+        st = load().stag_kde_exact(_ptr(X), n, _ptr(Q), m, d, float(a), float(eps), FORMS[form], flags, _ptr(S),
+                                   _ptr(B), _stream_handle(X.device))
         check(st, "stag_kde_exact")
     else:
-        st = load().stag_kde_exact_kernel(_ptr(X), n, _ptr(Q), m, d, KERNELS[kernel], float(a), FORMS[form], flags,
-                                          _ptr(S), _ptr(B), _stream_handle(X.device))
+        st = load().stag_kde_exact_kernel(_ptr(X), n, _ptr(Q), m, d, KERNELS[kernel], float(a), float(eps),
+                                          FORMS[form], flags, _ptr(S), _ptr(B), _stream_handle(X.device))
         check(st, "stag_kde_exact_kernel")
     return (S, B) if return_bound else S
 

@@ -28,6 +28,8 @@
 // The value of a query depends only on its own row, X and a: chunking and
 // tiling are functions of n alone, so results are identical whatever m is and
 // whatever other queries share a launch.
+#include <cstring>
+
 #include "runtime.h"
 #include "kde_exact.h"
 #include "kde_tiles.h"
@@ -170,6 +172,40 @@ stag_status prep_any(int form, const float* src, int64_t n, int d, int dp, int64
   }
 }
 
+// Statistics of an input for the form choice and the finiteness check: the
+// largest squared row norm (fp64 bits), the largest |element| (fp32 bits) and
+// whether any element is not finite.  One wave per row, 16 rows per wave.
+__global__ __launch_bounds__(256) void scan_rows(const float* __restrict__ src, int64_t rows, int d,
+                                                 unsigned long long* __restrict__ max_nrm_bits,
+                                                 unsigned int* __restrict__ max_abs_bits, int* __restrict__ bad) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  double mx = 0.0;
+  float amax = 0.0f;
+  int nonfinite = 0;
+  for (int rr = 0; rr < kPrepRowsPerWave; ++rr) {
+    const int64_t row = (int64_t)blockIdx.x * kPrepRowsPerBlock + wave * kPrepRowsPerWave + rr;
+    if (row >= rows) break;
+    double sq = 0.0;
+    for (int j = lane; j < d; j += 64) {
+      const float v = src[row * d + j];
+      if (!(fabsf(v) <= 3.402823466e38f)) nonfinite = 1;
+      else amax = fmaxf(amax, fabsf(v));
+      sq += (double)v * (double)v;
+    }
+    for (int o = 32; o > 0; o >>= 1) sq += __shfl_xor(sq, o);
+    if (sq == sq) mx = fmax(mx, sq);
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    amax = fmaxf(amax, __shfl_xor(amax, o));
+    nonfinite |= __shfl_xor(nonfinite, o);
+  }
+  if (lane == 0) {
+    if (mx > 0.0) atomicMax(max_nrm_bits, (unsigned long long)__double_as_longlong(mx));
+    if (amax > 0.0f) atomicMax(max_abs_bits, __float_as_uint(amax));
+    if (nonfinite) atomicOr(bad, 1);
+  }
+}
+
 }  // namespace
 
 int exact_padded_dim(int d) {
@@ -276,18 +312,72 @@ BoundModel make_bound_model(int form, int d, double a_tile, int kernel) {
 namespace stag {
 namespace {
 
+struct InputStats {
+  double max_nrm_x, max_nrm_q;
+  float max_abs_x, max_abs_q;
+  bool nonfinite;
+};
+
+stag_status input_stats(const float* X, int64_t n, const float* Q, int64_t m, int d, Workspace& ws,
+                        InputStats* out, hipStream_t st) {
+  unsigned long long* nb = nullptr;
+  unsigned int* ab = nullptr;
+  int* bad = nullptr;
+  STAG_TRY(ws.alloc(&nb, 2));
+  STAG_TRY(ws.alloc(&ab, 2));
+  STAG_TRY(ws.alloc(&bad, 1));
+  STAG_HIP(hipMemsetAsync(nb, 0, 2 * sizeof(unsigned long long), st));
+  STAG_HIP(hipMemsetAsync(ab, 0, 2 * sizeof(unsigned int), st));
+  STAG_HIP(hipMemsetAsync(bad, 0, sizeof(int), st));
+  hipLaunchKernelGGL(scan_rows, dim3((unsigned)ceil_div(n, kPrepRowsPerBlock)), dim3(256), 0, st, X, n, d, nb, ab,
+                     bad);
+  STAG_TRY(check_launch("scan_rows"));
+  hipLaunchKernelGGL(scan_rows, dim3((unsigned)ceil_div(m, kPrepRowsPerBlock)), dim3(256), 0, st, Q, m, d, nb + 1,
+                     ab + 1, bad);
+  STAG_TRY(check_launch("scan_rows"));
+  unsigned long long hn[2];
+  unsigned int ha[2];
+  int hb = 0;
+  STAG_HIP(hipMemcpyAsync(hn, nb, sizeof(hn), hipMemcpyDeviceToHost, st));
+  STAG_HIP(hipMemcpyAsync(ha, ab, sizeof(ha), hipMemcpyDeviceToHost, st));
+  STAG_HIP(hipMemcpyAsync(&hb, bad, sizeof(int), hipMemcpyDeviceToHost, st));
+  STAG_HIP(hipStreamSynchronize(st));
+  std::memcpy(&out->max_nrm_x, &hn[0], sizeof(double));
+  std::memcpy(&out->max_nrm_q, &hn[1], sizeof(double));
+  std::memcpy(&out->max_abs_x, &ha[0], sizeof(float));
+  std::memcpy(&out->max_abs_q, &ha[1], sizeof(float));
+  out->nonfinite = hb != 0;
+  return STAG_OK;
+}
+
+// The cheapest form whose a-priori bound at the largest query norm is <= eps
+// (the bound grows with ||q||), FP32 if none is.
+int choose_form(int d, double a_tile, int kernel, double eps, const InputStats& is) {
+  const double qscale = 2.0 * a_tile * kLog2e;  // the split query operand is q * qscale
+  const bool fp16_ok = (double)is.max_abs_x < 65504.0 && (double)is.max_abs_q * qscale < 65504.0;
+  const int order[3] = {STAG_FORM_FP16_SPLIT, STAG_FORM_BF16_SPLIT, STAG_FORM_BF16_SPLIT3};
+  if (d <= 256)
+    for (int f : order) {
+      if (f == STAG_FORM_FP16_SPLIT && !fp16_ok) continue;
+      if (relative_bound(make_bound_model(f, d, a_tile, kernel), is.max_nrm_q, is.max_nrm_x) <= eps) return f;
+    }
+  return STAG_FORM_FP32;
+}
+
 stag_status exact_kernel_impl(const char* fn, const float* X, int64_t n, const float* Q, int64_t m, int32_t d,
-                              int32_t kernel, double a, int32_t form, uint32_t flags, double* S_out,
+                              int32_t kernel, double a, double eps, int32_t form, uint32_t flags, double* S_out,
                               double* bound_out, hipStream_t stream) {
   if (!X || !Q || !S_out) return fail(STAG_E_INVAL, "%s: NULL pointer argument", fn);
   if (n < 1 || m < 1 || d < 1) return fail(STAG_E_INVAL, "%s: n, m, d must be >= 1", fn);
   if (!(a > 0.0) || !std::isfinite(a)) return fail(STAG_E_INVAL, "%s: a must be positive and finite", fn);
   if (kernel < STAG_KERNEL_GAUSSIAN || kernel > STAG_KERNEL_LOGISTIC)
     return fail(STAG_E_INVAL, "%s: unknown kernel %d", fn, kernel);
-  if (form < STAG_FORM_FP32 || form > STAG_FORM_BF16_SPLIT3) return fail(STAG_E_INVAL, "%s: unknown form %d", fn, form);
-  if (flags & ~STAG_NORMALIZE) return fail(STAG_E_INVAL, "%s: unknown flags 0x%x", fn, flags);
+  if (form < STAG_FORM_FP32 || form > STAG_FORM_AUTO) return fail(STAG_E_INVAL, "%s: unknown form %d", fn, form);
+  if (form == STAG_FORM_AUTO && !(eps > 0.0))
+    return fail(STAG_E_INVAL, "%s: STAG_FORM_AUTO needs a target eps > 0", fn);
+  if (flags & ~(STAG_NORMALIZE | STAG_CHECK_FINITE)) return fail(STAG_E_INVAL, "%s: unknown flags 0x%x", fn, flags);
   if (d > 1024) return fail(STAG_E_UNSUPPORTED, "%s: d = %d > 1024 is not supported", fn, d);
-  if (d > 256 && form != STAG_FORM_FP32)
+  if (d > 256 && form != STAG_FORM_FP32 && form != STAG_FORM_AUTO)
     return fail(STAG_E_UNSUPPORTED, "%s: d = %d > 256 is supported by the fp32 form only", fn, d);
   if ((double)n * d >= 2147483648.0 || (double)m * d >= 2147483648.0)
     return fail(STAG_E_INVAL, "%s: n*d and m*d must be < 2^31", fn);
@@ -295,6 +385,12 @@ stag_status exact_kernel_impl(const char* fn, const float* X, int64_t n, const f
   if (!std::isfinite(at) || !(at > 0.0)) return fail(STAG_E_INVAL, "%s: a out of range for this kernel", fn);
   clear_error();
   Workspace ws(stream);
+  if (form == STAG_FORM_AUTO || (flags & STAG_CHECK_FINITE)) {
+    InputStats is;
+    STAG_TRY(input_stats(X, n, Q, m, d, ws, &is, stream));
+    if ((flags & STAG_CHECK_FINITE) && is.nonfinite) return fail(STAG_E_INVAL, "%s: X or Q holds NaN or Inf", fn);
+    if (form == STAG_FORM_AUTO) form = choose_form(d, at, kernel, eps, is);
+  }
   Operands xo, qo;
   STAG_TRY(prepare_operands(form, X, n, d, at, false, ws, &xo, stream));
   STAG_TRY(prepare_operands(form, Q, m, d, at, true, ws, &qo, stream));
@@ -315,14 +411,13 @@ stag_status exact_kernel_impl(const char* fn, const float* X, int64_t n, const f
 extern "C" stag_status stag_kde_exact(const float* X, int64_t n, const float* Q, int64_t m, int32_t d, double a,
                                       double eps, int32_t form, uint32_t flags, double* S_out, double* bound_out,
                                       hipStream_t stream) {
-  (void)eps;
-  return stag::exact_kernel_impl("stag_kde_exact", X, n, Q, m, d, STAG_KERNEL_GAUSSIAN, a, form, flags, S_out,
+  return stag::exact_kernel_impl("stag_kde_exact", X, n, Q, m, d, STAG_KERNEL_GAUSSIAN, a, eps, form, flags, S_out,
                                  bound_out, stream);
 }
 
 extern "C" stag_status stag_kde_exact_kernel(const float* X, int64_t n, const float* Q, int64_t m, int32_t d,
-                                             int32_t kernel, double a, int32_t form, uint32_t flags, double* S_out,
-                                             double* bound_out, hipStream_t stream) {
-  return stag::exact_kernel_impl("stag_kde_exact_kernel", X, n, Q, m, d, kernel, a, form, flags, S_out, bound_out,
-                                 stream);
+                                             int32_t kernel, double a, double eps, int32_t form, uint32_t flags,
+                                             double* S_out, double* bound_out, hipStream_t stream) {
+  return stag::exact_kernel_impl("stag_kde_exact_kernel", X, n, Q, m, d, kernel, a, eps, form, flags, S_out,
+                                 bound_out, stream);
 }

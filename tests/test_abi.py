@@ -45,16 +45,23 @@ def test_invalid_arguments_rejected_before_launch():
     assert st == _lib.STAG_E_INVAL
     st = lib.stag_kde_exact(fake, 10, fake, 10, 4, 1.0, 0.0, 0, 0x80, fake, null, null)
     assert st == _lib.STAG_E_INVAL
-    st = lib.stag_kde_exact_kernel(fake, 10, fake, 10, 4, 3, 1.0, 0, 0, fake, null, null)
+    st = lib.stag_kde_exact_kernel(fake, 10, fake, 10, 4, 3, 1.0, 0.0, 0, 0, fake, null, null)
     assert st == _lib.STAG_E_INVAL and "unknown kernel" in stag.last_error()
-    st = lib.stag_kde_exact_kernel(fake, 10, fake, 10, 4, -1, 1.0, 0, 0, fake, null, null)
+    st = lib.stag_kde_exact_kernel(fake, 10, fake, 10, 4, -1, 1.0, 0.0, 0, 0, fake, null, null)
     assert st == _lib.STAG_E_INVAL
-    st = lib.stag_kde_exact_kernel(fake, 10, fake, 10, 4, 1, 0.0, 0, 0, fake, null, null)
+    st = lib.stag_kde_exact_kernel(fake, 10, fake, 10, 4, 1, 0.0, 0.0, 0, 0, fake, null, null)
     assert st == _lib.STAG_E_INVAL and "a must be" in stag.last_error()
-    st = lib.stag_kde_exact_kernel(fake, 10, fake, 10, 4, 2, 1e200, 0, 0, fake, null, null)
+    st = lib.stag_kde_exact_kernel(fake, 10, fake, 10, 4, 2, 1e200, 0.0, 0, 0, fake, null, null)
     assert st == _lib.STAG_E_INVAL and "out of range" in stag.last_error()
-    st = lib.stag_kde_exact_kernel(fake, 10, fake, 10, 300, 1, 1.0, 2, 0, fake, null, null)
+    st = lib.stag_kde_exact_kernel(fake, 10, fake, 10, 300, 1, 1.0, 0.0, 2, 0, fake, null, null)
     assert st == _lib.STAG_E_UNSUPPORTED
+    # STAG_FORM_AUTO needs eps > 0; unknown forms and flags
+    st = lib.stag_kde_exact(fake, 10, fake, 10, 4, 1.0, 0.0, 4, 0, fake, null, null)
+    assert st == _lib.STAG_E_INVAL and "eps" in stag.last_error()
+    st = lib.stag_kde_exact(fake, 10, fake, 10, 4, 1.0, 1e-3, 5, 0, fake, null, null)
+    assert st == _lib.STAG_E_INVAL
+    st = lib.stag_kde_exact(fake, 10, fake, 10, 4, 1.0, 0.0, 0, 4, fake, null, null)
+    assert st == _lib.STAG_E_INVAL
     it = C.c_int32(0)
     st = lib.stag_spectral_embedding(10, fake, fake, fake, 5, 0, 1e-8, 10, 0, null, fake, C.byref(it), null)
     assert st == _lib.STAG_E_INVAL and "k must be" in stag.last_error()

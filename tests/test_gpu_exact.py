@@ -5,6 +5,8 @@ Tolerance: the fp32 form must be within 1e-5 relative wherever the
 exponent magnitudes allow it (a small enough that a(||q||^2+||x||^2) stays
 moderate); every form must be within its own per-result bound on every query.
 """
+import math
+
 import numpy as np
 import pytest
 
@@ -138,3 +140,58 @@ def test_config3_full_size_sampled(stag, orc):
         err = rel_err(S[idx], ref)
         assert np.all(err <= B[idx]), (form, err.max())
         assert np.all(np.isfinite(S))
+
+
+def _auto_expected(bounds, eps, fp16_ok):
+    for f in (["fp16_split"] if fp16_ok else []) + ["bf16_split", "bf16_split3"]:
+        if bounds[f] <= eps:
+            return f
+    return "fp32"
+
+
+@pytest.mark.parametrize("scale", [1.0, 1e5])
+def test_auto_form_choice(stag, scale):
+    """STAG_FORM_AUTO returns, bit for bit, the cheapest form (fp16 split when
+    the operands fit fp16, bf16 split, bf16 three-way, fp32) whose largest
+    per-result bound is <= eps, fp32 when none is."""
+    import torch
+    X, Q, _ = synth.config_points(2, n=9000, m=300)
+    X, Q = (X * scale).astype(np.float32), (Q * scale).astype(np.float32)
+    a = 0.01 / scale ** 2
+    Xd, Qd = to_dev(X), to_dev(Q)
+    res, bounds = {}, {}
+    for f in FORMS:
+        S, B = stag.kde_exact(Xd, Qd, a, form=f, return_bound=True)
+        torch.cuda.synchronize()
+        res[f], bounds[f] = S.cpu().numpy(), float(B.cpu().numpy().max())
+    fp16_ok = scale == 1.0  # |x| ~ 5e5 is past fp16's range
+    levels = sorted(set(bounds.values()))
+    eps_list = [levels[0] / 2] + [math.sqrt(u * v) for u, v in zip(levels, levels[1:])] + [levels[-1] * 2]
+    for eps in eps_list:
+        announce(f"auto form scale={scale} eps={eps:.3e}")
+        S = stag.kde_exact(Xd, Qd, a, form="auto", eps=eps)
+        torch.cuda.synchronize()
+        want = _auto_expected(bounds, eps, fp16_ok)
+        assert np.array_equal(S.cpu().numpy(), res[want]), (eps, want, bounds)
+
+
+def test_check_finite_flag(stag):
+    import torch
+    import paper_2407_07096_amd._lib as L
+    X, Q, _ = synth.config_points(1, n=500, m=40)
+    Xb = X.copy()
+    Xb[17, 3] = np.nan
+    Qb = Q.copy()
+    Qb[5, 0] = np.inf
+    announce("check finite flag")
+    for Xi, Qi in [(Xb, Q), (X, Qb)]:
+        with pytest.raises(L.StagError):
+            stag.kde_exact(to_dev(Xi), to_dev(Qi), 0.5, form="fp32", check_finite=True)
+    S = stag.kde_exact(to_dev(X), to_dev(Q), 0.5, form="fp32", check_finite=True)
+    S0 = stag.kde_exact(to_dev(X), to_dev(Q), 0.5, form="fp32")
+    torch.cuda.synchronize()
+    assert np.array_equal(S.cpu().numpy(), S0.cpu().numpy())
+    # without the flag the call runs and the NaN propagates to the affected results
+    Sn = stag.kde_exact(to_dev(Xb), to_dev(Q), 0.5, form="fp32")
+    torch.cuda.synchronize()
+    assert np.all(np.isnan(Sn.cpu().numpy()))
