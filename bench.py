@@ -70,8 +70,14 @@ def cpu_baseline(X, Q, a, budget_s: float):
         oracle.kde_exact(X, Q[done1:done1 + 8], a, nthreads=1)
         t1 += time.perf_counter() - t0
         done1 += min(8, Q.shape[0] - done1)
+    cpu = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            cpu = next((l.split(":", 1)[1].strip() for l in fh if l.startswith("model name")), cpu)
+    except OSError:
+        pass
     return {"value": X.shape[0] * done / t_total, "unit": "Gaussian kernel evals/s", "cores": threads,
-            "kind": "oracle", "value_1thread": X.shape[0] * done1 / t1,
+            "cpu_model": cpu, "kind": "oracle", "value_1thread": X.shape[0] * done1 / t1,
             "sample": f"{done} of the {Q.shape[0]} queries against all {X.shape[0]} points, exact FP64 direct "
                       f"differences with compensated log-sum-exp, OpenMP over queries; {t_total:.1f} s"}
 
@@ -273,8 +279,11 @@ def e2lsh_table_run(stag, torch, dev, lib, buf, Xd, Qd, K: int = 6, L: int = 50)
 
 
 def serving_run(stag, torch, dev, n_requests: int, seconds_cap: float):
-    """Poisson stream of requests of log-uniform size (1..65536) against four
-    resident data sets; returns latency percentiles and throughput."""
+    """Requests of log-uniform size (1..65536) against four resident data
+    sets.  A burst submitted at once measures the saturation throughput;
+    Poisson streams at 0.5, 0.8 and 0.95 of the saturation request rate then
+    give latency percentiles and throughput at each load (0.5 is the headline
+    figure)."""
     import numpy as np
 
     import synth
@@ -288,42 +297,64 @@ def serving_run(stag, torch, dev, n_requests: int, seconds_cap: float):
         ids.append(srv.add_dataset(X, 0.64 / d, form))
         mixes.append(mix)
         del X
-    arr, sizes, dsel = synth.poisson_requests(n_requests, rate_per_s=200.0, seed=4005)
-    # queries drawn once per request (host), moved to the device before the clock starts
-    reqs = []
-    for r in range(n_requests):
-        k = int(dsel[r])
-        Q = synth.sample(mixes[k], int(sizes[r]), 7000 + r)
-        reqs.append((k, torch.from_numpy(Q).to(dev)))
-    torch.cuda.synchronize()
-    t_start = time.perf_counter()
-    tickets = []
-    for r in range(n_requests):
-        now = time.perf_counter() - t_start
-        if arr[r] > now:
-            time.sleep(arr[r] - now)
-        if time.perf_counter() - t_start > seconds_cap:
-            break
-        k, Q = reqs[r]
-        tickets.append((srv.submit(ids[k], Q), Q.shape[0], specs[k][0]))
-    lat, evals = [], 0.0
-    for t, m, n in tickets:
-        _, st, l = srv.wait(t)
-        if st == 0:
-            lat.append(l)
-            evals += float(m) * n
-    t_end = time.perf_counter()
+
+    def make(count, rate, seed):
+        arr, sizes, dsel = synth.poisson_requests(count, rate_per_s=rate, seed=seed)
+        reqs = []
+        for r in range(count):
+            k = int(dsel[r])
+            Q = synth.sample(mixes[k], int(sizes[r]), seed * 100_000 + r)
+            reqs.append((k, torch.from_numpy(Q).to(dev)))
+        torch.cuda.synchronize()
+        return arr, reqs
+
+    def run(arr, reqs, paced):
+        t_start = time.perf_counter()
+        tickets = []
+        for r, (k, Q) in enumerate(reqs):
+            if paced:
+                now = time.perf_counter() - t_start
+                if arr[r] > now:
+                    time.sleep(arr[r] - now)
+            if time.perf_counter() - t_start > seconds_cap:
+                break
+            tickets.append((srv.submit(ids[k], Q), Q.shape[0], specs[k][0]))
+        lat, evals = [], 0.0
+        for t, m, n in tickets:
+            _, st, l = srv.wait(t)
+            if st == 0:
+                lat.append(l)
+                evals += float(m) * n
+        t_end = time.perf_counter()
+        lat = np.sort(np.array(lat))
+
+        def pct(p):
+            return float(lat[max(0, math.ceil(p / 100 * len(lat)) - 1)]) * 1e3 if len(lat) else None
+        return {"requests": len(tickets), "p50_ms": pct(50), "p99_ms": pct(99), "evals_per_s": evals / (t_end - t_start),
+                "evals": evals, "wall_s": t_end - t_start}
+
+    # saturation: a burst of requests submitted at once
+    arr, reqs = make(min(n_requests, 300), 1.0, 4005)
+    burst = run(arr, reqs, paced=False)
+    del reqs
+    evals_per_req = burst["evals"] / max(burst["requests"], 1)
+    sat_rate = burst["evals_per_s"] / evals_per_req
+    loads = []
+    for li, rho in enumerate((0.5, 0.8, 0.95)):
+        rate = rho * sat_rate
+        arr, reqs = make(n_requests, rate, 4006 + li)
+        r = run(arr, reqs, paced=True)
+        del reqs
+        r.update({"rho": rho, "offered_rate_per_s": rate})
+        loads.append(r)
     stats = srv.stats()
     srv.close()
-    lat = np.sort(np.array(lat))
-
-    def pct(p):
-        return float(lat[max(0, math.ceil(p / 100 * len(lat)) - 1)]) if len(lat) else None
-    return {"requests": len(tickets), "completed": int(stats["completed"]), "batches": int(stats["batches"]),
-            "p50_ms": pct(50) * 1e3 if len(lat) else None, "p99_ms": pct(99) * 1e3 if len(lat) else None,
-            "evals_per_s": evals / (t_end - t_start), "offered_rate_per_s": 200.0,
-            "datasets": [f"n={n} d={d}" for n, d in specs],
-            "batch_sizes": "log-uniform 1..65536", "wall_s": t_end - t_start}
+    head = loads[0]
+    return {"p50_ms": head["p50_ms"], "p99_ms": head["p99_ms"], "evals_per_s": head["evals_per_s"],
+            "headline_load": 0.5, "saturation_evals_per_s": burst["evals_per_s"],
+            "saturation_request_rate_per_s": sat_rate, "loads": loads, "completed": int(stats["completed"]),
+            "batches": int(stats["batches"]), "datasets": [f"n={n} d={d}" for n, d in specs],
+            "batch_sizes": "log-uniform 1..65536", "requests_per_load": n_requests}
 
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -363,7 +394,7 @@ def main():
     ap.add_argument("--a", type=float, default=0.01)
     ap.add_argument("--check-queries", type=int, default=256)
     ap.add_argument("--cpu-budget", type=float, default=12.0)
-    ap.add_argument("--serve-requests", type=int, default=400)
+    ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-precision-config", action="store_true",
