@@ -132,11 +132,21 @@ stag_status stag_kde_exact(const float* X, int64_t n, const float* Q, int64_t m,
  * lambda = (a log2 e)^2 for the exponential and logistic kernels, and takes
  * y = sqrt(max(-E, 0)) = a r log2(e); FP16_SPLIT then needs
  * |2 (a log2 e)^2 q_j| below 65504.
- * bound_out: the a-priori relative error bound per result.  Through the
- * expanded distance, the exponential kernel's bound is dominated by pairs at
- * distance near zero (an error dE in the exponent moves sqrt(-E) by up to
- * sqrt(dE)); the logistic kernel is flat at r = 0 and keeps a bound of the
- * Gaussian's order.  Unknown kernel: STAG_E_INVAL. */
+ * Exponential kernel, near pairs: where the computed -E is below 1/4
+ * (a r < 1/(2 log2 e), kernel value above 2^-1/2) an error dE in the
+ * exponent would move y by up to sqrt(dE); those terms are taken out of the
+ * tile sum and evaluated as exp(-a ||q - x||) from fp64 differences of the
+ * input rows, in a fixed order (results stay deterministic).  They cost d
+ * fp64 operations each and are rare unless many points lie within 1/(2 a
+ * log2 e) of a query.  At least 8 of the 32-row data tiles that hold such
+ * pairs are taken per query and 4096-row chunk; a query with more keeps the
+ * rest in its tile sums and the unrefined bound.
+ * bound_out: the a-priori relative error bound per result; for the
+ * exponential kernel it uses y^2 >= 1/4 - dE for the terms left to the tile
+ * (|dy| <= dE / (2 sqrt(1/4 - dE))), or |dy| <= sqrt(dE) for a query whose
+ * near pairs did not all fit; the logistic kernel is flat at r = 0 and keeps
+ * a bound of the Gaussian's order.  STAG_FORM_AUTO assumes the near pairs
+ * fit.  Unknown kernel: STAG_E_INVAL. */
 stag_status stag_kde_exact_kernel(const float* X, int64_t n, const float* Q, int64_t m, int32_t d, int32_t kernel,
                                   double a, double eps, int32_t form, uint32_t flags, double* S_out,
                                   double* bound_out, hipStream_t stream);

@@ -34,9 +34,14 @@ struct Operands {
 // |d ln k / d(r^2)| <= 1/4 bounds the effect of the exponent error, and
 // dy = 2^-23 min(150, sqrt(la) (||q|| + max||x||)) is the rounding of
 // y = sqrt(-E) (terms with y > 150 are below 2^-150 and flush to zero).
+// Exponential kernel: terms with computed y^2 = -E below this are evaluated
+// exactly from the input rows (the tile's near pairs).
+constexpr double kNearY2 = 0.25;
+
 struct BoundModel {
   double la, c_acc, c_split, c_off, c_tail;
-  int kern = 0;  // a stag_kernel
+  int kern = 0;          // a stag_kernel
+  double near_y2 = 0.0;  // exponential kernel: terms with computed y^2 below this are exact
 };
 
 __host__ __device__ inline double relative_bound(const BoundModel& bm, double qn, double xm) {
@@ -46,7 +51,13 @@ __host__ __device__ inline double relative_bound(const BoundModel& bm, double qn
   const double dE = bm.c_acc * (cross + offs) + bm.c_split * cross + bm.c_off * offs;
   if (bm.kern == 0) return expm1(ln2 * dE) + bm.c_tail;
   const double dy = 0x1.0p-23 * fmin(150.0, sqrt(bm.la) * (sqrt(qn) + sqrt(xm)));
-  if (bm.kern == 1) return expm1(ln2 * (sqrt(dE) + dy)) + bm.c_tail;
+  if (bm.kern == 1) {
+    // A term left to the tile has computed y^2 >= near_y2, so its true y^2 is
+    // >= near_y2 - dE and |dy| <= dE / (2 sqrt(near_y2 - dE)); without that
+    // floor, y -> 0 gives |dy| <= sqrt(dE).
+    const double dyE = bm.near_y2 > 2.0 * dE ? dE / (2.0 * sqrt(bm.near_y2 - dE)) : sqrt(dE);
+    return expm1(ln2 * (dyE + dy)) + bm.c_tail;
+  }
   const double log2e = 1.4426950408889634074;
   return expm1(dE / (4.0 * log2e * log2e) + ln2 * dy) + bm.c_tail + 5.0 * 0x1.0p-23;
 }
@@ -57,7 +68,20 @@ __host__ __device__ inline double relative_bound(const BoundModel& bm, double qn
 // partial sums tp[query * ntile + tile] (fp32; ntile, the row stride, is at
 // least padded data rows / 32 and a multiple of 16).
 struct TileExtra {
-  int kernel = 0;  // a stag_kernel; the two outputs below need the Gaussian
+  int kernel = 0;  // a stag_kernel; self and tp need the Gaussian
+  // Exponential kernel, near pairs: a value whose computed -E is below near_e
+  // (of a query < m_rows) is taken out of the tile sum and replaced by
+  // exp(-a ||q - x||) from fp64 direct differences of the input rows
+  // near_x[row * d], near_q[query * d].  Off when near_x is null.  A query
+  // with more near pairs than the tile can hold gets near_over[query] = 1
+  // (the array starts at zero) and keeps the excess in its tile sums.
+  const float* near_x = nullptr;
+  int* near_over = nullptr;
+  const float* near_q = nullptr;
+  int d = 0;
+  float near_e = 0.0f;
+  double a = 0.0;
+  int64_t m_rows = 0;
   int self = 0;
   float* tp = nullptr;
   int64_t ntile = 0;
@@ -83,6 +107,7 @@ int64_t query_tile_rows();
 stag_status launch_exact_tiles(const Operands& xo, const Operands& qo, double* partial, const TileExtra& ex,
                                hipStream_t st);
 stag_status launch_reduce(const double* partial, int P, const Operands& qo, const Operands& xo, double scale,
-                          const BoundModel& bm, double* S_out, double* bound_out, hipStream_t st);
+                          const BoundModel& bm, double* S_out, double* bound_out, hipStream_t st,
+                          const int* near_over = nullptr);
 
 }  // namespace stag

@@ -130,7 +130,8 @@ __global__ __launch_bounds__(256) void prep_rows(const float* __restrict__ src, 
 // S(q) = sum of chunk partials in chunk order; optional 1/n; a-priori bound.
 __global__ void reduce_partials(const double* __restrict__ partial, int P, int64_t m_pad, int64_t m, double scale,
                                 const double* __restrict__ qnrm, const unsigned long long* __restrict__ max_xnrm_bits,
-                                BoundModel bm, double* __restrict__ S_out, double* __restrict__ bound_out) {
+                                BoundModel bm, const int* __restrict__ near_over, double* __restrict__ S_out,
+                                double* __restrict__ bound_out) {
   const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= m) return;
   double s = 0.0;
@@ -138,6 +139,7 @@ __global__ void reduce_partials(const double* __restrict__ partial, int P, int64
   S_out[q] = s * scale;
   if (bound_out) {
     const double xm = __longlong_as_double((long long)*max_xnrm_bits);
+    if (near_over && near_over[q]) bm.near_y2 = 0.0;  // near pairs left in the tile sums
     bound_out[q] = relative_bound(bm, qnrm[q], xm);
   }
 }
@@ -276,11 +278,12 @@ stag_status launch_exact_tiles(const Operands& xo, const Operands& qo, double* p
 }
 
 stag_status launch_reduce(const double* partial, int P, const Operands& qo, const Operands& xo, double scale,
-                          const BoundModel& bm, double* S_out, double* bound_out, hipStream_t st) {
+                          const BoundModel& bm, double* S_out, double* bound_out, hipStream_t st,
+                          const int* near_over) {
   const int64_t m = qo.rows;
   ScopedTimer tm("kde_reduce", st);
   hipLaunchKernelGGL(reduce_partials, dim3((unsigned)ceil_div(m, 256)), dim3(256), 0, st, partial, P, qo.rows_pad, m,
-                     scale, qo.nrm, xo.max_nrm_bits, bm, S_out, bound_out);
+                     scale, qo.nrm, xo.max_nrm_bits, bm, near_over, S_out, bound_out);
   return check_launch("reduce_partials");
 }
 
@@ -304,6 +307,7 @@ BoundModel make_bound_model(int form, int d, double a_tile, int kernel) {
   bm.c_split = c_split;
   bm.c_off = 3.0 * u;                   // alpha, beta rounded to fp32
   bm.c_tail = 0x1.0p-22 + 16.0 * u;     // exp2 and the 16-term fp32 tile sums
+  if (kernel == STAG_KERNEL_EXPONENTIAL) bm.near_y2 = kNearY2;
   return bm;
 }
 
@@ -399,9 +403,20 @@ stag_status exact_kernel_impl(const char* fn, const float* X, int64_t n, const f
   STAG_TRY(ws.alloc(&partial, (size_t)P * qo.rows_pad));
   TileExtra ex;
   ex.kernel = kernel;
+  if (kernel == STAG_KERNEL_EXPONENTIAL) {
+    ex.near_x = X;
+    ex.near_q = Q;
+    ex.d = d;
+    ex.near_e = (float)kNearY2;
+    ex.a = a;
+    ex.m_rows = m;
+    STAG_TRY(ws.alloc(&ex.near_over, (size_t)m));
+    STAG_HIP(hipMemsetAsync(ex.near_over, 0, (size_t)m * sizeof(int), stream));
+  }
   STAG_TRY(launch_exact_tiles(xo, qo, partial, ex, stream));
   const double scale = (flags & STAG_NORMALIZE) ? 1.0 / (double)n : 1.0;
-  STAG_TRY(launch_reduce(partial, P, qo, xo, scale, make_bound_model(form, d, at, kernel), S_out, bound_out, stream));
+  STAG_TRY(launch_reduce(partial, P, qo, xo, scale, make_bound_model(form, d, at, kernel), S_out, bound_out, stream,
+                         ex.near_over));
   return STAG_OK;
 }
 

@@ -93,16 +93,66 @@ struct TileSums8 {
   float v[8];
 };
 
+// Near pairs of the exponential kernel.  The epilogue only records them: per
+// lane and chunk up to kNearSlots tiles that hold some, each as (chunk-relative
+// tile index << 16 | 16-bit mask of the lane's values), in the workgroup's LDS
+// (slot k of thread tid at k * 256 + tid), in tile order.  After the tile
+// loop each lane adds their exact values, exp(-a ||q - x||) from fp64
+// differences of the input rows, in row order; a lane with near pairs in more
+// tiles than slots leaves the rest in its tile sums and flags its query in
+// ex.near_over (the bound of that query then takes no credit for the
+// refinement).  The slow path stays outside the tile loop.
+constexpr int kNearSlots = 8;
+
+struct NearRec {
+  uint32_t* slots;  // LDS, kNearSlots * 256
+  int n;
+  bool over;
+};
+
+template <int MODE>
+using near_lds_t = uint32_t[MODE == kModeExponential ? kNearSlots * 256 : 1];
+
+// End of a chunk for one lane (column qi, half h; value i of tile t is row
+// 32 t + 8(i/4) + 4h + i%4 of the chunk starting at row0): exact near terms
+// and the overflow flag.
+__device__ inline double near_finish(const TileExtra& ex, const NearRec& nr, int64_t qi, int h, int64_t row0,
+                                     int tid) {
+  if (nr.over) ex.near_over[qi] = 1;
+  double s = 0.0;
+  if (nr.n > 0) {
+    const float* qr = ex.near_q + qi * ex.d;
+    for (int k = 0; k < nr.n; ++k) {
+      const uint32_t e = nr.slots[k * 256 + tid];
+      const int64_t rb = row0 + (int64_t)(e >> 16) * kTileRows + 4 * h;
+      for (uint32_t b = e & 0xFFFFu; b != 0; b &= b - 1) {
+        const int i = __builtin_ctz(b);
+        const float* xr = ex.near_x + (rb + 8 * (i >> 2) + (i & 3)) * ex.d;
+        double r2 = 0.0;
+        for (int j = 0; j < ex.d; ++j) {
+          const double t = (double)qr[j] - (double)xr[j];
+          r2 = fma(t, t, r2);
+        }
+        s += exp(-ex.a * sqrt(r2));
+      }
+    }
+  }
+  return s;
+}
+
 // Epilogue of one finished 32x32 tile held by a lane (column qi, half h):
 // kernel values and fp32 tree sum; in kModeGaussExtra, optionally drops the diagonal element
 // (data row == query index, for a data set queried against itself) and
 // records the tile's 32-row partial sum (both halves, fixed order), through
 // the group buffer `grp` when the caller walks tiles in order (`last` marks
-// the chunk's final tile), else with a direct store.
+// the chunk's final tile), else with a direct store.  In kModeExponential
+// with near pairs on (ex.near_x), values whose computed -E is below
+// ex.near_e leave the fp32 sum and are recorded in *nr (tile_rel: the tile's
+// index in its chunk).
 template <int MODE>
 __device__ inline float tile_epilogue(const f32x16& c, int64_t row_base, int64_t col_base, int r32, int h,
                                       int64_t qi, const TileExtra& ex, TileSums8* grp = nullptr,
-                                      bool last = false) {
+                                      bool last = false, NearRec* nr = nullptr, int tile_rel = 0) {
   constexpr bool EXTRA = MODE == kModeGaussExtra;
   float cp[16];
 #pragma unroll
@@ -114,6 +164,28 @@ __device__ inline float tile_epilogue(const f32x16& c, int64_t row_base, int64_t
       const bool mine = h == ((r32 & 7) >> 2);
 #pragma unroll
       for (int i = 0; i < 16; ++i) cp[i] = (mine && i == idg) ? kPadOffset : cp[i];
+    }
+  }
+  if constexpr (MODE == kModeExponential) {
+    if (ex.near_x) {
+      // Near a data point -E = y^2 is the difference of large terms and y =
+      // sqrt(-E) magnifies its error; such terms (kernel above 2^-sqrt(near_e))
+      // are rare and are evaluated from the input rows instead.
+      float mx = cp[0];
+#pragma unroll
+      for (int i = 1; i < 16; ++i) mx = fmaxf(mx, cp[i]);
+      if (-mx < ex.near_e && qi < ex.m_rows) {
+        uint32_t nm = 0;
+#pragma unroll
+        for (int i = 0; i < 16; ++i) nm |= (-cp[i] < ex.near_e) ? (1u << i) : 0u;
+        const bool room = nr->n < kNearSlots;
+        if (room) nr->slots[nr->n * 256 + threadIdx.x] = ((uint32_t)tile_rel << 16) | nm;
+        nr->n += room ? 1 : 0;
+        nr->over |= !room;
+        const uint32_t took = room ? nm : 0u;
+#pragma unroll
+        for (int i = 0; i < 16; ++i) cp[i] = ((took >> i) & 1u) ? kPadOffset : cp[i];
+      }
     }
   }
   const float s = kernel_tile_sum<MODE>(cp);
@@ -139,9 +211,6 @@ __device__ inline float tile_epilogue(const f32x16& c, int64_t row_base, int64_t
   }
   return s;
 }
-
-// Split v into parts of the form's element type: v ~= p0 + p1 (+ p2); each
-// remainder is exact in fp32 (Sterbenz), so only the last part is rounded.
 
 // ---------------------------------------------------------------------------
 // Tile loop shared by both forms.  Each step t (one 32-row data tile):
@@ -214,12 +283,16 @@ __global__ __launch_bounds__(256, 2) void tile_f32(const float* __restrict__ Xp,
 
   double acc = 0.0;
   TileSums8 grp = {};
+  __shared__ near_lds_t<MODE> near_lds;
+  NearRec nr = {near_lds, 0, false};
   auto step = [&](int t, const f32x16& cdone, f32x16& cnew) {
     const int buf = t & 1;
     __syncthreads();
     if constexpr (MODE == kModeGaussExtra) {
       if (t > 0)
         acc += (double)tile_epilogue<MODE>(cdone, row0 + (int64_t)(t - 1) * kTileRows, col_base, r32, h, qi, ex, &grp);
+    } else if constexpr (MODE == kModeExponential) {
+      acc += (double)tile_epilogue<MODE>(cdone, 0, 0, r32, h, qi, ex, nullptr, false, &nr, t - 1);
     } else {
       acc += (double)tile_epilogue<MODE>(cdone, 0, 0, r32, h, qi, ex);
     }
@@ -268,7 +341,8 @@ __global__ __launch_bounds__(256, 2) void tile_f32(const float* __restrict__ Xp,
     ca = cb;
   }
   acc += (double)tile_epilogue<MODE>(ca, row0 + (int64_t)(ntiles - 1) * kTileRows, col_base, r32, h, qi, ex, &grp,
-                                    true);
+                                    true, &nr, ntiles - 1);
+  if constexpr (MODE == kModeExponential) acc += near_finish(ex, nr, qi, h, row0, tid);
   const double other = __shfl_down(acc, 32);
   if (h == 0) partial[(int64_t)chunk * m_pad + qi] = acc + other;
 }
@@ -352,12 +426,16 @@ __global__ __launch_bounds__(256, 2) void tile_split(
 
   double acc = 0.0;
   TileSums8 grp = {};
+  __shared__ near_lds_t<MODE> near_lds;
+  NearRec nr = {near_lds, 0, false};
   auto step = [&](int t, const f32x16& cdone, f32x16& cnew) {
     const int buf = t & 1;
     __syncthreads();
     if constexpr (MODE == kModeGaussExtra) {
       if (t > 0)
         acc += (double)tile_epilogue<MODE>(cdone, row0 + (int64_t)(t - 1) * kTileRows, col_base, r32, h, qi, ex, &grp);
+    } else if constexpr (MODE == kModeExponential) {
+      acc += (double)tile_epilogue<MODE>(cdone, 0, 0, r32, h, qi, ex, nullptr, false, &nr, t - 1);
     } else {
       acc += (double)tile_epilogue<MODE>(cdone, 0, 0, r32, h, qi, ex);
     }
@@ -413,7 +491,8 @@ __global__ __launch_bounds__(256, 2) void tile_split(
     ca = cb;
   }
   acc += (double)tile_epilogue<MODE>(ca, row0 + (int64_t)(ntiles - 1) * kTileRows, col_base, r32, h, qi, ex, &grp,
-                                    true);
+                                    true, &nr, ntiles - 1);
+  if constexpr (MODE == kModeExponential) acc += near_finish(ex, nr, qi, h, row0, tid);
   const double other = __shfl_down(acc, 32);
   if (h == 0) partial[(int64_t)chunk * m_pad + qi] = acc + other;
 }
@@ -454,6 +533,8 @@ __global__ __launch_bounds__(256) void tile_f32_wide(const float* __restrict__ X
   const int ntiles = (int)(rem < kChunkRows / kTileRows ? rem : kChunkRows / kTileRows);
   const float* brow = &qlds[r32 * LD + h * H];
   double acc = 0.0;
+  __shared__ near_lds_t<MODE> near_lds;
+  NearRec nr = {near_lds, 0, false};
   for (int t = wave; t < ntiles; t += 4) {
     const int64_t rb = row0 + (int64_t)t * kTileRows;
     const f32x4* arow = reinterpret_cast<const f32x4*>(Xp + (rb + r32) * DP + h * H);
@@ -478,8 +559,9 @@ __global__ __launch_bounds__(256) void tile_f32_wide(const float* __restrict__ X
     }
     const float tb = beta[rb + r32];
     c = __builtin_amdgcn_mfma_f32_32x32x2f32(h == 0 ? 1.0f : tb, baug, c, 0, 0, 0);
-    acc += (double)tile_epilogue<MODE>(c, rb, col_base, r32, h, qi, ex);
+    acc += (double)tile_epilogue<MODE>(c, rb, col_base, r32, h, qi, ex, nullptr, false, &nr, t);
   }
+  if constexpr (MODE == kModeExponential) acc += near_finish(ex, nr, qi, h, row0, tid);
   const double other = __shfl_down(acc, 32);
   if (h == 0) wsum[wave][r32] = acc + other;
   __syncthreads();
