@@ -35,6 +35,10 @@
 //                           - Sec. "The MS Algorithm", eq. (sampling_prob) and
 //                             the degree deg_F(i) = sum_j K(||x_i - x_j||),
 //                             with exact or CKNS kernel sums.
+//   orc_simgraph_tree       - the same section's construction with a KDE
+//                             algorithm as a black box: a neighbour is drawn
+//                             by descending a binary tree over the data with
+//                             random-sampling kernel-sum estimates per node.
 //
 // Where the paper leaves a detail open, the reading taken is stated at the
 // function (level boundaries half-open, log base 2, reweighting by the
@@ -860,6 +864,150 @@ void orc_kde_random_sample(const float* X, int64_t n, const float* Q, int64_t m,
 
 int64_t orc_rs_sample_size(double eps, double mu, int64_t m, double delta) {
   return (int64_t)std::ceil(3.0 * std::log(2.0 * (double)m / delta) / (eps * eps * mu));
+}
+
+// ---------------------------------------------------------------------------
+// Edge sampling through a KDE tree (Sec. "The MS Algorithm": each edge (i, j)
+// is sampled with probability close to eq. (sampling_prob), the kernel sums
+// coming from a KDE algorithm used as a black box).  The black box here is
+// the random-sampling estimator of Sec. "Kernel Density Estimation".
+//
+// Tree: leaves are blocks of 32 consecutive rows, nb = ceil(n/32) of them;
+// h = ceil(log2 nb); node (l, k), l = 0..h, holds rows
+// [k 32 2^(h-l), (k+1) 32 2^(h-l)) clipped to [0, n).
+// est(i, node, stream): with P rows in the node, if P <= t the exact sum of
+// k_ij over its rows j != i (ascending j); otherwise (P/t) sum_c k_{i,j_c}
+// [j_c != i] over c = 0..t-1 ascending, j_c = lo + floor(U_c P), U_c the c-th
+// 53-bit uniform of the stream.  Both are unbiased for sum_{j in node, j != i}.
+// Draw (i, r): from the root, at level l with children A, B (B possibly
+// empty): eA = est(i, A, (i, r, l, 0)), eB = est(i, B, (i, r, l, 1)),
+// u = U(i, r, l); go to A iff u (eA + eB) < eA; if eA + eB = 0, to the child
+// with more rows other than i (A on a tie).  At the leaf (level h): values
+// k_ij of its rows (0 for j = i) and their running sum c_j in row order,
+// total T, target u T with u = U(i, r, h): j = the first row with c_j >
+// target (the last positive one if rounding leaves none); if T = 0 the
+// floor(u m)-th of the leaf's m rows other than i.
+// Degrees: rest_i = est(i, root, degree stream of i) with t_deg samples
+// (exact when n <= t_deg); deg_out[i] = 1 + rest_i; a draw (i, j) gets the
+// weight 1/(s (1/rest_i + 1/rest_j)) (0 when an estimate is 0).
+// margin_out: the smallest relative distance of a decision's target to its
+// boundary along the draw's path (|u (eA+eB) - eA| / (eA+eB) per level, the
+// leaf's as in orc_simgraph_exact); 1 where no decision was random.
+// ---------------------------------------------------------------------------
+
+}  // extern "C"
+
+namespace {
+const uint64_t kTagTree = 0x54524545ULL;     // "TREE": node-estimate samples
+const uint64_t kTagTreeU = 0x5452554EULL;    // "TRUN": descent uniforms
+const uint64_t kTagTreeDeg = 0x54444547ULL;  // "TDEG": degree samples
+
+double tree_u53(uint64_t bits) { return (double)(bits >> 11) * 0x1.0p-53; }
+
+int64_t tree_pick(uint64_t bits, int64_t P) {
+  return (int64_t)(((unsigned __int128)(bits >> 11) * (uint64_t)P) >> 53);
+}
+
+double gauss_k(const float* X, int32_t d, double a, int64_t i, int64_t j) {
+  return std::exp(-a * sqdist_direct(X + (size_t)i * d, X + (size_t)j * d, d));
+}
+
+// est(i, [lo, hi)) with t samples from stream (tag, i, b).
+double tree_estimate(const float* X, int32_t d, double a, int64_t i, int64_t lo, int64_t hi, int64_t t,
+                     uint64_t seed, uint64_t tag, uint64_t b) {
+  const int64_t P = hi - lo;
+  if (P <= 0) return 0.0;
+  double s = 0.0;
+  if (P <= t) {
+    for (int64_t j = lo; j < hi; ++j)
+      if (j != i) s = s + gauss_k(X, d, a, i, j);
+    return s;
+  }
+  for (int64_t c = 0; c < t; ++c) {
+    const int64_t j = lo + tree_pick(counter_bits(seed, tag, (uint64_t)i, b, (uint64_t)c), P);
+    if (j != i) s = s + gauss_k(X, d, a, i, j);
+  }
+  return s * ((double)P / (double)t);
+}
+}  // namespace
+
+extern "C" {
+
+void orc_simgraph_tree(const float* X, int64_t n, int32_t d, double a, int32_t s, int32_t t, int64_t t_deg,
+                       uint64_t seed, int64_t* src, int64_t* dst, double* w, double* deg_out, double* margin_out,
+                       int32_t nthreads) {
+  if (nthreads <= 0) nthreads = omp_get_max_threads();
+  const int64_t nb = (n + 31) / 32;
+  int h = 0;
+  while (((int64_t)1 << h) < nb) ++h;
+  std::vector<double> rest((size_t)n);
+#pragma omp parallel for schedule(static) num_threads(nthreads)
+  for (int64_t i = 0; i < n; ++i) rest[i] = tree_estimate(X, d, a, i, 0, n, t_deg, seed, kTagTreeDeg, 0);
+#pragma omp parallel for schedule(dynamic, 16) num_threads(nthreads)
+  for (int64_t i = 0; i < n; ++i) {
+    for (int32_t r = 0; r < s; ++r) {
+      int64_t k = 0;
+      double margin = 1.0;
+      for (int l = 0; l < h; ++l) {
+        const int64_t span = (int64_t)32 << (h - l - 1);  // rows per child
+        const int64_t aLo = std::min(n, 2 * k * span), aHi = std::min(n, (2 * k + 1) * span);
+        const int64_t bLo = aHi, bHi = std::min(n, (2 * k + 2) * span);
+        const uint64_t b0 = ((uint64_t)r << 16) | ((uint64_t)l << 1);
+        const double eA = tree_estimate(X, d, a, i, aLo, aHi, t, seed, kTagTree, b0);
+        const double eB = tree_estimate(X, d, a, i, bLo, bHi, t, seed, kTagTree, b0 | 1);
+        const double u = tree_u53(counter_bits(seed, kTagTreeU, (uint64_t)i, (uint64_t)r, (uint64_t)l));
+        const double tot = eA + eB;
+        bool left;
+        if (tot > 0.0) {
+          const double x = u * tot;
+          left = x < eA;
+          margin = std::min(margin, std::fabs(x - eA) / tot);
+        } else {
+          const int64_t mA = (aHi - aLo) - (i >= aLo && i < aHi ? 1 : 0);
+          const int64_t mB = (bHi - bLo) - (i >= bLo && i < bHi ? 1 : 0);
+          left = mA >= mB;
+        }
+        k = left ? 2 * k : 2 * k + 1;
+      }
+      const int64_t lo = std::min(n, k * 32), hi = std::min(n, (k + 1) * 32);
+      const double u = tree_u53(counter_bits(seed, kTagTreeU, (uint64_t)i, (uint64_t)r, (uint64_t)h));
+      double T = 0.0;
+      for (int64_t j = lo; j < hi; ++j)
+        if (j != i) T = T + gauss_k(X, d, a, i, j);
+      int64_t pick = -1;
+      if (T > 0.0) {
+        const double target = u * T;
+        double c = 0.0, before = 0.0;
+        int64_t last = -1;
+        for (int64_t j = lo; j < hi; ++j) {
+          const double v = j != i ? gauss_k(X, d, a, i, j) : 0.0;
+          if (v > 0.0) last = j;
+          before = c;
+          c = c + v;
+          if (c > target) {
+            pick = j;
+            margin = std::min(margin, std::min(target - before, c - target) / T);
+            break;
+          }
+        }
+        if (pick < 0) { pick = last; margin = 0.0; }
+      } else {
+        const int64_t m = (hi - lo) - (i >= lo && i < hi ? 1 : 0);
+        int64_t idx = (int64_t)(u * (double)m);
+        for (int64_t j = lo; j < hi; ++j) {
+          if (j == i) continue;
+          if (idx-- == 0) { pick = j; break; }
+        }
+      }
+      const size_t e = (size_t)i * s + r;
+      src[e] = i;
+      dst[e] = pick;
+      w[e] = (rest[i] > 0.0 && rest[pick] > 0.0) ? 1.0 / ((double)s * (1.0 / rest[i] + 1.0 / rest[pick])) : 0.0;
+      if (margin_out) margin_out[e] = margin;
+    }
+  }
+  if (deg_out)
+    for (int64_t i = 0; i < n; ++i) deg_out[i] = 1.0 + rest[i];
 }
 
 }  // extern "C"
