@@ -338,6 +338,42 @@ stag_status stag_simgraph_sample(const float* X, int64_t n, int32_t d, double a,
                                  uint64_t seed, int64_t* src_out, int64_t* dst_out, double* w_out, double* deg_out,
                                  hipStream_t stream);
 
+/* Edge sampling through a KDE tree (Sec. "The MS Algorithm": the sampling
+ * probabilities of eq. sampling_prob reached with a KDE algorithm as a black
+ * box; here the random-sampling estimator of Sec. "Kernel Density
+ * Estimation" per tree node).  Gaussian kernel exp(-a r^2).
+ * Tree over the rows in index order: leaves are blocks of 32 rows, h =
+ * ceil(log2 ceil(n/32)), node (l, k) holds rows [k 32 2^(h-l),
+ * (k+1) 32 2^(h-l)) clipped to [0, n).  A node estimate of sum_{j in node,
+ * j != i} k_ij is exact for a node of P <= est_samples rows, else (P/t) times
+ * the sum over t = est_samples rows j_c = lo + floor(U_c P) (own row 0).
+ * Draw r of node i descends from the root: with estimates eA, eB of the two
+ * children and u = U(i, r, l) it goes to A iff u (eA + eB) < eA (if both are
+ * 0, to the child with more rows other than i, A on a tie); in the leaf it
+ * inverts the cumulative exact values of the leaf's rows (j != i) on
+ * u = U(i, r, h), or takes the floor(u m)-th of its m rows other than i when
+ * they are all 0.  Degrees: rest_i = the root estimate with degree_samples
+ * samples (exact when n <= degree_samples), deg_out[i] = 1 + rest_i; draw
+ * (i, j) is output at index i*s + r with weight 1/(s (1/rest_i + 1/rest_j))
+ * (0 if one of them is 0).  Every dst is in [0, n) and differs from src.
+ * Randomness: SplitMix64 counter streams, output c of stream (seed, tag,
+ * a, b) = mix(S + (c+1) 0x9E3779B97F4A7C15), S = mix(mix(mix(seed ^ tag) ^
+ * a) ^ b): node samples tag 0x54524545, a = i, b = r << 16 | l << 1 | side
+ * (A = 0); descent uniforms tag 0x5452554E, a = i, b = r, c = l; degree
+ * samples tag 0x54444547, a = i, b = 0.  U = (output >> 11) 2^-53 and an
+ * index floor(U P) is taken exactly in integers.
+ * Work: n s draws of h levels x 2 est_samples kernel values + 32 in the leaf,
+ * each an fp64 direct-difference distance (no n^2 pass); n degree_samples
+ * values for the degrees.  Results are deterministic for a given seed.
+ * Arguments: X [n][d] f32 device; 2 <= n < 2^31; 1 <= d <= 1024; a > 0;
+ * samples_per_node 0 (= ceil(log2 n)) to 64; est_samples 1 to 32;
+ * degree_samples >= 1.  Outputs (device, caller-owned): src/dst int64
+ * [n*s], w f64 [n*s], deg_out f64 [n] or NULL.  Invalid arguments:
+ * STAG_E_INVAL before any launch. */
+stag_status stag_simgraph_sample_tree(const float* X, int64_t n, int32_t d, double a, int32_t samples_per_node,
+                                      int32_t est_samples, int64_t degree_samples, uint64_t seed, int64_t* src_out,
+                                      int64_t* dst_out, double* w_out, double* deg_out, hipStream_t stream);
+
 /* ------------------------------------------------------------------------
  * Spectral clustering (Sec. "Fast Spectral Clustering": a similarity graph,
  * the bottom k eigenvectors of its Laplacian as an embedding in R^k, then

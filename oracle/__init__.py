@@ -84,7 +84,7 @@ def _load():
     lib.orc_draw_uniform.argtypes = [C.c_uint64, C.c_int64, C.c_int32]
     lib.orc_simgraph_exact.restype = None
     lib.orc_simgraph_tree.argtypes = [f32p, C.c_int64, C.c_int32, C.c_double, C.c_int32, C.c_int32, C.c_int64,
-                                      C.c_uint64, i64p, i64p, f64p, f64p, f64p, C.c_int32]
+                                      C.c_uint64, C.c_int64, C.c_int64, i64p, i64p, f64p, f64p, f64p, C.c_int32]
     lib.orc_simgraph_tree.restype = None
     lib.orc_simgraph_exact.argtypes = [f32p, C.c_int64, C.c_int32, C.c_double, C.c_int32, C.c_uint64, i64p, i64p, f64p,
                                        f64p, f64p, C.c_int32]
@@ -317,19 +317,21 @@ def simgraph_exact(X, a, s, seed, nthreads: int = 0, return_margin: bool = False
     return (src, dst, w, deg, mg) if return_margin else (src, dst, w, deg)
 
 
-def simgraph_tree(X, a, s, t, t_deg, seed, nthreads: int = 0):
+def simgraph_tree(X, a, s, t, t_deg, seed, nthreads: int = 0, rows=None):
     """(src, dst, w, deg, margin) of the KDE-tree edge sampler: descent by
-    random-sampling node estimates with t samples, degrees with t_deg."""
+    random-sampling node estimates with t samples, degrees with t_deg.
+    rows = (lo, hi) limits the draws to those rows (degrees cover all)."""
     X = _f32(X)
     n, d = X.shape
-    e = n * s
+    lo, hi = (0, n) if rows is None else (int(rows[0]), int(rows[1]))
+    e = (hi - lo) * s
     src = np.empty(e, dtype=np.int64)
     dst = np.empty(e, dtype=np.int64)
     w = np.empty(e, dtype=np.float64)
     deg = np.empty(n, dtype=np.float64)
     mg = np.empty(e, dtype=np.float64)
     _load().orc_simgraph_tree(_p(X, C.c_float), n, d, float(a), int(s), int(t), int(t_deg),
-                              seed & 0xFFFFFFFFFFFFFFFF, _p(src, C.c_int64), _p(dst, C.c_int64), _p(w, C.c_double),
+                              seed & 0xFFFFFFFFFFFFFFFF, lo, hi, _p(src, C.c_int64), _p(dst, C.c_int64), _p(w, C.c_double),
                               _p(deg, C.c_double), _p(mg, C.c_double), int(nthreads))
     return src, dst, w, deg, mg
 

@@ -933,9 +933,11 @@ double tree_estimate(const float* X, int32_t d, double a, int64_t i, int64_t lo,
 
 extern "C" {
 
+// Draws are made for the rows i in [i_lo, i_hi) only (all rows: 0, n), output
+// at (i - i_lo) s + r; the degrees always cover every row.
 void orc_simgraph_tree(const float* X, int64_t n, int32_t d, double a, int32_t s, int32_t t, int64_t t_deg,
-                       uint64_t seed, int64_t* src, int64_t* dst, double* w, double* deg_out, double* margin_out,
-                       int32_t nthreads) {
+                       uint64_t seed, int64_t i_lo, int64_t i_hi, int64_t* src, int64_t* dst, double* w,
+                       double* deg_out, double* margin_out, int32_t nthreads) {
   if (nthreads <= 0) nthreads = omp_get_max_threads();
   const int64_t nb = (n + 31) / 32;
   int h = 0;
@@ -944,7 +946,7 @@ void orc_simgraph_tree(const float* X, int64_t n, int32_t d, double a, int32_t s
 #pragma omp parallel for schedule(static) num_threads(nthreads)
   for (int64_t i = 0; i < n; ++i) rest[i] = tree_estimate(X, d, a, i, 0, n, t_deg, seed, kTagTreeDeg, 0);
 #pragma omp parallel for schedule(dynamic, 16) num_threads(nthreads)
-  for (int64_t i = 0; i < n; ++i) {
+  for (int64_t i = i_lo; i < i_hi; ++i) {
     for (int32_t r = 0; r < s; ++r) {
       int64_t k = 0;
       double margin = 1.0;
@@ -999,7 +1001,7 @@ void orc_simgraph_tree(const float* X, int64_t n, int32_t d, double a, int32_t s
           if (idx-- == 0) { pick = j; break; }
         }
       }
-      const size_t e = (size_t)i * s + r;
+      const size_t e = (size_t)(i - i_lo) * s + r;
       src[e] = i;
       dst[e] = pick;
       w[e] = (rest[i] > 0.0 && rest[pick] > 0.0) ? 1.0 / ((double)s * (1.0 / rest[i] + 1.0 / rest[pick])) : 0.0;

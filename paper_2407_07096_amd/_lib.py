@@ -101,6 +101,8 @@ def load():
     lib.stag_lsh_index_segment.argtypes = [vp, i32, i32, C.POINTER(C.c_int64), vp, vp, vp]
     lib.stag_lsh_index_destroy.restype = None
     lib.stag_lsh_index_destroy.argtypes = [vp]
+    lib.stag_simgraph_sample_tree.restype = C.c_int
+    lib.stag_simgraph_sample_tree.argtypes = [vp, i64, i32, f64, i32, i32, i64, C.c_uint64, vp, vp, vp, vp, vp]
     lib.stag_simgraph_sample.restype = C.c_int
     lib.stag_simgraph_sample.argtypes = [vp, i64, i32, f64, i32, i32, i32, f64, pp, C.c_uint64, vp, vp, vp, vp, vp]
     lib.stag_server_create.restype = C.c_int
@@ -418,6 +420,25 @@ def simgraph_sample(X, a: float, samples_per_node: int = 0, mode: str = "exact",
                                      float(eps), C.byref(prm), int(seed) & 0xFFFFFFFFFFFFFFFF, _ptr(src), _ptr(dst),
                                      _ptr(w), _ptr(deg), _stream_handle(X.device))
     check(st, "stag_simgraph_sample")
+    return src, dst, w, deg
+
+
+def simgraph_sample_tree(X, a: float, samples_per_node: int = 0, est_samples: int = 32, degree_samples: int = 1024,
+                         seed: int = 0):
+    """Edge sample through the KDE tree with random-sampling node estimates:
+    (src, dst, w, deg) tensors."""
+    torch = _torch()
+    _need(X, torch.float32, 2, "X")
+    n, d = X.shape
+    s = max(1, int(n - 1).bit_length()) if samples_per_node <= 0 else int(samples_per_node)
+    src = torch.empty(n * s, dtype=torch.int64, device=X.device)
+    dst = torch.empty(n * s, dtype=torch.int64, device=X.device)
+    w = torch.empty(n * s, dtype=torch.float64, device=X.device)
+    deg = torch.empty(n, dtype=torch.float64, device=X.device)
+    st = load().stag_simgraph_sample_tree(_ptr(X), n, d, float(a), s, int(est_samples), int(degree_samples),
+                                          int(seed) & 0xFFFFFFFFFFFFFFFF, _ptr(src), _ptr(dst), _ptr(w), _ptr(deg),
+                                          _stream_handle(X.device))
+    check(st, "stag_simgraph_sample_tree")
     return src, dst, w, deg
 
 
