@@ -209,6 +209,60 @@ def spectral_run(stag, torch, lib, buf, graph, n: int, k: int, labels_true, seed
             "kernels_ms": {kk: v[1] for kk, v in tm.items()}}
 
 
+def tree_run(stag, torch, lib, buf, X, Xd, a: float, graph, labels, k: int, s: int = 17, t: int = 32,
+             t_deg: int = 1024, seed: int = 4004):
+    """KDE-tree edge sampler (random-sampling node estimates, t per estimate,
+    t_deg for the degrees) over the step's data: time and draws/s with its
+    kernels, fp64 rate of the draw kernel against the vector fp64 peak, and
+    against the step's exact sampler: the share of sampled weight inside the
+    mixture components, the degree estimates' error, and the purity of
+    spectral clustering on each graph; draws of 32 rows against the oracle."""
+    import numpy as np
+
+    import oracle
+    n, d = X.shape
+    stag.simgraph_sample_tree(Xd, a, s, t, t_deg, seed)  # warm-up
+    torch.cuda.synchronize()
+    lib.stag_timing_report(buf, len(buf))
+    lib.stag_timing_enable(1)
+    t0 = time.perf_counter()
+    tg = stag.simgraph_sample_tree(Xd, a, s, t, t_deg, seed)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    lib.stag_timing_enable(0)
+    lib.stag_timing_report(buf, len(buf))
+    tm = parse_timing(buf.value.decode())
+    h = max(0, int(np.ceil(np.log2(-(-n // 32)))))
+    values = n * s * (h * 2 * t + 32)  # kernel values per launch of the draw kernel (upper count)
+    draw_ms = tm["tree_draws"][1]
+    flops64 = values * 3.0 * d  # difference, product, sum per coordinate
+
+    def stats(g):
+        src, dst, w, deg = (x.cpu().numpy() for x in g)
+        ok = dst >= 0
+        inside = float(w[ok][labels[src[ok]] == labels[dst[ok]]].sum() / w[ok].sum())
+        lam, U, _ = stag.spectral_embedding(n, g[0], g[1], g[2], k, seed=seed)
+        lab, _, _, _ = stag.kmeans(U, k, seed=seed)
+        labh = lab.cpu().numpy()
+        purity = sum(np.bincount(labh[labels == c]).max() for c in range(k) if np.any(labels == c)) / n
+        return inside, float(purity), deg
+
+    in_tree, pur_tree, deg_tree = stats(tg)
+    in_exact, pur_exact, deg_exact = stats(graph)
+    drel = np.abs(deg_tree - deg_exact) / deg_exact
+    lo, hi = n // 2, n // 2 + 32
+    ref = oracle.simgraph_tree(X, a, s, t, t_deg, seed, rows=(lo, hi))
+    dst_h = tg[1].cpu().numpy()[lo * s:hi * s]
+    return {"workload": f"KDE-tree edge sampling n={n}, d={d}, a={a}, s={s}, t={t}, t_deg={t_deg}",
+            "wall_ms": (t1 - t0) * 1e3, "draws_per_s": n * s / (t1 - t0),
+            "kernels_ms": {kk: v[1] for kk, v in tm.items()},
+            "draw_kernel_fp64_tflops": flops64 / (draw_ms / 1e3) / 1e12, "fp64_vector_peak_tflops": 78.6,
+            "weight_share_inside_components": {"tree": in_tree, "exact": in_exact},
+            "spectral_purity": {"tree": pur_tree, "exact": pur_exact},
+            "degree_rel_err_vs_exact": {"median": float(np.median(drel)), "max": float(drel.max())},
+            "oracle_draws_differing_of_32_rows": int(np.sum(dst_h != ref[1]))}
+
+
 def rs_run(stag, torch, lib, buf, X, Q, Xd, Qd, a: float, form: str, n_check: int = 32):
     """Random-sampling KDE (the paper's sampling baseline) over the step's
     data and queries at s = n/100 and n/10 samples: time, throughput of
@@ -587,6 +641,7 @@ def main():
     result["kernels"] = kernels_run(stag, torch, dev, lib, buf, X, Q, Xd, Qd, args.form)
     result["random_sampling"] = rs_run(stag, torch, lib, buf, X, Q, Xd, Qd, a, args.form)
     result["spectral"] = spectral_run(stag, torch, lib, buf, graph, n, info["k"], info["labels"])
+    result["kde_tree_sampler"] = tree_run(stag, torch, lib, buf, X, Xd, a, graph, info["labels"], info["k"])
     del graph
     if not args.no_precision_config:
         result["precision_config"] = precision_config_run(stag, torch, dev, lib, buf)
