@@ -33,7 +33,10 @@
 // gathered row.  Results are deterministic; against a sequential fp64 sum
 // they differ by rounding only, which moves a decision only when its target
 // lies within that rounding of a boundary.
+#include <utility>
+
 #include "runtime.h"
+#include "sort.h"
 
 namespace stag {
 namespace {
@@ -126,58 +129,105 @@ __global__ __launch_bounds__(256) void tree_degrees(const float* __restrict__ X,
   }
 }
 
-// One wave per draw e = i s + r.
-__global__ __launch_bounds__(256) void tree_draws(const float* __restrict__ X, int64_t n, int d, double a, int s,
-                                                  int t, int h, uint64_t seed, bool vec4,
-                                                  const double* __restrict__ rest,
-                                                  int64_t* __restrict__ src, int64_t* __restrict__ dst,
-                                                  double* __restrict__ w) {
+// Draws run level by level: one launch per tree level, then the draws are
+// sorted (stable radix sort) by the node they reached, so that the waves of
+// a launch that work in the same node are neighbours; with the XCD-aware
+// block order below each XCD takes a contiguous range of nodes, and from the
+// level where a node's rows fit an XCD's L2 the gathers hit in L2.  The
+// order changes only where a draw runs, not what it computes.
+//
+// Workgroups go round-robin to the 8 XCDs: block b works on logical block
+// (b % 8) per + b / 8 (the grid is 8 per blocks), i.e. slots
+// [4 L, 4 L + 4) of the sorted order.
+__device__ inline int64_t tree_slot(int per) {
+  const int b = blockIdx.x;
+  const int64_t L = (int64_t)(b % 8) * per + b / 8;
+  return L * kTreeWaves + (threadIdx.x >> 6);
+}
+
+// Stage x_i of the draw in slot `slot` (if any) into this wave's LDS row.
+__device__ inline void stage_row(float* xi, const float* __restrict__ X, int64_t i, int d, bool active) {
+  const int lane = threadIdx.x & 63;
+  if (active)
+    for (int c = lane; c < d; c += 64) xi[c] = X[i * d + c];
+}
+
+// perm[w] = w, node[w] = 0.
+__global__ void tree_init(uint32_t* __restrict__ perm, uint32_t* __restrict__ node, int64_t total) {
+  const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (w < total) {
+    perm[w] = (uint32_t)w;
+    node[w] = 0;
+  }
+}
+
+// One level l < h for the draw in each slot: node_in[slot] -> node_out[slot].
+__global__ __launch_bounds__(256) void tree_level(const float* __restrict__ X, int64_t n, int d, double a, int s,
+                                                  int t, int h, int l, uint64_t seed, bool vec4,
+                                                  const uint32_t* __restrict__ perm,
+                                                  const uint32_t* __restrict__ node_in, uint32_t* __restrict__ node_out,
+                                                  int64_t total, int per) {
   extern __shared__ float txi[];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int64_t e = (int64_t)blockIdx.x * kTreeWaves + wave;
-  const int64_t total = n * s;
-  const int64_t i = e < total ? e / s : 0;
-  const int64_t r = e < total ? e % s : 0;
+  const int64_t slot = tree_slot(per);
+  const bool active = slot < total;
+  const int64_t e = active ? (int64_t)perm[slot] : 0;
+  const int64_t i = e / s, r = e % s;
   float* xi = txi + wave * d;
-  if (e < total)
-    for (int c = lane; c < d; c += 64) xi[c] = X[i * d + c];
+  stage_row(xi, X, i, d, active);
   __syncthreads();
-  if (e >= total) return;
-
+  if (!active) return;
   const int side = lane >> 5, c = lane & 31;
-  const uint64_t ust = tstream(seed, kTagTreeUniform, (uint64_t)i, (uint64_t)r);
-  int64_t k = 0;
-  for (int l = 0; l < h; ++l) {
-    const int64_t span = (int64_t)kTreeLeaf << (h - l - 1);
-    const int64_t lo = min(n, (2 * k + side) * span), hi = min(n, (2 * k + side + 1) * span);
-    const int64_t P = hi - lo;
-    double v = 0.0;
-    if (P > 0 && P <= t) {
-      const int64_t j = lo + c;
-      if (c < P && j != i) v = tkernel(xi, X + j * d, d, a, vec4);
-    } else if (P > t && c < t) {
-      const uint64_t st =
-          tstream(seed, kTagTreeSamples, (uint64_t)i, ((uint64_t)r << 16) | ((uint64_t)l << 1) | (uint64_t)side);
-      const int64_t j = lo + tpick(tout(st, (uint64_t)c), P);
-      if (j != i) v = tkernel(xi, X + j * d, d, a, vec4);
-    }
-    double est = half_sum(v);
-    if (P > t) est = est * ((double)P / (double)t);
-    const double eA = __shfl(est, 0), eB = __shfl(est, 32);
-    const double u = tuniform(tout(ust, (uint64_t)l));
-    const double tot = eA + eB;
-    bool left;
-    if (tot > 0.0) {
-      left = u * tot < eA;
-    } else {
-      const int64_t aLo = min(n, 2 * k * span), aHi = min(n, (2 * k + 1) * span), bHi = min(n, (2 * k + 2) * span);
-      const int64_t mA = (aHi - aLo) - ((i >= aLo && i < aHi) ? 1 : 0);
-      const int64_t mB = (bHi - aHi) - ((i >= aHi && i < bHi) ? 1 : 0);
-      left = mA >= mB;
-    }
-    k = left ? 2 * k : 2 * k + 1;
+  const int64_t k = node_in[slot];
+  const int64_t span = (int64_t)kTreeLeaf << (h - l - 1);
+  const int64_t lo = min(n, (2 * k + side) * span), hi = min(n, (2 * k + side + 1) * span);
+  const int64_t P = hi - lo;
+  double v = 0.0;
+  if (P > 0 && P <= t) {
+    const int64_t j = lo + c;
+    if (c < P && j != i) v = tkernel(xi, X + j * d, d, a, vec4);
+  } else if (P > t && c < t) {
+    const uint64_t st =
+        tstream(seed, kTagTreeSamples, (uint64_t)i, ((uint64_t)r << 16) | ((uint64_t)l << 1) | (uint64_t)side);
+    const int64_t j = lo + tpick(tout(st, (uint64_t)c), P);
+    if (j != i) v = tkernel(xi, X + j * d, d, a, vec4);
   }
-  // leaf: inverse CDF over its rows in row order
+  double est = half_sum(v);
+  if (P > t) est = est * ((double)P / (double)t);
+  const double eA = __shfl(est, 0), eB = __shfl(est, 32);
+  const double u = tuniform(tout(tstream(seed, kTagTreeUniform, (uint64_t)i, (uint64_t)r), (uint64_t)l));
+  const double tot = eA + eB;
+  bool left;
+  if (tot > 0.0) {
+    left = u * tot < eA;
+  } else {
+    const int64_t aLo = min(n, 2 * k * span), aHi = min(n, (2 * k + 1) * span), bHi = min(n, (2 * k + 2) * span);
+    const int64_t mA = (aHi - aLo) - ((i >= aLo && i < aHi) ? 1 : 0);
+    const int64_t mB = (bHi - aHi) - ((i >= aHi && i < bHi) ? 1 : 0);
+    left = mA >= mB;
+  }
+  if (lane == 0) node_out[slot] = (uint32_t)(left ? 2 * k : 2 * k + 1);
+}
+
+// The leaf (level h) of the draw in each slot: inverse CDF over its rows in
+// row order; outputs at the draw's own index e = i s + r.
+__global__ __launch_bounds__(256) void tree_leaf(const float* __restrict__ X, int64_t n, int d, double a, int s,
+                                                 int h, uint64_t seed, bool vec4, const uint32_t* __restrict__ perm,
+                                                 const uint32_t* __restrict__ node, const double* __restrict__ rest,
+                                                 int64_t* __restrict__ src, int64_t* __restrict__ dst,
+                                                 double* __restrict__ w, int64_t total, int per) {
+  extern __shared__ float txi[];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t slot = tree_slot(per);
+  const bool active = slot < total;
+  const int64_t e = active ? (int64_t)perm[slot] : 0;
+  const int64_t i = e / s, r = e % s;
+  float* xi = txi + wave * d;
+  stage_row(xi, X, i, d, active);
+  __syncthreads();
+  if (!active) return;
+  const int side = lane >> 5, c = lane & 31;
+  const int64_t k = node[slot];
   const int64_t lo = min(n, k * kTreeLeaf), hi = min(n, (k + 1) * kTreeLeaf);
   const int64_t j = lo + c;
   double v = 0.0;
@@ -189,7 +239,7 @@ __global__ __launch_bounds__(256) void tree_draws(const float* __restrict__ X, i
     if (c >= o) incl += y;
   }
   const double T = __shfl(incl, 31);
-  const double u = tuniform(tout(ust, (uint64_t)h));
+  const double u = tuniform(tout(tstream(seed, kTagTreeUniform, (uint64_t)i, (uint64_t)r), (uint64_t)h));
   int64_t pick;
   if (T > 0.0) {
     const double target = u * T;
@@ -238,7 +288,7 @@ extern "C" stag_status stag_simgraph_sample_tree(const float* X, int64_t n, int3
   if (s == 0)
     while (((int64_t)1 << s) < n) ++s;  // ceil(log2 n)
   const int64_t draws = n * s;
-  if (draws / kTreeWaves >= 2147483647LL) return fail(STAG_E_INVAL, "%s: n * samples_per_node too large", fn);
+  if (draws >= 2147483647LL) return fail(STAG_E_INVAL, "%s: n * samples_per_node must be < 2^31", fn);
   const int64_t nb = (n + kTreeLeaf - 1) / kTreeLeaf;
   int h = 0;
   while (((int64_t)1 << h) < nb) ++h;
@@ -254,11 +304,32 @@ extern "C" stag_status stag_simgraph_sample_tree(const float* X, int64_t n, int3
                        a, degree_samples, seed, vec4, rest, deg_out);
     STAG_TRY(check_launch("tree_degrees"));
   }
+  // draws level by level, sorted by node between levels
+  const int per = (int)ceil_div(ceil_div(draws, kTreeWaves), 8);
+  const dim3 grid((unsigned)(8 * per));
+  uint32_t *perm = nullptr, *perm2 = nullptr, *node = nullptr, *node2 = nullptr;
+  STAG_TRY(ws.alloc(&perm, (size_t)draws));
+  STAG_TRY(ws.alloc(&perm2, (size_t)draws));
+  STAG_TRY(ws.alloc(&node, (size_t)draws));
+  STAG_TRY(ws.alloc(&node2, (size_t)draws));
+  hipLaunchKernelGGL(tree_init, dim3((unsigned)ceil_div(draws, 256)), dim3(256), 0, stream, perm, node, draws);
+  STAG_TRY(check_launch("tree_init"));
+  for (int l = 0; l < h; ++l) {
+    {
+      ScopedTimer tm("tree_draws", stream);
+      hipLaunchKernelGGL(tree_level, grid, dim3(256), lds, stream, X, n, (int)d, a, s, (int)est_samples, h, l, seed,
+                         vec4, perm, node, node2, draws, per);
+      STAG_TRY(check_launch("tree_level"));
+    }
+    ScopedTimer tm("tree_sort", stream);
+    STAG_TRY(radix_sort_pairs_u32(node2, perm, node, perm2, draws, l + 1, ws, stream));
+    std::swap(perm, perm2);
+  }
   {
     ScopedTimer tm("tree_draws", stream);
-    hipLaunchKernelGGL(tree_draws, dim3((unsigned)ceil_div(draws, kTreeWaves)), dim3(256), lds, stream, X, n,
-                       (int)d, a, s, (int)est_samples, h, seed, vec4, rest, src_out, dst_out, w_out);
-    STAG_TRY(check_launch("tree_draws"));
+    hipLaunchKernelGGL(tree_leaf, grid, dim3(256), lds, stream, X, n, (int)d, a, s, h, seed, vec4, perm, node, rest,
+                       src_out, dst_out, w_out, draws, per);
+    STAG_TRY(check_launch("tree_leaf"));
   }
   return STAG_OK;
 }
