@@ -101,6 +101,18 @@ def test_invalid_arguments_rejected_before_launch():
     st = lib.stag_e2lsh_table_neighbours(fake, fake, 0, fake, fake, null)
     assert st == _lib.STAG_E_INVAL
     lib.stag_e2lsh_table_destroy(null)
+    # KDE-tree sampler: (n, d, a, s, est_samples, degree_samples)
+    for args, msg in [((1, 4, 1.0, 0, 8, 8), "n"), ((10, 0, 1.0, 0, 8, 8), "d >= 1"), ((10, 4, 0.0, 0, 8, 8), "a must"),
+                      ((10, 4, 1.0, 65, 8, 8), "samples_per_node"), ((10, 4, 1.0, 0, 0, 8), "est_samples"),
+                      ((10, 4, 1.0, 0, 33, 8), "est_samples"), ((10, 4, 1.0, 0, 8, 0), "degree_samples"),
+                      ((2 ** 26, 4, 1.0, 64, 8, 8), "2^31")]:
+        n, d, a, s_, t, td = args
+        st = lib.stag_simgraph_sample_tree(fake, n, d, a, s_, t, td, 1, fake, fake, fake, null, null)
+        assert st == _lib.STAG_E_INVAL and msg in stag.last_error(), (args, stag.last_error())
+    st = lib.stag_simgraph_sample_tree(fake, 10, 1025, 1.0, 0, 8, 8, 1, fake, fake, fake, null, null)
+    assert st == _lib.STAG_E_UNSUPPORTED
+    st = lib.stag_simgraph_sample_tree(null, 10, 4, 1.0, 0, 8, 8, 1, fake, fake, fake, null, null)
+    assert st == _lib.STAG_E_INVAL and "NULL" in stag.last_error()
 
 
 @pytest.mark.parametrize("n", [1, 7, 1000, 100_000, 2_000_000])
