@@ -114,3 +114,17 @@ def test_full_size_sampled_rows(stag, orc):
     ref = orc.simgraph_tree(X, 0.01, 17, 32, 1024, 99, rows=(51200, 51400))
     nd = _compare(got, ref, rows=(51200, 51400))
     print(f"[measured] tree full size: {nd} of 3400 sampled draws differ", flush=True)
+
+
+def test_config4_sampled_rows(stag, orc):
+    """n = 70,000, d = 784, sparse non-negative data (entries 0 with
+    probability 0.8, else U[0,1]), a = 1e-3, 17 draws per node, t = 16, 64
+    degree samples: the whole launch, oracle parity on 100 rows."""
+    X = synth.sparse_uniform(70_000, 784, 1004)
+    n = len(X)
+    announce("tree sampler config4 n=70000 d=784 s=17 t=16 t_deg=64")
+    got = _gpu(stag, X, 1e-3, 17, 16, 64, 5)
+    _valid(got[0], got[1], n)
+    ref = orc.simgraph_tree(X, 1e-3, 17, 16, 64, 5, rows=(35000, 35100))
+    nd = _compare(got, ref, rows=(35000, 35100))
+    print(f"[measured] tree config4: {nd} of 1700 sampled draws differ", flush=True)
