@@ -90,6 +90,100 @@ __device__ inline uint64_t table_key(int l, const double* xr, const float* __res
   return hkey;
 }
 
+// E2LSH hashing with one lane per projection (d <= 64, K <= 64), for the
+// CKNS queries (TQ: keys[table * mb + row]) and the E2LSH tables (keys[row *
+// ntab + table], codes[(row * ntab + table) * K + e] when codes is not null).
+// A wave takes TW = floor(64 / K) whole tables, lane t K + e holding
+// projection e of its table t in registers as binary64 (DG values, zero
+// padded); the 4 waves of a block share batches of 64 rows, widened to
+// binary64 in LDS once per batch and read as broadcasts.  Each lane forms <x, g> for four queries at
+// a time as the same left-to-right chain of fused products over the DG
+// coordinates as table_key (so codes and keys are bit-identical), takes the
+// code, and the 4 TW keys of the four queries are folded by one lane each
+// from their table's K codes, gathered in code order with lane shuffles.
+// Without scalar coefficient operands the kernel needs no scalar registers
+// per coefficient (the per-query kernel spills them through vector lanes).
+// code_of without branches (selects), so that the four chains below stay in
+// one basic block: floor((s + b) / 4) saturated to int32, the in-range
+// conversion being the hardware's (exact for these integral values).
+__device__ inline int32_t code_sel(double s, double b) {
+  const double v = floor((s + b) / 4.0);
+  const int32_t c = __double2int_rz(v);
+  return v >= 2147483647.0 ? 2147483647 : (v <= -2147483648.0 ? (int32_t)(-2147483647 - 1) : c);
+}
+
+template <int DG, bool TQ>
+__global__ __launch_bounds__(256) void hash_lanes(const float* __restrict__ Q, int ldq, int64_t q0, int64_t mb, int d,
+                                                  const double* __restrict__ G8, const double* __restrict__ B, int K,
+                                                  int L, int nch, int64_t ntab, int TW, int qbatches,
+                                                  uint64_t* __restrict__ qkeys, int32_t* __restrict__ codes) {
+  __shared__ double xs[64 * DG];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t tab0 = ((int64_t)blockIdx.x * 4 + wave) * TW;
+  const int ti = lane / K, e = lane - ti * K;
+  const int64_t tab = tab0 + ti;
+  const bool act = ti < TW && tab < ntab;
+  double g[DG];
+  {
+    const double* gp = G8 + (act ? tab : 0) * nch * DG * 8 + (e >> 3) * DG * 8 + (e & 7);
+#pragma unroll
+    for (int j = 0; j < DG; ++j) g[j] = gp[j * 8];  // inactive lanes read table 0 and never store
+  }
+  const double bv = act ? B[tab * K + e] : 0.0;
+  const int nfold = 4 * TW;
+  const int64_t qfirst = (int64_t)blockIdx.y * qbatches * 64;
+  for (int qb = 0; qb < qbatches; ++qb) {
+    const int64_t qs = qfirst + (int64_t)qb * 64;
+    if (qs >= mb) break;  // uniform over the block
+    __syncthreads();      // the previous batch's reads are done
+    for (int idx = threadIdx.x; idx < 64 * DG; idx += 256) {
+      const int r = idx / DG, c = idx - r * DG;
+      const int64_t q = qs + r;
+      xs[idx] = (q < mb && c < d) ? (double)Q[(q0 + q) * ldq + c] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll 1
+    for (int r0 = 0; r0 < 64; r0 += 4) {
+      const double* x0 = xs + r0 * DG;
+      double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+#pragma unroll
+      for (int j = 0; j < DG; ++j) {
+        s0 = __builtin_fma(x0[j], g[j], s0);
+        s1 = __builtin_fma(x0[DG + j], g[j], s1);
+        s2 = __builtin_fma(x0[2 * DG + j], g[j], s2);
+        s3 = __builtin_fma(x0[3 * DG + j], g[j], s3);
+      }
+
+      const int32_t c0 = code_sel(s0, bv), c1 = code_sel(s1, bv), c2 = code_sel(s2, bv), c3 = code_sel(s3, bv);
+      if (codes && act) {
+        const int32_t cs[4] = {c0, c1, c2, c3};
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const int64_t q = qs + r0 + k;
+          if (q < mb) codes[((q0 + q) * ntab + tab) * K + e] = cs[k];
+        }
+      }
+      for (int f0 = 0; f0 < nfold; f0 += 64) {  // uniform
+        const int f = f0 + lane;
+        const int fq = f / TW, ft = f - fq * TW;  // query fq of the four, table ft of the wave
+        uint64_t h = mix64(kKeySalt ^ (uint64_t)(uint32_t)((tab0 + ft) % L));
+#pragma unroll 1
+        for (int e2 = 0; e2 < K; ++e2) {
+          const int src = (ft * K + e2) & 63;
+          const int32_t a0 = __shfl(c0, src), a1 = __shfl(c1, src), a2 = __shfl(c2, src), a3 = __shfl(c3, src);
+          const int32_t cc = fq == 0 ? a0 : (fq == 1 ? a1 : (fq == 2 ? a2 : a3));
+          h = mix64(h ^ (uint64_t)(uint32_t)cc);
+        }
+        const int64_t q = qs + r0 + fq, tb = tab0 + ft;
+        if (qkeys && f < nfold && tb < ntab && q < mb) {
+          if constexpr (TQ) qkeys[tb * mb + q] = h;
+          else qkeys[(q0 + q) * ntab + tb] = h;
+        }
+      }
+    }
+  }
+}
+
 // Loads point row into registers as binary64 (zero padded to DREG).
 template <int DREG>
 __device__ inline void load_point(double* xr, const float* __restrict__ xrow, int d) {
