@@ -115,6 +115,12 @@ double stag_e2lsh_collision_probability(double c, int32_t K, int32_t L);
  *                       result (the value is |S_gpu - S| / S <= bound except
  *                       with probability < 1e-9 per result; see the library
  *                       documentation for the model).
+ * Small densities: the tiles form each term as 2^E in fp32.  A query whose
+ * sum comes out below 2^-60 (its terms may lie below the fp32 range) is
+ * recomputed on the device with its exponents shifted by their maximum
+ * m_q (a max pass and a second pass over the 128-query tiles that hold
+ * such queries; S = sum * 2^m_q, its bound widened by |m_q|); a result below
+ * the fp64 range is 0.  Without such queries the two passes end at once.
  * Limits: 1 <= d <= 1024 (d > 256: fp32 form only; STAG_E_UNSUPPORTED
  * otherwise), n, m >= 1, n*d and m*d < 2^31.  FP16_SPLIT additionally needs |x_j| and
  * |2a log2(e) q_j| below 65504; out-of-range inputs give a NaN result.

@@ -44,10 +44,12 @@ struct BoundModel {
   double near_y2 = 0.0;  // exponential kernel: terms with computed y^2 below this are exact
 };
 
-__host__ __device__ inline double relative_bound(const BoundModel& bm, double qn, double xm) {
+// extra: a further offset magnitude carried by the accumulators (the shift
+// |m_q| of an underflow-rescued query, in exponent units).
+__host__ __device__ inline double relative_bound(const BoundModel& bm, double qn, double xm, double extra = 0.0) {
   const double ln2 = 0.69314718055994530942;
   const double cross = 2.0 * bm.la * sqrt(qn) * sqrt(xm);
-  const double offs = bm.la * (qn + xm);
+  const double offs = bm.la * (qn + xm) + extra;
   const double dE = bm.c_acc * (cross + offs) + bm.c_split * cross + bm.c_off * offs;
   if (bm.kern == 0) return expm1(ln2 * dE) + bm.c_tail;
   const double dy = 0x1.0p-23 * fmin(150.0, sqrt(bm.la) * (sqrt(qn) + sqrt(xm)));
@@ -85,6 +87,12 @@ struct TileExtra {
   int self = 0;
   float* tp = nullptr;
   int64_t ntile = 0;
+  // Gaussian underflow rescue: max_pass makes each partial the largest
+  // exponent E of its (chunk, query) instead of a sum; with qtile_active, a
+  // workgroup whose 128-query tile has flag 0 returns at once (its partials
+  // are not written).
+  int max_pass = 0;
+  const int* qtile_active = nullptr;
 };
 
 int exact_padded_dim(int d);  // 0 if unsupported
@@ -108,6 +116,6 @@ stag_status launch_exact_tiles(const Operands& xo, const Operands& qo, double* p
                                hipStream_t st);
 stag_status launch_reduce(const double* partial, int P, const Operands& qo, const Operands& xo, double scale,
                           const BoundModel& bm, double* S_out, double* bound_out, hipStream_t st,
-                          const int* near_over = nullptr);
+                          const int* near_over = nullptr, int* flag = nullptr, int* qtile_flag = nullptr);
 
 }  // namespace stag

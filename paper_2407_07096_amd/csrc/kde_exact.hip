@@ -127,15 +127,25 @@ __global__ __launch_bounds__(256) void prep_rows(const float* __restrict__ src, 
   }
 }
 
+// A Gaussian sum below this is recomputed with its exponents shifted by
+// their maximum (its terms may lie below the fp32 range of the tile).
+constexpr double kRescueBelow = 0x1.0p-60;
+
 // S(q) = sum of chunk partials in chunk order; optional 1/n; a-priori bound.
+// With flag: a sum below kRescueBelow sets flag[q] and its 128-query tile's
+// flag (both zeroed beforehand).
 __global__ void reduce_partials(const double* __restrict__ partial, int P, int64_t m_pad, int64_t m, double scale,
                                 const double* __restrict__ qnrm, const unsigned long long* __restrict__ max_xnrm_bits,
                                 BoundModel bm, const int* __restrict__ near_over, double* __restrict__ S_out,
-                                double* __restrict__ bound_out) {
+                                double* __restrict__ bound_out, int* __restrict__ flag, int* __restrict__ qtile_flag) {
   const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= m) return;
   double s = 0.0;
   for (int p = 0; p < P; ++p) s += partial[(int64_t)p * m_pad + q];
+  if (flag && s < kRescueBelow) {
+    flag[q] = 1;
+    qtile_flag[q / kBQ] = 1;
+  }
   S_out[q] = s * scale;
   if (bound_out) {
     const double xm = __longlong_as_double((long long)*max_xnrm_bits);
@@ -270,6 +280,7 @@ stag_status launch_exact_tiles(const Operands& xo, const Operands& qo, double* p
   if (ex.kernel != STAG_KERNEL_GAUSSIAN && (ex.self || ex.tp))
     return fail(STAG_E_UNSUPPORTED, "tile extras need the Gaussian kernel");
   switch (tiles::tile_mode(ex)) {
+    case tiles::kModeMax: return launch_tiles_max(xo, qo, partial, ex, st);
     case tiles::kModeGauss: return launch_tiles_gauss(xo, qo, partial, ex, st);
     case tiles::kModeGaussExtra: return launch_tiles_gauss_extra(xo, qo, partial, ex, st);
     case tiles::kModeExponential: return launch_tiles_exponential(xo, qo, partial, ex, st);
@@ -279,11 +290,11 @@ stag_status launch_exact_tiles(const Operands& xo, const Operands& qo, double* p
 
 stag_status launch_reduce(const double* partial, int P, const Operands& qo, const Operands& xo, double scale,
                           const BoundModel& bm, double* S_out, double* bound_out, hipStream_t st,
-                          const int* near_over) {
+                          const int* near_over, int* flag, int* qtile_flag) {
   const int64_t m = qo.rows;
   ScopedTimer tm("kde_reduce", st);
   hipLaunchKernelGGL(reduce_partials, dim3((unsigned)ceil_div(m, 256)), dim3(256), 0, st, partial, P, qo.rows_pad, m,
-                     scale, qo.nrm, xo.max_nrm_bits, bm, near_over, S_out, bound_out);
+                     scale, qo.nrm, xo.max_nrm_bits, bm, near_over, S_out, bound_out, flag, qtile_flag);
   return check_launch("reduce_partials");
 }
 
@@ -315,6 +326,69 @@ BoundModel make_bound_model(int form, int d, double a_tile, int kernel) {
 
 namespace stag {
 namespace {
+
+// Underflow rescue of the Gaussian exact sum.  For a flagged query (sum
+// below kRescueBelow), m_q = the largest exponent E over the data (max pass
+// of the tiles); its offset becomes fl32(-a log2(e) ||q||^2 - m_q) (one
+// rounding from binary64), so that its largest term is about 2^0, and the
+// tiles run again on the flagged query tiles; S = (sum) 2^{m_q}.
+__global__ void rescue_shift(const double* __restrict__ pmax, int P, int64_t m_pad, int64_t m,
+                             const int* __restrict__ flag, const double* __restrict__ qnrm, double neg_a_l2e,
+                             const float* __restrict__ off, float* __restrict__ off2, double* __restrict__ shift) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= m_pad) return;
+  double mq = 0.0;
+  float o = off[q];
+  if (q < m && flag[q]) {
+    mq = -HUGE_VAL;
+    for (int p = 0; p < P; ++p) mq = fmax(mq, pmax[(int64_t)p * m_pad + q]);
+    o = (float)(neg_a_l2e * qnrm[q] - mq);
+  }
+  off2[q] = o;
+  shift[q] = mq;
+}
+
+__global__ void rescue_reduce(const double* __restrict__ partial, int P, int64_t m_pad, int64_t m,
+                              const int* __restrict__ flag, const double* __restrict__ shift, double scale,
+                              const double* __restrict__ qnrm, const unsigned long long* __restrict__ max_xnrm_bits,
+                              BoundModel bm, double* __restrict__ S_out, double* __restrict__ bound_out) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= m || !flag[q]) return;
+  double s = 0.0;
+  for (int p = 0; p < P; ++p) s += partial[(int64_t)p * m_pad + q];
+  S_out[q] = s * exp2(shift[q]) * scale;
+  if (bound_out) {
+    const double xm = __longlong_as_double((long long)*max_xnrm_bits);
+    bound_out[q] = relative_bound(bm, qnrm[q], xm, fabs(shift[q]));
+  }
+}
+
+stag_status rescue_underflow(const Operands& xo, const Operands& qo, int P, double a_tile, double scale,
+                             const BoundModel& bm, const int* flag, const int* qtile_flag, double* S_out,
+                             double* bound_out, Workspace& ws, hipStream_t st) {
+  const int64_t m_pad = qo.rows_pad, m = qo.rows;
+  double *pmax = nullptr, *p2 = nullptr, *shift = nullptr;
+  float* off2 = nullptr;
+  STAG_TRY(ws.alloc(&pmax, (size_t)P * m_pad));
+  STAG_TRY(ws.alloc(&p2, (size_t)P * m_pad));
+  STAG_TRY(ws.alloc(&shift, (size_t)m_pad));
+  STAG_TRY(ws.alloc(&off2, (size_t)m_pad));
+  TileExtra exm;
+  exm.max_pass = 1;
+  exm.qtile_active = qtile_flag;
+  STAG_TRY(launch_exact_tiles(xo, qo, pmax, exm, st));
+  hipLaunchKernelGGL(rescue_shift, dim3((unsigned)ceil_div(m_pad, 256)), dim3(256), 0, st, pmax, P, m_pad, m, flag,
+                     qo.nrm, -a_tile * kLog2e, qo.off, off2, shift);
+  STAG_TRY(check_launch("rescue_shift"));
+  Operands q2 = qo;
+  q2.off = off2;
+  TileExtra exs;
+  exs.qtile_active = qtile_flag;
+  STAG_TRY(launch_exact_tiles(xo, q2, p2, exs, st));
+  hipLaunchKernelGGL(rescue_reduce, dim3((unsigned)ceil_div(m, 256)), dim3(256), 0, st, p2, P, m_pad, m, flag, shift,
+                     scale, qo.nrm, xo.max_nrm_bits, bm, S_out, bound_out);
+  return check_launch("rescue_reduce");
+}
 
 struct InputStats {
   double max_nrm_x, max_nrm_q;
@@ -415,8 +489,18 @@ stag_status exact_kernel_impl(const char* fn, const float* X, int64_t n, const f
   }
   STAG_TRY(launch_exact_tiles(xo, qo, partial, ex, stream));
   const double scale = (flags & STAG_NORMALIZE) ? 1.0 / (double)n : 1.0;
-  STAG_TRY(launch_reduce(partial, P, qo, xo, scale, make_bound_model(form, d, at, kernel), S_out, bound_out, stream,
-                         ex.near_over));
+  const BoundModel bm = make_bound_model(form, d, at, kernel);
+  // Gaussian: sums below kRescueBelow are flagged and recomputed with a shift
+  int *flag = nullptr, *qflag = nullptr;
+  const bool rescue = kernel == STAG_KERNEL_GAUSSIAN;
+  if (rescue) {
+    STAG_TRY(ws.alloc(&flag, (size_t)m));
+    STAG_TRY(ws.alloc(&qflag, (size_t)(qo.rows_pad / kBQ)));
+    STAG_HIP(hipMemsetAsync(flag, 0, (size_t)m * sizeof(int), stream));
+    STAG_HIP(hipMemsetAsync(qflag, 0, (size_t)(qo.rows_pad / kBQ) * sizeof(int), stream));
+  }
+  STAG_TRY(launch_reduce(partial, P, qo, xo, scale, bm, S_out, bound_out, stream, ex.near_over, flag, qflag));
+  if (rescue) STAG_TRY(rescue_underflow(xo, qo, P, at, scale, bm, flag, qflag, S_out, bound_out, ws, stream));
   return STAG_OK;
 }
 

@@ -52,6 +52,20 @@ constexpr int kModeGauss = 0;
 constexpr int kModeGaussExtra = 1;
 constexpr int kModeExponential = 2;
 constexpr int kModeLogistic = 3;
+// kModeMax: no kernel values; each partial is the largest exponent E of its
+// (chunk, query), the shift of the underflow rescue of the Gaussian sum.
+constexpr int kModeMax = 4;
+
+// Per-lane accumulation across tiles: fp64 sum, or the maximum in kModeMax.
+template <int MODE>
+__device__ inline double acc_init() {
+  return MODE == kModeMax ? -HUGE_VAL : 0.0;
+}
+template <int MODE>
+__device__ inline double acc_add(double acc, double v) {
+  if constexpr (MODE == kModeMax) return fmax(acc, v);
+  else return acc + v;
+}
 
 template <int MODE>
 __device__ inline float kernel_value(float e) {
@@ -157,6 +171,12 @@ __device__ inline float tile_epilogue(const f32x16& c, int64_t row_base, int64_t
   float cp[16];
 #pragma unroll
   for (int i = 0; i < 16; ++i) cp[i] = c[i];
+  if constexpr (MODE == kModeMax) {
+    float mx = cp[0];
+#pragma unroll
+    for (int i = 1; i < 16; ++i) mx = fmaxf(mx, cp[i]);
+    return mx;
+  }
   if constexpr (EXTRA) {
     if (ex.self && row_base == col_base) {
       // lane (column r32, half h) holds rows 8(i/4) + 4h + i%4
@@ -247,6 +267,7 @@ __global__ __launch_bounds__(256, 2) void tile_f32(const float* __restrict__ Xp,
   const int chunk = blockIdx.x / n_qtiles;
   const int64_t col_base = (int64_t)qtile * kBQ + wave * 32;
   const int64_t qi = col_base + r32;
+  if (ex.qtile_active && ex.qtile_active[qtile] == 0) return;  // whole block: no query of its tile is active
 
   float bq[H];
   {
@@ -281,7 +302,7 @@ __global__ __launch_bounds__(256, 2) void tile_f32(const float* __restrict__ Xp,
     tbeta[buf][tid & 31] = sbeta;
   };
 
-  double acc = 0.0;
+  double acc = acc_init<MODE>();
   TileSums8 grp = {};
   __shared__ near_lds_t<MODE> near_lds;
   NearRec nr = {near_lds, 0, false};
@@ -290,11 +311,11 @@ __global__ __launch_bounds__(256, 2) void tile_f32(const float* __restrict__ Xp,
     __syncthreads();
     if constexpr (MODE == kModeGaussExtra) {
       if (t > 0)
-        acc += (double)tile_epilogue<MODE>(cdone, row0 + (int64_t)(t - 1) * kTileRows, col_base, r32, h, qi, ex, &grp);
+        acc = acc_add<MODE>(acc, (double)tile_epilogue<MODE>(cdone, row0 + (int64_t)(t - 1) * kTileRows, col_base, r32, h, qi, ex, &grp));
     } else if constexpr (MODE == kModeExponential) {
-      acc += (double)tile_epilogue<MODE>(cdone, 0, 0, r32, h, qi, ex, nullptr, false, &nr, t - 1);
+      acc = acc_add<MODE>(acc, (double)tile_epilogue<MODE>(cdone, 0, 0, r32, h, qi, ex, nullptr, false, &nr, t - 1));
     } else {
-      acc += (double)tile_epilogue<MODE>(cdone, 0, 0, r32, h, qi, ex);
+      acc = acc_add<MODE>(acc, (double)tile_epilogue<MODE>(cdone, 0, 0, r32, h, qi, ex));
     }
     const float* arow = &tile[buf][r32 * LD + h * H];
     // the accumulators start from the offsets alpha_q + beta_x of their pairs
@@ -340,11 +361,11 @@ __global__ __launch_bounds__(256, 2) void tile_f32(const float* __restrict__ Xp,
     step(t, ca, cb);
     ca = cb;
   }
-  acc += (double)tile_epilogue<MODE>(ca, row0 + (int64_t)(ntiles - 1) * kTileRows, col_base, r32, h, qi, ex, &grp,
-                                    true, &nr, ntiles - 1);
+  acc = acc_add<MODE>(acc, (double)tile_epilogue<MODE>(ca, row0 + (int64_t)(ntiles - 1) * kTileRows, col_base, r32, h, qi, ex, &grp,
+                                    true, &nr, ntiles - 1));
   if constexpr (MODE == kModeExponential) acc += near_finish(ex, nr, qi, h, row0, tid);
   const double other = __shfl_down(acc, 32);
-  if (h == 0) partial[(int64_t)chunk * m_pad + qi] = acc + other;
+  if (h == 0) partial[(int64_t)chunk * m_pad + qi] = acc_add<MODE>(acc, other);
 }
 
 // Split forms: v_mfma_f32_32x32x16_{f16,bf16}.  Lane l supplies 8 consecutive
@@ -386,6 +407,7 @@ __global__ __launch_bounds__(256, 2) void tile_split(
   const int chunk = blockIdx.x / n_qtiles;
   const int64_t col_base = (int64_t)qtile * kBQ + wave * 32;
   const int64_t qi = col_base + r32;
+  if (ex.qtile_active && ex.qtile_active[qtile] == 0) return;  // whole block: no query of its tile is active
 
   const unsigned short* Qp[3] = {Q0, Q1, Q2};
   const unsigned short* Xpp[3] = {X0, X1, X2};
@@ -424,7 +446,7 @@ __global__ __launch_bounds__(256, 2) void tile_split(
     tbeta[buf][tid & 31] = sbeta;
   };
 
-  double acc = 0.0;
+  double acc = acc_init<MODE>();
   TileSums8 grp = {};
   __shared__ near_lds_t<MODE> near_lds;
   NearRec nr = {near_lds, 0, false};
@@ -433,11 +455,11 @@ __global__ __launch_bounds__(256, 2) void tile_split(
     __syncthreads();
     if constexpr (MODE == kModeGaussExtra) {
       if (t > 0)
-        acc += (double)tile_epilogue<MODE>(cdone, row0 + (int64_t)(t - 1) * kTileRows, col_base, r32, h, qi, ex, &grp);
+        acc = acc_add<MODE>(acc, (double)tile_epilogue<MODE>(cdone, row0 + (int64_t)(t - 1) * kTileRows, col_base, r32, h, qi, ex, &grp));
     } else if constexpr (MODE == kModeExponential) {
-      acc += (double)tile_epilogue<MODE>(cdone, 0, 0, r32, h, qi, ex, nullptr, false, &nr, t - 1);
+      acc = acc_add<MODE>(acc, (double)tile_epilogue<MODE>(cdone, 0, 0, r32, h, qi, ex, nullptr, false, &nr, t - 1));
     } else {
-      acc += (double)tile_epilogue<MODE>(cdone, 0, 0, r32, h, qi, ex);
+      acc = acc_add<MODE>(acc, (double)tile_epilogue<MODE>(cdone, 0, 0, r32, h, qi, ex));
     }
     // the accumulators start from the offsets alpha_q + beta_x of their pairs
     f32x16 c;
@@ -490,11 +512,11 @@ __global__ __launch_bounds__(256, 2) void tile_split(
     step(t, ca, cb);
     ca = cb;
   }
-  acc += (double)tile_epilogue<MODE>(ca, row0 + (int64_t)(ntiles - 1) * kTileRows, col_base, r32, h, qi, ex, &grp,
-                                    true, &nr, ntiles - 1);
+  acc = acc_add<MODE>(acc, (double)tile_epilogue<MODE>(ca, row0 + (int64_t)(ntiles - 1) * kTileRows, col_base, r32, h, qi, ex, &grp,
+                                    true, &nr, ntiles - 1));
   if constexpr (MODE == kModeExponential) acc += near_finish(ex, nr, qi, h, row0, tid);
   const double other = __shfl_down(acc, 32);
-  if (h == 0) partial[(int64_t)chunk * m_pad + qi] = acc + other;
+  if (h == 0) partial[(int64_t)chunk * m_pad + qi] = acc_add<MODE>(acc, other);
 }
 
 // ---------------------------------------------------------------------------
@@ -517,6 +539,7 @@ __global__ __launch_bounds__(256) void tile_f32_wide(const float* __restrict__ X
   const int chunk = blockIdx.x / n_qt32;
   const int64_t col_base = (int64_t)qtile * 32;
   const int64_t qi = col_base + r32;
+  if (ex.qtile_active && ex.qtile_active[col_base / kBQ] == 0) return;  // whole block
   // B operand into LDS
   {
     const f32x4* src = reinterpret_cast<const f32x4*>(Qs + col_base * DP);
@@ -532,7 +555,7 @@ __global__ __launch_bounds__(256) void tile_f32_wide(const float* __restrict__ X
   const int64_t rem = (n_pad - row0) / kTileRows;
   const int ntiles = (int)(rem < kChunkRows / kTileRows ? rem : kChunkRows / kTileRows);
   const float* brow = &qlds[r32 * LD + h * H];
-  double acc = 0.0;
+  double acc = acc_init<MODE>();
   __shared__ near_lds_t<MODE> near_lds;
   NearRec nr = {near_lds, 0, false};
   for (int t = wave; t < ntiles; t += 4) {
@@ -559,20 +582,28 @@ __global__ __launch_bounds__(256) void tile_f32_wide(const float* __restrict__ X
     }
     const float tb = beta[rb + r32];
     c = __builtin_amdgcn_mfma_f32_32x32x2f32(h == 0 ? 1.0f : tb, baug, c, 0, 0, 0);
-    acc += (double)tile_epilogue<MODE>(c, rb, col_base, r32, h, qi, ex, nullptr, false, &nr, t);
+    acc = acc_add<MODE>(acc, (double)tile_epilogue<MODE>(c, rb, col_base, r32, h, qi, ex, nullptr, false, &nr, t));
   }
   if constexpr (MODE == kModeExponential) acc += near_finish(ex, nr, qi, h, row0, tid);
   const double other = __shfl_down(acc, 32);
-  if (h == 0) wsum[wave][r32] = acc + other;
+  if (h == 0) wsum[wave][r32] = acc_add<MODE>(acc, other);
   __syncthreads();
   if (tid < 32) {
-    const double tot = ((wsum[0][tid] + wsum[1][tid]) + wsum[2][tid]) + wsum[3][tid];
+    const double tot =
+        acc_add<MODE>(acc_add<MODE>(acc_add<MODE>(wsum[0][tid], wsum[1][tid]), wsum[2][tid]), wsum[3][tid]);
     partial[(int64_t)chunk * m_pad + col_base + tid] = tot;
   }
 }
 
+// Timer name of a launch: the underflow rescue's passes are timed apart from
+// the tiles they repeat.
+inline const char* rescue_timer(const TileExtra& ex, const char* name) {
+  return ex.max_pass ? "kde_rescue_max" : (ex.qtile_active ? "kde_rescue_sum" : name);
+}
+
 // Epilogue mode of a launch (kernel function, TileExtra outputs).
 inline int tile_mode(const TileExtra& ex) {
+  if (ex.max_pass) return kModeMax;
   if (ex.kernel == STAG_KERNEL_EXPONENTIAL) return kModeExponential;
   if (ex.kernel == STAG_KERNEL_LOGISTIC) return kModeLogistic;
   return (ex.self || ex.tp) ? kModeGaussExtra : kModeGauss;
@@ -582,7 +613,7 @@ template <int DP, int MODE>
 stag_status launch_tile_f32(const float* Xp, const float* beta, const float* Qs, const float* alpha, int64_t n_pad,
                             int n_qtiles, int64_t m_pad, int P, double* partial, const TileExtra& ex,
                             hipStream_t st) {
-  ScopedTimer tm("kde_tile_f32", st);
+  ScopedTimer tm(rescue_timer(ex, "kde_tile_f32"), st);
   hipLaunchKernelGGL((tile_f32<DP, MODE>), dim3((unsigned)((int64_t)n_qtiles * P)), dim3(256), 0, st, Xp, beta, Qs,
                      alpha, n_pad, n_qtiles, m_pad, partial, ex);
   return check_launch("tile_f32");
@@ -593,7 +624,10 @@ stag_status launch_tile_split(void* const* xp, const float* xaug, void* const* q
                               int n_qtiles, int64_t m_pad, int P, double* partial, const TileExtra& ex,
                               hipStream_t st) {
   using U = const unsigned short*;
-  ScopedTimer tm(FORM == STAG_FORM_FP16_SPLIT ? "kde_tile_fp16x3" : (FORM == STAG_FORM_BF16_SPLIT ? "kde_tile_bf16x3" : "kde_tile_bf16x6"), st);
+  ScopedTimer tm(rescue_timer(ex, FORM == STAG_FORM_FP16_SPLIT
+                                     ? "kde_tile_fp16x3"
+                                     : (FORM == STAG_FORM_BF16_SPLIT ? "kde_tile_bf16x3" : "kde_tile_bf16x6")),
+                 st);
   hipLaunchKernelGGL((tile_split<FORM, DP, MODE>), dim3((unsigned)((int64_t)n_qtiles * P)), dim3(256), 0, st,
                      (U)xp[0], (U)xp[1], (U)xp[2], xaug, (U)qp[0], (U)qp[1], (U)qp[2], qaug, n_pad, n_qtiles, m_pad,
                      partial, ex);
@@ -648,7 +682,7 @@ stag_status launch_tiles(const Operands& xo, const Operands& qo, double* partial
     const size_t lds = (size_t)32 * (xo.dp + 4) * sizeof(float);
     STAG_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&tile_f32_wide<MODE>),
                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    ScopedTimer tm("kde_tile_f32_wide", st);
+    ScopedTimer tm(rescue_timer(ex, "kde_tile_f32_wide"), st);
     hipLaunchKernelGGL(tile_f32_wide<MODE>, dim3((unsigned)((int64_t)n_qt32 * P)), dim3(256), lds, st,
                        (const float*)xo.part[0], xo.off, (const float*)qo.part[0], qo.off, xo.dp, xo.rows_pad,
                        n_qt32, qo.rows_pad, partial, ex);
@@ -681,5 +715,7 @@ stag_status launch_tiles_exponential(const Operands& xo, const Operands& qo, dou
                                      hipStream_t st);
 stag_status launch_tiles_logistic(const Operands& xo, const Operands& qo, double* partial, const TileExtra& ex,
                                   hipStream_t st);
+stag_status launch_tiles_max(const Operands& xo, const Operands& qo, double* partial, const TileExtra& ex,
+                             hipStream_t st);
 
 }  // namespace stag
