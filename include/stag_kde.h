@@ -167,7 +167,8 @@ stag_status stag_kde_exact_kernel(const float* X, int64_t n, const float* Q, int
  *   S_out [m] f64 device: (n/s) sum_r exp(-a ||q - x_{j_r}||^2), n/s rounded
  *   once; an unbiased estimate of S(q).
  *   bound_out [m] f64 device or NULL: relative error bound of S_out against
- *   the exact fp64 value of that same estimator (as stag_kde_exact's).
+ *   the exact fp64 value of that same estimator (as stag_kde_exact's, small
+ *   estimates taking the same underflow rescue).
  *   idx_out [s] int64 device or NULL: the sampled indices.
  * form, d and size limits as stag_kde_exact (samples * d < 2^31). */
 stag_status stag_kde_random_sample(const float* X, int64_t n, const float* Q, int64_t m, int32_t d, double a,

@@ -114,6 +114,12 @@ stag_status prep_query_into(int form, const float* src, int64_t rows, int d, dou
 int64_t query_tile_rows();
 stag_status launch_exact_tiles(const Operands& xo, const Operands& qo, double* partial, const TileExtra& ex,
                                hipStream_t st);
+// launch_reduce for the Gaussian kernel with the underflow rescue: sums
+// below 2^-60 are recomputed with their exponents shifted by their maximum
+// (two more tile passes over the 128-query tiles that hold such queries).
+stag_status reduce_with_rescue(const double* partial, int P, const Operands& qo, const Operands& xo, double a_tile,
+                               double scale, const BoundModel& bm, double* S_out, double* bound_out, Workspace& ws,
+                               hipStream_t st);
 stag_status launch_reduce(const double* partial, int P, const Operands& qo, const Operands& xo, double scale,
                           const BoundModel& bm, double* S_out, double* bound_out, hipStream_t st,
                           const int* near_over = nullptr, int* flag = nullptr, int* qtile_flag = nullptr);

@@ -325,6 +325,7 @@ BoundModel make_bound_model(int form, int d, double a_tile, int kernel) {
 }  // namespace stag
 
 namespace stag {
+
 namespace {
 
 // Underflow rescue of the Gaussian exact sum.  For a flagged query (sum
@@ -389,6 +390,23 @@ stag_status rescue_underflow(const Operands& xo, const Operands& qo, int P, doub
                      scale, qo.nrm, xo.max_nrm_bits, bm, S_out, bound_out);
   return check_launch("rescue_reduce");
 }
+
+}  // namespace
+
+stag_status reduce_with_rescue(const double* partial, int P, const Operands& qo, const Operands& xo, double a_tile,
+                               double scale, const BoundModel& bm, double* S_out, double* bound_out, Workspace& ws,
+                               hipStream_t st) {
+  const int64_t m = qo.rows;
+  int *flag = nullptr, *qflag = nullptr;
+  STAG_TRY(ws.alloc(&flag, (size_t)m));
+  STAG_TRY(ws.alloc(&qflag, (size_t)(qo.rows_pad / kBQ)));
+  STAG_HIP(hipMemsetAsync(flag, 0, (size_t)m * sizeof(int), st));
+  STAG_HIP(hipMemsetAsync(qflag, 0, (size_t)(qo.rows_pad / kBQ) * sizeof(int), st));
+  STAG_TRY(launch_reduce(partial, P, qo, xo, scale, bm, S_out, bound_out, st, nullptr, flag, qflag));
+  return rescue_underflow(xo, qo, P, a_tile, scale, bm, flag, qflag, S_out, bound_out, ws, st);
+}
+
+namespace {
 
 struct InputStats {
   double max_nrm_x, max_nrm_q;
@@ -490,18 +508,10 @@ stag_status exact_kernel_impl(const char* fn, const float* X, int64_t n, const f
   STAG_TRY(launch_exact_tiles(xo, qo, partial, ex, stream));
   const double scale = (flags & STAG_NORMALIZE) ? 1.0 / (double)n : 1.0;
   const BoundModel bm = make_bound_model(form, d, at, kernel);
-  // Gaussian: sums below kRescueBelow are flagged and recomputed with a shift
-  int *flag = nullptr, *qflag = nullptr;
-  const bool rescue = kernel == STAG_KERNEL_GAUSSIAN;
-  if (rescue) {
-    STAG_TRY(ws.alloc(&flag, (size_t)m));
-    STAG_TRY(ws.alloc(&qflag, (size_t)(qo.rows_pad / kBQ)));
-    STAG_HIP(hipMemsetAsync(flag, 0, (size_t)m * sizeof(int), stream));
-    STAG_HIP(hipMemsetAsync(qflag, 0, (size_t)(qo.rows_pad / kBQ) * sizeof(int), stream));
-  }
-  STAG_TRY(launch_reduce(partial, P, qo, xo, scale, bm, S_out, bound_out, stream, ex.near_over, flag, qflag));
-  if (rescue) STAG_TRY(rescue_underflow(xo, qo, P, at, scale, bm, flag, qflag, S_out, bound_out, ws, stream));
-  return STAG_OK;
+  // Gaussian: sums below kRescueBelow are recomputed with shifted exponents
+  if (kernel == STAG_KERNEL_GAUSSIAN)
+    return reduce_with_rescue(partial, P, qo, xo, at, scale, bm, S_out, bound_out, ws, stream);
+  return launch_reduce(partial, P, qo, xo, scale, bm, S_out, bound_out, stream, ex.near_over);
 }
 
 }  // namespace

@@ -82,7 +82,7 @@ extern "C" stag_status stag_kde_random_sample(const float* X, int64_t n, const f
   STAG_TRY(ws.alloc(&partial, (size_t)P * qo.rows_pad));
   STAG_TRY(launch_exact_tiles(xo, qo, partial, TileExtra{}, stream));
   const double scale = (double)n / (double)samples;
-  return launch_reduce(partial, P, qo, xo, scale, make_bound_model(form, d, a), S_out, bound_out, stream);
+  return reduce_with_rescue(partial, P, qo, xo, a, scale, make_bound_model(form, d, a), S_out, bound_out, ws, stream);
 }
 
 extern "C" int64_t stag_rs_sample_size(double eps, double mu, int64_t m, double delta) {

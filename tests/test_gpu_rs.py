@@ -86,3 +86,24 @@ def test_full_size_sampled(stag):
     assert np.array_equal(I.cpu().numpy(), ridx)
     err = rel_err(S.cpu().numpy()[idx], ref)
     assert np.all(err <= B.cpu().numpy()[idx]) and err.max() <= 1e-5
+
+
+@pytest.mark.parametrize("form", ["fp32", "fp16_split"])
+def test_small_densities(stag, form):
+    # queries far from the data at a = 1: the estimates (down to ~1e-250) lie
+    # below the fp32 range of the tile's terms and take the underflow rescue;
+    # they match the oracle's estimator within the bound
+    import oracle
+    rng = np.random.default_rng(41)
+    d = 32
+    X = rng.normal(size=(4000, d)).astype(np.float32)
+    Q = (X[:128] + rng.uniform(3.0, 6.0, size=(128, 1)).astype(np.float32)
+         * rng.normal(size=(128, d)).astype(np.float32) / np.sqrt(d) * 4.0).astype(np.float32)
+    announce(f"random sampling small densities m=128 d={d} a=1 form={form}")
+    S, B, _ = _run(stag, X, Q, 1.0, 1000, 5, form)
+    ref, _ = oracle.kde_random_sample(X, Q, 1.0, 1000, 5)
+    ok = ref > 1e-300
+    assert np.sum(ref[ok] < 1e-38) > 20
+    err = np.abs(S[ok] - ref[ok]) / ref[ok]
+    print(f"[measured] rs small densities {form}: min {ref[ok].min():.3e}, max rel err {err.max():.3e}", flush=True)
+    assert np.all(err <= B[ok]), (err.max(), B[ok].min())
