@@ -281,6 +281,7 @@ stag_status launch_exact_tiles(const Operands& xo, const Operands& qo, double* p
     return fail(STAG_E_UNSUPPORTED, "tile extras need the Gaussian kernel");
   switch (tiles::tile_mode(ex)) {
     case tiles::kModeMax: return launch_tiles_max(xo, qo, partial, ex, st);
+    case tiles::kModeGaussRescue: return launch_tiles_gauss_rescue(xo, qo, partial, ex, st);
     case tiles::kModeGauss: return launch_tiles_gauss(xo, qo, partial, ex, st);
     case tiles::kModeGaussExtra: return launch_tiles_gauss_extra(xo, qo, partial, ex, st);
     case tiles::kModeExponential: return launch_tiles_exponential(xo, qo, partial, ex, st);

@@ -55,6 +55,10 @@ constexpr int kModeLogistic = 3;
 // kModeMax: no kernel values; each partial is the largest exponent E of its
 // (chunk, query), the shift of the underflow rescue of the Gaussian sum.
 constexpr int kModeMax = 4;
+// kModeGaussRescue: the Gaussian sum of the rescue's second pass (the same
+// arithmetic as kModeGauss, a kernel of its own so that traces and timers
+// tell it apart from the tiles it repeats).
+constexpr int kModeGaussRescue = 5;
 
 // Per-lane accumulation across tiles: fp64 sum, or the maximum in kModeMax.
 template <int MODE>
@@ -69,7 +73,7 @@ __device__ inline double acc_add(double acc, double v) {
 
 template <int MODE>
 __device__ inline float kernel_value(float e) {
-  if constexpr (MODE == kModeGauss || MODE == kModeGaussExtra) {
+  if constexpr (MODE == kModeGauss || MODE == kModeGaussExtra || MODE == kModeGaussRescue) {
     return __builtin_amdgcn_exp2f(e);
   } else {
     const float ne = -e;
@@ -604,6 +608,7 @@ inline const char* rescue_timer(const TileExtra& ex, const char* name) {
 // Epilogue mode of a launch (kernel function, TileExtra outputs).
 inline int tile_mode(const TileExtra& ex) {
   if (ex.max_pass) return kModeMax;
+  if (ex.qtile_active) return kModeGaussRescue;
   if (ex.kernel == STAG_KERNEL_EXPONENTIAL) return kModeExponential;
   if (ex.kernel == STAG_KERNEL_LOGISTIC) return kModeLogistic;
   return (ex.self || ex.tp) ? kModeGaussExtra : kModeGauss;
@@ -717,5 +722,7 @@ stag_status launch_tiles_logistic(const Operands& xo, const Operands& qo, double
                                   hipStream_t st);
 stag_status launch_tiles_max(const Operands& xo, const Operands& qo, double* partial, const TileExtra& ex,
                              hipStream_t st);
+stag_status launch_tiles_gauss_rescue(const Operands& xo, const Operands& qo, double* partial, const TileExtra& ex,
+                                      hipStream_t st);
 
 }  // namespace stag
