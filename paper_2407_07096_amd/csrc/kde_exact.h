@@ -114,6 +114,18 @@ stag_status prep_query_into(int form, const float* src, int64_t rows, int d, dou
 int64_t query_tile_rows();
 stag_status launch_exact_tiles(const Operands& xo, const Operands& qo, double* partial, const TileExtra& ex,
                                hipStream_t st);
+// A Gaussian sum below this is recomputed with its exponents shifted by
+// their maximum (its terms may lie below the fp32 range of the tile).
+constexpr double kRescueBelow = 0x1.0p-60;
+
+// Shift of the underflow rescue: for the flagged queries (flag[q] != 0, their
+// 128-query tiles in qtile_flag) m_q = the largest exponent E over the data
+// (a max pass of the tiles; self: leave out the diagonal of a data set
+// queried against itself), shift[q] = m_q and off2[q] = fl32(-a_tile log2(e)
+// ||q||^2 - m_q); other queries keep their offset and shift 0.  off2 and
+// shift have qo.rows_pad entries.
+stag_status rescue_offsets(const Operands& xo, const Operands& qo, int P, double a_tile, int self, const int* flag,
+                           const int* qtile_flag, float* off2, double* shift, Workspace& ws, hipStream_t st);
 // launch_reduce for the Gaussian kernel with the underflow rescue: sums
 // below 2^-60 are recomputed with their exponents shifted by their maximum
 // (two more tile passes over the 128-query tiles that hold such queries).

@@ -127,10 +127,6 @@ __global__ __launch_bounds__(256) void prep_rows(const float* __restrict__ src, 
   }
 }
 
-// A Gaussian sum below this is recomputed with its exponents shifted by
-// their maximum (its terms may lie below the fp32 range of the tile).
-constexpr double kRescueBelow = 0x1.0p-60;
-
 // S(q) = sum of chunk partials in chunk order; optional 1/n; a-priori bound.
 // With flag: a sum below kRescueBelow sets flag[q] and its 128-query tile's
 // flag (both zeroed beforehand).
@@ -282,6 +278,7 @@ stag_status launch_exact_tiles(const Operands& xo, const Operands& qo, double* p
   switch (tiles::tile_mode(ex)) {
     case tiles::kModeMax: return launch_tiles_max(xo, qo, partial, ex, st);
     case tiles::kModeGaussRescue: return launch_tiles_gauss_rescue(xo, qo, partial, ex, st);
+    case tiles::kModeGaussExtraRescue: return launch_tiles_gauss_extra_rescue(xo, qo, partial, ex, st);
     case tiles::kModeGauss: return launch_tiles_gauss(xo, qo, partial, ex, st);
     case tiles::kModeGaussExtra: return launch_tiles_gauss_extra(xo, qo, partial, ex, st);
     case tiles::kModeExponential: return launch_tiles_exponential(xo, qo, partial, ex, st);
@@ -369,19 +366,12 @@ stag_status rescue_underflow(const Operands& xo, const Operands& qo, int P, doub
                              const BoundModel& bm, const int* flag, const int* qtile_flag, double* S_out,
                              double* bound_out, Workspace& ws, hipStream_t st) {
   const int64_t m_pad = qo.rows_pad, m = qo.rows;
-  double *pmax = nullptr, *p2 = nullptr, *shift = nullptr;
+  double *p2 = nullptr, *shift = nullptr;
   float* off2 = nullptr;
-  STAG_TRY(ws.alloc(&pmax, (size_t)P * m_pad));
   STAG_TRY(ws.alloc(&p2, (size_t)P * m_pad));
   STAG_TRY(ws.alloc(&shift, (size_t)m_pad));
   STAG_TRY(ws.alloc(&off2, (size_t)m_pad));
-  TileExtra exm;
-  exm.max_pass = 1;
-  exm.qtile_active = qtile_flag;
-  STAG_TRY(launch_exact_tiles(xo, qo, pmax, exm, st));
-  hipLaunchKernelGGL(rescue_shift, dim3((unsigned)ceil_div(m_pad, 256)), dim3(256), 0, st, pmax, P, m_pad, m, flag,
-                     qo.nrm, -a_tile * kLog2e, qo.off, off2, shift);
-  STAG_TRY(check_launch("rescue_shift"));
+  STAG_TRY(rescue_offsets(xo, qo, P, a_tile, 0, flag, qtile_flag, off2, shift, ws, st));
   Operands q2 = qo;
   q2.off = off2;
   TileExtra exs;
@@ -393,6 +383,21 @@ stag_status rescue_underflow(const Operands& xo, const Operands& qo, int P, doub
 }
 
 }  // namespace
+
+stag_status rescue_offsets(const Operands& xo, const Operands& qo, int P, double a_tile, int self, const int* flag,
+                           const int* qtile_flag, float* off2, double* shift, Workspace& ws, hipStream_t st) {
+  const int64_t m_pad = qo.rows_pad, m = qo.rows;
+  double* pmax = nullptr;
+  STAG_TRY(ws.alloc(&pmax, (size_t)P * m_pad));
+  TileExtra exm;
+  exm.max_pass = 1;
+  exm.self = self;
+  exm.qtile_active = qtile_flag;
+  STAG_TRY(launch_exact_tiles(xo, qo, pmax, exm, st));
+  hipLaunchKernelGGL(rescue_shift, dim3((unsigned)ceil_div(m_pad, 256)), dim3(256), 0, st, pmax, P, m_pad, m, flag,
+                     qo.nrm, -a_tile * kLog2e, qo.off, off2, shift);
+  return check_launch("rescue_shift");
+}
 
 stag_status reduce_with_rescue(const double* partial, int P, const Operands& qo, const Operands& xo, double a_tile,
                                double scale, const BoundModel& bm, double* S_out, double* bound_out, Workspace& ws,

@@ -59,6 +59,15 @@ constexpr int kModeMax = 4;
 // arithmetic as kModeGauss, a kernel of its own so that traces and timers
 // tell it apart from the tiles it repeats).
 constexpr int kModeGaussRescue = 5;
+// kModeGaussExtraRescue: kModeGaussExtra (diagonal drop, tile sums) in the
+// rescue's second pass of the edge sampler's self pass, a kernel of its own.
+constexpr int kModeGaussExtraRescue = 6;
+// modes with the TileExtra outputs (self, tp), and modes that need the true
+// row and column bases of a tile in the epilogue
+template <int MODE>
+constexpr bool kExtraMode = MODE == kModeGaussExtra || MODE == kModeGaussExtraRescue;
+template <int MODE>
+constexpr bool kBasedMode = kExtraMode<MODE> || MODE == kModeMax;
 
 // Per-lane accumulation across tiles: fp64 sum, or the maximum in kModeMax.
 template <int MODE>
@@ -73,7 +82,8 @@ __device__ inline double acc_add(double acc, double v) {
 
 template <int MODE>
 __device__ inline float kernel_value(float e) {
-  if constexpr (MODE == kModeGauss || MODE == kModeGaussExtra || MODE == kModeGaussRescue) {
+  if constexpr (MODE == kModeGauss || MODE == kModeGaussExtra || MODE == kModeGaussRescue ||
+                MODE == kModeGaussExtraRescue) {
     return __builtin_amdgcn_exp2f(e);
   } else {
     const float ne = -e;
@@ -171,11 +181,17 @@ template <int MODE>
 __device__ inline float tile_epilogue(const f32x16& c, int64_t row_base, int64_t col_base, int r32, int h,
                                       int64_t qi, const TileExtra& ex, TileSums8* grp = nullptr,
                                       bool last = false, NearRec* nr = nullptr, int tile_rel = 0) {
-  constexpr bool EXTRA = MODE == kModeGaussExtra;
+  constexpr bool EXTRA = kExtraMode<MODE>;
   float cp[16];
 #pragma unroll
   for (int i = 0; i < 16; ++i) cp[i] = c[i];
   if constexpr (MODE == kModeMax) {
+    if (ex.self && row_base == col_base) {  // a data set against itself: leave out the diagonal
+      const int idg = 4 * (r32 >> 3) + (r32 & 3);
+      const bool mine = h == ((r32 & 7) >> 2);
+#pragma unroll
+      for (int i = 0; i < 16; ++i) cp[i] = (mine && i == idg) ? kPadOffset : cp[i];
+    }
     float mx = cp[0];
 #pragma unroll
     for (int i = 1; i < 16; ++i) mx = fmaxf(mx, cp[i]);
@@ -313,7 +329,7 @@ __global__ __launch_bounds__(256, 2) void tile_f32(const float* __restrict__ Xp,
   auto step = [&](int t, const f32x16& cdone, f32x16& cnew) {
     const int buf = t & 1;
     __syncthreads();
-    if constexpr (MODE == kModeGaussExtra) {
+    if constexpr (kBasedMode<MODE>) {
       if (t > 0)
         acc = acc_add<MODE>(acc, (double)tile_epilogue<MODE>(cdone, row0 + (int64_t)(t - 1) * kTileRows, col_base, r32, h, qi, ex, &grp));
     } else if constexpr (MODE == kModeExponential) {
@@ -457,7 +473,7 @@ __global__ __launch_bounds__(256, 2) void tile_split(
   auto step = [&](int t, const f32x16& cdone, f32x16& cnew) {
     const int buf = t & 1;
     __syncthreads();
-    if constexpr (MODE == kModeGaussExtra) {
+    if constexpr (kBasedMode<MODE>) {
       if (t > 0)
         acc = acc_add<MODE>(acc, (double)tile_epilogue<MODE>(cdone, row0 + (int64_t)(t - 1) * kTileRows, col_base, r32, h, qi, ex, &grp));
     } else if constexpr (MODE == kModeExponential) {
@@ -608,7 +624,7 @@ inline const char* rescue_timer(const TileExtra& ex, const char* name) {
 // Epilogue mode of a launch (kernel function, TileExtra outputs).
 inline int tile_mode(const TileExtra& ex) {
   if (ex.max_pass) return kModeMax;
-  if (ex.qtile_active) return kModeGaussRescue;
+  if (ex.qtile_active) return (ex.self || ex.tp) ? kModeGaussExtraRescue : kModeGaussRescue;
   if (ex.kernel == STAG_KERNEL_EXPONENTIAL) return kModeExponential;
   if (ex.kernel == STAG_KERNEL_LOGISTIC) return kModeLogistic;
   return (ex.self || ex.tp) ? kModeGaussExtra : kModeGauss;
@@ -724,5 +740,7 @@ stag_status launch_tiles_max(const Operands& xo, const Operands& qo, double* par
                              hipStream_t st);
 stag_status launch_tiles_gauss_rescue(const Operands& xo, const Operands& qo, double* partial, const TileExtra& ex,
                                       hipStream_t st);
+stag_status launch_tiles_gauss_extra_rescue(const Operands& xo, const Operands& qo, double* partial,
+                                            const TileExtra& ex, hipStream_t st);
 
 }  // namespace stag

@@ -47,8 +47,11 @@ __device__ inline double scan64(double v) {
 
 // rest_i (chunk order) and a node-major copy of the chunk sums, so that a
 // draw reads its node's P sums from consecutive addresses.
+// A row whose sum is below kRescueBelow sets flag[i] and the flag of its
+// query tile of qtile_rows rows (underflow rescue).
 __global__ void row_rest(const double* __restrict__ partial, int P, int64_t m_pad, int64_t n,
-                         double* __restrict__ rest, double* __restrict__ deg, double* __restrict__ chunk_t) {
+                         double* __restrict__ rest, double* __restrict__ deg, double* __restrict__ chunk_t,
+                         int* __restrict__ flag, int* __restrict__ qtile_flag, int qtile_rows) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   double s = 0.0;
@@ -59,6 +62,36 @@ __global__ void row_rest(const double* __restrict__ partial, int P, int64_t m_pa
   }
   rest[i] = s;
   if (deg) deg[i] = 1.0 + s;
+  if (flag && s < kRescueBelow) {
+    flag[i] = 1;
+    qtile_flag[i / qtile_rows] = 1;
+  }
+}
+
+// Rows of the rescue's second self pass: a flagged row takes its shifted
+// chunk sums (the draws use them and the shifted total rest_draw), and its
+// true total rest = rest_draw 2^{m_i} for the weights and degrees; other rows
+// keep rest_draw = rest.
+__global__ void rescue_rows(const double* __restrict__ partial, int P, int64_t m_pad, int64_t n,
+                            const int* __restrict__ flag, const double* __restrict__ shift,
+                            double* __restrict__ rest, double* __restrict__ rest_draw, double* __restrict__ deg,
+                            double* __restrict__ chunk_t) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  if (!flag[i]) {
+    rest_draw[i] = rest[i];
+    return;
+  }
+  double s = 0.0;
+  for (int p = 0; p < P; ++p) {
+    const double v = partial[(int64_t)p * m_pad + i];
+    chunk_t[i * P + p] = v;
+    s += v;
+  }
+  rest_draw[i] = s;
+  const double t = s * exp2(shift[i]);
+  rest[i] = t;
+  if (deg) deg[i] = 1.0 + t;
 }
 
 // Inverts a cumulative sum over `count` values v(k) (k ascending, fetched by
@@ -93,8 +126,11 @@ __device__ inline int invert_level(int count, double target, Fetch&& fetch, doub
 __global__ __launch_bounds__(256) void draw_exact(const float* __restrict__ X, int64_t n, int d, double a, int s,
                                                   uint64_t seed, int P, int64_t m_pad, int64_t ntile, int64_t tstride,
                                                   const double* __restrict__ chunk_t, const float* __restrict__ tp,
-                                                  const double* __restrict__ rest, int vec4, int64_t* __restrict__ src,
-                                                  int64_t* __restrict__ dst, double* __restrict__ w) {
+                                                  const double* __restrict__ rest,
+                                                  const double* __restrict__ rest_draw,
+                                                  const double* __restrict__ shift, int vec4,
+                                                  int64_t* __restrict__ src, int64_t* __restrict__ dst,
+                                                  double* __restrict__ w) {
   const int lane = threadIdx.x & 63;
   const int64_t e = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (e >= n * s) return;
@@ -102,9 +138,12 @@ __global__ __launch_bounds__(256) void draw_exact(const float* __restrict__ X, i
   const int r = (int)(e % s);
   uint64_t ds = mixs(mixs(mixs(seed ^ kTagDrawS) ^ (uint64_t)i) ^ 0ULL);
   const double u = (double)(mixs(ds + (uint64_t)(r + 1) * kGammaS) >> 11) * 0x1.0p-53;
-  const double tot = rest[i];
+  // rest_draw: the total in the scale of the chunk and tile sums (2^{-m_i}
+  // times the true one for a row of the underflow rescue, else the same)
+  const double tot = rest_draw[i];
+  const double kscale = exp2(-shift[i]);  // 1 for rows without a shift
   int64_t pick = -1;
-  if (tot > 0.0) {
+  if (rest[i] > 0.0 && tot > 0.0) {
     double resid = 0.0;
     const int c = invert_level(P, u * tot, [&](int k) { return chunk_t[i * P + k]; }, &resid);
     if (c >= 0) {
@@ -145,7 +184,7 @@ __global__ __launch_bounds__(256) void draw_exact(const float* __restrict__ X, i
           }
         }
         D += __shfl_xor(D, 32);
-        const double kv = (lane < 32 && live) ? exp(-a * D) : 0.0;
+        const double kv = (lane < 32 && live) ? exp(-a * D) * kscale : 0.0;
         double resid3 = 0.0;
         const int jl = invert_level(32, resid2, [&](int) { return kv; }, &resid3);  // lane k owns row k
         if (jl >= 0) pick = rb + jl;
@@ -181,13 +220,36 @@ stag_status sample_exact(const float* X, int64_t n, int d, double a, int form, i
   ex.tp = tp;
   ex.ntile = tstride;
   STAG_TRY(launch_exact_tiles(xo, qo, partial, ex, st));
+  // underflow rescue: rows whose sum is below kRescueBelow get their
+  // exponents shifted by their maximum over the other rows and a second self
+  // pass (over their 128-row tiles only; other workgroups return at once)
+  const int64_t nqt = qo.rows_pad / query_tile_rows();
+  int *flag = nullptr, *qflag = nullptr;
+  double *rest_draw = nullptr, *shift = nullptr;
+  float* off2 = nullptr;
+  STAG_TRY(ws.alloc(&flag, (size_t)n));
+  STAG_TRY(ws.alloc(&qflag, (size_t)nqt));
+  STAG_TRY(ws.alloc(&rest_draw, (size_t)n));
+  STAG_TRY(ws.alloc(&shift, (size_t)qo.rows_pad));
+  STAG_TRY(ws.alloc(&off2, (size_t)qo.rows_pad));
+  STAG_HIP(hipMemsetAsync(flag, 0, (size_t)n * sizeof(int), st));
+  STAG_HIP(hipMemsetAsync(qflag, 0, (size_t)nqt * sizeof(int), st));
   hipLaunchKernelGGL(row_rest, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, st, partial, P, qo.rows_pad, n, rest,
-                     deg_out, chunk_t);
+                     deg_out, chunk_t, flag, qflag, (int)query_tile_rows());
   STAG_TRY(check_launch("row_rest"));
+  STAG_TRY(rescue_offsets(xo, qo, P, a, 1, flag, qflag, off2, shift, ws, st));
+  Operands q2 = qo;
+  q2.off = off2;
+  TileExtra exr = ex;
+  exr.qtile_active = qflag;
+  STAG_TRY(launch_exact_tiles(xo, q2, partial, exr, st));
+  hipLaunchKernelGGL(rescue_rows, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, st, partial, P, qo.rows_pad, n,
+                     flag, shift, rest, rest_draw, deg_out, chunk_t);
+  STAG_TRY(check_launch("rescue_rows"));
   const int vec4 = (d % 4 == 0) && (reinterpret_cast<uintptr_t>(X) % 16 == 0);
   ScopedTimer tm("simgraph_draw_exact", st);
   hipLaunchKernelGGL(draw_exact, dim3((unsigned)ceil_div(n * s, 4)), dim3(256), 0, st, X, n, d, a, s, seed, P,
-                     qo.rows_pad, ntile, tstride, chunk_t, tp, rest, vec4, src, dst, w);
+                     qo.rows_pad, ntile, tstride, chunk_t, tp, rest, rest_draw, shift, vec4, src, dst, w);
   return check_launch("draw_exact");
 }
 

@@ -65,6 +65,39 @@ def test_exact_mode_config1(stag, orc, form, tol):
     assert np.allclose(w[ok], ow[ok], rtol=tol)
 
 
+@pytest.mark.parametrize("form", ["fp32", "fp16_split"])
+def test_exact_mode_small_densities(stag, orc, form):
+    # 40 outliers far from a cluster and from each other: their rows' kernel
+    # values (~1e-125) lie below the fp32 range of the tile's terms and take
+    # the underflow rescue; their draws and weights match the oracle's
+    rng = np.random.default_rng(77)
+    d = 8
+    main = rng.normal(size=(2000, d))
+    out = 20.0 + 6.0 * rng.normal(size=(40, d))
+    X = np.concatenate([main, out]).astype(np.float32)
+    a, s, seed, tol = 0.5, 8, 23, 1e-4
+    announce(f"simgraph exact small densities n={len(X)} d={d} form={form}")
+    src, dst, w, deg = _gpu(stag, X, a, s, mode="exact", form=form, seed=seed)
+    osrc, odst, ow, odeg, mg = orc.simgraph_exact(X, a, s, seed, return_margin=True)
+    assert np.array_equal(src, osrc)
+    rows = np.arange(2000, len(X))
+    orest = np.array([np.sum(np.delete(orc.kernel_row(X, a, i), i)) for i in rows])
+    assert np.sum(orest < 2.0 ** -60) >= 30 and np.all(orest > 1e-300)  # the case is exercised
+    same = dst == odst
+    firm = mg > tol
+    assert np.all(same[firm]), np.nonzero(firm & ~same)[0][:10]
+    _check_valid_draws(orc, X, a, s, seed, src, dst, np.nonzero(~same)[0], tol)
+    assert np.all(dst != src) and np.all(dst >= 0)
+    assert np.allclose(w[same], ow[same], rtol=tol)
+    e_out = np.arange(2000 * s, len(X) * s)
+    werr = np.abs(w[e_out] - ow[e_out]) / ow[e_out]
+    print(f"[measured] small densities {form}: outlier draws equal {np.mean(same[e_out]):.3f}, "
+          f"max weight rel err {werr.max():.3e}", flush=True)
+    # relative, since the weights are ~1e-60: the expanded distance at
+    # ||x||^2 ~ 3000 gives ~5e-4 (the exponent's error grows with the norms)
+    assert werr.max() <= 5e-3, werr.max()
+
+
 def test_exact_mode_wide_rows(stag, orc):
     """d = 784 (the wide fp32 tile), sparse non-negative data, a = 1e-3."""
     X = synth.sparse_uniform(3000, 784, 1004)
