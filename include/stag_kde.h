@@ -138,6 +138,9 @@ stag_status stag_kde_exact(const float* X, int64_t n, const float* Q, int64_t m,
  * lambda = (a log2 e)^2 for the exponential and logistic kernels, and takes
  * y = sqrt(max(-E, 0)) = a r log2(e); FP16_SPLIT then needs
  * |2 (a log2 e)^2 q_j| below 65504.
+ * Small densities: as in stag_kde_exact, a sum below 2^-60 is recomputed
+ * on the device, here with each term taken as 2^{ys - y}, ys the query's
+ * smallest y (from a max pass), and S = sum * 2^{-ys}.
  * Exponential kernel, near pairs: where the computed -E is below 1/4
  * (a r < 1/(2 log2 e), kernel value above 2^-1/2) an error dE in the
  * exponent would move y by up to sqrt(dE); those terms are taken out of the

@@ -44,15 +44,16 @@ struct BoundModel {
   double near_y2 = 0.0;  // exponential kernel: terms with computed y^2 below this are exact
 };
 
-// extra: a further offset magnitude carried by the accumulators (the shift
-// |m_q| of an underflow-rescued query, in exponent units).
+// extra (underflow rescue): Gaussian, a further offset magnitude carried by
+// the accumulators (the shift |m_q|, in exponent units); exponential and
+// logistic, the shift ys of y = sqrt(-E) (terms up to y = 150 + ys count).
 __host__ __device__ inline double relative_bound(const BoundModel& bm, double qn, double xm, double extra = 0.0) {
   const double ln2 = 0.69314718055994530942;
   const double cross = 2.0 * bm.la * sqrt(qn) * sqrt(xm);
-  const double offs = bm.la * (qn + xm) + extra;
+  const double offs = bm.la * (qn + xm) + (bm.kern == 0 ? extra : 0.0);
   const double dE = bm.c_acc * (cross + offs) + bm.c_split * cross + bm.c_off * offs;
   if (bm.kern == 0) return expm1(ln2 * dE) + bm.c_tail;
-  const double dy = 0x1.0p-23 * fmin(150.0, sqrt(bm.la) * (sqrt(qn) + sqrt(xm)));
+  const double dy = 0x1.0p-23 * fmin(150.0 + extra, sqrt(bm.la) * (sqrt(qn) + sqrt(xm)));
   if (bm.kern == 1) {
     // A term left to the tile has computed y^2 >= near_y2, so its true y^2 is
     // >= near_y2 - dE and |dy| <= dE / (2 sqrt(near_y2 - dE)); without that
@@ -93,6 +94,9 @@ struct TileExtra {
   // are not written).
   int max_pass = 0;
   const int* qtile_active = nullptr;
+  // exponential / logistic in the rescue's second pass: per query the shift
+  // ys (smallest y = sqrt(-E)); the terms are 2^{ys - y}
+  const float* yshift = nullptr;
 };
 
 int exact_padded_dim(int d);  // 0 if unsupported

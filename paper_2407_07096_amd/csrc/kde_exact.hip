@@ -279,6 +279,8 @@ stag_status launch_exact_tiles(const Operands& xo, const Operands& qo, double* p
     case tiles::kModeMax: return launch_tiles_max(xo, qo, partial, ex, st);
     case tiles::kModeGaussRescue: return launch_tiles_gauss_rescue(xo, qo, partial, ex, st);
     case tiles::kModeGaussExtraRescue: return launch_tiles_gauss_extra_rescue(xo, qo, partial, ex, st);
+    case tiles::kModeExpShift: return launch_tiles_exp_shift(xo, qo, partial, ex, st);
+    case tiles::kModeLogShift: return launch_tiles_log_shift(xo, qo, partial, ex, st);
     case tiles::kModeGauss: return launch_tiles_gauss(xo, qo, partial, ex, st);
     case tiles::kModeGaussExtra: return launch_tiles_gauss_extra(xo, qo, partial, ex, st);
     case tiles::kModeExponential: return launch_tiles_exponential(xo, qo, partial, ex, st);
@@ -382,6 +384,37 @@ stag_status rescue_underflow(const Operands& xo, const Operands& qo, int P, doub
   return check_launch("rescue_reduce");
 }
 
+// Exponential and logistic kernels: ys = sqrt(-max E) of each flagged
+// query (its smallest y), 0 otherwise.
+__global__ void rescue_yshift(const double* __restrict__ pmax, int P, int64_t m_pad, int64_t m,
+                              const int* __restrict__ flag, float* __restrict__ yshift) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= m_pad) return;
+  float ys = 0.0f;
+  if (q < m && flag[q]) {
+    double mq = -HUGE_VAL;
+    for (int p = 0; p < P; ++p) mq = fmax(mq, pmax[(int64_t)p * m_pad + q]);
+    ys = (float)sqrt(fmax(-mq, 0.0));
+  }
+  yshift[q] = ys;
+}
+
+__global__ void rescue_reduce_y(const double* __restrict__ partial, int P, int64_t m_pad, int64_t m,
+                                const int* __restrict__ flag, const float* __restrict__ yshift, double scale,
+                                const double* __restrict__ qnrm, const unsigned long long* __restrict__ max_xnrm_bits,
+                                BoundModel bm, double* __restrict__ S_out, double* __restrict__ bound_out) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= m || !flag[q]) return;
+  double s = 0.0;
+  for (int p = 0; p < P; ++p) s += partial[(int64_t)p * m_pad + q];
+  const double ys = (double)yshift[q];
+  S_out[q] = s * exp2(-ys) * scale;
+  if (bound_out) {
+    const double xm = __longlong_as_double((long long)*max_xnrm_bits);
+    bound_out[q] = relative_bound(bm, qnrm[q], xm, ys);
+  }
+}
+
 }  // namespace
 
 stag_status rescue_offsets(const Operands& xo, const Operands& qo, int P, double a_tile, int self, const int* flag,
@@ -397,6 +430,41 @@ stag_status rescue_offsets(const Operands& xo, const Operands& qo, int P, double
   hipLaunchKernelGGL(rescue_shift, dim3((unsigned)ceil_div(m_pad, 256)), dim3(256), 0, st, pmax, P, m_pad, m, flag,
                      qo.nrm, -a_tile * kLog2e, qo.off, off2, shift);
   return check_launch("rescue_shift");
+}
+
+// launch_reduce for the exponential and logistic kernels with the underflow
+// rescue: a flagged query's terms are recomputed as 2^{ys - y}, ys its
+// smallest y (from the max pass), and S = (sum) 2^{-ys}.
+stag_status reduce_with_rescue_y(const double* partial, int P, const Operands& qo, const Operands& xo, int kernel,
+                                 double scale, const BoundModel& bm, const int* near_over, double* S_out,
+                                 double* bound_out, Workspace& ws, hipStream_t st) {
+  const int64_t m = qo.rows, m_pad = qo.rows_pad;
+  int *flag = nullptr, *qflag = nullptr;
+  STAG_TRY(ws.alloc(&flag, (size_t)m));
+  STAG_TRY(ws.alloc(&qflag, (size_t)(m_pad / kBQ)));
+  STAG_HIP(hipMemsetAsync(flag, 0, (size_t)m * sizeof(int), st));
+  STAG_HIP(hipMemsetAsync(qflag, 0, (size_t)(m_pad / kBQ) * sizeof(int), st));
+  STAG_TRY(launch_reduce(partial, P, qo, xo, scale, bm, S_out, bound_out, st, near_over, flag, qflag));
+  double *pmax = nullptr, *p2 = nullptr;
+  float* yshift = nullptr;
+  STAG_TRY(ws.alloc(&pmax, (size_t)P * m_pad));
+  STAG_TRY(ws.alloc(&p2, (size_t)P * m_pad));
+  STAG_TRY(ws.alloc(&yshift, (size_t)m_pad));
+  TileExtra exm;
+  exm.max_pass = 1;
+  exm.qtile_active = qflag;
+  STAG_TRY(launch_exact_tiles(xo, qo, pmax, exm, st));
+  hipLaunchKernelGGL(rescue_yshift, dim3((unsigned)ceil_div(m_pad, 256)), dim3(256), 0, st, pmax, P, m_pad, m, flag,
+                     yshift);
+  STAG_TRY(check_launch("rescue_yshift"));
+  TileExtra exs;
+  exs.kernel = kernel;
+  exs.qtile_active = qflag;
+  exs.yshift = yshift;
+  STAG_TRY(launch_exact_tiles(xo, qo, p2, exs, st));
+  hipLaunchKernelGGL(rescue_reduce_y, dim3((unsigned)ceil_div(m, 256)), dim3(256), 0, st, p2, P, m_pad, m, flag,
+                     yshift, scale, qo.nrm, xo.max_nrm_bits, bm, S_out, bound_out);
+  return check_launch("rescue_reduce_y");
 }
 
 stag_status reduce_with_rescue(const double* partial, int P, const Operands& qo, const Operands& xo, double a_tile,
@@ -517,7 +585,7 @@ stag_status exact_kernel_impl(const char* fn, const float* X, int64_t n, const f
   // Gaussian: sums below kRescueBelow are recomputed with shifted exponents
   if (kernel == STAG_KERNEL_GAUSSIAN)
     return reduce_with_rescue(partial, P, qo, xo, at, scale, bm, S_out, bound_out, ws, stream);
-  return launch_reduce(partial, P, qo, xo, scale, bm, S_out, bound_out, stream, ex.near_over);
+  return reduce_with_rescue_y(partial, P, qo, xo, kernel, scale, bm, ex.near_over, S_out, bound_out, ws, stream);
 }
 
 }  // namespace

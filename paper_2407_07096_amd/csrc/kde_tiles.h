@@ -68,6 +68,14 @@ template <int MODE>
 constexpr bool kExtraMode = MODE == kModeGaussExtra || MODE == kModeGaussExtraRescue;
 template <int MODE>
 constexpr bool kBasedMode = kExtraMode<MODE> || MODE == kModeMax;
+// kModeExpShift, kModeLogShift: the exponential and logistic kernels in the
+// rescue's second pass, with each query's terms scaled by 2^{ys}, ys = the
+// smallest y = sqrt(-E) of the query (TileExtra::yshift): the largest term
+// becomes about 1 and the sum is multiplied by 2^{-ys} afterwards.
+constexpr int kModeExpShift = 7;
+constexpr int kModeLogShift = 8;
+template <int MODE>
+constexpr bool kShiftMode = MODE == kModeExpShift || MODE == kModeLogShift;
 
 // Per-lane accumulation across tiles: fp64 sum, or the maximum in kModeMax.
 template <int MODE>
@@ -81,10 +89,20 @@ __device__ inline double acc_add(double acc, double v) {
 }
 
 template <int MODE>
-__device__ inline float kernel_value(float e) {
+__device__ inline float kernel_value(float e, float ys = 0.0f) {
   if constexpr (MODE == kModeGauss || MODE == kModeGaussExtra || MODE == kModeGaussRescue ||
                 MODE == kModeGaussExtraRescue) {
     return __builtin_amdgcn_exp2f(e);
+  } else if constexpr (kShiftMode<MODE>) {
+    const float ne = -e;
+    const float y = __builtin_amdgcn_sqrtf(ne < 0.0f ? 0.0f : ne);
+    const float ts = __builtin_amdgcn_exp2f(ys - y);  // 2^{ys} t
+    if constexpr (MODE == kModeExpShift) {
+      return ts;
+    } else {
+      const float u = 1.0f + __builtin_amdgcn_exp2f(-y);
+      return 4.0f * ts * __builtin_amdgcn_rcpf(u * u);
+    }
   } else {
     const float ne = -e;
     const float t = __builtin_amdgcn_exp2f(-__builtin_amdgcn_sqrtf(ne < 0.0f ? 0.0f : ne));
@@ -100,10 +118,10 @@ __device__ inline float kernel_value(float e) {
 // Kernel values of one 32x32 accumulator tile held by a lane (16 exponents),
 // summed as a balanced tree in fp32.
 template <int MODE>
-__device__ inline float kernel_tile_sum(const float* c) {
+__device__ inline float kernel_tile_sum(const float* c, float ys = 0.0f) {
   float k[16];
 #pragma unroll
-  for (int i = 0; i < 16; ++i) k[i] = kernel_value<MODE>(c[i]);
+  for (int i = 0; i < 16; ++i) k[i] = kernel_value<MODE>(c[i], ys);
 #pragma unroll
   for (int w = 8; w > 0; w >>= 1)
 #pragma unroll
@@ -180,7 +198,8 @@ __device__ inline double near_finish(const TileExtra& ex, const NearRec& nr, int
 template <int MODE>
 __device__ inline float tile_epilogue(const f32x16& c, int64_t row_base, int64_t col_base, int r32, int h,
                                       int64_t qi, const TileExtra& ex, TileSums8* grp = nullptr,
-                                      bool last = false, NearRec* nr = nullptr, int tile_rel = 0) {
+                                      bool last = false, NearRec* nr = nullptr, int tile_rel = 0,
+                                      float ys = 0.0f) {
   constexpr bool EXTRA = kExtraMode<MODE>;
   float cp[16];
 #pragma unroll
@@ -228,7 +247,7 @@ __device__ inline float tile_epilogue(const f32x16& c, int64_t row_base, int64_t
       }
     }
   }
-  const float s = kernel_tile_sum<MODE>(cp);
+  const float s = kernel_tile_sum<MODE>(cp, ys);
   if constexpr (EXTRA) {
     if (ex.tp) {
       const float o = __shfl_xor(s, 32);
@@ -299,6 +318,7 @@ __global__ __launch_bounds__(256, 2) void tile_f32(const float* __restrict__ Xp,
     }
   }
   const float aq = alpha[qi];
+  const float ys = kShiftMode<MODE> ? ex.yshift[qi] : 0.0f;
 
   const int64_t row0 = (int64_t)chunk * kChunkRows;
   const int64_t rem = (n_pad - row0) / kTileRows;
@@ -335,7 +355,7 @@ __global__ __launch_bounds__(256, 2) void tile_f32(const float* __restrict__ Xp,
     } else if constexpr (MODE == kModeExponential) {
       acc = acc_add<MODE>(acc, (double)tile_epilogue<MODE>(cdone, 0, 0, r32, h, qi, ex, nullptr, false, &nr, t - 1));
     } else {
-      acc = acc_add<MODE>(acc, (double)tile_epilogue<MODE>(cdone, 0, 0, r32, h, qi, ex));
+      acc = acc_add<MODE>(acc, (double)tile_epilogue<MODE>(cdone, 0, 0, r32, h, qi, ex, nullptr, false, nullptr, 0, ys));
     }
     const float* arow = &tile[buf][r32 * LD + h * H];
     // the accumulators start from the offsets alpha_q + beta_x of their pairs
@@ -382,7 +402,7 @@ __global__ __launch_bounds__(256, 2) void tile_f32(const float* __restrict__ Xp,
     ca = cb;
   }
   acc = acc_add<MODE>(acc, (double)tile_epilogue<MODE>(ca, row0 + (int64_t)(ntiles - 1) * kTileRows, col_base, r32, h, qi, ex, &grp,
-                                    true, &nr, ntiles - 1));
+                                    true, &nr, ntiles - 1, ys));
   if constexpr (MODE == kModeExponential) acc += near_finish(ex, nr, qi, h, row0, tid);
   const double other = __shfl_down(acc, 32);
   if (h == 0) partial[(int64_t)chunk * m_pad + qi] = acc_add<MODE>(acc, other);
@@ -438,6 +458,7 @@ __global__ __launch_bounds__(256, 2) void tile_split(
     for (int s = 0; s < KS; ++s)
       bq[p][s] = *reinterpret_cast<const u16x8*>(Qp[p] + qi * DP + s * 16 + h * 8);
   const float alpha = Qoff[qi];
+  const float ys = kShiftMode<MODE> ? ex.yshift[qi] : 0.0f;
 
   const int64_t row0 = (int64_t)chunk * kChunkRows;
   const int64_t rem = (n_pad - row0) / kTileRows;
@@ -479,7 +500,7 @@ __global__ __launch_bounds__(256, 2) void tile_split(
     } else if constexpr (MODE == kModeExponential) {
       acc = acc_add<MODE>(acc, (double)tile_epilogue<MODE>(cdone, 0, 0, r32, h, qi, ex, nullptr, false, &nr, t - 1));
     } else {
-      acc = acc_add<MODE>(acc, (double)tile_epilogue<MODE>(cdone, 0, 0, r32, h, qi, ex));
+      acc = acc_add<MODE>(acc, (double)tile_epilogue<MODE>(cdone, 0, 0, r32, h, qi, ex, nullptr, false, nullptr, 0, ys));
     }
     // the accumulators start from the offsets alpha_q + beta_x of their pairs
     f32x16 c;
@@ -533,7 +554,7 @@ __global__ __launch_bounds__(256, 2) void tile_split(
     ca = cb;
   }
   acc = acc_add<MODE>(acc, (double)tile_epilogue<MODE>(ca, row0 + (int64_t)(ntiles - 1) * kTileRows, col_base, r32, h, qi, ex, &grp,
-                                    true, &nr, ntiles - 1));
+                                    true, &nr, ntiles - 1, ys));
   if constexpr (MODE == kModeExponential) acc += near_finish(ex, nr, qi, h, row0, tid);
   const double other = __shfl_down(acc, 32);
   if (h == 0) partial[(int64_t)chunk * m_pad + qi] = acc_add<MODE>(acc, other);
@@ -571,6 +592,7 @@ __global__ __launch_bounds__(256) void tile_f32_wide(const float* __restrict__ X
   }
   __syncthreads();
   const float baug = h == 0 ? alpha[qi] : 1.0f;
+  const float ys = kShiftMode<MODE> ? ex.yshift[qi] : 0.0f;
   const int64_t row0 = (int64_t)chunk * kChunkRows;
   const int64_t rem = (n_pad - row0) / kTileRows;
   const int ntiles = (int)(rem < kChunkRows / kTileRows ? rem : kChunkRows / kTileRows);
@@ -602,7 +624,7 @@ __global__ __launch_bounds__(256) void tile_f32_wide(const float* __restrict__ X
     }
     const float tb = beta[rb + r32];
     c = __builtin_amdgcn_mfma_f32_32x32x2f32(h == 0 ? 1.0f : tb, baug, c, 0, 0, 0);
-    acc = acc_add<MODE>(acc, (double)tile_epilogue<MODE>(c, rb, col_base, r32, h, qi, ex, nullptr, false, &nr, t));
+    acc = acc_add<MODE>(acc, (double)tile_epilogue<MODE>(c, rb, col_base, r32, h, qi, ex, nullptr, false, &nr, t, ys));
   }
   if constexpr (MODE == kModeExponential) acc += near_finish(ex, nr, qi, h, row0, tid);
   const double other = __shfl_down(acc, 32);
@@ -624,7 +646,11 @@ inline const char* rescue_timer(const TileExtra& ex, const char* name) {
 // Epilogue mode of a launch (kernel function, TileExtra outputs).
 inline int tile_mode(const TileExtra& ex) {
   if (ex.max_pass) return kModeMax;
-  if (ex.qtile_active) return (ex.self || ex.tp) ? kModeGaussExtraRescue : kModeGaussRescue;
+  if (ex.qtile_active) {
+    if (ex.kernel == STAG_KERNEL_EXPONENTIAL) return kModeExpShift;
+    if (ex.kernel == STAG_KERNEL_LOGISTIC) return kModeLogShift;
+    return (ex.self || ex.tp) ? kModeGaussExtraRescue : kModeGaussRescue;
+  }
   if (ex.kernel == STAG_KERNEL_EXPONENTIAL) return kModeExponential;
   if (ex.kernel == STAG_KERNEL_LOGISTIC) return kModeLogistic;
   return (ex.self || ex.tp) ? kModeGaussExtra : kModeGauss;
@@ -742,5 +768,9 @@ stag_status launch_tiles_gauss_rescue(const Operands& xo, const Operands& qo, do
                                       hipStream_t st);
 stag_status launch_tiles_gauss_extra_rescue(const Operands& xo, const Operands& qo, double* partial,
                                             const TileExtra& ex, hipStream_t st);
+stag_status launch_tiles_exp_shift(const Operands& xo, const Operands& qo, double* partial, const TileExtra& ex,
+                                   hipStream_t st);
+stag_status launch_tiles_log_shift(const Operands& xo, const Operands& qo, double* partial, const TileExtra& ex,
+                                   hipStream_t st);
 
 }  // namespace stag

@@ -190,3 +190,32 @@ def test_full_size_sampled(stag, orc, kernel):
     err = rel_err(S[idx], ref)
     assert np.all(err <= B[idx]), (err.max(), B[idx].min())
     assert err.max() <= MEASURED[kernel], err.max()
+
+
+@pytest.mark.parametrize("kernel", KERNELS)
+@pytest.mark.parametrize("form", ["fp32", "fp16_split"])
+def test_small_densities(stag, orc, kernel, form):
+    # queries 60-150 away at a = 2: e^{-a r} between ~1e-52 and ~1e-130, below
+    # the fp32 range of the tile's terms (y = a r log2 e > 149): the rescue
+    # recomputes them as 2^{ys - y} (ys the query's smallest y) and scales by
+    # 2^{-ys}; near queries in the same batch are untouched (bit-identical)
+    rng = np.random.default_rng(53)
+    d = 16
+    X = rng.normal(size=(3000, d)).astype(np.float32)
+    near = (X[:100] + 0.2 * rng.normal(size=(100, d))).astype(np.float32)
+    dirs = rng.normal(size=(60, d))
+    dirs /= np.linalg.norm(dirs, axis=1, keepdims=True)
+    far = (dirs * rng.uniform(60.0, 150.0, size=(60, 1))).astype(np.float32)
+    Q = np.concatenate([near, far]).astype(np.float32)
+    a = 2.0
+    announce(f"kernel={kernel} small densities m={len(Q)} d={d} a={a} form={form}")
+    ref = orc.kde_kernel(X, Q, a, kernel)
+    S, B = _run(stag, X, Q, a, form, kernel)
+    assert np.sum(ref < 1e-45) > 30  # the case is exercised
+    err = rel_err(S, ref)
+    print(f"[measured] {kernel} {form} small densities: min {ref.min():.3e}, max rel err {err.max():.3e}",
+          flush=True)
+    assert np.all(err <= B), (err.max(), B.min())
+    assert err.max() <= 1e-4, err.max()
+    Sn, _ = _run(stag, X, near, a, form, kernel)
+    assert np.array_equal(Sn, S[:100])
