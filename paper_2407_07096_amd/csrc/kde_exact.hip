@@ -247,7 +247,7 @@ stag_status prepare_operands(int form, const float* src, int64_t rows, int d, do
   out->max_nrm_bits = nullptr;
   if (!is_query) {
     STAG_TRY(ws.alloc(&out->max_nrm_bits, 1));
-    STAG_HIP(hipMemsetAsync(out->max_nrm_bits, 0, sizeof(unsigned long long), st));
+    STAG_TRY(zero_async(out->max_nrm_bits, sizeof(unsigned long long), st));
   }
   const double scale = is_query ? 2.0 * a * kLog2e : 1.0;
   return prep_any(form, src, rows, d, dp, rows_pad, scale, -a * kLog2e, is_query ? 1 : 0, out->part, out->off,
@@ -442,8 +442,8 @@ stag_status reduce_with_rescue_y(const double* partial, int P, const Operands& q
   int *flag = nullptr, *qflag = nullptr;
   STAG_TRY(ws.alloc(&flag, (size_t)m));
   STAG_TRY(ws.alloc(&qflag, (size_t)(m_pad / kBQ)));
-  STAG_HIP(hipMemsetAsync(flag, 0, (size_t)m * sizeof(int), st));
-  STAG_HIP(hipMemsetAsync(qflag, 0, (size_t)(m_pad / kBQ) * sizeof(int), st));
+  STAG_TRY(zero_async(flag, (size_t)m * sizeof(int), st));
+  STAG_TRY(zero_async(qflag, (size_t)(m_pad / kBQ) * sizeof(int), st));
   STAG_TRY(launch_reduce(partial, P, qo, xo, scale, bm, S_out, bound_out, st, near_over, flag, qflag));
   double *pmax = nullptr, *p2 = nullptr;
   float* yshift = nullptr;
@@ -474,8 +474,8 @@ stag_status reduce_with_rescue(const double* partial, int P, const Operands& qo,
   int *flag = nullptr, *qflag = nullptr;
   STAG_TRY(ws.alloc(&flag, (size_t)m));
   STAG_TRY(ws.alloc(&qflag, (size_t)(qo.rows_pad / kBQ)));
-  STAG_HIP(hipMemsetAsync(flag, 0, (size_t)m * sizeof(int), st));
-  STAG_HIP(hipMemsetAsync(qflag, 0, (size_t)(qo.rows_pad / kBQ) * sizeof(int), st));
+  STAG_TRY(zero_async(flag, (size_t)m * sizeof(int), st));
+  STAG_TRY(zero_async(qflag, (size_t)(qo.rows_pad / kBQ) * sizeof(int), st));
   STAG_TRY(launch_reduce(partial, P, qo, xo, scale, bm, S_out, bound_out, st, nullptr, flag, qflag));
   return rescue_underflow(xo, qo, P, a_tile, scale, bm, flag, qflag, S_out, bound_out, ws, st);
 }
@@ -577,7 +577,7 @@ stag_status exact_kernel_impl(const char* fn, const float* X, int64_t n, const f
     ex.a = a;
     ex.m_rows = m;
     STAG_TRY(ws.alloc(&ex.near_over, (size_t)m));
-    STAG_HIP(hipMemsetAsync(ex.near_over, 0, (size_t)m * sizeof(int), stream));
+    STAG_TRY(zero_async(ex.near_over, (size_t)m * sizeof(int), stream));
   }
   STAG_TRY(launch_exact_tiles(xo, qo, partial, ex, stream));
   const double scale = (flags & STAG_NORMALIZE) ? 1.0 / (double)n : 1.0;

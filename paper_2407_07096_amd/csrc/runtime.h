@@ -35,6 +35,11 @@ void clear_error();
 // Checks the launch that was just issued.
 stag_status check_launch(const char* what);
 
+// Sets `bytes` bytes at device pointer p to zero with a fill kernel on stream
+// st (in stream order; used instead of a memset where the call may be recorded
+// into a HIP graph).
+stag_status zero_async(void* p, size_t bytes, hipStream_t st);
+
 // Temporary device memory, allocated and released in stream order.
 // The current device's default stream-ordered pool keeps freed memory for
 // reuse (release threshold at the maximum) instead of returning it to the

@@ -232,8 +232,8 @@ stag_status sample_exact(const float* X, int64_t n, int d, double a, int form, i
   STAG_TRY(ws.alloc(&rest_draw, (size_t)n));
   STAG_TRY(ws.alloc(&shift, (size_t)qo.rows_pad));
   STAG_TRY(ws.alloc(&off2, (size_t)qo.rows_pad));
-  STAG_HIP(hipMemsetAsync(flag, 0, (size_t)n * sizeof(int), st));
-  STAG_HIP(hipMemsetAsync(qflag, 0, (size_t)nqt * sizeof(int), st));
+  STAG_TRY(zero_async(flag, (size_t)n * sizeof(int), st));
+  STAG_TRY(zero_async(qflag, (size_t)nqt * sizeof(int), st));
   hipLaunchKernelGGL(row_rest, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, st, partial, P, qo.rows_pad, n, rest,
                      deg_out, chunk_t, flag, qflag, (int)query_tile_rows());
   STAG_TRY(check_launch("row_rest"));
