@@ -670,10 +670,13 @@ __global__ __launch_bounds__(256) void draw_lsh(IndexView ix, LevelConst lc, con
         const int r = __ffsll((long long)pend) - 1;
         pend &= pend - 1;
         const double x = __shfl(resid, r);
-        const uint64_t over = __ballot(running + incl > x);
-        const int kl = __ffsll((long long)over) - 1;
+        // only a positive value can be the crossing (past the last positive
+        // value the tree scan may differ from it by a rounding); with none,
+        // the draw stays pending for the next block or the fallback below
+        const uint64_t over = __ballot(running + incl > x) & pos;
+        const int kl = over ? __ffsll((long long)over) - 1 : 0;
         const int32_t jj = __shfl(j, kl);
-        if (lane == r) pick = jj;
+        if (lane == r && over) pick = jj;
       }
       running += btot;
     });

@@ -111,10 +111,15 @@ __device__ inline int invert_level(int count, double target, Fetch&& fetch, doub
     const uint64_t pos = __ballot(v > 0.0);
     if (pos) last = k0 + 63 - __clzll((long long)pos);
     if (running + btot > target) {
-      const uint64_t over = __ballot(running + incl > target);
-      const int kl = __ffsll((long long)over) - 1;
-      *resid_out = target - (running + __shfl(incl - v, kl));
-      return k0 + kl;
+      // only a positive value can be the crossing: past the block's last
+      // positive value the tree scan may differ from it by a rounding, and a
+      // crossing found there means the target lies beyond this block
+      const uint64_t over = __ballot(running + incl > target) & pos;
+      if (over) {
+        const int kl = __ffsll((long long)over) - 1;
+        *resid_out = target - (running + __shfl(incl - v, kl));
+        return k0 + kl;
+      }
     }
     running += btot;
   }
