@@ -60,28 +60,29 @@ __global__ void add_offsets(uint64_t* __restrict__ out, int64_t n, const uint64_
   if (i < n) out[i] += block_off[i / kScanBlock];
 }
 
-__global__ void write_total(uint64_t* __restrict__ out, int64_t n, const uint64_t* __restrict__ block_off,
-                            int64_t nb) {
-  out[n] = block_off[nb];
+// out[n] = the grand total (the last entry of the scanned block offsets, or
+// the one block's total)
+__global__ void write_total(uint64_t* __restrict__ out, int64_t n, const uint64_t* __restrict__ total) {
+  out[n] = total[0];
 }
 
 template <typename T>
 stag_status scan_impl(const T* in, uint64_t* out, int64_t n, Workspace& ws, hipStream_t st) {
   const int64_t nb = ceil_div(n, kScanBlock);
   uint64_t* tot = nullptr;
-  uint64_t* off = nullptr;
   STAG_TRY(ws.alloc(&tot, (size_t)nb));
-  STAG_TRY(ws.alloc(&off, (size_t)nb + 1));
   hipLaunchKernelGGL(scan_blocks<T>, dim3((unsigned)nb), dim3(256), 0, st, in, n, out, tot);
   STAG_TRY(check_launch("scan_blocks"));
+  const uint64_t* total = tot;  // one block: its total is the grand total
   if (nb > 1) {
+    uint64_t* off = nullptr;
+    STAG_TRY(ws.alloc(&off, (size_t)nb + 1));
     STAG_TRY(scan_impl<uint64_t>(tot, off, nb, ws, st));
     hipLaunchKernelGGL(add_offsets, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, st, out, n, off);
     STAG_TRY(check_launch("add_offsets"));
-  } else {
-    STAG_HIP(hipMemcpyAsync(off + 1, tot, sizeof(uint64_t), hipMemcpyDeviceToDevice, st));
+    total = off + nb;
   }
-  hipLaunchKernelGGL(write_total, dim3(1), dim3(1), 0, st, out, n, off, nb);
+  hipLaunchKernelGGL(write_total, dim3(1), dim3(1), 0, st, out, n, total);
   return check_launch("write_total");
 }
 
