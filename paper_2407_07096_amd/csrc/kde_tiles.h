@@ -262,8 +262,11 @@ __device__ inline float tile_epilogue(const f32x16& c, int64_t row_base, int64_t
         for (int e = 0; e < 8; ++e) grp->v[e] = e == k ? tot : grp->v[e];
         if (k16 == 15 || last) {
           f32x4* dst = reinterpret_cast<f32x4*>(ex.tp + qi * ex.ntile + (tile & ~(int64_t)15) + 8 * h);
-          dst[0] = f32x4{grp->v[0], grp->v[1], grp->v[2], grp->v[3]};
-          dst[1] = f32x4{grp->v[4], grp->v[5], grp->v[6], grp->v[7]};
+          // streamed once and read by the draws much later: non-temporal, so
+          // that the tile sums do not evict the data tiles that the
+          // workgroups share in L2
+          __builtin_nontemporal_store(f32x4{grp->v[0], grp->v[1], grp->v[2], grp->v[3]}, dst);
+          __builtin_nontemporal_store(f32x4{grp->v[4], grp->v[5], grp->v[6], grp->v[7]}, dst + 1);
         }
       }
     }
