@@ -774,19 +774,27 @@ __global__ __launch_bounds__(256) void locate_queries(const uint64_t* __restrict
       }
       qslot[e] = slot;
     }
-    uint32_t rank = 0;
+    // group the wave's lanes by bucket (ballots only), then let every
+    // group's lowest lane take the group's ranks with one atomic, all groups
+    // in the same instruction
+    int leader_of = lane;
+    uint32_t gsize = 0, intra = 0;
     uint64_t pending = __ballot(slot >= 0);
     while (pending) {
       const int leader = __ffsll((long long)pending) - 1;
       const int32_t ls = __shfl(slot, leader);
       const uint64_t same = __ballot(slot == ls) & pending;
-      uint32_t base = 0;
-      if (lane == leader) base = atomicAdd(qcount + ls, (uint32_t)__popcll(same));
-      base = __shfl(base, leader);
-      if ((same >> lane) & 1ull) rank = base + (uint32_t)__popcll(same & ((1ull << lane) - 1ull));
+      if ((same >> lane) & 1ull) {
+        leader_of = leader;
+        intra = (uint32_t)__popcll(same & ((1ull << lane) - 1ull));
+      }
+      if (lane == leader) gsize = (uint32_t)__popcll(same);
       pending &= ~same;
     }
-    if (slot >= 0) qrank[e] = rank;
+    uint32_t base = 0;
+    if (gsize > 0) base = atomicAdd(qcount + slot, gsize);
+    base = __shfl(base, leader_of);
+    if (slot >= 0) qrank[e] = base + intra;
   }
 }
 
