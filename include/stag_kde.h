@@ -130,6 +130,30 @@ stag_status stag_kde_exact(const float* X, int64_t n, const float* Q, int64_t m,
                            double eps, int32_t form, uint32_t flags, double* S_out, double* bound_out,
                            hipStream_t stream);
 
+/* stag_kde_exact without device allocation, for callers that cannot allocate
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments and results as stag_kde_exact with the
+ * Gaussian kernel (bit for bit), except:
+ *   - form is FP32, BF16_SPLIT, FP16_SPLIT or BF16_SPLIT3 (STAG_FORM_AUTO:
+ *     STAG_E_UNSUPPORTED) and flags may hold STAG_NORMALIZE only
+ *     (STAG_CHECK_FINITE: STAG_E_UNSUPPORTED); eps is not taken;
+ *   - every temporary (prepared operands, partial sums, rescue buffers) lives
+ *     in a 128 MiB scratch array that the library holds on each device it
+ *     runs on until the process ends; a call whose temporaries do not fit is
+ *     STAG_E_INVAL before any launch (they take about
+ *     (n + m) * d_pad * 4 bytes of split operands (d_pad: d rounded up to 16,
+ *     32, 64, 96 ... 256) plus 24 * m_pad * ceil(n / 4096) bytes of partial
+ *     sums, m_pad = m rounded up to 128);
+ *   - no hipMalloc, hipFree or allocating routine is called; the first call
+ *     on a device looks up that device's scratch address once.
+ * Every call on one device shares that device's scratch: calls that overlap
+ * on one device (on different streams, or from several threads) race and
+ * give wrong results; serialise them.  The scratch keeps the last call's
+ * contents; whatever must start at zero is cleared by each call. */
+stag_status stag_kde_exact_noalloc(const float* X, int64_t n, const float* Q, int64_t m, int32_t d, double a,
+                                   int32_t form, uint32_t flags, double* S_out, double* bound_out,
+                                   hipStream_t stream);
+
 /* Exact kernel density S(q) = sum_i k(||q - x_i||) with any of the three
  * kernel functions of Sec. "Kernel Density Estimation" (stag_kernel); the
  * arguments, limits and determinism are those of stag_kde_exact, which is

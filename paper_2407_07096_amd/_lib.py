@@ -72,6 +72,8 @@ def load():
     lib.stag_e2lsh_collision_probability.argtypes = [f64, i32, i32]
     lib.stag_kde_exact.restype = C.c_int
     lib.stag_kde_exact.argtypes = [vp, i64, vp, i64, i32, f64, f64, i32, u32, vp, vp, vp]
+    lib.stag_kde_exact_noalloc.restype = C.c_int
+    lib.stag_kde_exact_noalloc.argtypes = [vp, i64, vp, i64, i32, f64, i32, u32, vp, vp, vp]
     lib.stag_kde_exact_kernel.restype = C.c_int
     lib.stag_kde_exact_kernel.argtypes = [vp, i64, vp, i64, i32, i32, f64, f64, i32, u32, vp, vp, vp]
     lib.stag_kde_random_sample.restype = C.c_int

@@ -110,6 +110,10 @@ BoundModel make_bound_model(int form, int d, double a_tile, int kernel = 0);
 
 stag_status prepare_operands(int form, const float* src, int64_t rows, int d, double a, bool is_query,
                              Workspace& ws, Operands* out, hipStream_t st);
+// The two halves of prepare_operands: the operand set's buffers from ws (no
+// launch), then the preparation kernel into them.
+stag_status alloc_operands(int form, int64_t rows, int d, bool is_query, Workspace& ws, Operands* out);
+stag_status prep_operands(const float* src, double a, bool is_query, const Operands& o, hipStream_t st);
 // Prepares `rows` query rows into a batch operand set (allocated by the
 // caller for batch.rows_pad rows) starting at row0 (a multiple of the query
 // tile, query_tile_rows()).
@@ -130,6 +134,23 @@ constexpr double kRescueBelow = 0x1.0p-60;
 // shift have qo.rows_pad entries.
 stag_status rescue_offsets(const Operands& xo, const Operands& qo, int P, double a_tile, int self, const int* flag,
                            const int* qtile_flag, float* off2, double* shift, Workspace& ws, hipStream_t st);
+// As rescue_offsets, with the max pass's partials pmax [P][qo.rows_pad] from
+// the caller.
+stag_status rescue_offsets_into(const Operands& xo, const Operands& qo, int P, double a_tile, int self,
+                                const int* flag, const int* qtile_flag, double* pmax, float* off2, double* shift,
+                                hipStream_t st);
+// Buffers of the underflow rescue of one call (flag [m], qflag [m_pad/128],
+// pmax and p2 [P][m_pad]; Gaussian: shift, off2 [m_pad]; other kernels:
+// yshift [m_pad]).
+struct RescueBuffers {
+  int *flag = nullptr, *qflag = nullptr;
+  double *pmax = nullptr, *p2 = nullptr, *shift = nullptr;
+  float *off2 = nullptr, *yshift = nullptr;
+};
+stag_status alloc_rescue(int kernel, int P, const Operands& qo, Workspace& ws, RescueBuffers* rb);
+stag_status reduce_with_rescue_into(const double* partial, int P, const Operands& qo, const Operands& xo,
+                                    double a_tile, double scale, const BoundModel& bm, const RescueBuffers& rb,
+                                    double* S_out, double* bound_out, hipStream_t st);
 // launch_reduce for the Gaussian kernel with the underflow rescue: sums
 // below 2^-60 are recomputed with their exponents shifted by their maximum
 // (two more tile passes over the 128-query tiles that hold such queries).

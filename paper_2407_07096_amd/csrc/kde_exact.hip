@@ -29,10 +29,19 @@
 // tiling are functions of n alone, so results are identical whatever m is and
 // whatever other queries share a launch.
 #include <cstring>
+#include <mutex>
 
 #include "runtime.h"
 #include "kde_exact.h"
 #include "kde_tiles.h"
+
+// Scratch of stag_kde_exact_noalloc: one array per device (the runtime gives
+// each device its own copy of a __device__ variable), kept until the process
+// ends.  Host code never passes `scratch` itself to a kernel (on the host it
+// names a stand-in, not device memory): the device address comes from
+// hipGetSymbolAddress, looked up once per device with that device current.
+static constexpr size_t kScratchBytes = (size_t)128 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
 
 namespace stag {
 namespace {
@@ -229,8 +238,7 @@ int form_parts(int form) {
   return form == STAG_FORM_FP32 ? 1 : (form == STAG_FORM_BF16_SPLIT3 ? 3 : 2);
 }
 
-stag_status prepare_operands(int form, const float* src, int64_t rows, int d, double a, bool is_query,
-                             Workspace& ws, Operands* out, hipStream_t st) {
+stag_status alloc_operands(int form, int64_t rows, int d, bool is_query, Workspace& ws, Operands* out) {
   const int dp = exact_padded_dim(d);
   const int64_t rows_pad = round_up(rows, is_query ? kBQ : kTileRows);
   out->form = form;
@@ -245,13 +253,21 @@ stag_status prepare_operands(int form, const float* src, int64_t rows, int d, do
   out->aug = nullptr;  // the tiles take the offsets directly
   STAG_TRY(ws.alloc(&out->nrm, (size_t)rows));
   out->max_nrm_bits = nullptr;
-  if (!is_query) {
-    STAG_TRY(ws.alloc(&out->max_nrm_bits, 1));
-    STAG_TRY(zero_async(out->max_nrm_bits, sizeof(unsigned long long), st));
-  }
+  if (!is_query) STAG_TRY(ws.alloc(&out->max_nrm_bits, 1));
+  return STAG_OK;
+}
+
+stag_status prep_operands(const float* src, double a, bool is_query, const Operands& o, hipStream_t st) {
+  if (o.max_nrm_bits) STAG_TRY(zero_async(o.max_nrm_bits, sizeof(unsigned long long), st));
   const double scale = is_query ? 2.0 * a * kLog2e : 1.0;
-  return prep_any(form, src, rows, d, dp, rows_pad, scale, -a * kLog2e, is_query ? 1 : 0, out->part, out->off,
-                  static_cast<u16x8*>(out->aug), out->nrm, out->max_nrm_bits, st);
+  return prep_any(o.form, src, o.rows, o.d, o.dp, o.rows_pad, scale, -a * kLog2e, is_query ? 1 : 0, o.part, o.off,
+                  static_cast<u16x8*>(o.aug), o.nrm, o.max_nrm_bits, st);
+}
+
+stag_status prepare_operands(int form, const float* src, int64_t rows, int d, double a, bool is_query,
+                             Workspace& ws, Operands* out, hipStream_t st) {
+  STAG_TRY(alloc_operands(form, rows, d, is_query, ws, out));
+  return prep_operands(src, a, is_query, *out, st);
 }
 
 int64_t exact_chunks(int64_t n_pad) { return ceil_div(n_pad, kChunkRows); }
@@ -365,22 +381,17 @@ __global__ void rescue_reduce(const double* __restrict__ partial, int P, int64_t
 }
 
 stag_status rescue_underflow(const Operands& xo, const Operands& qo, int P, double a_tile, double scale,
-                             const BoundModel& bm, const int* flag, const int* qtile_flag, double* S_out,
-                             double* bound_out, Workspace& ws, hipStream_t st) {
+                             const BoundModel& bm, const RescueBuffers& rb, double* S_out, double* bound_out,
+                             hipStream_t st) {
   const int64_t m_pad = qo.rows_pad, m = qo.rows;
-  double *p2 = nullptr, *shift = nullptr;
-  float* off2 = nullptr;
-  STAG_TRY(ws.alloc(&p2, (size_t)P * m_pad));
-  STAG_TRY(ws.alloc(&shift, (size_t)m_pad));
-  STAG_TRY(ws.alloc(&off2, (size_t)m_pad));
-  STAG_TRY(rescue_offsets(xo, qo, P, a_tile, 0, flag, qtile_flag, off2, shift, ws, st));
+  STAG_TRY(rescue_offsets_into(xo, qo, P, a_tile, 0, rb.flag, rb.qflag, rb.pmax, rb.off2, rb.shift, st));
   Operands q2 = qo;
-  q2.off = off2;
+  q2.off = rb.off2;
   TileExtra exs;
-  exs.qtile_active = qtile_flag;
-  STAG_TRY(launch_exact_tiles(xo, q2, p2, exs, st));
-  hipLaunchKernelGGL(rescue_reduce, dim3((unsigned)ceil_div(m, 256)), dim3(256), 0, st, p2, P, m_pad, m, flag, shift,
-                     scale, qo.nrm, xo.max_nrm_bits, bm, S_out, bound_out);
+  exs.qtile_active = rb.qflag;
+  STAG_TRY(launch_exact_tiles(xo, q2, rb.p2, exs, st));
+  hipLaunchKernelGGL(rescue_reduce, dim3((unsigned)ceil_div(m, 256)), dim3(256), 0, st, rb.p2, P, m_pad, m, rb.flag,
+                     rb.shift, scale, qo.nrm, xo.max_nrm_bits, bm, S_out, bound_out);
   return check_launch("rescue_reduce");
 }
 
@@ -417,11 +428,10 @@ __global__ void rescue_reduce_y(const double* __restrict__ partial, int P, int64
 
 }  // namespace
 
-stag_status rescue_offsets(const Operands& xo, const Operands& qo, int P, double a_tile, int self, const int* flag,
-                           const int* qtile_flag, float* off2, double* shift, Workspace& ws, hipStream_t st) {
+stag_status rescue_offsets_into(const Operands& xo, const Operands& qo, int P, double a_tile, int self,
+                                const int* flag, const int* qtile_flag, double* pmax, float* off2, double* shift,
+                                hipStream_t st) {
   const int64_t m_pad = qo.rows_pad, m = qo.rows;
-  double* pmax = nullptr;
-  STAG_TRY(ws.alloc(&pmax, (size_t)P * m_pad));
   TileExtra exm;
   exm.max_pass = 1;
   exm.self = self;
@@ -432,52 +442,71 @@ stag_status rescue_offsets(const Operands& xo, const Operands& qo, int P, double
   return check_launch("rescue_shift");
 }
 
+stag_status rescue_offsets(const Operands& xo, const Operands& qo, int P, double a_tile, int self, const int* flag,
+                           const int* qtile_flag, float* off2, double* shift, Workspace& ws, hipStream_t st) {
+  double* pmax = nullptr;
+  STAG_TRY(ws.alloc(&pmax, (size_t)P * qo.rows_pad));
+  return rescue_offsets_into(xo, qo, P, a_tile, self, flag, qtile_flag, pmax, off2, shift, st);
+}
+
+stag_status alloc_rescue(int kernel, int P, const Operands& qo, Workspace& ws, RescueBuffers* rb) {
+  const int64_t m = qo.rows, m_pad = qo.rows_pad;
+  *rb = RescueBuffers();
+  STAG_TRY(ws.alloc(&rb->flag, (size_t)m));
+  STAG_TRY(ws.alloc(&rb->qflag, (size_t)(m_pad / kBQ)));
+  STAG_TRY(ws.alloc(&rb->pmax, (size_t)P * m_pad));
+  STAG_TRY(ws.alloc(&rb->p2, (size_t)P * m_pad));
+  if (kernel == STAG_KERNEL_GAUSSIAN) {
+    STAG_TRY(ws.alloc(&rb->shift, (size_t)m_pad));
+    STAG_TRY(ws.alloc(&rb->off2, (size_t)m_pad));
+  } else {
+    STAG_TRY(ws.alloc(&rb->yshift, (size_t)m_pad));
+  }
+  return STAG_OK;
+}
+
 // launch_reduce for the exponential and logistic kernels with the underflow
 // rescue: a flagged query's terms are recomputed as 2^{ys - y}, ys its
 // smallest y (from the max pass), and S = (sum) 2^{-ys}.
 stag_status reduce_with_rescue_y(const double* partial, int P, const Operands& qo, const Operands& xo, int kernel,
-                                 double scale, const BoundModel& bm, const int* near_over, double* S_out,
-                                 double* bound_out, Workspace& ws, hipStream_t st) {
+                                 double scale, const BoundModel& bm, const int* near_over, const RescueBuffers& rb,
+                                 double* S_out, double* bound_out, hipStream_t st) {
   const int64_t m = qo.rows, m_pad = qo.rows_pad;
-  int *flag = nullptr, *qflag = nullptr;
-  STAG_TRY(ws.alloc(&flag, (size_t)m));
-  STAG_TRY(ws.alloc(&qflag, (size_t)(m_pad / kBQ)));
-  STAG_TRY(zero_async(flag, (size_t)m * sizeof(int), st));
-  STAG_TRY(zero_async(qflag, (size_t)(m_pad / kBQ) * sizeof(int), st));
-  STAG_TRY(launch_reduce(partial, P, qo, xo, scale, bm, S_out, bound_out, st, near_over, flag, qflag));
-  double *pmax = nullptr, *p2 = nullptr;
-  float* yshift = nullptr;
-  STAG_TRY(ws.alloc(&pmax, (size_t)P * m_pad));
-  STAG_TRY(ws.alloc(&p2, (size_t)P * m_pad));
-  STAG_TRY(ws.alloc(&yshift, (size_t)m_pad));
+  STAG_TRY(zero_async(rb.flag, (size_t)m * sizeof(int), st));
+  STAG_TRY(zero_async(rb.qflag, (size_t)(m_pad / kBQ) * sizeof(int), st));
+  STAG_TRY(launch_reduce(partial, P, qo, xo, scale, bm, S_out, bound_out, st, near_over, rb.flag, rb.qflag));
   TileExtra exm;
   exm.max_pass = 1;
-  exm.qtile_active = qflag;
-  STAG_TRY(launch_exact_tiles(xo, qo, pmax, exm, st));
-  hipLaunchKernelGGL(rescue_yshift, dim3((unsigned)ceil_div(m_pad, 256)), dim3(256), 0, st, pmax, P, m_pad, m, flag,
-                     yshift);
+  exm.qtile_active = rb.qflag;
+  STAG_TRY(launch_exact_tiles(xo, qo, rb.pmax, exm, st));
+  hipLaunchKernelGGL(rescue_yshift, dim3((unsigned)ceil_div(m_pad, 256)), dim3(256), 0, st, rb.pmax, P, m_pad, m,
+                     rb.flag, rb.yshift);
   STAG_TRY(check_launch("rescue_yshift"));
   TileExtra exs;
   exs.kernel = kernel;
-  exs.qtile_active = qflag;
-  exs.yshift = yshift;
-  STAG_TRY(launch_exact_tiles(xo, qo, p2, exs, st));
-  hipLaunchKernelGGL(rescue_reduce_y, dim3((unsigned)ceil_div(m, 256)), dim3(256), 0, st, p2, P, m_pad, m, flag,
-                     yshift, scale, qo.nrm, xo.max_nrm_bits, bm, S_out, bound_out);
+  exs.qtile_active = rb.qflag;
+  exs.yshift = rb.yshift;
+  STAG_TRY(launch_exact_tiles(xo, qo, rb.p2, exs, st));
+  hipLaunchKernelGGL(rescue_reduce_y, dim3((unsigned)ceil_div(m, 256)), dim3(256), 0, st, rb.p2, P, m_pad, m, rb.flag,
+                     rb.yshift, scale, qo.nrm, xo.max_nrm_bits, bm, S_out, bound_out);
   return check_launch("rescue_reduce_y");
+}
+
+stag_status reduce_with_rescue_into(const double* partial, int P, const Operands& qo, const Operands& xo,
+                                    double a_tile, double scale, const BoundModel& bm, const RescueBuffers& rb,
+                                    double* S_out, double* bound_out, hipStream_t st) {
+  STAG_TRY(zero_async(rb.flag, (size_t)qo.rows * sizeof(int), st));
+  STAG_TRY(zero_async(rb.qflag, (size_t)(qo.rows_pad / kBQ) * sizeof(int), st));
+  STAG_TRY(launch_reduce(partial, P, qo, xo, scale, bm, S_out, bound_out, st, nullptr, rb.flag, rb.qflag));
+  return rescue_underflow(xo, qo, P, a_tile, scale, bm, rb, S_out, bound_out, st);
 }
 
 stag_status reduce_with_rescue(const double* partial, int P, const Operands& qo, const Operands& xo, double a_tile,
                                double scale, const BoundModel& bm, double* S_out, double* bound_out, Workspace& ws,
                                hipStream_t st) {
-  const int64_t m = qo.rows;
-  int *flag = nullptr, *qflag = nullptr;
-  STAG_TRY(ws.alloc(&flag, (size_t)m));
-  STAG_TRY(ws.alloc(&qflag, (size_t)(qo.rows_pad / kBQ)));
-  STAG_TRY(zero_async(flag, (size_t)m * sizeof(int), st));
-  STAG_TRY(zero_async(qflag, (size_t)(qo.rows_pad / kBQ) * sizeof(int), st));
-  STAG_TRY(launch_reduce(partial, P, qo, xo, scale, bm, S_out, bound_out, st, nullptr, flag, qflag));
-  return rescue_underflow(xo, qo, P, a_tile, scale, bm, flag, qflag, S_out, bound_out, ws, st);
+  RescueBuffers rb;
+  STAG_TRY(alloc_rescue(STAG_KERNEL_GAUSSIAN, P, qo, ws, &rb));
+  return reduce_with_rescue_into(partial, P, qo, xo, a_tile, scale, bm, rb, S_out, bound_out, st);
 }
 
 namespace {
@@ -534,9 +563,8 @@ int choose_form(int d, double a_tile, int kernel, double eps, const InputStats& 
   return STAG_FORM_FP32;
 }
 
-stag_status exact_kernel_impl(const char* fn, const float* X, int64_t n, const float* Q, int64_t m, int32_t d,
-                              int32_t kernel, double a, double eps, int32_t form, uint32_t flags, double* S_out,
-                              double* bound_out, hipStream_t stream) {
+stag_status check_exact_args(const char* fn, const float* X, int64_t n, const float* Q, int64_t m, int32_t d,
+                             int32_t kernel, double a, double eps, int32_t form, uint32_t flags, double* S_out) {
   if (!X || !Q || !S_out) return fail(STAG_E_INVAL, "%s: NULL pointer argument", fn);
   if (n < 1 || m < 1 || d < 1) return fail(STAG_E_INVAL, "%s: n, m, d must be >= 1", fn);
   if (!(a > 0.0) || !std::isfinite(a)) return fail(STAG_E_INVAL, "%s: a must be positive and finite", fn);
@@ -553,20 +581,35 @@ stag_status exact_kernel_impl(const char* fn, const float* X, int64_t n, const f
     return fail(STAG_E_INVAL, "%s: n*d and m*d must be < 2^31", fn);
   const double at = kernel_tile_a(kernel, a);
   if (!std::isfinite(at) || !(at > 0.0)) return fail(STAG_E_INVAL, "%s: a out of range for this kernel", fn);
-  clear_error();
-  Workspace ws(stream);
-  if (form == STAG_FORM_AUTO || (flags & STAG_CHECK_FINITE)) {
-    InputStats is;
-    STAG_TRY(input_stats(X, n, Q, m, d, ws, &is, stream));
-    if ((flags & STAG_CHECK_FINITE) && is.nonfinite) return fail(STAG_E_INVAL, "%s: X or Q holds NaN or Inf", fn);
-    if (form == STAG_FORM_AUTO) form = choose_form(d, at, kernel, eps, is);
-  }
+  return STAG_OK;
+}
+
+// Every device buffer of one exact call, taken from one Workspace before
+// any launch (so that a counting Workspace gives the call's exact need).
+struct ExactBuffers {
   Operands xo, qo;
-  STAG_TRY(prepare_operands(form, X, n, d, at, false, ws, &xo, stream));
-  STAG_TRY(prepare_operands(form, Q, m, d, at, true, ws, &qo, stream));
-  const int P = (int)exact_chunks(xo.rows_pad);
+  int P = 0;
   double* partial = nullptr;
-  STAG_TRY(ws.alloc(&partial, (size_t)P * qo.rows_pad));
+  int* near_over = nullptr;  // exponential kernel
+  RescueBuffers rb;
+};
+
+stag_status alloc_exact(int form, int kernel, int64_t n, int64_t m, int d, Workspace& ws, ExactBuffers* b) {
+  STAG_TRY(alloc_operands(form, n, d, false, ws, &b->xo));
+  STAG_TRY(alloc_operands(form, m, d, true, ws, &b->qo));
+  b->P = (int)exact_chunks(b->xo.rows_pad);
+  STAG_TRY(ws.alloc(&b->partial, (size_t)b->P * b->qo.rows_pad));
+  if (kernel == STAG_KERNEL_EXPONENTIAL) STAG_TRY(ws.alloc(&b->near_over, (size_t)m));
+  return alloc_rescue(kernel, b->P, b->qo, ws, &b->rb);
+}
+
+// The launches of one exact call into buffers from alloc_exact.
+stag_status run_exact(const float* X, int64_t n, const float* Q, int64_t m, int32_t d, int32_t kernel, double a,
+                      int32_t form, uint32_t flags, double* S_out, double* bound_out, const ExactBuffers& b,
+                      hipStream_t stream) {
+  const double at = kernel_tile_a(kernel, a);
+  STAG_TRY(prep_operands(X, at, false, b.xo, stream));
+  STAG_TRY(prep_operands(Q, at, true, b.qo, stream));
   TileExtra ex;
   ex.kernel = kernel;
   if (kernel == STAG_KERNEL_EXPONENTIAL) {
@@ -576,20 +619,79 @@ stag_status exact_kernel_impl(const char* fn, const float* X, int64_t n, const f
     ex.near_e = (float)kNearY2;
     ex.a = a;
     ex.m_rows = m;
-    STAG_TRY(ws.alloc(&ex.near_over, (size_t)m));
+    ex.near_over = b.near_over;
     STAG_TRY(zero_async(ex.near_over, (size_t)m * sizeof(int), stream));
   }
-  STAG_TRY(launch_exact_tiles(xo, qo, partial, ex, stream));
+  STAG_TRY(launch_exact_tiles(b.xo, b.qo, b.partial, ex, stream));
   const double scale = (flags & STAG_NORMALIZE) ? 1.0 / (double)n : 1.0;
   const BoundModel bm = make_bound_model(form, d, at, kernel);
   // Gaussian: sums below kRescueBelow are recomputed with shifted exponents
   if (kernel == STAG_KERNEL_GAUSSIAN)
-    return reduce_with_rescue(partial, P, qo, xo, at, scale, bm, S_out, bound_out, ws, stream);
-  return reduce_with_rescue_y(partial, P, qo, xo, kernel, scale, bm, ex.near_over, S_out, bound_out, ws, stream);
+    return reduce_with_rescue_into(b.partial, b.P, b.qo, b.xo, at, scale, bm, b.rb, S_out, bound_out, stream);
+  return reduce_with_rescue_y(b.partial, b.P, b.qo, b.xo, kernel, scale, bm, ex.near_over, b.rb, S_out, bound_out,
+                              stream);
+}
+
+stag_status exact_kernel_impl(const char* fn, const float* X, int64_t n, const float* Q, int64_t m, int32_t d,
+                              int32_t kernel, double a, double eps, int32_t form, uint32_t flags, double* S_out,
+                              double* bound_out, hipStream_t stream) {
+  STAG_TRY(check_exact_args(fn, X, n, Q, m, d, kernel, a, eps, form, flags, S_out));
+  clear_error();
+  Workspace ws(stream);
+  if (form == STAG_FORM_AUTO || (flags & STAG_CHECK_FINITE)) {
+    InputStats is;
+    STAG_TRY(input_stats(X, n, Q, m, d, ws, &is, stream));
+    if ((flags & STAG_CHECK_FINITE) && is.nonfinite) return fail(STAG_E_INVAL, "%s: X or Q holds NaN or Inf", fn);
+    if (form == STAG_FORM_AUTO) form = choose_form(d, kernel_tile_a(kernel, a), kernel, eps, is);
+  }
+  ExactBuffers b;
+  STAG_TRY(alloc_exact(form, kernel, n, m, d, ws, &b));
+  return run_exact(X, n, Q, m, d, kernel, a, form, flags, S_out, bound_out, b, stream);
+}
+
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[64] = {};
+
+stag_status scratch_on_current_device(void** out) {
+  int dev = 0;
+  STAG_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) return fail(STAG_E_UNSUPPORTED, "device ordinal %d out of range", dev);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    STAG_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) return fail(STAG_E_DEVICE, "hipGetSymbolAddress gave a null scratch address");
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return STAG_OK;
 }
 
 }  // namespace
 }  // namespace stag
+
+extern "C" stag_status stag_kde_exact_noalloc(const float* X, int64_t n, const float* Q, int64_t m, int32_t d, double a,
+                                              int32_t form, uint32_t flags, double* S_out, double* bound_out,
+                                              hipStream_t stream) {
+  using namespace stag;
+  const char* fn = "stag_kde_exact_noalloc";
+  if (form == STAG_FORM_AUTO) return fail(STAG_E_UNSUPPORTED, "%s: STAG_FORM_AUTO is not available here", fn);
+  if (flags & STAG_CHECK_FINITE) return fail(STAG_E_UNSUPPORTED, "%s: STAG_CHECK_FINITE is not available here", fn);
+  STAG_TRY(check_exact_args(fn, X, n, Q, m, d, STAG_KERNEL_GAUSSIAN, a, 0.0, form, flags, S_out));
+  ExactBuffers need;
+  Workspace counter{Workspace::CountTag{}};
+  STAG_TRY(alloc_exact(form, STAG_KERNEL_GAUSSIAN, n, m, d, counter, &need));
+  if (counter.used() > kScratchBytes)
+    return fail(STAG_E_INVAL, "%s: this call needs %zu bytes of scratch, more than the %zu available", fn,
+                counter.used(), kScratchBytes);
+  clear_error();
+  void* base = nullptr;
+  STAG_TRY(scratch_on_current_device(&base));
+  Workspace arena(stream, base, kScratchBytes);
+  ExactBuffers b;
+  STAG_TRY(alloc_exact(form, STAG_KERNEL_GAUSSIAN, n, m, d, arena, &b));
+  return run_exact(X, n, Q, m, d, STAG_KERNEL_GAUSSIAN, a, form, flags, S_out, bound_out, b, stream);
+}
 
 extern "C" stag_status stag_kde_exact(const float* X, int64_t n, const float* Q, int64_t m, int32_t d, double a,
                                       double eps, int32_t form, uint32_t flags, double* S_out, double* bound_out,

@@ -111,6 +111,17 @@ stag_status Workspace::alloc_bytes(void** p, size_t bytes) {
   *p = nullptr;
   bytes = (bytes + 255) / 256 * 256;
   if (bytes == 0) bytes = 256;
+  if (mode_ == kCount) {
+    used_ += bytes;
+    return STAG_OK;
+  }
+  if (mode_ == kArena) {
+    if (used_ + bytes > cap_)
+      return fail(STAG_E_NOMEM, "scratch arena exhausted: %zu + %zu bytes > %zu", used_, bytes, cap_);
+    *p = cur_ + used_;
+    used_ += bytes;
+    return STAG_OK;
+  }
   if (bytes >= kSmallBytes) return raw_alloc(p, bytes);
   if (cur_ == nullptr || used_ + bytes > cap_) {
     void* blk = nullptr;

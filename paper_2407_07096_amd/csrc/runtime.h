@@ -56,6 +56,16 @@ void cached_free(void* p, size_t bytes);
 class Workspace {
  public:
   explicit Workspace(hipStream_t s) : stream_(s) {}
+  // Arena: every request is a 256-byte-aligned slice of the caller's
+  // device buffer [base, base + cap); nothing is allocated or freed, and a
+  // request past the end fails.
+  Workspace(hipStream_t s, void* base, size_t cap)
+      : stream_(s), mode_(kArena), cur_(static_cast<char*>(base)), cap_(cap) {}
+  // Counter: requests only add up their (aligned) sizes, read by used(); the
+  // pointers handed out are null and must not reach a launch.
+  struct CountTag {};
+  explicit Workspace(CountTag) : stream_(nullptr), mode_(kCount) {}
+  size_t used() const { return used_; }
   ~Workspace();
   Workspace(const Workspace&) = delete;
   Workspace& operator=(const Workspace&) = delete;
@@ -86,7 +96,9 @@ class Workspace {
 
  private:
   stag_status raw_alloc(void** p, size_t bytes);
+  enum Mode { kPool, kArena, kCount };
   hipStream_t stream_;
+  Mode mode_ = kPool;
   std::vector<void*> ptrs_;
   char* cur_ = nullptr;
   size_t used_ = 0, cap_ = 0;

@@ -62,6 +62,15 @@ def test_invalid_arguments_rejected_before_launch():
     assert st == _lib.STAG_E_INVAL
     st = lib.stag_kde_exact(fake, 10, fake, 10, 4, 1.0, 0.0, 0, 4, fake, null, null)
     assert st == _lib.STAG_E_INVAL
+    # the no-allocation variant: scratch limit, AUTO and CHECK_FINITE refused before any device work
+    st = lib.stag_kde_exact_noalloc(fake, 3_000_000, fake, 300_000, 64, 0.1, 2, 0, fake, null, null)
+    assert st == _lib.STAG_E_INVAL and "scratch" in stag.last_error()
+    st = lib.stag_kde_exact_noalloc(fake, 100, fake, 100, 8, 0.1, 4, 0, fake, null, null)
+    assert st == _lib.STAG_E_UNSUPPORTED
+    st = lib.stag_kde_exact_noalloc(fake, 100, fake, 100, 8, 0.1, 0, 2, fake, null, null)
+    assert st == _lib.STAG_E_UNSUPPORTED
+    st = lib.stag_kde_exact_noalloc(null, 100, fake, 100, 8, 0.1, 0, 0, fake, null, null)
+    assert st == _lib.STAG_E_INVAL and "NULL" in stag.last_error()
     it = C.c_int32(0)
     st = lib.stag_spectral_embedding(10, fake, fake, fake, 5, 0, 1e-8, 10, 0, null, fake, C.byref(it), null)
     assert st == _lib.STAG_E_INVAL and "k must be" in stag.last_error()
