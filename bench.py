@@ -1,24 +1,26 @@
 #!/usr/bin/env python3
 """Benchmark of the Gaussian-KDE hot path on one MI355X.
 
-Workload: n = 100,000 data points and m = 100,000 queries in d = 64 drawn
-from a 20-component isotropic Gaussian mixture (means U[-5,5]^64, sigma
-U[0.5,2]), a = 0.01 (seeded, synthetic).
+Headline (the timed steps): exact kernel density at the largest workload
+that fits one GPU, n = 2,000,000 data points and m = 200,000 queries in
+d = 128 drawn from a 50-component isotropic Gaussian mixture (means
+U[-5,5]^128, sigma U[0.5,2]), a = 0.01 (seeded, synthetic; it stands in for
+the large data sets of the paper's KDE comparison).  One step is one call of
+the exact KDE (operand prep, matrix-core tiles in the fp16 hi+lo split form,
+chunk reduction, underflow check) over all m queries, inputs resident in
+HBM.  value = n*m Gaussian kernel evaluations per second of the step, quoted
+at the relative error measured against the FP64 oracle on 1,000 sampled
+queries (<= 1e-5).
 
-One step runs the whole hot path over that input:
-  exact   exact kernel density of all m queries: operand prep, matrix-core
-          tile (fp16 hi+lo split form), chunk reduction;
-  lsh     CKNS estimate of all m queries: index build over X (subsamples,
-          E2LSH member keys, bucket tables) and query (query hashing, probe);
-  graph   similarity-graph edge sampling over X (exact kernel rows, 17 draws
-          per node).
-value = n*m exact kernel evaluations (at max relative error <= 1e-5 against
-the FP64 oracle, checked on sampled queries) per second of the whole step.
-
-After the timed steps: the fp32 form of the exact tile for comparison, a
-short serving run (Poisson arrivals, log-uniform batch sizes, resident data
-sets) for p50/p99 latency, and the FP64 CPU oracle timed on a bounded sample
-of the same exact workload.  One JSON line is printed.
+After the timed steps, each in its own JSON object: the other arithmetic
+forms on the same workload (error and tile time), the full hot-path step at
+n = m = 100,000, d = 64 (exact KDE + CKNS index build and query + edge
+sampling, each leg timed alone), the CKNS estimator at the paper-derived
+default parameters, edge sampling of the 784-dimensional sparse workload in
+exact and CKNS mode, the other kernels, random sampling, spectral clustering,
+the KDE-tree sampler, the E2LSH table, a serving run (p50/p99) and the FP64
+CPU oracle timed on a bounded sample of the headline workload.  One JSON line
+is printed.
 """
 from __future__ import annotations
 
@@ -37,13 +39,16 @@ MFMA_PEAK = {"fp32": 157.3e12, "fp16_split": 2.5e15, "bf16_split": 2.5e15, "bf16
 PRODUCTS = {"fp32": 1, "fp16_split": 3, "bf16_split": 3, "bf16_split3": 6}
 TILE_KERNEL = {"fp32": "kde_tile_f32", "fp16_split": "kde_tile_fp16x3", "bf16_split": "kde_tile_bf16x3",
                "bf16_split3": "kde_tile_bf16x6"}
+DTYPE = {"fp32": "f32", "fp16_split": "f16x3->f32->f64", "bf16_split": "bf16x3->f32->f64",
+         "bf16_split3": "bf16x6->f32->f64"}
 HBM_PEAK = 8.0e12
 FP64_PEAK = 78.6e12
 FP32_PEAK = 157.3e12  # vector fp32 (published)
-# CKNS parameters of the lsh leg: the cheapest setting found on this workload
-# whose average relative error is below 0.1 (the acceptance level of the
-# paper's KDE comparison), eps = 0.5
+# CKNS parameters of the hot-path step's lsh leg: the cheapest setting found on
+# that workload whose average relative error is below 0.1 (the acceptance
+# level of the paper's KDE comparison), eps = 0.5
 LSH = dict(eps=0.5, k1=1, k2_constant=8, p_offset=1, lsh_seed=3002)
+HEADLINE_A = 0.01
 
 
 def parse_timing(txt: str) -> dict:
@@ -54,10 +59,33 @@ def parse_timing(txt: str) -> dict:
     return out
 
 
+class Timers:
+    """The library's per-launch HIP event timers (stag_timing_*) around a
+    region: per kernel name (launches, total ms)."""
+
+    def __init__(self, lib, buf, torch):
+        self.lib, self.buf, self.torch = lib, buf, torch
+
+    def __enter__(self):
+        self.torch.cuda.synchronize()
+        self.lib.stag_timing_report(self.buf, len(self.buf))  # drop older records
+        self.lib.stag_timing_enable(1)
+        self.t0 = time.perf_counter()
+        return self
+
+    def __exit__(self, *exc):
+        self.torch.cuda.synchronize()
+        self.wall_s = time.perf_counter() - self.t0
+        self.lib.stag_timing_enable(0)
+        self.lib.stag_timing_report(self.buf, len(self.buf))
+        self.t = parse_timing(self.buf.value.decode())
+        return False
+
+
 def cpu_baseline(X, Q, a, budget_s: float):
     import oracle
     threads = os.cpu_count() or 1
-    done, t_total, chunk = 0, 0.0, 256
+    done, t_total, chunk = 0, 0.0, 64
     while t_total < budget_s and done < Q.shape[0]:
         t0 = time.perf_counter()
         oracle.kde_exact(X, Q[done:done + chunk], a, nthreads=threads)
@@ -67,9 +95,9 @@ def cpu_baseline(X, Q, a, budget_s: float):
     done1, t1 = 0, 0.0
     while t1 < min(3.0, budget_s / 4) and done1 < Q.shape[0]:
         t0 = time.perf_counter()
-        oracle.kde_exact(X, Q[done1:done1 + 8], a, nthreads=1)
+        oracle.kde_exact(X, Q[done1:done1 + 1], a, nthreads=1)
         t1 += time.perf_counter() - t0
-        done1 += min(8, Q.shape[0] - done1)
+        done1 += 1
     cpu = "unknown"
     try:
         with open("/proc/cpuinfo") as fh:
@@ -78,56 +106,281 @@ def cpu_baseline(X, Q, a, budget_s: float):
         pass
     return {"value": X.shape[0] * done / t_total, "unit": "Gaussian kernel evals/s", "cores": threads,
             "cpu_model": cpu, "kind": "oracle", "value_1thread": X.shape[0] * done1 / t1,
-            "sample": f"{done} of the {Q.shape[0]} queries against all {X.shape[0]} points, exact FP64 direct "
-                      f"differences with compensated log-sum-exp, OpenMP over queries; {t_total:.1f} s"}
+            "sample": f"{done} of the {Q.shape[0]} headline queries against all {X.shape[0]} points (d = "
+                      f"{X.shape[1]}), exact FP64 direct differences with compensated log-sum-exp, OpenMP over "
+                      f"queries; {t_total:.1f} s; one-thread figure from {done1} queries"}
 
 
-def precision_config_run(stag, torch, dev, lib, buf, n_check: int = 64):
-    """Exact KDE at the precision-form configuration (n = 2e6, m = 2e5,
-    d = 128, 50-component mixture, a = 0.01): tile time, pairs/s and
-    matrix-core fraction per form, and the error against the FP64 oracle on
-    sampled queries next to the largest stated per-result bound."""
+def oracle_reference(X, Q, idx, a):
+    import oracle
+    return oracle.kde_exact(X, Q[idx], a)
+
+
+def forms_run(stag, torch, lib, buf, Xd, Qd, a, idx, ref, forms, n, m, d, reps: int = 2):
+    """Exact KDE of the headline workload in other arithmetic forms: tile
+    time, evaluations per second of the tile, matrix-core fraction (on the
+    method's 2d flops per pair and on the hardware's products) and the error
+    against the FP64 oracle on the headline's sampled queries next to the
+    largest stated per-result bound."""
+    import numpy as np
+    S = torch.empty(m, dtype=torch.float64, device=Qd.device)
+    B = torch.empty(m, dtype=torch.float64, device=Qd.device)
+    out = {}
+    for form in forms:
+        stag.kde_exact(Xd, Qd, a, form=form, S_out=S)  # warm-up
+        with Timers(lib, buf, torch) as tm:
+            for _ in range(reps):
+                stag.kde_exact(Xd, Qd, a, form=form, S_out=S, bound_out=B, return_bound=True)
+        tk = TILE_KERNEL[form]
+        tile_ms = tm.t[tk][1] / tm.t[tk][0]
+        useful = 2.0 * d * n * m
+        err = np.abs(S.cpu().numpy()[idx] - ref) / ref
+        out[form] = {"call_ms": tm.wall_s * 1e3 / reps, "tile_ms": tile_ms,
+                     "evals_per_s_call": n * m / (tm.wall_s / reps), "evals_per_s_tile": n * m / (tile_ms / 1e3),
+                     "frac_of_peak_useful": useful / (tile_ms / 1e3) / MFMA_PEAK[form],
+                     "frac_of_peak_hardware": useful * PRODUCTS[form] / (tile_ms / 1e3) / MFMA_PEAK[form],
+                     "max_rel_err_sampled": float(err.max()), "max_bound_sampled": float(B.cpu().numpy()[idx].max()),
+                     "meets_1e-5": bool(err.max() <= 1e-5)}
+    return out
+
+def hot_path_step_run(stag, torch, dev, lib, buf, X, Q, Xd, Qd, form: str, a: float, steps: int, n_check: int = 256):
+    """The full hot path at n = m = 100,000, d = 64 (20-component mixture,
+    a = 0.01): exact KDE of all queries, CKNS index build and query, exact
+    edge sampling (17 draws per node).  Each leg is timed alone, then the
+    whole step in order and with its legs on three streams."""
     import numpy as np
 
     import oracle
-    import synth
-    X, Q, info = synth.config_points(3)
-    n, m, d = X.shape[0], Q.shape[0], X.shape[1]
-    a = 0.01
-    rng = np.random.default_rng(2003)
+    n, d = X.shape
+    m = Q.shape[0]
+    S = torch.empty(m, dtype=torch.float64, device=dev)
+    lsh_kw = {k: v for k, v in LSH.items() if k not in ("eps", "lsh_seed")}
+    res = {}
+
+    def exact_leg():
+        stag.kde_exact(Xd, Qd, a, form=form, S_out=S)
+
+    def lsh_leg():
+        idx = stag.LshIndex(Xd, a, eps=LSH["eps"], seed=LSH["lsh_seed"], **lsh_kw)
+        res["lsh"] = idx.query(Qd)
+        idx.close()
+
+    def graph_leg():
+        res["graph"] = stag.simgraph_sample(Xd, a, mode="exact", form=form, seed=4002)
+
+    def step():
+        lsh_leg()
+        exact_leg()
+        graph_leg()
+
+    legs = {}
+    for name, fn in (("exact", exact_leg), ("lsh", lsh_leg), ("graph", graph_leg)):
+        fn()
+        with Timers(lib, buf, torch) as tm:
+            for _ in range(steps):
+                fn()
+        legs[name] = {"ms": tm.wall_s * 1e3 / steps,
+                      "kernels_ms": {k: v[1] / steps for k, v in tm.t.items()}}
+    step()
+    with Timers(lib, buf, torch) as tm:
+        for _ in range(steps):
+            step()
+    ms_step = tm.wall_s * 1e3 / steps
+    per_step = {k: v[1] / steps for k, v in tm.t.items()}
+    timing = tm.t
+    S_main = S.clone()
+    rng = np.random.default_rng(12345)
     idx = np.sort(rng.choice(m, size=n_check, replace=False))
     ref = oracle.kde_exact(X, Q[idx], a)
-    Xd, Qd = torch.from_numpy(X).to(dev), torch.from_numpy(Q).to(dev)
-    del X, Q
-    S = torch.empty(m, dtype=torch.float64, device=dev)
-    B = torch.empty(m, dtype=torch.float64, device=dev)
-    out = {"workload": "exact KDE n=2000000 data, m=200000 queries, d=128, 50-component mixture "
-                       "(sigma U[0.5,2]), a=0.01", "checked_queries": n_check, "forms": {}}
-    for form in ["fp16_split", "bf16_split", "fp32"]:
-        stag.kde_exact(Xd, Qd, a, form=form, S_out=S)  # warm-up
-        torch.cuda.synchronize()
-        lib.stag_timing_report(buf, len(buf))
-        lib.stag_timing_enable(1)
-        reps = 3
-        for _ in range(reps):
-            stag.kde_exact(Xd, Qd, a, form=form, S_out=S, bound_out=B, return_bound=True)
-        torch.cuda.synchronize()
-        lib.stag_timing_enable(0)
-        lib.stag_timing_report(buf, len(buf))
-        t = parse_timing(buf.value.decode())
-        tk = TILE_KERNEL[form]
-        tile_ms = t[tk][1] / t[tk][0]
-        flops = 2.0 * d * n * m * PRODUCTS[form]
-        err = np.abs(S.cpu().numpy()[idx] - ref) / ref
-        out["forms"][form] = {"tile_ms": tile_ms, "pairs_per_s": n * m / (tile_ms / 1e3),
-                              "achieved_tflops": flops / (tile_ms / 1e3) / 1e12,
-                              "frac_of_peak": flops / (tile_ms / 1e3) / MFMA_PEAK[form],
-                              "max_rel_err_sampled": float(err.max()),
-                              "max_bound_sampled": float(B.cpu().numpy()[idx].max())}
-    del Xd, Qd, S, B
+    max_rel = float(np.max(np.abs(S_main.cpu().numpy()[idx] - ref) / ref))
+    lsh_rel = float(np.mean(np.abs(res["lsh"].cpu().numpy()[idx] - ref) / ref))
+    index = stag.LshIndex(Xd, a, eps=LSH["eps"], seed=LSH["lsh_seed"], **lsh_kw)
+    _, st = index.query(Qd, stats=True)
+    n_cand = int(st["n_cand"].sum().item())
+    n_acc = int(st["n_acc"].sum().item())
+    index.close()
+    t_lsh = sum(v for k, v in per_step.items() if k.startswith("lsh_")) / 1e3
+    evals = float(n) * m
+    # rooflines of the step's kernels
+    tk = TILE_KERNEL[form]
+    roofs = {}
+    c, tot = timing[tk]
+    tile_avg = tot / c
+    useful = 2.0 * d * evals
+    roofs[tk] = {"bound": "mfma", "achieved": useful / (tile_avg / 1e3) / 1e12, "peak": MFMA_PEAK[form] / 1e12,
+                 "unit": "TFLOP/s", "frac": useful / (tile_avg / 1e3) / MFMA_PEAK[form],
+                 "frac_hardware": useful * PRODUCTS[form] / (tile_avg / 1e3) / MFMA_PEAK[form],
+                 "avg_launch_ms": tile_avg, "launches_per_step": c / steps,
+                 "algorithmic": f"2*d flops per pair x n*m = {useful:.3e} (x{PRODUCTS[form]} products on the "
+                                f"matrix cores); the exact KDE and the edge sampler's self pass"}
+    if "lsh_join" in timing:
+        c, tot = timing["lsh_join"]
+        fl = 3.0 * d * n_cand
+        roofs["lsh_join"] = {"bound": "alu", "achieved": fl / (tot / c / 1e3) / 1e12, "peak": FP32_PEAK / 1e12,
+                             "unit": "TFLOP/s", "frac": fl / (tot / c / 1e3) / FP32_PEAK, "avg_launch_ms": tot / c,
+                             "algorithmic": f"{n_cand} (query, bucket member) pairs x 3d fp32 flops"}
+    if "lsh_hash_queries" in timing:
+        c, tot = timing["lsh_hash_queries"]
+        sh = stag.lsh_derive(n, a, LSH["eps"], **lsh_kw)
+        fl = 2.0 * d * m * sh["K1"] * sh["J"] * sh["L"] * sh["K"]
+        roofs["lsh_hash_queries"] = {"bound": "alu", "achieved": fl / (tot / c / 1e3) / 1e12,
+                                     "peak": FP64_PEAK / 1e12, "unit": "TFLOP/s", "frac": fl / (tot / c / 1e3) / FP64_PEAK,
+                                     "avg_launch_ms": tot / c, "algorithmic": "2*d fp64 flops per (query, projection)"}
+    if "simgraph_draw_exact" in timing:
+        c, tot = timing["simgraph_draw_exact"]
+        s = stag.draws_per_node(n)
+        by = n * s * (32 * 4 * d + 8 * 2 * ((n + 4095) // 4096) + 4 * 2 * 128)
+        roofs["simgraph_draw_exact"] = {"bound": "hbm", "achieved": by / (tot / c / 1e3) / 1e9, "peak": 8000.0,
+                                        "unit": "GB/s", "frac": by / (tot / c / 1e3) / HBM_PEAK,
+                                        "avg_launch_ms": tot / c,
+                                        "algorithmic": "per draw: the 32 rows of its tile (4d bytes each), its "
+                                                       "row's chunk sums and one 128-tile group of tile sums"}
+    # the same step with its legs on three streams (default priority)
+    streams = [torch.cuda.Stream(device=dev) for _ in range(3)]
+    S2 = torch.empty(m, dtype=torch.float64, device=dev)
+
+    def step_overlapped():
+        with torch.cuda.stream(streams[0]):
+            stag.kde_exact(Xd, Qd, a, form=form, S_out=S2)
+        with torch.cuda.stream(streams[1]):
+            stag.simgraph_sample(Xd, a, mode="exact", form=form, seed=4002)
+        with torch.cuda.stream(streams[2]):
+            ix2 = stag.LshIndex(Xd, a, eps=LSH["eps"], seed=LSH["lsh_seed"], **lsh_kw)
+            ix2.query(Qd)
+            ix2.close()
+
+    torch.cuda.synchronize()
+    step_overlapped()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step_overlapped()
+    torch.cuda.synchronize()
+    ms_ov = (time.perf_counter() - t0) * 1e3 / steps
+    src, dst, w, deg = (t.cpu().numpy() for t in res["graph"])
+    out = {"workload": f"n={n} data, m={m} queries, d={d}, 20-component mixture (sigma U[0.5,2]), a={a}: exact KDE "
+                       f"({form}) + CKNS LSH KDE (build+query, eps={LSH['eps']}, k1={LSH['k1']}, "
+                       f"k2_constant={LSH['k2_constant']}, p_offset={LSH['p_offset']}) + exact edge sampling "
+                       f"({stag.draws_per_node(n)} draws/node)",
+           "steps": steps, "ms_per_step": ms_step, "evals_per_s": evals / (ms_step / 1e3),
+           "legs_alone": legs, "exact_kde_ms": legs["exact"]["ms"],
+           "exact_evals_per_s": evals / (legs["exact"]["ms"] / 1e3),
+           "max_rel_err_sampled": max_rel, "checked_queries": n_check,
+           "lsh_avg_rel_err_sampled": lsh_rel, "lsh_candidates_per_query": n_cand / m,
+           "lsh_accepted_per_query": n_acc / m,
+           "lsh_leg": {"kernel_ms_per_step": t_lsh * 1e3, "effective_evals_per_s": n * m / t_lsh,
+                       "distance_evals_per_s": n_cand / t_lsh, "kernel_evals_per_s": n_acc / t_lsh},
+           "graph_edges": int(src.size), "graph_valid_edges": int((dst >= 0).sum()),
+           "kernels_ms_per_step": per_step, "rooflines": roofs,
+           "overlapped_legs": {"ms_per_step": ms_ov, "exact_results_identical": bool(torch.equal(S2, S_main))}}
+    return out, res["graph"]
+
+
+def lsh_defaults_run(stag, torch, dev, lib, buf, X, Q, Xd, Qd, a: float, m_sub: int = 2000, n_check: int = 64):
+    """The CKNS estimator at the paper-derived default parameters (eps = 0.5:
+    K1 = ceil(log2(n)/eps^2), L = ceil(log2 n), K from the recovery target,
+    J = ceil(log2 n) levels) over the hot-path step's data: index build, query
+    of m_sub queries, work counts, and the average and largest relative error
+    against the exact density."""
+    import numpy as np
+
+    import oracle
+    n, d = X.shape
+    rng = np.random.default_rng(2007)
+    qi = np.sort(rng.choice(Q.shape[0], size=m_sub, replace=False))
+    Qs = torch.from_numpy(np.ascontiguousarray(Q[qi])).to(dev)
+    sh = stag.lsh_derive(n, a, 0.5)
+    torch.cuda.synchronize()
+    with Timers(lib, buf, torch) as tb:
+        idx = stag.LshIndex(Xd, a, eps=0.5, seed=3002)
+    build_ms = tb.wall_s * 1e3
+    idx.query(Qs[:128])  # warm-up
+    with Timers(lib, buf, torch) as tq:
+        S, st = idx.query(Qs, stats=True)
+    idx.close()
+    ex = stag.kde_exact(Xd, Qs, a, form="fp16_split")
+    Sh, exh = S.cpu().numpy(), ex.cpu().numpy()
+    rel = np.abs(Sh - exh) / exh
+    ref = oracle.kde_exact(X, Q[qi[:n_check]], a)
+    return {"workload": f"CKNS KDE, default parameters (eps=0.5), n={n}, d={d}, a={a}; {m_sub} sampled queries",
+            "shape": sh, "build_ms": build_ms, "build_kernels_ms": {k: v[1] for k, v in tb.t.items()},
+            "query_ms": tq.wall_s * 1e3, "queries_per_s": m_sub / tq.wall_s,
+            "query_kernels_ms": {k: v[1] for k, v in tq.t.items()},
+            "candidates_per_query": float(st["n_cand"].double().mean().item()),
+            "accepted_per_query": float(st["n_acc"].double().mean().item()),
+            "avg_rel_err_vs_exact": float(rel.mean()), "max_rel_err_vs_exact": float(rel.max()),
+            "frac_within_eps": float(np.mean(rel <= 0.5)),
+            "exact_vs_oracle_max_rel_err": float(np.max(np.abs(exh[:n_check] - ref) / ref))}
+
+
+def c4_run(stag, torch, dev, lib, buf, s_lsh: dict, n_nodes_law: int = 256):
+    """Edge sampling of the 784-dimensional sparse workload (n = 70,000,
+    entries 0 w.p. 0.8 else U[0,1], a = 1e-3, ceil(log2 n) = 17 draws per
+    node) in exact mode (fp32 tiles; d > 256) and CKNS mode.  Reported: times,
+    draws/s, the CKNS-mode degree estimates against the exact degrees, and
+    total-variation distances between histograms of the drawn edges' squared
+    distances: CKNS mode vs exact mode, and each mode vs the exact law of
+    n_nodes_law sampled nodes (the noise floor of the comparison)."""
+    import numpy as np
+
+    import synth
+    n, d, a = 70_000, 784, 1e-3
+    X = synth.sparse_uniform(n, d, 1004)
+    Xd = torch.from_numpy(X).to(dev)
+    out = {"workload": f"edge sampling n={n}, d={d} (80% zeros, else U[0,1]), a={a}, "
+                       f"{stag.draws_per_node(n)} draws/node", "modes": {}}
+    graphs = {}
+    for mode, kw in (("exact", dict(form="fp32")), ("lsh", dict(eps=0.5, lsh_seed=3004, **s_lsh))):
+        stag.simgraph_sample(Xd, a, mode=mode, seed=4004, **kw)  # warm-up
+        with Timers(lib, buf, torch) as tm:
+            g = stag.simgraph_sample(Xd, a, mode=mode, seed=4004, **kw)
+        graphs[mode] = g
+        out["modes"][mode] = {"ms": tm.wall_s * 1e3, "draws_per_s": n * stag.draws_per_node(n) / tm.wall_s,
+                              "kernels_ms": {k: v[1] for k, v in tm.t.items()}}
+    out["modes"]["lsh"]["params"] = dict(eps=0.5, **s_lsh)
+
+    def drawn_d2(g):
+        src, dst = g[0], g[1]
+        ok = dst >= 0
+        s_, d_ = src[ok], dst[ok]
+        vals = []
+        for c0 in range(0, s_.numel(), 100_000):
+            xs, xd = Xd[s_[c0:c0 + 100_000]], Xd[d_[c0:c0 + 100_000]]
+            vals.append(((xs.double() - xd.double()) ** 2).sum(1))
+        return torch.cat(vals).cpu().numpy()
+
+    de, dl = drawn_d2(graphs["exact"]), drawn_d2(graphs["lsh"])
+    rng = np.random.default_rng(4104)
+    nodes = rng.choice(n, size=n_nodes_law, replace=False)
+    lw, ld = [], []
+    X64 = Xd.double()
+    for i in nodes:
+        dd = ((X64 - X64[int(i)]) ** 2).sum(1)
+        row = torch.exp(-a * dd)
+        row[int(i)] = 0.0
+        lw.append((row / row.sum()).cpu().numpy())
+        ld.append(dd.cpu().numpy())
+    del X64
+    lw, ld = np.concatenate(lw) / n_nodes_law, np.concatenate(ld)
+    lo, hi = float(min(de.min(), dl.min())), float(max(de.max(), dl.max()))
+    bins = np.linspace(lo, hi, 65)
+
+    def hist(v, w=None):
+        h, _ = np.histogram(np.clip(v, lo, hi), bins=bins, weights=w)
+        return h / h.sum()
+
+    he, hl, hlaw = hist(de), hist(dl), hist(ld, lw)
+    deg_e, deg_l = graphs["exact"][3].cpu().numpy(), graphs["lsh"][3].cpu().numpy()
+    drel = np.abs(deg_l - deg_e) / deg_e
+    out["tv_drawn_d2_lsh_vs_exact"] = float(0.5 * np.abs(hl - he).sum())
+    out["tv_drawn_d2_exact_vs_law"] = float(0.5 * np.abs(he - hlaw).sum())
+    out["tv_drawn_d2_lsh_vs_law"] = float(0.5 * np.abs(hl - hlaw).sum())
+    out["lsh_degree_rel_err"] = {"median": float(np.median(drel)), "p90": float(np.quantile(drel, 0.9)),
+                                 "max": float(drel.max())}
+    out["histogram"] = f"64 bins of ||x_i - x_j||^2 over [{lo:.1f}, {hi:.1f}]; law from {n_nodes_law} nodes' exact rows"
+    del Xd, graphs
     torch.cuda.empty_cache()
     return out
-
 
 def kernels_run(stag, torch, dev, lib, buf, X, Q, Xd, Qd, form: str, n_check: int = 32):
     """Exact KDE with each kernel function of the paper (Gaussian a = 0.01,
@@ -335,31 +588,33 @@ def e2lsh_table_run(stag, torch, dev, lib, buf, Xd, Qd, K: int = 6, L: int = 50)
 def serving_run(stag, torch, dev, n_requests: int, seconds_cap: float):
     """Requests of log-uniform size (1..65536) against four resident data
     sets.  A burst submitted at once measures the saturation throughput;
-    Poisson streams at 0.5, 0.8 and 0.95 of the saturation request rate then
-    give latency percentiles and throughput at each load (0.5 is the headline
-    figure)."""
+    Poisson streams of n_requests requests at 0.5, 0.8 and 0.95 of the
+    saturation request rate then give latency percentiles and throughput at
+    each load (0.5 is the headline figure).  Each request's queries are a
+    contiguous slice of a resident pool of 65,536 draws from its data set's
+    mixture (no host traffic per request)."""
     import numpy as np
 
     import synth
     specs = [(100_000, 16), (300_000, 64), (1_000_000, 256), (2_000_000, 64)]
     srv = stag.Server(budget_bytes=16 << 30, n_streams=4, max_batch_queries=65536)
-    ids, mixes = [], []
+    ids, pools = [], []
     for k, (n, d) in enumerate(specs):
         mix = synth.mixture(d, 20, 4005 + 10 * k, sigma=(0.5, 2.0))
         X = torch.from_numpy(synth.sample(mix, n, 4105 + 10 * k)).to(dev)
         form = "fp16_split" if d <= 256 else "fp32"
         ids.append(srv.add_dataset(X, 0.64 / d, form))
-        mixes.append(mix)
+        pools.append(torch.from_numpy(synth.sample(mix, 65536, 4205 + 10 * k)).to(dev))
         del X
+    torch.cuda.synchronize()
 
     def make(count, rate, seed):
         arr, sizes, dsel = synth.poisson_requests(count, rate_per_s=rate, seed=seed)
         reqs = []
         for r in range(count):
-            k = int(dsel[r])
-            Q = synth.sample(mixes[k], int(sizes[r]), seed * 100_000 + r)
-            reqs.append((k, torch.from_numpy(Q).to(dev)))
-        torch.cuda.synchronize()
+            k, mr = int(dsel[r]), int(sizes[r])
+            off = (r * 7919) % (65536 - mr + 1)
+            reqs.append((k, pools[k][off:off + mr]))
         return arr, reqs
 
     def run(arr, reqs, paced):
@@ -384,13 +639,12 @@ def serving_run(stag, torch, dev, n_requests: int, seconds_cap: float):
 
         def pct(p):
             return float(lat[max(0, math.ceil(p / 100 * len(lat)) - 1)]) * 1e3 if len(lat) else None
-        return {"requests": len(tickets), "p50_ms": pct(50), "p99_ms": pct(99), "evals_per_s": evals / (t_end - t_start),
-                "evals": evals, "wall_s": t_end - t_start}
+        return {"requests": len(tickets), "completed": len(lat), "p50_ms": pct(50), "p99_ms": pct(99),
+                "evals_per_s": evals / (t_end - t_start), "evals": evals, "wall_s": t_end - t_start}
 
     # saturation: a burst of requests submitted at once
-    arr, reqs = make(min(n_requests, 300), 1.0, 4005)
+    arr, reqs = make(min(n_requests, 1000), 1.0, 4005)
     burst = run(arr, reqs, paced=False)
-    del reqs
     evals_per_req = burst["evals"] / max(burst["requests"], 1)
     sat_rate = burst["evals_per_s"] / evals_per_req
     loads = []
@@ -398,7 +652,6 @@ def serving_run(stag, torch, dev, n_requests: int, seconds_cap: float):
         rate = rho * sat_rate
         arr, reqs = make(n_requests, rate, 4006 + li)
         r = run(arr, reqs, paced=True)
-        del reqs
         r.update({"rho": rho, "offered_rate_per_s": rate})
         loads.append(r)
     stats = srv.stats()
@@ -412,30 +665,35 @@ def serving_run(stag, torch, dev, n_requests: int, seconds_cap: float):
 
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-TRAFFIC_FILE = os.path.join(HERE, "profiles", "hot_path_step_n100k_d64_hbm_traffic.txt")
+TRAFFIC_FILES = [os.path.join(HERE, "profiles", "exact_tile_n2m_q200k_d128_hbm_traffic.txt"),
+                 os.path.join(HERE, "profiles", "hot_path_step_n100k_d64_hbm_traffic.txt")]
 CSRC = os.path.join(HERE, "paper_2407_07096_amd", "csrc")
 TRAFFIC_SOURCES = {"kde_tile": ["kde_tiles.h", "kde_tiles_gauss.hip", "kde_tiles_gauss_extra.hip", "kde_exact.h"],
                    "lsh_": ["lsh.hip", "e2lsh.h"], "simgraph_draw": ["simgraph.hip"]}
 
 
-def committed_traffic(key):
-    """HBM bytes per launch of a kernel from the committed counter summary
-    (FETCH_SIZE/WRITE_SIZE scaled by the copy calibration), or None when the
-    summary has no entry or the kernel's sources changed since it was taken."""
+def committed_traffic(key, workload_tag):
+    """HBM bytes per launch of a kernel from a committed counter summary
+    (FETCH_SIZE/WRITE_SIZE scaled by the copy calibration), or None when no
+    summary of that workload has an entry or the kernel's sources changed
+    since it was taken."""
     import hashlib
     srcs = next((v for k, v in TRAFFIC_SOURCES.items() if key.startswith(k)), None)
-    if srcs is None or not os.path.exists(TRAFFIC_FILE):
+    if srcs is None:
         return None
     h = hashlib.sha256()
     for f in srcs:
         with open(os.path.join(CSRC, f), "rb") as fh:
             h.update(fh.read())
     cur = h.hexdigest()[:16]
-    with open(TRAFFIC_FILE) as fh:
-        for line in fh:
-            parts = line.split()
-            if len(parts) == 6 and parts[0] == key and not line.startswith("#"):
-                return float(parts[5]) if parts[2] == cur else None
+    for path in TRAFFIC_FILES:
+        if not os.path.exists(path) or workload_tag not in os.path.basename(path):
+            continue
+        with open(path) as fh:
+            for line in fh:
+                parts = line.split()
+                if len(parts) == 6 and parts[0] == key and not line.startswith("#"):
+                    return float(parts[5]) if parts[2] == cur else None
     return None
 
 
@@ -445,14 +703,13 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--form", default="fp16_split", choices=sorted(MFMA_PEAK))
-    ap.add_argument("--a", type=float, default=0.01)
-    ap.add_argument("--check-queries", type=int, default=256)
+    ap.add_argument("--check-queries", type=int, default=1000)
     ap.add_argument("--cpu-budget", type=float, default=12.0)
-    ap.add_argument("--serve-requests", type=int, default=2000)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=10000)
+    ap.add_argument("--no-extras", action="store_true",
+                    help="only the headline (and the CPU baseline unless --no-cpu-baseline)")
     ap.add_argument("--no-serve", action="store_true")
-    ap.add_argument("--no-precision-config", action="store_true",
-                    help="skip the n=2e6, m=2e5, d=128 exact-tile measurement")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="after the timed steps, one plain device copy of this many MiB (a reference for "
                          "hardware byte counters)")
@@ -477,112 +734,44 @@ def main():
     lib.stag_timing_report.argtypes = [ctypes.c_char_p, ctypes.c_size_t]
     buf = ctypes.create_string_buffer(1 << 16)
     dev = torch.device("cuda:0")
-    X, Q, info = synth.config_points(2)
-    n, d, m = info["n"], info["d"], info["m"]
-    a = args.a
-    Xd = torch.from_numpy(X).to(dev)
-    Qd = torch.from_numpy(Q).to(dev)
+
+    # ---- headline: exact KDE, n = 2e6, m = 2e5, d = 128 ----
+    X3, Q3, info3 = synth.config_points(3)
+    n, d, m = info3["n"], info3["d"], info3["m"]
+    a = HEADLINE_A
+    Xd = torch.from_numpy(X3).to(dev)
+    Qd = torch.from_numpy(Q3).to(dev)
     S = torch.empty(m, dtype=torch.float64, device=dev)
-    lsh_kw = {k: v for k, v in LSH.items() if k not in ("eps", "lsh_seed")}
-    out = {}
-
-    def step():
-        # the LSH leg synchronises with the host (index sizes, task counts);
-        # the exact KDE and the edge sampler are queued behind it and keep the
-        # GPU busy while the host starts the next step
-        idx = stag.LshIndex(Xd, a, eps=LSH["eps"], seed=LSH["lsh_seed"], **lsh_kw)
-        out["lsh"] = idx.query(Qd)
-        idx.close()
-        stag.kde_exact(Xd, Qd, a, form=args.form, S_out=S)
-        out["graph"] = stag.simgraph_sample(Xd, a, mode="exact", form=args.form, seed=4002)
-
+    print(f"[bench] headline data ready: n={n} m={m} d={d}", file=sys.stderr, flush=True)
     for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    lib.stag_timing_report(buf, len(buf))  # drop warmup records
-    lib.stag_timing_enable(1)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    lib.stag_timing_enable(0)
-    lib.stag_timing_report(buf, len(buf))
-    timing = parse_timing(buf.value.decode())
-    S_main = S.clone()  # the step's exact result (S is reused by the fp32-form leg)
-    ms_per_step = (t1 - t0) * 1e3 / args.steps
+        stag.kde_exact(Xd, Qd, a, form=args.form, S_out=S)
+    with Timers(lib, buf, torch) as tm:
+        for _ in range(args.steps):
+            stag.kde_exact(Xd, Qd, a, form=args.form, S_out=S)
+    ms_per_step = tm.wall_s * 1e3 / args.steps
     evals = float(n) * m
     value = evals / (ms_per_step / 1e3)
-    per_step = {k: v[1] / args.steps for k, v in timing.items()}
-
-    # accuracy of this run's results against the FP64 oracle on sampled queries
-    import oracle
-    rng = np.random.default_rng(12345)
-    idx = np.sort(rng.choice(m, size=args.check_queries, replace=False))
-    ref = oracle.kde_exact(X, Q[idx], a)
-    max_rel = float(np.max(np.abs(S.cpu().numpy()[idx] - ref) / ref))
-    lsh_rel = float(np.mean(np.abs(out["lsh"].cpu().numpy()[idx] - ref) / ref))
-    src, dst, w, deg = (t.cpu().numpy() for t in out["graph"])
-
-    # LSH work counts (one extra, untimed query with statistics)
-    index = stag.LshIndex(Xd, a, eps=LSH["eps"], seed=LSH["lsh_seed"], **lsh_kw)
-    _, st = index.query(Qd, stats=True)
-    n_cand = int(st["n_cand"].sum().item())
-    n_acc = int(st["n_acc"].sum().item())
-    index.close()
-
-    # the LSH leg: effective rate (n*m per second of its kernels) beside the
-    # distance and kernel evaluations it actually performs
-    t_lsh = sum(v for k, v in per_step.items() if k.startswith("lsh_")) / 1e3
-    lsh_leg = {"kernel_ms_per_step": t_lsh * 1e3, "effective_evals_per_s": n * m / t_lsh,
-               "distance_evals_per_s": n_cand / t_lsh, "kernel_evals_per_s": n_acc / t_lsh}
-
-    # rooflines of the kernels of the step
+    per_step = {k: v[1] / args.steps for k, v in tm.t.items()}
+    print(f"[bench] headline {ms_per_step:.2f} ms/step", file=sys.stderr, flush=True)
+    if args.calib_copy_mb > 0:
+        src_c = torch.ones(args.calib_copy_mb << 18, dtype=torch.float32, device=dev)
+        dst_c = torch.empty_like(src_c)
+        torch.cuda.synchronize()
+        torch.mul(src_c, 1.0, out=dst_c)  # one streaming kernel: reads and writes calib bytes
+        torch.cuda.synchronize()
+        del src_c, dst_c
     tk = TILE_KERNEL[args.form]
-    flops_tile = 2.0 * d * evals * PRODUCTS[args.form]
-    roofs = {}
-    cnt = timing.get(tk, (1, float("nan")))[0]
-    tile_avg = timing[tk][1] / max(cnt, 1)
-    # the tile kernel runs twice per step: exact KDE and the edge sampler's pass
-    roofs[tk] = {"bound": "mfma", "achieved": flops_tile / (tile_avg / 1e3) / 1e12,
-                 "peak": MFMA_PEAK[args.form] / 1e12, "unit": "TFLOP/s",
-                 "frac": flops_tile / (tile_avg / 1e3) / MFMA_PEAK[args.form], "traffic": None,
-                 "avg_launch_ms": tile_avg, "launches_per_step": cnt / args.steps,
-                 "algorithmic": f"2*d*{PRODUCTS[args.form]} flops per pair x n*m = {flops_tile:.3e}"}
-    if "lsh_probe" in timing:
-        c, tot = timing["lsh_probe"]
-        probe_avg = tot / c
-        bytes_probe = n_cand * (4 + 4 + 4 * d)
-        roofs["lsh_probe"] = {"bound": "hbm", "achieved": bytes_probe / (probe_avg / 1e3) / 1e9, "peak": 8000.0,
-                              "unit": "GB/s", "frac": bytes_probe / (probe_avg / 1e3) / HBM_PEAK, "traffic": None,
-                              "avg_launch_ms": probe_avg,
-                              "algorithmic": f"{n_cand} bucket members x (4+4+4d) bytes"}
-    if "lsh_join" in timing:
-        c, tot = timing["lsh_join"]
-        join_avg = tot / c
-        fl_join = 3.0 * d * n_cand  # fp32 screen: d subtractions + d FMAs per (query, bucket member)
-        roofs["lsh_join"] = {"bound": "alu", "achieved": fl_join / (join_avg / 1e3) / 1e12,
-                             "peak": FP32_PEAK / 1e12, "unit": "TFLOP/s",
-                             "frac": fl_join / (join_avg / 1e3) / FP32_PEAK, "traffic": None,
-                             "avg_launch_ms": join_avg,
-                             "algorithmic": f"{n_cand} (query, bucket member) pairs x 3d fp32 flops"}
-    if "lsh_hash_queries" in timing:
-        c, tot = timing["lsh_hash_queries"]
-        sh = stag.lsh_derive(n, a, LSH["eps"], **lsh_kw)
-        fl = 2.0 * d * m * sh["K1"] * sh["J"] * sh["L"] * sh["K"]
-        roofs["lsh_hash_queries"] = {"bound": "alu", "achieved": fl / (tot / c / 1e3) / 1e12,
-                                     "peak": FP64_PEAK / 1e12, "unit": "TFLOP/s",
-                                     "frac": fl / (tot / c / 1e3) / FP64_PEAK, "traffic": None,
-                                     "avg_launch_ms": tot / c,
-                                     "algorithmic": "2*d fp64 flops per (query, projection)"}
-    for k, v in roofs.items():
-        v["traffic"] = committed_traffic(k)
-    dom = max(((k, v["avg_launch_ms"] * v.get("launches_per_step", 1.0)) for k, v in roofs.items()),
-              key=lambda kv: kv[1])[0]
-    roof = dict(roofs[dom])
-    roof["kernel"] = dom
-
+    c, tot = tm.t[tk]
+    tile_avg = tot / c
+    useful = 2.0 * d * evals
+    roof = {"bound": "mfma", "achieved": useful / (tile_avg / 1e3) / 1e12, "peak": MFMA_PEAK[args.form] / 1e12,
+            "unit": "TFLOP/s", "frac": useful / (tile_avg / 1e3) / MFMA_PEAK[args.form],
+            "traffic": committed_traffic(tk, "n2m_q200k_d128"), "kernel": tk, "avg_launch_ms": tile_avg,
+            "launches_per_step": c / args.steps,
+            "frac_hardware": useful * PRODUCTS[args.form] / (tile_avg / 1e3) / MFMA_PEAK[args.form],
+            "algorithmic": f"2*d = {2 * d} flops per (query, point) pair x n*m = {useful:.4e} per launch (the "
+                           f"method's work); the {args.form} form issues {PRODUCTS[args.form]} matrix-core "
+                           f"products per pair (frac_hardware)"}
     result = {
         "metric": "Gaussian kernel evals/sec at <=1e-5 rel err vs FP64; p50/p99 KDE query latency",
         "value": value,
@@ -594,94 +783,63 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"fp32": "f32", "fp16_split": "f16x3->f32->f64", "bf16_split": "bf16x3->f32->f64",
-                  "bf16_split3": "bf16x6->f32->f64"}[args.form],
+        "dtype": DTYPE[args.form],
         "data": "synthetic",
-        "config": {"workload": "Gaussian KDE hot path on n=100000 data, m=100000 queries, d=64, 20-component "
-                               "mixture (sigma U[0.5,2]), a=%g: exact KDE + CKNS LSH KDE (build+query) + "
-                               "similarity-graph edge sampling (17 draws/node)" % a,
-                   "exact_form": args.form, "lsh": LSH, "n": n, "m": m, "d": d},
-        "max_rel_err_sampled": max_rel,
-        "checked_queries": int(args.check_queries),
-        "lsh_avg_rel_err_sampled": lsh_rel,
-        "lsh_candidates_per_query": n_cand / m,
-        "lsh_accepted_per_query": n_acc / m,
-        "lsh_leg": lsh_leg,
-        "graph_edges": int(src.size), "graph_valid_edges": int((dst >= 0).sum()),
+        "config": {"workload": f"exact Gaussian KDE, n={n} data, m={m} queries, d={d}, 50-component isotropic "
+                               f"mixture (means U[-5,5]^d, sigma U[0.5,2]), a={a}, form {args.form}; one step = "
+                               f"one call over all queries, inputs resident in HBM",
+                   "n": n, "m": m, "d": d, "a": a, "form": args.form},
+        "exact_kde_ms_per_step": ms_per_step,
         "kernels_ms_per_step": per_step,
-        "exact_kde_ms_per_step": sum(v for k, v in per_step.items() if k.startswith("kde_")) / 2.0,
         "roofline": roof,
-        "rooflines": roofs,
     }
-    # fp32 form of the exact tile on the same workload (equal-accuracy comparison)
-    if args.form != "fp32":
-        stag.kde_exact(Xd, Qd, a, form="fp32", S_out=S)
-        torch.cuda.synchronize()
-        lib.stag_timing_report(buf, len(buf))
-        lib.stag_timing_enable(1)
-        stag.kde_exact(Xd, Qd, a, form="fp32", S_out=S)
-        torch.cuda.synchronize()
-        lib.stag_timing_enable(0)
-        lib.stag_timing_report(buf, len(buf))
-        t32 = parse_timing(buf.value.decode())
-        err32 = float(np.max(np.abs(S.cpu().numpy()[idx] - ref) / ref))
-        result["fp32_form"] = {"tile_ms": t32["kde_tile_f32"][1], "max_rel_err_sampled": err32,
-                               "evals_per_s_tile": evals / (t32["kde_tile_f32"][1] / 1e3)}
-        result["split_form_tile_ms"] = tile_avg
-    # the same step with its three legs on three streams (default priority):
-    # the exact KDE and the edge sampler are queued first, then the LSH leg
-    # (which waits on its own stream for its sizes); the matrix-core tiles
-    # overlap the VALU-bound join.  Reported beside the headline, which keeps
-    # the legs in order so that every kernel's event time is its own.
-    streams = [torch.cuda.Stream(device=dev) for _ in range(3)]
-    S2 = torch.empty(m, dtype=torch.float64, device=dev)
+    if args.check_queries > 0:
+        rng = np.random.default_rng(2003)
+        idx = np.sort(rng.choice(m, size=args.check_queries, replace=False))
+        t0 = time.perf_counter()
+        ref = oracle_reference(X3, Q3, idx, a)
+        t_ref = time.perf_counter() - t0
+        err = np.abs(S.cpu().numpy()[idx] - ref) / ref
+        result["max_rel_err_sampled"] = float(err.max())
+        result["median_rel_err_sampled"] = float(np.median(err))
+        result["checked_queries"] = int(args.check_queries)
+        result["oracle_check_s"] = t_ref
+        print(f"[bench] checked {args.check_queries} queries: max rel err {err.max():.3e}", file=sys.stderr,
+              flush=True)
+        if not args.no_extras:
+            others = [f for f in ("fp16_split", "bf16_split", "bf16_split3", "fp32") if f != args.form]
+            result["forms"] = forms_run(stag, torch, lib, buf, Xd, Qd, a, idx, ref, others, n, m, d)
+            print("[bench] other forms done", file=sys.stderr, flush=True)
+    del Xd, Qd, S
+    torch.cuda.empty_cache()
 
-    def step_overlapped():
-        with torch.cuda.stream(streams[0]):
-            stag.kde_exact(Xd, Qd, a, form=args.form, S_out=S2)
-        with torch.cuda.stream(streams[1]):
-            g2 = stag.simgraph_sample(Xd, a, mode="exact", form=args.form, seed=4002)
-        with torch.cuda.stream(streams[2]):
-            ix2 = stag.LshIndex(Xd, a, eps=LSH["eps"], seed=LSH["lsh_seed"], **lsh_kw)
-            r2 = ix2.query(Qd)
-            ix2.close()
-        return g2, r2
-
-    torch.cuda.synchronize()
-    step_overlapped()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step_overlapped()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ms_ov = (t1 - t0) * 1e3 / args.steps
-    same = bool(torch.equal(S2, S_main))
-    result["overlapped_legs"] = {"ms_per_step": ms_ov, "evals_per_s": evals / (ms_ov / 1e3),
-                                 "exact_results_identical": same,
-                                 "note": "the step's legs on three streams; not the headline"}
-    graph = out["graph"]
-    del out
-    if args.calib_copy_mb > 0:
-        src_c = torch.ones(args.calib_copy_mb << 18, dtype=torch.float32, device=dev)
-        dst_c = torch.empty_like(src_c)
-        torch.cuda.synchronize()
-        torch.mul(src_c, 1.0, out=dst_c)  # one streaming kernel: reads and writes calib bytes
-        torch.cuda.synchronize()
-        result["calib_copy_bytes"] = args.calib_copy_mb << 20
-        del src_c, dst_c
-    result["e2lsh_table"] = e2lsh_table_run(stag, torch, dev, lib, buf, Xd, Qd)
-    result["kernels"] = kernels_run(stag, torch, dev, lib, buf, X, Q, Xd, Qd, args.form)
-    result["random_sampling"] = rs_run(stag, torch, lib, buf, X, Q, Xd, Qd, a, args.form)
-    result["spectral"] = spectral_run(stag, torch, lib, buf, graph, n, info["k"], info["labels"])
-    result["kde_tree_sampler"] = tree_run(stag, torch, lib, buf, X, Xd, a, graph, info["labels"], info["k"])
-    del graph
-    if not args.no_precision_config:
-        result["precision_config"] = precision_config_run(stag, torch, dev, lib, buf)
-    if not args.no_serve:
-        result["serving"] = serving_run(stag, torch, dev, args.serve_requests, seconds_cap=30.0)
+    if not args.no_extras:
+        X, Q, info = synth.config_points(2)
+        Xd = torch.from_numpy(X).to(dev)
+        Qd = torch.from_numpy(Q).to(dev)
+        a2 = 0.01
+        step, graph = hot_path_step_run(stag, torch, dev, lib, buf, X, Q, Xd, Qd, args.form, a2, steps=5)
+        result["hot_path_step"] = step
+        for k, v in result["hot_path_step"]["rooflines"].items():
+            v["traffic"] = committed_traffic(k, "n100k_d64")
+        print("[bench] hot-path step done", file=sys.stderr, flush=True)
+        result["lsh_default_parameters"] = lsh_defaults_run(stag, torch, dev, lib, buf, X, Q, Xd, Qd, a2)
+        print("[bench] CKNS defaults done", file=sys.stderr, flush=True)
+        result["e2lsh_table"] = e2lsh_table_run(stag, torch, dev, lib, buf, Xd, Qd)
+        result["kernels"] = kernels_run(stag, torch, dev, lib, buf, X, Q, Xd, Qd, args.form)
+        result["random_sampling"] = rs_run(stag, torch, lib, buf, X, Q, Xd, Qd, a2, args.form)
+        result["spectral"] = spectral_run(stag, torch, lib, buf, graph, info["n"], info["k"], info["labels"])
+        result["kde_tree_sampler"] = tree_run(stag, torch, lib, buf, X, Xd, a2, graph, info["labels"], info["k"])
+        del graph, Xd, Qd
+        torch.cuda.empty_cache()
+        print("[bench] step extras done", file=sys.stderr, flush=True)
+        result["edge_sampling_784d"] = c4_run(stag, torch, dev, lib, buf, dict(k1=1, k2_constant=8, p_offset=3))
+        print("[bench] 784-d edge sampling done", file=sys.stderr, flush=True)
+        if not args.no_serve:
+            result["serving"] = serving_run(stag, torch, dev, args.serve_requests, seconds_cap=90.0)
+            print("[bench] serving done", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
-        result["cpu_baseline"] = cpu_baseline(X, Q, a, args.cpu_budget)
+        result["cpu_baseline"] = cpu_baseline(X3, Q3, a, args.cpu_budget)
     print(json.dumps(result), flush=True)
 
 

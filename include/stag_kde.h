@@ -107,6 +107,10 @@ double stag_e2lsh_collision_probability(double c, int32_t K, int32_t L);
  *                       a-priori bound at the largest query norm is <= eps;
  *                       FP32 if none is (bound_out then shows it).  The
  *                       result equals that of the chosen form bit for bit.
+ *                       The choice rests on the same bound as bound_out,
+ *                       whose accumulation term is probabilistic (below), so
+ *                       "<= eps" holds except with probability < 1e-9 per
+ *                       result, not with certainty.
  *   flags               STAG_NORMALIZE, STAG_CHECK_FINITE (one device scan
  *                       and synchronisation; a NaN or Inf in X or Q is
  *                       STAG_E_INVAL with nothing launched after the scan).
@@ -364,6 +368,12 @@ stag_status stag_kde_lsh(const float* X, int64_t n, const float* Q, int64_t m, i
  * dst = -1 (w = 0) for a node whose row is empty (all kernel values 0).
  * samples_per_node 0 means ceil(log2 n); at most 64.
  * ------------------------------------------------------------------------ */
+/* Host-only: the draws per node s that stag_simgraph_sample and
+ * stag_simgraph_sample_tree take for a samples_per_node argument (0 means
+ * ceil(log2 n), at least 1), so that a caller can size the outputs; -1 if
+ * n < 1 or samples_per_node is outside [0, 64]. */
+int32_t stag_simgraph_draws_per_node(int64_t n, int32_t samples_per_node);
+
 #define STAG_SIMGRAPH_EXACT 0
 #define STAG_SIMGRAPH_LSH 1
 

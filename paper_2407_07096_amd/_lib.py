@@ -74,6 +74,8 @@ def load():
     lib.stag_kde_exact.argtypes = [vp, i64, vp, i64, i32, f64, f64, i32, u32, vp, vp, vp]
     lib.stag_kde_exact_noalloc.restype = C.c_int
     lib.stag_kde_exact_noalloc.argtypes = [vp, i64, vp, i64, i32, f64, i32, u32, vp, vp, vp]
+    lib.stag_simgraph_draws_per_node.restype = i32
+    lib.stag_simgraph_draws_per_node.argtypes = [i64, i32]
     lib.stag_kde_exact_kernel.restype = C.c_int
     lib.stag_kde_exact_kernel.argtypes = [vp, i64, vp, i64, i32, i32, f64, f64, i32, u32, vp, vp, vp]
     lib.stag_kde_random_sample.restype = C.c_int
@@ -401,6 +403,15 @@ def kde_lsh(X, Q, a: float, eps: float = 0.5, G0=None, b=None, **kw):
     return S
 
 
+def draws_per_node(n: int, samples_per_node: int = 0) -> int:
+    """Draws per node the edge samplers take (the library's rule: 0 means
+    ceil(log2 n)); raises for arguments the samplers reject."""
+    s = load().stag_simgraph_draws_per_node(int(n), int(samples_per_node))
+    if s < 1:
+        raise StagError(STAG_E_INVAL, f"samples_per_node = {samples_per_node} outside [0, 64] or n < 1")
+    return s
+
+
 def simgraph_sample(X, a: float, samples_per_node: int = 0, mode: str = "exact", form: str = "fp32",
                     eps: float = 0.5, seed: int = 0, G0=None, b=None, lsh_seed: int = 0, **lsh_kw):
     """Edge sample of the kernel similarity graph: (src, dst, w, deg) tensors.
@@ -409,10 +420,7 @@ def simgraph_sample(X, a: float, samples_per_node: int = 0, mode: str = "exact",
     torch = _torch()
     _need(X, torch.float32, 2, "X")
     n, d = X.shape
-    if samples_per_node <= 0:
-        s = max(1, int(n - 1).bit_length())
-    else:
-        s = int(samples_per_node)
+    s = draws_per_node(n, samples_per_node)
     src = torch.empty(n * s, dtype=torch.int64, device=X.device)
     dst = torch.empty(n * s, dtype=torch.int64, device=X.device)
     w = torch.empty(n * s, dtype=torch.float64, device=X.device)
@@ -432,7 +440,7 @@ def simgraph_sample_tree(X, a: float, samples_per_node: int = 0, est_samples: in
     torch = _torch()
     _need(X, torch.float32, 2, "X")
     n, d = X.shape
-    s = max(1, int(n - 1).bit_length()) if samples_per_node <= 0 else int(samples_per_node)
+    s = draws_per_node(n, samples_per_node)
     src = torch.empty(n * s, dtype=torch.int64, device=X.device)
     dst = torch.empty(n * s, dtype=torch.int64, device=X.device)
     w = torch.empty(n * s, dtype=torch.float64, device=X.device)

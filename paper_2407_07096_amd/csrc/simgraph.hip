@@ -258,14 +258,16 @@ stag_status sample_exact(const float* X, int64_t n, int d, double a, int form, i
   return check_launch("draw_exact");
 }
 
-int default_samples(int64_t n) {
-  int s = 0;
-  while (((int64_t)1 << s) < n) ++s;
-  return s < 1 ? 1 : s;
-}
-
 }  // namespace
 }  // namespace stag
+
+extern "C" int32_t stag_simgraph_draws_per_node(int64_t n, int32_t samples_per_node) {
+  if (n < 1 || samples_per_node < 0 || samples_per_node > 64) return -1;
+  if (samples_per_node > 0) return samples_per_node;
+  int s = 0;
+  while (((int64_t)1 << s) < n) ++s;  // ceil(log2 n)
+  return s < 1 ? 1 : s;
+}
 
 extern "C" stag_status stag_simgraph_sample(const float* X, int64_t n, int32_t d, double a, int32_t samples_per_node,
                                             int32_t kde_mode, int32_t form, double eps, const stag_lsh_params* lsh,
@@ -277,7 +279,7 @@ extern "C" stag_status stag_simgraph_sample(const float* X, int64_t n, int32_t d
   if (!(a > 0.0) || !std::isfinite(a)) return fail(STAG_E_INVAL, "stag_simgraph_sample: a must be positive and finite");
   if (samples_per_node < 0 || samples_per_node > 64)
     return fail(STAG_E_INVAL, "stag_simgraph_sample: samples_per_node must be in [0, 64]");
-  const int s = samples_per_node > 0 ? samples_per_node : default_samples(n);
+  const int s = stag_simgraph_draws_per_node(n, samples_per_node);
   clear_error();
   if (kde_mode == STAG_SIMGRAPH_EXACT) {
     if (form < STAG_FORM_FP32 || form > STAG_FORM_BF16_SPLIT3)

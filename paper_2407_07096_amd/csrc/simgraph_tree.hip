@@ -284,9 +284,7 @@ extern "C" stag_status stag_simgraph_sample_tree(const float* X, int64_t n, int3
     return fail(STAG_E_INVAL, "%s: samples_per_node must be in [0, 64]", fn);
   if (est_samples < 1 || est_samples > 32) return fail(STAG_E_INVAL, "%s: est_samples must be in [1, 32]", fn);
   if (degree_samples < 1) return fail(STAG_E_INVAL, "%s: degree_samples must be >= 1", fn);
-  int s = samples_per_node;
-  if (s == 0)
-    while (((int64_t)1 << s) < n) ++s;  // ceil(log2 n)
+  const int s = stag_simgraph_draws_per_node(n, samples_per_node);
   const int64_t draws = n * s;
   if (draws >= 2147483647LL) return fail(STAG_E_INVAL, "%s: n * samples_per_node must be < 2^31", fn);
   const int64_t nb = (n + kTreeLeaf - 1) / kTreeLeaf;

@@ -25,6 +25,17 @@ def test_collision_probability_host(orc, c, K, L):
                                                                 abs=1e-300)
 
 
+def test_draws_per_node_rule():
+    # 0 means ceil(log2 n), at least one draw; explicit counts pass through
+    assert [stag.draws_per_node(n) for n in (1, 2, 3, 4, 5, 1024, 1025, 70_000, 100_000)] == \
+        [1, 1, 2, 2, 3, 10, 11, 17, 17]
+    assert stag.draws_per_node(100, 7) == 7
+    with pytest.raises(stag.StagError):
+        stag.draws_per_node(100, 65)
+    with pytest.raises(stag.StagError):
+        stag.draws_per_node(0, 0)
+
+
 def test_collision_probability_rejects():
     import math
     assert math.isnan(stag.collision_probability(-1.0))

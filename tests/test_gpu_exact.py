@@ -169,11 +169,13 @@ def test_config2_full_size_sampled(stag, orc):
 
 
 def test_config3_full_size_sampled(stag, orc):
-    """n = 2,000,000, m = 200,000, d = 128, a = 0.01: oracle on 48 sampled queries."""
+    """n = 2,000,000, m = 200,000, d = 128, a = 0.01 (the headline workload):
+    full launch, oracle on 1,000 sampled queries.  fp16 split, bf16 three-way
+    and fp32 within 1e-5; every form within its per-result bound."""
     import torch
     X, Q, _ = synth.config_points(3)
     rng = np.random.default_rng(2003)
-    idx = np.sort(rng.choice(Q.shape[0], size=48, replace=False))
+    idx = np.sort(rng.choice(Q.shape[0], size=1000, replace=False))
     ref = orc.kde_exact(X, Q[idx], 0.01)
     Xd, Qd = to_dev(X), to_dev(Q)
     for form in ["fp16_split", "bf16_split", "bf16_split3", "fp32"]:
@@ -182,8 +184,11 @@ def test_config3_full_size_sampled(stag, orc):
         torch.cuda.synchronize()
         S, B = S.cpu().numpy(), B.cpu().numpy()
         err = rel_err(S[idx], ref)
+        print(f"[measured] config3 {form}: max rel err {err.max():.3e} over {len(idx)} queries", flush=True)
         assert np.all(err <= B[idx]), (form, err.max())
         assert np.all(np.isfinite(S))
+        if form != "bf16_split":
+            assert err.max() <= 1e-5, (form, err.max())
 
 
 def _auto_expected(bounds, eps, fp16_ok):

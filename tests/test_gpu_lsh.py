@@ -98,6 +98,22 @@ def test_config2_default_parameters_reduced(stag, orc):
     assert np.mean(np.abs(S[ok] - ex[ok]) / ex[ok] <= 0.5) >= 0.9
 
 
+def test_config2_default_parameters_full(stag, orc):
+    """n = 100,000, d = 64, a = 0.01 at the default reading (eps = 0.5: K1 = 67
+    copies, J = 17 levels, L = 17 tables, K = 9): counts bit-exact and values
+    within 1e-9 on 32 sampled queries."""
+    X, Q, _ = synth.config_points(2)
+    rng = np.random.default_rng(5)
+    idx = rng.choice(Q.shape[0], size=32, replace=False)
+    announce("lsh config2 n=1e5 d=64 default parameters (K1=67, J=17, L=17, K=9)")
+    sh = orc.lsh_derive(X.shape[0], 0.01)
+    assert (sh["K1"], sh["J"], sh["L"], sh["K"]) == (67, 17, 17, 9)
+    S, S_ref, _ = _compare(stag, orc, X, Q[idx], 0.01, seed=3002, check_segments=False)
+    ex = orc.kde_exact(X, Q[idx], 0.01)
+    print(f"[measured] default CKNS n=1e5: mean rel err {np.mean(np.abs(S - ex) / ex):.3e}", flush=True)
+    assert np.mean(np.abs(S - ex) / ex <= 0.5) >= 0.9
+
+
 def test_degenerate_case_is_truncated_exact(stag, orc):
     X, Q, _ = synth.config_points(1, n=300, m=40)
     a = 0.05

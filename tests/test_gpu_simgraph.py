@@ -144,6 +144,48 @@ def test_exact_mode_config4_full_sampled(stag, orc):
         _check_valid_draws(orc, X, a, s, seed, src, dst, np.arange(i * s, (i + 1) * s), 1e-5)
 
 
+def test_lsh_mode_config4_full(stag):
+    """n = 70,000, d = 784, a = 1e-3 in CKNS mode: every draw valid, weights
+    positive, degree estimates near the exact mode's, runs deterministic."""
+    X = synth.sparse_uniform(70_000, 784, 1004)
+    a, seed = 1e-3, 4004
+    kw = dict(eps=0.5, k1=1, k2_constant=8, p_offset=3, lsh_seed=3004)
+    announce("simgraph lsh config4 full n=70000 d=784")
+    src, dst, w, deg = _gpu(stag, X, a, 0, mode="lsh", seed=seed, **kw)
+    s = 17
+    assert src.shape[0] == 70_000 * s
+    assert np.array_equal(src, np.repeat(np.arange(70_000), s))
+    ok = dst >= 0
+    assert ok.mean() > 0.99
+    assert np.all(dst[ok] != src[ok]) and np.all(dst[ok] < 70_000) and np.all(w[ok] > 0)
+    _, _, _, deg_e = _gpu(stag, X, a, 0, mode="exact", form="fp32", seed=seed)
+    rel = np.abs(deg - deg_e) / deg_e
+    print(f"[measured] config4 CKNS degrees vs exact: median {np.median(rel):.3e}, max {rel.max():.3e}", flush=True)
+    assert np.median(rel) < 0.05
+    src2, dst2, w2, deg2 = _gpu(stag, X, a, 0, mode="lsh", seed=seed, **kw)
+    assert np.array_equal(dst, dst2) and np.array_equal(w, w2) and np.array_equal(deg, deg2)
+
+
+def test_lsh_mode_784d_matches_oracle(stag, orc):
+    """The CKNS mode at d = 784 (the wide-row paths) against the oracle on a
+    reduced sparse workload."""
+    X = synth.sparse_uniform(3000, 784, 1004)
+    n, d = X.shape
+    a = 1e-3
+    kw = dict(eps=0.5, k1=1, k2_constant=8, p_offset=3)
+    G0, B = _lsh_inputs(orc, n, d, a, 33, **kw)
+    s, seed = 6, 78
+    announce("simgraph lsh 784-d n=3000")
+    src, dst, w, deg = _gpu(stag, X, a, s, mode="lsh", seed=seed, G0=to_dev(G0), b=to_dev(B), lsh_seed=0, **kw)
+    osrc, odst, ow, odeg, mg = orc.simgraph_lsh(X, a, s, seed, G0, B, lsh_seed=0, **kw)
+    assert np.array_equal(src, osrc)
+    assert np.allclose(deg, odeg, rtol=1e-9)
+    same = dst == odst
+    assert np.all(same[mg > 1e-9]) and same.mean() > 0.99
+    ok = same & (dst >= 0)
+    assert np.allclose(w[ok], ow[ok], rtol=1e-9)
+
+
 def _lsh_inputs(orc, n, d, a, seed, **kw):
     sh = orc.lsh_derive(n, a, **kw)
     npj = sh["K1"] * sh["J"] * sh["L"] * sh["K"]
