@@ -20,7 +20,36 @@ struct Operands {
   void* aug = nullptr;                          // 8 x bf16 augmentation operand per row (split forms)
   double* nrm = nullptr;                        // ||row||^2, fp64, [rows]
   unsigned long long* max_nrm_bits = nullptr;   // max ||row||^2 (fp64 bits)
+  // Centred data (fp32 form, d <= 256): rows grouped into compact 32-row
+  // tiles, part[0] holds fl32(x - c_T) and off holds -a log2(e) ||x - c_T||^2
+  // (padding rows -1e30); centre [rows_pad/32][dp] fp32 c_T, radius
+  // [rows_pad/32] max ||x - c_T|| (rounded up).  rows_pad is an upper bound
+  // of the padded row count; the count itself is *n_pad_dev (device).
+  bool centred = false;
+  float* centre = nullptr;
+  float* radius = nullptr;
+  int64_t* n_pad_dev = nullptr;
 };
+
+// Temporaries of the centring's grouping (kde_centre.hip).
+struct CentreTemp {
+  int K = 0, K_pad = 0;
+  int64_t nblk = 0;
+  float *seeds = nullptr, *hn = nullptr, *ref = nullptr;
+  uint8_t* label = nullptr;
+  uint32_t *hist = nullptr, *count = nullptr, *goff = nullptr;
+  int* map = nullptr;
+};
+// Upper bound of the padded row count of centred data of n rows.
+int64_t centred_rows_max(int64_t n);
+// Centred data operands of n rows (buffers from ws, no launch), the
+// temporaries of their grouping (from a workspace that may be released once
+// the preparation has run), and the preparation from X [n][d] (a_tile: the
+// kernel's bandwidth, a for the Gaussian).
+stag_status alloc_centred_operands(int64_t n, int d, Workspace& ws, Operands* out);
+stag_status alloc_centre_temp(const Operands& o, Workspace& ws, CentreTemp* t);
+stag_status prep_centred_operands(const float* X, double a_tile, const Operands& o, const CentreTemp& t,
+                                  hipStream_t st);
 
 // Rounding-error model of one result.  The tiles produce the exponent
 // E = -lambda D (base 2; lambda = la) with an absolute error of at most
@@ -40,6 +69,10 @@ constexpr double kNearY2 = 0.25;
 
 struct BoundModel {
   double la, c_acc, c_split, c_off, c_tail;
+  // centred fp32 tile: each term's exponent error is at most c_cent M_T,
+  // M_T = la (||q - c_T|| + R_T)^2 + |shift| (accumulated per tile in the
+  // kernel, weighted by the tile's sum)
+  double c_cent = 0.0;
   int kern = 0;          // a stag_kernel
   double near_y2 = 0.0;  // exponential kernel: terms with computed y^2 below this are exact
 };
@@ -97,6 +130,10 @@ struct TileExtra {
   // exponential / logistic in the rescue's second pass: per query the shift
   // ys (smallest y = sqrt(-E)); the terms are 2^{ys - y}
   const float* yshift = nullptr;
+  // centred data: bpart[chunk][query] = sum over the chunk's tiles of the
+  // tile's kernel sum times (2^{c_cent M_T} - 1), the bound's numerator
+  double* bpart = nullptr;
+  float c_cent = 0.0f;
 };
 
 int exact_padded_dim(int d);  // 0 if unsupported
@@ -118,7 +155,19 @@ stag_status prep_operands(const float* src, double a, bool is_query, const Opera
 // caller for batch.rows_pad rows) starting at row0 (a multiple of the query
 // tile, query_tile_rows()).
 stag_status prep_query_into(int form, const float* src, int64_t rows, int d, double a, const Operands& batch,
-                            int64_t row0, hipStream_t st);
+                            int64_t row0, hipStream_t st, bool centred = false);
+// Largest squared row norm (fp64 bits), largest |element| (fp32 bits) and a
+// non-finite flag of A [rows][d], into caller device words (cleared first;
+// asynchronous on st).
+stag_status row_stats_async(const float* A, int64_t rows, int d, unsigned long long* nrm_bits, unsigned int* abs_bits,
+                            int* bad, hipStream_t st);
+// The form the STAG_FORM_AUTO rule takes among the resident ones (bit mask of
+// 1 << form) for the Gaussian kernel: the first of fp16 split (if the
+// operands fit fp16), bf16 split, bf16 three-way whose a-priori bound at the
+// largest norms is <= eps, else fp32 if resident, else the resident split
+// form of smallest bound; -1 if none is resident.
+int choose_resident_form(uint32_t resident, int d, double a, double eps, double max_nrm_q, double max_nrm_x,
+                         float max_abs_q, float max_abs_x);
 int64_t query_tile_rows();
 stag_status launch_exact_tiles(const Operands& xo, const Operands& qo, double* partial, const TileExtra& ex,
                                hipStream_t st);

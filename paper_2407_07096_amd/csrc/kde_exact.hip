@@ -159,6 +159,31 @@ __global__ void reduce_partials(const double* __restrict__ partial, int P, int64
   }
 }
 
+// Centred fp32 data: S(q) = sum of chunk partials in chunk order; the
+// bound is (sum of the chunks' bound numerators) / S, plus its square and
+// c_tail (the numerators come from computed tile sums: first-order slack),
+// and infinite for S = 0.  Flags as in reduce_partials.
+__global__ void reduce_centred(const double* __restrict__ partial, const double* __restrict__ bpart, int P,
+                               int64_t m_pad, int64_t m, double scale, double c_tail, double* __restrict__ S_out,
+                               double* __restrict__ bound_out, int* __restrict__ flag, int* __restrict__ qtile_flag) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= m) return;
+  double s = 0.0, b = 0.0;
+  for (int p = 0; p < P; ++p) {
+    s += partial[(int64_t)p * m_pad + q];
+    b += bpart[(int64_t)p * m_pad + q];
+  }
+  if (flag && s < kRescueBelow) {
+    flag[q] = 1;
+    qtile_flag[q / kBQ] = 1;
+  }
+  S_out[q] = s * scale;
+  if (bound_out) {
+    const double r = b / s;
+    bound_out[q] = s > 0.0 ? r + r * r + c_tail : HUGE_VAL;
+  }
+}
+
 template <int FORM>
 stag_status launch_prep(const float* src, int64_t n, int d, int dp, int64_t rows_pad, double scale, double neg_a_l2e,
                         int is_query, void* const* parts, float* off, u16x8* aug, double* nrm,
@@ -273,7 +298,7 @@ stag_status prepare_operands(int form, const float* src, int64_t rows, int d, do
 int64_t exact_chunks(int64_t n_pad) { return ceil_div(n_pad, kChunkRows); }
 
 stag_status prep_query_into(int form, const float* src, int64_t rows, int d, double a, const Operands& batch,
-                            int64_t row0, hipStream_t st) {
+                            int64_t row0, hipStream_t st, bool centred) {
   const int dp = batch.dp;
   const int64_t rows_pad = round_up(rows, kBQ);
   const size_t eb = form_element_bytes(form);
@@ -281,8 +306,40 @@ stag_status prep_query_into(int form, const float* src, int64_t rows, int d, dou
   for (int p = 0; p < form_parts(form); ++p)
     parts[p] = static_cast<char*>(batch.part[p]) + (size_t)row0 * dp * eb;
   u16x8* aug = batch.aug ? static_cast<u16x8*>(batch.aug) + row0 : nullptr;
-  return prep_any(form, src, rows, d, dp, rows_pad, 2.0 * a * kLog2e, -a * kLog2e, 1, parts, batch.off + row0, aug,
-                  batch.nrm ? batch.nrm + row0 : nullptr, nullptr, st);
+  // queries of centred data are kept unscaled with offset 0 (the tile adds
+  // -a log2(e) ||q - c_T||^2 itself)
+  return prep_any(form, src, rows, d, dp, rows_pad, centred ? 1.0 : 2.0 * a * kLog2e, centred ? 0.0 : -a * kLog2e, 1,
+                  parts, batch.off + row0, aug, batch.nrm ? batch.nrm + row0 : nullptr, nullptr, st);
+}
+
+stag_status row_stats_async(const float* A, int64_t rows, int d, unsigned long long* nrm_bits, unsigned int* abs_bits,
+                            int* bad, hipStream_t st) {
+  STAG_TRY(zero_async(nrm_bits, sizeof(unsigned long long), st));
+  STAG_TRY(zero_async(abs_bits, sizeof(unsigned int), st));
+  STAG_TRY(zero_async(bad, sizeof(int), st));
+  hipLaunchKernelGGL(scan_rows, dim3((unsigned)ceil_div(rows, kPrepRowsPerBlock)), dim3(256), 0, st, A, rows, d,
+                     nrm_bits, abs_bits, bad);
+  return check_launch("scan_rows");
+}
+
+int choose_resident_form(uint32_t resident, int d, double a, double eps, double max_nrm_q, double max_nrm_x,
+                         float max_abs_q, float max_abs_x) {
+  const double qscale = 2.0 * a * kLog2e;
+  const bool fp16_ok = (double)max_abs_x < 65504.0 && (double)max_abs_q * qscale < 65504.0;
+  const int order[3] = {STAG_FORM_FP16_SPLIT, STAG_FORM_BF16_SPLIT, STAG_FORM_BF16_SPLIT3};
+  int best = -1;
+  double best_b = HUGE_VAL;
+  for (int f : order) {
+    if (!(resident & (1u << f)) || d > 256 || (f == STAG_FORM_FP16_SPLIT && !fp16_ok)) continue;
+    const double b = relative_bound(make_bound_model(f, d, a, STAG_KERNEL_GAUSSIAN), max_nrm_q, max_nrm_x);
+    if (b <= eps) return f;
+    if (b < best_b) {
+      best_b = b;
+      best = f;
+    }
+  }
+  if (resident & (1u << STAG_FORM_FP32)) return STAG_FORM_FP32;
+  return best;
 }
 
 int64_t query_tile_rows() { return kBQ; }
@@ -334,6 +391,11 @@ BoundModel make_bound_model(int form, int d, double a_tile, int kernel) {
   bm.c_split = c_split;
   bm.c_off = 3.0 * u;                   // alpha, beta rounded to fp32
   bm.c_tail = 0x1.0p-22 + 16.0 * u;     // exp2 and the 16-term fp32 tile sums
+  // centred fp32 tile (per term, times M_T): the MFMA accumulation and the
+  // fp32 sum of the d squared differences (c_acc each), the roundings of
+  // q - c, its scaling and x - c in the cross term (3u), beta, the final
+  // exponent add and the offset (3u), with 2u to spare
+  bm.c_cent = 2.0 * bm.c_acc + 8.0 * u;
   if (kernel == STAG_KERNEL_EXPONENTIAL) bm.near_y2 = kNearY2;
   return bm;
 }
@@ -377,6 +439,42 @@ __global__ void rescue_reduce(const double* __restrict__ partial, int P, int64_t
   if (bound_out) {
     const double xm = __longlong_as_double((long long)*max_xnrm_bits);
     bound_out[q] = relative_bound(bm, qnrm[q], xm, fabs(shift[q]));
+  }
+}
+
+// Centred data: a flagged query's offset becomes fl32(-m_q) (the tile adds it
+// to alpha'), others keep theirs (0).
+__global__ void rescue_shift_centred(const double* __restrict__ pmax, int P, int64_t m_pad, int64_t m,
+                                     const int* __restrict__ flag, const float* __restrict__ off,
+                                     float* __restrict__ off2, double* __restrict__ shift) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= m_pad) return;
+  double mq = 0.0;
+  float o = off[q];
+  if (q < m && flag[q]) {
+    mq = -HUGE_VAL;
+    for (int p = 0; p < P; ++p) mq = fmax(mq, pmax[(int64_t)p * m_pad + q]);
+    o = (float)(-mq);
+  }
+  off2[q] = o;
+  shift[q] = mq;
+}
+
+__global__ void rescue_reduce_centred(const double* __restrict__ partial, const double* __restrict__ bpart, int P,
+                                      int64_t m_pad, int64_t m, const int* __restrict__ flag,
+                                      const double* __restrict__ shift, double scale, double c_tail,
+                                      double* __restrict__ S_out, double* __restrict__ bound_out) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= m || !flag[q]) return;
+  double s = 0.0, b = 0.0;
+  for (int p = 0; p < P; ++p) {
+    s += partial[(int64_t)p * m_pad + q];
+    b += bpart[(int64_t)p * m_pad + q];
+  }
+  S_out[q] = s * exp2(shift[q]) * scale;
+  if (bound_out) {
+    const double r = b / s;
+    bound_out[q] = s > 0.0 ? r + r * r + c_tail : HUGE_VAL;
   }
 }
 
@@ -592,9 +690,30 @@ struct ExactBuffers {
   double* partial = nullptr;
   int* near_over = nullptr;  // exponential kernel
   RescueBuffers rb;
+  // centred data (fp32 form, Gaussian kernel, d <= 256)
+  bool centred = false;
+  CentreTemp ct;
+  double *bpart = nullptr, *bp2 = nullptr;
 };
 
+// The fp32 form of the Gaussian sum centres the data tile by tile (the wide
+// tile of d > 256 does not).
+bool use_centred(int form, int kernel, int d) {
+  return form == STAG_FORM_FP32 && kernel == STAG_KERNEL_GAUSSIAN && exact_padded_dim(d) <= 256;
+}
+
 stag_status alloc_exact(int form, int kernel, int64_t n, int64_t m, int d, Workspace& ws, ExactBuffers* b) {
+  if (use_centred(form, kernel, d)) {
+    b->centred = true;
+    STAG_TRY(alloc_centred_operands(n, d, ws, &b->xo));
+    STAG_TRY(alloc_centre_temp(b->xo, ws, &b->ct));
+    STAG_TRY(alloc_operands(STAG_FORM_FP32, m, d, true, ws, &b->qo));
+    b->P = (int)exact_chunks(b->xo.rows_pad);
+    STAG_TRY(ws.alloc(&b->partial, (size_t)b->P * b->qo.rows_pad));
+    STAG_TRY(ws.alloc(&b->bpart, (size_t)b->P * b->qo.rows_pad));
+    STAG_TRY(ws.alloc(&b->bp2, (size_t)b->P * b->qo.rows_pad));
+    return alloc_rescue(kernel, b->P, b->qo, ws, &b->rb);
+  }
   STAG_TRY(alloc_operands(form, n, d, false, ws, &b->xo));
   STAG_TRY(alloc_operands(form, m, d, true, ws, &b->qo));
   b->P = (int)exact_chunks(b->xo.rows_pad);
@@ -603,10 +722,57 @@ stag_status alloc_exact(int form, int kernel, int64_t n, int64_t m, int d, Works
   return alloc_rescue(kernel, b->P, b->qo, ws, &b->rb);
 }
 
+// Centred fp32 Gaussian sum: grouping and centring of X, the unscaled query
+// copy, the centred tiles with their bound numerators, the reduction, and the
+// underflow rescue (max pass, offsets -m_q, second pass) on the same tiles.
+stag_status run_centred(const float* X, int64_t n, const float* Q, int64_t m, int32_t d, double a, uint32_t flags,
+                        double* S_out, double* bound_out, const ExactBuffers& b, hipStream_t st) {
+  const Operands& xo = b.xo;
+  const Operands& qo = b.qo;
+  const RescueBuffers& rb = b.rb;
+  STAG_TRY(prep_centred_operands(X, a, xo, b.ct, st));
+  STAG_TRY(prep_any(STAG_FORM_FP32, Q, m, d, qo.dp, qo.rows_pad, 1.0, 0.0, 1, qo.part, qo.off, nullptr, qo.nrm,
+                    nullptr, st));
+  const BoundModel bm = make_bound_model(STAG_FORM_FP32, d, a, STAG_KERNEL_GAUSSIAN);
+  TileExtra ex;
+  ex.a = a;
+  ex.bpart = b.bpart;
+  ex.c_cent = (float)bm.c_cent;
+  STAG_TRY(launch_exact_tiles(xo, qo, b.partial, ex, st));
+  const double scale = (flags & STAG_NORMALIZE) ? 1.0 / (double)n : 1.0;
+  const int64_t m_pad = qo.rows_pad;
+  STAG_TRY(zero_async(rb.flag, (size_t)m * sizeof(int), st));
+  STAG_TRY(zero_async(rb.qflag, (size_t)(m_pad / kBQ) * sizeof(int), st));
+  {
+    ScopedTimer tm("kde_reduce", st);
+    hipLaunchKernelGGL(reduce_centred, dim3((unsigned)ceil_div(m, 256)), dim3(256), 0, st, b.partial, b.bpart, b.P,
+                       m_pad, m, scale, bm.c_tail, S_out, bound_out, rb.flag, rb.qflag);
+    STAG_TRY(check_launch("reduce_centred"));
+  }
+  TileExtra exm;
+  exm.max_pass = 1;
+  exm.qtile_active = rb.qflag;
+  exm.a = a;
+  STAG_TRY(launch_exact_tiles(xo, qo, rb.pmax, exm, st));
+  hipLaunchKernelGGL(rescue_shift_centred, dim3((unsigned)ceil_div(m_pad, 256)), dim3(256), 0, st, rb.pmax, b.P,
+                     m_pad, m, rb.flag, qo.off, rb.off2, rb.shift);
+  STAG_TRY(check_launch("rescue_shift_centred"));
+  Operands q2 = qo;
+  q2.off = rb.off2;
+  TileExtra exs = ex;
+  exs.qtile_active = rb.qflag;
+  exs.bpart = b.bp2;
+  STAG_TRY(launch_exact_tiles(xo, q2, rb.p2, exs, st));
+  hipLaunchKernelGGL(rescue_reduce_centred, dim3((unsigned)ceil_div(m, 256)), dim3(256), 0, st, rb.p2, b.bp2, b.P,
+                     m_pad, m, rb.flag, rb.shift, scale, bm.c_tail, S_out, bound_out);
+  return check_launch("rescue_reduce_centred");
+}
+
 // The launches of one exact call into buffers from alloc_exact.
 stag_status run_exact(const float* X, int64_t n, const float* Q, int64_t m, int32_t d, int32_t kernel, double a,
                       int32_t form, uint32_t flags, double* S_out, double* bound_out, const ExactBuffers& b,
                       hipStream_t stream) {
+  if (b.centred) return run_centred(X, n, Q, m, d, a, flags, S_out, bound_out, b, stream);
   const double at = kernel_tile_a(kernel, a);
   STAG_TRY(prep_operands(X, at, false, b.xo, stream));
   STAG_TRY(prep_operands(Q, at, true, b.qo, stream));

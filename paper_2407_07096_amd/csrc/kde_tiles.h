@@ -411,6 +411,190 @@ __global__ __launch_bounds__(256, 2) void tile_f32(const float* __restrict__ Xp,
   if (h == 0) partial[(int64_t)chunk * m_pad + qi] = acc_add<MODE>(acc, other);
 }
 
+// Centred fp32 form: the data rows are grouped into compact 32-row tiles,
+// each stored as fl32(x - c_T) with beta = -a log2(e) ||x - c_T||^2 and its
+// centre c_T and radius R_T (kde_centre.hip).  As tile_f32, but the queries
+// (unscaled fp32) are re-centred on every tile: the B operand of dimension k
+// is b = fl(s fl(q_k - c_k)), s = 2 a log2(e), the accumulators start from
+// beta, and alpha' = -a log2(e) ||q - c_T||^2 (fp32 sum of the squared
+// differences of both lane halves) plus the query's offset off[q] (0, or the
+// shift -m_q of the underflow rescue) is added to the 16 exponents before
+// the epilogue.  For the bound, each lane adds the tile's kernel sum times
+// 2^{c_cent M_T} - 1, M_T = la (||q - c_T|| + R_T)^2 + |off[q]|, to a second
+// fp64 accumulator (every term of the tile has an exponent error of at most
+// c_cent M_T), written to ex.bpart.  The padded row count is read from the
+// device (*n_pad); chunks past it write the neutral partial.
+__device__ inline float centred_bound_factor(float sqt, float R, float qoff, float la, float c_cent) {
+  const float r = __builtin_amdgcn_sqrtf(sqt) + R;
+  const float M = (la * r * r + fabsf(qoff)) * 1.000001f;
+  const float x = c_cent * M * 0.6931472f;
+  // e^x - 1 <= x (1 + x) on [0, 1]; beyond, 2^{c M} - 1 itself (kept finite
+  // so that a zero tile sum times it stays 0)
+  const float e = x <= 1.0f ? x * (1.0f + x) : __builtin_amdgcn_exp2f(c_cent * M) - 1.0f;
+  return fminf(e, 3.0e38f);
+}
+
+template <int DP, int MODE>
+__global__ __launch_bounds__(256, 2) void tile_f32c(const float* __restrict__ Xp, const float* __restrict__ beta,
+                                                    const float* __restrict__ cen, const float* __restrict__ rad,
+                                                    const int64_t* __restrict__ n_pad_dev, const float* __restrict__ Qu,
+                                                    const float* __restrict__ qoff, float la, int n_qtiles,
+                                                    int64_t m_pad, double* __restrict__ partial, TileExtra ex) {
+  constexpr int H = DP / 2;
+  constexpr int LD = DP + 4;
+  constexpr int F4_ROW = DP / 4;
+  constexpr int NV = kTileRows * F4_ROW;
+  constexpr int NLD = (NV + 255) / 256;
+  constexpr int NMMA = H;
+  __shared__ __attribute__((aligned(16))) float tile[2][kTileRows * LD];
+  __shared__ __attribute__((aligned(16))) float tbeta[2][kTileRows];
+  __shared__ __attribute__((aligned(16))) float tcen[2][DP];
+  __shared__ float trad[2];
+
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, r32 = lane & 31, h = lane >> 5;
+  const int qtile = blockIdx.x % n_qtiles;
+  const int chunk = blockIdx.x / n_qtiles;
+  const int64_t col_base = (int64_t)qtile * kBQ + wave * 32;
+  const int64_t qi = col_base + r32;
+  if (ex.qtile_active && ex.qtile_active[qtile] == 0) return;  // whole block: no query of its tile is active
+  const int64_t n_pad = *n_pad_dev;
+  const int64_t row0 = (int64_t)chunk * kChunkRows;
+  if (row0 >= n_pad) {
+    if (h == 0) {
+      partial[(int64_t)chunk * m_pad + qi] = acc_init<MODE>();
+      if (ex.bpart) ex.bpart[(int64_t)chunk * m_pad + qi] = 0.0;
+    }
+    return;
+  }
+  const float s2 = 2.0f * la;
+  const float c_cent = ex.c_cent;
+  float bq[H];
+  {
+    const f32x4* qrow = reinterpret_cast<const f32x4*>(Qu + qi * DP + h * H);
+#pragma unroll
+    for (int s = 0; s < H / 4; ++s) {
+      f32x4 v = qrow[s];
+      bq[4 * s] = v.x; bq[4 * s + 1] = v.y; bq[4 * s + 2] = v.z; bq[4 * s + 3] = v.w;
+    }
+  }
+  const float qo = qoff[qi];
+
+  const int64_t rem = (n_pad - row0) / kTileRows;
+  const int ntiles = (int)(rem < kChunkRows / kTileRows ? rem : kChunkRows / kTileRows);
+  const int64_t tile0 = row0 / kTileRows;
+
+  f32x4 stage[NLD];
+  float sbeta;
+  f32x4 scen = {0.0f, 0.0f, 0.0f, 0.0f};
+  float srad = 0.0f;
+  auto gload = [&](int t) {
+    const f32x4* srcp = reinterpret_cast<const f32x4*>(Xp + (row0 + (int64_t)t * kTileRows) * DP);
+#pragma unroll
+    for (int k = 0; k < NLD; ++k) stage[k] = srcp[min(tid + 256 * k, NV - 1)];
+    sbeta = beta[row0 + (int64_t)t * kTileRows + (tid & 31)];
+    const int64_t tg = tile0 + t;
+    if (tid < F4_ROW) scen = reinterpret_cast<const f32x4*>(cen + tg * DP)[tid];
+    srad = rad[tg];
+  };
+  auto lstore = [&](int buf) {
+#pragma unroll
+    for (int k = 0; k < NLD; ++k) {
+      const int idx = min(tid + 256 * k, NV - 1);
+      const int r = idx / F4_ROW, c4 = idx % F4_ROW;
+      *reinterpret_cast<f32x4*>(&tile[buf][r * LD + c4 * 4]) = stage[k];
+    }
+    tbeta[buf][tid & 31] = sbeta;
+    if (tid < F4_ROW) *reinterpret_cast<f32x4*>(&tcen[buf][4 * tid]) = scen;
+    if (tid == 0) trad[buf] = srad;
+  };
+
+  double acc = acc_init<MODE>();
+  double bacc = 0.0;
+  auto epilogue = [&](const f32x16& cdone, float adone, float edone) {
+    float e[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) e[i] = cdone[i] + adone;
+    if constexpr (MODE == kModeMax) {
+      float mx = e[0];
+#pragma unroll
+      for (int i = 1; i < 16; ++i) mx = fmaxf(mx, e[i]);
+      acc = acc_add<MODE>(acc, (double)mx);
+    } else {
+      const float sum = kernel_tile_sum<MODE>(e);
+      acc += (double)sum;
+      bacc += (double)(sum * edone);
+    }
+  };
+  auto step = [&](int t, const f32x16& cdone, float adone, float edone, f32x16& cnew, float& anew, float& enew) {
+    const int buf = t & 1;
+    __syncthreads();
+    epilogue(cdone, adone, edone);
+    const float* arow = &tile[buf][r32 * LD + h * H];
+    const float* crow = &tcen[buf][h * H];
+    f32x16 c;
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+      const f32x4 bv = *reinterpret_cast<const f32x4*>(&tbeta[buf][8 * g + 4 * h]);
+      c[4 * g] = bv.x;
+      c[4 * g + 1] = bv.y;
+      c[4 * g + 2] = bv.z;
+      c[4 * g + 3] = bv.w;
+    }
+    float sq = 0.0f;
+#pragma unroll
+    for (int s = 0; s < H; s += 4) {
+      const f32x4 a4 = *reinterpret_cast<const f32x4*>(arow + s);
+      const f32x4 c4 = *reinterpret_cast<const f32x4*>(crow + s);
+      const float d0 = bq[s] - c4.x, d1 = bq[s + 1] - c4.y, d2 = bq[s + 2] - c4.z, d3 = bq[s + 3] - c4.w;
+      sq = fmaf(d0, d0, sq);
+      sq = fmaf(d1, d1, sq);
+      sq = fmaf(d2, d2, sq);
+      sq = fmaf(d3, d3, sq);
+      c = __builtin_amdgcn_mfma_f32_32x32x2f32(a4.x, d0 * s2, c, 0, 0, 0);
+      c = __builtin_amdgcn_mfma_f32_32x32x2f32(a4.y, d1 * s2, c, 0, 0, 0);
+      c = __builtin_amdgcn_mfma_f32_32x32x2f32(a4.z, d2 * s2, c, 0, 0, 0);
+      c = __builtin_amdgcn_mfma_f32_32x32x2f32(a4.w, d3 * s2, c, 0, 0, 0);
+    }
+    const float sqt = sq + __shfl_xor(sq, 32);
+    cnew = c;
+    anew = -la * sqt + qo;
+    enew = MODE == kModeMax ? 0.0f : centred_bound_factor(sqt, trad[buf], qo, la, c_cent);
+    lstore(buf ^ 1);
+    gload(min(t + 2, ntiles - 1));
+#pragma unroll
+    for (int i = 0; i < NMMA; ++i) {
+      __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+      __builtin_amdgcn_sched_group_barrier(0x002, (40 + 3 * H + NMMA - 1) / NMMA, 0);
+    }
+  };
+
+  gload(0);
+  lstore(0);
+  gload(min(1, ntiles - 1));
+  f32x16 ca, cb;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) ca[i] = kPadOffset;  // kernel value 0: neutral first epilogue
+  float aa = 0.0f, ab = 0.0f, ea = 0.0f, eb = 0.0f;
+  int t = 0;
+  for (; t + 1 < ntiles; t += 2) {
+    step(t, ca, aa, ea, cb, ab, eb);
+    step(t + 1, cb, ab, eb, ca, aa, ea);
+  }
+  if (t < ntiles) {
+    step(t, ca, aa, ea, cb, ab, eb);
+    ca = cb;
+    aa = ab;
+    ea = eb;
+  }
+  epilogue(ca, aa, ea);
+  const double other = __shfl_down(acc, 32);
+  const double bother = __shfl_down(bacc, 32);
+  if (h == 0) {
+    partial[(int64_t)chunk * m_pad + qi] = acc_add<MODE>(acc, other);
+    if (ex.bpart) ex.bpart[(int64_t)chunk * m_pad + qi] = bacc + bother;
+  }
+}
+
 // Split forms: v_mfma_f32_32x32x16_{f16,bf16}.  Lane l supplies 8 consecutive
 // k values of row/column l%32; lane half h covers dimensions
 // [16 s + 8 h, 16 s + 8 h + 8) of k-step s.
@@ -719,13 +903,46 @@ stag_status dispatch_f32(int dp, const float* Xp, const float* beta, const float
   }
   return fail(STAG_E_UNSUPPORTED, "padded dimension %d not instantiated", dp);
 }
+template <int DP, int MODE>
+stag_status launch_tile_f32c(const Operands& xo, const Operands& qo, float la, int n_qtiles, int P, double* partial,
+                             const TileExtra& ex, hipStream_t st) {
+  ScopedTimer tm(rescue_timer(ex, "kde_tile_f32c"), st);
+  hipLaunchKernelGGL((tile_f32c<DP, MODE>), dim3((unsigned)((int64_t)n_qtiles * P)), dim3(256), 0, st,
+                     (const float*)xo.part[0], xo.off, xo.centre, xo.radius, xo.n_pad_dev, (const float*)qo.part[0],
+                     qo.off, la, n_qtiles, qo.rows_pad, partial, ex);
+  return check_launch("tile_f32c");
+}
+
+template <int MODE>
+stag_status dispatch_f32c(const Operands& xo, const Operands& qo, float la, int n_qtiles, int P, double* partial,
+                          const TileExtra& ex, hipStream_t st) {
+  switch (xo.dp) {
+    case 16: return launch_tile_f32c<16, MODE>(xo, qo, la, n_qtiles, P, partial, ex, st);
+    case 32: return launch_tile_f32c<32, MODE>(xo, qo, la, n_qtiles, P, partial, ex, st);
+    case 64: return launch_tile_f32c<64, MODE>(xo, qo, la, n_qtiles, P, partial, ex, st);
+    case 96: return launch_tile_f32c<96, MODE>(xo, qo, la, n_qtiles, P, partial, ex, st);
+    case 128: return launch_tile_f32c<128, MODE>(xo, qo, la, n_qtiles, P, partial, ex, st);
+    case 160: return launch_tile_f32c<160, MODE>(xo, qo, la, n_qtiles, P, partial, ex, st);
+    case 192: return launch_tile_f32c<192, MODE>(xo, qo, la, n_qtiles, P, partial, ex, st);
+    case 224: return launch_tile_f32c<224, MODE>(xo, qo, la, n_qtiles, P, partial, ex, st);
+    case 256: return launch_tile_f32c<256, MODE>(xo, qo, la, n_qtiles, P, partial, ex, st);
+  }
+  return fail(STAG_E_UNSUPPORTED, "padded dimension %d not instantiated", xo.dp);
+}
+
 // All tiles of one launch in epilogue mode MODE: wide fp32 rows, the fp32
-// tile or a split form, by padded dimension.
+// tile, the centred fp32 tile or a split form, by padded dimension.
 template <int MODE>
 stag_status launch_tiles(const Operands& xo, const Operands& qo, double* partial, const TileExtra& ex,
                          hipStream_t st) {
   const int P = (int)exact_chunks(xo.rows_pad);
   const int n_qtiles = (int)(qo.rows_pad / kBQ);
+  if (xo.centred) {
+    if constexpr (MODE == kModeGauss || MODE == kModeGaussRescue || MODE == kModeMax)
+      return dispatch_f32c<MODE>(xo, qo, (float)(ex.a * kLog2e), n_qtiles, P, partial, ex, st);
+    else
+      return fail(STAG_E_UNSUPPORTED, "centred data: Gaussian sums only");
+  }
   if (xo.dp > 256) {
     if (xo.form != STAG_FORM_FP32) return fail(STAG_E_UNSUPPORTED, "d > 256 needs the fp32 form");
     const int n_qt32 = (int)(qo.rows_pad / 32);
