@@ -37,7 +37,7 @@ if ROOT not in sys.path:
 
 MFMA_PEAK = {"fp32": 157.3e12, "fp16_split": 2.5e15, "bf16_split": 2.5e15, "bf16_split3": 2.5e15}
 PRODUCTS = {"fp32": 1, "fp16_split": 3, "bf16_split": 3, "bf16_split3": 6}
-TILE_KERNEL = {"fp32": "kde_tile_f32", "fp16_split": "kde_tile_fp16x3", "bf16_split": "kde_tile_bf16x3",
+TILE_KERNEL = {"fp32": "kde_tile_f32c", "fp16_split": "kde_tile_fp16x3", "bf16_split": "kde_tile_bf16x3",
                "bf16_split3": "kde_tile_bf16x6"}
 DTYPE = {"fp32": "f32", "fp16_split": "f16x3->f32->f64", "bf16_split": "bf16x3->f32->f64",
          "bf16_split3": "bf16x6->f32->f64"}
@@ -585,83 +585,133 @@ def e2lsh_table_run(stag, torch, dev, lib, buf, Xd, Qd, K: int = 6, L: int = 50)
             "queries_per_s": m / (t2 - t1), "listed_per_s": total / (t2 - t1)}
 
 
-def serving_run(stag, torch, dev, n_requests: int, seconds_cap: float):
+def serving_run(stag, torch, dev, n_requests: int, seconds_cap: float, eps: float = 1e-3, lsh_share: float = 0.1,
+                cmp_requests: int = 600, cmp_eps: float = 3e-3):
     """Requests of log-uniform size (1..65536) against four resident data
-    sets.  A burst submitted at once measures the saturation throughput;
-    Poisson streams of n_requests requests at 0.5, 0.8 and 0.95 of the
-    saturation request rate then give latency percentiles and throughput at
-    each load (0.5 is the headline figure).  Each request's queries are a
+    sets, each held in fp32 (centred tiles), bf16 split and fp16 split with a
+    CKNS index.  Mixed stream: exact requests with a stated accuracy eps (the
+    form chosen per request by the STAG_FORM_AUTO rule) and a share of LSH
+    requests; a burst submitted at once measures the saturation throughput,
+    then Poisson streams of n_requests requests at 0.5, 0.8 and 0.95 of the
+    saturation request rate give latency percentiles (overall and per form)
+    and throughput (0.5 is the headline figure).  Equal-accuracy comparison
+    at the stated accuracy cmp_eps (the bf16 split form's largest bound on
+    these data sets is about 2e-3): the same exact requests in the fp32, bf16
+    split and fp16 split forms, each as a burst (saturation) and as a Poisson
+    stream at half of the fp32 saturation rate, with the largest bound seen.  Each request's queries are a
     contiguous slice of a resident pool of 65,536 draws from its data set's
     mixture (no host traffic per request)."""
     import numpy as np
 
     import synth
     specs = [(100_000, 16), (300_000, 64), (1_000_000, 256), (2_000_000, 64)]
-    srv = stag.Server(budget_bytes=16 << 30, n_streams=4, max_batch_queries=65536)
+    lsh = dict(eps=0.5, k1=1, k2_constant=8, p_offset=1, seed=3005)
+    with_index = (0, 1)  # CKNS indexes on the two smaller data sets (the estimator's work grows with n)
+    srv = stag.Server(budget_bytes=24 << 30, n_streams=4, max_batch_queries=65536, chunk_queries=4096)
     ids, pools = [], []
     for k, (n, d) in enumerate(specs):
         mix = synth.mixture(d, 20, 4005 + 10 * k, sigma=(0.5, 2.0))
         X = torch.from_numpy(synth.sample(mix, n, 4105 + 10 * k)).to(dev)
-        form = "fp16_split" if d <= 256 else "fp32"
-        ids.append(srv.add_dataset(X, 0.64 / d, form))
+        ids.append(srv.add_dataset(X, 0.64 / d, ["fp32", "bf16_split", "fp16_split"],
+                                   lsh=lsh if k in with_index else None))
         pools.append(torch.from_numpy(synth.sample(mix, 65536, 4205 + 10 * k)).to(dev))
         del X
     torch.cuda.synchronize()
+    print("[bench] serving: data sets resident", file=sys.stderr, flush=True)
 
-    def make(count, rate, seed):
+    def make(count, rate, seed, kinds):
         arr, sizes, dsel = synth.poisson_requests(count, rate_per_s=rate, seed=seed)
+        u = np.random.default_rng(seed + 1).random(count)
         reqs = []
         for r in range(count):
             k, mr = int(dsel[r]), int(sizes[r])
             off = (r * 7919) % (65536 - mr + 1)
-            reqs.append((k, pools[k][off:off + mr]))
+            if isinstance(kinds, str):
+                kind = kinds
+            else:
+                kind = "lsh" if (k in with_index and u[r] < lsh_share / (len(with_index) / len(specs))) else "auto"
+            reqs.append((k, pools[k][off:off + mr], kind))
         return arr, reqs
 
     def run(arr, reqs, paced):
         t_start = time.perf_counter()
         tickets = []
-        for r, (k, Q) in enumerate(reqs):
+        for r, (k, Q, kind) in enumerate(reqs):
             if paced:
                 now = time.perf_counter() - t_start
                 if arr[r] > now:
                     time.sleep(arr[r] - now)
             if time.perf_counter() - t_start > seconds_cap:
                 break
-            tickets.append((srv.submit(ids[k], Q), Q.shape[0], specs[k][0]))
-        lat, evals = [], 0.0
-        for t, m, n in tickets:
+            if kind == "lsh":
+                t = srv.submit(ids[k], Q, lsh=True)
+            else:
+                t = srv.submit(ids[k], Q, form=kind, eps=eps, bound=True)
+            tickets.append((t, srv.form_of(t) or "lsh", Q.shape[0], specs[k][0]))
+        lat, evals, by, bmax = [], 0.0, {}, 0.0
+        for t, f, m, n in tickets:
             _, st, l = srv.wait(t)
+            B = srv.bound_of(t)
             if st == 0:
                 lat.append(l)
-                evals += float(m) * n
+                by.setdefault(f, []).append(l)
+                if f != "lsh":
+                    evals += float(m) * n
+                    bmax = max(bmax, float(B.max().item()))
         t_end = time.perf_counter()
-        lat = np.sort(np.array(lat))
 
-        def pct(p):
-            return float(lat[max(0, math.ceil(p / 100 * len(lat)) - 1)]) * 1e3 if len(lat) else None
-        return {"requests": len(tickets), "completed": len(lat), "p50_ms": pct(50), "p99_ms": pct(99),
-                "evals_per_s": evals / (t_end - t_start), "evals": evals, "wall_s": t_end - t_start}
+        def pct(v, p):
+            v = np.sort(np.array(v))
+            return float(v[max(0, math.ceil(p / 100 * len(v)) - 1)]) * 1e3 if len(v) else None
+        return {"requests": len(tickets), "completed": len(lat), "p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99),
+                "exact_evals_per_s": evals / (t_end - t_start), "exact_evals": evals, "wall_s": t_end - t_start,
+                "max_bound": bmax,
+                "per_form": {f: {"requests": len(v), "p50_ms": pct(v, 50), "p99_ms": pct(v, 99)}
+                             for f, v in sorted(by.items())}}
 
-    # saturation: a burst of requests submitted at once
-    arr, reqs = make(min(n_requests, 1000), 1.0, 4005)
+    # mixed stream: saturation burst, then three loads
+    arr, reqs = make(min(n_requests, 1000), 1.0, 4005, None)
     burst = run(arr, reqs, paced=False)
-    evals_per_req = burst["evals"] / max(burst["requests"], 1)
-    sat_rate = burst["evals_per_s"] / evals_per_req
+    req_rate = burst["requests"] / burst["wall_s"]
+    print(f"[bench] serving: saturation {req_rate:.1f} requests/s", file=sys.stderr, flush=True)
     loads = []
     for li, rho in enumerate((0.5, 0.8, 0.95)):
-        rate = rho * sat_rate
-        arr, reqs = make(n_requests, rate, 4006 + li)
+        arr, reqs = make(n_requests, rho * req_rate, 4006 + li, None)
         r = run(arr, reqs, paced=True)
-        r.update({"rho": rho, "offered_rate_per_s": rate})
+        r.update({"rho": rho, "offered_rate_per_s": rho * req_rate})
         loads.append(r)
+        print(f"[bench] serving: load {rho} p50 {r['p50_ms']:.2f} ms p99 {r['p99_ms']:.2f} ms", file=sys.stderr,
+              flush=True)
+    # equal stated accuracy: fp32 vs bf16 split, exact requests only
+    cmp = {}
+    cmp_forms = ("fp32", "bf16_split", "fp16_split")
+    arr_b, reqs_b = make(min(cmp_requests, 400), 1.0, 4010, "x")
+    for form in cmp_forms:
+        rb = run(arr_b, [(k, Q, form) for k, Q, _ in reqs_b], paced=False)
+        cmp[form] = {"saturation_exact_evals_per_s": rb["exact_evals_per_s"],
+                     "saturation_request_rate_per_s": rb["requests"] / rb["wall_s"], "max_bound": rb["max_bound"]}
+    print("[bench] serving: equal-accuracy bursts done", file=sys.stderr, flush=True)
+    rate32 = 0.5 * cmp["fp32"]["saturation_request_rate_per_s"]
+    arr_c, reqs_c = make(cmp_requests, rate32, 4011, "x")
+    for form in cmp_forms:
+        r = run(arr_c, [(k, Q, form) for k, Q, _ in reqs_c], paced=True)
+        cmp[form].update({"load": {"offered_rate_per_s": rate32, "requests": r["requests"], "p50_ms": r["p50_ms"],
+                                   "p99_ms": r["p99_ms"], "exact_evals_per_s": r["exact_evals_per_s"],
+                                   "max_bound": r["max_bound"]}})
+    cmp["stated_accuracy"] = cmp_eps
+    cmp["all_within_stated_accuracy"] = bool(max(cmp[f]["max_bound"] for f in cmp_forms) <= cmp_eps)
+    cmp["bf16_split_over_fp32_saturation"] = (cmp["bf16_split"]["saturation_exact_evals_per_s"] /
+                                              cmp["fp32"]["saturation_exact_evals_per_s"])
     stats = srv.stats()
     srv.close()
     head = loads[0]
-    return {"p50_ms": head["p50_ms"], "p99_ms": head["p99_ms"], "evals_per_s": head["evals_per_s"],
-            "headline_load": 0.5, "saturation_evals_per_s": burst["evals_per_s"],
-            "saturation_request_rate_per_s": sat_rate, "loads": loads, "completed": int(stats["completed"]),
+    return {"p50_ms": head["p50_ms"], "p99_ms": head["p99_ms"], "exact_evals_per_s": head["exact_evals_per_s"],
+            "headline_load": 0.5, "stated_accuracy": eps, "lsh_share": lsh_share,
+            "saturation": burst, "saturation_request_rate_per_s": req_rate, "loads": loads,
+            "equal_accuracy_forms": cmp, "completed": int(stats["completed"]),
             "batches": int(stats["batches"]), "datasets": [f"n={n} d={d}" for n, d in specs],
-            "batch_sizes": "log-uniform 1..65536", "requests_per_load": n_requests}
+            "resident_forms": ["fp32 (centred)", "bf16_split", "fp16_split"], "lsh_index": lsh,
+            "chunk_queries": 4096, "batch_sizes": "log-uniform 1..65536", "requests_per_load": n_requests}
 
 
 HERE = os.path.dirname(os.path.abspath(__file__))

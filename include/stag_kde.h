@@ -479,21 +479,37 @@ stag_status stag_spectral_cluster(int64_t n, const int64_t* src, const int64_t* 
                                   int32_t k, uint64_t seed, int32_t* labels_out, hipStream_t stream);
 
 /* ------------------------------------------------------------------------
- * Serving loop: continuous batching of exact kernel-density requests against
+ * Serving loop: continuous batching of kernel-density requests against
  * resident data sets.
- *   - A data set (X, a, form) is prepared once and stays in device memory.
- *   - Requests (Q [m][d] device fp32, S_out [m] device f64) are queued FIFO;
- *     a request is admitted when its workspace footprint fits the remaining
- *     budget (larger than the whole budget: status STAG_E_BUSY).
- *   - Every idle stream packs admitted requests of one data set (oldest
- *     first, up to max_batch_queries queries) into one launch; requests that
- *     arrive while others run are admitted as memory frees up and run
- *     concurrently on the other streams.
- *   - A result is bitwise identical whether its request ran alone or batched.
- * Q must be fully written before submission (synchronise its producer);
- * S_out is valid once wait/poll reports the request done.  A worker thread
- * owned by the server drives the loop; every function is thread safe.
- * Latency is measured from submission to completion.
+ *   - A data set (X, a) is prepared once and stays in device memory in each
+ *     of its resident exact forms (a bit mask of 1 << STAG_FORM_*; the fp32
+ *     form with its data tiles centred as in stag_kde_exact) and, on
+ *     request, with a CKNS index (stag_lsh_index_create with lsh_eps and the
+ *     given parameters) for LSH requests.
+ *   - A request is exact (in a resident form, or STAG_FORM_AUTO: the form
+ *     the stag_kde_exact rule picks among the resident ones for eps, from
+ *     the largest norms of the request's queries and of X; without a split
+ *     form whose a-priori bound is <= eps, fp32 if resident) or LSH (the
+ *     resident index's estimate, stag_lsh_index_query).
+ *   - Requests are queued FIFO and admitted when their workspace footprint
+ *     fits the remaining budget (larger than the whole budget: status
+ *     STAG_E_BUSY).
+ *   - An admitted request is served in chunks of at most chunk_queries
+ *     queries.  Every idle stream takes the oldest admitted request with
+ *     rows left and packs the next chunk of every admitted request of the
+ *     same data set and kind/form (arrival order, one chunk per request) up
+ *     to max_batch_queries queries and 1024 chunks into one batch; small
+ *     requests arriving behind a large one share its next batches.
+ *   - A result is bitwise identical whether its request ran alone, chunked
+ *     or batched, and equal to stag_kde_exact in the same form (exact; the
+ *     serving loop has no underflow rescue, so sums below 2^-60 keep the
+ *     tile's accuracy) or to stag_lsh_index_query on the same index (LSH).
+ * Q must be fully written before submission and X before it is added
+ * (synchronise their producers: the server works on streams of its own).
+ * S_out (and bound_out) are valid once wait/poll reports the request done.
+ * A worker thread owned by the server drives the loop and one host thread
+ * per stream issues its batches; every function is thread safe.  Latency
+ * is measured from submission to completion.
  * ------------------------------------------------------------------------ */
 typedef struct stag_server stag_server;
 
@@ -503,12 +519,32 @@ typedef struct {
   uint64_t inflight_bytes, peak_inflight_bytes;
 } stag_server_stats_t;
 
-/* budget_bytes 0: 8 GiB; n_streams 0: 4 (at most 16); max_batch_queries 0: 65536. */
+#define STAG_REQUEST_EXACT 0
+#define STAG_REQUEST_LSH 1
+
+/* budget_bytes 0: 8 GiB; n_streams 0: 4 (at most 16); max_batch_queries 0:
+ * 65536; chunk_queries 0: 4096. */
 stag_status stag_server_create(size_t budget_bytes, int32_t n_streams, int64_t max_batch_queries,
-                               stag_server** out);
-/* X [n][d] device fp32 (copied into the server's prepared operands). */
+                               int64_t chunk_queries, stag_server** out);
+/* X [n][d] device fp32 (prepared into the server's own buffers).  forms: bit
+ * mask of resident exact forms (0 allowed with an index); d > 256: fp32
+ * only.  lsh: NULL for no index, else the CKNS parameters (eps = lsh_eps in
+ * (0, 1)).  Synchronises.  Errors: STAG_E_INVAL, STAG_E_UNSUPPORTED,
+ * STAG_E_NOMEM. */
+stag_status stag_server_add_dataset_ex(stag_server* s, const float* X, int64_t n, int32_t d, double a, uint32_t forms,
+                                       double lsh_eps, const stag_lsh_params* lsh, int32_t* id_out);
+/* One resident exact form, no index. */
 stag_status stag_server_add_dataset(stag_server* s, const float* X, int64_t n, int32_t d, double a, int32_t form,
                                     int32_t* id_out);
+/* kind STAG_REQUEST_EXACT or STAG_REQUEST_LSH; form a resident form or
+ * STAG_FORM_AUTO with eps > 0 (exact only; the AUTO choice scans Q on the
+ * device and waits for it); S_out [m] f64 device; bound_out [m] f64 device
+ * or NULL (exact only: the per-result bound of the chosen form); form_out
+ * (host, or NULL) receives the form (-1 for LSH). */
+stag_status stag_server_submit_ex(stag_server* s, int32_t dataset, const float* Q, int64_t m, int32_t kind,
+                                  int32_t form, double eps, double* S_out, double* bound_out, int32_t* form_out,
+                                  uint64_t* ticket);
+/* Exact, in the data set's first resident form (lowest form number). */
 stag_status stag_server_submit(stag_server* s, int32_t dataset, const float* Q, int64_t m, double* S_out,
                                uint64_t* ticket);
 /* Blocks until the request is done; *result is its status. */

@@ -110,11 +110,16 @@ def load():
     lib.stag_simgraph_sample.restype = C.c_int
     lib.stag_simgraph_sample.argtypes = [vp, i64, i32, f64, i32, i32, i32, f64, pp, C.c_uint64, vp, vp, vp, vp, vp]
     lib.stag_server_create.restype = C.c_int
-    lib.stag_server_create.argtypes = [C.c_size_t, i32, i64, C.POINTER(vp)]
+    lib.stag_server_create.argtypes = [C.c_size_t, i32, i64, i64, C.POINTER(vp)]
     lib.stag_server_add_dataset.restype = C.c_int
     lib.stag_server_add_dataset.argtypes = [vp, vp, i64, i32, f64, i32, C.POINTER(C.c_int32)]
+    lib.stag_server_add_dataset_ex.restype = C.c_int
+    lib.stag_server_add_dataset_ex.argtypes = [vp, vp, i64, i32, f64, u32, f64, pp, C.POINTER(C.c_int32)]
     lib.stag_server_submit.restype = C.c_int
     lib.stag_server_submit.argtypes = [vp, i32, vp, i64, vp, C.POINTER(C.c_uint64)]
+    lib.stag_server_submit_ex.restype = C.c_int
+    lib.stag_server_submit_ex.argtypes = [vp, i32, vp, i64, i32, i32, f64, vp, vp, C.POINTER(C.c_int32),
+                                          C.POINTER(C.c_uint64)]
     lib.stag_server_wait.restype = C.c_int
     lib.stag_server_wait.argtypes = [vp, C.c_uint64, C.POINTER(C.c_int), C.POINTER(f64)]
     lib.stag_server_poll.restype = C.c_int
@@ -509,40 +514,83 @@ def spectral_cluster(n: int, src, dst, w, k: int, seed: int = 0):
 
 
 class Server:
-    """Continuous-batching KDE server over resident data sets (exact form).
+    """Continuous-batching KDE server over resident data sets and CKNS
+    indexes (see include/stag_kde.h).
 
-    submit() returns a ticket; wait(ticket) returns (S, status, latency_s)."""
+    submit() returns a ticket; wait(ticket) returns (S, status, latency_s)
+    and, for requests submitted with bound=True, bound_of(ticket) the
+    per-result bounds afterwards."""
 
-    def __init__(self, budget_bytes: int = 0, n_streams: int = 0, max_batch_queries: int = 0):
+    def __init__(self, budget_bytes: int = 0, n_streams: int = 0, max_batch_queries: int = 0,
+                 chunk_queries: int = 0):
         h = C.c_void_p()
-        check(load().stag_server_create(int(budget_bytes), int(n_streams), int(max_batch_queries), C.byref(h)),
-              "stag_server_create")
+        check(load().stag_server_create(int(budget_bytes), int(n_streams), int(max_batch_queries),
+                                        int(chunk_queries), C.byref(h)), "stag_server_create")
         self._h = h
         self._live = {}
+        self._bounds = {}
 
-    def add_dataset(self, X, a: float, form: str = "fp32") -> int:
+    def add_dataset(self, X, a: float, form="fp32", lsh: dict | None = None) -> int:
+        """form: one form name or a list of names to keep resident (may be
+        empty with an index); lsh: None, or dict(eps=..., plus stag_lsh_params
+        fields k1, k2_constant, p_offset, min_mu, seed, flags) for a resident
+        CKNS index."""
         torch = _torch()
         _need(X, torch.float32, 2, "X")
+        forms = [form] if isinstance(form, str) else list(form)
+        mask = 0
+        for f in forms:
+            mask |= 1 << FORMS[f]
+        torch.cuda.current_stream(X.device).synchronize()  # X must be complete before the server reads it
         i = C.c_int32()
-        check(load().stag_server_add_dataset(self._h, _ptr(X), X.shape[0], X.shape[1], float(a), FORMS[form],
-                                             C.byref(i)), "stag_server_add_dataset")
+        if lsh is None:
+            prm, eps = None, 0.0
+        else:
+            kw = dict(lsh)
+            eps = float(kw.pop("eps", 0.5))
+            prm = C.byref(_lsh_params(**kw))
+        check(load().stag_server_add_dataset_ex(self._h, _ptr(X), X.shape[0], X.shape[1], float(a), mask, eps, prm,
+                                                C.byref(i)), "stag_server_add_dataset_ex")
         return int(i.value)
 
-    def submit(self, dataset: int, Q, S_out=None) -> int:
+    def submit(self, dataset: int, Q, S_out=None, form: str | None = None, eps: float = 0.0, lsh: bool = False,
+               bound: bool = False) -> int:
+        """Exact request in `form` (None: the data set's first resident form;
+        "auto": chosen from eps), or an LSH request (lsh=True)."""
         torch = _torch()
         _need(Q, torch.float32, 2, "Q")
         S = S_out if S_out is not None else torch.empty(Q.shape[0], dtype=torch.float64, device=Q.device)
+        B = torch.empty(Q.shape[0], dtype=torch.float64, device=Q.device) if bound else None
         torch.cuda.current_stream(Q.device).synchronize()  # Q must be complete before the server reads it
         t = C.c_uint64()
-        check(load().stag_server_submit(self._h, int(dataset), _ptr(Q), Q.shape[0], _ptr(S), C.byref(t)),
-              "stag_server_submit")
-        self._live[t.value] = (Q, S)
+        if form is None and not lsh and not bound:
+            check(load().stag_server_submit(self._h, int(dataset), _ptr(Q), Q.shape[0], _ptr(S), C.byref(t)),
+                  "stag_server_submit")
+            self._live[t.value] = (Q, S, None, None)
+            return int(t.value)
+        chosen = C.c_int32(-1)
+        kind = 1 if lsh else 0
+        fcode = FORMS["fp32" if form is None else form] if not lsh else 0
+        check(load().stag_server_submit_ex(self._h, int(dataset), _ptr(Q), Q.shape[0], kind, fcode, float(eps),
+                                           _ptr(S), _ptr(B), C.byref(chosen), C.byref(t)), "stag_server_submit_ex")
+        name = None if chosen.value < 0 else next(k for k, v in FORMS.items() if v == chosen.value)
+        self._live[t.value] = (Q, S, B, name)
         return int(t.value)
+
+    def form_of(self, ticket: int):
+        """The form a pending request runs in (None for LSH or the plain
+        submit)."""
+        return self._live[ticket][3]
+
+    def bound_of(self, ticket: int):
+        return self._bounds.pop(ticket, None)
 
     def wait(self, ticket: int):
         st, lat = C.c_int(), C.c_double()
         check(load().stag_server_wait(self._h, ticket, C.byref(st), C.byref(lat)), "stag_server_wait")
-        Q, S = self._live.pop(ticket)
+        Q, S, B, _ = self._live.pop(ticket)
+        if B is not None:
+            self._bounds[ticket] = B
         return S, int(st.value), float(lat.value)
 
     def poll(self, ticket: int):
@@ -560,6 +608,7 @@ class Server:
             load().stag_server_destroy(self._h)
             self._h = None
             self._live.clear()
+            self._bounds.clear()
 
     def __del__(self):
         try:

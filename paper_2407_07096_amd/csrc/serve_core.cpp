@@ -22,22 +22,23 @@ double pct(std::vector<double> v, double p) {  // nearest-rank percentile
 }
 }  // namespace
 
-Scheduler::Scheduler(Executor* ex, size_t budget_bytes, int64_t max_batch_queries)
-    : ex_(ex), budget_(budget_bytes), max_batch_(max_batch_queries) {
+Scheduler::Scheduler(Executor* ex, size_t budget_bytes, int64_t max_batch_queries, int64_t chunk_queries)
+    : ex_(ex), budget_(budget_bytes), max_batch_(max_batch_queries), chunk_(chunk_queries > 0 ? chunk_queries : 1) {
   running_.resize((size_t)ex_->n_streams());
-  run_ds_.assign((size_t)ex_->n_streams(), -1);
 }
 
 Scheduler::~Scheduler() { stop(); }
 
-uint64_t Scheduler::submit(int ds, const void* Q, int64_t m, void* S) {
+uint64_t Scheduler::submit(int ds, int key, const void* Q, int64_t m, void* S, void* B) {
   if (m < 1 || !Q || !S) return 0;
   std::unique_ptr<Request> r(new Request());
   r->dataset = ds;
+  r->key = key;
   r->m = m;
   r->Q = Q;
   r->S = S;
-  r->footprint = ex_->footprint(ds, m);
+  r->B = B;
+  r->footprint = ex_->footprint(ds, key, m);
   if (r->footprint == 0) return 0;
   std::lock_guard<std::mutex> lk(mu_);
   r->id = next_id_++;
@@ -64,6 +65,19 @@ bool Scheduler::step() {
   return step_locked();
 }
 
+void Scheduler::finish_locked(Request* r, double t) {
+  r->t_done = t;
+  r->done = true;
+  st_.inflight_bytes -= r->footprint;
+  if (r->status == kOk) {
+    st_.completed++;
+    st_.queries += (uint64_t)r->m;
+    latencies_.push_back(r->t_done - r->t_submit);
+  } else {
+    st_.failed++;
+  }
+}
+
 bool Scheduler::step_locked() {
   bool changed = false;
   const int ns = ex_->n_streams();
@@ -73,21 +87,13 @@ bool Scheduler::step_locked() {
     std::vector<int> sts = ex_->retire(s);
     const double t = ex_->now();
     for (size_t k = 0; k < running_[s].size(); ++k) {
-      Request* r = running_[s][k];
-      r->status = k < sts.size() ? sts[k] : kOk;
-      r->t_done = t;
-      r->done = true;
-      st_.inflight_bytes -= r->footprint;
-      if (r->status == kOk) {
-        st_.completed++;
-        st_.queries += (uint64_t)r->m;
-        latencies_.push_back(r->t_done - r->t_submit);
-      } else {
-        st_.failed++;
-      }
+      Request* r = running_[s][k].r;
+      const int stk = k < sts.size() ? sts[k] : kOk;
+      if (r->status == -1 || r->status == kOk) r->status = stk;  // the first failure sticks
+      r->outstanding--;
+      if (r->outstanding == 0 && r->next_row >= r->m) finish_locked(r, t);
     }
     running_[s].clear();
-    run_ds_[s] = -1;
     changed = true;
   }
   if (changed) cv_done_.notify_all();
@@ -99,40 +105,56 @@ bool Scheduler::step_locked() {
     st_.inflight_bytes += r->footprint;
     st_.peak_inflight_bytes = std::max(st_.peak_inflight_bytes, st_.inflight_bytes);
     r->t_admit = ex_->now();
+    r->status = kOk;
     ready_.push_back(r);
     changed = true;
   }
-  // launch on idle streams
+  // launch on idle streams: the oldest request with rows left sets the data
+  // set and key; every ready request of that data set and key gives its next
+  // chunk, in arrival order, while the batch has room
+  const int max_items = std::max(1, ex_->max_batch_items());
   for (int s = 0; s < ns && !ready_.empty(); ++s) {
     if (!running_[s].empty()) continue;
-    const int ds = ready_.front()->dataset;
-    std::vector<Request*> batch;
+    const int ds = ready_.front()->dataset, key = ready_.front()->key;
+    std::vector<Item> batch;
     int64_t q = 0;
-    for (auto it = ready_.begin(); it != ready_.end();) {
+    for (auto it = ready_.begin(); it != ready_.end() && (int)batch.size() < max_items;) {
       Request* r = *it;
-      if (r->dataset == ds && (batch.empty() || q + r->m <= max_batch_)) {
-        batch.push_back(r);
-        q += r->m;
-        it = ready_.erase(it);
-      } else {
+      if (r->dataset != ds || r->key != key) {
         ++it;
+        continue;
       }
+      const int64_t take = std::min(chunk_, r->m - r->next_row);
+      if (!batch.empty() && q + take > max_batch_) break;
+      batch.push_back(Item{r, r->next_row, take});
+      q += take;
+      r->next_row += take;
+      r->outstanding++;
+      if (r->next_row >= r->m) it = ready_.erase(it);
+      else ++it;
     }
     const double t = ex_->now();
-    for (Request* r : batch) r->t_launch = t;
-    const int rc = ex_->launch(ds, batch, s);
+    for (Item& b : batch)
+      if (b.row0 == 0) b.r->t_launch = t;
+    const int rc = ex_->launch(ds, key, batch, s);
     if (rc != kOk) {
-      for (Request* r : batch) {
+      for (Item& b : batch) {
+        Request* r = b.r;
         r->status = rc;
-        r->done = true;
-        r->t_done = t;
-        st_.inflight_bytes -= r->footprint;
-        st_.failed++;
+        r->outstanding--;
+        if (r->next_row < r->m) {  // its remaining rows are not started
+          r->next_row = r->m;
+          for (auto it = ready_.begin(); it != ready_.end(); ++it)
+            if (*it == r) {
+              ready_.erase(it);
+              break;
+            }
+        }
+        if (r->outstanding == 0) finish_locked(r, t);
       }
       cv_done_.notify_all();
     } else {
       running_[s] = batch;
-      run_ds_[s] = ds;
       st_.batches++;
     }
     changed = true;

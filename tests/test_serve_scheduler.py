@@ -22,10 +22,11 @@ def mock(tmp_path_factory):
                     "-o", str(out)], check=True)
     lib = C.CDLL(str(out))
     lib.mock_create.restype = C.c_void_p
-    lib.mock_create.argtypes = [C.c_uint64, C.c_int32, C.c_int64, C.c_double, C.c_double, C.c_uint64]
+    lib.mock_create.argtypes = [C.c_uint64, C.c_int32, C.c_int64, C.c_double, C.c_double, C.c_uint64, C.c_int64,
+                                C.c_int32]
     lib.mock_destroy.argtypes = [C.c_void_p]
     lib.mock_submit.restype = C.c_uint64
-    lib.mock_submit.argtypes = [C.c_void_p, C.c_int32, C.c_int64, C.c_int32]
+    lib.mock_submit.argtypes = [C.c_void_p, C.c_int32, C.c_int64, C.c_int32, C.c_int32]
     lib.mock_advance.argtypes = [C.c_void_p, C.c_double]
     lib.mock_poll.restype = C.c_int32
     lib.mock_poll.argtypes = [C.c_void_p, C.c_uint64, C.POINTER(C.c_int32), C.POINTER(C.c_double)]
@@ -36,12 +37,12 @@ def mock(tmp_path_factory):
 
 
 class Sim:
-    def __init__(self, lib, budget, ns, maxb=1 << 30, c0=1.0, c1=0.0, bpq=1):
+    def __init__(self, lib, budget, ns, maxb=1 << 30, c0=1.0, c1=0.0, bpq=1, chunk=1 << 40, max_items=1024):
         self.lib = lib
-        self.h = lib.mock_create(budget, ns, maxb, c0, c1, bpq)
+        self.h = lib.mock_create(budget, ns, maxb, c0, c1, bpq, chunk, max_items)
 
-    def submit(self, ds, m, fail=False):
-        t = self.lib.mock_submit(self.h, ds, m, 1 if fail else 0)
+    def submit(self, ds, m, fail=False, key=0):
+        t = self.lib.mock_submit(self.h, ds, m, 1 if fail else 0, key)
         return t
 
     def advance(self, dt):
@@ -60,9 +61,14 @@ class Sim:
         return dict(zip(keys, list(out)))
 
     def launches(self):
-        buf = (C.c_int32 * 4096)()
-        n = self.lib.mock_launches(self.h, buf, 4096)
-        return [tuple(buf[4 * k:4 * k + 4]) for k in range(n)]
+        buf = (C.c_int32 * 65536)()
+        n = self.lib.mock_launches(self.h, buf, 65536)
+        return [tuple(buf[5 * k:5 * k + 4]) for k in range(n)]
+
+    def launch_keys(self):
+        buf = (C.c_int32 * 65536)()
+        n = self.lib.mock_launches(self.h, buf, 65536)
+        return [buf[5 * k + 4] for k in range(n)]
 
     def close(self):
         self.lib.mock_destroy(self.h)
@@ -149,4 +155,77 @@ def test_failure_isolated_to_request(mock):
     assert sim.poll(later)[:2] == (1, 0)  # the loop keeps going
     st = sim.stats()
     assert st["failed"] == 2 and st["completed"] == 3 and st["inflight"] == 0
+    sim.close()
+
+
+def test_batch_item_limit(mock):
+    """Many one-query requests of one data set: no batch exceeds the
+    executor's item limit, and every request completes."""
+    sim = Sim(mock, budget=10 ** 9, ns=2, c0=1.0, maxb=65536, max_items=1024)
+    ts = [sim.submit(0, 1) for _ in range(2600)]
+    for _ in range(4):
+        sim.advance(1.0)
+    lg = sim.launches()
+    assert max(l[2] for l in lg) <= 1024
+    assert sum(l[2] for l in lg) == 2600
+    assert all(sim.poll(t)[:2] == (1, 0) for t in ts)
+    assert sim.stats()["completed"] == 2600
+    sim.close()
+
+
+def test_chunks_let_small_requests_pass(mock):
+    """A large request is served in chunks; a small one that arrives right
+    after it rides in the next batch instead of waiting for all its chunks.
+    Batch time is proportional to its queries."""
+    sim = Sim(mock, budget=10 ** 9, ns=1, c0=0.0, c1=1.0, maxb=1000, chunk=100)
+    big = sim.submit(0, 1000)
+    sim.advance(0.0)
+    small = sim.submit(0, 5)
+    sim.advance(100.0)                  # first chunk (100 queries) done
+    lg = sim.launches()
+    assert lg[0] == (0, 0, 1, 100)      # the big request's first chunk alone
+    assert lg[1] == (0, 0, 2, 105)      # its second chunk with the small request
+    assert sim.poll(small)[0] == 0
+    sim.advance(105.0)
+    assert sim.poll(small) == (1, 0, 205.0)
+    assert sim.poll(big)[0] == 0
+    for _ in range(8):
+        sim.advance(100.0)
+    done, st, lat = sim.poll(big)
+    assert (done, st) == (1, 0) and lat == 1005.0
+    st = sim.stats()
+    assert st["completed"] == 2 and st["queries"] == 1005
+    sim.close()
+
+
+def test_chunks_over_streams_and_keys(mock):
+    """One large request spreads its chunks over the idle streams; a request
+    with another key (form or estimator) is never batched with it and, being
+    younger, takes the next free stream."""
+    sim = Sim(mock, budget=10 ** 9, ns=4, c0=1.0, maxb=10 ** 6, chunk=256)
+    big = sim.submit(0, 1024)
+    other = sim.submit(0, 10, key=1)
+    sim.advance(0.0)
+    lg, keys = sim.launches(), sim.launch_keys()
+    assert [(l[0], l[3]) for l in lg] == [(0, 256), (1, 256), (2, 256), (3, 256)] and keys == [0, 0, 0, 0]
+    sim.advance(1.0)
+    assert sim.poll(big) == (1, 0, 1.0)
+    lg, keys = sim.launches(), sim.launch_keys()
+    assert lg[-1][2:] == (1, 10) and keys[-1] == 1
+    sim.advance(1.0)
+    assert sim.poll(other) == (1, 0, 2.0)
+    sim.close()
+
+
+def test_chunk_failure_fails_request_once(mock):
+    """A failed chunk fails its request (once), the others complete."""
+    sim = Sim(mock, budget=10 ** 9, ns=2, c0=1.0, maxb=10 ** 6, chunk=8)
+    bad = sim.submit(0, 40, fail=True)
+    good = sim.submit(0, 40)
+    for _ in range(10):
+        sim.advance(1.0)
+    assert sim.poll(bad)[:2] == (1, 3)
+    assert sim.poll(good)[:2] == (1, 0)
+    st = sim.stats()
+    assert st["failed"] == 1 and st["completed"] == 1 and st["inflight"] == 0
     sim.close()
