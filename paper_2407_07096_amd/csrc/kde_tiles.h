@@ -747,6 +747,174 @@ __global__ __launch_bounds__(256, 2) void tile_split(
   if (h == 0) partial[(int64_t)chunk * m_pad + qi] = acc_add<MODE>(acc, other);
 }
 
+// Split forms (hi + lo), 64 queries per wave.  Every wave holds two 32-query
+// column blocks as B operands and uses each A operand it reads from LDS for
+// both, which halves the LDS reads per matrix-core product: in tile_split
+// the four waves of a workgroup each read the whole data tile from LDS for
+// their 32 queries, and at d = 128 those reads (with the staging writes)
+// kept the matrix cores waiting.  Four waves cover 256 queries; when m_pad
+// is an odd multiple of 128 the last workgroup's waves 2 and 3 have no
+// queries and only stage tiles.  The products per block come in the same k
+// order, from the same accumulator seeds, as in tile_split, so every result
+// is bitwise the same.  Gaussian sums only (kModeGauss).
+template <int FORM, int DP, int MODE>
+__global__ __launch_bounds__(256, 2) void tile_split_w64(
+    const unsigned short* __restrict__ X0, const unsigned short* __restrict__ X1, const float* __restrict__ Xoff,
+    const unsigned short* __restrict__ Q0, const unsigned short* __restrict__ Q1, const float* __restrict__ Qoff,
+    int64_t n_pad, int n_qt256, int64_t m_pad, double* __restrict__ partial) {
+  static_assert(MODE == kModeGauss, "Gaussian sums only");
+  constexpr int NP = 2;
+  constexpr int KS = DP / 16;
+  constexpr int LD = DP + 8;
+  constexpr int V_ROW = DP / 8;
+  constexpr int NV = kTileRows * V_ROW;
+  constexpr int NLD = (NV + 255) / 256;
+  constexpr int NMMA = KS * 6;
+  __shared__ __attribute__((aligned(16))) unsigned short tile[2][NP][kTileRows * LD];
+  __shared__ __attribute__((aligned(16))) float tbeta[2][kTileRows];
+
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, r32 = lane & 31, h = lane >> 5;
+  const int qtile = blockIdx.x % n_qt256;
+  const int chunk = blockIdx.x / n_qt256;
+  const int64_t col0 = (int64_t)qtile * 256 + wave * 64;
+  const bool live = col0 < m_pad;  // wave-uniform
+  const int64_t q0 = col0 + r32, q1 = q0 + 32;
+
+  u16x8 b0[NP][KS], b1[NP][KS];
+  float alpha0 = 0.0f, alpha1 = 0.0f;
+  {
+    const unsigned short* Qp[2] = {Q0, Q1};
+#pragma unroll
+    for (int p = 0; p < NP; ++p)
+#pragma unroll
+      for (int s = 0; s < KS; ++s) {
+        b0[p][s] = live ? *reinterpret_cast<const u16x8*>(Qp[p] + q0 * DP + s * 16 + h * 8) : u16x8{};
+        b1[p][s] = live ? *reinterpret_cast<const u16x8*>(Qp[p] + q1 * DP + s * 16 + h * 8) : u16x8{};
+      }
+    if (live) {
+      alpha0 = Qoff[q0];
+      alpha1 = Qoff[q1];
+    }
+  }
+
+  const int64_t row0 = (int64_t)chunk * kChunkRows;
+  const int64_t rem = (n_pad - row0) / kTileRows;
+  const int ntiles = (int)(rem < kChunkRows / kTileRows ? rem : kChunkRows / kTileRows);
+
+  const unsigned short* Xpp[2] = {X0, X1};
+  u16x8 stage[NP][NLD];
+  float sbeta;
+  auto gload = [&](int t) {
+    const int64_t base = (row0 + (int64_t)t * kTileRows) * DP;
+#pragma unroll
+    for (int p = 0; p < NP; ++p)
+#pragma unroll
+      for (int k = 0; k < NLD; ++k)
+        stage[p][k] = reinterpret_cast<const u16x8*>(Xpp[p] + base)[min(tid + 256 * k, NV - 1)];
+    sbeta = Xoff[row0 + (int64_t)t * kTileRows + (tid & 31)];
+  };
+  auto lstore = [&](int buf) {
+#pragma unroll
+    for (int p = 0; p < NP; ++p)
+#pragma unroll
+      for (int k = 0; k < NLD; ++k) {
+        const int idx = min(tid + 256 * k, NV - 1);
+        const int r = idx / V_ROW, c8 = idx % V_ROW;
+        *reinterpret_cast<u16x8*>(&tile[buf][p][r * LD + c8 * 8]) = stage[p][k];
+      }
+    tbeta[buf][tid & 31] = sbeta;
+  };
+
+  double acc0 = 0.0, acc1 = 0.0;
+  auto step = [&](int t, const f32x16& d0, const f32x16& d1, f32x16& n0, f32x16& n1) {
+    const int buf = t & 1;
+    __syncthreads();
+    if (live) {
+      float e0[16], e1[16];
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        e0[i] = d0[i];
+        e1[i] = d1[i];
+      }
+      acc0 += (double)kernel_tile_sum<MODE>(e0);
+      acc1 += (double)kernel_tile_sum<MODE>(e1);
+      // the accumulators start from the offsets alpha_q + beta_x of their pairs
+      f32x16 c0, c1;
+#pragma unroll
+      for (int g = 0; g < 4; ++g) {
+        const f32x4 bv = *reinterpret_cast<const f32x4*>(&tbeta[buf][8 * g + 4 * h]);
+        c0[4 * g] = alpha0 + bv.x;
+        c0[4 * g + 1] = alpha0 + bv.y;
+        c0[4 * g + 2] = alpha0 + bv.z;
+        c0[4 * g + 3] = alpha0 + bv.w;
+        c1[4 * g] = alpha1 + bv.x;
+        c1[4 * g + 1] = alpha1 + bv.y;
+        c1[4 * g + 2] = alpha1 + bv.z;
+        c1[4 * g + 3] = alpha1 + bv.w;
+      }
+#pragma unroll
+      for (int s = 0; s < KS; ++s) {
+        const u16x8 ahi = *reinterpret_cast<const u16x8*>(&tile[buf][0][r32 * LD + s * 16 + h * 8]);
+        const u16x8 alo = *reinterpret_cast<const u16x8*>(&tile[buf][1][r32 * LD + s * 16 + h * 8]);
+        // small corrections first, then the leading product (tile_split's order)
+        c0 = mma16<FORM>(alo, b0[0][s], c0);
+        c1 = mma16<FORM>(alo, b1[0][s], c1);
+        c0 = mma16<FORM>(ahi, b0[1][s], c0);
+        c1 = mma16<FORM>(ahi, b1[1][s], c1);
+        c0 = mma16<FORM>(ahi, b0[0][s], c0);
+        c1 = mma16<FORM>(ahi, b1[0][s], c1);
+      }
+      n0 = c0;
+      n1 = c1;
+    }
+    lstore(buf ^ 1);
+    gload(min(t + 2, ntiles - 1));
+#pragma unroll
+    for (int i = 0; i < NMMA; ++i) {
+      __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+      __builtin_amdgcn_sched_group_barrier(0x002, (80 + NMMA - 1) / NMMA, 0);
+    }
+  };
+
+  gload(0);
+  lstore(0);
+  gload(min(1, ntiles - 1));
+  f32x16 ca0, ca1, cb0, cb1;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    ca0[i] = kPadOffset;  // kernel value 0: neutral first epilogue
+    ca1[i] = kPadOffset;
+    cb0[i] = kPadOffset;
+    cb1[i] = kPadOffset;
+  }
+  int t = 0;
+  for (; t + 1 < ntiles; t += 2) {
+    step(t, ca0, ca1, cb0, cb1);
+    step(t + 1, cb0, cb1, ca0, ca1);
+  }
+  if (t < ntiles) {
+    step(t, ca0, ca1, cb0, cb1);
+    ca0 = cb0;
+    ca1 = cb1;
+  }
+  if (live) {
+    float e0[16], e1[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      e0[i] = ca0[i];
+      e1[i] = ca1[i];
+    }
+    acc0 += (double)kernel_tile_sum<MODE>(e0);
+    acc1 += (double)kernel_tile_sum<MODE>(e1);
+  }
+  const double o0 = __shfl_down(acc0, 32);
+  const double o1 = __shfl_down(acc1, 32);
+  if (live && h == 0) {
+    partial[(int64_t)chunk * m_pad + q0] = acc0 + o0;
+    partial[(int64_t)chunk * m_pad + q1] = acc1 + o1;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Wide rows (256 < d <= 1024), fp32 form.  The 32 queries of a workgroup sit
 // in LDS as the B operand ([32][DP+4] floats, loaded once); each of the 4
@@ -858,6 +1026,16 @@ stag_status launch_tile_split(void* const* xp, const float* xaug, void* const* q
                               int n_qtiles, int64_t m_pad, int P, double* partial, const TileExtra& ex,
                               hipStream_t st) {
   using U = const unsigned short*;
+  if constexpr (MODE == kModeGauss && FORM != STAG_FORM_BF16_SPLIT3 && DP >= 64 && DP <= 128) {
+    // 64 queries per wave (the same results, fewer LDS reads per product)
+    ScopedTimer tm(FORM == STAG_FORM_FP16_SPLIT ? "kde_tile_fp16x3" : "kde_tile_bf16x3", st);
+    const int n_qt256 = (int)ceil_div(m_pad, 256);
+    hipLaunchKernelGGL((tile_split_w64<FORM, DP, MODE>), dim3((unsigned)((int64_t)n_qt256 * P)), dim3(256), 0, st,
+                       (U)xp[0], (U)xp[1], xaug, (U)qp[0], (U)qp[1], qaug, n_pad, n_qt256, m_pad, partial);
+    (void)n_qtiles;
+    (void)ex;
+    return check_launch("tile_split_w64");
+  }
   ScopedTimer tm(rescue_timer(ex, FORM == STAG_FORM_FP16_SPLIT
                                      ? "kde_tile_fp16x3"
                                      : (FORM == STAG_FORM_BF16_SPLIT ? "kde_tile_bf16x3" : "kde_tile_bf16x6")),

@@ -28,6 +28,7 @@ namespace {
 constexpr uint64_t kGammaS = 0x9E3779B97F4A7C15ULL;
 constexpr uint64_t kTagDrawS = 0x44524157ULL;
 constexpr int kChunkTiles = 128;  // 32-row tiles per 4096-row chunk
+constexpr double kLog2eS = 1.4426950408889634074;
 
 __device__ inline uint64_t mixs(uint64_t z) {
   z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
@@ -146,7 +147,7 @@ __global__ __launch_bounds__(256) void draw_exact(const float* __restrict__ X, i
   // rest_draw: the total in the scale of the chunk and tile sums (2^{-m_i}
   // times the true one for a row of the underflow rescue, else the same)
   const double tot = rest_draw[i];
-  const double kscale = exp2(-shift[i]);  // 1 for rows without a shift
+  const double sh = shift[i];  // 0 for rows without a shift
   int64_t pick = -1;
   if (rest[i] > 0.0 && tot > 0.0) {
     double resid = 0.0;
@@ -189,7 +190,11 @@ __global__ __launch_bounds__(256) void draw_exact(const float* __restrict__ X, i
           }
         }
         D += __shfl_xor(D, 32);
-        const double kv = (lane < 32 && live) ? exp(-a * D) * kscale : 0.0;
+        // a shifted row's values are 2^{E - m_i} with E = -a log2(e) D in one
+        // exponent (2^{-m_i} alone overflows for m_i < -1024, and exp(-a D)
+        // is subnormal there)
+        double kv = 0.0;
+        if (lane < 32 && live) kv = sh == 0.0 ? exp(-a * D) : exp2(fma(-a * kLog2eS, D, -sh));
         double resid3 = 0.0;
         const int jl = invert_level(32, resid2, [&](int) { return kv; }, &resid3);  // lane k owns row k
         if (jl >= 0) pick = rb + jl;

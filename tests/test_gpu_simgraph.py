@@ -98,6 +98,45 @@ def test_exact_mode_small_densities(stag, orc, form):
     assert werr.max() <= 5e-3, werr.max()
 
 
+@pytest.mark.parametrize("form", ["fp32", "fp16_split"])
+def test_exact_mode_subnormal_row(stag, orc, form):
+    """One outlier whose row sum lies in the fp64 subnormal range (~1e-315):
+    its exponents' maximum is below -1024, where 2^{-m_i} alone overflows; the
+    draws take 2^{E - m_i} in one exponent and match the oracle's."""
+    rng = np.random.default_rng(78)
+    d, a = 8, 0.5
+    main = rng.normal(size=(2000, d))
+
+    def log_rest(R):
+        x0 = np.zeros(d)
+        x0[0] = R
+        D = ((main - x0) ** 2).sum(1)
+        v = -a * D
+        return v.max() + np.log(np.exp(v - v.max()).sum())
+
+    lo, hi = 10.0, 60.0
+    for _ in range(60):  # R with a row sum near 1e-315
+        mid = 0.5 * (lo + hi)
+        lo, hi = (mid, hi) if log_rest(mid) > np.log(1e-315) else (lo, mid)
+    x0 = np.zeros((1, d))
+    x0[0, 0] = lo
+    X = np.concatenate([main, x0]).astype(np.float32)
+    s, seed, tol = 8, 29, 1e-4
+    i = len(X) - 1
+    orest = np.sum(np.delete(orc.kernel_row(X, a, i), i))
+    assert 1e-320 < orest < 1e-308  # the case is exercised: subnormal row sum
+    announce(f"simgraph exact subnormal row form={form}")
+    src, dst, w, deg = _gpu(stag, X, a, s, mode="exact", form=form, seed=seed)
+    osrc, odst, ow, odeg, mg = orc.simgraph_exact(X, a, s, seed, return_margin=True)
+    e = np.arange(i * s, (i + 1) * s)
+    assert np.all(dst[e] >= 0) and np.all(dst[e] != i)
+    same = dst[e] == odst[e]
+    assert np.all(same[mg[e] > tol])
+    _check_valid_draws(orc, X, a, s, seed, src, dst, e[~same], tol)
+    assert deg[i] == odeg[i] == 1.0  # deg = 1 + rest_i rounds to 1 in binary64
+    assert np.all(np.abs(w[e][same] - ow[e][same]) <= 5e-3 * ow[e][same])
+
+
 def test_exact_mode_wide_rows(stag, orc):
     """d = 784 (the wide fp32 tile), sparse non-negative data, a = 1e-3."""
     X = synth.sparse_uniform(3000, 784, 1004)
