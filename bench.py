@@ -608,13 +608,15 @@ def serving_run(stag, torch, dev, n_requests: int, seconds_cap: float, eps: floa
     lsh = dict(eps=0.5, k1=1, k2_constant=8, p_offset=1, seed=3005)
     with_index = (0, 1)  # CKNS indexes on the two smaller data sets (the estimator's work grows with n)
     srv = stag.Server(budget_bytes=24 << 30, n_streams=4, max_batch_queries=65536, chunk_queries=4096)
-    ids, pools = [], []
+    ids, pools, host = [], [], []
     for k, (n, d) in enumerate(specs):
         mix = synth.mixture(d, 20, 4005 + 10 * k, sigma=(0.5, 2.0))
-        X = torch.from_numpy(synth.sample(mix, n, 4105 + 10 * k)).to(dev)
+        Xh = synth.sample(mix, n, 4105 + 10 * k)
+        X = torch.from_numpy(Xh).to(dev)
         ids.append(srv.add_dataset(X, 0.64 / d, ["fp32", "bf16_split", "fp16_split"],
                                    lsh=lsh if k in with_index else None))
         pools.append(torch.from_numpy(synth.sample(mix, 65536, 4205 + 10 * k)).to(dev))
+        host.append(Xh)
         del X
     torch.cuda.synchronize()
     print("[bench] serving: data sets resident", file=sys.stderr, flush=True)
@@ -702,13 +704,30 @@ def serving_run(stag, torch, dev, n_requests: int, seconds_cap: float, eps: floa
     cmp["all_within_stated_accuracy"] = bool(max(cmp[f]["max_bound"] for f in cmp_forms) <= cmp_eps)
     cmp["bf16_split_over_fp32_saturation"] = (cmp["bf16_split"]["saturation_exact_evals_per_s"] /
                                               cmp["fp32"]["saturation_exact_evals_per_s"])
+    # accuracy of served results against the FP64 oracle: 32 queries per data
+    # set at the stream's eps (AUTO) and in each compared form
+    import oracle
+    check = {}
+    for form in ("auto",) + cmp_forms:
+        worst, wb = 0.0, 0.0
+        for k, (n, d) in enumerate(specs):
+            Q = pools[k][1000:1032]
+            t = srv.submit(ids[k], Q, form=form, eps=eps if form == "auto" else cmp_eps, bound=True)
+            S, st, _ = srv.wait(t)
+            B = srv.bound_of(t).cpu().numpy()
+            ref = oracle.kde_exact(host[k], Q.cpu().numpy(), 0.64 / d)
+            err = np.abs(S.cpu().numpy() - ref) / ref
+            worst, wb = max(worst, float(err.max())), max(wb, float((err / B).max()))
+        check[form] = {"max_rel_err": worst, "max_err_over_bound": wb}
+    print("[bench] serving: oracle check done", file=sys.stderr, flush=True)
     stats = srv.stats()
     srv.close()
     head = loads[0]
     return {"p50_ms": head["p50_ms"], "p99_ms": head["p99_ms"], "exact_evals_per_s": head["exact_evals_per_s"],
             "headline_load": 0.5, "stated_accuracy": eps, "lsh_share": lsh_share,
             "saturation": burst, "saturation_request_rate_per_s": req_rate, "loads": loads,
-            "equal_accuracy_forms": cmp, "completed": int(stats["completed"]),
+            "equal_accuracy_forms": cmp, "oracle_check_32_queries_per_dataset": check,
+            "completed": int(stats["completed"]),
             "batches": int(stats["batches"]), "datasets": [f"n={n} d={d}" for n, d in specs],
             "resident_forms": ["fp32 (centred)", "bf16_split", "fp16_split"], "lsh_index": lsh,
             "chunk_queries": 4096, "batch_sizes": "log-uniform 1..65536", "requests_per_load": n_requests}
@@ -760,6 +779,8 @@ def main():
                     help="only the headline (and the CPU baseline unless --no-cpu-baseline)")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--only-step", action="store_true",
+                    help="profiling aid: only the hot-path step at n = m = 1e5, d = 64 (its JSON object alone)")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="after the timed steps, one plain device copy of this many MiB (a reference for "
                          "hardware byte counters)")
@@ -784,6 +805,20 @@ def main():
     lib.stag_timing_report.argtypes = [ctypes.c_char_p, ctypes.c_size_t]
     buf = ctypes.create_string_buffer(1 << 16)
     dev = torch.device("cuda:0")
+
+    if args.only_step:
+        X, Q, info = synth.config_points(2)
+        Xd = torch.from_numpy(X).to(dev)
+        Qd = torch.from_numpy(Q).to(dev)
+        step, _ = hot_path_step_run(stag, torch, dev, lib, buf, X, Q, Xd, Qd, args.form, 0.01, steps=args.steps)
+        if args.calib_copy_mb > 0:
+            src_c = torch.ones(args.calib_copy_mb << 18, dtype=torch.float32, device=dev)
+            dst_c = torch.empty_like(src_c)
+            torch.cuda.synchronize()
+            torch.mul(src_c, 1.0, out=dst_c)
+            torch.cuda.synchronize()
+        print(json.dumps({"hot_path_step": step}), flush=True)
+        return
 
     # ---- headline: exact KDE, n = 2e6, m = 2e5, d = 128 ----
     X3, Q3, info3 = synth.config_points(3)

@@ -167,7 +167,7 @@ def test_exact_kde_wide_rows(stag, orc):
 
 
 def test_exact_mode_config4_full_sampled(stag, orc):
-    """n = 70,000, d = 784 (config 4): full GPU run, oracle on 12 nodes."""
+    """n = 70,000, d = 784 (config 4): full GPU run, oracle on 48 nodes."""
     X = synth.sparse_uniform(70_000, 784, 1004)
     a, seed = 1e-3, 4004
     announce("simgraph exact config4 full n=70000 d=784")
@@ -176,7 +176,7 @@ def test_exact_mode_config4_full_sampled(stag, orc):
     assert src.shape[0] == 70_000 * s
     assert np.all(dst >= 0) and np.all(dst != src) and np.all(w > 0)
     rng = np.random.default_rng(1)
-    nodes = rng.choice(70_000, size=12, replace=False)
+    nodes = rng.choice(70_000, size=48, replace=False)
     for i in nodes:
         row = orc.kernel_row(X, a, int(i))
         assert abs(deg[i] - row.sum()) <= 1e-5 * row.sum()
