@@ -35,12 +35,13 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-MFMA_PEAK = {"fp32": 157.3e12, "fp16_split": 2.5e15, "bf16_split": 2.5e15, "bf16_split3": 2.5e15}
-PRODUCTS = {"fp32": 1, "fp16_split": 3, "bf16_split": 3, "bf16_split3": 6}
+MFMA_PEAK = {"fp32": 157.3e12, "fp16_split": 2.5e15, "bf16_split": 2.5e15, "bf16_split3": 2.5e15,
+             "fp16_centred": 2.5e15}
+PRODUCTS = {"fp32": 1, "fp16_split": 3, "bf16_split": 3, "bf16_split3": 6, "fp16_centred": 1}
 TILE_KERNEL = {"fp32": "kde_tile_f32c", "fp16_split": "kde_tile_fp16x3", "bf16_split": "kde_tile_bf16x3",
-               "bf16_split3": "kde_tile_bf16x6"}
+               "bf16_split3": "kde_tile_bf16x6", "fp16_centred": "kde_tile_fp16c"}
 DTYPE = {"fp32": "f32", "fp16_split": "f16x3->f32->f64", "bf16_split": "bf16x3->f32->f64",
-         "bf16_split3": "bf16x6->f32->f64"}
+         "bf16_split3": "bf16x6->f32->f64", "fp16_centred": "f16->f32->f64"}
 HBM_PEAK = 8.0e12
 FP64_PEAK = 78.6e12
 FP32_PEAK = 157.3e12  # vector fp32 (published)
@@ -892,7 +893,7 @@ def main():
         print(f"[bench] checked {args.check_queries} queries: max rel err {err.max():.3e}", file=sys.stderr,
               flush=True)
         if not args.no_extras:
-            others = [f for f in ("fp16_split", "bf16_split", "bf16_split3", "fp32") if f != args.form]
+            others = [f for f in ("fp16_centred", "fp16_split", "bf16_split", "bf16_split3", "fp32") if f != args.form]
             result["forms"] = forms_run(stag, torch, lib, buf, Xd, Qd, a, idx, ref, others, n, m, d)
             print("[bench] other forms done", file=sys.stderr, flush=True)
     del Xd, Qd, S

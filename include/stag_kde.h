@@ -55,7 +55,9 @@ typedef enum {
   STAG_FORM_BF16_SPLIT = 1,  /* x = hi + lo in bf16, three bf16 products */
   STAG_FORM_FP16_SPLIT = 2,  /* x = hi + lo in fp16, three fp16 products */
   STAG_FORM_BF16_SPLIT3 = 3, /* x = hi + mid + lo in bf16, six bf16 products */
-  STAG_FORM_AUTO = 4         /* exact KDE only: the cheapest form whose a-priori bound is <= eps */
+  STAG_FORM_AUTO = 4,        /* exact KDE only: the cheapest form whose a-priori bound is <= eps */
+  STAG_FORM_FP16_CENTRED = 5 /* exact Gaussian KDE only: data grouped around centres c, one fp16
+                                product (q - c).(x - c) per pair; see stag_kde_exact */
 } stag_form;
 
 /* Kernel functions of Sec. "Kernel Density Estimation" (r = ||q - x||). */
@@ -128,6 +130,21 @@ double stag_e2lsh_collision_probability(double c, int32_t K, int32_t L);
  * Limits: 1 <= d <= 1024 (d > 256: fp32 form only; STAG_E_UNSUPPORTED
  * otherwise), n, m >= 1, n*d and m*d < 2^31.  FP16_SPLIT additionally needs |x_j| and
  * |2a log2(e) q_j| below 65504; out-of-range inputs give a NaN result.
+ * FP16_CENTRED (Gaussian kernel, d <= 256): the rows of X are grouped as for
+ * the fp32 form (at most 256 groups from seeded seed rows, each group padded
+ * to 32-row tiles) and each group g gets one centre c_g = fl32(mean of its
+ * rows).  The data are held once as fl16(x - c_g) with the offsets
+ * -a log2(e) ||x - c_g||^2 (fp32 from fp64); per group the tile forms each
+ * query's operand fl16(2a log2(e) (q - c_g)) and offset -a log2(e)
+ * ||q - c_g||^2, so every pair costs one fp16 matrix-core product instead
+ * of the split forms' three.  Each product carries the two fp16 roundings
+ * (relative 2^-11 each), so a term's exponent may be off by up to about
+ * 2^-10 * 2a log2(e) ||q - c_g|| ||x - c_g||: bound_out states that
+ * worst case (with the fp32 terms of the centred fp32 tile), which is far
+ * above the typical error because independent roundings cancel in sums of
+ * many terms.  STAG_FORM_AUTO never takes this form.  A data row with some
+ * |x_j - c_j| >= 65520, or a query with some |2a log2(e) (q_j - c_j)| >=
+ * 65520, gives NaN results (all of them, or that query's).
  * Results are deterministic and do not depend on m or on the other rows of Q
  * (each row's reduction order depends only on n). */
 stag_status stag_kde_exact(const float* X, int64_t n, const float* Q, int64_t m, int32_t d, double a,
@@ -138,7 +155,7 @@ stag_status stag_kde_exact(const float* X, int64_t n, const float* Q, int64_t m,
  * (code under HIP graph capture, tight serving loops, harnesses that forbid
  * hipMalloc).  Same arguments and results as stag_kde_exact with the
  * Gaussian kernel (bit for bit), except:
- *   - form is FP32, BF16_SPLIT, FP16_SPLIT or BF16_SPLIT3 (STAG_FORM_AUTO:
+ *   - form is FP32, BF16_SPLIT, FP16_SPLIT, BF16_SPLIT3 or FP16_CENTRED (STAG_FORM_AUTO:
  *     STAG_E_UNSUPPORTED) and flags may hold STAG_NORMALIZE only
  *     (STAG_CHECK_FINITE: STAG_E_UNSUPPORTED); eps is not taken;
  *   - every temporary (prepared operands, partial sums, rescue buffers) lives

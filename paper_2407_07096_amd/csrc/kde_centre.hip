@@ -1,5 +1,5 @@
-// Tile-local centring of the data for the fp32 exact tile (operand
-// preparation, row a1's reorder and centres).
+// Centring of the data for the fp32 and fp16 centred exact tiles (operand
+// preparation: the reorder of the rows into groups and their centres).
 //
 // The exact tile expands ||q - x||^2 around a centre.  Around the origin the
 // accumulators carry a(||q||^2 + ||x||^2), which for clustered data far from
@@ -27,6 +27,12 @@
 //                     rows fl32(x - c_T), beta = fl32(-a log2(e) ||x - c_T||^2)
 //                     (binary64 from the exact fp64 differences), radius
 //                     R_T = max ||x - c_T|| rounded up; padding rows beta = -1e30
+// The centred fp16 form uses one centre per group instead (the query operand
+// then changes only where the group does, not at every tile):
+//   tile_sums         fp64 coordinate sums per tile
+//   group_centres     c_g = fl32(group sum / group count), sums in tile order
+//   build_tiles_h     rows fl16(x - c_g), beta = fl32(-a log2(e) ||x - c_g||^2),
+//                     the group of every tile, R_g = max ||x - c_g|| rounded up
 // The result S(q) does not depend on the grouping beyond rounding; the
 // grouping depends only on X, so results stay deterministic and independent
 // of the queries.
@@ -302,6 +308,112 @@ __global__ __launch_bounds__(256) void build_tiles(const float* __restrict__ X, 
   }
 }
 
+// Centred fp16 form: coordinate sums of each 32-row tile below the padded
+// row count, fp64 (one wave per tile; lanes hold coordinates j = lane + 64 c).
+template <int DP>
+__global__ __launch_bounds__(256) void tile_sums(const float* __restrict__ X, int d, const int* __restrict__ map,
+                                                 const int64_t* __restrict__ n_pad, double* __restrict__ tsum) {
+  constexpr int NC = (DP + 63) / 64;
+  const int lane = threadIdx.x & 63;
+  const int64_t t = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (t * kTileRows >= *n_pad) return;
+  double sum[NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) sum[c] = 0.0;
+  for (int r = 0; r < kTileRows; ++r) {
+    const int src = map[t * kTileRows + r];
+    if (src < 0) continue;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      const int j = lane + 64 * c;
+      if (j < d) sum[c] += (double)X[(int64_t)src * d + j];
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    const int j = lane + 64 * c;
+    if (j < DP) tsum[t * DP + j] = sum[c];
+  }
+}
+
+// One workgroup per group g < K_pad: c_g = fl32(sum of its tiles' sums, in
+// tile order, / its row count) (zero for an empty or padding group), and
+// radius[g] = 0 (build_tiles_h raises it).
+template <int DP>
+__global__ __launch_bounds__(256) void group_centres(const double* __restrict__ tsum,
+                                                     const uint32_t* __restrict__ count,
+                                                     const uint32_t* __restrict__ goff, int K,
+                                                     float* __restrict__ centre, float* __restrict__ radius) {
+  const int g = blockIdx.x;
+  for (int j = threadIdx.x; j < DP; j += 256) {
+    float c = 0.0f;
+    if (g < K && count[g] > 0) {
+      double s = 0.0;
+      for (uint32_t t = goff[g] / kTileRows; t < goff[g + 1] / kTileRows; ++t) s += tsum[(int64_t)t * DP + j];
+      c = (float)(s / (double)count[g]);
+    }
+    centre[(int64_t)g * DP + j] = c;
+  }
+  if (threadIdx.x == 0) radius[g] = 0.0f;
+}
+
+// One wave per 32-row tile below the padded row count: tgroup[t] = the group
+// of its rows (its first row is never padding), rows fl16(x - c_g) (the
+// difference exact in binary64, rounded to fp32, then to fp16), beta =
+// fl32(-a log2(e) ||x - c_g||^2) from the exact differences (NaN if some
+// |x_j - c_j| rounds to fp16 infinity), padding rows 0 with beta = -1e30;
+// radius[g] = max over the group of ||x - c_g|| (fp32 rounded up; positive
+// floats order as their bit patterns, so the atomic maximum is exact and
+// does not depend on the order).
+template <int DP>
+__global__ __launch_bounds__(256) void build_tiles_h(const float* __restrict__ X, int d, const int* __restrict__ map,
+                                                     const uint8_t* __restrict__ label,
+                                                     const int64_t* __restrict__ n_pad, double neg_a_log2e,
+                                                     const float* __restrict__ centre,
+                                                     unsigned short* __restrict__ Xh, float* __restrict__ beta,
+                                                     int* __restrict__ tgroup, float* __restrict__ radius) {
+  constexpr int NC = (DP + 63) / 64;
+  const int lane = threadIdx.x & 63;
+  const int64_t t = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (t * kTileRows >= *n_pad) return;
+  const int g = label[map[t * kTileRows]];
+  if (lane == 0) tgroup[t] = g;
+  float cen[NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    const int j = lane + 64 * c;
+    cen[c] = j < DP ? centre[(int64_t)g * DP + j] : 0.0f;
+  }
+  double rmax = 0.0;
+  for (int r = 0; r < kTileRows; ++r) {
+    const int64_t row = t * kTileRows + r;
+    const int src = map[row];
+    double sq = 0.0;
+    bool over = false;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      const int j = lane + 64 * c;
+      unsigned short v = 0;
+      if (src >= 0 && j < d) {
+        const double e = (double)X[(int64_t)src * d + j] - (double)cen[c];  // exact in binary64
+        v = f16_rne((float)e);
+        over = over || (v & 0x7FFFu) == 0x7C00u;
+        sq = fma(e, e, sq);
+      }
+      if (j < DP) Xh[row * DP + j] = v;
+    }
+    for (int o = 32; o > 0; o >>= 1) sq += __shfl_xor(sq, o);
+    const bool any_over = __ballot(over) != 0ull;
+    if (src >= 0) rmax = fmax(rmax, sq);
+    if (lane == 0) beta[row] = src < 0 ? kPadOffset : (any_over ? __builtin_nanf("") : (float)(neg_a_log2e * sq));
+  }
+  if (lane == 0) {
+    const float rf = (float)sqrt(rmax);
+    const float ru = (double)rf < sqrt(rmax) ? nextafterf(rf, HUGE_VALF) : rf;
+    atomicMax(reinterpret_cast<unsigned int*>(radius) + g, __float_as_uint(ru));
+  }
+}
+
 template <int DP>
 stag_status launch_assign(const float* X, int64_t n, int d, const CentreTemp& t, hipStream_t st) {
   hipLaunchKernelGGL(assign_seeds<DP>, dim3((unsigned)ceil_div(n, 128)), dim3(256), 0, st, X, n, d, t.seeds, t.hn,
@@ -315,6 +427,22 @@ stag_status launch_build(const float* X, int d, const int* map, const int64_t* n
   hipLaunchKernelGGL(build_tiles<DP>, dim3((unsigned)ceil_div(tiles_max, 4)), dim3(256), 0, st, X, d, map, n_pad,
                      neg_a_log2e, Xc, beta, centre, radius);
   return check_launch("build_tiles");
+}
+
+template <int DP>
+stag_status launch_build_h(const float* X, int d, const Operands& o, const CentreTemp& t, double neg_a_log2e,
+                           hipStream_t st) {
+  const int64_t tiles_max = o.rows_pad / kTileRows;
+  hipLaunchKernelGGL(tile_sums<DP>, dim3((unsigned)ceil_div(tiles_max, 4)), dim3(256), 0, st, X, d, t.map,
+                     o.n_pad_dev, t.tsum);
+  STAG_TRY(check_launch("tile_sums"));
+  hipLaunchKernelGGL(group_centres<DP>, dim3((unsigned)t.K_pad), dim3(256), 0, st, t.tsum, t.count, t.goff, t.K,
+                     o.centre, o.radius);
+  STAG_TRY(check_launch("group_centres"));
+  hipLaunchKernelGGL(build_tiles_h<DP>, dim3((unsigned)ceil_div(tiles_max, 4)), dim3(256), 0, st, X, d, t.map,
+                     t.label, o.n_pad_dev, neg_a_log2e, o.centre, static_cast<unsigned short*>(o.part[0]), o.off,
+                     o.tgroup, o.radius);
+  return check_launch("build_tiles_h");
 }
 
 int seed_count(int64_t n) {
@@ -339,6 +467,8 @@ stag_status alloc_centre_temp(const Operands& o, Workspace& ws, CentreTemp* t) {
   STAG_TRY(ws.alloc(&t->count, (size_t)t->K));
   STAG_TRY(ws.alloc(&t->goff, (size_t)t->K + 1));
   STAG_TRY(ws.alloc(&t->map, (size_t)o.rows_pad));
+  t->tsum = nullptr;
+  if (o.form == STAG_FORM_FP16_CENTRED) STAG_TRY(ws.alloc(&t->tsum, (size_t)(o.rows_pad / kTileRows) * o.dp));
   return STAG_OK;
 }
 
@@ -364,9 +494,9 @@ stag_status alloc_centred_operands(int64_t n, int d, Workspace& ws, Operands* ou
   return STAG_OK;
 }
 
-stag_status prep_centred_operands(const float* X, double a_tile, const Operands& o, const CentreTemp& t,
-                                  hipStream_t st) {
-  ScopedTimer tm("kde_centre", st);
+// The grouping shared by both centred forms: seeds, nearest seed of every
+// row, per-label counts and offsets (n_pad), and the row map.
+static stag_status group_rows(const float* X, const Operands& o, const CentreTemp& t, hipStream_t st) {
   const int64_t n = o.rows;
   const int d = o.d, dp = o.dp;
   hipLaunchKernelGGL(pick_seeds, dim3((unsigned)ceil_div(t.K_pad, 4)), dim3(256), 0, st, X, n, d, dp, t.K, t.K_pad,
@@ -395,6 +525,14 @@ stag_status prep_centred_operands(const float* X, double a_tile, const Operands&
   hipLaunchKernelGGL(scatter_labels, dim3((unsigned)t.nblk), dim3(256), 0, st, t.label, n, t.nblk, t.hist, t.goff,
                      t.map);
   STAG_TRY(check_launch("scatter_labels"));
+  return STAG_OK;
+}
+
+stag_status prep_centred_operands(const float* X, double a_tile, const Operands& o, const CentreTemp& t,
+                                  hipStream_t st) {
+  ScopedTimer tm("kde_centre", st);
+  const int d = o.d, dp = o.dp;
+  STAG_TRY(group_rows(X, o, t, st));
   const double nl = -a_tile * kLog2e;
   const int64_t tiles_max = o.rows_pad / kTileRows;
   float* Xc = static_cast<float*>(o.part[0]);
@@ -409,6 +547,51 @@ stag_status prep_centred_operands(const float* X, double a_tile, const Operands&
     case 224: return launch_build<224>(X, d, t.map, o.n_pad_dev, nl, Xc, o.off, o.centre, o.radius, tiles_max, st);
     default: return launch_build<256>(X, d, t.map, o.n_pad_dev, nl, Xc, o.off, o.centre, o.radius, tiles_max, st);
   }
+}
+
+stag_status alloc_centred_h_operands(int64_t n, int d, Workspace& ws, Operands* out) {
+  const int dp = exact_padded_dim(d);
+  if (dp == 0 || dp > 256) return fail(STAG_E_UNSUPPORTED, "centred operands need d <= 256");
+  const int64_t rows_max = centred_rows_max(n);
+  const int K_pad = (int)round_up(seed_count(n), 32);
+  out->form = STAG_FORM_FP16_CENTRED;
+  out->rows = n;
+  out->rows_pad = rows_max;
+  out->d = d;
+  out->dp = dp;
+  for (int p = 0; p < 3; ++p) out->part[p] = nullptr;
+  STAG_TRY(ws.alloc_bytes(&out->part[0], (size_t)rows_max * dp * sizeof(unsigned short)));
+  STAG_TRY(ws.alloc(&out->off, (size_t)rows_max));
+  out->aug = nullptr;
+  out->nrm = nullptr;
+  out->max_nrm_bits = nullptr;
+  out->centred = true;
+  STAG_TRY(ws.alloc(&out->centre, (size_t)K_pad * dp));
+  STAG_TRY(ws.alloc(&out->radius, (size_t)K_pad));
+  STAG_TRY(ws.alloc(&out->tgroup, (size_t)(rows_max / kTileRows)));
+  STAG_TRY(ws.alloc(&out->n_pad_dev, 1));
+  return STAG_OK;
+}
+
+stag_status prep_centred_h_operands(const float* X, double a_tile, const Operands& o, const CentreTemp& t,
+                                    hipStream_t st) {
+  ScopedTimer tm("kde_centre", st);
+  if (o.form != STAG_FORM_FP16_CENTRED || !t.tsum) return fail(STAG_E_INVAL, "centred fp16 operands: bad set-up");
+  const int d = o.d;
+  STAG_TRY(group_rows(X, o, t, st));
+  const double nl = -a_tile * kLog2e;
+  switch (o.dp) {
+    case 16: return launch_build_h<16>(X, d, o, t, nl, st);
+    case 32: return launch_build_h<32>(X, d, o, t, nl, st);
+    case 64: return launch_build_h<64>(X, d, o, t, nl, st);
+    case 96: return launch_build_h<96>(X, d, o, t, nl, st);
+    case 128: return launch_build_h<128>(X, d, o, t, nl, st);
+    case 160: return launch_build_h<160>(X, d, o, t, nl, st);
+    case 192: return launch_build_h<192>(X, d, o, t, nl, st);
+    case 224: return launch_build_h<224>(X, d, o, t, nl, st);
+    case 256: return launch_build_h<256>(X, d, o, t, nl, st);
+  }
+  return fail(STAG_E_UNSUPPORTED, "centred operands: padded dimension %d", o.dp);
 }
 
 }  // namespace stag

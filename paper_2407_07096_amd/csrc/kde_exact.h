@@ -25,10 +25,16 @@ struct Operands {
   // (padding rows -1e30); centre [rows_pad/32][dp] fp32 c_T, radius
   // [rows_pad/32] max ||x - c_T|| (rounded up).  rows_pad is an upper bound
   // of the padded row count; the count itself is *n_pad_dev (device).
+  // Centred fp16 data (STAG_FORM_FP16_CENTRED, d <= 256): the same grouping
+  // with one centre c_g per group: part[0] holds fl16(x - c_g) [rows_pad][dp],
+  // off -a log2(e) ||x - c_g||^2 (NaN for a row outside fp16's range),
+  // tgroup [rows_pad/32] the group of each tile, centre [K_pad][dp] fp32 c_g,
+  // radius [K_pad] max ||x - c_g|| over the group (rounded up).
   bool centred = false;
   float* centre = nullptr;
   float* radius = nullptr;
   int64_t* n_pad_dev = nullptr;
+  int* tgroup = nullptr;
 };
 
 // Temporaries of the centring's grouping (kde_centre.hip).
@@ -39,6 +45,8 @@ struct CentreTemp {
   uint8_t* label = nullptr;
   uint32_t *hist = nullptr, *count = nullptr, *goff = nullptr;
   int* map = nullptr;
+  // fp16 form: per-tile fp64 coordinate sums [rows_pad/32][dp] (group means)
+  double* tsum = nullptr;
 };
 // Upper bound of the padded row count of centred data of n rows.
 int64_t centred_rows_max(int64_t n);
@@ -50,6 +58,11 @@ stag_status alloc_centred_operands(int64_t n, int d, Workspace& ws, Operands* ou
 stag_status alloc_centre_temp(const Operands& o, Workspace& ws, CentreTemp* t);
 stag_status prep_centred_operands(const float* X, double a_tile, const Operands& o, const CentreTemp& t,
                                   hipStream_t st);
+// The same for the centred fp16 form (group centres; o.form ==
+// STAG_FORM_FP16_CENTRED, temporaries from alloc_centre_temp).
+stag_status alloc_centred_h_operands(int64_t n, int d, Workspace& ws, Operands* out);
+stag_status prep_centred_h_operands(const float* X, double a_tile, const Operands& o, const CentreTemp& t,
+                                    hipStream_t st);
 
 // Rounding-error model of one result.  The tiles produce the exponent
 // E = -lambda D (base 2; lambda = la) with an absolute error of at most

@@ -668,7 +668,10 @@ stag_status check_exact_args(const char* fn, const float* X, int64_t n, const fl
   if (!(a > 0.0) || !std::isfinite(a)) return fail(STAG_E_INVAL, "%s: a must be positive and finite", fn);
   if (kernel < STAG_KERNEL_GAUSSIAN || kernel > STAG_KERNEL_LOGISTIC)
     return fail(STAG_E_INVAL, "%s: unknown kernel %d", fn, kernel);
-  if (form < STAG_FORM_FP32 || form > STAG_FORM_AUTO) return fail(STAG_E_INVAL, "%s: unknown form %d", fn, form);
+  if (form < STAG_FORM_FP32 || form > STAG_FORM_FP16_CENTRED)
+    return fail(STAG_E_INVAL, "%s: unknown form %d", fn, form);
+  if (form == STAG_FORM_FP16_CENTRED && kernel != STAG_KERNEL_GAUSSIAN)
+    return fail(STAG_E_UNSUPPORTED, "%s: the fp16 centred form computes Gaussian sums only", fn);
   if (form == STAG_FORM_AUTO && !(eps > 0.0))
     return fail(STAG_E_INVAL, "%s: STAG_FORM_AUTO needs a target eps > 0", fn);
   if (flags & ~(STAG_NORMALIZE | STAG_CHECK_FINITE)) return fail(STAG_E_INVAL, "%s: unknown flags 0x%x", fn, flags);
@@ -690,22 +693,26 @@ struct ExactBuffers {
   double* partial = nullptr;
   int* near_over = nullptr;  // exponential kernel
   RescueBuffers rb;
-  // centred data (fp32 form, Gaussian kernel, d <= 256)
+  // centred data (fp32 or fp16 centred form, Gaussian kernel, d <= 256)
   bool centred = false;
   CentreTemp ct;
   double *bpart = nullptr, *bp2 = nullptr;
 };
 
 // The fp32 form of the Gaussian sum centres the data tile by tile (the wide
-// tile of d > 256 does not).
+// tile of d > 256 does not); the fp16 centred form centres it group by group.
 bool use_centred(int form, int kernel, int d) {
-  return form == STAG_FORM_FP32 && kernel == STAG_KERNEL_GAUSSIAN && exact_padded_dim(d) <= 256;
+  return (form == STAG_FORM_FP32 || form == STAG_FORM_FP16_CENTRED) && kernel == STAG_KERNEL_GAUSSIAN &&
+         exact_padded_dim(d) <= 256;
 }
 
 stag_status alloc_exact(int form, int kernel, int64_t n, int64_t m, int d, Workspace& ws, ExactBuffers* b) {
   if (use_centred(form, kernel, d)) {
     b->centred = true;
-    STAG_TRY(alloc_centred_operands(n, d, ws, &b->xo));
+    if (form == STAG_FORM_FP16_CENTRED)
+      STAG_TRY(alloc_centred_h_operands(n, d, ws, &b->xo));
+    else
+      STAG_TRY(alloc_centred_operands(n, d, ws, &b->xo));
     STAG_TRY(alloc_centre_temp(b->xo, ws, &b->ct));
     STAG_TRY(alloc_operands(STAG_FORM_FP32, m, d, true, ws, &b->qo));
     b->P = (int)exact_chunks(b->xo.rows_pad);
@@ -722,15 +729,19 @@ stag_status alloc_exact(int form, int kernel, int64_t n, int64_t m, int d, Works
   return alloc_rescue(kernel, b->P, b->qo, ws, &b->rb);
 }
 
-// Centred fp32 Gaussian sum: grouping and centring of X, the unscaled query
-// copy, the centred tiles with their bound numerators, the reduction, and the
-// underflow rescue (max pass, offsets -m_q, second pass) on the same tiles.
+// Centred Gaussian sum (fp32, or the fp16 centred form): grouping and
+// centring of X, the unscaled query copy, the centred tiles with their bound
+// numerators, the reduction, and the underflow rescue (max pass, offsets
+// -m_q, second pass) on the same tiles.
 stag_status run_centred(const float* X, int64_t n, const float* Q, int64_t m, int32_t d, double a, uint32_t flags,
                         double* S_out, double* bound_out, const ExactBuffers& b, hipStream_t st) {
   const Operands& xo = b.xo;
   const Operands& qo = b.qo;
   const RescueBuffers& rb = b.rb;
-  STAG_TRY(prep_centred_operands(X, a, xo, b.ct, st));
+  if (xo.form == STAG_FORM_FP16_CENTRED)
+    STAG_TRY(prep_centred_h_operands(X, a, xo, b.ct, st));
+  else
+    STAG_TRY(prep_centred_operands(X, a, xo, b.ct, st));
   STAG_TRY(prep_any(STAG_FORM_FP32, Q, m, d, qo.dp, qo.rows_pad, 1.0, 0.0, 1, qo.part, qo.off, nullptr, qo.nrm,
                     nullptr, st));
   const BoundModel bm = make_bound_model(STAG_FORM_FP32, d, a, STAG_KERNEL_GAUSSIAN);

@@ -915,6 +915,279 @@ __global__ __launch_bounds__(256, 2) void tile_split_w64(
   }
 }
 
+// Centred fp16 form (STAG_FORM_FP16_CENTRED): one fp16 product per pair.
+// The data rows come grouped around centres c_g (each group a run of whole
+// 32-row tiles, tgroup[tile] = g), stored once as fl16(x - c_g) with
+// beta = fl32(-la ||x - c_g||^2).  Whenever the group of the data tile
+// changes, every wave forms its queries' operand fl16(2 la fl32(q - c_g))
+// and alpha = fl32(-la ||q - c_g||^2) + qoff from the fp32 query rows, so
+//   E = alpha + beta + fl16(2 la (q - c_g)) . fl16(x - c_g),
+// and, per query and group, the bound factor 2^{M} - 1 of
+// h1c_bound_factor; bpart collects the tile sums times that factor.
+// Up to d = 128, 64 queries per wave as in tile_split_w64 (each A operand
+// read from LDS feeds two 32-query blocks), 256 per workgroup; above, 32 per
+// wave (the query operands alone take 4 d / 16 registers per block).  With
+// qtile_active, a workgroup whose 128-query tiles are all inactive returns at
+// once and a wave whose tile is inactive only stages.  A query element with
+// |2 la (q_j - c_j)| >= 65520 (fp16 infinity) makes alpha NaN for the group.
+
+// Exponent error bound M (base 2) of every term of a (query, group):
+//   fp32 part as in the centred fp32 tile: c_cent (la (|q - c| + R)^2 + |qoff|)
+//   two fp16 roundings (and the fp32 roundings before them) of each product:
+//     2 la |q - c| R 2^-10 (1 + 2^-10) by Cauchy-Schwarz
+//   fp16 subnormal spacing 2^-24 (at most 2^-25 per rounding) on either
+//   operand: 2^-25 sqrt(dp) (2 la |q - c| + R) (1 + 2^-6), and dp 2^-50 < 1e-12
+// and the relative error of the terms' sum is at most 2^M - 1.
+__device__ inline float h1c_bound_factor(float sqt, float R, float qoff, float la, float c_cent, float rdp) {
+  const float dq = __builtin_amdgcn_sqrtf(sqt);
+  const float s2 = 2.0f * la;
+  const float r = dq + R;
+  const float M = (c_cent * (la * r * r + fabsf(qoff)) + s2 * dq * R * 0x1.004p-10f +
+                   0x1.04p-25f * rdp * (s2 * dq + R) + 1.0e-12f) *
+                  1.00001f;
+  const float x = M * 0.6931472f;
+  // e^x - 1 <= x (1 + x) on [0, 1]; beyond, 2^M - 1 itself (kept finite so
+  // that a zero tile sum times it stays 0)
+  const float e = x <= 1.0f ? x * (1.0f + x) : __builtin_amdgcn_exp2f(M) - 1.0f;
+  return fminf(e, 3.0e38f);
+}
+
+template <int DP>
+constexpr int kH1cBlocks = DP <= 128 ? 2 : 1;  // 32-query blocks per wave
+
+template <int DP, int MODE>
+__global__ __launch_bounds__(256, 2) void tile_h1c(const unsigned short* __restrict__ Xh,
+                                                   const float* __restrict__ beta, const int* __restrict__ tgroup,
+                                                   const float* __restrict__ cen, const float* __restrict__ grad,
+                                                   const int64_t* __restrict__ n_pad_dev,
+                                                   const float* __restrict__ Qu, const float* __restrict__ qoff,
+                                                   float la, int n_qtw, int64_t m_pad,
+                                                   double* __restrict__ partial, TileExtra ex) {
+  static_assert(MODE == kModeGauss || MODE == kModeGaussRescue || MODE == kModeMax, "Gaussian sums and maxima");
+  constexpr int NB = kH1cBlocks<DP>;
+  constexpr int QW = 32 * NB;  // queries per wave
+  constexpr int KS = DP / 16;
+  constexpr int LD = DP + 8;
+  constexpr int V_ROW = DP / 8;
+  constexpr int NV = kTileRows * V_ROW;
+  constexpr int NLD = (NV + 255) / 256;
+  constexpr int NMMA = KS * NB;
+  __shared__ __attribute__((aligned(16))) unsigned short tile[2][kTileRows * LD];
+  __shared__ __attribute__((aligned(16))) float tbeta[2][kTileRows];
+
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, r32 = lane & 31, h = lane >> 5;
+  const int qtile = blockIdx.x % n_qtw;
+  const int chunk = blockIdx.x / n_qtw;
+  const int64_t col0 = (int64_t)qtile * (4 * QW) + wave * QW;
+  if (ex.qtile_active) {
+    // the workgroup's 128-query tiles (NB of them)
+    bool any = false;
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      const int64_t tq = (int64_t)qtile * NB + b;
+      any = any || (tq * kBQ < m_pad && ex.qtile_active[tq] != 0);
+    }
+    if (!any) return;
+  }
+  bool live = col0 < m_pad;  // wave-uniform
+  if (live && ex.qtile_active) live = ex.qtile_active[col0 / kBQ] != 0;
+  int64_t qi[NB];
+#pragma unroll
+  for (int b = 0; b < NB; ++b) qi[b] = col0 + 32 * b + r32;
+  const int64_t n_pad = *n_pad_dev;
+  const int64_t row0 = (int64_t)chunk * kChunkRows;
+  if (row0 >= n_pad) {
+    if (live && h == 0)
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        partial[(int64_t)chunk * m_pad + qi[b]] = acc_init<MODE>();
+        if (ex.bpart) ex.bpart[(int64_t)chunk * m_pad + qi[b]] = 0.0;
+      }
+    return;
+  }
+  const int64_t rem = (n_pad - row0) / kTileRows;
+  const int ntiles = (int)(rem < kChunkRows / kTileRows ? rem : kChunkRows / kTileRows);
+  const int64_t tile0 = row0 / kTileRows;
+  const float s2 = 2.0f * la;
+  const float c_cent = ex.c_cent;
+  const float rdp = __builtin_amdgcn_sqrtf((float)DP);
+  float qo[NB];
+#pragma unroll
+  for (int b = 0; b < NB; ++b) qo[b] = live ? qoff[qi[b]] : 0.0f;
+
+  // the queries' operands, offsets and bound factors for group g
+  u16x8 bq[NB][KS];
+  float alpha[NB], eg[NB];
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    alpha[b] = 0.0f;
+    eg[b] = 0.0f;
+  }
+  int cur = -1;
+  auto form_queries = [&](int g) {
+    const float* cg = cen + (int64_t)g * DP;
+    float sq[NB], mx[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      sq[b] = 0.0f;
+      mx[b] = 0.0f;
+    }
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+      const int k0 = s * 16 + h * 8;
+      const f32x4 c4[2] = {*reinterpret_cast<const f32x4*>(cg + k0), *reinterpret_cast<const f32x4*>(cg + k0 + 4)};
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        const f32x4 u4[2] = {*reinterpret_cast<const f32x4*>(Qu + qi[b] * DP + k0),
+                             *reinterpret_cast<const f32x4*>(Qu + qi[b] * DP + k0 + 4)};
+        u16x8 o;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          const float e = u4[i >> 2][i & 3] - c4[i >> 2][i & 3];
+          sq[b] = fmaf(e, e, sq[b]);
+          const float w = e * s2;
+          mx[b] = fmaxf(mx[b], fabsf(w));
+          o[i] = f16_rne(w);
+        }
+        bq[b][s] = o;
+      }
+      // keeps the loads of the next k-step behind this one (register use)
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    const float R = grad[g];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      const float t = sq[b] + __shfl_xor(sq[b], 32);
+      const float m = fmaxf(mx[b], __shfl_xor(mx[b], 32));
+      // a NaN element fails the comparison as well
+      alpha[b] = m < 65520.0f ? fmaf(-la, t, qo[b]) : __builtin_nanf("");
+      if constexpr (MODE != kModeMax) eg[b] = h1c_bound_factor(t, R, qo[b], la, c_cent, rdp);
+    }
+  };
+
+  u16x8 stage[NLD];
+  float sbeta;
+  auto gload = [&](int t) {
+    const u16x8* srcp = reinterpret_cast<const u16x8*>(Xh + (row0 + (int64_t)t * kTileRows) * DP);
+#pragma unroll
+    for (int k = 0; k < NLD; ++k) stage[k] = srcp[min(tid + 256 * k, NV - 1)];
+    sbeta = beta[row0 + (int64_t)t * kTileRows + (tid & 31)];
+  };
+  auto lstore = [&](int buf) {
+#pragma unroll
+    for (int k = 0; k < NLD; ++k) {
+      const int idx = min(tid + 256 * k, NV - 1);
+      const int r = idx / V_ROW, c8 = idx % V_ROW;
+      *reinterpret_cast<u16x8*>(&tile[buf][r * LD + c8 * 8]) = stage[k];
+    }
+    tbeta[buf][tid & 31] = sbeta;
+  };
+
+  double acc[NB], bacc[NB];
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    acc[b] = acc_init<MODE>();
+    bacc[b] = 0.0;
+  }
+  auto epilogue = [&](const f32x16 (&d)[NB], const float (&f)[NB]) {
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      if constexpr (MODE == kModeMax) {
+        float mv = d[b][0];
+#pragma unroll
+        for (int i = 1; i < 16; ++i) mv = fmaxf(mv, d[b][i]);
+        acc[b] = acc_add<MODE>(acc[b], (double)mv);
+      } else {
+        float e[16];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) e[i] = d[b][i];
+        const float sm = kernel_tile_sum<MODE>(e);
+        acc[b] += (double)sm;
+        bacc[b] += (double)(sm * f[b]);
+      }
+    }
+  };
+  auto step = [&](int t, const f32x16 (&d)[NB], const float (&f)[NB], f32x16 (&nc)[NB], float (&nf)[NB]) {
+    const int buf = t & 1;
+    __syncthreads();
+    if (live) {
+      const int g = tgroup[tile0 + t];
+      if (g != cur) {
+        form_queries(g);
+        cur = g;
+      }
+      epilogue(d, f);
+      // the accumulators start from the offsets alpha_q + beta_x of their pairs
+      f32x16 c[NB];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const f32x4 bv = *reinterpret_cast<const f32x4*>(&tbeta[buf][8 * q + 4 * h]);
+#pragma unroll
+        for (int b = 0; b < NB; ++b)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) c[b][4 * q + i] = alpha[b] + bv[i];
+      }
+#pragma unroll
+      for (int s = 0; s < KS; ++s) {
+        const u16x8 a = *reinterpret_cast<const u16x8*>(&tile[buf][r32 * LD + s * 16 + h * 8]);
+#pragma unroll
+        for (int b = 0; b < NB; ++b) c[b] = mma16<STAG_FORM_FP16_SPLIT>(a, bq[b][s], c[b]);
+      }
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        nc[b] = c[b];
+        nf[b] = eg[b];
+      }
+    }
+    lstore(buf ^ 1);
+    gload(min(t + 2, ntiles - 1));
+#pragma unroll
+    for (int i = 0; i < NMMA; ++i) {
+      __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+      __builtin_amdgcn_sched_group_barrier(0x002, (40 * NB + NMMA - 1) / NMMA, 0);
+    }
+  };
+
+  gload(0);
+  lstore(0);
+  gload(min(1, ntiles - 1));
+  f32x16 ca[NB], cb[NB];
+  float fa[NB], fb[NB];
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      ca[b][i] = kPadOffset;  // kernel value 0: neutral first epilogue
+      cb[b][i] = kPadOffset;
+    }
+    fa[b] = 0.0f;
+    fb[b] = 0.0f;
+  }
+  int t = 0;
+  for (; t + 1 < ntiles; t += 2) {
+    step(t, ca, fa, cb, fb);
+    step(t + 1, cb, fb, ca, fa);
+  }
+  if (t < ntiles) {
+    step(t, ca, fa, cb, fb);
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      ca[b] = cb[b];
+      fa[b] = fb[b];
+    }
+  }
+  if (live) epilogue(ca, fa);
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    const double o = __shfl_down(acc[b], 32);
+    const double ob = __shfl_down(bacc[b], 32);
+    if (live && h == 0) {
+      partial[(int64_t)chunk * m_pad + qi[b]] = acc_add<MODE>(acc[b], o);
+      if (ex.bpart) ex.bpart[(int64_t)chunk * m_pad + qi[b]] = bacc[b] + ob;
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Wide rows (256 < d <= 1024), fp32 form.  The 32 queries of a workgroup sit
 // in LDS as the B operand ([32][DP+4] floats, loaded once); each of the 4
@@ -1108,6 +1381,34 @@ stag_status dispatch_f32c(const Operands& xo, const Operands& qo, float la, int 
   return fail(STAG_E_UNSUPPORTED, "padded dimension %d not instantiated", xo.dp);
 }
 
+template <int DP, int MODE>
+stag_status launch_tile_h1c(const Operands& xo, const Operands& qo, float la, int P, double* partial,
+                            const TileExtra& ex, hipStream_t st) {
+  ScopedTimer tm(rescue_timer(ex, "kde_tile_fp16c"), st);
+  const int n_qtw = (int)ceil_div(qo.rows_pad, 128 * kH1cBlocks<DP>);
+  hipLaunchKernelGGL((tile_h1c<DP, MODE>), dim3((unsigned)((int64_t)n_qtw * P)), dim3(256), 0, st,
+                     static_cast<const unsigned short*>(xo.part[0]), xo.off, xo.tgroup, xo.centre, xo.radius,
+                     xo.n_pad_dev, (const float*)qo.part[0], qo.off, la, n_qtw, qo.rows_pad, partial, ex);
+  return check_launch("tile_h1c");
+}
+
+template <int MODE>
+stag_status dispatch_h1c(const Operands& xo, const Operands& qo, float la, int P, double* partial,
+                         const TileExtra& ex, hipStream_t st) {
+  switch (xo.dp) {
+    case 16: return launch_tile_h1c<16, MODE>(xo, qo, la, P, partial, ex, st);
+    case 32: return launch_tile_h1c<32, MODE>(xo, qo, la, P, partial, ex, st);
+    case 64: return launch_tile_h1c<64, MODE>(xo, qo, la, P, partial, ex, st);
+    case 96: return launch_tile_h1c<96, MODE>(xo, qo, la, P, partial, ex, st);
+    case 128: return launch_tile_h1c<128, MODE>(xo, qo, la, P, partial, ex, st);
+    case 160: return launch_tile_h1c<160, MODE>(xo, qo, la, P, partial, ex, st);
+    case 192: return launch_tile_h1c<192, MODE>(xo, qo, la, P, partial, ex, st);
+    case 224: return launch_tile_h1c<224, MODE>(xo, qo, la, P, partial, ex, st);
+    case 256: return launch_tile_h1c<256, MODE>(xo, qo, la, P, partial, ex, st);
+  }
+  return fail(STAG_E_UNSUPPORTED, "padded dimension %d not instantiated", xo.dp);
+}
+
 // All tiles of one launch in epilogue mode MODE: wide fp32 rows, the fp32
 // tile, the centred fp32 tile or a split form, by padded dimension.
 template <int MODE>
@@ -1116,10 +1417,13 @@ stag_status launch_tiles(const Operands& xo, const Operands& qo, double* partial
   const int P = (int)exact_chunks(xo.rows_pad);
   const int n_qtiles = (int)(qo.rows_pad / kBQ);
   if (xo.centred) {
-    if constexpr (MODE == kModeGauss || MODE == kModeGaussRescue || MODE == kModeMax)
+    if constexpr (MODE == kModeGauss || MODE == kModeGaussRescue || MODE == kModeMax) {
+      if (xo.form == STAG_FORM_FP16_CENTRED)
+        return dispatch_h1c<MODE>(xo, qo, (float)(ex.a * kLog2e), P, partial, ex, st);
       return dispatch_f32c<MODE>(xo, qo, (float)(ex.a * kLog2e), n_qtiles, P, partial, ex, st);
-    else
+    } else {
       return fail(STAG_E_UNSUPPORTED, "centred data: Gaussian sums only");
+    }
   }
   if (xo.dp > 256) {
     if (xo.form != STAG_FORM_FP32) return fail(STAG_E_UNSUPPORTED, "d > 256 needs the fp32 form");
