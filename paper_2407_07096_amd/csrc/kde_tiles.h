@@ -26,7 +26,6 @@ constexpr int kTileRows = 32;
 constexpr int kWaves = 4;
 constexpr int kBQ = 32 * kWaves;      // queries per workgroup
 constexpr int kChunkRows = 4096;      // data rows per partial sum
-constexpr int kW64Chunks = 8;         // chunks per workgroup of tile_split_w64 (queries loaded once)
 constexpr float kPadOffset = -1.0e30f;  // exponent offset of padding rows: exp2 -> 0
 constexpr unsigned short kBf16One = 0x3F80;
 constexpr int kWideMaxDim = 1024;     // largest d of the wide fp32 tile
@@ -757,16 +756,12 @@ __global__ __launch_bounds__(256, 2) void tile_split(
 // is an odd multiple of 128 the last workgroup's waves 2 and 3 have no
 // queries and only stage tiles.  The products per block come in the same k
 // order, from the same accumulator seeds, as in tile_split, so every result
-// is bitwise the same.  A workgroup takes kW64Chunks consecutive 4096-row
-// chunks (one partial each) for its 256 queries, so that their operands are
-// fetched once per 8 chunks instead of once per chunk (at n = 2e6, m = 2e5,
-// d = 128 the per-chunk query loads were 50 of the launch's 63 GB of L2
-// misses).  Gaussian sums only (kModeGauss).
+// is bitwise the same.  Gaussian sums only (kModeGauss).
 template <int FORM, int DP, int MODE>
 __global__ __launch_bounds__(256, 2) void tile_split_w64(
     const unsigned short* __restrict__ X0, const unsigned short* __restrict__ X1, const float* __restrict__ Xoff,
     const unsigned short* __restrict__ Q0, const unsigned short* __restrict__ Q1, const float* __restrict__ Qoff,
-    int64_t n_pad, int n_qt256, int64_t m_pad, int P, double* __restrict__ partial) {
+    int64_t n_pad, int n_qt256, int64_t m_pad, double* __restrict__ partial) {
   static_assert(MODE == kModeGauss, "Gaussian sums only");
   constexpr int NP = 2;
   constexpr int KS = DP / 16;
@@ -780,7 +775,7 @@ __global__ __launch_bounds__(256, 2) void tile_split_w64(
 
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, r32 = lane & 31, h = lane >> 5;
   const int qtile = blockIdx.x % n_qt256;
-  const int cgroup = blockIdx.x / n_qt256;  // kW64Chunks consecutive chunks
+  const int chunk = blockIdx.x / n_qt256;
   const int64_t col0 = (int64_t)qtile * 256 + wave * 64;
   const bool live = col0 < m_pad;  // wave-uniform
   const int64_t q0 = col0 + r32, q1 = q0 + 32;
@@ -802,8 +797,9 @@ __global__ __launch_bounds__(256, 2) void tile_split_w64(
     }
   }
 
-  int64_t row0 = 0;  // the current chunk's first row and tile count
-  int ntiles = 0;
+  const int64_t row0 = (int64_t)chunk * kChunkRows;
+  const int64_t rem = (n_pad - row0) / kTileRows;
+  const int ntiles = (int)(rem < kChunkRows / kTileRows ? rem : kChunkRows / kTileRows);
 
   const unsigned short* Xpp[2] = {X0, X1};
   u16x8 stage[NP][NLD];
@@ -829,7 +825,7 @@ __global__ __launch_bounds__(256, 2) void tile_split_w64(
     tbeta[buf][tid & 31] = sbeta;
   };
 
-  double acc0, acc1;
+  double acc0 = 0.0, acc1 = 0.0;
   auto step = [&](int t, const f32x16& d0, const f32x16& d1, f32x16& n0, f32x16& n1) {
     const int buf = t & 1;
     __syncthreads();
@@ -880,53 +876,42 @@ __global__ __launch_bounds__(256, 2) void tile_split_w64(
     }
   };
 
-  const int chunk_end = min(P, (cgroup + 1) * kW64Chunks);
-  for (int chunk = cgroup * kW64Chunks; chunk < chunk_end; ++chunk) {
-    row0 = (int64_t)chunk * kChunkRows;
-    {
-      const int64_t rem = (n_pad - row0) / kTileRows;
-      ntiles = (int)(rem < kChunkRows / kTileRows ? rem : kChunkRows / kTileRows);
-    }
-    acc0 = 0.0;
-    acc1 = 0.0;
-    __syncthreads();  // every wave is done with the previous chunk's LDS tiles
-    gload(0);
-    lstore(0);
-    gload(min(1, ntiles - 1));
-    f32x16 ca0, ca1, cb0, cb1;
-  #pragma unroll
+  gload(0);
+  lstore(0);
+  gload(min(1, ntiles - 1));
+  f32x16 ca0, ca1, cb0, cb1;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    ca0[i] = kPadOffset;  // kernel value 0: neutral first epilogue
+    ca1[i] = kPadOffset;
+    cb0[i] = kPadOffset;
+    cb1[i] = kPadOffset;
+  }
+  int t = 0;
+  for (; t + 1 < ntiles; t += 2) {
+    step(t, ca0, ca1, cb0, cb1);
+    step(t + 1, cb0, cb1, ca0, ca1);
+  }
+  if (t < ntiles) {
+    step(t, ca0, ca1, cb0, cb1);
+    ca0 = cb0;
+    ca1 = cb1;
+  }
+  if (live) {
+    float e0[16], e1[16];
+#pragma unroll
     for (int i = 0; i < 16; ++i) {
-      ca0[i] = kPadOffset;  // kernel value 0: neutral first epilogue
-      ca1[i] = kPadOffset;
-      cb0[i] = kPadOffset;
-      cb1[i] = kPadOffset;
+      e0[i] = ca0[i];
+      e1[i] = ca1[i];
     }
-    int t = 0;
-    for (; t + 1 < ntiles; t += 2) {
-      step(t, ca0, ca1, cb0, cb1);
-      step(t + 1, cb0, cb1, ca0, ca1);
-    }
-    if (t < ntiles) {
-      step(t, ca0, ca1, cb0, cb1);
-      ca0 = cb0;
-      ca1 = cb1;
-    }
-    if (live) {
-      float e0[16], e1[16];
-  #pragma unroll
-      for (int i = 0; i < 16; ++i) {
-        e0[i] = ca0[i];
-        e1[i] = ca1[i];
-      }
-      acc0 += (double)kernel_tile_sum<MODE>(e0);
-      acc1 += (double)kernel_tile_sum<MODE>(e1);
-    }
-    const double o0 = __shfl_down(acc0, 32);
-    const double o1 = __shfl_down(acc1, 32);
-    if (live && h == 0) {
-      partial[(int64_t)chunk * m_pad + q0] = acc0 + o0;
-      partial[(int64_t)chunk * m_pad + q1] = acc1 + o1;
-    }
+    acc0 += (double)kernel_tile_sum<MODE>(e0);
+    acc1 += (double)kernel_tile_sum<MODE>(e1);
+  }
+  const double o0 = __shfl_down(acc0, 32);
+  const double o1 = __shfl_down(acc1, 32);
+  if (live && h == 0) {
+    partial[(int64_t)chunk * m_pad + q0] = acc0 + o0;
+    partial[(int64_t)chunk * m_pad + q1] = acc1 + o1;
   }
 }
 
@@ -1318,9 +1303,8 @@ stag_status launch_tile_split(void* const* xp, const float* xaug, void* const* q
     // 64 queries per wave (the same results, fewer LDS reads per product)
     ScopedTimer tm(FORM == STAG_FORM_FP16_SPLIT ? "kde_tile_fp16x3" : "kde_tile_bf16x3", st);
     const int n_qt256 = (int)ceil_div(m_pad, 256);
-    const int64_t ngroups = ceil_div(P, kW64Chunks);
-    hipLaunchKernelGGL((tile_split_w64<FORM, DP, MODE>), dim3((unsigned)((int64_t)n_qt256 * ngroups)), dim3(256), 0,
-                       st, (U)xp[0], (U)xp[1], xaug, (U)qp[0], (U)qp[1], qaug, n_pad, n_qt256, m_pad, P, partial);
+    hipLaunchKernelGGL((tile_split_w64<FORM, DP, MODE>), dim3((unsigned)((int64_t)n_qt256 * P)), dim3(256), 0, st,
+                       (U)xp[0], (U)xp[1], xaug, (U)qp[0], (U)qp[1], qaug, n_pad, n_qt256, m_pad, partial);
     (void)n_qtiles;
     (void)ex;
     return check_launch("tile_split_w64");
