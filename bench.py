@@ -117,6 +117,45 @@ def oracle_reference(X, Q, idx, a):
     return oracle.kde_exact(X, Q[idx], a)
 
 
+def lsh_headline_run(stag, torch, lib, buf, Xd, Qd, a, idx, ref, exact_ms, reps: int = 2):
+    """The CKNS estimator on the headline workload (n = 2e6, m = 2e5, d = 128):
+    index build, query of all queries, candidates and accepted terms per
+    query, and the error against the FP64 oracle on the headline's sampled
+    queries, next to the exact call's query rate."""
+    import numpy as np
+    n, m = Xd.shape[0], Qd.shape[0]
+    sel = torch.from_numpy(idx).to(Qd.device)
+    out = {"workload": f"CKNS KDE over the headline workload (n={n}, m={m}, d={Xd.shape[1]}, a={a}), eps=0.5",
+           "exact_queries_per_s": m / (exact_ms / 1e3), "settings": []}
+    for kw in (dict(k1=1, k2_constant=8, p_offset=1), dict(k1=1, k2_constant=8, p_offset=0)):
+        torch.cuda.synchronize()
+        with Timers(lib, buf, torch) as tb:
+            ix = stag.LshIndex(Xd, a, eps=0.5, seed=3003, **kw)
+        S, st = ix.query(Qd[sel].contiguous(), stats=True)
+        Sa = ix.query(Qd)  # warm-up of the full query
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            ix.query(Qd)
+        torch.cuda.synchronize()
+        q_ms = (time.perf_counter() - t0) * 1e3 / reps
+        with Timers(lib, buf, torch) as tq:
+            ix.query(Qd)
+        shape = dict(ix.shape)
+        ix.close()
+        err = np.abs(S.cpu().numpy() - ref) / ref
+        out["settings"].append({
+            "params": kw, "shape": shape, "build_ms": tb.wall_s * 1e3, "query_ms_all": q_ms,
+            "queries_per_s": m / (q_ms / 1e3), "speedup_vs_exact": exact_ms / q_ms,
+            "candidates_per_query": float(st["n_cand"].double().mean().item()),
+            "accepted_per_query": float(st["n_acc"].double().mean().item()),
+            "avg_rel_err_sampled": float(err.mean()), "max_rel_err_sampled": float(err.max()),
+            "frac_within_eps": float(np.mean(err <= 0.5)), "checked_queries": int(len(idx)),
+            "query_kernels_ms": {k: v[1] for k, v in tq.t.items()}})
+        del Sa
+    return out
+
+
 def forms_run(stag, torch, lib, buf, Xd, Qd, a, idx, ref, forms, n, m, d, reps: int = 2):
     """Exact KDE of the headline workload in other arithmetic forms: tile
     time, evaluations per second of the tile, matrix-core fraction (on the
@@ -896,6 +935,8 @@ def main():
             others = [f for f in ("fp16_centred", "fp16_split", "bf16_split", "bf16_split3", "fp32") if f != args.form]
             result["forms"] = forms_run(stag, torch, lib, buf, Xd, Qd, a, idx, ref, others, n, m, d)
             print("[bench] other forms done", file=sys.stderr, flush=True)
+            result["lsh_headline_workload"] = lsh_headline_run(stag, torch, lib, buf, Xd, Qd, a, idx, ref, ms_per_step)
+            print("[bench] CKNS on the headline workload done", file=sys.stderr, flush=True)
     del Xd, Qd, S
     torch.cuda.empty_cache()
 
