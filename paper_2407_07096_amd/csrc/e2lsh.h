@@ -2,6 +2,8 @@
 // entry point and by the CKNS index).
 #pragma once
 
+#include <type_traits>
+
 #include <hip/hip_runtime.h>
 
 #include "runtime.h"
@@ -112,22 +114,27 @@ __device__ inline int32_t code_sel(double s, double b) {
   return v >= 2147483647.0 ? 2147483647 : (v <= -2147483648.0 ? (int32_t)(-2147483647 - 1) : c);
 }
 
-template <int DG, bool TQ>
+// GF: the lane keeps its coefficients as fp32 (they are fp32 values widened
+// exactly) and widens each one where it is used, so that d up to 128 fits
+// the registers; dg is the regrouped copy's row width (DG, or d when the
+// copy is not padded).
+template <int DG, bool TQ, bool GF = false>
 __global__ __launch_bounds__(256) void hash_lanes(const float* __restrict__ Q, int ldq, int64_t q0, int64_t mb, int d,
-                                                  const double* __restrict__ G8, const double* __restrict__ B, int K,
-                                                  int L, int nch, int64_t ntab, int TW, int qbatches,
+                                                  const double* __restrict__ G8, int dg, const double* __restrict__ B,
+                                                  int K, int L, int nch, int64_t ntab, int TW, int qbatches,
                                                   uint64_t* __restrict__ qkeys, int32_t* __restrict__ codes) {
+  typedef typename std::conditional<GF, float, double>::type GT;
   __shared__ double xs[64 * DG];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int64_t tab0 = ((int64_t)blockIdx.x * 4 + wave) * TW;
   const int ti = lane / K, e = lane - ti * K;
   const int64_t tab = tab0 + ti;
   const bool act = ti < TW && tab < ntab;
-  double g[DG];
+  GT g[DG];
   {
-    const double* gp = G8 + (act ? tab : 0) * nch * DG * 8 + (e >> 3) * DG * 8 + (e & 7);
+    const double* gp = G8 + (act ? tab : 0) * nch * dg * 8 + (e >> 3) * dg * 8 + (e & 7);
 #pragma unroll
-    for (int j = 0; j < DG; ++j) g[j] = gp[j * 8];  // inactive lanes read table 0 and never store
+    for (int j = 0; j < DG; ++j) g[j] = j < dg ? (GT)gp[j * 8] : (GT)0;  // inactive lanes read table 0, never store
   }
   const double bv = act ? B[tab * K + e] : 0.0;
   const int nfold = 4 * TW;
@@ -148,10 +155,13 @@ __global__ __launch_bounds__(256) void hash_lanes(const float* __restrict__ Q, i
       double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
 #pragma unroll
       for (int j = 0; j < DG; ++j) {
-        s0 = __builtin_fma(x0[j], g[j], s0);
-        s1 = __builtin_fma(x0[DG + j], g[j], s1);
-        s2 = __builtin_fma(x0[2 * DG + j], g[j], s2);
-        s3 = __builtin_fma(x0[3 * DG + j], g[j], s3);
+        GT gj = g[j];
+        if constexpr (GF) asm volatile("" : "+v"(gj));  // widen here, not once for the whole loop
+        const double gd = (double)gj;
+        s0 = __builtin_fma(x0[j], gd, s0);
+        s1 = __builtin_fma(x0[DG + j], gd, s1);
+        s2 = __builtin_fma(x0[2 * DG + j], gd, s2);
+        s3 = __builtin_fma(x0[3 * DG + j], gd, s3);
       }
 
       const int32_t c0 = code_sel(s0, bv), c1 = code_sel(s1, bv), c2 = code_sel(s2, bv), c3 = code_sel(s3, bv);

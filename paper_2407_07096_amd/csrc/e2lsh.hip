@@ -101,23 +101,28 @@ stag_status e2lsh_launch(const float* X, int64_t n, int d, const double* G8, int
   const dim3 grid((unsigned)pblocks, (unsigned)ceil_div(L, 4 * tpw));
   const int dreg = e2lsh_reg_dim(d);
   ScopedTimer tm("e2lsh_hash", st);
-  if (dreg > 0 && K <= 64) {
+  if ((dreg > 0 || d <= 128) && K <= 64) {
     // one lane per projection: blocks of 4 waves x TW tables, 8 batches of 64 points each
+    // (64 < d <= 128: the lane's coefficients held as fp32)
     const int TW = 64 / K;
     const int qbatches = (int)std::max<int64_t>(8, ceil_div(n, (int64_t)64 * 65535));  // grid.y <= 65535
     const dim3 lgrid((unsigned)ceil_div(L, 4 * TW), (unsigned)ceil_div(n, (int64_t)64 * qbatches));
     switch (dreg) {
       case 16:
-        hipLaunchKernelGGL((hash_lanes<16, false>), lgrid, dim3(256), 0, st, X, d, (int64_t)0, n, d, G8, b, K, L, nch,
-                           (int64_t)L, TW, qbatches, keys, codes);
+        hipLaunchKernelGGL((hash_lanes<16, false>), lgrid, dim3(256), 0, st, X, d, (int64_t)0, n, d, G8, dg, b, K, L,
+                           nch, (int64_t)L, TW, qbatches, keys, codes);
         break;
       case 32:
-        hipLaunchKernelGGL((hash_lanes<32, false>), lgrid, dim3(256), 0, st, X, d, (int64_t)0, n, d, G8, b, K, L, nch,
-                           (int64_t)L, TW, qbatches, keys, codes);
+        hipLaunchKernelGGL((hash_lanes<32, false>), lgrid, dim3(256), 0, st, X, d, (int64_t)0, n, d, G8, dg, b, K, L,
+                           nch, (int64_t)L, TW, qbatches, keys, codes);
+        break;
+      case 64:
+        hipLaunchKernelGGL((hash_lanes<64, false>), lgrid, dim3(256), 0, st, X, d, (int64_t)0, n, d, G8, dg, b, K, L,
+                           nch, (int64_t)L, TW, qbatches, keys, codes);
         break;
       default:
-        hipLaunchKernelGGL((hash_lanes<64, false>), lgrid, dim3(256), 0, st, X, d, (int64_t)0, n, d, G8, b, K, L, nch,
-                           (int64_t)L, TW, qbatches, keys, codes);
+        hipLaunchKernelGGL((hash_lanes<128, false, true>), lgrid, dim3(256), 0, st, X, d, (int64_t)0, n, d, G8, dg, b,
+                           K, L, nch, (int64_t)L, TW, qbatches, keys, codes);
         break;
     }
     return check_launch("hash_lanes");

@@ -1505,16 +1505,24 @@ stag_status hash_query_batch(const stag_lsh_index* idx, const float* Q, int ldq,
   const int64_t qb = ceil_div(cur, 256);
   const int64_t tpw = std::max<int64_t>(1, std::min<int64_t>(idx->ntab, idx->ntab * qb / 2048));
   const int K = prm.shape.K;
-  if (idx->dreg > 0 && K <= 64) {
+  if ((idx->dreg > 0 || idx->d <= 128) && K <= 64) {
     // one lane per projection: blocks of 4 waves x TW tables, 8 batches of 64 queries each
+    // (64 < d <= 128: the lane's coefficients held as fp32)
     const int TW = 64 / K;
     const int qbatches = (int)std::max<int64_t>(8, ceil_div(cur, (int64_t)64 * 65535));  // grid.y <= 65535
     const dim3 grid((unsigned)ceil_div(idx->ntab, 4 * TW), (unsigned)ceil_div(cur, (int64_t)64 * qbatches));
+    if (idx->dreg == 0) {
+      hipLaunchKernelGGL((hash_lanes<128, true, true>), grid, dim3(256), 0, st, Q, ldq, q0, cur, idx->d, idx->G8,
+                         idx->dg, idx->B, K, prm.shape.L, idx->nch, idx->ntab, TW, qbatches, qkeys,
+                         (int32_t*)nullptr);
+      return check_launch("hash_lanes");
+    }
     return dispatch_dreg(idx->dreg, [&](auto D) {
       constexpr int DR = decltype(D)::value;
       if constexpr (DR > 0) {
         hipLaunchKernelGGL((hash_lanes<DR, true>), grid, dim3(256), 0, st, Q, ldq, q0, cur, idx->d, idx->G8,
-                           idx->B, K, prm.shape.L, idx->nch, idx->ntab, TW, qbatches, qkeys, (int32_t*)nullptr);
+                           idx->dg, idx->B, K, prm.shape.L, idx->nch, idx->ntab, TW, qbatches, qkeys,
+                           (int32_t*)nullptr);
         return check_launch("hash_lanes");
       } else {
         return fail(STAG_E_UNSUPPORTED, "query hashing: no register width");

@@ -128,6 +128,18 @@ def test_degenerate_case_is_truncated_exact(stag, orc):
     idx.close()
 
 
+@pytest.mark.parametrize("d", [96, 128])
+def test_wide_rows_bit_exact(stag, orc, d):
+    """64 < d <= 128: query hashing with fp32-held coefficients (lane per
+    projection) and the bucket join; structure bit-exact, values to 1e-9."""
+    rng = np.random.default_rng(d)
+    means = rng.uniform(-3, 3, size=(6, d))
+    X = (means[rng.integers(0, 6, size=4000)] + rng.normal(size=(4000, d))).astype(np.float32)
+    Q = (X[rng.integers(0, 4000, size=150)] + 0.3 * rng.normal(size=(150, d))).astype(np.float32)
+    announce(f"lsh wide rows n=4000 d={d}")
+    _compare(stag, orc, X, Q, 0.3 / d, seed=41 + d, k1=2, k2_constant=6, p_offset=1)
+
+
 def test_unbiased_on_gpu(stag, orc):
     """Mean of 2000 independent GPU copies = truncated exact sum (4 SE)."""
     import torch
