@@ -499,8 +499,9 @@ stag_status stag_spectral_cluster(int64_t n, const int64_t* src, const int64_t* 
  * Serving loop: continuous batching of kernel-density requests against
  * resident data sets.
  *   - A data set (X, a) is prepared once and stays in device memory in each
- *     of its resident exact forms (a bit mask of 1 << STAG_FORM_*; the fp32
- *     form with its data tiles centred as in stag_kde_exact) and, on
+ *     of its resident exact forms (a bit mask of 1 << STAG_FORM_* over FP32,
+ *     BF16_SPLIT, FP16_SPLIT and BF16_SPLIT3; other bits are STAG_E_INVAL;
+ *     the fp32 form with its data tiles centred as in stag_kde_exact) and, on
  *     request, with a CKNS index (stag_lsh_index_create with lsh_eps and the
  *     given parameters) for LSH requests.
  *   - A request is exact (in a resident form, or STAG_FORM_AUTO: the form
