@@ -56,8 +56,10 @@ typedef enum {
   STAG_FORM_FP16_SPLIT = 2,  /* x = hi + lo in fp16, three fp16 products */
   STAG_FORM_BF16_SPLIT3 = 3, /* x = hi + mid + lo in bf16, six bf16 products */
   STAG_FORM_AUTO = 4,        /* exact KDE only: the cheapest form whose a-priori bound is <= eps */
-  STAG_FORM_FP16_CENTRED = 5 /* exact Gaussian KDE only: data grouped around centres c, one fp16
-                                product (q - c).(x - c) per pair; see stag_kde_exact */
+  STAG_FORM_FP16_CENTRED = 5, /* exact Gaussian KDE only: data grouped around centres c, one fp16
+                                 product (q - c).(x - c) per pair; see stag_kde_exact */
+  STAG_FORM_FP16_ADAPTIVE = 6 /* exact Gaussian KDE only: FP16_CENTRED everywhere, FP16_SPLIT where
+                                 its bound would matter; see stag_kde_exact */
 } stag_form;
 
 /* Kernel functions of Sec. "Kernel Density Estimation" (r = ||q - x||). */
@@ -145,6 +147,17 @@ double stag_e2lsh_collision_probability(double c, int32_t K, int32_t L);
  * many terms.  STAG_FORM_AUTO never takes this form.  A data row with some
  * |x_j - c_j| >= 65520, or a query with some |2a log2(e) (q_j - c_j)| >=
  * 65520, gives NaN results (all of them, or that query's).
+ * FP16_ADAPTIVE (Gaussian kernel, d <= 256): the queries are ordered by
+ * their nearest seed of the same grouping, the FP16_CENTRED tiles run over
+ * all pairs, and every (4096-row chunk, 256-query tile) pair in which some
+ * query's FP16_CENTRED bound numerator for that chunk exceeds 2e-6 / P of
+ * its sum (P chunks) is computed again in the FP16_SPLIT form.  Where the
+ * data are clustered and the kernel narrow against the clusters' spacing,
+ * few pairs are recomputed and the result has the split form's accuracy at
+ * near the single product's cost; otherwise it costs up to both forms
+ * together.  bound_out adds the kept chunks' FP16_CENTRED numerators and the
+ * recomputed chunks' FP16_SPLIT bounds.  Sums below 2^-60 are recomputed in
+ * the split form (underflow rescue).  Range rules of both forms apply.
  * Results are deterministic and do not depend on m or on the other rows of Q
  * (each row's reduction order depends only on n). */
 stag_status stag_kde_exact(const float* X, int64_t n, const float* Q, int64_t m, int32_t d, double a,
@@ -155,7 +168,7 @@ stag_status stag_kde_exact(const float* X, int64_t n, const float* Q, int64_t m,
  * (code under HIP graph capture, tight serving loops, harnesses that forbid
  * hipMalloc).  Same arguments and results as stag_kde_exact with the
  * Gaussian kernel (bit for bit), except:
- *   - form is FP32, BF16_SPLIT, FP16_SPLIT, BF16_SPLIT3 or FP16_CENTRED (STAG_FORM_AUTO:
+ *   - form is FP32, BF16_SPLIT, FP16_SPLIT, BF16_SPLIT3, FP16_CENTRED or FP16_ADAPTIVE (STAG_FORM_AUTO:
  *     STAG_E_UNSUPPORTED) and flags may hold STAG_NORMALIZE only
  *     (STAG_CHECK_FINITE: STAG_E_UNSUPPORTED); eps is not taken;
  *   - every temporary (prepared operands, partial sums, rescue buffers) lives

@@ -16,7 +16,8 @@ LIB_PATH = os.path.join(HERE, "libstagkde.so")
 HEADER = os.path.join(HERE, "..", "include", "stag_kde.h")
 
 STAG_OK, STAG_E_INVAL, STAG_E_NOMEM, STAG_E_DEVICE, STAG_E_UNSUPPORTED, STAG_E_BUSY = range(6)
-FORMS = {"fp32": 0, "bf16_split": 1, "fp16_split": 2, "bf16_split3": 3, "auto": 4, "fp16_centred": 5}
+FORMS = {"fp32": 0, "bf16_split": 1, "fp16_split": 2, "bf16_split3": 3, "auto": 4, "fp16_centred": 5,
+         "fp16_adaptive": 6}
 KERNELS = {"gaussian": 0, "exponential": 1, "logistic": 2}
 NORMALIZE = 1
 CHECK_FINITE = 2

@@ -192,14 +192,15 @@ __global__ __launch_bounds__(256) void scan_labels(uint32_t* __restrict__ hist, 
   }
 }
 
-// goff[k] = sum_{k' < k} ceil32(count[k']); n_pad = goff[K].  One thread.
-__global__ void group_offsets(const uint32_t* __restrict__ count, int K, uint32_t* __restrict__ goff,
-                              int64_t* __restrict__ n_pad) {
+// goff[k] = sum_{k' < k} count[k'] rounded up to a multiple of align_mask + 1
+// (32 for data: whole tiles; 1 for queries); n_pad = goff[K].  One thread.
+__global__ void group_offsets(const uint32_t* __restrict__ count, int K, uint32_t align_mask,
+                              uint32_t* __restrict__ goff, int64_t* __restrict__ n_pad) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   uint32_t run = 0;
   for (int k = 0; k < K; ++k) {
     goff[k] = run;
-    run += (count[k] + 31u) & ~31u;
+    run += (count[k] + align_mask) & ~align_mask;
   }
   goff[K] = run;
   *n_pad = (int64_t)run;
@@ -518,7 +519,7 @@ static stag_status group_rows(const float* X, const Operands& o, const CentreTem
   STAG_TRY(check_launch("label_hist"));
   hipLaunchKernelGGL(scan_labels, dim3((unsigned)t.K), dim3(256), 0, st, t.hist, t.nblk, t.count);
   STAG_TRY(check_launch("scan_labels"));
-  hipLaunchKernelGGL(group_offsets, dim3(1), dim3(64), 0, st, t.count, t.K, t.goff, o.n_pad_dev);
+  hipLaunchKernelGGL(group_offsets, dim3(1), dim3(64), 0, st, t.count, t.K, 31u, t.goff, o.n_pad_dev);
   STAG_TRY(check_launch("group_offsets"));
   hipLaunchKernelGGL(fill_minus_one, dim3((unsigned)ceil_div(o.rows_pad, 256)), dim3(256), 0, st, t.map, o.rows_pad);
   STAG_TRY(check_launch("fill_minus_one"));
@@ -592,6 +593,47 @@ stag_status prep_centred_h_operands(const float* X, double a_tile, const Operand
     case 256: return launch_build_h<256>(X, d, o, t, nl, st);
   }
   return fail(STAG_E_UNSUPPORTED, "centred operands: padded dimension %d", o.dp);
+}
+
+stag_status alloc_query_sort(int64_t m, int64_t m_pad, int K, Workspace& ws, QuerySort* qs) {
+  qs->nblk = ceil_div(m, kHistBlock);
+  STAG_TRY(ws.alloc(&qs->label, (size_t)m));
+  STAG_TRY(ws.alloc(&qs->hist, (size_t)K * qs->nblk));
+  STAG_TRY(ws.alloc(&qs->count, (size_t)K));
+  STAG_TRY(ws.alloc(&qs->goff, (size_t)K + 1));
+  STAG_TRY(ws.alloc(&qs->total, 1));
+  STAG_TRY(ws.alloc(&qs->perm, (size_t)m_pad));
+  return STAG_OK;
+}
+
+stag_status sort_queries(const float* Q, int64_t m, int64_t m_pad, int d, int dp, const CentreTemp& t,
+                         const QuerySort& qs, hipStream_t st) {
+  ScopedTimer tm("kde_query_sort", st);
+  CentreTemp tq = t;  // the data's seeds, the queries' labels
+  tq.label = qs.label;
+  switch (dp) {
+    case 16: STAG_TRY(launch_assign<16>(Q, m, d, tq, st)); break;
+    case 32: STAG_TRY(launch_assign<32>(Q, m, d, tq, st)); break;
+    case 64: STAG_TRY(launch_assign<64>(Q, m, d, tq, st)); break;
+    case 96: STAG_TRY(launch_assign<96>(Q, m, d, tq, st)); break;
+    case 128: STAG_TRY(launch_assign<128>(Q, m, d, tq, st)); break;
+    case 160: STAG_TRY(launch_assign<160>(Q, m, d, tq, st)); break;
+    case 192: STAG_TRY(launch_assign<192>(Q, m, d, tq, st)); break;
+    case 224: STAG_TRY(launch_assign<224>(Q, m, d, tq, st)); break;
+    case 256: STAG_TRY(launch_assign<256>(Q, m, d, tq, st)); break;
+    default: return fail(STAG_E_UNSUPPORTED, "query sort: padded dimension %d", dp);
+  }
+  hipLaunchKernelGGL(label_hist, dim3((unsigned)qs.nblk), dim3(256), 0, st, qs.label, m, t.K, qs.nblk, qs.hist);
+  STAG_TRY(check_launch("label_hist"));
+  hipLaunchKernelGGL(scan_labels, dim3((unsigned)t.K), dim3(256), 0, st, qs.hist, qs.nblk, qs.count);
+  STAG_TRY(check_launch("scan_labels"));
+  hipLaunchKernelGGL(group_offsets, dim3(1), dim3(64), 0, st, qs.count, t.K, 0u, qs.goff, qs.total);
+  STAG_TRY(check_launch("group_offsets"));
+  hipLaunchKernelGGL(fill_minus_one, dim3((unsigned)ceil_div(m_pad, 256)), dim3(256), 0, st, qs.perm, m_pad);
+  STAG_TRY(check_launch("fill_minus_one"));
+  hipLaunchKernelGGL(scatter_labels, dim3((unsigned)qs.nblk), dim3(256), 0, st, qs.label, m, qs.nblk, qs.hist,
+                     qs.goff, qs.perm);
+  return check_launch("scatter_labels");
 }
 
 }  // namespace stag

@@ -58,6 +58,19 @@ stag_status alloc_centred_operands(int64_t n, int d, Workspace& ws, Operands* ou
 stag_status alloc_centre_temp(const Operands& o, Workspace& ws, CentreTemp* t);
 stag_status prep_centred_operands(const float* X, double a_tile, const Operands& o, const CentreTemp& t,
                                   hipStream_t st);
+// Queries ordered by their nearest seed of the data's grouping (the data's
+// seeds), so that a 256-query tile holds queries of few groups: perm
+// [m_pad] maps a sorted position to its query row (-1: padding).
+struct QuerySort {
+  int64_t nblk = 0;
+  uint8_t* label = nullptr;
+  uint32_t *hist = nullptr, *count = nullptr, *goff = nullptr;
+  int64_t* total = nullptr;
+  int* perm = nullptr;
+};
+stag_status alloc_query_sort(int64_t m, int64_t m_pad, int K, Workspace& ws, QuerySort* qs);
+stag_status sort_queries(const float* Q, int64_t m, int64_t m_pad, int d, int dp, const CentreTemp& t,
+                         const QuerySort& qs, hipStream_t st);
 // The same for the centred fp16 form (group centres; o.form ==
 // STAG_FORM_FP16_CENTRED, temporaries from alloc_centre_temp).
 stag_status alloc_centred_h_operands(int64_t n, int d, Workspace& ws, Operands* out);
@@ -147,6 +160,10 @@ struct TileExtra {
   // tile's kernel sum times (2^{c_cent M_T} - 1), the bound's numerator
   double* bpart = nullptr;
   float c_cent = 0.0f;
+  // split tiles: with cflag, only the (chunk, 256-query tile) pairs with
+  // cflag[chunk * ceil(m_pad / 256) + tile] != 0 run (the others return at
+  // once, their partials not written)
+  const uint8_t* cflag = nullptr;
 };
 
 int exact_padded_dim(int d);  // 0 if unsupported

@@ -73,6 +73,7 @@ __device__ inline void split_value(float v, unsigned short* p) {
 // in fp32; aug = bf16 three-way parts of off laid out for the augmentation
 // step (data: [o1,o2,o3,1,1,1,0,0], queries: [1,1,1,o1,o2,o3,0,0]).  Rows >= n
 // are padding.  The block's largest norm goes to max_nrm_bits with one atomic.
+// With map, row r is src row map[r] (-1: padding), n unused.
 constexpr int kPrepRowsPerWave = 16;
 constexpr int kPrepRowsPerBlock = 4 * kPrepRowsPerWave;
 
@@ -82,18 +83,20 @@ __global__ __launch_bounds__(256) void prep_rows(const float* __restrict__ src, 
                                                  int is_query, void* __restrict__ part0, void* __restrict__ part1,
                                                  void* __restrict__ part2, float* __restrict__ off,
                                                  u16x8* __restrict__ aug, double* __restrict__ nrm,
-                                                 unsigned long long* __restrict__ max_nrm_bits) {
+                                                 unsigned long long* __restrict__ max_nrm_bits,
+                                                 const int* __restrict__ map) {
   __shared__ double wmax[4];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   double mx = 0.0;
   for (int rr = 0; rr < kPrepRowsPerWave; ++rr) {
     const int64_t row = (int64_t)blockIdx.x * kPrepRowsPerBlock + wave * kPrepRowsPerWave + rr;
     if (row >= rows_pad) break;
-    const bool real = row < n;
+    const int64_t srow = map ? (int64_t)map[row] : row;
+    const bool real = map ? srow >= 0 : row < n;
     double sq = 0.0;
     for (int j = lane; j < dp; j += 64) {
       float v = 0.0f;
-      if (real && j < d) v = src[row * d + j];
+      if (real && j < d) v = src[srow * d + j];
       sq += (double)v * (double)v;
       const float w = (float)((double)v * scale);
       const int64_t o = row * dp + j;
@@ -184,33 +187,97 @@ __global__ void reduce_centred(const double* __restrict__ partial, const double*
   }
 }
 
+// Adaptive form: the first pass's sum per (sorted) query, all m_pad rows.
+__global__ void sum_partials(const double* __restrict__ partial, int P, int64_t m_pad, double* __restrict__ out) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= m_pad) return;
+  double s = 0.0;
+  for (int p = 0; p < P; ++p) s += partial[(int64_t)p * m_pad + q];
+  out[q] = s;
+}
+
+// Adaptive form: a (chunk, 256-query tile) pair is recomputed in the split
+// form when some query's bound numerator of that chunk from the single-
+// product pass exceeds thr times its first-pass sum (cflag starts at zero;
+// every writer stores 1).  Grid: (query blocks, chunks).
+__global__ void adaptive_flags(const double* __restrict__ bpart, const double* __restrict__ S1, int64_t m_pad,
+                               int64_t m, int n_qt256, double thr, uint8_t* __restrict__ cflag) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t c = blockIdx.y;
+  if (q >= m) return;
+  if (bpart[c * m_pad + q] > thr * S1[q]) cflag[c * n_qt256 + q / 256] = 1;
+}
+
+// Adaptive form: S(q) = sum of the chunk partials in chunk order (first
+// pass, or the split form where the chunk was recomputed); the bound's
+// numerator adds the first pass's bound numerator of a kept chunk and
+// partial x the split form's a-priori relative bound of a recomputed one;
+// bound = r + r^2 + c_tail with r = numerator / S.  Results in sorted order;
+// rescue flags as in reduce_partials.
+__global__ void reduce_adaptive(const double* __restrict__ partial, const double* __restrict__ bpart,
+                                const uint8_t* __restrict__ cflag, int P, int64_t m_pad, int64_t m, int n_qt256,
+                                double scale, const double* __restrict__ qnrm,
+                                const unsigned long long* __restrict__ max_xnrm_bits, BoundModel bm, double c_tail,
+                                double* __restrict__ S_s, double* __restrict__ B_s, int* __restrict__ flag,
+                                int* __restrict__ qtile_flag) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= m) return;
+  const double xm = __longlong_as_double((long long)*max_xnrm_bits);
+  const double rs = relative_bound(bm, qnrm[q], xm);
+  double s = 0.0, b = 0.0;
+  for (int p = 0; p < P; ++p) {
+    const double v = partial[(int64_t)p * m_pad + q];
+    s += v;
+    b += cflag[(int64_t)p * n_qt256 + q / 256] ? v * rs : bpart[(int64_t)p * m_pad + q];
+  }
+  if (s < kRescueBelow) {
+    flag[q] = 1;
+    qtile_flag[q / kBQ] = 1;
+  }
+  S_s[q] = s * scale;
+  const double r = b / s;
+  B_s[q] = s > 0.0 ? r + r * r + c_tail : HUGE_VAL;
+}
+
+// Sorted results back to the queries' rows.
+__global__ void scatter_results(const double* __restrict__ S_s, const double* __restrict__ B_s,
+                                const int* __restrict__ perm, int64_t m_pad, double* __restrict__ S_out,
+                                double* __restrict__ bound_out) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= m_pad) return;
+  const int i = perm[q];
+  if (i < 0) return;
+  S_out[i] = S_s[q];
+  if (bound_out) bound_out[i] = B_s[q];
+}
+
 template <int FORM>
 stag_status launch_prep(const float* src, int64_t n, int d, int dp, int64_t rows_pad, double scale, double neg_a_l2e,
                         int is_query, void* const* parts, float* off, u16x8* aug, double* nrm,
-                        unsigned long long* maxbits, hipStream_t st) {
+                        unsigned long long* maxbits, hipStream_t st, const int* map) {
   ScopedTimer tm("kde_prep", st);
   hipLaunchKernelGGL(prep_rows<FORM>, dim3((unsigned)ceil_div(rows_pad, kPrepRowsPerBlock)), dim3(256), 0, st, src,
-                     n, d, dp,
-                     rows_pad, scale, neg_a_l2e, is_query, parts[0], parts[1], parts[2], off, aug, nrm, maxbits);
+                     n, d, dp, rows_pad, scale, neg_a_l2e, is_query, parts[0], parts[1], parts[2], off, aug, nrm,
+                     maxbits, map);
   return check_launch("prep_rows");
 }
 
 stag_status prep_any(int form, const float* src, int64_t n, int d, int dp, int64_t rows_pad, double scale,
                      double neg_a_l2e, int is_query, void* const* parts, float* off, u16x8* aug, double* nrm,
-                     unsigned long long* maxbits, hipStream_t st) {
+                     unsigned long long* maxbits, hipStream_t st, const int* map = nullptr) {
   switch (form) {
     case STAG_FORM_FP32:
       return launch_prep<STAG_FORM_FP32>(src, n, d, dp, rows_pad, scale, neg_a_l2e, is_query, parts, off, aug, nrm,
-                                         maxbits, st);
+                                         maxbits, st, map);
     case STAG_FORM_BF16_SPLIT:
       return launch_prep<STAG_FORM_BF16_SPLIT>(src, n, d, dp, rows_pad, scale, neg_a_l2e, is_query, parts, off, aug,
-                                               nrm, maxbits, st);
+                                               nrm, maxbits, st, map);
     case STAG_FORM_FP16_SPLIT:
       return launch_prep<STAG_FORM_FP16_SPLIT>(src, n, d, dp, rows_pad, scale, neg_a_l2e, is_query, parts, off, aug,
-                                               nrm, maxbits, st);
+                                               nrm, maxbits, st, map);
     default:
       return launch_prep<STAG_FORM_BF16_SPLIT3>(src, n, d, dp, rows_pad, scale, neg_a_l2e, is_query, parts, off, aug,
-                                                nrm, maxbits, st);
+                                                nrm, maxbits, st, map);
   }
 }
 
@@ -668,10 +735,10 @@ stag_status check_exact_args(const char* fn, const float* X, int64_t n, const fl
   if (!(a > 0.0) || !std::isfinite(a)) return fail(STAG_E_INVAL, "%s: a must be positive and finite", fn);
   if (kernel < STAG_KERNEL_GAUSSIAN || kernel > STAG_KERNEL_LOGISTIC)
     return fail(STAG_E_INVAL, "%s: unknown kernel %d", fn, kernel);
-  if (form < STAG_FORM_FP32 || form > STAG_FORM_FP16_CENTRED)
+  if (form < STAG_FORM_FP32 || form > STAG_FORM_FP16_ADAPTIVE)
     return fail(STAG_E_INVAL, "%s: unknown form %d", fn, form);
-  if (form == STAG_FORM_FP16_CENTRED && kernel != STAG_KERNEL_GAUSSIAN)
-    return fail(STAG_E_UNSUPPORTED, "%s: the fp16 centred form computes Gaussian sums only", fn);
+  if ((form == STAG_FORM_FP16_CENTRED || form == STAG_FORM_FP16_ADAPTIVE) && kernel != STAG_KERNEL_GAUSSIAN)
+    return fail(STAG_E_UNSUPPORTED, "%s: the fp16 centred forms compute Gaussian sums only", fn);
   if (form == STAG_FORM_AUTO && !(eps > 0.0))
     return fail(STAG_E_INVAL, "%s: STAG_FORM_AUTO needs a target eps > 0", fn);
   if (flags & ~(STAG_NORMALIZE | STAG_CHECK_FINITE)) return fail(STAG_E_INVAL, "%s: unknown flags 0x%x", fn, flags);
@@ -697,6 +764,14 @@ struct ExactBuffers {
   bool centred = false;
   CentreTemp ct;
   double *bpart = nullptr, *bp2 = nullptr;
+  // adaptive form: the split operands (data in the grouped order, queries
+  // sorted), the query order, the first pass's sums, the chunk selection
+  // and the sorted results
+  bool adaptive = false;
+  Operands xs, qsp;
+  QuerySort qs;
+  double *S1 = nullptr, *Ss = nullptr, *Bs = nullptr;
+  uint8_t* cflag = nullptr;
 };
 
 // The fp32 form of the Gaussian sum centres the data tile by tile (the wide
@@ -707,6 +782,25 @@ bool use_centred(int form, int kernel, int d) {
 }
 
 stag_status alloc_exact(int form, int kernel, int64_t n, int64_t m, int d, Workspace& ws, ExactBuffers* b) {
+  if (form == STAG_FORM_FP16_ADAPTIVE) {
+    b->centred = true;
+    b->adaptive = true;
+    STAG_TRY(alloc_centred_h_operands(n, d, ws, &b->xo));
+    STAG_TRY(alloc_centre_temp(b->xo, ws, &b->ct));
+    STAG_TRY(alloc_operands(STAG_FORM_FP32, m, d, true, ws, &b->qo));
+    STAG_TRY(alloc_operands(STAG_FORM_FP16_SPLIT, b->xo.rows_pad, d, false, ws, &b->xs));
+    STAG_TRY(alloc_operands(STAG_FORM_FP16_SPLIT, m, d, true, ws, &b->qsp));
+    STAG_TRY(alloc_query_sort(m, b->qo.rows_pad, b->ct.K, ws, &b->qs));
+    b->P = (int)exact_chunks(b->xo.rows_pad);
+    const int64_t m_pad = b->qo.rows_pad;
+    STAG_TRY(ws.alloc(&b->partial, (size_t)b->P * m_pad));
+    STAG_TRY(ws.alloc(&b->bpart, (size_t)b->P * m_pad));
+    STAG_TRY(ws.alloc(&b->S1, (size_t)m_pad));
+    STAG_TRY(ws.alloc(&b->Ss, (size_t)m_pad));
+    STAG_TRY(ws.alloc(&b->Bs, (size_t)m_pad));
+    STAG_TRY(ws.alloc(&b->cflag, (size_t)b->P * ceil_div(m_pad, 256)));
+    return alloc_rescue(kernel, b->P, b->qsp, ws, &b->rb);
+  }
   if (use_centred(form, kernel, d)) {
     b->centred = true;
     if (form == STAG_FORM_FP16_CENTRED)
@@ -779,10 +873,73 @@ stag_status run_centred(const float* X, int64_t n, const float* Q, int64_t m, in
   return check_launch("rescue_reduce_centred");
 }
 
+// Adaptive fp16 form: the single-product centred pass over all pairs with
+// the queries in group order, then the fp16 split form over the (chunk,
+// 256-query tile) pairs where some query's first-pass bound share exceeds
+// kAdaptiveShare / P of its sum, the reduction in sorted order with the
+// underflow rescue in the split form, and the results back to the query rows.
+constexpr double kAdaptiveShare = 2.0e-6;
+
+stag_status run_adaptive(const float* X, int64_t n, const float* Q, int64_t m, int32_t d, double a, uint32_t flags,
+                         double* S_out, double* bound_out, const ExactBuffers& b, hipStream_t st) {
+  const Operands& xo = b.xo;
+  const Operands& qo = b.qo;
+  const int64_t m_pad = qo.rows_pad;
+  const int n_qt256 = (int)ceil_div(m_pad, 256);
+  STAG_TRY(prep_centred_h_operands(X, a, xo, b.ct, st));
+  STAG_TRY(sort_queries(Q, m, m_pad, d, xo.dp, b.ct, b.qs, st));
+  STAG_TRY(prep_any(STAG_FORM_FP32, Q, m, d, qo.dp, m_pad, 1.0, 0.0, 1, qo.part, qo.off, nullptr, qo.nrm, nullptr,
+                    st, b.qs.perm));
+  STAG_TRY(zero_async(b.xs.max_nrm_bits, sizeof(unsigned long long), st));
+  STAG_TRY(prep_any(STAG_FORM_FP16_SPLIT, X, b.xs.rows, d, b.xs.dp, b.xs.rows_pad, 1.0, -a * kLog2e, 0, b.xs.part,
+                    b.xs.off, nullptr, b.xs.nrm, b.xs.max_nrm_bits, st, b.ct.map));
+  STAG_TRY(prep_any(STAG_FORM_FP16_SPLIT, Q, m, d, b.qsp.dp, b.qsp.rows_pad, 2.0 * a * kLog2e, -a * kLog2e, 1,
+                    b.qsp.part, b.qsp.off, nullptr, b.qsp.nrm, nullptr, st, b.qs.perm));
+  // first pass: one fp16 product per pair, with the bound numerators
+  const BoundModel bm1 = make_bound_model(STAG_FORM_FP32, d, a, STAG_KERNEL_GAUSSIAN);
+  TileExtra ex1;
+  ex1.a = a;
+  ex1.bpart = b.bpart;
+  ex1.c_cent = (float)bm1.c_cent;
+  STAG_TRY(launch_exact_tiles(xo, qo, b.partial, ex1, st));
+  // selection of the pairs to recompute
+  {
+    ScopedTimer tm("kde_adaptive_select", st);
+    hipLaunchKernelGGL(sum_partials, dim3((unsigned)ceil_div(m_pad, 256)), dim3(256), 0, st, b.partial, b.P, m_pad,
+                       b.S1);
+    STAG_TRY(check_launch("sum_partials"));
+    STAG_TRY(zero_async(b.cflag, (size_t)b.P * n_qt256, st));
+    hipLaunchKernelGGL(adaptive_flags, dim3((unsigned)ceil_div(m, 256), (unsigned)b.P), dim3(256), 0, st, b.bpart,
+                       b.S1, m_pad, m, n_qt256, kAdaptiveShare / b.P, b.cflag);
+    STAG_TRY(check_launch("adaptive_flags"));
+  }
+  // second pass: the split form on the selected pairs (overwrites their partials)
+  TileExtra ex2;
+  ex2.cflag = b.cflag;
+  STAG_TRY(launch_exact_tiles(b.xs, b.qsp, b.partial, ex2, st));
+  const BoundModel bm2 = make_bound_model(STAG_FORM_FP16_SPLIT, d, a, STAG_KERNEL_GAUSSIAN);
+  const double scale = (flags & STAG_NORMALIZE) ? 1.0 / (double)n : 1.0;
+  STAG_TRY(zero_async(b.rb.flag, (size_t)m * sizeof(int), st));
+  STAG_TRY(zero_async(b.rb.qflag, (size_t)(m_pad / kBQ) * sizeof(int), st));
+  {
+    ScopedTimer tm("kde_reduce", st);
+    hipLaunchKernelGGL(reduce_adaptive, dim3((unsigned)ceil_div(m, 256)), dim3(256), 0, st, b.partial, b.bpart,
+                       b.cflag, b.P, m_pad, m, n_qt256, scale, b.qsp.nrm, b.xs.max_nrm_bits, bm2, bm1.c_tail, b.Ss,
+                       b.Bs, b.rb.flag, b.rb.qflag);
+    STAG_TRY(check_launch("reduce_adaptive"));
+  }
+  // queries whose sum lies below the fp32 terms' range: recomputed in the split form
+  STAG_TRY(rescue_underflow(b.xs, b.qsp, b.P, a, scale, bm2, b.rb, b.Ss, b.Bs, st));
+  hipLaunchKernelGGL(scatter_results, dim3((unsigned)ceil_div(m_pad, 256)), dim3(256), 0, st, b.Ss, b.Bs, b.qs.perm,
+                     m_pad, S_out, bound_out);
+  return check_launch("scatter_results");
+}
+
 // The launches of one exact call into buffers from alloc_exact.
 stag_status run_exact(const float* X, int64_t n, const float* Q, int64_t m, int32_t d, int32_t kernel, double a,
                       int32_t form, uint32_t flags, double* S_out, double* bound_out, const ExactBuffers& b,
                       hipStream_t stream) {
+  if (b.adaptive) return run_adaptive(X, n, Q, m, d, a, flags, S_out, bound_out, b, stream);
   if (b.centred) return run_centred(X, n, Q, m, d, a, flags, S_out, bound_out, b, stream);
   const double at = kernel_tile_a(kernel, a);
   STAG_TRY(prep_operands(X, at, false, b.xo, stream));

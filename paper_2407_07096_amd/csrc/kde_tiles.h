@@ -635,6 +635,7 @@ __global__ __launch_bounds__(256, 2) void tile_split(
   const int64_t col_base = (int64_t)qtile * kBQ + wave * 32;
   const int64_t qi = col_base + r32;
   if (ex.qtile_active && ex.qtile_active[qtile] == 0) return;  // whole block: no query of its tile is active
+  if (ex.cflag && ex.cflag[(int64_t)chunk * ((m_pad + 255) / 256) + qtile / 2] == 0) return;  // not selected
 
   const unsigned short* Qp[3] = {Q0, Q1, Q2};
   const unsigned short* Xpp[3] = {X0, X1, X2};
@@ -761,7 +762,7 @@ template <int FORM, int DP, int MODE>
 __global__ __launch_bounds__(256, 2) void tile_split_w64(
     const unsigned short* __restrict__ X0, const unsigned short* __restrict__ X1, const float* __restrict__ Xoff,
     const unsigned short* __restrict__ Q0, const unsigned short* __restrict__ Q1, const float* __restrict__ Qoff,
-    int64_t n_pad, int n_qt256, int64_t m_pad, double* __restrict__ partial) {
+    int64_t n_pad, int n_qt256, int64_t m_pad, double* __restrict__ partial, TileExtra ex) {
   static_assert(MODE == kModeGauss, "Gaussian sums only");
   constexpr int NP = 2;
   constexpr int KS = DP / 16;
@@ -776,6 +777,7 @@ __global__ __launch_bounds__(256, 2) void tile_split_w64(
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, r32 = lane & 31, h = lane >> 5;
   const int qtile = blockIdx.x % n_qt256;
   const int chunk = blockIdx.x / n_qt256;
+  if (ex.cflag && ex.cflag[(int64_t)chunk * n_qt256 + qtile] == 0) return;  // whole block: not selected
   const int64_t col0 = (int64_t)qtile * 256 + wave * 64;
   const bool live = col0 < m_pad;  // wave-uniform
   const int64_t q0 = col0 + r32, q1 = q0 + 32;
@@ -1304,9 +1306,8 @@ stag_status launch_tile_split(void* const* xp, const float* xaug, void* const* q
     ScopedTimer tm(FORM == STAG_FORM_FP16_SPLIT ? "kde_tile_fp16x3" : "kde_tile_bf16x3", st);
     const int n_qt256 = (int)ceil_div(m_pad, 256);
     hipLaunchKernelGGL((tile_split_w64<FORM, DP, MODE>), dim3((unsigned)((int64_t)n_qt256 * P)), dim3(256), 0, st,
-                       (U)xp[0], (U)xp[1], xaug, (U)qp[0], (U)qp[1], qaug, n_pad, n_qt256, m_pad, partial);
+                       (U)xp[0], (U)xp[1], xaug, (U)qp[0], (U)qp[1], qaug, n_pad, n_qt256, m_pad, partial, ex);
     (void)n_qtiles;
-    (void)ex;
     return check_launch("tile_split_w64");
   }
   ScopedTimer tm(rescue_timer(ex, FORM == STAG_FORM_FP16_SPLIT

@@ -1,0 +1,135 @@
+"""GPU parity of the adaptive fp16 form of the exact Gaussian density
+(Sec. "Kernel Density Estimation": the all-pairs sum) against the FP64
+oracle, through the C ABI.
+
+The form runs the single-product fp16 centred tiles over all pairs and the
+fp16 split tiles again over the (chunk, 256-query tile) pairs where the
+first pass's bound share is not negligible.  Every result must lie within
+its per-result bound; at the n = 2,000,000, m = 200,000, d = 128 workload
+the measured error must be within 1e-5, as for the fp16 split form.  A
+query's result may depend on the other queries of the call (they decide
+together which chunks of their tile are recomputed), always within the
+bound.
+"""
+import numpy as np
+import pytest
+
+import synth
+from tests.gpu_util import announce, rel_err, to_dev
+
+pytestmark = pytest.mark.gpu
+
+FORM = "fp16_adaptive"
+
+
+@pytest.fixture(scope="module")
+def stag():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_2407_07096_amd as s
+    s.load()
+    return s
+
+
+def _run(stag, X, Q, a, **kw):
+    import torch
+    S, B = stag.kde_exact(to_dev(X), to_dev(Q), a, form=FORM, return_bound=True, **kw)
+    torch.cuda.synchronize()
+    return S.cpu().numpy(), B.cpu().numpy()
+
+
+def test_config1_full(stag, orc):
+    X, Q, _ = synth.config_points(1)
+    announce("fp16 adaptive config1 n=m=1000 d=10 a=0.5")
+    ref = orc.kde_exact(X, Q, 0.5)
+    S, B = _run(stag, X, Q, 0.5)
+    err = rel_err(S, ref)
+    print(f"[measured] fp16 adaptive config1: max rel err {err.max():.3e}, max bound {B.max():.3e}", flush=True)
+    assert np.all(err <= B), (err.max(), B.min())
+
+
+@pytest.mark.parametrize("a", [0.01, 0.1, 0.3, 1.0])
+def test_config2_reduced(stag, orc, a):
+    X, Q, _ = synth.config_points(2, n=9000, m=300)
+    announce(f"fp16 adaptive config2-reduced n=9000 m=300 d=64 a={a}")
+    ref = orc.kde_exact(X, Q, a)
+    S, B = _run(stag, X, Q, a)
+    ok = ref > 1e-300
+    err = rel_err(S[ok], ref[ok])
+    print(f"[measured] fp16 adaptive config2 a={a}: max rel err {err.max():.3e}, max bound {B.max():.3e}",
+          flush=True)
+    assert np.all(err <= B[ok]), (err.max(), B[ok].min())
+    if a == 0.01:
+        assert err.max() <= 1e-5
+
+
+@pytest.mark.parametrize("n,m,d", [(1, 1, 1), (2, 3, 3), (31, 129, 5), (33, 257, 16), (100, 300, 100),
+                                   (4097, 64, 7), (5000, 513, 128), (3000, 200, 160), (5000, 130, 256),
+                                   (20000, 512, 40)])
+def test_shapes(stag, orc, n, m, d):
+    """Ragged sizes, clustered data far from the origin, both pass-2 tiles
+    (64 and 32 queries per wave); deterministic."""
+    rng = np.random.default_rng(n + 13 * d + m)
+    means = rng.uniform(-20, 20, size=(4, d))
+    X = (means[rng.integers(0, 4, size=n)] + rng.normal(size=(n, d))).astype(np.float32)
+    Q = (X[rng.integers(0, n, size=m)] + 0.5 * rng.normal(size=(m, d))).astype(np.float32)
+    a = 0.3 / d
+    announce(f"fp16 adaptive n={n} m={m} d={d}")
+    ref = orc.kde_exact(X, Q, a)
+    S, B = _run(stag, X, Q, a)
+    err = rel_err(S, ref)
+    assert np.all(err <= B), (err.max(), B.max())
+    S2, _ = _run(stag, X, Q, a)
+    assert np.array_equal(S, S2)
+
+
+def test_underflow_rescue(stag, orc):
+    """Far queries (sums down to ~1e-270) are recomputed in the split form
+    with shifted exponents, within their bounds."""
+    rng = np.random.default_rng(31)
+    d = 32
+    X = rng.normal(size=(5000, d)).astype(np.float32)
+    near = (X[:200] + 0.1 * rng.normal(size=(200, d))).astype(np.float32)
+    far = (X[200:328] + rng.uniform(3.0, 6.0, size=(128, 1)).astype(np.float32)
+           * rng.normal(size=(128, d)).astype(np.float32) / np.sqrt(d) * 4.0).astype(np.float32)
+    Q = np.concatenate([near, far]).astype(np.float32)
+    announce(f"fp16 adaptive underflow rescue m={len(Q)} d={d}")
+    ref = orc.kde_exact(X, Q, 1.0)
+    S, B = _run(stag, X, Q, 1.0)
+    ok = ref > 1e-300
+    err = rel_err(S[ok], ref[ok])
+    print(f"[measured] fp16 adaptive rescue: max rel err {err.max():.3e}", flush=True)
+    assert np.sum(ref < 1e-38) > 20
+    assert np.all(err <= B[ok]), (err.max(), B[ok].min())
+
+
+def test_normalize_and_order(stag, orc):
+    """S/n with STAG_NORMALIZE; results land on their own queries' rows
+    (queries given in reverse order give the reversed results)."""
+    X, Q, _ = synth.config_points(2, n=9000, m=300)
+    ref = orc.kde_exact(X, Q, 0.05) / 9000.0
+    S, B = _run(stag, X, Q, 0.05, normalize=True)
+    assert np.all(rel_err(S, ref) <= B)
+    Sr, Br = _run(stag, X, Q[::-1].copy(), 0.05, normalize=True)
+    assert np.all(rel_err(Sr, ref[::-1]) <= Br)
+
+
+def test_config3_full_size_sampled(stag, orc):
+    """n = 2,000,000, m = 200,000, d = 128, a = 0.01: full launch, oracle on
+    the same 1,000 sampled queries as the other forms: within the bound and
+    within 1e-5."""
+    import torch
+    X, Q, _ = synth.config_points(3)
+    rng = np.random.default_rng(2003)
+    idx = np.sort(rng.choice(Q.shape[0], size=1000, replace=False))
+    ref = orc.kde_exact(X, Q[idx], 0.01)
+    announce("fp16 adaptive config3 full n=2e6 m=2e5 d=128 a=0.01")
+    S, B = stag.kde_exact(to_dev(X), to_dev(Q), 0.01, form=FORM, return_bound=True)
+    torch.cuda.synchronize()
+    S, B = S.cpu().numpy(), B.cpu().numpy()
+    err = rel_err(S[idx], ref)
+    print(f"[measured] fp16 adaptive config3: max rel err {err.max():.3e}, median {np.median(err):.3e}, "
+          f"max bound {B[idx].max():.3e}", flush=True)
+    assert np.all(np.isfinite(S))
+    assert np.all(err <= B[idx]), err.max()
+    assert err.max() <= 1e-5, err.max()
