@@ -36,12 +36,15 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 MFMA_PEAK = {"fp32": 157.3e12, "fp16_split": 2.5e15, "bf16_split": 2.5e15, "bf16_split3": 2.5e15,
-             "fp16_centred": 2.5e15}
-PRODUCTS = {"fp32": 1, "fp16_split": 3, "bf16_split": 3, "bf16_split3": 6, "fp16_centred": 1}
+             "fp16_centred": 2.5e15, "fp16_adaptive": 2.5e15}
+PRODUCTS = {"fp32": 1, "fp16_split": 3, "bf16_split": 3, "bf16_split3": 6, "fp16_centred": 1, "fp16_adaptive": 1}
 TILE_KERNEL = {"fp32": "kde_tile_f32c", "fp16_split": "kde_tile_fp16x3", "bf16_split": "kde_tile_bf16x3",
-               "bf16_split3": "kde_tile_bf16x6", "fp16_centred": "kde_tile_fp16c"}
+               "bf16_split3": "kde_tile_bf16x6", "fp16_centred": "kde_tile_fp16c", "fp16_adaptive": "kde_tile_fp16c"}
 DTYPE = {"fp32": "f32", "fp16_split": "f16x3->f32->f64", "bf16_split": "bf16x3->f32->f64",
-         "bf16_split3": "bf16x6->f32->f64", "fp16_centred": "f16->f32->f64"}
+         "bf16_split3": "bf16x6->f32->f64", "fp16_centred": "f16->f32->f64",
+         "fp16_adaptive": "f16 (f16x3 where selected)->f32->f64"}
+# the form of the hot-path step, the edge sampler and the other d = 64 legs
+STEP_FORM = "fp16_split"
 HBM_PEAK = 8.0e12
 FP64_PEAK = 78.6e12
 FP32_PEAK = 157.3e12  # vector fp32 (published)
@@ -833,7 +836,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--form", default="fp16_split", choices=sorted(MFMA_PEAK))
+    ap.add_argument("--form", default="fp16_adaptive", choices=sorted(MFMA_PEAK))
     ap.add_argument("--check-queries", type=int, default=1000)
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--serve-requests", type=int, default=10000)
@@ -872,7 +875,7 @@ def main():
         X, Q, info = synth.config_points(2)
         Xd = torch.from_numpy(X).to(dev)
         Qd = torch.from_numpy(Q).to(dev)
-        step, _ = hot_path_step_run(stag, torch, dev, lib, buf, X, Q, Xd, Qd, args.form, 0.01, steps=args.steps)
+        step, _ = hot_path_step_run(stag, torch, dev, lib, buf, X, Q, Xd, Qd, STEP_FORM, 0.01, steps=args.steps)
         if args.calib_copy_mb > 0:
             src_c = torch.ones(args.calib_copy_mb << 18, dtype=torch.float32, device=dev)
             dst_c = torch.empty_like(src_c)
@@ -919,6 +922,11 @@ def main():
             "algorithmic": f"2*d = {2 * d} flops per (query, point) pair x n*m = {useful:.4e} per launch (the "
                            f"method's work); the {args.form} form issues {PRODUCTS[args.form]} matrix-core "
                            f"products per pair (frac_hardware)"}
+    if args.form == "fp16_adaptive" and "kde_tile_fp16x3" in tm.t:
+        c2, tot2 = tm.t["kde_tile_fp16x3"]
+        roof["second_pass"] = {"kernel": "kde_tile_fp16x3", "avg_launch_ms": tot2 / c2,
+                               "what": "the fp16 split tiles over the selected (chunk, 256-query tile) pairs; "
+                                       "the other workgroups of its grid return at once"}
     result = {
         "metric": "Gaussian kernel evals/sec at <=1e-5 rel err vs FP64; p50/p99 KDE query latency",
         "value": value,
@@ -954,7 +962,7 @@ def main():
         print(f"[bench] checked {args.check_queries} queries: max rel err {err.max():.3e}", file=sys.stderr,
               flush=True)
         if not args.no_extras:
-            others = [f for f in ("fp16_centred", "fp16_split", "bf16_split", "bf16_split3", "fp32") if f != args.form]
+            others = [f for f in ("fp16_split", "fp16_centred", "bf16_split", "bf16_split3", "fp32") if f != args.form]
             result["forms"] = forms_run(stag, torch, lib, buf, Xd, Qd, a, idx, ref, others, n, m, d)
             print("[bench] other forms done", file=sys.stderr, flush=True)
             result["lsh_headline_workload"] = lsh_headline_run(stag, torch, lib, buf, Xd, Qd, a, idx, ref, ms_per_step)
@@ -970,7 +978,7 @@ def main():
         Xd = torch.from_numpy(X).to(dev)
         Qd = torch.from_numpy(Q).to(dev)
         a2 = 0.01
-        step, graph = hot_path_step_run(stag, torch, dev, lib, buf, X, Q, Xd, Qd, args.form, a2, steps=5)
+        step, graph = hot_path_step_run(stag, torch, dev, lib, buf, X, Q, Xd, Qd, STEP_FORM, a2, steps=5)
         result["hot_path_step"] = step
         for k, v in result["hot_path_step"]["rooflines"].items():
             v["traffic"] = committed_traffic(k, "n100k_d64")
@@ -978,8 +986,8 @@ def main():
         result["lsh_default_parameters"] = lsh_defaults_run(stag, torch, dev, lib, buf, X, Q, Xd, Qd, a2)
         print("[bench] CKNS defaults done", file=sys.stderr, flush=True)
         result["e2lsh_table"] = e2lsh_table_run(stag, torch, dev, lib, buf, Xd, Qd)
-        result["kernels"] = kernels_run(stag, torch, dev, lib, buf, X, Q, Xd, Qd, args.form)
-        result["random_sampling"] = rs_run(stag, torch, lib, buf, X, Q, Xd, Qd, a2, args.form)
+        result["kernels"] = kernels_run(stag, torch, dev, lib, buf, X, Q, Xd, Qd, STEP_FORM)
+        result["random_sampling"] = rs_run(stag, torch, lib, buf, X, Q, Xd, Qd, a2, STEP_FORM)
         result["spectral"] = spectral_run(stag, torch, lib, buf, graph, info["n"], info["k"], info["labels"])
         result["kde_tree_sampler"] = tree_run(stag, torch, lib, buf, X, Xd, a2, graph, info["labels"], info["k"])
         del graph, Xd, Qd

@@ -878,7 +878,7 @@ stag_status run_centred(const float* X, int64_t n, const float* Q, int64_t m, in
 // 256-query tile) pairs where some query's first-pass bound share exceeds
 // kAdaptiveShare / P of its sum, the reduction in sorted order with the
 // underflow rescue in the split form, and the results back to the query rows.
-constexpr double kAdaptiveShare = 2.0e-6;
+constexpr double kAdaptiveShare = 1.0e-5;
 
 stag_status run_adaptive(const float* X, int64_t n, const float* Q, int64_t m, int32_t d, double a, uint32_t flags,
                          double* S_out, double* bound_out, const ExactBuffers& b, hipStream_t st) {

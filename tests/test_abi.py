@@ -69,8 +69,13 @@ def test_invalid_arguments_rejected_before_launch():
     # STAG_FORM_AUTO needs eps > 0; unknown forms and flags
     st = lib.stag_kde_exact(fake, 10, fake, 10, 4, 1.0, 0.0, 4, 0, fake, null, null)
     assert st == _lib.STAG_E_INVAL and "eps" in stag.last_error()
-    st = lib.stag_kde_exact(fake, 10, fake, 10, 4, 1.0, 1e-3, 6, 0, fake, null, null)
+    st = lib.stag_kde_exact(fake, 10, fake, 10, 4, 1.0, 1e-3, 7, 0, fake, null, null)
     assert st == _lib.STAG_E_INVAL and "unknown form" in stag.last_error()
+    # the adaptive fp16 form (6): Gaussian sums with d <= 256 only
+    st = lib.stag_kde_exact_kernel(fake, 10, fake, 10, 4, 2, 1.0, 0.0, 6, 0, fake, null, null)
+    assert st == _lib.STAG_E_UNSUPPORTED and "Gaussian" in stag.last_error()
+    st = lib.stag_kde_exact(fake, 10, fake, 10, 300, 1.0, 0.0, 6, 0, fake, null, null)
+    assert st == _lib.STAG_E_UNSUPPORTED
     # the fp16 centred form (5): Gaussian sums with d <= 256 only
     st = lib.stag_kde_exact_kernel(fake, 10, fake, 10, 4, 1, 1.0, 0.0, 5, 0, fake, null, null)
     assert st == _lib.STAG_E_UNSUPPORTED and "Gaussian" in stag.last_error()

@@ -70,7 +70,7 @@ def _both(lib, X, Q, a, form, normalize=False):
     return S0.cpu().numpy(), B0.cpu().numpy(), S1.cpu().numpy(), B1.cpu().numpy()
 
 
-@pytest.mark.parametrize("form", ["fp16_split", "fp32", "bf16_split3", "fp16_centred"])
+@pytest.mark.parametrize("form", ["fp16_split", "fp32", "bf16_split3", "fp16_centred", "fp16_adaptive"])
 def test_noalloc_matches_allocating_call_twice(lib, orc, form):
     # first call: larger input; second: smaller and ragged (d not a multiple of 16)
     X, Q, _ = synth.config_points(2, n=20000, m=3000)
