@@ -154,8 +154,11 @@ double stag_e2lsh_collision_probability(double c, int32_t K, int32_t L);
  * its sum (P chunks) is computed again in the FP16_SPLIT form.  Where the
  * data are clustered and the kernel narrow against the clusters' spacing,
  * few pairs are recomputed and the result has the split form's accuracy at
- * near the single product's cost; otherwise it costs up to both forms
- * together.  bound_out adds the kept chunks' FP16_CENTRED numerators and the
+ * near the single product's cost.  A first estimate runs the selection on
+ * every (m_pad / 128 / 8)-th 128-query tile and reads the count back (one
+ * synchronisation of `stream`); when more than half of those pairs would be
+ * recomputed (wide kernels), the single-product pass is skipped and every
+ * pair runs in the split form.  bound_out adds the kept chunks' FP16_CENTRED numerators and the
  * recomputed chunks' FP16_SPLIT bounds.  Sums below 2^-60 are recomputed in
  * the split form (underflow rescue).  Range rules of both forms apply.
  * Results are deterministic and do not depend on m or on the other rows of Q

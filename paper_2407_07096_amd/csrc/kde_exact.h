@@ -164,6 +164,8 @@ struct TileExtra {
   // cflag[chunk * ceil(m_pad / 256) + tile] != 0 run (the others return at
   // once, their partials not written)
   const uint8_t* cflag = nullptr;
+  // the adaptive form's estimate on sampled query tiles (a timer of its own)
+  int sample = 0;
 };
 
 int exact_padded_dim(int d);  // 0 if unsupported

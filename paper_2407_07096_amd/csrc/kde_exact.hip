@@ -201,11 +201,36 @@ __global__ void sum_partials(const double* __restrict__ partial, int P, int64_t 
 // product pass exceeds thr times its first-pass sum (cflag starts at zero;
 // every writer stores 1).  Grid: (query blocks, chunks).
 __global__ void adaptive_flags(const double* __restrict__ bpart, const double* __restrict__ S1, int64_t m_pad,
-                               int64_t m, int n_qt256, double thr, uint8_t* __restrict__ cflag) {
+                               int64_t m, int n_qt256, double thr, const int* __restrict__ qmask,
+                               uint8_t* __restrict__ cflag) {
   const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t c = blockIdx.y;
-  if (q >= m) return;
+  if (q >= m || (qmask && qmask[q / kBQ] == 0)) return;
   if (bpart[c * m_pad + q] > thr * S1[q]) cflag[c * n_qt256 + q / 256] = 1;
+}
+
+// Adaptive form, the estimate: every stride-th 128-query tile is sampled.
+__global__ void mark_sample(int* __restrict__ qsample, int n_qt128, int stride) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n_qt128) qsample[t] = t % stride == 0 ? 1 : 0;
+}
+
+// counts[0] += selected and counts[1] += all (chunk, 256-query tile) pairs
+// of the tiles that hold a sampled 128-query tile.  Grid: (tiles, chunks).
+__global__ void count_selected(const uint8_t* __restrict__ cflag, int n_qt256, const int* __restrict__ qsample,
+                               int n_qt128, unsigned int* __restrict__ counts) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t c = blockIdx.y;
+  if (t >= n_qt256) return;
+  const bool sampled = qsample[2 * t] != 0 || (2 * t + 1 < n_qt128 && qsample[2 * t + 1] != 0);
+  if (!sampled) return;
+  atomicAdd(counts, cflag[c * n_qt256 + t] ? 1u : 0u);
+  atomicAdd(counts + 1, 1u);
+}
+
+__global__ void fill_ones(uint8_t* __restrict__ p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 1;
 }
 
 // Adaptive form: S(q) = sum of the chunk partials in chunk order (first
@@ -772,6 +797,8 @@ struct ExactBuffers {
   QuerySort qs;
   double *S1 = nullptr, *Ss = nullptr, *Bs = nullptr;
   uint8_t* cflag = nullptr;
+  int* qsample = nullptr;
+  unsigned int* counts = nullptr;
 };
 
 // The fp32 form of the Gaussian sum centres the data tile by tile (the wide
@@ -799,6 +826,8 @@ stag_status alloc_exact(int form, int kernel, int64_t n, int64_t m, int d, Works
     STAG_TRY(ws.alloc(&b->Ss, (size_t)m_pad));
     STAG_TRY(ws.alloc(&b->Bs, (size_t)m_pad));
     STAG_TRY(ws.alloc(&b->cflag, (size_t)b->P * ceil_div(m_pad, 256)));
+    STAG_TRY(ws.alloc(&b->qsample, (size_t)(m_pad / kBQ)));
+    STAG_TRY(ws.alloc(&b->counts, 2));
     return alloc_rescue(kernel, b->P, b->qsp, ws, &b->rb);
   }
   if (use_centred(form, kernel, d)) {
@@ -878,7 +907,14 @@ stag_status run_centred(const float* X, int64_t n, const float* Q, int64_t m, in
 // 256-query tile) pairs where some query's first-pass bound share exceeds
 // kAdaptiveShare / P of its sum, the reduction in sorted order with the
 // underflow rescue in the split form, and the results back to the query rows.
+// First an estimate: the single-product pass and the selection on every
+// stride-th 128-query tile (about kAdaptiveSamples of them), read back with
+// one synchronisation; when more than kAdaptiveMaxShare of the sampled pairs
+// are selected (wide kernels: every chunk matters), the single-product pass
+// is skipped and every pair runs in the split form.
 constexpr double kAdaptiveShare = 1.0e-5;
+constexpr int kAdaptiveSamples = 8;
+constexpr double kAdaptiveMaxShare = 0.5;
 
 stag_status run_adaptive(const float* X, int64_t n, const float* Q, int64_t m, int32_t d, double a, uint32_t flags,
                          double* S_out, double* bound_out, const ExactBuffers& b, hipStream_t st) {
@@ -895,23 +931,50 @@ stag_status run_adaptive(const float* X, int64_t n, const float* Q, int64_t m, i
                     b.xs.off, nullptr, b.xs.nrm, b.xs.max_nrm_bits, st, b.ct.map));
   STAG_TRY(prep_any(STAG_FORM_FP16_SPLIT, Q, m, d, b.qsp.dp, b.qsp.rows_pad, 2.0 * a * kLog2e, -a * kLog2e, 1,
                     b.qsp.part, b.qsp.off, nullptr, b.qsp.nrm, nullptr, st, b.qs.perm));
-  // first pass: one fp16 product per pair, with the bound numerators
+  // first pass: one fp16 product per pair, with the bound numerators, then
+  // the selection of the pairs to recompute (on the sampled tiles: qmask)
   const BoundModel bm1 = make_bound_model(STAG_FORM_FP32, d, a, STAG_KERNEL_GAUSSIAN);
   TileExtra ex1;
   ex1.a = a;
   ex1.bpart = b.bpart;
   ex1.c_cent = (float)bm1.c_cent;
-  STAG_TRY(launch_exact_tiles(xo, qo, b.partial, ex1, st));
-  // selection of the pairs to recompute
-  {
+  auto first_pass = [&](const int* qmask) -> stag_status {
+    TileExtra e = ex1;
+    e.qtile_active = qmask;
+    e.sample = qmask ? 1 : 0;
+    STAG_TRY(launch_exact_tiles(xo, qo, b.partial, e, st));
     ScopedTimer tm("kde_adaptive_select", st);
     hipLaunchKernelGGL(sum_partials, dim3((unsigned)ceil_div(m_pad, 256)), dim3(256), 0, st, b.partial, b.P, m_pad,
                        b.S1);
     STAG_TRY(check_launch("sum_partials"));
     STAG_TRY(zero_async(b.cflag, (size_t)b.P * n_qt256, st));
     hipLaunchKernelGGL(adaptive_flags, dim3((unsigned)ceil_div(m, 256), (unsigned)b.P), dim3(256), 0, st, b.bpart,
-                       b.S1, m_pad, m, n_qt256, kAdaptiveShare / b.P, b.cflag);
-    STAG_TRY(check_launch("adaptive_flags"));
+                       b.S1, m_pad, m, n_qt256, kAdaptiveShare / b.P, qmask, b.cflag);
+    return check_launch("adaptive_flags");
+  };
+  const int n_qt128 = (int)(m_pad / kBQ);
+  const int stride = std::max(1, n_qt128 / kAdaptiveSamples);
+  hipLaunchKernelGGL(mark_sample, dim3((unsigned)ceil_div(n_qt128, 256)), dim3(256), 0, st, b.qsample, n_qt128,
+                     stride);
+  STAG_TRY(check_launch("mark_sample"));
+  STAG_TRY(first_pass(stride > 1 ? b.qsample : nullptr));
+  unsigned int hc[2] = {0u, 0u};
+  {
+    ScopedTimer tm("kde_adaptive_select", st);
+    STAG_TRY(zero_async(b.counts, 2 * sizeof(unsigned int), st));
+    hipLaunchKernelGGL(count_selected, dim3((unsigned)ceil_div(n_qt256, 256), (unsigned)b.P), dim3(256), 0, st,
+                       b.cflag, n_qt256, b.qsample, n_qt128, b.counts);
+    STAG_TRY(check_launch("count_selected"));
+    STAG_HIP(hipMemcpyAsync(hc, b.counts, sizeof(hc), hipMemcpyDeviceToHost, st));
+    STAG_HIP(hipStreamSynchronize(st));
+  }
+  if (hc[1] > 0 && (double)hc[0] > kAdaptiveMaxShare * (double)hc[1]) {
+    // every pair in the split form (the partials of the sampled pass are overwritten)
+    hipLaunchKernelGGL(fill_ones, dim3((unsigned)ceil_div((int64_t)b.P * n_qt256, 256)), dim3(256), 0, st, b.cflag,
+                       (int64_t)b.P * n_qt256);
+    STAG_TRY(check_launch("fill_ones"));
+  } else if (stride > 1) {
+    STAG_TRY(first_pass(nullptr));
   }
   // second pass: the split form on the selected pairs (overwrites their partials)
   TileExtra ex2;

@@ -1270,6 +1270,7 @@ __global__ __launch_bounds__(256) void tile_f32_wide(const float* __restrict__ X
 // Timer name of a launch: the underflow rescue's passes are timed apart from
 // the tiles they repeat.
 inline const char* rescue_timer(const TileExtra& ex, const char* name) {
+  if (ex.sample) return "kde_adaptive_sample";
   return ex.max_pass ? "kde_rescue_max" : (ex.qtile_active ? "kde_rescue_sum" : name);
 }
 

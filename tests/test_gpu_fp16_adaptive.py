@@ -83,6 +83,21 @@ def test_shapes(stag, orc, n, m, d):
     assert np.array_equal(S, S2)
 
 
+@pytest.mark.parametrize("a", [1e-4, 0.001])
+def test_wide_kernel_fallback(stag, orc, a):
+    """A kernel wide against the clusters' spacing selects most pairs, so the
+    estimate sends every pair to the split form: within the bound and 1e-5,
+    as the split form is."""
+    X, Q, _ = synth.config_points(2, n=20000, m=2000)
+    idx = np.arange(0, 2000, 7)
+    announce(f"fp16 adaptive wide kernel n=20000 m=2000 d=64 a={a}")
+    ref = orc.kde_exact(X, Q[idx], a)
+    S, B = _run(stag, X, Q, a)
+    err = rel_err(S[idx], ref)
+    print(f"[measured] fp16 adaptive a={a}: max rel err {err.max():.3e}, max bound {B[idx].max():.3e}", flush=True)
+    assert np.all(err <= B[idx]) and err.max() <= 1e-5, err.max()
+
+
 def test_underflow_rescue(stag, orc):
     """Far queries (sums down to ~1e-270) are recomputed in the split form
     with shifted exponents, within their bounds."""
