@@ -161,8 +161,11 @@ double stag_e2lsh_collision_probability(double c, int32_t K, int32_t L);
  * pair runs in the split form.  bound_out adds the kept chunks' FP16_CENTRED numerators and the
  * recomputed chunks' FP16_SPLIT bounds.  Sums below 2^-60 are recomputed in
  * the split form (underflow rescue).  Range rules of both forms apply.
- * Results are deterministic and do not depend on m or on the other rows of Q
- * (each row's reduction order depends only on n). */
+ * Results are deterministic.  In every form but FP16_ADAPTIVE they do not
+ * depend on m or on the other rows of Q (each row's reduction order depends
+ * only on n); in FP16_ADAPTIVE the queries of a 256-query tile decide
+ * together which chunks are recomputed, so a row's result (always within
+ * its bound) may change with the other rows of Q. */
 stag_status stag_kde_exact(const float* X, int64_t n, const float* Q, int64_t m, int32_t d, double a,
                            double eps, int32_t form, uint32_t flags, double* S_out, double* bound_out,
                            hipStream_t stream);
@@ -182,7 +185,9 @@ stag_status stag_kde_exact(const float* X, int64_t n, const float* Q, int64_t m,
  *     32, 64, 96 ... 256) plus 24 * m_pad * ceil(n / 4096) bytes of partial
  *     sums, m_pad = m rounded up to 128);
  *   - no hipMalloc, hipFree or allocating routine is called; the first call
- *     on a device looks up that device's scratch address once.
+ *     on a device looks up that device's scratch address once;
+ *   - FP16_ADAPTIVE reads its estimate back (one synchronisation of
+ *     `stream`), so that form cannot be recorded into a HIP graph.
  * Every call on one device shares that device's scratch: calls that overlap
  * on one device (on different streams, or from several threads) race and
  * give wrong results; serialise them.  The scratch keeps the last call's
