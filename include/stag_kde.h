@@ -158,7 +158,11 @@ double stag_e2lsh_collision_probability(double c, int32_t K, int32_t L);
  * every (m_pad / 128 / 8)-th 128-query tile and reads the count back (one
  * synchronisation of `stream`); when more than half of those pairs would be
  * recomputed (wide kernels), the single-product pass is skipped and every
- * pair runs in the split form.  bound_out adds the kept chunks' FP16_CENTRED numerators and the
+ * pair runs in the split form.  In the single-product pass, a wave of 64
+ * queries whose offsets -a log2(e) ||q - c_g||^2 all lie in [-60, 0] for a
+ * group sums 2^(E + a log2(e) ||q - c_g||^2) and scales the sums by
+ * fl32(2^(-a log2(e) ||q - c_g||^2)) (one rounding more, in its bound).
+ * bound_out adds the kept chunks' FP16_CENTRED numerators and the
  * recomputed chunks' FP16_SPLIT bounds.  Sums below 2^-60 are recomputed in
  * the split form (underflow rescue).  Range rules of both forms apply.
  * Results are deterministic.  In every form but FP16_ADAPTIVE they do not

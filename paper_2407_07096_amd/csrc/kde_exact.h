@@ -166,6 +166,11 @@ struct TileExtra {
   const uint8_t* cflag = nullptr;
   // the adaptive form's estimate on sampled query tiles (a timer of its own)
   int sample = 0;
+  // centred fp16 tile, Gaussian sums: a wave whose queries all have their
+  // offset alpha in [-60, 0] for a group starts its accumulators from beta
+  // alone and scales its tile sums by 2^alpha (a query's bits then depend on
+  // the other queries of its wave)
+  int fold_alpha = 0;
 };
 
 int exact_padded_dim(int d);  // 0 if unsupported

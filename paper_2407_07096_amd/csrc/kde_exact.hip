@@ -942,6 +942,7 @@ stag_status run_adaptive(const float* X, int64_t n, const float* Q, int64_t m, i
     TileExtra e = ex1;
     e.qtile_active = qmask;
     e.sample = qmask ? 1 : 0;
+    e.fold_alpha = 1;
     STAG_TRY(launch_exact_tiles(xo, qo, b.partial, e, st));
     ScopedTimer tm("kde_adaptive_select", st);
     hipLaunchKernelGGL(sum_partials, dim3((unsigned)ceil_div(m_pad, 256)), dim3(256), 0, st, b.partial, b.P, m_pad,

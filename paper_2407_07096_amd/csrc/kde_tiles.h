@@ -932,6 +932,13 @@ __global__ __launch_bounds__(256, 2) void tile_split_w64(
 // qtile_active, a workgroup whose 128-query tiles are all inactive returns at
 // once and a wave whose tile is inactive only stages.  A query element with
 // |2 la (q_j - c_j)| >= 65520 (fp16 infinity) makes alpha NaN for the group.
+// Gaussian sums with ex.fold_alpha: where every alpha of the wave lies in
+// [-60, 0] for the group, the accumulators start from beta alone (the first
+// product reads the beta registers as its accumulator input: no seeding
+// instructions) and each tile sum is multiplied by fl32(2^alpha) instead, so
+// that a term is 2^(beta + cross) 2^alpha with 2^(beta + cross) <= 2^-alpha
+// <= 2^60; the bound factor of such a group adds 2^-21 for the two extra
+// roundings.  A query's result then depends on the other queries of its wave.
 
 // Exponent error bound M (base 2) of every term of a (query, group):
 //   fp32 part as in the centred fp32 tile: c_cent (la (|q - c| + R)^2 + |qoff|)
@@ -1019,12 +1026,14 @@ __global__ __launch_bounds__(256, 2) void tile_h1c(const unsigned short* __restr
 
   // the queries' operands, offsets and bound factors for group g
   u16x8 bq[NB][KS];
-  float alpha[NB], eg[NB];
+  float alpha[NB], eg[NB], scl[NB];
 #pragma unroll
   for (int b = 0; b < NB; ++b) {
     alpha[b] = 0.0f;
     eg[b] = 0.0f;
+    scl[b] = 1.0f;
   }
+  bool noseed = false;  // wave-uniform
   int cur = -1;
   auto form_queries = [&](int g) {
     const float* cg = cen + (int64_t)g * DP;
@@ -1065,6 +1074,17 @@ __global__ __launch_bounds__(256, 2) void tile_h1c(const unsigned short* __restr
       alpha[b] = m < 65520.0f ? fmaf(-la, t, qo[b]) : __builtin_nanf("");
       if constexpr (MODE != kModeMax) eg[b] = h1c_bound_factor(t, R, qo[b], la, c_cent, rdp);
     }
+    if constexpr (MODE == kModeGauss) {
+      bool ok = ex.fold_alpha != 0;
+#pragma unroll
+      for (int b = 0; b < NB; ++b) ok = ok && alpha[b] >= -60.0f && alpha[b] <= 0.0f;  // NaN fails
+      noseed = __all(ok) != 0;
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        scl[b] = noseed ? __builtin_amdgcn_exp2f(alpha[b]) : 1.0f;
+        if (noseed) eg[b] += 0x1p-21f;  // applies to the scaled tile sum
+      }
+    }
   };
 
   u16x8 stage[NLD];
@@ -1091,7 +1111,7 @@ __global__ __launch_bounds__(256, 2) void tile_h1c(const unsigned short* __restr
     acc[b] = acc_init<MODE>();
     bacc[b] = 0.0;
   }
-  auto epilogue = [&](const f32x16 (&d)[NB], const float (&f)[NB]) {
+  auto epilogue = [&](const f32x16 (&d)[NB], const float (&f)[NB], const float (&sc)[NB]) {
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
       if constexpr (MODE == kModeMax) {
@@ -1103,34 +1123,51 @@ __global__ __launch_bounds__(256, 2) void tile_h1c(const unsigned short* __restr
         float e[16];
 #pragma unroll
         for (int i = 0; i < 16; ++i) e[i] = d[b][i];
-        const float sm = kernel_tile_sum<MODE>(e);
+        float sm = kernel_tile_sum<MODE>(e);
+        if constexpr (MODE == kModeGauss) sm *= sc[b];
         acc[b] += (double)sm;
         bacc[b] += (double)(sm * f[b]);
       }
     }
   };
-  auto step = [&](int t, const f32x16 (&d)[NB], const float (&f)[NB], f32x16 (&nc)[NB], float (&nf)[NB]) {
+  int gnext = tgroup[tile0];  // the next tile's group, loaded a step ahead
+  auto step = [&](int t, const f32x16 (&d)[NB], const float (&f)[NB], const float (&sc)[NB], f32x16 (&nc)[NB],
+                  float (&nf)[NB], float (&ns)[NB]) {
     const int buf = t & 1;
     __syncthreads();
+    const int g = gnext;
+    gnext = tgroup[tile0 + min(t + 1, ntiles - 1)];
     if (live) {
-      const int g = tgroup[tile0 + t];
       if (g != cur) {
         form_queries(g);
         cur = g;
       }
-      epilogue(d, f);
-      // the accumulators start from the offsets alpha_q + beta_x of their pairs
-      f32x16 c[NB];
+      epilogue(d, f, sc);
+      // the accumulators start from the offsets alpha_q + beta_x of their
+      // pairs, or from beta_x alone (alpha applied to the tile sums)
+      f32x16 bvec;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const f32x4 bv = *reinterpret_cast<const f32x4*>(&tbeta[buf][8 * q + 4 * h]);
 #pragma unroll
-        for (int b = 0; b < NB; ++b)
+        for (int i = 0; i < 4; ++i) bvec[4 * q + i] = bv[i];
+      }
+      f32x16 c[NB];
+      const u16x8 a0 = *reinterpret_cast<const u16x8*>(&tile[buf][r32 * LD + h * 8]);
+      if (noseed) {
 #pragma unroll
-          for (int i = 0; i < 4; ++i) c[b][4 * q + i] = alpha[b] + bv[i];
+        for (int b = 0; b < NB; ++b) c[b] = mma16<STAG_FORM_FP16_SPLIT>(a0, bq[b][0], bvec);
+      } else {
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+          f32x16 c0;
+#pragma unroll
+          for (int i = 0; i < 16; ++i) c0[i] = alpha[b] + bvec[i];
+          c[b] = mma16<STAG_FORM_FP16_SPLIT>(a0, bq[b][0], c0);
+        }
       }
 #pragma unroll
-      for (int s = 0; s < KS; ++s) {
+      for (int s = 1; s < KS; ++s) {
         const u16x8 a = *reinterpret_cast<const u16x8*>(&tile[buf][r32 * LD + s * 16 + h * 8]);
 #pragma unroll
         for (int b = 0; b < NB; ++b) c[b] = mma16<STAG_FORM_FP16_SPLIT>(a, bq[b][s], c[b]);
@@ -1139,14 +1176,17 @@ __global__ __launch_bounds__(256, 2) void tile_h1c(const unsigned short* __restr
       for (int b = 0; b < NB; ++b) {
         nc[b] = c[b];
         nf[b] = eg[b];
+        ns[b] = scl[b];
       }
     }
     lstore(buf ^ 1);
     gload(min(t + 2, ntiles - 1));
+    // the products after the first k-step, each with its share of the epilogue
+    constexpr int NM2 = NMMA - NB;
 #pragma unroll
-    for (int i = 0; i < NMMA; ++i) {
+    for (int i = 0; i < NM2; ++i) {
       __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
-      __builtin_amdgcn_sched_group_barrier(0x002, (40 * NB + NMMA - 1) / NMMA, 0);
+      __builtin_amdgcn_sched_group_barrier(0x002, (44 * NB + NM2 - 1) / (NM2 > 0 ? NM2 : 1), 0);
     }
   };
 
@@ -1154,7 +1194,7 @@ __global__ __launch_bounds__(256, 2) void tile_h1c(const unsigned short* __restr
   lstore(0);
   gload(min(1, ntiles - 1));
   f32x16 ca[NB], cb[NB];
-  float fa[NB], fb[NB];
+  float fa[NB], fb[NB], sa[NB], sb[NB];
 #pragma unroll
   for (int b = 0; b < NB; ++b) {
 #pragma unroll
@@ -1164,21 +1204,24 @@ __global__ __launch_bounds__(256, 2) void tile_h1c(const unsigned short* __restr
     }
     fa[b] = 0.0f;
     fb[b] = 0.0f;
+    sa[b] = 1.0f;
+    sb[b] = 1.0f;
   }
   int t = 0;
   for (; t + 1 < ntiles; t += 2) {
-    step(t, ca, fa, cb, fb);
-    step(t + 1, cb, fb, ca, fa);
+    step(t, ca, fa, sa, cb, fb, sb);
+    step(t + 1, cb, fb, sb, ca, fa, sa);
   }
   if (t < ntiles) {
-    step(t, ca, fa, cb, fb);
+    step(t, ca, fa, sa, cb, fb, sb);
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
       ca[b] = cb[b];
       fa[b] = fb[b];
+      sa[b] = sb[b];
     }
   }
-  if (live) epilogue(ca, fa);
+  if (live) epilogue(ca, fa, sa);
 #pragma unroll
   for (int b = 0; b < NB; ++b) {
     const double o = __shfl_down(acc[b], 32);
