@@ -925,7 +925,7 @@ __global__ __launch_bounds__(256, 2) void tile_split_w64(
 // and alpha = fl32(-la ||q - c_g||^2) + qoff from the fp32 query rows, so
 //   E = alpha + beta + fl16(2 la (q - c_g)) . fl16(x - c_g),
 // and, per query and group, the bound factor 2^{M} - 1 of
-// h1c_bound_factor; bpart collects the tile sums times that factor.
+// h1c_bound_factor; bpart collects the group's sums times that factor.
 // Up to d = 128, 64 queries per wave as in tile_split_w64 (each A operand
 // read from LDS feeds two 32-query blocks), 256 per workgroup; above, 32 per
 // wave (the query operands alone take 4 d / 16 registers per block).  With
@@ -935,10 +935,11 @@ __global__ __launch_bounds__(256, 2) void tile_split_w64(
 // Gaussian sums with ex.fold_alpha: where every alpha of the wave lies in
 // [-60, 0] for the group, the accumulators start from beta alone (the first
 // product reads the beta registers as its accumulator input: no seeding
-// instructions) and each tile sum is multiplied by fl32(2^alpha) instead, so
-// that a term is 2^(beta + cross) 2^alpha with 2^(beta + cross) <= 2^-alpha
-// <= 2^60; the bound factor of such a group adds 2^-21 for the two extra
-// roundings.  A query's result then depends on the other queries of its wave.
+// instructions) and the group's sum is multiplied by fl32(2^alpha) instead,
+// so that a term is 2^(beta + cross) 2^alpha with 2^(beta + cross) <= 2^-alpha
+// <= 2^60; the bound factor of such a group adds 2^-21 for the rounding of
+// fl32(2^alpha).  A query's result then depends on the other queries of its
+// wave.
 
 // Exponent error bound M (base 2) of every term of a (query, group):
 //   fp32 part as in the centred fp32 tile: c_cent (la (|q - c| + R)^2 + |qoff|)
@@ -1082,7 +1083,7 @@ __global__ __launch_bounds__(256, 2) void tile_h1c(const unsigned short* __restr
 #pragma unroll
       for (int b = 0; b < NB; ++b) {
         scl[b] = noseed ? __builtin_amdgcn_exp2f(alpha[b]) : 1.0f;
-        if (noseed) eg[b] += 0x1p-21f;  // applies to the scaled tile sum
+        if (noseed) eg[b] += 0x1p-21f;
       }
     }
   };
@@ -1105,13 +1106,20 @@ __global__ __launch_bounds__(256, 2) void tile_h1c(const unsigned short* __restr
     tbeta[buf][tid & 31] = sbeta;
   };
 
-  double acc[NB], bacc[NB];
+  // Sums: a group's tiles add their tile sums into aseg (fp64); once the
+  // group's last tile is in (one step after the group changed, so that the
+  // epilogue stays beside the next tile's products), aseg times the group's
+  // scale goes to acc and times scale and bound factor to bacc.
+  double acc[NB], bacc[NB], aseg[NB];
+  float psc[NB], peg[NB];  // the closed group's scale and bound factor
+  bool pend = false;       // wave-uniform: a closed group awaits its flush
 #pragma unroll
   for (int b = 0; b < NB; ++b) {
     acc[b] = acc_init<MODE>();
     bacc[b] = 0.0;
+    aseg[b] = 0.0;
   }
-  auto epilogue = [&](const f32x16 (&d)[NB], const float (&f)[NB], const float (&sc)[NB]) {
+  auto epilogue = [&](const f32x16 (&d)[NB]) {
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
       if constexpr (MODE == kModeMax) {
@@ -1123,28 +1131,46 @@ __global__ __launch_bounds__(256, 2) void tile_h1c(const unsigned short* __restr
         float e[16];
 #pragma unroll
         for (int i = 0; i < 16; ++i) e[i] = d[b][i];
-        float sm = kernel_tile_sum<MODE>(e);
-        if constexpr (MODE == kModeGauss) sm *= sc[b];
-        acc[b] += (double)sm;
-        bacc[b] += (double)(sm * f[b]);
+        aseg[b] += (double)kernel_tile_sum<MODE>(e);
+      }
+    }
+  };
+  auto flush = [&](const float (&fs)[NB], const float (&fe)[NB]) {
+    if constexpr (MODE != kModeMax) {
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        const double sc = (double)fs[b];
+        acc[b] = fma(aseg[b], sc, acc[b]);
+        bacc[b] = fma(aseg[b], sc * (double)fe[b], bacc[b]);
+        aseg[b] = 0.0;
       }
     }
   };
   int gnext = tgroup[tile0];  // the next tile's group, loaded a step ahead
-  auto step = [&](int t, const f32x16 (&d)[NB], const float (&f)[NB], const float (&sc)[NB], f32x16 (&nc)[NB],
-                  float (&nf)[NB], float (&ns)[NB]) {
+  auto step = [&](int t, const f32x16 (&d)[NB], f32x16 (&nc)[NB]) {
     const int buf = t & 1;
     __syncthreads();
     const int g = gnext;
     gnext = tgroup[tile0 + min(t + 1, ntiles - 1)];
     if (live) {
+      if (pend) {
+        // aseg holds the closed group's tiles (the last one added a step ago)
+        flush(psc, peg);
+        pend = false;
+      }
       if (g != cur) {
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+          psc[b] = scl[b];
+          peg[b] = eg[b];
+        }
+        pend = true;
         form_queries(g);
         cur = g;
       }
-      epilogue(d, f, sc);
+      epilogue(d);
       // the accumulators start from the offsets alpha_q + beta_x of their
-      // pairs, or from beta_x alone (alpha applied to the tile sums)
+      // pairs, or from beta_x alone (alpha applied to the group's sums)
       f32x16 bvec;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
@@ -1173,11 +1199,7 @@ __global__ __launch_bounds__(256, 2) void tile_h1c(const unsigned short* __restr
         for (int b = 0; b < NB; ++b) c[b] = mma16<STAG_FORM_FP16_SPLIT>(a, bq[b][s], c[b]);
       }
 #pragma unroll
-      for (int b = 0; b < NB; ++b) {
-        nc[b] = c[b];
-        nf[b] = eg[b];
-        ns[b] = scl[b];
-      }
+      for (int b = 0; b < NB; ++b) nc[b] = c[b];
     }
     lstore(buf ^ 1);
     gload(min(t + 2, ntiles - 1));
@@ -1186,7 +1208,7 @@ __global__ __launch_bounds__(256, 2) void tile_h1c(const unsigned short* __restr
 #pragma unroll
     for (int i = 0; i < NM2; ++i) {
       __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
-      __builtin_amdgcn_sched_group_barrier(0x002, (44 * NB + NM2 - 1) / (NM2 > 0 ? NM2 : 1), 0);
+      __builtin_amdgcn_sched_group_barrier(0x002, (40 * NB + NM2 - 1) / (NM2 > 0 ? NM2 : 1), 0);
     }
   };
 
@@ -1194,7 +1216,6 @@ __global__ __launch_bounds__(256, 2) void tile_h1c(const unsigned short* __restr
   lstore(0);
   gload(min(1, ntiles - 1));
   f32x16 ca[NB], cb[NB];
-  float fa[NB], fb[NB], sa[NB], sb[NB];
 #pragma unroll
   for (int b = 0; b < NB; ++b) {
 #pragma unroll
@@ -1202,26 +1223,22 @@ __global__ __launch_bounds__(256, 2) void tile_h1c(const unsigned short* __restr
       ca[b][i] = kPadOffset;  // kernel value 0: neutral first epilogue
       cb[b][i] = kPadOffset;
     }
-    fa[b] = 0.0f;
-    fb[b] = 0.0f;
-    sa[b] = 1.0f;
-    sb[b] = 1.0f;
   }
   int t = 0;
   for (; t + 1 < ntiles; t += 2) {
-    step(t, ca, fa, sa, cb, fb, sb);
-    step(t + 1, cb, fb, sb, ca, fa, sa);
+    step(t, ca, cb);
+    step(t + 1, cb, ca);
   }
   if (t < ntiles) {
-    step(t, ca, fa, sa, cb, fb, sb);
+    step(t, ca, cb);
 #pragma unroll
-    for (int b = 0; b < NB; ++b) {
-      ca[b] = cb[b];
-      fa[b] = fb[b];
-      sa[b] = sb[b];
-    }
+    for (int b = 0; b < NB; ++b) ca[b] = cb[b];
   }
-  if (live) epilogue(ca, fa, sa);
+  if (live) {
+    if (pend) flush(psc, peg);
+    epilogue(ca);
+    flush(scl, eg);
+  }
 #pragma unroll
   for (int b = 0; b < NB; ++b) {
     const double o = __shfl_down(acc[b], 32);
