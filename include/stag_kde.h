@@ -149,9 +149,11 @@ double stag_e2lsh_collision_probability(double c, int32_t K, int32_t L);
  * 65520, gives NaN results (all of them, or that query's).
  * FP16_ADAPTIVE (Gaussian kernel, d <= 256): the queries are ordered by
  * their nearest seed of the same grouping, the FP16_CENTRED tiles run over
- * all pairs, and every (4096-row chunk, 256-query tile) pair in which some
- * query's FP16_CENTRED bound numerator for that chunk exceeds 1e-5 / P of
- * its sum (P chunks) is computed again in the FP16_SPLIT form.  Where the
+ * all pairs; per query, the chunks with the smallest FP16_CENTRED bound
+ * numerators whose numerators add up to at most 1e-5 of its sum keep their
+ * values (the cut taken at a power of 4 of that budget), and every (4096-row
+ * chunk, 256-query tile) pair in which some query's chunk is not among them
+ * is computed again in the FP16_SPLIT form.  Where the
  * data are clustered and the kernel narrow against the clusters' spacing,
  * few pairs are recomputed and the result has the split form's accuracy at
  * near the single product's cost.  A first estimate runs the selection on

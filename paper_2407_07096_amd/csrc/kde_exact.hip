@@ -187,26 +187,71 @@ __global__ void reduce_centred(const double* __restrict__ partial, const double*
   }
 }
 
-// Adaptive form: the first pass's sum per (sorted) query, all m_pad rows.
-__global__ void sum_partials(const double* __restrict__ partial, int P, int64_t m_pad, double* __restrict__ out) {
+// Adaptive form, per (sorted) query: the first pass's sum S1 over its P
+// chunk partials, and the threshold T below which its chunks keep their
+// first-pass values.  With budget = share * S1, T is the largest of the
+// candidates 4^-j budget (j = 0 .. kBudgetSteps - 1) for which the chunk
+// bound numerators below it add up to at most 0.999 budget (each candidate's
+// sum kept in a register, in units of the budget); the chunks left to the
+// first pass then carry at most share * S1 of bound numerator between them,
+// and the recomputed ones are those with the largest numerators.  T = 0 where
+// the budget is 0 (S1 = 0) or outside the range its reciprocal needs, on the
+// rows past m and outside qmask (where S1 is not needed and not written).
+constexpr int kBudgetSteps = 16;
+__global__ void adaptive_budget(const double* __restrict__ partial, const double* __restrict__ bpart, int P,
+                                int64_t m_pad, int64_t m, double share, const int* __restrict__ qmask,
+                                double* __restrict__ S1, double* __restrict__ T) {
   const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= m_pad) return;
+  if (q >= m || (qmask && qmask[q / kBQ] == 0)) {
+    T[q] = 0.0;
+    return;
+  }
   double s = 0.0;
   for (int p = 0; p < P; ++p) s += partial[(int64_t)p * m_pad + q];
-  out[q] = s;
+  S1[q] = s;
+  const double budget = share * s;
+  const double inv = 1.0 / budget;
+  if (!(budget > 0.0) || !(inv < HUGE_VAL)) {
+    T[q] = 0.0;
+    return;
+  }
+  float acc[kBudgetSteps];
+#pragma unroll
+  for (int j = 0; j < kBudgetSteps; ++j) acc[j] = 0.0f;
+  for (int p = 0; p < P; ++p) {
+    const double v = bpart[(int64_t)p * m_pad + q];
+    if (!(v < budget)) continue;  // recomputed whatever the others hold (NaN as well)
+    const float r = (float)(v * inv);
+    // every chunk with v < 4^-j budget is counted under candidate j (the
+    // margin covers the roundings of r)
+    float c = 1.000001f;
+#pragma unroll
+    for (int j = 0; j < kBudgetSteps; ++j) {
+      acc[j] += r <= c ? r : 0.0f;
+      c *= 0.25f;
+    }
+  }
+  double t = 0.0, c = 1.0;
+#pragma unroll
+  for (int j = 0; j < kBudgetSteps; ++j) {
+    if (t == 0.0 && acc[j] <= 0.999f) t = c;
+    c *= 0.25;
+  }
+  T[q] = t * budget;
 }
 
 // Adaptive form: a (chunk, 256-query tile) pair is recomputed in the split
-// form when some query's bound numerator of that chunk from the single-
-// product pass exceeds thr times its first-pass sum (cflag starts at zero;
-// every writer stores 1).  Grid: (query blocks, chunks).
-__global__ void adaptive_flags(const double* __restrict__ bpart, const double* __restrict__ S1, int64_t m_pad,
-                               int64_t m, int n_qt256, double thr, const int* __restrict__ qmask,
-                               uint8_t* __restrict__ cflag) {
+// form when some query's bound numerator v of that chunk from the single-
+// product pass is positive and not below the query's threshold T (cflag
+// starts at zero; every writer stores 1).  Grid: (query blocks, chunks).
+__global__ void adaptive_flags(const double* __restrict__ bpart, const double* __restrict__ T, int64_t m_pad,
+                               int64_t m, int n_qt256, const int* __restrict__ qmask, uint8_t* __restrict__ cflag) {
   const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t c = blockIdx.y;
   if (q >= m || (qmask && qmask[q / kBQ] == 0)) return;
-  if (bpart[c * m_pad + q] > thr * S1[q]) cflag[c * n_qt256 + q / 256] = 1;
+  const double v = bpart[c * m_pad + q];
+  if (v > 0.0 && !(v < T[q])) cflag[c * n_qt256 + q / 256] = 1;
 }
 
 // Adaptive form, the estimate: every stride-th 128-query tile is sampled.
@@ -795,7 +840,7 @@ struct ExactBuffers {
   bool adaptive = false;
   Operands xs, qsp;
   QuerySort qs;
-  double *S1 = nullptr, *Ss = nullptr, *Bs = nullptr;
+  double *S1 = nullptr, *T = nullptr, *Ss = nullptr, *Bs = nullptr;
   uint8_t* cflag = nullptr;
   int* qsample = nullptr;
   unsigned int* counts = nullptr;
@@ -823,6 +868,7 @@ stag_status alloc_exact(int form, int kernel, int64_t n, int64_t m, int d, Works
     STAG_TRY(ws.alloc(&b->partial, (size_t)b->P * m_pad));
     STAG_TRY(ws.alloc(&b->bpart, (size_t)b->P * m_pad));
     STAG_TRY(ws.alloc(&b->S1, (size_t)m_pad));
+    STAG_TRY(ws.alloc(&b->T, (size_t)m_pad));
     STAG_TRY(ws.alloc(&b->Ss, (size_t)m_pad));
     STAG_TRY(ws.alloc(&b->Bs, (size_t)m_pad));
     STAG_TRY(ws.alloc(&b->cflag, (size_t)b->P * ceil_div(m_pad, 256)));
@@ -904,8 +950,9 @@ stag_status run_centred(const float* X, int64_t n, const float* Q, int64_t m, in
 
 // Adaptive fp16 form: the single-product centred pass over all pairs with
 // the queries in group order, then the fp16 split form over the (chunk,
-// 256-query tile) pairs where some query's first-pass bound share exceeds
-// kAdaptiveShare / P of its sum, the reduction in sorted order with the
+// 256-query tile) pairs where some query's first-pass bound numerator lies
+// above the part of its budget, kAdaptiveShare of its sum, that its smaller
+// numerators fill (adaptive_budget), the reduction in sorted order with the
 // underflow rescue in the split form, and the results back to the query rows.
 // First an estimate: the single-product pass and the selection on every
 // stride-th 128-query tile (about kAdaptiveSamples of them), read back with
@@ -945,12 +992,12 @@ stag_status run_adaptive(const float* X, int64_t n, const float* Q, int64_t m, i
     e.fold_alpha = 1;
     STAG_TRY(launch_exact_tiles(xo, qo, b.partial, e, st));
     ScopedTimer tm("kde_adaptive_select", st);
-    hipLaunchKernelGGL(sum_partials, dim3((unsigned)ceil_div(m_pad, 256)), dim3(256), 0, st, b.partial, b.P, m_pad,
-                       b.S1);
-    STAG_TRY(check_launch("sum_partials"));
+    hipLaunchKernelGGL(adaptive_budget, dim3((unsigned)ceil_div(m_pad, 256)), dim3(256), 0, st, b.partial, b.bpart,
+                       b.P, m_pad, m, kAdaptiveShare, qmask, b.S1, b.T);
+    STAG_TRY(check_launch("adaptive_budget"));
     STAG_TRY(zero_async(b.cflag, (size_t)b.P * n_qt256, st));
     hipLaunchKernelGGL(adaptive_flags, dim3((unsigned)ceil_div(m, 256), (unsigned)b.P), dim3(256), 0, st, b.bpart,
-                       b.S1, m_pad, m, n_qt256, kAdaptiveShare / b.P, qmask, b.cflag);
+                       b.T, m_pad, m, n_qt256, qmask, b.cflag);
     return check_launch("adaptive_flags");
   };
   const int n_qt128 = (int)(m_pad / kBQ);
