@@ -15,8 +15,8 @@
 //                     SplitMix64 counter stream (tag "CNTR"), taken relative
 //                     to seed 0's row r
 //   assign_seeds      every row's nearest seed (largest (x - r).(s - r) -
-//                     ||s - r||^2/2 on the fp32 matrix cores, ties to the
-//                     lower seed)
+//                     ||s - r||^2/2, the product in fp16 on the matrix
+//                     cores, ties to the lower seed)
 //   label_hist        per 1024-row block, the rows of each seed
 //   scan_labels       per seed, the exclusive sum over blocks
 //   group_offsets     group k starts at sum_{k' < k} ceil32(count_k'), so
@@ -88,48 +88,60 @@ __global__ __launch_bounds__(256) void pick_seeds(const float* __restrict__ X, i
 }
 
 // Nearest seed of every row: the largest x.s - ||s||^2/2 over the seeds
-// (v_mfma_f32_32x32x2_f32, accumulators seeded with -||s||^2/2; 32 seeds as
-// the A operand staged in LDS, each wave's 32 rows as the B operand, lane
-// half h holding dimensions [h DP/2, (h+1) DP/2)), ties to the lower seed.
+// (one v_mfma_f32_32x32x16_f16 product of fl16(x - r) and fl16(s - r) per
+// 16 dimensions, accumulators seeded with -||s||^2/2; 32 seeds as the A
+// operand staged in LDS, each wave's 32 rows as the B operand in registers),
+// ties to the lower seed.  The fp16 roundings can send a row whose two
+// nearest seeds lie within about 2^-10 ||x - r|| ||s - r|| of each other to
+// the farther one: any assignment is valid (the centres and radii are
+// measured on the groups as formed), and this one is deterministic.
 template <int DP>
 __global__ __launch_bounds__(256) void assign_seeds(const float* __restrict__ X, int64_t n, int d,
                                                     const float* __restrict__ seeds, const float* __restrict__ hn,
                                                     const float* __restrict__ ref, int K_pad,
                                                     uint8_t* __restrict__ label) {
-  constexpr int H = DP / 2;
-  constexpr int LD = DP + 4;
-  __shared__ __attribute__((aligned(16))) float st[32 * LD];
+  constexpr int KS = DP / 16;
+  constexpr int LD = DP + 8;
+  __shared__ __attribute__((aligned(16))) unsigned short st[32 * LD];
   __shared__ float shn[32];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, r32 = lane & 31, h = lane >> 5;
   const int64_t row = (int64_t)blockIdx.x * 128 + wave * 32 + r32;
-  float bq[H];
+  u16x8 bq[KS];
 #pragma unroll
-  for (int k = 0; k < H; ++k) {
-    const int j = h * H + k;
-    bq[k] = (row < n && j < d) ? X[row * d + j] - ref[j] : 0.0f;
+  for (int s = 0; s < KS; ++s) {
+    u16x8 o;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int j = s * 16 + h * 8 + i;
+      o[i] = f16_rne((row < n && j < d) ? X[row * d + j] - ref[j] : 0.0f);
+    }
+    bq[s] = o;
   }
   float best = -HUGE_VALF;
   int bests = 0;
   for (int g = 0; g < K_pad / 32; ++g) {
     __syncthreads();
-    for (int v = tid; v < 32 * DP / 4; v += 256) {
-      const int r = (v * 4) / DP, c = (v * 4) % DP;
-      *reinterpret_cast<f32x4*>(&st[r * LD + c]) =
-          *reinterpret_cast<const f32x4*>(&seeds[((int64_t)g * 32 + r) * DP + c]);
+    for (int v = tid; v < 32 * DP / 8; v += 256) {
+      const int r = (v * 8) / DP, c = (v * 8) % DP;
+      const float* src = &seeds[((int64_t)g * 32 + r) * DP + c];
+      const f32x4 lo = *reinterpret_cast<const f32x4*>(src), hi = *reinterpret_cast<const f32x4*>(src + 4);
+      u16x8 o;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        o[i] = f16_rne(lo[i]);
+        o[4 + i] = f16_rne(hi[i]);
+      }
+      *reinterpret_cast<u16x8*>(&st[r * LD + c]) = o;
     }
     if (tid < 32) shn[tid] = hn[g * 32 + tid];
     __syncthreads();
     f32x16 acc;
 #pragma unroll
     for (int i = 0; i < 16; ++i) acc[i] = shn[8 * (i >> 2) + 4 * h + (i & 3)];
-    const float* arow = &st[r32 * LD + h * H];
 #pragma unroll
-    for (int k = 0; k < H; k += 4) {
-      const f32x4 a4 = *reinterpret_cast<const f32x4*>(arow + k);
-      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a4.x, bq[k], acc, 0, 0, 0);
-      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a4.y, bq[k + 1], acc, 0, 0, 0);
-      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a4.z, bq[k + 2], acc, 0, 0, 0);
-      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a4.w, bq[k + 3], acc, 0, 0, 0);
+    for (int s = 0; s < KS; ++s) {
+      const u16x8 a = *reinterpret_cast<const u16x8*>(&st[r32 * LD + s * 16 + h * 8]);
+      acc = mma16<STAG_FORM_FP16_SPLIT>(a, bq[s], acc);
     }
     // the lane's 16 seeds come in increasing order: strict > keeps the lower
 #pragma unroll
