@@ -106,6 +106,22 @@ struct BoundModel {
 // extra (underflow rescue): Gaussian, a further offset magnitude carried by
 // the accumulators (the shift |m_q|, in exponent units); exponential and
 // logistic, the shift ys of y = sqrt(-E) (terms up to y = 150 + ys count).
+// Sum of col[p * stride] over p = 0 .. P-1, added in increasing p (the loads
+// issued eight at a time, so that a thread does not wait on each in turn).
+__device__ inline double chunk_sum(const double* __restrict__ col, int P, int64_t stride) {
+  double s = 0.0;
+  int p = 0;
+  for (; p + 8 <= P; p += 8) {
+    double v[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) v[i] = col[(int64_t)(p + i) * stride];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) s += v[i];
+  }
+  for (; p < P; ++p) s += col[(int64_t)p * stride];
+  return s;
+}
+
 __host__ __device__ inline double relative_bound(const BoundModel& bm, double qn, double xm, double extra = 0.0) {
   const double ln2 = 0.69314718055994530942;
   const double cross = 2.0 * bm.la * sqrt(qn) * sqrt(xm);

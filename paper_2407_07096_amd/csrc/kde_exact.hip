@@ -148,8 +148,7 @@ __global__ void reduce_partials(const double* __restrict__ partial, int P, int64
                                 double* __restrict__ bound_out, int* __restrict__ flag, int* __restrict__ qtile_flag) {
   const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= m) return;
-  double s = 0.0;
-  for (int p = 0; p < P; ++p) s += partial[(int64_t)p * m_pad + q];
+  const double s = chunk_sum(partial + q, P, m_pad);
   if (flag && s < kRescueBelow) {
     flag[q] = 1;
     qtile_flag[q / kBQ] = 1;
@@ -171,11 +170,8 @@ __global__ void reduce_centred(const double* __restrict__ partial, const double*
                                double* __restrict__ bound_out, int* __restrict__ flag, int* __restrict__ qtile_flag) {
   const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= m) return;
-  double s = 0.0, b = 0.0;
-  for (int p = 0; p < P; ++p) {
-    s += partial[(int64_t)p * m_pad + q];
-    b += bpart[(int64_t)p * m_pad + q];
-  }
+  const double s = chunk_sum(partial + q, P, m_pad);
+  const double b = chunk_sum(bpart + q, P, m_pad);
   if (flag && s < kRescueBelow) {
     flag[q] = 1;
     qtile_flag[q / kBQ] = 1;
@@ -207,8 +203,7 @@ __global__ void adaptive_budget(const double* __restrict__ partial, const double
     T[q] = 0.0;
     return;
   }
-  double s = 0.0;
-  for (int p = 0; p < P; ++p) s += partial[(int64_t)p * m_pad + q];
+  const double s = chunk_sum(partial + q, P, m_pad);
   S1[q] = s;
   const double budget = share * s;
   const double inv = 1.0 / budget;
@@ -219,9 +214,8 @@ __global__ void adaptive_budget(const double* __restrict__ partial, const double
   float acc[kBudgetSteps];
 #pragma unroll
   for (int j = 0; j < kBudgetSteps; ++j) acc[j] = 0.0f;
-  for (int p = 0; p < P; ++p) {
-    const double v = bpart[(int64_t)p * m_pad + q];
-    if (!(v < budget)) continue;  // recomputed whatever the others hold (NaN as well)
+  auto count = [&](double v) {
+    if (!(v < budget)) return;  // recomputed whatever the others hold (NaN as well)
     const float r = (float)(v * inv);
     // every chunk with v < 4^-j budget is counted under candidate j (the
     // margin covers the roundings of r)
@@ -231,7 +225,16 @@ __global__ void adaptive_budget(const double* __restrict__ partial, const double
       acc[j] += r <= c ? r : 0.0f;
       c *= 0.25f;
     }
+  };
+  int p = 0;
+  for (; p + 8 <= P; p += 8) {  // loads eight at a time, counted in order
+    double v[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) v[i] = bpart[(int64_t)(p + i) * m_pad + q];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) count(v[i]);
   }
+  for (; p < P; ++p) count(bpart[(int64_t)p * m_pad + q]);
   double t = 0.0, c = 1.0;
 #pragma unroll
   for (int j = 0; j < kBudgetSteps; ++j) {
@@ -295,11 +298,26 @@ __global__ void reduce_adaptive(const double* __restrict__ partial, const double
   const double xm = __longlong_as_double((long long)*max_xnrm_bits);
   const double rs = relative_bound(bm, qnrm[q], xm);
   double s = 0.0, b = 0.0;
-  for (int p = 0; p < P; ++p) {
-    const double v = partial[(int64_t)p * m_pad + q];
+  auto add = [&](double v, uint8_t f, double w) {
     s += v;
-    b += cflag[(int64_t)p * n_qt256 + q / 256] ? v * rs : bpart[(int64_t)p * m_pad + q];
+    b += f ? v * rs : w;
+  };
+  const int64_t t = q / 256;
+  int p = 0;
+  for (; p + 8 <= P; p += 8) {  // loads eight at a time, added in order
+    double v[8], w[8];
+    uint8_t f[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      v[i] = partial[(int64_t)(p + i) * m_pad + q];
+      w[i] = bpart[(int64_t)(p + i) * m_pad + q];
+      f[i] = cflag[(int64_t)(p + i) * n_qt256 + t];
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) add(v[i], f[i], w[i]);
   }
+  for (; p < P; ++p)
+    add(partial[(int64_t)p * m_pad + q], cflag[(int64_t)p * n_qt256 + t], bpart[(int64_t)p * m_pad + q]);
   if (s < kRescueBelow) {
     flag[q] = 1;
     qtile_flag[q / kBQ] = 1;
@@ -570,8 +588,7 @@ __global__ void rescue_reduce(const double* __restrict__ partial, int P, int64_t
                               BoundModel bm, double* __restrict__ S_out, double* __restrict__ bound_out) {
   const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= m || !flag[q]) return;
-  double s = 0.0;
-  for (int p = 0; p < P; ++p) s += partial[(int64_t)p * m_pad + q];
+  const double s = chunk_sum(partial + q, P, m_pad);
   S_out[q] = s * exp2(shift[q]) * scale;
   if (bound_out) {
     const double xm = __longlong_as_double((long long)*max_xnrm_bits);
@@ -651,8 +668,7 @@ __global__ void rescue_reduce_y(const double* __restrict__ partial, int P, int64
                                 BoundModel bm, double* __restrict__ S_out, double* __restrict__ bound_out) {
   const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= m || !flag[q]) return;
-  double s = 0.0;
-  for (int p = 0; p < P; ++p) s += partial[(int64_t)p * m_pad + q];
+  const double s = chunk_sum(partial + q, P, m_pad);
   const double ys = (double)yshift[q];
   S_out[q] = s * exp2(-ys) * scale;
   if (bound_out) {

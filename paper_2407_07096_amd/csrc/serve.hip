@@ -64,12 +64,11 @@ __global__ void serve_reduce(const double* __restrict__ partial, const double* _
   }
   const int64_t local = row - segs[lo].row0;
   if (local < 0 || local >= segs[lo].m) return;
-  double s = 0.0, b = 0.0;
-  for (int p = 0; p < P; ++p) s += partial[(int64_t)p * m_pad + row];
+  const double s = chunk_sum(partial + row, P, m_pad);
   segs[lo].S[local] = s;
   if (segs[lo].B) {
     if (bpart) {
-      for (int p = 0; p < P; ++p) b += bpart[(int64_t)p * m_pad + row];
+      const double b = chunk_sum(bpart + row, P, m_pad);
       const double r = b / s;
       segs[lo].B[local] = s > 0.0 ? r + r * r + bm.c_tail : HUGE_VAL;
     } else {
