@@ -180,8 +180,13 @@ struct TileExtra {
   // cflag[chunk * ceil(m_pad / 256) + tile] != 0 run (the others return at
   // once, their partials not written)
   const uint8_t* cflag = nullptr;
-  // the adaptive form's estimate on sampled query tiles (a timer of its own)
+  // the adaptive form's estimate on sampled query tiles (a timer of its own);
+  // with qsel_n > 0 the centred fp16 tile launches only the workgroups that
+  // hold the 128-query tiles qsel[0 .. qsel_n) (at most kMaxSel of them)
   int sample = 0;
+  static constexpr int kMaxSel = 16;
+  int qsel_n = 0;
+  int qsel[kMaxSel] = {};
   // centred fp16 tile, Gaussian sums: a wave whose queries all have their
   // offset alpha in [-60, 0] for a group starts its accumulators from beta
   // alone and scales its tile sums by 2^alpha (a query's bits then depend on

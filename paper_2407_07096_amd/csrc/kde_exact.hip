@@ -1001,11 +1001,17 @@ stag_status run_adaptive(const float* X, int64_t n, const float* Q, int64_t m, i
   ex1.a = a;
   ex1.bpart = b.bpart;
   ex1.c_cent = (float)bm1.c_cent;
+  const int n_qt128 = (int)(m_pad / kBQ);
+  const int stride = std::max(1, n_qt128 / kAdaptiveSamples);
   auto first_pass = [&](const int* qmask) -> stag_status {
     TileExtra e = ex1;
     e.qtile_active = qmask;
     e.sample = qmask ? 1 : 0;
     e.fold_alpha = 1;
+    if (qmask && ceil_div(n_qt128, stride) <= TileExtra::kMaxSel) {
+      // the sampled tiles (those mark_sample flags), launched alone
+      for (int t = 0; t < n_qt128; t += stride) e.qsel[e.qsel_n++] = t;
+    }
     STAG_TRY(launch_exact_tiles(xo, qo, b.partial, e, st));
     ScopedTimer tm("kde_adaptive_select", st);
     hipLaunchKernelGGL(adaptive_budget, dim3((unsigned)ceil_div(m_pad, 256)), dim3(256), 0, st, b.partial, b.bpart,
@@ -1016,8 +1022,6 @@ stag_status run_adaptive(const float* X, int64_t n, const float* Q, int64_t m, i
                        b.T, m_pad, m, n_qt256, qmask, b.cflag);
     return check_launch("adaptive_flags");
   };
-  const int n_qt128 = (int)(m_pad / kBQ);
-  const int stride = std::max(1, n_qt128 / kAdaptiveSamples);
   hipLaunchKernelGGL(mark_sample, dim3((unsigned)ceil_div(n_qt128, 256)), dim3(256), 0, st, b.qsample, n_qt128,
                      stride);
   STAG_TRY(check_launch("mark_sample"));

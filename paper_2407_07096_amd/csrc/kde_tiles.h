@@ -986,8 +986,11 @@ __global__ __launch_bounds__(256, 2) void tile_h1c(const unsigned short* __restr
   __shared__ __attribute__((aligned(16))) float tbeta[2][kTileRows];
 
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, r32 = lane & 31, h = lane >> 5;
-  const int qtile = blockIdx.x % n_qtw;
-  const int chunk = blockIdx.x / n_qtw;
+  // with a tile list (qsel holds workgroup tiles here), blockIdx.x runs over
+  // (list entry, chunk)
+  const int nw = ex.qsel_n > 0 ? ex.qsel_n : n_qtw;
+  const int qtile = ex.qsel_n > 0 ? ex.qsel[blockIdx.x % nw] : (int)(blockIdx.x % nw);
+  const int chunk = blockIdx.x / nw;
   const int64_t col0 = (int64_t)qtile * (4 * QW) + wave * QW;
   if (ex.qtile_active) {
     // the workgroup's 128-query tiles (NB of them)
@@ -1448,9 +1451,23 @@ stag_status launch_tile_h1c(const Operands& xo, const Operands& qo, float la, in
                             const TileExtra& ex, hipStream_t st) {
   ScopedTimer tm(rescue_timer(ex, "kde_tile_fp16c"), st);
   const int n_qtw = (int)ceil_div(qo.rows_pad, 128 * kH1cBlocks<DP>);
-  hipLaunchKernelGGL((tile_h1c<DP, MODE>), dim3((unsigned)((int64_t)n_qtw * P)), dim3(256), 0, st,
+  // a list of 128-query tiles becomes the list of the workgroup tiles that
+  // hold them (ascending, each once); the mask still marks the active ones
+  TileExtra e = ex;
+  int nw = n_qtw;
+  if (ex.qsel_n > 0) {
+    int n = 0;
+    for (int i = 0; i < ex.qsel_n; ++i) {
+      const int w = ex.qsel[i] / kH1cBlocks<DP>;
+      if (w < n_qtw && (n == 0 || e.qsel[n - 1] < w)) e.qsel[n++] = w;
+    }
+    e.qsel_n = n;
+    nw = n;
+  }
+  if (nw == 0) return STAG_OK;
+  hipLaunchKernelGGL((tile_h1c<DP, MODE>), dim3((unsigned)((int64_t)nw * P)), dim3(256), 0, st,
                      static_cast<const unsigned short*>(xo.part[0]), xo.off, xo.tgroup, xo.centre, xo.radius,
-                     xo.n_pad_dev, (const float*)qo.part[0], qo.off, la, n_qtw, qo.rows_pad, partial, ex);
+                     xo.n_pad_dev, (const float*)qo.part[0], qo.off, la, n_qtw, qo.rows_pad, partial, e);
   return check_launch("tile_h1c");
 }
 
