@@ -186,10 +186,12 @@ stag_status stag_kde_exact(const float* X, int64_t n, const float* Q, int64_t m,
  *   - every temporary (prepared operands, partial sums, rescue buffers) lives
  *     in a 128 MiB scratch array that the library holds on each device it
  *     runs on until the process ends; a call whose temporaries do not fit is
- *     STAG_E_INVAL before any launch (they take about
+ *     STAG_E_INVAL before any launch (the split forms take about
  *     (n + m) * d_pad * 4 bytes of split operands (d_pad: d rounded up to 16,
  *     32, 64, 96 ... 256) plus 24 * m_pad * ceil(n / 4096) bytes of partial
- *     sums, m_pad = m rounded up to 128);
+ *     sums, m_pad = m rounded up to 128; FP16_ADAPTIVE about (1.5 n + 2 m)
+ *     * d_pad * 4 plus 32 * m_pad * ceil(n / 4096) bytes; the error message
+ *     states the call's exact need);
  *   - no hipMalloc, hipFree or allocating routine is called; the first call
  *     on a device looks up that device's scratch address once;
  *   - FP16_ADAPTIVE reads its estimate back (one synchronisation of
