@@ -187,6 +187,7 @@ struct TileExtra {
   static constexpr int kMaxSel = 16;
   int qsel_n = 0;
   int qsel[kMaxSel] = {};
+  int h1c_chunks = 0;  // chunks of the centred fp16 tile's grid (set by its launcher)
   // centred fp16 tile, Gaussian sums: a wave whose queries all have their
   // offset alpha in [-60, 0] for a group starts its accumulators from beta
   // alone and scales its tile sums by 2^alpha (a query's bits then depend on

@@ -965,6 +965,28 @@ __device__ inline float h1c_bound_factor(float sqt, float R, float qoff, float l
 template <int DP>
 constexpr int kH1cBlocks = DP <= 128 ? 2 : 1;  // 32-query blocks per wave
 
+// XCD-aware order of the (query tile, chunk) workgroups of the centred fp16
+// tile.  Workgroup b runs on XCD b % 8 (the dispatcher deals workgroups to
+// the 8 XCDs in turn); XCD x owns the query tiles [x Qx, (x+1) Qx), Qx =
+// ceil(nq / 8), and takes them in windows of kWinQ tiles, each window over
+// all P chunks with the window's tiles innermost: the window's query rows
+// (kWinQ x 256 x d_pad x 4 bytes, 2 MB at d = 128) stay in that XCD's L2
+// while the chunks stream past, instead of every workgroup fetching its
+// query rows again.  Grid = 8 Qx P; every (tile, chunk) pair has exactly one
+// workgroup, and those past the last tile (qtile >= nq) return at once.
+constexpr int kWinQ = 16;
+__device__ inline void xcd_tile(int64_t b, int nq, int P, int* qtile, int* chunk) {
+  const int Qx = (nq + 7) / 8;
+  const int x = (int)(b % 8);
+  const int64_t j = b / 8;  // < Qx P
+  const int64_t per = (int64_t)kWinQ * P;
+  const int w = (int)(j / per);
+  const int64_t r = j - (int64_t)w * per;
+  const int wq = min(kWinQ, Qx - w * kWinQ);  // the window's width (the last may be narrower)
+  *chunk = (int)(r / wq);
+  *qtile = x * Qx + w * kWinQ + (int)(r % wq);
+}
+
 template <int DP, int MODE>
 __global__ __launch_bounds__(256, 2) void tile_h1c(const unsigned short* __restrict__ Xh,
                                                    const float* __restrict__ beta, const int* __restrict__ tgroup,
@@ -987,10 +1009,15 @@ __global__ __launch_bounds__(256, 2) void tile_h1c(const unsigned short* __restr
 
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, r32 = lane & 31, h = lane >> 5;
   // with a tile list (qsel holds workgroup tiles here), blockIdx.x runs over
-  // (list entry, chunk)
-  const int nw = ex.qsel_n > 0 ? ex.qsel_n : n_qtw;
-  const int qtile = ex.qsel_n > 0 ? ex.qsel[blockIdx.x % nw] : (int)(blockIdx.x % nw);
-  const int chunk = blockIdx.x / nw;
+  // (list entry, chunk); else the XCD-aware order of xcd_tile
+  int qtile, chunk;
+  if (ex.qsel_n > 0) {
+    qtile = ex.qsel[blockIdx.x % ex.qsel_n];
+    chunk = blockIdx.x / ex.qsel_n;
+  } else {
+    xcd_tile(blockIdx.x, n_qtw, (int)ex.h1c_chunks, &qtile, &chunk);
+    if (qtile >= n_qtw) return;
+  }
   const int64_t col0 = (int64_t)qtile * (4 * QW) + wave * QW;
   if (ex.qtile_active) {
     // the workgroup's 128-query tiles (NB of them)
@@ -1465,6 +1492,9 @@ stag_status launch_tile_h1c(const Operands& xo, const Operands& qo, float la, in
     nw = n;
   }
   if (nw == 0) return STAG_OK;
+  // the full grid in the XCD-aware order: 8 ceil(n_qtw / 8) P workgroups
+  if (ex.qsel_n == 0) nw = 8 * (int)ceil_div(n_qtw, 8);
+  e.h1c_chunks = P;
   hipLaunchKernelGGL((tile_h1c<DP, MODE>), dim3((unsigned)((int64_t)nw * P)), dim3(256), 0, st,
                      static_cast<const unsigned short*>(xo.part[0]), xo.off, xo.tgroup, xo.centre, xo.radius,
                      xo.n_pad_dev, (const float*)qo.part[0], qo.off, la, n_qtw, qo.rows_pad, partial, e);
