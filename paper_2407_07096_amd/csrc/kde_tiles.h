@@ -972,8 +972,11 @@ constexpr int kH1cBlocks = DP <= 128 ? 2 : 1;  // 32-query blocks per wave
 // all P chunks with the window's tiles innermost: the window's query rows
 // (kWinQ x 256 x d_pad x 4 bytes, 2 MB at d = 128) stay in that XCD's L2
 // while the chunks stream past, instead of every workgroup fetching its
-// query rows again.  Grid = 8 Qx P; every (tile, chunk) pair has exactly one
-// workgroup, and those past the last tile (qtile >= nq) return at once.
+// query rows again; the data (fp16, one part) are fetched once per window.
+// (The split tiles keep the chunk-major order: their data are twice the
+// bytes, and fetching them once per window cost more L2 misses than the
+// query rows saved.)  Grid = 8 Qx P; every (tile, chunk) pair has exactly
+// one workgroup, and those past the last tile (qtile >= nq) return at once.
 constexpr int kWinQ = 16;
 __device__ inline void xcd_tile(int64_t b, int nq, int P, int* qtile, int* chunk) {
   const int Qx = (nq + 7) / 8;
