@@ -20,6 +20,9 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
+// Word 3 of a raw buffer resource on gfx9-family GPUs (gfx950 included):
+// 32-bit data format, no swizzle; loads past num_records return 0.
+constexpr int kBufferWord3 = 0x00020000;
 
 constexpr double kLog2e = 1.4426950408889634074;
 constexpr int kTileRows = 32;
@@ -1121,13 +1124,26 @@ __global__ __launch_bounds__(256, 2) void tile_h1c(const unsigned short* __restr
     }
   };
 
+  // The chunk's rows and offsets through buffer resources based at the
+  // chunk (range-checked loads; the lane's byte offsets are fixed, the
+  // tile's is a scalar, so that staging a tile takes no address arithmetic)
+  const int64_t rows_left = min((int64_t)kChunkRows, n_pad - row0);
+  const __amdgpu_buffer_rsrc_t xr = __builtin_amdgcn_make_buffer_rsrc(
+      (void*)(Xh + row0 * DP), (short)0, (int)(rows_left * DP * 2), kBufferWord3);
+  const __amdgpu_buffer_rsrc_t br =
+      __builtin_amdgcn_make_buffer_rsrc((void*)(beta + row0), (short)0, (int)(rows_left * 4), kBufferWord3);
+  int voff[NLD];
+#pragma unroll
+  for (int k = 0; k < NLD; ++k) voff[k] = min(tid + 256 * k, NV - 1) * 16;
+  const int boff = (tid & 31) * 4;
   u16x8 stage[NLD];
   float sbeta;
   auto gload = [&](int t) {
-    const u16x8* srcp = reinterpret_cast<const u16x8*>(Xh + (row0 + (int64_t)t * kTileRows) * DP);
+    const int so = t * kTileRows * DP * 2;
 #pragma unroll
-    for (int k = 0; k < NLD; ++k) stage[k] = srcp[min(tid + 256 * k, NV - 1)];
-    sbeta = beta[row0 + (int64_t)t * kTileRows + (tid & 31)];
+    for (int k = 0; k < NLD; ++k)
+      stage[k] = __builtin_bit_cast(u16x8, __builtin_amdgcn_raw_buffer_load_b128(xr, voff[k], so, 0));
+    sbeta = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(br, boff, t * kTileRows * 4, 0));
   };
   auto lstore = [&](int buf) {
 #pragma unroll
