@@ -655,16 +655,30 @@ __global__ __launch_bounds__(256, 2) void tile_split(
   const int64_t rem = (n_pad - row0) / kTileRows;
   const int ntiles = (int)(rem < kChunkRows / kTileRows ? rem : kChunkRows / kTileRows);
 
+  // the chunk's rows and offsets through buffer resources based at the chunk
+  // (as in the centred tile: no per-tile address arithmetic)
+  const int64_t rows_left = min((int64_t)kChunkRows, n_pad - row0);
+  __amdgpu_buffer_rsrc_t xr[NP];
+#pragma unroll
+  for (int p = 0; p < NP; ++p)
+    xr[p] = __builtin_amdgcn_make_buffer_rsrc((void*)(Xpp[p] + row0 * DP), (short)0, (int)(rows_left * DP * 2),
+                                              kBufferWord3);
+  const __amdgpu_buffer_rsrc_t br =
+      __builtin_amdgcn_make_buffer_rsrc((void*)(Xoff + row0), (short)0, (int)(rows_left * 4), kBufferWord3);
+  int voff[NLD];
+#pragma unroll
+  for (int k = 0; k < NLD; ++k) voff[k] = min(tid + 256 * k, NV - 1) * 16;
+  const int boff = (tid & 31) * 4;
   u16x8 stage[NP][NLD];
   float sbeta;
   auto gload = [&](int t) {
-    const int64_t base = (row0 + (int64_t)t * kTileRows) * DP;
+    const int so = t * kTileRows * DP * 2;
 #pragma unroll
     for (int p = 0; p < NP; ++p)
 #pragma unroll
       for (int k = 0; k < NLD; ++k)
-        stage[p][k] = reinterpret_cast<const u16x8*>(Xpp[p] + base)[min(tid + 256 * k, NV - 1)];
-    sbeta = Xoff[row0 + (int64_t)t * kTileRows + (tid & 31)];
+        stage[p][k] = __builtin_bit_cast(u16x8, __builtin_amdgcn_raw_buffer_load_b128(xr[p], voff[k], so, 0));
+    sbeta = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(br, boff, t * kTileRows * 4, 0));
   };
   auto lstore = [&](int buf) {
 #pragma unroll
@@ -807,16 +821,30 @@ __global__ __launch_bounds__(256, 2) void tile_split_w64(
   const int ntiles = (int)(rem < kChunkRows / kTileRows ? rem : kChunkRows / kTileRows);
 
   const unsigned short* Xpp[2] = {X0, X1};
+  // the chunk's rows and offsets through buffer resources based at the chunk
+  // (as in the centred tile: no per-tile address arithmetic)
+  const int64_t rows_left = min((int64_t)kChunkRows, n_pad - row0);
+  __amdgpu_buffer_rsrc_t xr[NP];
+#pragma unroll
+  for (int p = 0; p < NP; ++p)
+    xr[p] = __builtin_amdgcn_make_buffer_rsrc((void*)(Xpp[p] + row0 * DP), (short)0, (int)(rows_left * DP * 2),
+                                              kBufferWord3);
+  const __amdgpu_buffer_rsrc_t br =
+      __builtin_amdgcn_make_buffer_rsrc((void*)(Xoff + row0), (short)0, (int)(rows_left * 4), kBufferWord3);
+  int voff[NLD];
+#pragma unroll
+  for (int k = 0; k < NLD; ++k) voff[k] = min(tid + 256 * k, NV - 1) * 16;
+  const int boff = (tid & 31) * 4;
   u16x8 stage[NP][NLD];
   float sbeta;
   auto gload = [&](int t) {
-    const int64_t base = (row0 + (int64_t)t * kTileRows) * DP;
+    const int so = t * kTileRows * DP * 2;
 #pragma unroll
     for (int p = 0; p < NP; ++p)
 #pragma unroll
       for (int k = 0; k < NLD; ++k)
-        stage[p][k] = reinterpret_cast<const u16x8*>(Xpp[p] + base)[min(tid + 256 * k, NV - 1)];
-    sbeta = Xoff[row0 + (int64_t)t * kTileRows + (tid & 31)];
+        stage[p][k] = __builtin_bit_cast(u16x8, __builtin_amdgcn_raw_buffer_load_b128(xr[p], voff[k], so, 0));
+    sbeta = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(br, boff, t * kTileRows * 4, 0));
   };
   auto lstore = [&](int buf) {
 #pragma unroll
