@@ -129,6 +129,31 @@ def test_normalize_and_order(stag, orc):
     assert np.all(rel_err(Sr, ref[::-1]) <= Br)
 
 
+@pytest.mark.parametrize("n,m,d,a", [(20000, 2000, 64, 0.01), (20000, 2000, 64, 0.05), (40000, 1024, 128, 0.005),
+                                     (9000, 300, 64, 1.0)])
+def test_budget_guarantee(stag, n, m, d, a):
+    """The chunks left to the single product carry at most 1e-5 of the first
+    pass's sum in bound numerators, so the relative numerator r of every
+    adaptive result is at most the split form's bound for the same query plus
+    about 1e-5, and the reported bound is r + r^2 + (fp32 tail, 3.3e-7) (both
+    bounds read back from the library; the first pass's sum and the final one
+    differ by far less than the 1 % allowed here)."""
+    import torch
+    X, Q, _ = synth.config_points(2, n=n, m=m) if d == 64 else synth.config_points(3, n=n, m=m)
+    announce(f"fp16 adaptive budget n={n} m={m} d={d} a={a}")
+    Xd, Qd = to_dev(X), to_dev(Q)
+    _, Ba = stag.kde_exact(Xd, Qd, a, form=FORM, return_bound=True)
+    _, Bs = stag.kde_exact(Xd, Qd, a, form="fp16_split", return_bound=True)
+    torch.cuda.synchronize()
+    Ba, Bs = Ba.cpu().numpy(), Bs.cpu().numpy()
+    ok = np.isfinite(Bs)
+    g = 1.01 * Bs[ok] + 1.01e-5
+    excess = Ba[ok] - (g + g * g + 4e-7)
+    print(f"[measured] fp16 adaptive budget a={a}: max bound {Ba[ok].max():.3e} (split {Bs[ok].max():.3e}), "
+          f"largest excess over the guarantee {excess.max():.3e}", flush=True)
+    assert np.all(excess <= 0.0), excess.max()
+
+
 def test_config3_full_size_sampled(stag, orc):
     """n = 2,000,000, m = 200,000, d = 128, a = 0.01: full launch, oracle on
     the same 1,000 sampled queries as the other forms: within the bound and
