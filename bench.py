@@ -381,7 +381,8 @@ def lsh_defaults_run(stag, torch, dev, lib, buf, X, Q, Xd, Qd, a: float, m_sub: 
 def c4_run(stag, torch, dev, lib, buf, s_lsh: dict, n_nodes_law: int = 256):
     """Edge sampling of the 784-dimensional sparse workload (n = 70,000,
     entries 0 w.p. 0.8 else U[0,1], a = 1e-3, ceil(log2 n) = 17 draws per
-    node) in exact mode (fp32 tiles; d > 256) and CKNS mode.  Reported: times,
+    node) in exact mode (the wide fp32 tile, and the wide fp16 split tile) and
+    CKNS mode.  Reported: times,
     draws/s, the CKNS-mode degree estimates against the exact degrees, and
     total-variation distances between histograms of the drawn edges' squared
     distances: CKNS mode vs exact mode, and each mode vs the exact law of
@@ -395,13 +396,15 @@ def c4_run(stag, torch, dev, lib, buf, s_lsh: dict, n_nodes_law: int = 256):
     out = {"workload": f"edge sampling n={n}, d={d} (80% zeros, else U[0,1]), a={a}, "
                        f"{stag.draws_per_node(n)} draws/node", "modes": {}}
     graphs = {}
-    for mode, kw in (("exact", dict(form="fp32")), ("lsh", dict(eps=0.5, lsh_seed=3004, **s_lsh))):
+    for key, mode, kw in (("exact", "exact", dict(form="fp32")),
+                          ("exact_fp16_split", "exact", dict(form="fp16_split")),
+                          ("lsh", "lsh", dict(eps=0.5, lsh_seed=3004, **s_lsh))):
         stag.simgraph_sample(Xd, a, mode=mode, seed=4004, **kw)  # warm-up
         with Timers(lib, buf, torch) as tm:
             g = stag.simgraph_sample(Xd, a, mode=mode, seed=4004, **kw)
-        graphs[mode] = g
-        out["modes"][mode] = {"ms": tm.wall_s * 1e3, "draws_per_s": n * stag.draws_per_node(n) / tm.wall_s,
-                              "kernels_ms": {k: v[1] for k, v in tm.t.items()}}
+        graphs[key] = g
+        out["modes"][key] = {"ms": tm.wall_s * 1e3, "draws_per_s": n * stag.draws_per_node(n) / tm.wall_s,
+                             "kernels_ms": {k: v[1] for k, v in tm.t.items()}}
     out["modes"]["lsh"]["params"] = dict(eps=0.5, **s_lsh)
 
     def drawn_d2(g):
@@ -414,7 +417,7 @@ def c4_run(stag, torch, dev, lib, buf, s_lsh: dict, n_nodes_law: int = 256):
             vals.append(((xs.double() - xd.double()) ** 2).sum(1))
         return torch.cat(vals).cpu().numpy()
 
-    de, dl = drawn_d2(graphs["exact"]), drawn_d2(graphs["lsh"])
+    de, dl, dh = drawn_d2(graphs["exact"]), drawn_d2(graphs["lsh"]), drawn_d2(graphs["exact_fp16_split"])
     rng = np.random.default_rng(4104)
     nodes = rng.choice(n, size=n_nodes_law, replace=False)
     lw, ld = [], []
@@ -434,12 +437,17 @@ def c4_run(stag, torch, dev, lib, buf, s_lsh: dict, n_nodes_law: int = 256):
         h, _ = np.histogram(np.clip(v, lo, hi), bins=bins, weights=w)
         return h / h.sum()
 
-    he, hl, hlaw = hist(de), hist(dl), hist(ld, lw)
+    he, hl, hh, hlaw = hist(de), hist(dl), hist(dh), hist(ld, lw)
     deg_e, deg_l = graphs["exact"][3].cpu().numpy(), graphs["lsh"][3].cpu().numpy()
     drel = np.abs(deg_l - deg_e) / deg_e
     out["tv_drawn_d2_lsh_vs_exact"] = float(0.5 * np.abs(hl - he).sum())
     out["tv_drawn_d2_exact_vs_law"] = float(0.5 * np.abs(he - hlaw).sum())
     out["tv_drawn_d2_lsh_vs_law"] = float(0.5 * np.abs(hl - hlaw).sum())
+    out["tv_drawn_d2_exact_fp16_split_vs_law"] = float(0.5 * np.abs(hh - hlaw).sum())
+    gs, gf = graphs["exact_fp16_split"], graphs["exact"]
+    out["exact_fp16_split_vs_fp32"] = {
+        "same_draws": float((gs[1] == gf[1]).double().mean().item()),
+        "max_rel_degree_diff": float((torch.abs(gs[3] - gf[3]) / gf[3]).max().item())}
     out["lsh_degree_rel_err"] = {"median": float(np.median(drel)), "p90": float(np.quantile(drel, 0.9)),
                                  "max": float(drel.max())}
     out["histogram"] = f"64 bins of ||x_i - x_j||^2 over [{lo:.1f}, {hi:.1f}]; law from {n_nodes_law} nodes' exact rows"

@@ -129,8 +129,9 @@ double stag_e2lsh_collision_probability(double c, int32_t K, int32_t L);
  * m_q (a max pass and a second pass over the 128-query tiles that hold
  * such queries; S = sum * 2^m_q, its bound widened by |m_q|); a result below
  * the fp64 range is 0.  Without such queries the two passes end at once.
- * Limits: 1 <= d <= 1024 (d > 256: fp32 form only; STAG_E_UNSUPPORTED
- * otherwise), n, m >= 1, n*d and m*d < 2^31.  FP16_SPLIT additionally needs |x_j| and
+ * Limits: 1 <= d <= 1024 (d > 256: FP32, FP16_SPLIT or BF16_SPLIT, with
+ * STAG_FORM_AUTO taking FP32; STAG_E_UNSUPPORTED otherwise), n, m >= 1,
+ * n*d and m*d < 2^31.  FP16_SPLIT additionally needs |x_j| and
  * |2a log2(e) q_j| below 65504; out-of-range inputs give a NaN result.
  * FP16_CENTRED (Gaussian kernel, d <= 256): the rows of X are grouped as for
  * the fp32 form (at most 256 groups from seeded seed rows, each group padded
@@ -406,7 +407,8 @@ stag_status stag_kde_lsh(const float* X, int64_t n, const float* Q, int64_t m, i
  * s_i = mix(mix(mix(seed ^ 0x44524157) ^ i) ^ 0), inverting the cumulative
  * sum of the row in ascending j.
  *   STAG_SIMGRAPH_EXACT: kernel row sums from one exact tile pass in `form`
- *     (chunk and tile sums), the final 32 values recomputed in fp64.
+ *     (chunk and tile sums), the final 32 values recomputed in fp64; for
+ *     d > 256 the form is FP32, FP16_SPLIT or BF16_SPLIT.
  *   STAG_SIMGRAPH_LSH: rest_i is the CKNS estimate (eps, lsh params) of
  *     sum_{j != i} k_ij and the draw inverts the estimator's own terms (copy,
  *     level, table, bucket order): E[term of j] = k_ij.

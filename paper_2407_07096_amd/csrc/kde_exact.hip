@@ -829,8 +829,10 @@ stag_status check_exact_args(const char* fn, const float* X, int64_t n, const fl
     return fail(STAG_E_INVAL, "%s: STAG_FORM_AUTO needs a target eps > 0", fn);
   if (flags & ~(STAG_NORMALIZE | STAG_CHECK_FINITE)) return fail(STAG_E_INVAL, "%s: unknown flags 0x%x", fn, flags);
   if (d > 1024) return fail(STAG_E_UNSUPPORTED, "%s: d = %d > 1024 is not supported", fn, d);
-  if (d > 256 && form != STAG_FORM_FP32 && form != STAG_FORM_AUTO)
-    return fail(STAG_E_UNSUPPORTED, "%s: d = %d > 256 is supported by the fp32 form only", fn, d);
+  if (d > 256 && form != STAG_FORM_FP32 && form != STAG_FORM_AUTO && form != STAG_FORM_FP16_SPLIT &&
+      form != STAG_FORM_BF16_SPLIT)
+    return fail(STAG_E_UNSUPPORTED, "%s: d = %d > 256 is supported by the fp32, fp16 split and bf16 split forms only",
+                fn, d);
   if ((double)n * d >= 2147483648.0 || (double)m * d >= 2147483648.0)
     return fail(STAG_E_INVAL, "%s: n*d and m*d must be < 2^31", fn);
   const double at = kernel_tile_a(kernel, a);

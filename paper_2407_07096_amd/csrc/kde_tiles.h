@@ -1404,6 +1404,120 @@ __global__ __launch_bounds__(256) void tile_f32_wide(const float* __restrict__ X
   }
 }
 
+// ---------------------------------------------------------------------------
+// Wide rows (256 < d <= 1024), split forms (fp16 or bf16 hi + lo: three
+// products per pair).  The 32 queries of a workgroup sit in LDS as hi and lo
+// B operands ([2][32][DP+8] halfs, loaded once); each of the 4 waves takes
+// every 4th 32-row data tile of the chunk and streams its hi and lo A
+// operands from global memory, four k-steps of 16 at a time (register double
+// buffered); the accumulators start from the offsets alpha_q + beta_x.  The
+// epilogue is tile_epilogue in every mode, as in tile_f32_wide; per-wave fp64
+// sums are combined in wave order.  DP is a multiple of 64 (so of 4 k-steps).
+// ---------------------------------------------------------------------------
+template <int FORM, int MODE>
+__global__ __launch_bounds__(256) void tile_split_wide(const unsigned short* __restrict__ X0,
+                                                       const unsigned short* __restrict__ X1,
+                                                       const float* __restrict__ Xoff,
+                                                       const unsigned short* __restrict__ Q0,
+                                                       const unsigned short* __restrict__ Q1,
+                                                       const float* __restrict__ Qoff, int DP, int64_t n_pad,
+                                                       int n_qt32, int64_t m_pad, double* __restrict__ partial,
+                                                       TileExtra ex) {
+  static_assert(FORM == STAG_FORM_FP16_SPLIT || FORM == STAG_FORM_BF16_SPLIT, "hi + lo split forms");
+  extern __shared__ __attribute__((aligned(16))) unsigned short qsh[];
+  __shared__ double wsum[4][32];
+  const int LD = DP + 8;
+  const int KS = DP / 16;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, r32 = lane & 31, h = lane >> 5;
+  const int qtile = blockIdx.x % n_qt32;
+  const int chunk = blockIdx.x / n_qt32;
+  const int64_t col_base = (int64_t)qtile * 32;
+  const int64_t qi = col_base + r32;
+  if (ex.qtile_active && ex.qtile_active[col_base / kBQ] == 0) return;  // whole block
+  // B operands (hi, lo) into LDS
+  {
+    const int nv = 32 * DP / 8;
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+      const u16x8* src = reinterpret_cast<const u16x8*>((p == 0 ? Q0 : Q1) + col_base * DP);
+      for (int v = tid; v < nv; v += 256) {
+        const int r = (v * 8) / DP, c = (v * 8) % DP;
+        *reinterpret_cast<u16x8*>(&qsh[(p * 32 + r) * LD + c]) = src[v];
+      }
+    }
+  }
+  __syncthreads();
+  const float alpha = Qoff[qi];
+  const float ys = kShiftMode<MODE> ? ex.yshift[qi] : 0.0f;
+  const int64_t row0 = (int64_t)chunk * kChunkRows;
+  const int64_t rem = (n_pad - row0) / kTileRows;
+  const int ntiles = (int)(rem < kChunkRows / kTileRows ? rem : kChunkRows / kTileRows);
+  const unsigned short* bh = &qsh[r32 * LD + h * 8];
+  const unsigned short* bl = &qsh[(32 + r32) * LD + h * 8];
+  double acc = acc_init<MODE>();
+  __shared__ near_lds_t<MODE> near_lds;
+  NearRec nr = {near_lds, 0, false};
+  for (int t = wave; t < ntiles; t += 4) {
+    const int64_t rb = row0 + (int64_t)t * kTileRows;
+    // k-step s of row rb + r32, lane half h: dimensions [16 s + 8 h, +8)
+    const u16x8* ah = reinterpret_cast<const u16x8*>(X0 + (rb + r32) * DP) + h;
+    const u16x8* al = reinterpret_cast<const u16x8*>(X1 + (rb + r32) * DP) + h;
+    f32x16 c;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const f32x4 bv = *reinterpret_cast<const f32x4*>(Xoff + rb + 8 * q + 4 * h);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) c[4 * q + i] = alpha + bv[i];
+    }
+    // blocks of four k-steps in three rotating register buffers: a block's
+    // loads are issued two blocks before its products
+    u16x8 bufh[3][4], bufl[3][4];
+    auto load = [&](int j, int kb) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        bufh[j][k] = ah[2 * (kb + k)];
+        bufl[j][k] = al[2 * (kb + k)];
+      }
+    };
+    auto products = [&](int j, int kb) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int s16 = (kb + k) * 16;
+        const u16x8 b_h = *reinterpret_cast<const u16x8*>(bh + s16);
+        const u16x8 b_l = *reinterpret_cast<const u16x8*>(bl + s16);
+        c = mma16<FORM>(bufh[j][k], b_h, c);
+        c = mma16<FORM>(bufh[j][k], b_l, c);
+        c = mma16<FORM>(bufl[j][k], b_h, c);
+      }
+    };
+    load(0, 0);
+    if (4 < KS) load(1, 4);
+    if (8 < KS) load(2, 8);
+    for (int kb = 0; kb < KS; kb += 12) {
+      products(0, kb);
+      if (kb + 12 < KS) load(0, kb + 12);
+      if (kb + 4 < KS) {
+        products(1, kb + 4);
+        if (kb + 16 < KS) load(1, kb + 16);
+      }
+      if (kb + 8 < KS) {
+        products(2, kb + 8);
+        if (kb + 20 < KS) load(2, kb + 20);
+      }
+    }
+    acc = acc_add<MODE>(acc, (double)tile_epilogue<MODE>(c, rb, col_base, r32, h, qi, ex, nullptr, false, &nr, t, ys));
+  }
+  if constexpr (MODE == kModeExponential) acc += near_finish(ex, nr, qi, h, row0, tid);
+  const double other = __shfl_down(acc, 32);
+  if (h == 0) wsum[wave][r32] = acc_add<MODE>(acc, other);
+  __syncthreads();
+  if (tid < 32) {
+    const double tot =
+        acc_add<MODE>(acc_add<MODE>(acc_add<MODE>(wsum[0][tid], wsum[1][tid]), wsum[2][tid]), wsum[3][tid]);
+    partial[(int64_t)chunk * m_pad + col_base + tid] = tot;
+  }
+}
+
 // Timer name of a launch: the underflow rescue's passes are timed apart from
 // the tiles they repeat.
 inline const char* rescue_timer(const TileExtra& ex, const char* name) {
@@ -1581,8 +1695,29 @@ stag_status launch_tiles(const Operands& xo, const Operands& qo, double* partial
       return fail(STAG_E_UNSUPPORTED, "centred data: Gaussian sums only");
     }
   }
+  if (xo.dp > 256 && (xo.form == STAG_FORM_FP16_SPLIT || xo.form == STAG_FORM_BF16_SPLIT)) {
+    const int n_qt32 = (int)(qo.rows_pad / 32);
+    const size_t lds = (size_t)2 * 32 * (xo.dp + 8) * sizeof(unsigned short);
+    using U = const unsigned short*;
+    if (xo.form == STAG_FORM_FP16_SPLIT) {
+      STAG_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&tile_split_wide<STAG_FORM_FP16_SPLIT, MODE>),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+      ScopedTimer tm(rescue_timer(ex, "kde_tile_fp16x3_wide"), st);
+      hipLaunchKernelGGL((tile_split_wide<STAG_FORM_FP16_SPLIT, MODE>), dim3((unsigned)((int64_t)n_qt32 * P)),
+                         dim3(256), lds, st, (U)xo.part[0], (U)xo.part[1], xo.off, (U)qo.part[0], (U)qo.part[1],
+                         qo.off, xo.dp, xo.rows_pad, n_qt32, qo.rows_pad, partial, ex);
+    } else {
+      STAG_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&tile_split_wide<STAG_FORM_BF16_SPLIT, MODE>),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+      ScopedTimer tm(rescue_timer(ex, "kde_tile_bf16x3_wide"), st);
+      hipLaunchKernelGGL((tile_split_wide<STAG_FORM_BF16_SPLIT, MODE>), dim3((unsigned)((int64_t)n_qt32 * P)),
+                         dim3(256), lds, st, (U)xo.part[0], (U)xo.part[1], xo.off, (U)qo.part[0], (U)qo.part[1],
+                         qo.off, xo.dp, xo.rows_pad, n_qt32, qo.rows_pad, partial, ex);
+    }
+    return check_launch("tile_split_wide");
+  }
   if (xo.dp > 256) {
-    if (xo.form != STAG_FORM_FP32) return fail(STAG_E_UNSUPPORTED, "d > 256 needs the fp32 form");
+    if (xo.form != STAG_FORM_FP32) return fail(STAG_E_UNSUPPORTED, "d > 256 needs the fp32, fp16 split or bf16 split form");
     const int n_qt32 = (int)(qo.rows_pad / 32);
     const size_t lds = (size_t)32 * (xo.dp + 4) * sizeof(float);
     STAG_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&tile_f32_wide<MODE>),

@@ -289,7 +289,7 @@ extern "C" stag_status stag_simgraph_sample(const float* X, int64_t n, int32_t d
   if (kde_mode == STAG_SIMGRAPH_EXACT) {
     if (form < STAG_FORM_FP32 || form > STAG_FORM_BF16_SPLIT3)
       return fail(STAG_E_INVAL, "stag_simgraph_sample: unknown form %d", form);
-    if (exact_padded_dim(d) == 0 || (d > 256 && form != STAG_FORM_FP32))
+    if (exact_padded_dim(d) == 0 || (d > 256 && form == STAG_FORM_BF16_SPLIT3))
       return fail(STAG_E_UNSUPPORTED, "stag_simgraph_sample: d = %d not supported by this form", d);
     return sample_exact(X, n, d, a, form, s, seed, src_out, dst_out, w_out, deg_out, stream);
   }

@@ -64,7 +64,8 @@ def test_invalid_arguments_rejected_before_launch():
     assert st == _lib.STAG_E_INVAL and "a must be" in stag.last_error()
     st = lib.stag_kde_exact_kernel(fake, 10, fake, 10, 4, 2, 1e200, 0.0, 0, 0, fake, null, null)
     assert st == _lib.STAG_E_INVAL and "out of range" in stag.last_error()
-    st = lib.stag_kde_exact_kernel(fake, 10, fake, 10, 300, 1, 1.0, 0.0, 2, 0, fake, null, null)
+    # d > 256: fp32, fp16 split and bf16 split only (bf16 three-way is not)
+    st = lib.stag_kde_exact_kernel(fake, 10, fake, 10, 300, 1, 1.0, 0.0, 3, 0, fake, null, null)
     assert st == _lib.STAG_E_UNSUPPORTED
     # STAG_FORM_AUTO needs eps > 0; unknown forms and flags
     st = lib.stag_kde_exact(fake, 10, fake, 10, 4, 1.0, 0.0, 4, 0, fake, null, null)

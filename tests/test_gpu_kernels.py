@@ -77,7 +77,7 @@ def test_queries_on_data_points(stag, orc, kernel, form):
 
 
 @pytest.mark.parametrize("form,d", [("fp32", 64), ("fp16_split", 64), ("bf16_split", 64), ("bf16_split3", 64),
-                                    ("fp32", 300), ("fp32", 1024)])
+                                    ("fp32", 300), ("fp32", 1024), ("fp16_split", 300), ("fp16_split", 1024)])
 def test_exponential_near_pairs(stag, orc, form, d):
     # self-queries, queries a hair away from a data point, exact duplicates in
     # the data and points near a query across chunk boundaries (n > 4096)
@@ -127,7 +127,7 @@ def test_ragged_shapes(stag, orc, kernel, n, m, d):
     X = rng.normal(size=(n, d)).astype(np.float32)
     Q = (X[rng.integers(0, n, size=m)] + 0.3 * rng.normal(size=(m, d))).astype(np.float32)
     a = 1.0 / np.sqrt(d)
-    forms = ["fp32"] if d > 256 else ["fp32", "fp16_split"]
+    forms = ["fp32", "fp16_split"]
     for form in forms:
         announce(f"kernel={kernel} ragged n={n} m={m} d={d} form={form}")
         ref = orc.kde_kernel(X, Q, a, kernel)

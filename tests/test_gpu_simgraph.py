@@ -137,12 +137,13 @@ def test_exact_mode_subnormal_row(stag, orc, form):
     assert np.all(np.abs(w[e][same] - ow[e][same]) <= 5e-3 * ow[e][same])
 
 
-def test_exact_mode_wide_rows(stag, orc):
-    """d = 784 (the wide fp32 tile), sparse non-negative data, a = 1e-3."""
+@pytest.mark.parametrize("form", ["fp32", "fp16_split"])
+def test_exact_mode_wide_rows(stag, orc, form):
+    """d = 784 (the wide fp32 and split tiles), sparse non-negative data, a = 1e-3."""
     X = synth.sparse_uniform(3000, 784, 1004)
     a, s, seed = 1e-3, 12, 5
-    announce("simgraph exact n=3000 d=784")
-    src, dst, w, deg = _gpu(stag, X, a, s, mode="exact", form="fp32", seed=seed)
+    announce(f"simgraph exact n=3000 d=784 form={form}")
+    src, dst, w, deg = _gpu(stag, X, a, s, mode="exact", form=form, seed=seed)
     osrc, odst, ow, odeg, mg = orc.simgraph_exact(X, a, s, seed, return_margin=True)
     assert np.allclose(deg, odeg, rtol=1e-5)
     same = dst == odst
@@ -150,20 +151,26 @@ def test_exact_mode_wide_rows(stag, orc):
     _check_valid_draws(orc, X, a, s, seed, src, dst, np.nonzero(~same)[0], 1e-5)
 
 
-def test_exact_kde_wide_rows(stag, orc):
-    """Exact KDE through the wide fp32 tile (256 < d <= 1024) with ragged n, m."""
+@pytest.mark.parametrize("form", ["fp32", "fp16_split", "bf16_split"])
+def test_exact_kde_wide_rows(stag, orc, form):
+    """Exact KDE through the wide tiles (256 < d <= 1024) with ragged n, m:
+    within the bound, and within 1e-5 for fp32 and fp16 split."""
     import torch
     rng = np.random.default_rng(3)
-    for n, m, d in [(4100, 70, 784), (33, 5, 300), (5000, 129, 1024)]:
+    for n, m, d in [(4100, 70, 784), (33, 5, 300), (5000, 129, 1024), (4200, 300, 832)]:
         X = rng.uniform(0, 1, size=(n, d)).astype(np.float32) * (rng.uniform(size=(n, d)) > 0.8)
         Q = X[rng.integers(0, n, size=m)] + 0.01 * rng.normal(size=(m, d)).astype(np.float32)
         Q = Q.astype(np.float32)
-        announce(f"wide exact n={n} m={m} d={d}")
-        S, B = stag.kde_exact(to_dev(X), to_dev(Q), 1e-3, return_bound=True)
+        announce(f"wide exact n={n} m={m} d={d} form={form}")
+        S, B = stag.kde_exact(to_dev(X), to_dev(Q), 1e-3, form=form, return_bound=True)
         torch.cuda.synchronize()
         ref = orc.kde_exact(X, Q, 1e-3)
         err = np.abs(S.cpu().numpy() - ref) / ref
-        assert np.all(err <= B.cpu().numpy()) and err.max() <= 1e-5
+        print(f"[measured] wide {form} d={d}: max rel err {err.max():.3e}, max bound {B.cpu().numpy().max():.3e}",
+              flush=True)
+        assert np.all(err <= B.cpu().numpy())
+        if form != "bf16_split":
+            assert err.max() <= 1e-5
 
 
 def test_exact_mode_config4_full_sampled(stag, orc):
