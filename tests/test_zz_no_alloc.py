@@ -88,6 +88,18 @@ def test_noalloc_matches_allocating_call_twice(lib, orc, form):
     assert np.all(err <= B1)
 
 
+@pytest.mark.parametrize("form", ["fp32", "fp16_split"])
+def test_noalloc_wide_rows(lib, orc, form):
+    # d = 784: the wide tiles (queries staged in LDS, data rows streamed)
+    X = synth.sparse_uniform(3000, 784, 1004)
+    Q = np.ascontiguousarray(X[::30])
+    announce(f"noalloc wide n=3000 m={Q.shape[0]} d=784 form={form}")
+    S0, B0, S1, B1 = _both(lib, X, Q, 1e-3, form)
+    assert np.array_equal(S0, S1) and np.array_equal(B0, B1)
+    ref = orc.kde_exact(X, Q, 1e-3)
+    assert np.all(np.abs(S1 - ref) / ref <= B1)
+
+
 def test_noalloc_underflow_rescue(lib, orc):
     # queries far from the data take the rescue passes (max pass, shifted
     # offsets), whose buffers also live in the scratch
