@@ -151,6 +151,46 @@ def test_exact_mode_wide_rows(stag, orc, form):
     _check_valid_draws(orc, X, a, s, seed, src, dst, np.nonzero(~same)[0], 1e-5)
 
 
+@pytest.mark.parametrize("form", ["fp32", "fp16_split"])
+def test_exact_mode_wide_scalar_rows_rescue(stag, orc, form):
+    """d = 301 > 256 (draws sorted by tile before the row step) with rows
+    that are not a multiple of 4 (element-wise staging and differences),
+    n = 1501 (a ragged last tile) and one outlier whose row sum (~1e-100)
+    takes the underflow rescue (shifted exponents): every draw matches the
+    oracle's outside the tolerance band and is valid inside it."""
+    rng = np.random.default_rng(81)
+    d, a = 301, 0.005
+    main = rng.normal(size=(1500, d))
+
+    def log_rest(R):
+        x0 = np.zeros(d)
+        x0[0] = R
+        v = -a * ((main - x0) ** 2).sum(1)
+        return v.max() + np.log(np.exp(v - v.max()).sum())
+
+    lo, hi = 0.0, 1000.0
+    for _ in range(60):  # R with a row sum near 1e-100
+        mid = 0.5 * (lo + hi)
+        lo, hi = (mid, hi) if log_rest(mid) > np.log(1e-100) else (lo, mid)
+    x0 = np.zeros((1, d))
+    x0[0, 0] = lo
+    X = np.concatenate([main, x0]).astype(np.float32)
+    s, seed, tol = 9, 31, 1e-4
+    i = len(X) - 1
+    orest = np.sum(np.delete(orc.kernel_row(X, a, i), i))
+    assert 1e-110 < orest < 2.0 ** -60  # the rescue is exercised
+    announce(f"simgraph exact n={len(X)} d={d} scalar rows + rescue form={form}")
+    src, dst, w, deg = _gpu(stag, X, a, s, mode="exact", form=form, seed=seed)
+    osrc, odst, ow, odeg, mg = orc.simgraph_exact(X, a, s, seed, return_margin=True)
+    assert np.array_equal(src, osrc)
+    assert np.allclose(deg, odeg, rtol=1e-5)
+    assert np.all(dst >= 0) and np.all(dst != src)
+    same = dst == odst
+    assert np.all(same[mg > tol])
+    _check_valid_draws(orc, X, a, s, seed, src, dst, np.nonzero(~same)[0], tol)
+    assert np.all(np.abs(w[same] - ow[same]) <= 1e-4 * ow[same])
+
+
 @pytest.mark.parametrize("form", ["fp32", "fp16_split", "bf16_split"])
 def test_exact_kde_wide_rows(stag, orc, form):
     """Exact KDE through the wide tiles (256 < d <= 1024) with ragged n, m:
