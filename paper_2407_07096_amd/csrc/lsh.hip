@@ -409,13 +409,14 @@ struct WalkScratch {
 __device__ inline double screen_delta(int d) { return 2.0 * (double)(d + 3) * 0x1.0p-24; }
 
 // fp64 squared distance in the order the level test uses (fused, ascending
-// coordinates); the query row is wave-uniform (scalar loads).
+// coordinates); the query row is wave-uniform (scalar loads).  The candidate
+// row is read eight 16-byte pieces at a time, all eight loads issued before
+// their products, so that a lane has eight loads in flight instead of one
+// (same occupancy, 4 waves per SIMD, in the walk kernels).
 __device__ inline double dist2_f64(const float* __restrict__ qrow, const float* __restrict__ xrow, int d) {
   const float4* x4 = reinterpret_cast<const float4*>(xrow);
   double D = 0.0;
-  const int d4 = d >> 2;
-  for (int h4 = 0; h4 < d4; ++h4) {
-    const float4 xv = x4[h4];
+  auto piece = [&](const float4& xv, int h4) {
     double dl = (double)qrow[4 * h4] - (double)xv.x;
     D = __builtin_fma(dl, dl, D);
     dl = (double)qrow[4 * h4 + 1] - (double)xv.y;
@@ -424,7 +425,22 @@ __device__ inline double dist2_f64(const float* __restrict__ qrow, const float* 
     D = __builtin_fma(dl, dl, D);
     dl = (double)qrow[4 * h4 + 3] - (double)xv.w;
     D = __builtin_fma(dl, dl, D);
+  };
+  const int d4 = d >> 2;
+  int h4 = 0;
+  for (; h4 + 7 < d4; h4 += 8) {
+    const float4 x0 = x4[h4], x1 = x4[h4 + 1], x2 = x4[h4 + 2], x3 = x4[h4 + 3];
+    const float4 x5 = x4[h4 + 4], x6 = x4[h4 + 5], x7 = x4[h4 + 6], x8 = x4[h4 + 7];
+    piece(x0, h4);
+    piece(x1, h4 + 1);
+    piece(x2, h4 + 2);
+    piece(x3, h4 + 3);
+    piece(x5, h4 + 4);
+    piece(x6, h4 + 5);
+    piece(x7, h4 + 6);
+    piece(x8, h4 + 7);
   }
+  for (; h4 < d4; ++h4) piece(x4[h4], h4);
   for (int h = 4 * d4; h < d; ++h) {
     const double dl = (double)qrow[h] - (double)xrow[h];
     D = __builtin_fma(dl, dl, D);
@@ -432,12 +448,12 @@ __device__ inline double dist2_f64(const float* __restrict__ qrow, const float* 
   return D;
 }
 
+// fp32 squared distance of the screen (two accumulators, alternate
+// coordinates; the same eight-piece loads as dist2_f64).
 __device__ inline float dist2_f32(const float* __restrict__ qrow, const float* __restrict__ xrow, int d) {
   const float4* x4 = reinterpret_cast<const float4*>(xrow);
   float D0 = 0.0f, D1 = 0.0f;
-  const int d4 = d >> 2;
-  for (int h4 = 0; h4 < d4; ++h4) {
-    const float4 xv = x4[h4];
+  auto piece = [&](const float4& xv, int h4) {
     float dl = qrow[4 * h4] - xv.x;
     D0 = __builtin_fmaf(dl, dl, D0);
     dl = qrow[4 * h4 + 1] - xv.y;
@@ -446,7 +462,22 @@ __device__ inline float dist2_f32(const float* __restrict__ qrow, const float* _
     D0 = __builtin_fmaf(dl, dl, D0);
     dl = qrow[4 * h4 + 3] - xv.w;
     D1 = __builtin_fmaf(dl, dl, D1);
+  };
+  const int d4 = d >> 2;
+  int h4 = 0;
+  for (; h4 + 7 < d4; h4 += 8) {
+    const float4 x0 = x4[h4], x1 = x4[h4 + 1], x2 = x4[h4 + 2], x3 = x4[h4 + 3];
+    const float4 x5 = x4[h4 + 4], x6 = x4[h4 + 5], x7 = x4[h4 + 6], x8 = x4[h4 + 7];
+    piece(x0, h4);
+    piece(x1, h4 + 1);
+    piece(x2, h4 + 2);
+    piece(x3, h4 + 3);
+    piece(x5, h4 + 4);
+    piece(x6, h4 + 5);
+    piece(x7, h4 + 6);
+    piece(x8, h4 + 7);
   }
+  for (; h4 < d4; ++h4) piece(x4[h4], h4);
   for (int h = 4 * d4; h < d; ++h) {
     const float dl = qrow[h] - xrow[h];
     D0 = __builtin_fmaf(dl, dl, D0);
