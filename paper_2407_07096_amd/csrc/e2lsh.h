@@ -45,7 +45,19 @@ __device__ inline void chunk_sums(const double* xr, const float* __restrict__ xr
       for (int e = 0; e < KC; ++e) s[e] = __builtin_fma(xj, g8[j * 8 + e], s[e]);
     }
   } else {
-    for (int j = 0; j < dg; ++j) {
+    // while eight coordinates are in range, their loads are issued before
+    // their products (same chains)
+    int j = 0;
+    for (; j + 8 <= d; j += 8) {
+      float xv[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) xv[u] = xrow[j + u];
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+#pragma unroll
+        for (int e = 0; e < KC; ++e) s[e] = __builtin_fma((double)xv[u], g8[(j + u) * 8 + e], s[e]);
+    }
+    for (; j < dg; ++j) {
       const double xj = j < d ? (double)xrow[j] : 0.0;
 #pragma unroll
       for (int e = 0; e < KC; ++e) s[e] = __builtin_fma(xj, g8[j * 8 + e], s[e]);
@@ -71,7 +83,7 @@ __device__ inline uint64_t chunk_fold(uint64_t hkey, const double* xr, const flo
 // Bucket key of one table: K codes in chunks of up to 8 projections (G8 for
 // this table is [nch][dg][8], bl its K offsets), folded in code order.
 template <int DREG>
-__device__ inline uint64_t table_key(int l, const double* xr, const float* __restrict__ xrow, int d, int dg,
+__device__ __attribute__((always_inline)) inline uint64_t table_key(int l, const double* xr, const float* __restrict__ xrow, int d, int dg,
                                      const double* __restrict__ g8t, const double* __restrict__ bl, int K, int nch,
                                      int32_t* __restrict__ codes_row) {
   uint64_t hkey = mix64(kKeySalt ^ (uint64_t)(uint32_t)l);
