@@ -71,8 +71,7 @@ __device__ inline double tkernel(const float* __restrict__ xi, const float* __re
   double D = 0.0;
   if (vec4) {
     const float4* x4 = reinterpret_cast<const float4*>(xj);
-    for (int c = 0; c < d / 4; ++c) {
-      const float4 v = x4[c];
+    auto piece = [&](const float4& v, int c) {
       double t = (double)xi[4 * c] - (double)v.x;
       D = __dadd_rn(D, __dmul_rn(t, t));
       t = (double)xi[4 * c + 1] - (double)v.y;
@@ -81,7 +80,18 @@ __device__ inline double tkernel(const float* __restrict__ xi, const float* __re
       D = __dadd_rn(D, __dmul_rn(t, t));
       t = (double)xi[4 * c + 3] - (double)v.w;
       D = __dadd_rn(D, __dmul_rn(t, t));
+    };
+    // eight 16-byte pieces' loads issued before their products (same order)
+    const int d4 = d / 4;
+    int c = 0;
+    for (; c + 7 < d4; c += 8) {
+      float4 v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = x4[c + u];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) piece(v[u], c + u);
     }
+    for (; c < d4; ++c) piece(x4[c], c);
   } else {
     for (int c = 0; c < d; ++c) {
       const double t = (double)xi[c] - (double)xj[c];
