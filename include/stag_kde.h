@@ -408,7 +408,12 @@ stag_status stag_kde_lsh(const float* X, int64_t n, const float* Q, int64_t m, i
  * sum of the row in ascending j.
  *   STAG_SIMGRAPH_EXACT: kernel row sums from one exact tile pass in `form`
  *     (chunk and tile sums), the final 32 values recomputed in fp64; for
- *     d > 256 the form is FP32, FP16_SPLIT or BF16_SPLIT.
+ *     d > 256 the form is FP32, FP16_SPLIT or BF16_SPLIT.  Device workspace:
+ *     the fp32 sums of every 32-row tile of every row (about n^2 / 8 bytes)
+ *     and, for d > 256, where the draws are sorted by tile between the tile
+ *     and the row step, about 24 bytes per draw (n * s must then stay below
+ *     2^31, else STAG_E_UNSUPPORTED).  Which path runs does not change the
+ *     draws.
  *   STAG_SIMGRAPH_LSH: rest_i is the CKNS estimate (eps, lsh params) of
  *     sum_{j != i} k_ij and the draw inverts the estimator's own terms (copy,
  *     level, table, bucket order): E[term of j] = k_ij.
