@@ -401,6 +401,7 @@ struct WalkScratch {
   int64_t base[64];    // csr index of the query's bucket in each table
   uint32_t pre[64];    // exclusive prefix of the bucket sizes over tables
   int32_t ring[128];   // survivors of the fp32 screen, in candidate order
+  double ringD[128];   // their fp64 squared distances
 };
 
 // Relative error bound of the fp32 squared distance of d coordinates (one
@@ -408,60 +409,36 @@ struct WalkScratch {
 // roundoff 2^-24, doubled for margin).
 __device__ inline double screen_delta(int d) { return 2.0 * (double)(d + 3) * 0x1.0p-24; }
 
-// fp64 squared distance in the order the level test uses (fused, ascending
-// coordinates); the query row is wave-uniform (scalar loads).  The candidate
-// row is read eight 16-byte pieces at a time, all eight loads issued before
-// their products, so that a lane has eight loads in flight instead of one
-// (same occupancy, 4 waves per SIMD, in the walk kernels).
-__device__ inline double dist2_f64(const float* __restrict__ qrow, const float* __restrict__ xrow, int d) {
-  const float4* x4 = reinterpret_cast<const float4*>(xrow);
-  double D = 0.0;
-  auto piece = [&](const float4& xv, int h4) {
-    double dl = (double)qrow[4 * h4] - (double)xv.x;
-    D = __builtin_fma(dl, dl, D);
-    dl = (double)qrow[4 * h4 + 1] - (double)xv.y;
-    D = __builtin_fma(dl, dl, D);
-    dl = (double)qrow[4 * h4 + 2] - (double)xv.z;
-    D = __builtin_fma(dl, dl, D);
-    dl = (double)qrow[4 * h4 + 3] - (double)xv.w;
-    D = __builtin_fma(dl, dl, D);
-  };
-  const int d4 = d >> 2;
-  int h4 = 0;
-  for (; h4 + 7 < d4; h4 += 8) {
-    const float4 x0 = x4[h4], x1 = x4[h4 + 1], x2 = x4[h4 + 2], x3 = x4[h4 + 3];
-    const float4 x5 = x4[h4 + 4], x6 = x4[h4 + 5], x7 = x4[h4 + 6], x8 = x4[h4 + 7];
-    piece(x0, h4);
-    piece(x1, h4 + 1);
-    piece(x2, h4 + 2);
-    piece(x3, h4 + 3);
-    piece(x5, h4 + 4);
-    piece(x6, h4 + 5);
-    piece(x7, h4 + 6);
-    piece(x8, h4 + 7);
-  }
-  for (; h4 < d4; ++h4) piece(x4[h4], h4);
-  for (int h = 4 * d4; h < d; ++h) {
-    const double dl = (double)qrow[h] - (double)xrow[h];
-    D = __builtin_fma(dl, dl, D);
-  }
-  return D;
-}
-
-// fp32 squared distance of the screen (two accumulators, alternate
-// coordinates; the same eight-piece loads as dist2_f64).
-__device__ inline float dist2_f32(const float* __restrict__ qrow, const float* __restrict__ xrow, int d) {
+// Both squared distances of a candidate in one pass over its row (the query
+// row is wave-uniform: scalar loads): the fp32 value of the screen (two
+// accumulators, alternate coordinates) and the fp64 value of the level test
+// (one fused chain over ascending coordinates, the oracle's order).  The row
+// is read eight 16-byte pieces at a time, all eight loads issued before
+// their products, so that a lane has eight loads in flight instead of one;
+// one pass instead of a screen pass and a second pass for the survivors.
+__device__ inline float dist2_both(const float* __restrict__ qrow, const float* __restrict__ xrow, int d,
+                                   double* D64) {
   const float4* x4 = reinterpret_cast<const float4*>(xrow);
   float D0 = 0.0f, D1 = 0.0f;
+  double D = 0.0;
   auto piece = [&](const float4& xv, int h4) {
-    float dl = qrow[4 * h4] - xv.x;
+    const float q0 = qrow[4 * h4], q1 = qrow[4 * h4 + 1], q2 = qrow[4 * h4 + 2], q3 = qrow[4 * h4 + 3];
+    float dl = q0 - xv.x;
     D0 = __builtin_fmaf(dl, dl, D0);
-    dl = qrow[4 * h4 + 1] - xv.y;
+    dl = q1 - xv.y;
     D1 = __builtin_fmaf(dl, dl, D1);
-    dl = qrow[4 * h4 + 2] - xv.z;
+    dl = q2 - xv.z;
     D0 = __builtin_fmaf(dl, dl, D0);
-    dl = qrow[4 * h4 + 3] - xv.w;
+    dl = q3 - xv.w;
     D1 = __builtin_fmaf(dl, dl, D1);
+    double e = (double)q0 - (double)xv.x;
+    D = __builtin_fma(e, e, D);
+    e = (double)q1 - (double)xv.y;
+    D = __builtin_fma(e, e, D);
+    e = (double)q2 - (double)xv.z;
+    D = __builtin_fma(e, e, D);
+    e = (double)q3 - (double)xv.w;
+    D = __builtin_fma(e, e, D);
   };
   const int d4 = d >> 2;
   int h4 = 0;
@@ -481,7 +458,10 @@ __device__ inline float dist2_f32(const float* __restrict__ qrow, const float* _
   for (int h = 4 * d4; h < d; ++h) {
     const float dl = qrow[h] - xrow[h];
     D0 = __builtin_fmaf(dl, dl, D0);
+    const double e = (double)qrow[h] - (double)xrow[h];
+    D = __builtin_fma(e, e, D);
   }
+  *D64 = D;
   return D0 + D1;
 }
 
@@ -492,7 +472,8 @@ __device__ inline float dist2_f32(const float* __restrict__ qrow, const float* _
 // table of the level or is the query's own point (self_idx >= 0); the rest
 // pass an fp32 distance screen that removes only points certainly outside
 // the level (bound screen_delta), and the survivors queue up in candidate
-// order.  Every 64 queued points (and at the end of a level) form a batch in
+// order with their fp64 squared distances (taken in the same pass over the
+// row).  Every 64 queued points (and at the end of a level) form a batch in
 // which each lane decides the level in fp64 and computes its term:
 // on_batch(v, j, valid) receives it (0 outside the level) and the point j.
 // Returns the number of candidates walked.
@@ -550,7 +531,7 @@ __device__ inline int64_t walk_copy(const IndexView& ix, const LevelConst& lc, i
       int32_t j = -1;
       if (valid) {
         j = ws.ring[(head + lane) & 127];
-        const double D = dist2_f64(qrow, ix.X + (int64_t)j * ix.dx, d);
+        const double D = ws.ringD[(head + lane) & 127];
         if (D >= Tlo && D < Thi) {
           v = level_weight(ix.cheb + i * kChebRow, sqrt(D) / ri);
         }
@@ -562,6 +543,7 @@ __device__ inline int64_t walk_copy(const IndexView& ix, const LevelConst& lc, i
       const uint32_t k = k0 + lane;
       bool keep = false;
       int32_t j = -1;
+      double D64 = 0.0;
       if (k < total) {
         int lo = 0, hi = L - 1;  // last table whose prefix is <= k
         while (lo < hi) {
@@ -577,13 +559,16 @@ __device__ inline int64_t walk_copy(const IndexView& ix, const LevelConst& lc, i
 #pragma unroll 4
         for (int l2 = 0; l2 < l; ++l2) seen |= mk[l2] == ws.qk[l2];
         if (!seen && j != self_idx) {
-          const double D32 = (double)dist2_f32(qrow, ix.X + (int64_t)j * ix.dx, d);
+          const double D32 = (double)dist2_both(qrow, ix.X + (int64_t)j * ix.dx, d, &D64);
           keep = D32 >= lo_s && D32 < hi_s;
         }
       }
       const uint64_t km = __ballot(keep);
       const uint32_t pos = __builtin_amdgcn_mbcnt_hi((uint32_t)(km >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)km, 0u));
-      if (keep) ws.ring[(tail + pos) & 127] = j;
+      if (keep) {
+        ws.ring[(tail + pos) & 127] = j;
+        ws.ringD[(tail + pos) & 127] = D64;
+      }
       tail += (uint32_t)__popcll(km);
       __builtin_amdgcn_wave_barrier();
       if (tail - head >= 64) {
