@@ -38,7 +38,8 @@ def test_config1_bit_exact(stag, orc):
 
 
 @pytest.mark.parametrize("n,d,K,L", [(1, 1, 1, 1), (65, 3, 9, 17), (300, 64, 9, 17), (129, 100, 5, 7),
-                                     (300, 128, 9, 17), (70, 784, 3, 4), (200, 33, 17, 3)])
+                                     (300, 128, 9, 17), (70, 784, 3, 4), (200, 33, 17, 3),
+                                     (50, 301, 12, 5), (40, 1000, 10, 3)])
 def test_shapes_bit_exact(stag, orc, n, d, K, L):
     rng = np.random.default_rng(n + d)
     X = (rng.normal(size=(n, d)) * rng.uniform(0.1, 20)).astype(np.float32)
