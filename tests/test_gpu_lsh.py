@@ -183,12 +183,14 @@ def test_query_batch_independence(stag):
     idx.close()
 
 
-@pytest.mark.parametrize("d,k2", [(24, 6), (100, 6), (64, 8), (64, 9), (200, 4), (16, 40)])
+@pytest.mark.parametrize("d,k2", [(24, 6), (100, 6), (64, 8), (64, 9), (200, 4), (16, 40), (257, 4), (131, 5)])
 def test_query_paths_by_dimension_and_tables(stag, orc, d, k2):
     """Bucket join at the register widths 32 (d = 24) and 128 (d = 100), with
     the earlier tables' query keys in registers (L <= 8) and in LDS (L = 9),
-    and the per-query walk for d > 128 and for more than 32 tables per level:
-    bit-exact counts and 1e-9 values against the oracle, ragged sizes."""
+    and the per-query walk for d > 128 (d = 257 and 131: rows read in blocks
+    of eight 16-byte pieces plus an element-wise tail) and for more than 32
+    tables per level: bit-exact counts and 1e-9 values against the oracle,
+    ragged sizes."""
     mix = synth.mixture(d, 6, 7100 + d, sigma=(0.5, 1.5), box=3.0)
     X = synth.sample(mix, 1537, 7200 + d)
     Q = np.concatenate([synth.sample(mix, 131, 7300 + d), X[:5]])
