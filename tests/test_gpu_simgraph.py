@@ -151,6 +151,28 @@ def test_exact_mode_wide_rows(stag, orc, form):
     _check_valid_draws(orc, X, a, s, seed, src, dst, np.nonzero(~same)[0], 1e-5)
 
 
+@pytest.mark.parametrize("d,form", [(64, "fp32"), (100, "fp16_split"), (256, "fp32")])
+def test_exact_mode_fused_draw_widths(stag, orc, d, form):
+    """d = 64, 100 and 256 (the fused draw kernel: a lane half reads its row
+    four 16-byte pieces at a time, then the remaining pieces), n = 4500 (two
+    4096-row chunks, a ragged last tile), clustered data: degrees within
+    1e-5, draws equal to the oracle's outside the tolerance band and valid
+    inside it."""
+    mix = synth.mixture(d, 8, 8100 + d, sigma=(0.5, 1.5), box=3.0)
+    X = synth.sample(mix, 4500, 8200 + d)
+    a, s, seed, tol = 1.0 / d, 9, 41, 1e-4
+    announce(f"simgraph exact fused draws n=4500 d={d} form={form}")
+    src, dst, w, deg = _gpu(stag, X, a, s, mode="exact", form=form, seed=seed)
+    osrc, odst, ow, odeg, mg = orc.simgraph_exact(X, a, s, seed, return_margin=True)
+    assert np.array_equal(src, osrc)
+    assert np.allclose(deg, odeg, rtol=1e-5)
+    assert np.all(dst >= 0) and np.all(dst != src)
+    same = dst == odst
+    assert np.all(same[mg > tol])
+    _check_valid_draws(orc, X, a, s, seed, src, dst, np.nonzero(~same)[0], tol)
+    assert np.all(np.abs(w[same] - ow[same]) <= 1e-4 * ow[same])
+
+
 @pytest.mark.parametrize("form", ["fp32", "fp16_split"])
 def test_exact_mode_wide_scalar_rows_rescue(stag, orc, form):
     """d = 301 > 256 (draws sorted by tile before the row step) with rows
