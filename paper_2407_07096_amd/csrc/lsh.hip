@@ -475,17 +475,20 @@ __device__ inline float dist2_both(const float* __restrict__ qrow, const float* 
 // order with their fp64 squared distances (taken in the same pass over the
 // row).  Every 64 queued points (and at the end of a level) form a batch in
 // which each lane decides the level in fp64 and computes its term:
-// on_batch(v, j, valid) receives it (0 outside the level) and the point j.
+// on_batch(v, j, valid, i) receives it (0 outside the level), the point j
+// and the level i.  Levels whose bit (i - 1) is clear in `levels` are
+// skipped (callers pass a mask of the levels with a positive term).
 // Returns the number of candidates walked.
 template <class F>
 __device__ inline int64_t walk_copy(const IndexView& ix, const LevelConst& lc, int t, const uint64_t* __restrict__ qk,
                                     int64_t qs, WalkScratch& ws, const float* __restrict__ qrow, int64_t self_idx,
-                                    F&& on_batch) {
+                                    uint64_t levels, F&& on_batch) {
   const int lane = threadIdx.x & 63;
   const int L = ix.L, d = ix.d;
   const double delta = screen_delta(d);
   int64_t walked = 0;
-  for (int i = 1; i <= ix.J; ++i) {
+  for (int i = 1; i <= ix.J; ++i) {  // J <= 64
+    if (!((levels >> (i - 1)) & 1)) continue;
     const int seg = t * ix.J + (i - 1);
     const int64_t s0 = (int64_t)ix.seg_off[seg];
     const int64_t cnt = (int64_t)ix.seg_off[seg + 1] - s0;
@@ -536,7 +539,7 @@ __device__ inline int64_t walk_copy(const IndexView& ix, const LevelConst& lc, i
           v = level_weight(ix.cheb + i * kChebRow, sqrt(D) / ri);
         }
       }
-      on_batch(v, j, valid);
+      on_batch(v, j, valid, i);
     };
     uint32_t head = 0, tail = 0;
     for (uint32_t k0 = 0; k0 < total; k0 += 64) {
@@ -587,7 +590,8 @@ __device__ inline int64_t walk_copy(const IndexView& ix, const LevelConst& lc, i
 __global__ __launch_bounds__(256) void probe_queries(const float* __restrict__ Q, int ldq, int64_t q0, int64_t mb,
                                                      IndexView ix, LevelConst lc, const uint64_t* __restrict__ qkeys,
                                                      int64_t ntab, int self_excl, double* __restrict__ Scopy,
-                                                     int64_t* __restrict__ ncand, int64_t* __restrict__ nacc) {
+                                                     int64_t* __restrict__ ncand, int64_t* __restrict__ nacc,
+                                                     uint64_t* __restrict__ levels_out) {
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int64_t pair = (int64_t)blockIdx.x * 4 + wave;
@@ -598,10 +602,12 @@ __global__ __launch_bounds__(256) void probe_queries(const float* __restrict__ Q
   __shared__ WalkScratch wsc[4];
   double acc = 0.0;
   int64_t nc = 0, na = 0;
-  nc = walk_copy(ix, lc, t, qkeys + ql, mb, wsc[wave], qrow, self_excl ? q0 + ql : -1,
-                 [&](double v, int32_t j, bool valid) {
+  uint64_t hit = 0;  // levels with a positive term (wave-uniform)
+  nc = walk_copy(ix, lc, t, qkeys + ql, mb, wsc[wave], qrow, self_excl ? q0 + ql : -1, ~0ULL,
+                 [&](double v, int32_t j, bool valid, int i) {
                    acc += v;
                    na += v > 0.0 ? 1 : 0;
+                   if (__ballot(v > 0.0)) hit |= 1ULL << (i - 1);
                  });
   for (int o = 32; o > 0; o >>= 1) {
     acc += __shfl_xor(acc, o);
@@ -609,6 +615,7 @@ __global__ __launch_bounds__(256) void probe_queries(const float* __restrict__ Q
   }
   if (lane == 0) {
     Scopy[ql * ix.K1 + t] = acc;
+    if (levels_out) levels_out[(q0 + ql) * ix.K1 + t] = hit;
     if (ncand) atomicAdd(reinterpret_cast<unsigned long long*>(ncand + q0 + ql), (unsigned long long)nc);
     if (nacc) atomicAdd(reinterpret_cast<unsigned long long*>(nacc + q0 + ql), (unsigned long long)na);
   }
@@ -631,7 +638,8 @@ __device__ inline double wave_incl_scan_f64(double v) {
 // locate every pending remainder.
 __global__ __launch_bounds__(256) void draw_lsh(IndexView ix, LevelConst lc, const uint64_t* __restrict__ qkeys,
                                                 int64_t ntab, int64_t q0, int64_t mb, const double* __restrict__ Scopy,
-                                                const double* __restrict__ rest, int s, uint64_t seed,
+                                                const uint64_t* __restrict__ levels, const double* __restrict__ rest,
+                                                int s, uint64_t seed,
                                                 int64_t* __restrict__ src, int64_t* __restrict__ dst,
                                                 double* __restrict__ w) {
   const int lane = threadIdx.x & 63;
@@ -676,7 +684,10 @@ __global__ __launch_bounds__(256) void draw_lsh(IndexView ix, LevelConst lc, con
     if (__ballot(mine && tsel == t) == 0) continue;
     double running = 0.0;
     int32_t lastj = -1;
-    walk_copy(ix, lc, t, qkeys + ql, mb, wsc[wave], qrow, qi, [&](double v, int32_t j, bool valid) {
+    // levels without a positive term change neither the running sum nor the
+    // last positive point, so the walk skips them
+    const uint64_t lv = levels ? levels[qi * ix.K1 + t] : ~0ULL;
+    walk_copy(ix, lc, t, qkeys + ql, mb, wsc[wave], qrow, qi, lv, [&](double v, int32_t j, bool valid, int) {
       const double incl = wave_incl_scan_f64(v);
       const double btot = __shfl(incl, 63);
       const uint64_t pos = __ballot(v > 0.0);
@@ -1641,7 +1652,8 @@ stag_status join_batch(const stag_lsh_index* idx, const float* Q, int ldq, int64
 // Estimates for rows of Q (self_excl: Q is the index's own data and each
 // row's own point is left out).  Optional per-copy values and counts.
 stag_status query_index(const stag_lsh_index* idx, const float* Q, int ldq, int64_t m, int self_excl,
-                        double* S_out, double* copies_out, int64_t* ncand, int64_t* nacc, hipStream_t st) {
+                        double* S_out, double* copies_out, int64_t* ncand, int64_t* nacc, hipStream_t st,
+                        uint64_t* levels_out = nullptr) {
   const LshParams& prm = idx->prm;
   const int K1 = prm.shape.K1;
   Workspace ws(st);
@@ -1662,7 +1674,7 @@ stag_status query_index(const stag_lsh_index* idx, const float* Q, int ldq, int6
     } else {
       ScopedTimer tm("lsh_probe", st);
       hipLaunchKernelGGL(probe_queries, dim3((unsigned)ceil_div(cur * K1, 4)), dim3(256), 0, st, Q, ldq, q0, cur, ix,
-                         lc, qkeys, idx->ntab, self_excl, scopy, ncand, nacc);
+                         lc, qkeys, idx->ntab, self_excl, scopy, ncand, nacc, levels_out);
       STAG_TRY(check_launch("probe_queries"));
     }
     hipLaunchKernelGGL(mean_copies, dim3((unsigned)ceil_div(cur, 256)), dim3(256), 0, st, scopy, q0, cur, K1, S_out,
@@ -1686,7 +1698,11 @@ stag_status lsh_sample_edges(const stag_lsh_index* idx, int s, uint64_t seed, in
   double* copies = nullptr;
   STAG_TRY(ws.alloc(&rest, (size_t)n));
   STAG_TRY(ws.alloc(&copies, (size_t)n * K1));
-  STAG_TRY(query_index(idx, idx->X, idx->dx, n, 1, rest, copies, nullptr, nullptr, st));
+  // with the per-query walk (not the bucket join) the estimate also records,
+  // per node and copy, the levels with a positive term for the draws
+  uint64_t* levels = nullptr;
+  if (!join_applies(idx)) STAG_TRY(ws.alloc(&levels, (size_t)n * K1));
+  STAG_TRY(query_index(idx, idx->X, idx->dx, n, 1, rest, copies, nullptr, nullptr, st, levels));
   const int64_t mb = query_batch(idx, n);
   uint64_t* qkeys = nullptr;
   STAG_TRY(ws.alloc(&qkeys, (size_t)mb * idx->ntab));
@@ -1697,7 +1713,7 @@ stag_status lsh_sample_edges(const stag_lsh_index* idx, int s, uint64_t seed, in
     STAG_TRY(hash_query_batch(idx, idx->X, idx->dx, q0, cur, qkeys, st));
     ScopedTimer tm("simgraph_draw_lsh", st);
     hipLaunchKernelGGL(draw_lsh, dim3((unsigned)ceil_div(cur, 4)), dim3(256), 0, st, ix, lc, qkeys, idx->ntab, q0,
-                       cur, copies + q0 * K1, rest, s, seed, src, dst, w);
+                       cur, copies + q0 * K1, levels, rest, s, seed, src, dst, w);
     STAG_TRY(check_launch("draw_lsh"));
   }
   if (deg_out) {
