@@ -1651,16 +1651,18 @@ stag_status join_batch(const stag_lsh_index* idx, const float* Q, int ldq, int64
 
 // Estimates for rows of Q (self_excl: Q is the index's own data and each
 // row's own point is left out).  Optional per-copy values and counts.
+// keys_buf (optional): the caller's buffer of query_batch(idx, m) x ntab
+// keys; when the queries fit one batch it holds their keys on return.
 stag_status query_index(const stag_lsh_index* idx, const float* Q, int ldq, int64_t m, int self_excl,
                         double* S_out, double* copies_out, int64_t* ncand, int64_t* nacc, hipStream_t st,
-                        uint64_t* levels_out = nullptr) {
+                        uint64_t* levels_out = nullptr, uint64_t* keys_buf = nullptr) {
   const LshParams& prm = idx->prm;
   const int K1 = prm.shape.K1;
   Workspace ws(st);
   const int64_t mb = query_batch(idx, m);
-  uint64_t* qkeys = nullptr;
+  uint64_t* qkeys = keys_buf;
   double* scopy = nullptr;
-  STAG_TRY(ws.alloc(&qkeys, (size_t)mb * idx->ntab));
+  if (!qkeys) STAG_TRY(ws.alloc(&qkeys, (size_t)mb * idx->ntab));
   STAG_TRY(ws.alloc(&scopy, (size_t)mb * K1));
   if (ncand) hipLaunchKernelGGL(zero_i64, dim3((unsigned)ceil_div(m, 256)), dim3(256), 0, st, ncand, m);
   if (nacc) hipLaunchKernelGGL(zero_i64, dim3((unsigned)ceil_div(m, 256)), dim3(256), 0, st, nacc, m);
@@ -1702,15 +1704,16 @@ stag_status lsh_sample_edges(const stag_lsh_index* idx, int s, uint64_t seed, in
   // per node and copy, the levels with a positive term for the draws
   uint64_t* levels = nullptr;
   if (!join_applies(idx)) STAG_TRY(ws.alloc(&levels, (size_t)n * K1));
-  STAG_TRY(query_index(idx, idx->X, idx->dx, n, 1, rest, copies, nullptr, nullptr, st, levels));
   const int64_t mb = query_batch(idx, n);
   uint64_t* qkeys = nullptr;
   STAG_TRY(ws.alloc(&qkeys, (size_t)mb * idx->ntab));
+  STAG_TRY(query_index(idx, idx->X, idx->dx, n, 1, rest, copies, nullptr, nullptr, st, levels, qkeys));
   const IndexView ix = make_view(idx);
   const LevelConst lc = make_levels(prm);
   for (int64_t q0 = 0; q0 < n; q0 += mb) {
     const int64_t cur = std::min(mb, n - q0);
-    STAG_TRY(hash_query_batch(idx, idx->X, idx->dx, q0, cur, qkeys, st));
+    // with one batch the estimate's keys are still in qkeys
+    if (mb < n) STAG_TRY(hash_query_batch(idx, idx->X, idx->dx, q0, cur, qkeys, st));
     ScopedTimer tm("simgraph_draw_lsh", st);
     hipLaunchKernelGGL(draw_lsh, dim3((unsigned)ceil_div(cur, 4)), dim3(256), 0, st, ix, lc, qkeys, idx->ntab, q0,
                        cur, copies + q0 * K1, levels, rest, s, seed, src, dst, w);
