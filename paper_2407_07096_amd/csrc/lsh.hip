@@ -372,6 +372,7 @@ struct LevelConst {
 // Read-only view of an index for device code.
 struct IndexView {
   const float* X;
+  const double* xn;  // [n] ||x|| of each point (binary64)
   int dx, d, K1, J, L, K;
   double a;
   int literal;
@@ -486,6 +487,14 @@ __device__ inline int64_t walk_copy(const IndexView& ix, const LevelConst& lc, i
   const int lane = threadIdx.x & 63;
   const int L = ix.L, d = ix.d;
   const double delta = screen_delta(d);
+  // ||q|| (binary64, relative error below 1e-13 for d <= 1024, as ||x||)
+  double nq = 0.0;
+  for (int c = lane; c < d; c += 64) {
+    const double v = qrow[c];
+    nq = __builtin_fma(v, v, nq);
+  }
+  for (int o = 32; o > 0; o >>= 1) nq += __shfl_xor(nq, o);
+  const double sq = sqrt(nq);
   int64_t walked = 0;
   for (int i = 1; i <= ix.J; ++i) {  // J <= 64
     if (!((levels >> (i - 1)) & 1)) continue;
@@ -562,8 +571,19 @@ __device__ inline int64_t walk_copy(const IndexView& ix, const LevelConst& lc, i
 #pragma unroll 4
         for (int l2 = 0; l2 < l; ++l2) seen |= mk[l2] == ws.qk[l2];
         if (!seen && j != self_idx) {
-          const double D32 = (double)dist2_both(qrow, ix.X + (int64_t)j * ix.dx, d, &D64);
-          keep = D32 >= lo_s && D32 < hi_s;
+          // (||q|| - ||x||)^2 <= D <= (||q|| + ||x||)^2, with an absolute slack
+          // e above the norms' rounding: a point that these bounds put
+          // outside the level by more than the screen's own bound would fail
+          // the fp32 screen too, so it is dropped without reading its row
+          const double sx = ix.xn[j];
+          const double e = 4e-12 * (sq + sx);
+          const double up = sq + sx + e, dn = fmax(fabs(sq - sx) - e, 0.0);
+          if (up * up * (1.0 + delta) < lo_s || dn * dn * (1.0 - delta) >= hi_s) {
+            keep = false;
+          } else {
+            const double D32 = (double)dist2_both(qrow, ix.X + (int64_t)j * ix.dx, d, &D64);
+            keep = D32 >= lo_s && D32 < hi_s;
+          }
         }
       }
       const uint64_t km = __ballot(keep);
@@ -1251,6 +1271,7 @@ struct stag_lsh_index {
   char* arena = nullptr;  // current block of small index allocations
   size_t arena_used = 0;
   float* X = nullptr;
+  double* xn = nullptr;
   double* G8 = nullptr;
   double* B = nullptr;
   uint64_t* seg_off = nullptr;
@@ -1343,6 +1364,22 @@ __global__ void copy_rows(const float* __restrict__ src, int64_t n, int d, int d
   }
 }
 
+// xn[r] = ||x_r|| in binary64 (one wave per row; any summation order: the
+// walk uses it only for bounds with a margin).
+__global__ __launch_bounds__(256) void row_norms(const float* __restrict__ X, int64_t n, int dx,
+                                                 double* __restrict__ xn) {
+  const int lane = threadIdx.x & 63;
+  const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (r >= n) return;
+  double s2 = 0.0;
+  for (int c = lane; c < dx; c += 64) {
+    const double v = X[r * dx + c];
+    s2 = __builtin_fma(v, v, s2);
+  }
+  for (int o = 32; o > 0; o >>= 1) s2 += __shfl_xor(s2, o);
+  if (lane == 0) xn[r] = sqrt(s2);
+}
+
 stag_status create_index(const float* X, int64_t n, int d, double a, double eps, const stag_lsh_params* p,
                          stag_lsh_index* idx, hipStream_t st) {
   STAG_TRY(lsh_derive_params(n, a, eps, p, &idx->prm));
@@ -1362,6 +1399,9 @@ stag_status create_index(const float* X, int64_t n, int d, double a, double eps,
   hipLaunchKernelGGL(copy_rows, dim3((unsigned)std::min<int64_t>(ceil_div(n * idx->dx, 256), 65536)), dim3(256), 0,
                      st, X, n, d, idx->dx, idx->X);
   STAG_TRY(check_launch("copy_rows"));
+  STAG_TRY(own_alloc(idx, &idx->xn, (size_t)n));
+  hipLaunchKernelGGL(row_norms, dim3((unsigned)ceil_div(n, 4)), dim3(256), 0, st, idx->X, n, idx->dx, idx->xn);
+  STAG_TRY(check_launch("row_norms"));
 
   // level constants
   STAG_TRY(own_alloc(idx, &idx->rlev, 65));
@@ -1487,6 +1527,7 @@ IndexView make_view(const stag_lsh_index* idx) {
   const LshParams& prm = idx->prm;
   IndexView v;
   v.X = idx->X;
+  v.xn = idx->xn;
   v.dx = idx->dx;
   v.d = idx->d;
   v.K1 = prm.shape.K1;
